@@ -1,0 +1,154 @@
+/*
+ * of.h -- C ABI of the MI355X (gfx950) Oriented FAST detector.
+ *
+ * The library detects oriented FAST keypoints over a multi-level image pyramid and keeps
+ * the ones the Harris response ranks highest, as in the Oriented-FAST stage of ORB that
+ * the paper accelerates (Sec. 1: pyramid, FAST, Harris, NMS and centroid steps of Fig. 1).
+ * Steps, in order:
+ *   1. pyramid      -- levels at scale s^-l (s = scale_num/scale_den), each sampled from
+ *                      the input frame with fixed-point bilinear weights;
+ *   2. segment test -- Eq. (1) with the "9 or more contiguous" rule (Sec. 3.1), at
+ *                      fast_t, or at fast_t_min inside cells that hold no fast_t corner;
+ *   3. Harris       -- Sec. 3.2 / Eq. (4): 3x3 Sobel gradients summed over a 7x7 window,
+ *                      ranked by R' = 25 det(M) - tr(M)^2 (= 25 x score with k = 0.04);
+ *   4. 3x3 non-maximum suppression under the order (R' desc, y asc, x asc);
+ *   5. per-cell top-K then per-level top-N_l, N_l proportional to level area;
+ *   6. intensity-centroid orientation over a disk of radius patch_radius.
+ * Every step is exact integer arithmetic except the final atan2 (float).
+ *
+ * Conventions for every entry point:
+ *   - Pointers to pixels, keypoints, counts and workspace are DEVICE pointers unless the
+ *     argument says "host".  The caller owns every buffer; the library never allocates,
+ *     frees or synchronises on these calls and never throws across the ABI.
+ *   - Work is queued on `stream` (a hipStream_t; NULL = the default stream) and is
+ *     asynchronous; results are valid once the stream has reached that point.
+ *     Calls contain no memset or memcpy nodes, so a sequence can be captured in a
+ *     HIP graph and replayed.
+ *   - Concurrent calls must use distinct workspaces.
+ *   - Return 0 (OF_OK) or a negative status; of_status_string() explains it.  On
+ *     OF_EHIP the HIP error of the failing launch is kept per thread (of_last_hip_error).
+ */
+#ifndef OF_H
+#define OF_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct ihipStream_t* hipStream_t;
+
+#define OF_OK 0
+#define OF_EINVAL (-1)   /* bad argument: null pointer, size, parameter, capacity */
+#define OF_ENOSPACE (-2) /* workspace smaller than of_workspace_size() */
+#define OF_EHIP (-3)     /* a HIP launch failed */
+
+#define OF_MAX_LEVELS 16
+#define OF_MAX_BATCH 64  /* frames per of_detect_batch call */
+
+/* 8-bit grey frame, row-major, `stride` bytes between rows (stride >= width).
+ * 1 <= width, height <= 16384. */
+typedef struct {
+  const uint8_t* data;
+  int32_t width, height, stride;
+} of_image;
+
+/* Detector parameters.  Accepted ranges (else OF_EINVAL):
+ *   n_levels 1..16; 1 <= scale_den < scale_num <= 8;
+ *   fast_t 1..255; 1 <= fast_t_min <= fast_t (equal = no fallback);
+ *   cell 0 (the whole level is one cell) or 8..128;
+ *   n_features 1..65536, and every level quota N_l <= 4096;
+ *   harris_block 7; patch_radius 4..48;
+ *   every level at least 2*patch_radius+1 pixels in both directions. */
+typedef struct {
+  int32_t n_levels;
+  int32_t scale_num, scale_den; /* 6, 5 = scale 1.2 */
+  int32_t fast_t, fast_t_min;   /* 20, 7 */
+  int32_t cell;                 /* 30 */
+  int32_t n_features;           /* keypoints per frame over all levels */
+  int32_t harris_block;         /* 7 */
+  int32_t patch_radius;         /* 15: orientation radius and detection border */
+} of_params;
+
+/* One keypoint, 32 bytes.  (x, y) are in the coordinates of `level`. */
+typedef struct {
+  int32_t x, y, level;
+  int32_t m10, m01; /* intensity moments over the disk (y down) */
+  float angle;      /* atan2(m01, m10), radians in (-pi, pi] */
+  int64_t score;    /* R' */
+} of_keypoint;
+
+/* Pyramid layout as written by of_pyramid_build: level l is height[l] rows of
+ * width[l] pixels, row stride stride[l], starting at byte offset[l] of the buffer.
+ * quota[l] is the level's keypoint quota N_l. */
+typedef struct {
+  int32_t n_levels;
+  int32_t width[OF_MAX_LEVELS], height[OF_MAX_LEVELS], stride[OF_MAX_LEVELS];
+  int32_t quota[OF_MAX_LEVELS];
+  int64_t offset[OF_MAX_LEVELS];
+  int64_t total_bytes;
+} of_pyramid_desc;
+
+/* Launch shape of the batched path (tile sizes, persistent grid sizes).  Any field set
+ * to 0 takes the default; of_tuning_default() reports the defaults for a batch. */
+typedef struct {
+  int32_t mark_words; /* segment-test tile width in 64-pixel words, 1..4 */
+  int32_t mark_rows;  /* segment-test tile height, 4..64 */
+  int32_t det_cells_x, det_cells_y; /* Harris/NMS tile in cells (cell > 0); w*cell <= 256, h*cell <= 128 */
+  int32_t det_w, det_h;             /* Harris/NMS tile in pixels when cell == 0; <= 256 x 128 */
+  int32_t mark_grid;  /* workgroups of the persistent segment-test launch (0 = one per tile) */
+  int32_t det_grid;   /* workgroups of the persistent Harris/NMS launch (0 = one per tile) */
+} of_tuning;
+
+/* Host only.  Level sizes, strides and offsets of the pyramid of a W x H frame. */
+int of_pyramid_desc_get(int32_t width, int32_t height, const of_params* params,
+                        of_pyramid_desc* out);
+
+/* Build every level of `in` (level 0 copied) into `levels` (device, at least
+ * desc.total_bytes, laid out as of_pyramid_desc_get reports). */
+int of_pyramid_build(const of_image* in, const of_params* params, uint8_t* levels,
+                     hipStream_t stream);
+
+/* Host only.  Workspace bytes needed by of_detect (n = 1) or of_detect_batch for these
+ * frames (host array of n descriptors; only width and height are read). */
+int of_workspace_size(const of_image* frames, int32_t n, const of_params* params,
+                      size_t* bytes);
+
+/* Plain path: one frame, one launch per pyramid level and step.  Writes up to
+ * n_features keypoints to `out` in the order (level asc, R' desc, y asc, x asc) and
+ * their number to *count (device int32).  cap >= n_features is required.
+ * ws: device workspace of ws_bytes >= of_workspace_size(in, 1, params). */
+int of_detect(const of_image* in, const of_params* params, void* ws, size_t ws_bytes,
+              of_keypoint* out, int32_t cap, int32_t* count, hipStream_t stream);
+
+/* Batched path: n frames (host array of descriptors, 1 <= n <= OF_MAX_BATCH, sizes may
+ * differ) through one launch per step: a persistent fused pyramid + segment-test kernel
+ * over every level of every frame, a persistent Harris/NMS/cell-selection kernel, the
+ * level selection and the orientation.  Frame i writes its keypoints (same order as
+ * of_detect) at out + out_offset[i] (host array, in keypoints) and its count to
+ * counts[i] (device).  cap_per_frame >= n_features is required and the caller keeps
+ * the n output ranges disjoint.  `tuning` may be NULL (defaults). */
+int of_detect_batch(const of_image* frames, int32_t n, const of_params* params, void* ws,
+                    size_t ws_bytes, of_keypoint* out, const int64_t* out_offset,
+                    int32_t cap_per_frame, int32_t* counts, const of_tuning* tuning,
+                    hipStream_t stream);
+
+/* Host only.  The tuning of_detect_batch uses when given NULL (or zero fields). */
+int of_tuning_default(const of_image* frames, int32_t n, const of_params* params,
+                      of_tuning* out);
+
+/* Test entry point for the segment test alone: for each of n pixels, `circles` holds 17
+ * bytes (the centre, then circle positions 1..16 clockwise from the top) and out[i]
+ * gets bit 0 = corner at t_lo, bit 1 = corner at t_hi.  Device pointers. */
+int of_test_segment(const uint8_t* circles, int32_t n, int32_t t_lo, int32_t t_hi,
+                    uint8_t* out, hipStream_t stream);
+
+const char* of_status_string(int status);
+int of_last_hip_error(void); /* hipError_t of the last OF_EHIP on this thread */
+
+#ifdef __cplusplus
+}
+#endif
+#endif

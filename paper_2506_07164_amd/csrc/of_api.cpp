@@ -1,0 +1,387 @@
+// of_api.cpp -- the C ABI declared in include/of.h: validation, workspace layout and
+// launch sequencing.  Every step of the detector runs in the kernels of
+// of_kernels.hip; this file only checks arguments and queues launches.
+#include <string.h>
+
+#include "of_kernels.h"
+
+using namespace ofk;
+
+namespace {
+
+thread_local int g_last_hip = 0;
+
+int hip_fail(hipError_t e) {
+  g_last_hip = (int)e;
+  return OF_EHIP;
+}
+
+int check_params(const of_params* p) {
+  if (!p) return OF_EINVAL;
+  if (p->n_levels < 1 || p->n_levels > kMaxLevels) return OF_EINVAL;
+  if (p->scale_den < 1 || p->scale_num <= p->scale_den || p->scale_num > 8) return OF_EINVAL;
+  if (p->fast_t < 1 || p->fast_t > 255) return OF_EINVAL;
+  if (p->fast_t_min < 1 || p->fast_t_min > p->fast_t) return OF_EINVAL;
+  if (p->cell != 0 && (p->cell < 8 || p->cell > 128)) return OF_EINVAL;
+  if (p->n_features < 1 || p->n_features > 65536) return OF_EINVAL;
+  if (p->harris_block != 7) return OF_EINVAL;
+  if (p->patch_radius < 4 || p->patch_radius > 48) return OF_EINVAL;
+  return OF_OK;
+}
+
+int check_frame_size(int32_t W, int32_t H, const of_params& p) {
+  if (W < 1 || H < 1 || W > 16384 || H > 16384) return OF_EINVAL;
+  FrameGeom g;
+  frame_geom(W, H, p, &g);
+  for (int l = 0; l < p.n_levels; ++l) {
+    if (g.W[l] < 2 * p.patch_radius + 1 || g.H[l] < 2 * p.patch_radius + 1) return OF_EINVAL;
+    if (g.quota[l] > kMaxQuota) return OF_EINVAL;
+  }
+  return OF_OK;
+}
+
+int check_image(const of_image* im, const of_params& p) {
+  if (!im || !im->data) return OF_EINVAL;
+  if (im->stride < im->width) return OF_EINVAL;
+  return check_frame_size(im->width, im->height, p);
+}
+
+int device_cus() {
+  static int cus = 0;
+  if (!cus) {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+        cus <= 0)
+      cus = 256;
+  }
+  return cus;
+}
+
+// Defaults: 256 x 16 segment-test tiles; Harris/NMS tiles of about 120 x 30 pixels
+// (whole cells); persistent grids of a few blocks per compute unit.
+Tune default_tune(const of_params& p) {
+  Tune t;
+  t.mark_words = 4;
+  t.mark_rows = 16;
+  if (p.cell > 0) {
+    t.det_cx = 120 / p.cell > 0 ? 120 / p.cell : 1;
+    t.det_cy = 30 / p.cell > 0 ? 30 / p.cell : 1;
+  } else {
+    t.det_cx = t.det_cy = 1;
+  }
+  t.det_w = 128;
+  t.det_h = 32;
+  t.mark_grid = 6 * device_cus();
+  t.det_grid = 4 * device_cus();
+  return t;
+}
+
+int resolve_tune(const of_tuning* user, const of_params& p, Tune* out) {
+  Tune t = default_tune(p);
+  if (user) {
+    if (user->mark_words) t.mark_words = user->mark_words;
+    if (user->mark_rows) t.mark_rows = user->mark_rows;
+    if (user->det_cells_x) t.det_cx = user->det_cells_x;
+    if (user->det_cells_y) t.det_cy = user->det_cells_y;
+    if (user->det_w) t.det_w = user->det_w;
+    if (user->det_h) t.det_h = user->det_h;
+    if (user->mark_grid >= 0) t.mark_grid = user->mark_grid;
+    if (user->det_grid >= 0) t.det_grid = user->det_grid;
+  }
+  if (t.mark_words < 1 || t.mark_words > 4 || t.mark_rows < 4 || t.mark_rows > 64)
+    return OF_EINVAL;
+  if (p.cell > 0) {
+    if (t.det_cx < 1 || t.det_cy < 1 || t.det_cx * p.cell > kMaxDetW ||
+        t.det_cy * p.cell > kMaxDetH)
+      return OF_EINVAL;
+  }
+  if (t.det_w < 8 || t.det_w > kMaxDetW || t.det_h < 8 || t.det_h > kMaxDetH) return OF_EINVAL;
+  if (mark_lds(t).bytes > 65536 || det_lds(t, p.cell).bytes > 65536) return OF_EINVAL;
+  *out = t;
+  return OF_OK;
+}
+
+struct CallPlan {
+  WsLayout lay;
+  EntrySize es[kMaxEntries];
+  int64_t lvl_off[kMaxEntries];
+  FrameGeom geo[kMaxBatch];
+};
+
+void plan_call(const of_image* frames, int n, const of_params& p, const Tune& t, CallPlan* c) {
+  memset(&c->lay, 0, sizeof(c->lay));
+  int64_t lvl = 0;
+  for (int f = 0; f < n; ++f) {
+    frame_geom(frames[f].width, frames[f].height, p, &c->geo[f]);
+    for (int l = 0; l < p.n_levels; ++l) {
+      const int e = f * p.n_levels + l;
+      entry_size(c->geo[f], p, t, l, &c->es[e]);
+      c->lvl_off[e] = lvl;
+      lvl += c->es[e].lvl_bytes;
+      ws_layout_accumulate(&c->lay, c->es[e]);
+    }
+  }
+  ws_layout_finish(&c->lay);
+}
+
+int check_frames(const of_image* frames, int32_t n, const of_params* params) {
+  int st = check_params(params);
+  if (st) return st;
+  if (!frames || n < 1 || n > kMaxBatch) return OF_EINVAL;
+  for (int f = 0; f < n; ++f) {
+    st = check_frame_size(frames[f].width, frames[f].height, *params);
+    if (st) return st;
+  }
+  return OF_OK;
+}
+
+void fill_prologue(PrologueArgs* pa, const of_image* frames, int n, const of_params& p,
+                   const Tune& t, void* ws, const WsLayout& lay, of_keypoint* out,
+                   const int64_t* out_offset, int32_t* counts) {
+  memset(pa, 0, sizeof(*pa));
+  pa->p = p;
+  pa->t = t;
+  pa->n = n;
+  for (int f = 0; f < n; ++f) {
+    pa->f[f].data = frames[f].data;
+    pa->f[f].w = frames[f].width;
+    pa->f[f].h = frames[f].height;
+    pa->f[f].stride = frames[f].stride;
+    pa->f[f].out_off = out_offset ? out_offset[f] : 0;
+  }
+  pa->ws = (uint8_t*)ws;
+  pa->lay = lay;
+  pa->out = out;
+  pa->counts = counts;
+}
+
+KArgs kargs(void* ws, const WsLayout& lay, const Tune& t, const of_params& p) {
+  KArgs k;
+  memset(&k, 0, sizeof(k));
+  uint8_t* b = (uint8_t*)ws;
+  k.plan = (LevelPlan*)(b + lay.off_plan);
+  k.mark_base = (const int32_t*)(b + lay.off_mark_base);
+  k.det_base = (const int32_t*)(b + lay.off_det_base);
+  k.orient_base = (const int32_t*)(b + lay.off_orient_base);
+  k.qctr = (uint32_t*)(b + lay.off_hdr);
+  k.n_entries = lay.n_entries;
+  k.entry = -1;
+  k.cell = p.cell;
+  k.t = t;
+  return k;
+}
+
+}  // namespace
+
+extern "C" {
+
+int of_pyramid_desc_get(int32_t width, int32_t height, const of_params* params,
+                        of_pyramid_desc* out) {
+  int st = check_params(params);
+  if (st) return st;
+  if (!out) return OF_EINVAL;
+  st = check_frame_size(width, height, *params);
+  if (st) return st;
+  FrameGeom g;
+  frame_geom(width, height, *params, &g);
+  memset(out, 0, sizeof(*out));
+  out->n_levels = params->n_levels;
+  int64_t off = 0;
+  for (int l = 0; l < params->n_levels; ++l) {
+    out->width[l] = g.W[l];
+    out->height[l] = g.H[l];
+    out->stride[l] = level_stride(g.W[l]);
+    out->quota[l] = g.quota[l];
+    out->offset[l] = off;
+    off += align_up((int64_t)out->stride[l] * g.H[l], 256);
+  }
+  out->total_bytes = off;
+  return OF_OK;
+}
+
+int of_pyramid_build(const of_image* in, const of_params* params, uint8_t* levels,
+                     hipStream_t stream) {
+  of_pyramid_desc d;
+  int st = check_params(params);
+  if (st) return st;
+  st = check_image(in, *params);
+  if (st) return st;
+  if (!levels) return OF_EINVAL;
+  st = of_pyramid_desc_get(in->width, in->height, params, &d);
+  if (st) return st;
+  PyrArgs a;
+  memset(&a, 0, sizeof(a));
+  a.src = in->data;
+  a.src_w = in->width;
+  a.src_h = in->height;
+  a.src_stride = in->stride;
+  for (int l = 0; l < d.n_levels; ++l) {
+    a.lv[l].dst = levels + d.offset[l];
+    a.lv[l].w = d.width[l];
+    a.lv[l].h = d.height[l];
+    a.lv[l].stride = d.stride[l];
+  }
+  hipError_t e = launch_pyramid(a, d.n_levels, d.width[0], d.height[0], stream);
+  return e == hipSuccess ? OF_OK : hip_fail(e);
+}
+
+int of_workspace_size(const of_image* frames, int32_t n, const of_params* params, size_t* bytes) {
+  if (!bytes) return OF_EINVAL;
+  int st = check_frames(frames, n, params);
+  if (st) return st;
+  CallPlan* cp = new CallPlan;  // the layout does not depend on the tuning
+  plan_call(frames, n, *params, default_tune(*params), cp);
+  *bytes = (size_t)cp->lay.total;
+  delete cp;
+  return OF_OK;
+}
+
+int of_tuning_default(const of_image* frames, int32_t n, const of_params* params,
+                      of_tuning* out) {
+  if (!out) return OF_EINVAL;
+  int st = check_frames(frames, n, params);
+  if (st) return st;
+  const Tune t = default_tune(*params);
+  out->mark_words = t.mark_words;
+  out->mark_rows = t.mark_rows;
+  out->det_cells_x = t.det_cx;
+  out->det_cells_y = t.det_cy;
+  out->det_w = t.det_w;
+  out->det_h = t.det_h;
+  out->mark_grid = t.mark_grid;
+  out->det_grid = t.det_grid;
+  return OF_OK;
+}
+
+int of_detect(const of_image* in, const of_params* params, void* ws, size_t ws_bytes,
+              of_keypoint* out, int32_t cap, int32_t* count, hipStream_t stream) {
+  int st = check_params(params);
+  if (st) return st;
+  st = check_image(in, *params);
+  if (st) return st;
+  if (!ws || !out || !count || cap < params->n_features) return OF_EINVAL;
+  const of_params& p = *params;
+  const Tune t = default_tune(p);
+  CallPlan* c = new CallPlan;
+  plan_call(in, 1, p, t, c);
+  if ((size_t)c->lay.total > ws_bytes) {
+    delete c;
+    return OF_ENOSPACE;
+  }
+  PrologueArgs* pa = new PrologueArgs;
+  fill_prologue(pa, in, 1, p, t, ws, c->lay, out, nullptr, count);
+  hipError_t e = launch_prologue(*pa, stream);
+  delete pa;
+  const int L = p.n_levels;
+  // levels 1.. from the input frame, one launch per level
+  for (int l = 1; l < L && e == hipSuccess; ++l) {
+    PyrArgs a;
+    memset(&a, 0, sizeof(a));
+    a.src = in->data;
+    a.src_w = in->width;
+    a.src_h = in->height;
+    a.src_stride = in->stride;
+    a.lv[0].dst = (uint8_t*)ws + c->lay.off_lvl + c->lvl_off[l];
+    a.lv[0].w = c->geo[0].W[l];
+    a.lv[0].h = c->geo[0].H[l];
+    a.lv[0].stride = level_stride(c->geo[0].W[l]);
+    e = launch_pyramid(a, 1, a.lv[0].w, a.lv[0].h, stream);
+  }
+  KArgs k = kargs(ws, c->lay, t, p);
+  k.persistent = 0;
+  for (int l = 0; l < L && e == hipSuccess; ++l) {
+    k.entry = l;
+    k.total = c->es[l].mark_tiles;
+    e = launch_mark(k, false, k.total, stream);
+  }
+  for (int l = 0; l < L && e == hipSuccess; ++l) {
+    k.entry = l;
+    k.total = c->es[l].det_tiles;
+    e = launch_detect(k, k.total, stream);
+  }
+  for (int l = 0; l < L && e == hipSuccess; ++l) {
+    k.entry = l;
+    k.total = 1;
+    e = launch_select(k, 1, stream);
+  }
+  if (e == hipSuccess) {
+    k.entry = -1;
+    k.total = c->lay.orient_blocks;
+    e = launch_orient(k, k.total, stream);
+  }
+  delete c;
+  return e == hipSuccess ? OF_OK : hip_fail(e);
+}
+
+int of_detect_batch(const of_image* frames, int32_t n, const of_params* params, void* ws,
+                    size_t ws_bytes, of_keypoint* out, const int64_t* out_offset,
+                    int32_t cap_per_frame, int32_t* counts, const of_tuning* tuning,
+                    hipStream_t stream) {
+  int st = check_frames(frames, n, params);
+  if (st) return st;
+  for (int f = 0; f < n; ++f) {
+    st = check_image(&frames[f], *params);
+    if (st) return st;
+  }
+  if (!ws || !out || !out_offset || !counts || cap_per_frame < params->n_features)
+    return OF_EINVAL;
+  const of_params& p = *params;
+  Tune t;
+  st = resolve_tune(tuning, p, &t);
+  if (st) return st;
+  CallPlan* c = new CallPlan;
+  plan_call(frames, n, p, t, c);
+  if ((size_t)c->lay.total > ws_bytes) {
+    delete c;
+    return OF_ENOSPACE;
+  }
+  PrologueArgs* pa = new PrologueArgs;
+  fill_prologue(pa, frames, n, p, t, ws, c->lay, out, out_offset, counts);
+  hipError_t e = launch_prologue(*pa, stream);
+  delete pa;
+  KArgs k = kargs(ws, c->lay, t, p);
+  if (e == hipSuccess) {
+    k.total = c->lay.mark_tiles;
+    k.persistent = t.mark_grid > 0 && t.mark_grid < k.total;
+    e = launch_mark(k, true, k.persistent ? t.mark_grid : k.total, stream);
+  }
+  if (e == hipSuccess) {
+    k.total = c->lay.det_tiles;
+    k.persistent = t.det_grid > 0 && t.det_grid < k.total;
+    e = launch_detect(k, k.persistent ? t.det_grid : k.total, stream);
+  }
+  if (e == hipSuccess) {
+    k.persistent = 0;
+    k.total = c->lay.n_entries;
+    e = launch_select(k, k.total, stream);
+  }
+  if (e == hipSuccess) {
+    k.total = c->lay.orient_blocks;
+    e = launch_orient(k, k.total, stream);
+  }
+  delete c;
+  return e == hipSuccess ? OF_OK : hip_fail(e);
+}
+
+int of_test_segment(const uint8_t* circles, int32_t n, int32_t t_lo, int32_t t_hi,
+                    uint8_t* out, hipStream_t stream) {
+  if (!circles || !out || n < 0 || t_lo < 1 || t_hi < t_lo || t_hi > 255) return OF_EINVAL;
+  if (n == 0) return OF_OK;
+  hipError_t e = launch_test_segment(circles, n, t_lo, t_hi, out, stream);
+  return e == hipSuccess ? OF_OK : hip_fail(e);
+}
+
+const char* of_status_string(int status) {
+  switch (status) {
+    case OF_OK: return "ok";
+    case OF_EINVAL: return "invalid argument (pointer, frame size, parameter, capacity or tuning)";
+    case OF_ENOSPACE: return "workspace smaller than of_workspace_size()";
+    case OF_EHIP: return "HIP launch failed (see of_last_hip_error)";
+    default: return "unknown status";
+  }
+}
+
+int of_last_hip_error(void) { return g_last_hip; }
+
+}  // extern "C"

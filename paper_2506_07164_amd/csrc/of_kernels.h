@@ -1,0 +1,62 @@
+// of_kernels.h -- kernel argument blocks and launch functions (internal).
+#pragma once
+
+#include "of_plan.h"
+
+namespace ofk {
+
+struct FrameIn {
+  const uint8_t* data;
+  int32_t w, h, stride, pad;
+  int64_t out_off;
+};
+
+struct PrologueArgs {
+  of_params p;
+  Tune t;
+  int32_t n;
+  int32_t pad;
+  FrameIn f[kMaxBatch];
+  uint8_t* ws;
+  WsLayout lay;
+  of_keypoint* out;
+  int32_t* counts;
+};
+
+// Arguments of the tile kernels, selection and orientation.
+struct KArgs {
+  LevelPlan* plan;
+  const int32_t* mark_base;    // exclusive prefix of tiles per entry (n_entries + 1)
+  const int32_t* det_base;
+  const int32_t* orient_base;
+  uint32_t* qctr;              // queue counters: [0] segment-test tiles, [2] Harris tiles
+  int32_t n_entries;
+  int32_t total;               // tiles (or blocks) of this launch
+  int32_t entry;               // >= 0: one entry only, tile = blockIdx.x
+  int32_t persistent;          // 1: blocks draw tiles from qctr until exhausted
+  int32_t cell;                // params.cell
+  int32_t pad;
+  Tune t;
+};
+
+struct PyrLevel {
+  uint8_t* dst;
+  int32_t w, h, stride, pad;
+};
+
+struct PyrArgs {
+  const uint8_t* src;
+  int32_t src_w, src_h, src_stride, pad;
+  PyrLevel lv[kMaxLevels];
+};
+
+hipError_t launch_prologue(const PrologueArgs& a, hipStream_t s);
+hipError_t launch_pyramid(const PyrArgs& a, int n_levels, int max_w, int max_h, hipStream_t s);
+hipError_t launch_mark(const KArgs& a, bool fused, int grid, hipStream_t s);
+hipError_t launch_detect(const KArgs& a, int grid, hipStream_t s);
+hipError_t launch_select(const KArgs& a, int grid, hipStream_t s);
+hipError_t launch_orient(const KArgs& a, int grid, hipStream_t s);
+hipError_t launch_test_segment(const uint8_t* circles, int n, int t_lo, int t_hi, uint8_t* out,
+                               hipStream_t s);
+
+}  // namespace ofk

@@ -1,0 +1,973 @@
+// of_kernels.hip -- gfx950 kernels of the Oriented FAST pipeline.
+//
+// Steps (one launch each, over every level of every frame of a call):
+//   k_prologue  -- per-(frame, level) plan, tile prefix sums, zeroed counters and flags
+//   k_pyramid   -- fixed-point bilinear levels (plain path and of_pyramid_build)
+//   k_mark      -- segment test (Eq. 1, run of 9 of 16) at both thresholds over LDS
+//                  tiles; the fused form resamples its tile from the input frame
+//   k_detect    -- cell-aligned tiles: candidates at each cell's threshold, Harris R'
+//                  (Sec. 3.2 / Eq. 4, 7x7 window), 3x3 NMS, per-cell top-K
+//   k_select    -- per-level top-N_l by (R' desc, y asc, x asc), sorted
+//   k_orient    -- intensity-centroid moments over the disk and atan2
+// Wave64 throughout; nothing here is a dense contraction, so there is no MFMA use.
+#include <hip/hip_runtime.h>
+
+#include "of_kernels.h"
+
+namespace ofk {
+
+// ---------------------------------------------------------------- helpers --
+
+__device__ __forceinline__ int imin3(int a, int b, int c) { return min(min(a, b), c); }
+__device__ __forceinline__ int imax3(int a, int b, int c) { return max(max(a, b), c); }
+
+__device__ __forceinline__ uint32_t lanes_below(uint64_t m) {
+  return __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32),
+                                   __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+}
+
+__device__ __forceinline__ int uniform(int v) { return __builtin_amdgcn_readfirstlane(v); }
+
+// Ranking order: higher R' first; equal R' -> smaller y, then smaller x (pos = y<<16|x).
+__device__ __forceinline__ bool better(int64_t sa, uint32_t pa, int64_t sb, uint32_t pb) {
+  return sa > sb || (sa == sb && pa < pb);
+}
+
+// Last entry e with base[e] <= g (base is an exclusive prefix of n + 1 values).
+__device__ __forceinline__ int find_entry(const int32_t* base, int n, int g) {
+  int lo = 0, hi = n - 1;
+  while (lo < hi) {
+    int mid = (lo + hi + 1) >> 1;
+    if (base[mid] <= g) lo = mid; else hi = mid - 1;
+  }
+  return lo;
+}
+
+// Segment test at two thresholds from the centre value and the 16 circle differences
+// d[i] = I_i - I_p.  A bright run of 9 at threshold t exists iff
+// max_s min_{k<9} d[s+k] >= t; a dark run iff -(min_s max_{k<9} d[s+k]) >= t.  Both
+// scores come from 3-input min/max over cyclic windows (3 x 3 = 9 positions).
+// Returns bit 0 = corner at t_lo, bit 1 = corner at t_hi.
+__device__ __forceinline__ uint32_t segment_test2(const int (&d)[16], int t_lo, int t_hi) {
+  int mn3[16], mx3[16];
+#pragma unroll
+  for (int i = 0; i < 16; ++i) {
+    mn3[i] = imin3(d[i], d[(i + 1) & 15], d[(i + 2) & 15]);
+    mx3[i] = imax3(d[i], d[(i + 1) & 15], d[(i + 2) & 15]);
+  }
+  int sb = -1024, sd = 1024;
+#pragma unroll
+  for (int i = 0; i < 16; ++i) {
+    sb = max(sb, imin3(mn3[i], mn3[(i + 3) & 15], mn3[(i + 6) & 15]));
+    sd = min(sd, imax3(mx3[i], mx3[(i + 3) & 15], mx3[(i + 6) & 15]));
+  }
+  int s = max(sb, -sd);
+  return (s >= t_lo ? 1u : 0u) | (s >= t_hi ? 2u : 0u);
+}
+
+// Circle differences around pixel c of an 8-bit tile with row pitch P.  Positions 1..16
+// of the radius-3 Bresenham circle, clockwise from the top, y down.
+__device__ __forceinline__ void circle_diffs(const uint8_t* c, int P, int (&d)[16]) {
+  const int p = c[0];
+  d[0] = c[-3 * P] - p;
+  d[1] = c[-3 * P + 1] - p;
+  d[2] = c[-2 * P + 2] - p;
+  d[3] = c[-P + 3] - p;
+  d[4] = c[3] - p;
+  d[5] = c[P + 3] - p;
+  d[6] = c[2 * P + 2] - p;
+  d[7] = c[3 * P + 1] - p;
+  d[8] = c[3 * P] - p;
+  d[9] = c[3 * P - 1] - p;
+  d[10] = c[2 * P - 2] - p;
+  d[11] = c[P - 3] - p;
+  d[12] = c[-3] - p;
+  d[13] = c[-P - 3] - p;
+  d[14] = c[-2 * P - 2] - p;
+  d[15] = c[-3 * P - 1] - p;
+}
+
+// Copy rows [y0, y1) x cols [x0, x1) of an 8-bit image into LDS (row pitch lp, origin
+// (x0, y0)).  x0 is a multiple of 4; whole 32-bit words are used when the source row
+// allows it, single bytes at a ragged right edge.
+__device__ __forceinline__ void stage_rows(uint8_t* lds, int lp, const uint8_t* src, int stride,
+                                           int row_limit, int x0, int x1, int y0, int y1) {
+  const bool aligned = ((((uintptr_t)src) | (uintptr_t)stride) & 3) == 0;
+  const int nw = (x1 - x0 + 3) >> 2;
+  const int nrow = y1 - y0;
+  for (int i = threadIdx.x; i < nw * nrow; i += blockDim.x) {
+    const int r = i / nw, w = i - r * nw;
+    const int x = x0 + 4 * w;
+    const uint8_t* s = src + (size_t)(y0 + r) * stride + x;
+    uint8_t* d = lds + r * lp + 4 * w;
+    if (aligned && x + 4 <= row_limit) {
+      *(uint32_t*)d = *(const uint32_t*)s;
+    } else {
+      for (int k = 0; k < 4 && x + k < x1; ++k) d[k] = s[k];
+    }
+  }
+}
+
+// Harris R' at LDS pixel (cx, cy): Sobel G_x, G_y (Eq. 4) at the 49 pixels of the 7x7
+// window, summed as Sxx, Syy, Sxy (int32), R' = 25 (Sxx Syy - Sxy^2) - (Sxx + Syy)^2.
+// Separable form: each of the 9 rows gives horizontal differences hd = I[c+1] - I[c-1]
+// and smoothings hs = I[c-1] + 2 I[c] + I[c+1]; two earlier rows stay in registers and
+// G_x = hd[r-1] + 2 hd[r] + hd[r+1], G_y = hs[r+1] - hs[r-1].
+__device__ __forceinline__ void harris_row(const uint8_t* row, int (&hd)[7], int (&hs)[7]) {
+  int v[9];
+#pragma unroll
+  for (int k = 0; k < 9; ++k) v[k] = row[k];
+#pragma unroll
+  for (int c = 0; c < 7; ++c) {
+    hd[c] = v[c + 2] - v[c];
+    hs[c] = v[c] + 2 * v[c + 1] + v[c + 2];
+  }
+}
+
+__device__ __forceinline__ int64_t harris_lds(const uint8_t* pix, int P, int cx, int cy) {
+  int hd0[7], hs0[7], hd1[7], hs1[7];
+  const uint8_t* row = pix + (cy - 4) * P + (cx - 4);
+  harris_row(row, hd0, hs0);
+  harris_row(row + P, hd1, hs1);
+  int sxx = 0, syy = 0, sxy = 0;
+#pragma unroll 1
+  for (int r = 2; r < 9; ++r) {
+    int hd2[7], hs2[7];
+    harris_row(row + r * P, hd2, hs2);
+#pragma unroll
+    for (int c = 0; c < 7; ++c) {
+      const int gx = hd0[c] + 2 * hd1[c] + hd2[c];
+      const int gy = hs2[c] - hs0[c];
+      sxx += gx * gx;
+      syy += gy * gy;
+      sxy += gx * gy;
+      hd0[c] = hd1[c];
+      hd1[c] = hd2[c];
+      hs0[c] = hs1[c];
+      hs1[c] = hs2[c];
+    }
+  }
+  const int64_t a = sxx, b = syy, c = sxy;
+  return 25 * (a * b - c * c) - (a + b) * (a + b);
+}
+
+// Out-of-line Harris for the rare candidates beyond the per-tile score cache.
+__device__ __noinline__ int64_t harris_lds_uncached(const uint8_t* pix, int P, int cx, int cy) {
+  return harris_lds(pix, P, cx, cy);
+}
+
+// Exclusive scan of cnt[0..n) into pre[0..n], pre[n] = total, by the whole block.
+__device__ void block_scan_u32(const uint32_t* cnt, uint32_t* pre, int n, uint32_t* s_wsum) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nwave = blockDim.x >> 6;
+  uint32_t carry = 0;
+  for (int base = 0; base < n; base += blockDim.x) {
+    const int i = base + threadIdx.x;
+    uint32_t v = i < n ? cnt[i] : 0u;
+    uint32_t inc = v;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+      uint32_t t = __shfl_up(inc, o, 64);
+      if (lane >= o) inc += t;
+    }
+    if (lane == 63) s_wsum[wave] = inc;
+    __syncthreads();
+    uint32_t woff = 0, total = 0;
+    for (int w = 0; w < nwave; ++w) {
+      uint32_t s = s_wsum[w];
+      if (w < wave) woff += s;
+      total += s;
+    }
+    if (i < n) pre[i] = carry + woff + inc - v;
+    carry += total;
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) pre[n] = carry;
+  __syncthreads();
+}
+
+// ---------------------------------------------------------------- prologue --
+
+__global__ __launch_bounds__(1024) void k_prologue(PrologueArgs a) {
+  __shared__ int64_t s_scan[1024];
+  __shared__ int64_t s_tot;
+  const int L = a.p.n_levels;
+  const int nL = a.n * L;
+  const int i = threadIdx.x;
+  FrameGeom g;
+  EntrySize s = {};
+  int f = 0, l = 0;
+  if (i < nL) {
+    f = i / L;
+    l = i - f * L;
+    frame_geom(a.f[f].w, a.f[f].h, a.p, &g);
+    entry_size(g, a.p, a.t, l, &s);
+  }
+  // exclusive prefix of one quantity over the entries
+  auto scan = [&](int64_t v) -> int64_t {
+    s_scan[i] = i < nL ? v : 0;
+    __syncthreads();
+    for (int o = 1; o < 1024; o <<= 1) {
+      int64_t t = i >= o ? s_scan[i - o] : 0;
+      __syncthreads();
+      s_scan[i] += t;
+      __syncthreads();
+    }
+    int64_t incl = s_scan[i];
+    if (i == 1023) s_tot = incl;
+    __syncthreads();
+    int64_t r = incl - (i < nL ? v : 0);
+    __syncthreads();
+    return r;
+  };
+  const int64_t o_mark = scan(s.mark_tiles);
+  const int64_t t_mark = s_tot;
+  const int64_t o_det = scan(s.det_tiles);
+  const int64_t t_det = s_tot;
+  const int64_t o_or = scan(s.orient_blocks);
+  const int64_t t_or = s_tot;
+  const int64_t o_flag = scan(s.flag_bytes);
+  const int64_t o_bm = scan(s.bm_words);
+  const int64_t o_cand = scan(s.cand_cap);
+  const int64_t o_sel = scan(s.sel_cap);
+  const int64_t o_lvl = scan(s.lvl_bytes);
+
+  uint8_t* ws = a.ws;
+  LevelPlan* plan = (LevelPlan*)(ws + a.lay.off_plan);
+  int32_t* mark_base = (int32_t*)(ws + a.lay.off_mark_base);
+  int32_t* det_base = (int32_t*)(ws + a.lay.off_det_base);
+  int32_t* or_base = (int32_t*)(ws + a.lay.off_orient_base);
+  uint32_t* counters = (uint32_t*)(ws + a.lay.off_counters);
+  uint32_t* qctr = (uint32_t*)(ws + a.lay.off_hdr);
+
+  if (i < nL) {
+    LevelPlan P;
+    P.W = g.W[l];
+    P.H = g.H[l];
+    P.B = a.p.patch_radius;
+    P.level = l;
+    P.frame = f;
+    P.n_levels = L;
+    P.cs = g.cs[l];
+    P.ncx = g.ncx[l];
+    P.ncy = g.ncy[l];
+    P.quota = g.quota[l];
+    P.kcell = g.kcell[l];
+    P.fast_t = a.p.fast_t;
+    P.fast_t_min = a.p.fast_t_min;
+    P.base = a.f[f].data;
+    P.base_w = a.f[f].w;
+    P.base_h = a.f[f].h;
+    P.base_stride = a.f[f].stride;
+    if (l == 0) {
+      P.lvl = a.f[f].data;
+      P.lvl_w = nullptr;
+      P.lvl_stride = a.f[f].stride;
+    } else {
+      P.lvl_w = ws + a.lay.off_lvl + o_lvl;
+      P.lvl = P.lvl_w;
+      P.lvl_stride = level_stride(P.W);
+    }
+    P.wpr = s.wpr;
+    P.bm_lo = (uint32_t*)(ws + a.lay.off_bm) + o_bm;
+    P.bm_hi = P.bm_lo + (int64_t)s.wpr * P.H;
+    P.flags = ws + a.lay.off_flags + o_flag;
+    P.cand = (Cand*)(ws + a.lay.off_cand) + o_cand;
+    P.cand_count = counters + i;
+    P.cand_cap = (int32_t)s.cand_cap;
+    P.sel = (Cand*)(ws + a.lay.off_sel) + o_sel;
+    P.sel_count = counters + a.lay.n_entries + i;
+    P.mark_tx = s.mark_tx;
+    P.mark_ty = s.mark_ty;
+    P.det_tx = s.det_tx;
+    P.det_ty = s.det_ty;
+    P.det_x0 = s.det_x0;
+    P.det_y0 = s.det_y0;
+    P.det_xend = s.det_xend;
+    P.det_yend = s.det_yend;
+    P.orient_blocks = s.orient_blocks;
+    P.entry0 = f * L;
+    P.out = a.out + a.f[f].out_off;
+    P.count_out = a.counts + f;
+    plan[i] = P;
+    mark_base[i] = (int32_t)o_mark;
+    det_base[i] = (int32_t)o_det;
+    or_base[i] = (int32_t)o_or;
+    counters[i] = 0;
+    counters[a.lay.n_entries + i] = 0;
+  }
+  if (i == 0) {
+    mark_base[nL] = (int32_t)t_mark;
+    det_base[nL] = (int32_t)t_det;
+    or_base[nL] = (int32_t)t_or;
+  }
+  if (i < 64) qctr[i] = 0;
+  // zero the cell flags
+  uint4* fl = (uint4*)(ws + a.lay.off_flags);
+  const int64_t nq = a.lay.flag_bytes / 16;
+  for (int64_t k = i; k < nq; k += blockDim.x) fl[k] = make_uint4(0, 0, 0, 0);
+}
+
+// ----------------------------------------------------------------- pyramid --
+
+// One block = 64 x 16 output pixels of level blockIdx.z; the tap tables of its columns
+// and rows are computed once in LDS.  Weights are Q8; one rounding at the end.
+__global__ __launch_bounds__(256) void k_pyramid(PyrArgs a) {
+  __shared__ uint32_t xt[64], yt[16];
+  const PyrLevel& L = a.lv[blockIdx.z];
+  const int bx = blockIdx.x * 64, by = blockIdx.y * 16;
+  if (bx >= L.w || by >= L.h) return;
+  const int t = threadIdx.x;
+  if (t < 64 && bx + t < L.w) xt[t] = resample_tap(bx + t, a.src_w, L.w);
+  if (t >= 64 && t < 80 && by + t - 64 < L.h) yt[t - 64] = resample_tap(by + t - 64, a.src_h, L.h);
+  __syncthreads();
+  const int lx = t & 63;
+  const int x = bx + lx;
+  if (x >= L.w) return;
+  const uint32_t tx = xt[lx];
+  const int x0 = tx >> 9, wx = tx & 511;
+  const int x1 = min(x0 + 1, a.src_w - 1);
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    const int ly = (t >> 6) * 4 + k;
+    const int y = by + ly;
+    if (y >= L.h) break;
+    const uint32_t ty = yt[ly];
+    const int y0 = ty >> 9, wy = ty & 511;
+    const int y1 = min(y0 + 1, a.src_h - 1);
+    const uint8_t* r0 = a.src + (size_t)y0 * a.src_stride;
+    const uint8_t* r1 = a.src + (size_t)y1 * a.src_stride;
+    const int top = (256 - wx) * r0[x0] + wx * r0[x1];
+    const int bot = (256 - wx) * r1[x0] + wx * r1[x1];
+    L.dst[(size_t)y * L.stride + x] = (uint8_t)(((256 - wy) * top + wy * bot + 32768) >> 16);
+  }
+}
+
+// ------------------------------------------------------------ segment test --
+
+// Next tile index: blockIdx.x once, or drawn from the queue counter until exhausted.
+__device__ __forceinline__ int next_tile(const KArgs& a, int iter, uint32_t* ctr, int* s_tile) {
+  if (!a.persistent) return iter == 0 ? (int)blockIdx.x : a.total;
+  if (threadIdx.x == 0) *s_tile = (int)atomicAdd(ctr, 1u);
+  __syncthreads();
+  return *s_tile;
+}
+
+template <bool FUSED>
+__global__ __launch_bounds__(256) void k_mark(KArgs a) {
+  extern __shared__ __align__(16) uint8_t smem[];
+  __shared__ int s_tile, s_qn;
+  const MarkLds M = mark_lds(a.t);
+  const int TWW = a.t.mark_words;
+  uint8_t* pix = smem;
+  uint16_t* queue = (uint16_t*)(smem + M.off_queue);
+  uint32_t* bml = (uint32_t*)(smem + M.off_bml);
+  uint32_t* bmh = (uint32_t*)(smem + M.off_bmh);
+  uint32_t* xt = (uint32_t*)(smem + M.off_xt);
+  uint32_t* yt = (uint32_t*)(smem + M.off_yt);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nwave = blockDim.x >> 6;
+
+  for (int iter = 0;; ++iter) {
+    const int g = uniform(next_tile(a, iter, a.qctr + 0, &s_tile));
+    if (g >= a.total) break;
+    const int e = a.entry >= 0 ? a.entry : uniform(find_entry(a.mark_base, a.n_entries, g));
+    const int t = a.entry >= 0 ? g : g - a.mark_base[e];
+    const LevelPlan& P = a.plan[e];
+    const int W = P.W, H = P.H, B = P.B;
+    const int tx = t % P.mark_tx, ty = t / P.mark_tx;
+    const int x_t0 = tx * M.tw, x_t1 = min(W, x_t0 + M.tw);
+    const int y_t0 = ty * M.th, y_t1 = min(H, y_t0 + M.th);
+    const int ox = max(0, x_t0 - 4), oy = max(0, y_t0 - 3);
+    const int ex = min(W, x_t1 + 3), ey = min(H, y_t1 + 3);
+    const int nx = ex - ox, ny = ey - oy;
+
+    // 1. level pixels of the tile and its 3-pixel halo
+    if (FUSED && P.level > 0) {
+      for (int i = threadIdx.x; i < nx; i += blockDim.x) xt[i] = resample_tap(ox + i, P.base_w, W);
+      for (int j = threadIdx.x; j < ny; j += blockDim.x) yt[j] = resample_tap(oy + j, P.base_h, H);
+      __syncthreads();
+      const int bw1 = P.base_w - 1, bh1 = P.base_h - 1;
+      for (int j = wave; j < ny; j += nwave) {
+        const uint32_t tyy = yt[j];
+        const int y0 = tyy >> 9, wy = tyy & 511;
+        const uint8_t* r0 = P.base + (size_t)y0 * P.base_stride;
+        const uint8_t* r1 = P.base + (size_t)min(y0 + 1, bh1) * P.base_stride;
+        for (int i = lane; i < nx; i += 64) {
+          const uint32_t txx = xt[i];
+          const int x0 = txx >> 9, wx = txx & 511;
+          const int x1 = min(x0 + 1, bw1);
+          const int top = (256 - wx) * r0[x0] + wx * r0[x1];
+          const int bot = (256 - wx) * r1[x0] + wx * r1[x1];
+          pix[j * M.pitch + i] = (uint8_t)(((256 - wy) * top + wy * bot + 32768) >> 16);
+        }
+      }
+      __syncthreads();
+      // the tile's own pixels go to the level buffer for the later steps
+      const int lx0 = x_t0 - ox;
+      const int nwd = (x_t1 - x_t0 + 3) >> 2;
+      for (int i = threadIdx.x; i < nwd * (y_t1 - y_t0); i += blockDim.x) {
+        const int r = i / nwd, w = i - r * nwd;
+        const int y = y_t0 + r;
+        *(uint32_t*)(P.lvl_w + (size_t)y * P.lvl_stride + x_t0 + 4 * w) =
+            *(const uint32_t*)(pix + (y - oy) * M.pitch + lx0 + 4 * w);
+      }
+    } else {
+      const int limit = P.level == 0 ? W : P.lvl_stride;
+      stage_rows(pix, M.pitch, P.lvl, P.lvl_stride, limit, ox, ex, oy, ey);
+    }
+    for (int i = threadIdx.x; i < 2 * M.th * 2 * TWW; i += blockDim.x) bml[i] = 0u;  // lo and hi
+    if (threadIdx.x == 0) s_qn = 0;
+    __syncthreads();
+
+    // 2. compass pre-test at fast_t_min: a run of 9 holds two cyclically adjacent
+    //    compass points (positions 1/5/9/13), so (n|s) & (e|w) per polarity is necessary.
+    const int tlo = P.fast_t_min, thi = P.fast_t;
+    const int ya = max(y_t0, B), yb = min(y_t1, H - B);
+    const int units = max(0, yb - ya) * TWW;
+    for (int u = wave; u < units; u += nwave) {
+      const int y = ya + u / TWW;
+      const int x = x_t0 + 64 * (u % TWW) + lane;
+      const bool valid = x >= B && x < W - B;
+      const int lx = x - ox, ly = y - oy;
+      bool pass = false;
+      if (valid) {
+        const uint8_t* c = pix + ly * M.pitch + lx;
+        const int p = c[0];
+        const int vn = c[-3 * M.pitch], vs = c[3 * M.pitch], ve = c[3], vw = c[-3];
+        const int hi = p + tlo, lo = p - tlo;
+        const bool b = ((vn >= hi) | (vs >= hi)) & ((ve >= hi) | (vw >= hi));
+        const bool d = ((vn <= lo) | (vs <= lo)) & ((ve <= lo) | (vw <= lo));
+        pass = b | d;
+      }
+      const uint64_t m = __ballot(pass);
+      if (m) {
+        int base = 0;
+        if (lane == 0) base = atomicAdd(&s_qn, __popcll(m));
+        base = __shfl(base, 0, 64);
+        if (pass) queue[base + lanes_below(m)] = (uint16_t)(lx | (ly << 9));
+      }
+    }
+    __syncthreads();
+
+    // 3. full segment test of the queued pixels at both thresholds
+    const int qn = s_qn;
+    for (int q = threadIdx.x; q < qn; q += blockDim.x) {
+      const int ent = queue[q];
+      const int lx = ent & 511, ly = ent >> 9;
+      int d[16];
+      circle_diffs(pix + ly * M.pitch + lx, M.pitch, d);
+      const uint32_t r = segment_test2(d, tlo, thi);
+      if (r) {
+        const int x = ox + lx, y = oy + ly;
+        const int bit = x - x_t0;
+        const int word = (y - y_t0) * 2 * TWW + (bit >> 5);
+        atomicOr(&bml[word], 1u << (bit & 31));
+        if (r & 2u) {
+          atomicOr(&bmh[word], 1u << (bit & 31));
+          P.flags[(y / P.cs) * P.ncx + x / P.cs] = 1;
+        }
+      }
+    }
+    __syncthreads();
+
+    // 4. bitmap words of the tile rows (zero outside the valid region)
+    const int w0 = x_t0 >> 5;
+    const int nwd = min(2 * TWW, P.wpr - w0);
+    for (int i = threadIdx.x; i < nwd * (y_t1 - y_t0); i += blockDim.x) {
+      const int r = i / nwd, k = i - r * nwd;
+      const size_t gi = (size_t)(y_t0 + r) * P.wpr + w0 + k;
+      P.bm_lo[gi] = bml[r * 2 * TWW + k];
+      P.bm_hi[gi] = bmh[r * 2 * TWW + k];
+    }
+    __syncthreads();
+  }
+}
+
+// ------------------------------------------------------- Harris / NMS / cells --
+
+__global__ __launch_bounds__(256) void k_detect(KArgs a) {
+  extern __shared__ __align__(16) uint8_t smem[];
+  __shared__ int s_tile, s_ns, s_ne, s_base;
+  __shared__ uint32_t s_wsum[16];
+  const DetLds D = det_lds(a.t, a.cell);
+  uint8_t* pix = smem;
+  uint64_t* cw = (uint64_t*)(smem + D.off_cw);
+  uint32_t* cpre = (uint32_t*)(smem + D.off_cpre);
+  int64_t* crs = (int64_t*)(smem + D.off_crs);
+  uint32_t* cpos = (uint32_t*)(smem + D.off_cpos);
+  int64_t* srs = (int64_t*)(smem + D.off_srs);
+  uint32_t* spos = (uint32_t*)(smem + D.off_spos);
+  uint16_t* scell = (uint16_t*)(smem + D.off_scell);
+  uint16_t* order = (uint16_t*)(smem + D.off_order);
+  uint16_t* emit = (uint16_t*)(smem + D.off_emit);
+  uint32_t* ccnt = (uint32_t*)(smem + D.off_ccnt);
+  uint32_t* coff = (uint32_t*)(smem + D.off_coff);
+  uint32_t* cfill = (uint32_t*)(smem + D.off_cfill);
+  uint32_t* ucnt = (uint32_t*)(smem + D.off_ucnt);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nwave = blockDim.x >> 6;
+
+  for (int iter = 0;; ++iter) {
+    const int g = uniform(next_tile(a, iter, a.qctr + 2, &s_tile));
+    if (g >= a.total) break;
+    const int e = a.entry >= 0 ? a.entry : uniform(find_entry(a.det_base, a.n_entries, g));
+    const int t = a.entry >= 0 ? g : g - a.det_base[e];
+    const LevelPlan& P = a.plan[e];
+    const int W = P.W, H = P.H, B = P.B, cs = P.cs;
+    const int tx = t % P.det_tx, ty = t / P.det_tx;
+    int vx0, vx1, vy0, vy1, cxa = 0, cya = 0, nlcx = 1, nlcy = 1;
+    if (a.cell > 0) {
+      cxa = P.det_x0 + tx * a.t.det_cx;
+      cya = P.det_y0 + ty * a.t.det_cy;
+      const int cxb = min(cxa + a.t.det_cx, P.det_xend), cyb = min(cya + a.t.det_cy, P.det_yend);
+      nlcx = cxb - cxa;
+      nlcy = cyb - cya;
+      vx0 = max(cxa * cs, B);
+      vx1 = min(cxb * cs, W - B);
+      vy0 = max(cya * cs, B);
+      vy1 = min(cyb * cs, H - B);
+    } else {
+      vx0 = P.det_x0 + tx * a.t.det_w;
+      vx1 = min(vx0 + a.t.det_w, P.det_xend);
+      vy0 = P.det_y0 + ty * a.t.det_h;
+      vy1 = min(vy0 + a.t.det_h, P.det_yend);
+    }
+    const int rx0 = vx0 - 1, ry0 = vy0 - 1;
+    const int rw = vx1 - vx0 + 2, rh = vy1 - vy0 + 2;
+    const int sx0 = max(0, vx0 - 5) & ~3, sy0 = max(0, vy0 - 5);
+    const int sx1 = min(W, vx1 + 5), sy1 = min(H, vy1 + 5);
+    const int nwr = (rw + 63) >> 6;
+    const int nunits = rh * nwr;
+
+    // 1. stage the level pixels of the tile with a 5-pixel halo
+    stage_rows(pix, D.pitch, P.lvl, P.lvl_stride, P.level == 0 ? W : P.lvl_stride, sx0, sx1,
+               sy0, sy1);
+    if (threadIdx.x == 0) {
+      s_ns = 0;
+      s_ne = 0;
+    }
+    // 2. candidate words over tile + ring: corner at the threshold of its own cell
+    for (int u = wave; u < nunits; u += nwave) {
+      const int j = u / nwr, k = u - j * nwr;
+      const int lxr = 64 * k + lane;
+      const int x = rx0 + lxr, y = ry0 + j;
+      bool c = false;
+      if (lxr < rw && x >= B && x < W - B && y >= B && y < H - B) {
+        const size_t wi = (size_t)y * P.wpr + (x >> 5);
+        const uint32_t bit = 1u << (x & 31);
+        if (P.bm_hi[wi] & bit) {
+          c = true;
+        } else if (P.bm_lo[wi] & bit) {
+          c = P.flags[(y / cs) * P.ncx + x / cs] == 0;
+        }
+      }
+      const uint64_t m = __ballot(c);
+      if (lane == 0) {
+        cw[u] = m;
+        ucnt[u] = (uint32_t)__popcll(m);
+      }
+    }
+    __syncthreads();
+    block_scan_u32(ucnt, cpre, nunits, s_wsum);
+    const int ncand = (int)cpre[nunits];
+    // 3. cached candidate positions (raster order) and their Harris scores
+    for (int u = wave; u < nunits; u += nwave) {
+      const uint64_t m = cw[u];
+      if ((m >> lane) & 1ull) {
+        const uint32_t idx = cpre[u] + lanes_below(m);
+        if (idx < (uint32_t)kCandCache) {
+          const int j = u / nwr, k = u - j * nwr;
+          cpos[idx] = ((uint32_t)(ry0 + j) << 16) | (uint32_t)(rx0 + 64 * k + lane);
+        }
+      }
+    }
+    __syncthreads();
+    const int ncache = min(ncand, kCandCache);
+    for (int i = threadIdx.x; i < ncache; i += blockDim.x) {
+      const uint32_t pos = cpos[i];
+      crs[i] = harris_lds(pix, D.pitch, (int)(pos & 0xffff) - sx0, (int)(pos >> 16) - sy0);
+    }
+    __syncthreads();
+    // 4. NMS: a tile candidate survives when it ranks above every candidate neighbour
+    for (int u = wave; u < nunits; u += nwave) {
+      const int j = u / nwr, k = u - j * nwr;
+      const uint64_t m = cw[u];
+      const int lxr = 64 * k + lane;
+      if (!((m >> lane) & 1ull) || j == 0 || j == rh - 1 || lxr == 0 || lxr >= rw - 1) continue;
+      const int x = rx0 + lxr, y = ry0 + j;
+      const uint32_t idx = cpre[u] + lanes_below(m);
+      const int64_t R = idx < (uint32_t)kCandCache
+                            ? crs[idx]
+                            : harris_lds_uncached(pix, D.pitch, x - sx0, y - sy0);
+      const uint32_t pos = ((uint32_t)y << 16) | (uint32_t)x;
+      bool alive = true;
+      for (int dy = -1; dy <= 1 && alive; ++dy) {
+        for (int dx = -1; dx <= 1; ++dx) {
+          if (dx == 0 && dy == 0) continue;
+          const int qj = j + dy, ql = lxr + dx;
+          const int qu = qj * nwr + (ql >> 6);
+          const uint64_t qm = cw[qu];
+          const int qb = ql & 63;
+          if (!((qm >> qb) & 1ull)) continue;
+          const uint32_t qidx = cpre[qu] + (uint32_t)__popcll(qm & ((1ull << qb) - 1ull));
+          const int qx = x + dx, qy = y + dy;
+          const int64_t Rq = qidx < (uint32_t)kCandCache
+                                 ? crs[qidx]
+                                 : harris_lds_uncached(pix, D.pitch, qx - sx0, qy - sy0);
+          if (!better(R, pos, Rq, ((uint32_t)qy << 16) | (uint32_t)qx)) {
+            alive = false;
+            break;
+          }
+        }
+      }
+      if (alive) {
+        const int si = atomicAdd(&s_ns, 1);
+        srs[si] = R;
+        spos[si] = pos;
+        scell[si] = a.cell > 0 ? (uint16_t)((y / cs - cya) * nlcx + (x / cs - cxa)) : 0;
+      }
+    }
+    __syncthreads();
+    const int ns = s_ns;
+    // 5. per-cell top-K (K = quota when the whole level is one cell)
+    if (ns > 0) {
+      const int K = P.kcell;
+      const int ncell = nlcx * nlcy;
+      for (int c = threadIdx.x; c < ncell; c += blockDim.x) {
+        ccnt[c] = 0;
+        cfill[c] = 0;
+      }
+      __syncthreads();
+      for (int s = threadIdx.x; s < ns; s += blockDim.x) atomicAdd(&ccnt[scell[s]], 1u);
+      __syncthreads();
+      if (threadIdx.x == 0) {
+        uint32_t o = 0;
+        for (int c = 0; c < ncell; ++c) {
+          coff[c] = o;
+          o += ccnt[c];
+        }
+      }
+      __syncthreads();
+      for (int s = threadIdx.x; s < ns; s += blockDim.x) {
+        const int c = scell[s];
+        order[coff[c] + atomicAdd(&cfill[c], 1u)] = (uint16_t)s;
+      }
+      __syncthreads();
+      for (int s = threadIdx.x; s < ns; s += blockDim.x) {
+        const int c = scell[s];
+        const uint32_t n = ccnt[c];
+        bool keep = true;
+        if ((int)n > K) {
+          const int64_t R = srs[s];
+          const uint32_t pos = spos[s];
+          int rank = 0;
+          const uint32_t o = coff[c];
+          for (uint32_t q = 0; q < n && rank < K; ++q) {
+            const int s2 = order[o + q];
+            rank += better(srs[s2], spos[s2], R, pos) ? 1 : 0;
+          }
+          keep = rank < K;
+        }
+        if (keep) emit[atomicAdd(&s_ne, 1)] = (uint16_t)s;
+      }
+      __syncthreads();
+      const int ne = s_ne;
+      if (threadIdx.x == 0) s_base = (int)atomicAdd(P.cand_count, (uint32_t)ne);
+      __syncthreads();
+      const int base = s_base;
+      for (int i = threadIdx.x; i < ne; i += blockDim.x) {
+        if (base + i < P.cand_cap) {
+          const int s = emit[i];
+          Cand cd;
+          cd.score = srs[s];
+          cd.pos = spos[s];
+          cd.pad = 0;
+          P.cand[base + i] = cd;
+        }
+      }
+    }
+    __syncthreads();
+  }
+}
+
+// ---------------------------------------------------------- level selection --
+
+__device__ __forceinline__ uint64_t score_key(int64_t s) {
+  return (uint64_t)s ^ 0x8000000000000000ull;
+}
+
+// Bitonic sort of n (power of two) entries in LDS, best first.
+__device__ void bitonic_best_first(int64_t* sc, uint32_t* ps, int n) {
+  for (int k = 2; k <= n; k <<= 1) {
+    for (int j = k >> 1; j > 0; j >>= 1) {
+      for (int i = threadIdx.x; i < n; i += blockDim.x) {
+        const int ixj = i ^ j;
+        if (ixj > i) {
+          const int64_t a = sc[i], b = sc[ixj];
+          const uint32_t pa = ps[i], pb = ps[ixj];
+          const bool first_half = (i & k) == 0;
+          const bool swap = first_half ? better(b, pb, a, pa) : better(a, pa, b, pb);
+          if (swap) {
+            sc[i] = b;
+            sc[ixj] = a;
+            ps[i] = pb;
+            ps[ixj] = pa;
+          }
+        }
+      }
+      __syncthreads();
+    }
+  }
+}
+
+__global__ __launch_bounds__(1024) void k_select(KArgs a) {
+  __shared__ int64_t sc[kSortCap];
+  __shared__ uint32_t ps[kSortCap];
+  __shared__ uint32_t hist[256];
+  __shared__ uint64_t s_prefix;
+  __shared__ uint32_t s_k, s_n, s_eq;
+  const int e = a.entry >= 0 ? a.entry : (int)blockIdx.x;
+  const LevelPlan& P = a.plan[e];
+  const int N = P.quota;
+  const int C = min((int)*P.cand_count, P.cand_cap);
+  const int nout = min(C, N);
+  if (N <= 0 || C <= 0) {
+    if (threadIdx.x == 0) *P.sel_count = 0;
+    return;
+  }
+  int nsort;
+  if (C <= kSortCap) {
+    nsort = C;
+    for (int i = threadIdx.x; i < C; i += blockDim.x) {
+      sc[i] = P.cand[i].score;
+      ps[i] = P.cand[i].pos;
+    }
+  } else {
+    // radix select of the N-th best score, 8 bits at a time from the top
+    if (threadIdx.x == 0) {
+      s_prefix = 0;
+      s_k = (uint32_t)N;
+    }
+    uint64_t mask = 0;
+    for (int shift = 56; shift >= 0; shift -= 8) {
+      for (int i = threadIdx.x; i < 256; i += blockDim.x) hist[i] = 0;
+      __syncthreads();
+      const uint64_t prefix = s_prefix;
+      for (int i = threadIdx.x; i < C; i += blockDim.x) {
+        const uint64_t u = score_key(P.cand[i].score);
+        if ((u & mask) == prefix) atomicAdd(&hist[(u >> shift) & 255u], 1u);
+      }
+      __syncthreads();
+      if (threadIdx.x == 0) {
+        uint32_t acc = 0, k = s_k;
+        int dsel = 0;
+        for (int dgt = 255; dgt >= 0; --dgt) {
+          if (acc + hist[dgt] >= k) {
+            dsel = dgt;
+            break;
+          }
+          acc += hist[dgt];
+        }
+        s_k = k - acc;
+        s_prefix = prefix | ((uint64_t)dsel << shift);
+      }
+      mask |= 255ull << shift;
+      __syncthreads();
+    }
+    const uint64_t T = s_prefix;
+    const uint32_t k_eq = s_k;  // how many entries with score key == T are taken
+    // ties at T: the k_eq smallest positions, again by radix select
+    if (threadIdx.x == 0) s_eq = 0;
+    __syncthreads();
+    for (int i = threadIdx.x; i < C; i += blockDim.x)
+      if (score_key(P.cand[i].score) == T) atomicAdd(&s_eq, 1u);
+    __syncthreads();
+    uint32_t pcut = 0xffffffffu;
+    if (s_eq > k_eq) {
+      if (threadIdx.x == 0) {
+        s_prefix = 0;
+        s_k = k_eq;
+      }
+      uint32_t pmask = 0;
+      for (int shift = 24; shift >= 0; shift -= 8) {
+        for (int i = threadIdx.x; i < 256; i += blockDim.x) hist[i] = 0;
+        __syncthreads();
+        const uint32_t pp = (uint32_t)s_prefix;
+        for (int i = threadIdx.x; i < C; i += blockDim.x) {
+          const Cand cd = P.cand[i];
+          if (score_key(cd.score) == T && (cd.pos & pmask) == pp)
+            atomicAdd(&hist[(cd.pos >> shift) & 255u], 1u);
+        }
+        __syncthreads();
+        if (threadIdx.x == 0) {
+          uint32_t acc = 0, k = s_k;
+          int dsel = 0;
+          for (int dgt = 0; dgt < 256; ++dgt) {
+            if (acc + hist[dgt] >= k) {
+              dsel = dgt;
+              break;
+            }
+            acc += hist[dgt];
+          }
+          s_k = k - acc;
+          s_prefix = pp | ((uint32_t)dsel << shift);
+        }
+        pmask |= 255u << shift;
+        __syncthreads();
+      }
+      pcut = (uint32_t)s_prefix;
+    }
+    if (threadIdx.x == 0) s_n = 0;
+    __syncthreads();
+    for (int i = threadIdx.x; i < C; i += blockDim.x) {
+      const Cand cd = P.cand[i];
+      const uint64_t u = score_key(cd.score);
+      if (u > T || (u == T && cd.pos <= pcut)) {
+        const uint32_t slot = atomicAdd(&s_n, 1u);
+        if (slot < (uint32_t)kSortCap) {
+          sc[slot] = cd.score;
+          ps[slot] = cd.pos;
+        }
+      }
+    }
+    __syncthreads();
+    nsort = min((int)s_n, kSortCap);
+  }
+  int n2 = 1;
+  while (n2 < nsort) n2 <<= 1;
+  for (int i = nsort + threadIdx.x; i < n2; i += blockDim.x) {
+    sc[i] = INT64_MIN;
+    ps[i] = 0xffffffffu;
+  }
+  __syncthreads();
+  bitonic_best_first(sc, ps, n2);
+  for (int i = threadIdx.x; i < nout; i += blockDim.x) {
+    Cand cd;
+    cd.score = sc[i];
+    cd.pos = ps[i];
+    cd.pad = 0;
+    P.sel[i] = cd;
+  }
+  if (threadIdx.x == 0) *P.sel_count = (uint32_t)nout;
+}
+
+// -------------------------------------------------------------- orientation --
+
+// Four waves, each takes four keypoints in turn; lanes cover rows of the disk
+// dx^2 + dy^2 <= r^2 around the keypoint on its own level.
+__global__ __launch_bounds__(256) void k_orient(KArgs a) {
+  const int b = (int)blockIdx.x;
+  const int e = a.entry >= 0 ? a.entry : find_entry(a.orient_base, a.n_entries, b);
+  const int chunk = a.entry >= 0 ? b : b - a.orient_base[e];
+  const LevelPlan& P = a.plan[e];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int nsel = (int)*P.sel_count;
+  int prefix = 0;
+  for (int l = 0; l < P.level; ++l) prefix += (int)*a.plan[P.entry0 + l].sel_count;
+  if (P.level == 0 && chunk == 0 && threadIdx.x == 0) {
+    int total = 0;
+    for (int l = 0; l < P.n_levels; ++l) total += (int)*a.plan[P.entry0 + l].sel_count;
+    *P.count_out = total;
+  }
+  const int r = P.B;
+  const int span = 2 * r + 1;
+  const int cspan = min(span, 64);
+  const int rows_per = 64 / cspan;
+  const int lr = lane / cspan, lc = lane - lr * cspan;
+  const int r2 = r * r;
+  for (int kk = 0; kk < kOrientPerBlock / 4; ++kk) {
+    const int i = chunk * kOrientPerBlock + wave * (kOrientPerBlock / 4) + kk;
+    if (i >= nsel) break;
+    const Cand cd = P.sel[i];
+    const int x = (int)(cd.pos & 0xffff), y = (int)(cd.pos >> 16);
+    int m10 = 0, m01 = 0;
+    if (lr < rows_per) {
+      for (int row0 = 0; row0 < span; row0 += rows_per) {
+        const int dy = row0 + lr - r;
+        if (dy > r) break;
+        const uint8_t* rowp = P.lvl + (size_t)(y + dy) * P.lvl_stride + x;
+        for (int c0 = 0; c0 < span; c0 += cspan) {
+          const int dx = c0 + lc - r;
+          if (dx <= r && dx * dx + dy * dy <= r2) {
+            const int v = rowp[dx];
+            m10 += dx * v;
+            m01 += dy * v;
+          }
+        }
+      }
+    }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+      m10 += __shfl_xor(m10, o, 64);
+      m01 += __shfl_xor(m01, o, 64);
+    }
+    if (lane == 0) {
+      of_keypoint k;
+      k.x = x;
+      k.y = y;
+      k.level = P.level;
+      k.m10 = m10;
+      k.m01 = m01;
+      k.angle = atan2f((float)m01, (float)m10);
+      k.score = cd.score;
+      P.out[prefix + i] = k;
+    }
+  }
+}
+
+// ------------------------------------------------------------ test kernel --
+
+__global__ __launch_bounds__(256) void k_test_segment(const uint8_t* circles, int n, int t_lo,
+                                                      int t_hi, uint8_t* out) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const uint8_t* c = circles + (size_t)i * 17;
+  int d[16];
+  for (int k = 0; k < 16; ++k) d[k] = (int)c[1 + k] - (int)c[0];
+  out[i] = (uint8_t)segment_test2(d, t_lo, t_hi);
+}
+
+// ----------------------------------------------------------------- launches --
+
+hipError_t launch_prologue(const PrologueArgs& a, hipStream_t s) {
+  hipLaunchKernelGGL(k_prologue, dim3(1), dim3(1024), 0, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_pyramid(const PyrArgs& a, int n_levels, int max_w, int max_h, hipStream_t s) {
+  dim3 grid(cdiv(max_w, 64), cdiv(max_h, 16), n_levels);
+  hipLaunchKernelGGL(k_pyramid, grid, dim3(256), 0, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_mark(const KArgs& a, bool fused, int grid, hipStream_t s) {
+  const MarkLds M = mark_lds(a.t);
+  if (fused)
+    hipLaunchKernelGGL(k_mark<true>, dim3(grid), dim3(256), M.bytes, s, a);
+  else
+    hipLaunchKernelGGL(k_mark<false>, dim3(grid), dim3(256), M.bytes, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_detect(const KArgs& a, int grid, hipStream_t s) {
+  const DetLds D = det_lds(a.t, a.cell);
+  hipLaunchKernelGGL(k_detect, dim3(grid), dim3(256), D.bytes, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_select(const KArgs& a, int grid, hipStream_t s) {
+  hipLaunchKernelGGL(k_select, dim3(grid), dim3(1024), 0, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_orient(const KArgs& a, int grid, hipStream_t s) {
+  hipLaunchKernelGGL(k_orient, dim3(grid), dim3(256), 0, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_test_segment(const uint8_t* circles, int n, int t_lo, int t_hi, uint8_t* out,
+                               hipStream_t s) {
+  hipLaunchKernelGGL(k_test_segment, dim3(cdiv(n, 256)), dim3(256), 0, s, circles, n, t_lo, t_hi,
+                     out);
+  return hipGetLastError();
+}
+
+}  // namespace ofk

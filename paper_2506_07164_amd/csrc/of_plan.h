@@ -1,0 +1,296 @@
+// of_plan.h -- launch plan shared by the host library and the gfx950 kernels.
+//
+// The same __host__ __device__ functions size the workspace on the host and fill the
+// per-(frame, level) plan on the device, so both sides agree on every offset.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/of.h"
+
+#define OF_HD __host__ __device__ inline
+
+namespace ofk {
+
+constexpr int kMaxLevels = OF_MAX_LEVELS;
+constexpr int kMaxBatch = OF_MAX_BATCH;
+constexpr int kMaxEntries = kMaxLevels * kMaxBatch;  // (frame, level) pairs per call
+constexpr int kMaxQuota = 4096;                      // keypoints per level
+constexpr int kSortCap = 4096;                       // candidates sorted in LDS at once
+constexpr int kOrientPerBlock = 16;                  // keypoints per orientation block
+constexpr int kMaxDetW = 256, kMaxDetH = 128;        // Harris/NMS tile limits (pixels)
+constexpr int kCandCache = 1024;                     // Harris scores cached per tile
+
+struct Tune {
+  int32_t mark_words, mark_rows;
+  int32_t det_cx, det_cy, det_w, det_h;
+  int32_t mark_grid, det_grid;
+};
+
+// One ranked candidate: R' and (y << 16 | x) in level coordinates.
+struct Cand {
+  int64_t score;
+  uint32_t pos;
+  uint32_t pad;
+};
+
+// Everything a kernel needs about one (frame, level) pair.  Written by the prologue.
+struct LevelPlan {
+  int32_t W, H, B, level, frame, n_levels;
+  int32_t cs, ncx, ncy;        // cell side (whole level when cell == 0) and cell grid
+  int32_t quota, kcell;
+  int32_t fast_t, fast_t_min;
+  const uint8_t* base;         // input frame
+  int32_t base_w, base_h, base_stride;
+  const uint8_t* lvl;          // level pixels (the input frame for level 0)
+  uint8_t* lvl_w;              // writable level buffer (nullptr for level 0)
+  int32_t lvl_stride;
+  uint32_t* bm_lo;             // segment-test bitmaps: bit x of row y in 32-bit words,
+  uint32_t* bm_hi;             //   wpr words per row; lo = corner at fast_t_min
+  int32_t wpr;
+  uint8_t* flags;              // ncx * ncy bytes: 1 = cell holds a fast_t corner
+  Cand* cand;                  // cell winners emitted by the Harris/NMS tiles
+  uint32_t* cand_count;
+  int32_t cand_cap;
+  Cand* sel;                   // level selection, sorted, quota entries
+  uint32_t* sel_count;
+  int32_t mark_tx, mark_ty;    // segment-test tile grid (covers the whole level)
+  int32_t det_tx, det_ty;      // Harris/NMS tile grid (covers the valid region)
+  int32_t det_x0, det_y0;      // first cell column/row (cell > 0) or first pixel (cell == 0)
+  int32_t det_xend, det_yend;  // one past the last cell column/row, or W-B / H-B
+  int32_t orient_blocks;       // orientation blocks of this level
+  int32_t entry0;              // plan index of this frame's level 0
+  of_keypoint* out;            // this frame's output
+  int32_t* count_out;
+};
+
+// ------------------------------------------------------------------ geometry --
+
+OF_HD int32_t cdiv(int32_t a, int32_t b) { return (a + b - 1) / b; }
+OF_HD int64_t align_up(int64_t v, int64_t a) { return (v + a - 1) / a * a; }
+
+// Level size: round-half-up of n / s^l with s = num / den, exact in 64-bit integers.
+OF_HD int32_t level_extent(int32_t n, int l, int32_t num, int32_t den) {
+  int64_t a = 1, b = 1;
+  for (int i = 0; i < l; ++i) {
+    a *= num;
+    b *= den;
+  }
+  return (int32_t)((2 * (int64_t)n * b + a) / (2 * a));
+}
+
+struct FrameGeom {
+  int32_t L;
+  int32_t W[kMaxLevels], H[kMaxLevels], quota[kMaxLevels], kcell[kMaxLevels];
+  int32_t ncx[kMaxLevels], ncy[kMaxLevels], cs[kMaxLevels];
+};
+
+// Level sizes, quotas N_l (area-proportional, floor, level 0 takes the rest) and the
+// per-cell keep count K_l = max(1, ceil(N_l / cells_l)).
+OF_HD void frame_geom(int32_t W0, int32_t H0, const of_params& p, FrameGeom* g) {
+  g->L = p.n_levels;
+  int64_t area = 0;
+  for (int l = 0; l < p.n_levels; ++l) {
+    g->W[l] = level_extent(W0, l, p.scale_num, p.scale_den);
+    g->H[l] = level_extent(H0, l, p.scale_num, p.scale_den);
+    area += (int64_t)g->W[l] * g->H[l];
+  }
+  int32_t rest = p.n_features;
+  for (int l = 1; l < p.n_levels; ++l) {
+    g->quota[l] = (int32_t)(((int64_t)p.n_features * g->W[l] * g->H[l]) / area);
+    rest -= g->quota[l];
+  }
+  g->quota[0] = rest;
+  for (int l = 0; l < p.n_levels; ++l) {
+    int32_t cs = p.cell > 0 ? p.cell : (g->W[l] > g->H[l] ? g->W[l] : g->H[l]);
+    g->cs[l] = cs;
+    g->ncx[l] = cdiv(g->W[l], cs);
+    g->ncy[l] = cdiv(g->H[l], cs);
+    int32_t nc = g->ncx[l] * g->ncy[l];
+    int32_t k = (g->quota[l] + nc - 1) / nc;
+    g->kcell[l] = k < 1 ? 1 : k;
+  }
+}
+
+OF_HD int32_t level_stride(int32_t W) { return (int32_t)align_up(W, 64); }
+
+// Sizes of one (frame, level) entry inside each workspace region.
+struct EntrySize {
+  int32_t mark_tiles, det_tiles, orient_blocks;
+  int64_t bm_words;   // 32-bit words of both bitmaps
+  int64_t flag_bytes;
+  int64_t cand_cap;
+  int64_t sel_cap;
+  int64_t lvl_bytes;
+  // tile grids
+  int32_t mark_tx, mark_ty, det_tx, det_ty, det_x0, det_y0, det_xend, det_yend, wpr;
+};
+
+OF_HD void entry_size(const FrameGeom& g, const of_params& p, const Tune& t, int l,
+                      EntrySize* s) {
+  const int32_t W = g.W[l], H = g.H[l], B = p.patch_radius, cs = g.cs[l];
+  s->mark_tx = cdiv(W, 64 * t.mark_words);
+  s->mark_ty = cdiv(H, t.mark_rows);
+  s->mark_tiles = s->mark_tx * s->mark_ty;
+  s->wpr = 2 * cdiv(W, 64);
+  s->bm_words = 2 * (int64_t)s->wpr * H;
+  s->flag_bytes = align_up((int64_t)g.ncx[l] * g.ncy[l], 16);
+  if (p.cell > 0) {
+    s->det_x0 = B / cs;
+    s->det_y0 = B / cs;
+    s->det_xend = (W - 1 - B) / cs + 1;
+    s->det_yend = (H - 1 - B) / cs + 1;
+    s->det_tx = cdiv(s->det_xend - s->det_x0, t.det_cx);
+    s->det_ty = cdiv(s->det_yend - s->det_y0, t.det_cy);
+  } else {
+    s->det_x0 = B;
+    s->det_y0 = B;
+    s->det_xend = W - B;
+    s->det_yend = H - B;
+    s->det_tx = cdiv(W - 2 * B, t.det_w);
+    s->det_ty = cdiv(H - 2 * B, t.det_h);
+  }
+  // Emitted candidates: at most K per cell, and never more than the NMS survivors,
+  // which are pairwise non-adjacent (at most ceil(w/2) ceil(h/2) in the valid region).
+  // Both bounds hold for any tiling, so the workspace does not depend on the tuning.
+  {
+    const int64_t surv = (int64_t)cdiv(W - 2 * B, 2) * cdiv(H - 2 * B, 2);
+    const int64_t nvx = (W - 1 - B) / cs - B / cs + 1, nvy = (H - 1 - B) / cs - B / cs + 1;
+    const int64_t cells = nvx * nvy * g.kcell[l];
+    s->cand_cap = surv < cells ? surv : cells;
+  }
+  s->det_tiles = s->det_tx * s->det_ty;
+  s->sel_cap = g.quota[l];
+  int32_t ob = cdiv(g.quota[l], kOrientPerBlock);
+  s->orient_blocks = ob < 1 ? 1 : ob;
+  s->lvl_bytes = l == 0 ? 0 : align_up((int64_t)level_stride(W) * H, 256);
+}
+
+// ------------------------------------------------------------ workspace layout --
+
+// Region sizes of a whole call; offsets are from the workspace base (256-aligned).
+struct WsLayout {
+  int64_t off_hdr, off_plan, off_mark_base, off_det_base, off_orient_base, off_counters;
+  int64_t off_flags, off_bm, off_cand, off_sel, off_lvl, total;
+  int32_t n_entries, mark_tiles, det_tiles, orient_blocks;
+  int64_t flag_bytes, bm_words, cand_entries, sel_entries, lvl_bytes;
+};
+
+OF_HD void ws_layout_accumulate(WsLayout* w, const EntrySize& s) {
+  w->n_entries += 1;
+  w->mark_tiles += s.mark_tiles;
+  w->det_tiles += s.det_tiles;
+  w->orient_blocks += s.orient_blocks;
+  w->flag_bytes += s.flag_bytes;
+  w->bm_words += s.bm_words;
+  w->cand_entries += s.cand_cap;
+  w->sel_entries += s.sel_cap;
+  w->lvl_bytes += s.lvl_bytes;
+}
+
+OF_HD void ws_layout_finish(WsLayout* w) {
+  int64_t o = 0;
+  w->off_hdr = o;          o += 256;  // queue counters
+  w->off_plan = o;         o = align_up(o + (int64_t)w->n_entries * sizeof(LevelPlan), 256);
+  w->off_mark_base = o;    o = align_up(o + 4 * ((int64_t)w->n_entries + 1), 256);
+  w->off_det_base = o;     o = align_up(o + 4 * ((int64_t)w->n_entries + 1), 256);
+  w->off_orient_base = o;  o = align_up(o + 4 * ((int64_t)w->n_entries + 1), 256);
+  w->off_counters = o;     o = align_up(o + 8 * (int64_t)w->n_entries, 256);
+  w->off_flags = o;        o = align_up(o + w->flag_bytes, 256);
+  w->off_bm = o;           o = align_up(o + 4 * w->bm_words, 256);
+  w->off_cand = o;         o = align_up(o + (int64_t)sizeof(Cand) * w->cand_entries, 256);
+  w->off_sel = o;          o = align_up(o + (int64_t)sizeof(Cand) * w->sel_entries, 256);
+  w->off_lvl = o;          o = align_up(o + w->lvl_bytes, 256);
+  w->total = o;
+}
+
+// ------------------------------------------------------------------ resample --
+
+// Source tap of output coordinate i on an axis of n_src -> n_dst pixels: pixel centres
+// aligned, position ((2i+1) n_src - n_dst) / (2 n_dst); returns the integer part in the
+// high bits and the Q8 weight (fraction * 256 rounded half to even, 0..256) in the low 9.
+OF_HD uint32_t resample_tap(int32_t i, int32_t n_src, int32_t n_dst) {
+  int32_t num = (2 * i + 1) * n_src - n_dst;
+  int32_t den = 2 * n_dst;
+  int32_t i0 = num / den;
+  int32_t r = num - i0 * den;
+  int32_t a = 256 * r;
+  int32_t q = a / den;
+  int32_t rr = a - q * den;
+  if (2 * rr > den || (2 * rr == den && (q & 1))) ++q;
+  return ((uint32_t)i0 << 9) | (uint32_t)q;
+}
+
+// ------------------------------------------------------------- LDS layouts --
+
+// Segment-test tile: pixels (tile + 3-pixel halo, 4-aligned origin), the queue of
+// pixels that pass the compass pre-test, both bitmaps, and the resample tap tables.
+struct MarkLds {
+  int32_t tw, th, pitch, rows;
+  int32_t off_queue, off_bml, off_bmh, off_xt, off_yt, bytes;
+};
+
+OF_HD MarkLds mark_lds(const Tune& t) {
+  MarkLds m;
+  m.tw = 64 * t.mark_words;
+  m.th = t.mark_rows;
+  m.pitch = m.tw + 8;
+  m.rows = m.th + 6;
+  int32_t o = (int32_t)align_up((int64_t)m.pitch * m.rows, 16);
+  m.off_queue = o;  o += (int32_t)align_up(2 * m.tw * m.th, 16);
+  m.off_bml = o;    o += 4 * m.th * 2 * t.mark_words;
+  m.off_bmh = o;    o += 4 * m.th * 2 * t.mark_words;
+  m.off_xt = o;     o += 4 * m.pitch;
+  m.off_yt = o;     o += 4 * m.rows;
+  m.bytes = (int32_t)align_up(o, 16);
+  return m;
+}
+
+// Harris/NMS tile: staged pixels (tile + 5-pixel halo), candidate words of the tile
+// plus a 1-pixel ring, their prefix counts, the Harris score cache, survivors, cell
+// buckets and the emit list.
+struct DetLds {
+  int32_t mtw, mth;          // largest tile (pixels)
+  int32_t pitch, rows;       // staged pixels
+  int32_t nwr, nunits;       // 64-bit candidate words per ring row, total words
+  int32_t max_surv, max_cells;
+  int32_t off_cw, off_ucnt, off_cpre, off_cpos, off_crs, off_spos, off_srs, off_scell, off_order,
+      off_emit, off_ccnt, off_coff, off_cfill, bytes;
+};
+
+OF_HD DetLds det_lds(const Tune& t, int32_t cell) {
+  DetLds d;
+  if (cell > 0) {
+    d.mtw = t.det_cx * cell;
+    d.mth = t.det_cy * cell;
+    d.max_cells = t.det_cx * t.det_cy;
+  } else {
+    d.mtw = t.det_w;
+    d.mth = t.det_h;
+    d.max_cells = 1;
+  }
+  d.pitch = (int32_t)align_up(d.mtw + 10 + 3, 4);
+  d.rows = d.mth + 10;
+  d.nwr = cdiv(d.mtw + 2, 64);
+  d.nunits = (d.mth + 2) * d.nwr;
+  d.max_surv = cdiv(d.mtw, 2) * cdiv(d.mth, 2);
+  int32_t o = (int32_t)align_up((int64_t)d.pitch * d.rows, 16);
+  d.off_cw = o;     o += 8 * d.nunits;
+  d.off_ucnt = o;   o += (int32_t)align_up(4 * d.nunits, 16);
+  d.off_cpre = o;   o += (int32_t)align_up(4 * (d.nunits + 1), 16);
+  d.off_crs = o;    o += 8 * kCandCache;
+  d.off_cpos = o;   o += 4 * kCandCache;
+  d.off_srs = o;    o += (int32_t)align_up(8 * d.max_surv, 16);
+  d.off_spos = o;   o += (int32_t)align_up(4 * d.max_surv, 16);
+  d.off_scell = o;  o += (int32_t)align_up(2 * d.max_surv, 16);
+  d.off_order = o;  o += (int32_t)align_up(2 * d.max_surv, 16);
+  d.off_emit = o;   o += (int32_t)align_up(2 * d.max_surv, 16);
+  d.off_ccnt = o;   o += (int32_t)align_up(4 * d.max_cells, 16);
+  d.off_coff = o;   o += (int32_t)align_up(4 * d.max_cells, 16);
+  d.off_cfill = o;  o += (int32_t)align_up(4 * d.max_cells, 16);
+  d.bytes = o;
+  return d;
+}
+
+}  // namespace ofk

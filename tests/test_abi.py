@@ -1,0 +1,108 @@
+"""The C-ABI library loads and exports every entry point of include/of.h, and its
+host-only calls (validation, geometry, workspace sizing) behave.  No GPU needed."""
+import ctypes
+import os
+import re
+
+import pytest
+
+import oracle
+from paper_2506_07164_amd import ofhip
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    src = open(os.path.join(ROOT, "include", "of.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(of_[a-z_0-9]+)\s*\(", src)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(ofhip.LIB_PATH):
+        import paper_2506_07164_amd.build as b
+        b.build()
+    return ofhip.lib()
+
+
+def test_exports_every_declared_symbol(lib):
+    names = _declared()
+    assert {"of_pyramid_build", "of_detect", "of_detect_batch"} <= set(names)
+    for n in names:
+        assert hasattr(lib, n), n
+
+
+def test_status_strings(lib):
+    for s in (ofhip.OF_OK, ofhip.OF_EINVAL, ofhip.OF_ENOSPACE, ofhip.OF_EHIP):
+        assert lib.of_status_string(s)
+
+
+def test_pyramid_desc_matches_oracle_geometry(lib):
+    for (W, H, L) in [(1920, 1080, 8), (3840, 2160, 12), (641, 479, 3), (720, 540, 8)]:
+        p = ofhip.params(n_levels=L, n_features=2000 if L < 12 else 5000)
+        d = ofhip.of_pyramid_desc_get(W, H, p)
+        g = oracle.geometry(W, H, oracle.params(n_levels=L, n_features=p.n_features))
+        assert list(d.width[:L]) == g["width"].tolist()
+        assert list(d.height[:L]) == g["height"].tolist()
+        assert list(d.quota[:L]) == g["quota"].tolist()
+        for l in range(L):
+            assert d.stride[l] >= d.width[l] and d.stride[l] % 64 == 0
+            assert d.offset[l] % 256 == 0
+        assert d.total_bytes >= d.offset[L - 1] + d.stride[L - 1] * d.height[L - 1]
+
+
+def test_validation_rejects_bad_arguments(lib):
+    good = ofhip.params()
+    img = ofhip.OfImage(None, 1920, 1080, 1920)
+    assert ofhip.of_workspace_size([img], good) > 0
+    bad = [dict(n_levels=0), dict(n_levels=17), dict(fast_t=0), dict(fast_t_min=21),
+           dict(cell=7), dict(cell=129), dict(harris_block=5), dict(patch_radius=3),
+           dict(scale_num=5, scale_den=5), dict(n_features=0)]
+    for kw in bad:
+        with pytest.raises(ofhip.OfError) as e:
+            ofhip.of_workspace_size([img], ofhip.params(**kw))
+        assert e.value.status == ofhip.OF_EINVAL, kw
+    # a level smaller than 2 * patch_radius + 1
+    with pytest.raises(ofhip.OfError):
+        ofhip.of_workspace_size([ofhip.OfImage(None, 30, 400, 30)], ofhip.params(n_levels=1))
+    # level quota above 4096
+    with pytest.raises(ofhip.OfError):
+        ofhip.of_workspace_size([img], ofhip.params(n_levels=1, n_features=5000))
+    # batch size limits
+    with pytest.raises(ofhip.OfError):
+        ofhip.of_workspace_size([], good)
+    with pytest.raises(ofhip.OfError):
+        ofhip.of_workspace_size([img] * 65, good)
+
+
+def test_detect_argument_errors_before_any_launch(lib):
+    p = ofhip.params(n_levels=1, cell=0, n_features=100, fast_t_min=20)
+    img = ofhip.OfImage(0x1000, 64, 64, 64)
+    # null workspace / output / capacity below n_features: rejected on the host
+    assert lib.of_detect(ctypes.byref(img), ctypes.byref(p), None, 0, 0x1000, 100, 0x1000, None) \
+        == ofhip.OF_EINVAL
+    assert lib.of_detect(ctypes.byref(img), ctypes.byref(p), 0x1000, 1 << 30, 0x1000, 99, 0x1000,
+                         None) == ofhip.OF_EINVAL
+    # workspace too small
+    assert lib.of_detect(ctypes.byref(img), ctypes.byref(p), 0x1000, 16, 0x1000, 100, 0x1000,
+                         None) == ofhip.OF_ENOSPACE
+    # stride below width
+    bad = ofhip.OfImage(0x1000, 64, 64, 63)
+    assert lib.of_detect(ctypes.byref(bad), ctypes.byref(p), 0x1000, 1 << 30, 0x1000, 100,
+                         0x1000, None) == ofhip.OF_EINVAL
+    # tuning outside its ranges
+    imgs = (ofhip.OfImage * 1)(img)
+    offs = (ctypes.c_int64 * 1)(0)
+    for kw in (dict(mark_words=5), dict(mark_rows=65), dict(det_w=300), dict(det_h=4)):
+        t = ofhip.tuning(**kw)
+        assert lib.of_detect_batch(imgs, 1, ctypes.byref(p), 0x1000, 1 << 30, 0x1000, offs, 100,
+                                   0x1000, ctypes.byref(t), None) == ofhip.OF_EINVAL, kw
+    assert lib.of_test_segment(None, 4, 7, 20, 0x1000, None) == ofhip.OF_EINVAL
+
+
+def test_workspace_independent_of_tuning_and_monotone(lib):
+    p = ofhip.params()
+    a = ofhip.of_workspace_size([ofhip.OfImage(None, 1920, 1080, 1920)], p)
+    b = ofhip.of_workspace_size([ofhip.OfImage(None, 1920, 1080, 1920)] * 2, p)
+    assert b > a > 1920 * 1080

@@ -1,0 +1,290 @@
+"""GPU parity: the HIP path through the C ABI against the CPU oracle, bit for bit.
+
+Keypoints, moments and R' must match exactly and in order; angles within 1e-5 rad.
+Every case prints its name before touching the GPU."""
+import numpy as np
+import pytest
+
+import oracle
+from oracle_pool import detect_many
+from parity import assert_same_keypoints
+from synth import CONFIGS, FrameSpec, fig6_pattern_image, make_frame
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+def log(msg):
+    print(msg, flush=True)
+
+
+@pytest.fixture(scope="module")
+def hip():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2506_07164_amd import ofhip
+    ofhip.lib()
+    return ofhip
+
+
+def _kw(**kw):
+    base = dict(n_levels=8, fast_t=20, fast_t_min=7, cell=30, n_features=2000)
+    base.update(kw)
+    return base
+
+
+def run_batch(hip, imgs, kw, tune=None):
+    frames = [torch.from_numpy(i).cuda() for i in imgs]
+    det = hip.Detector([i.shape for i in imgs], hip.params(**kw))
+    det.detect_batch(frames, tune=tune)
+    return det.results()
+
+
+def run_plain(hip, img, kw):
+    frame = torch.from_numpy(img).cuda()
+    det = hip.Detector([img.shape], hip.params(**kw))
+    det.detect_plain(frame)
+    return det.results()[0]
+
+
+# ------------------------------------------------------------ segment test --
+
+def test_segment_test_all_masks(hip):
+    """All 2^16 bright and dark circle masks, differences exactly t (inclusive) and
+    t - 1 (not classified), through the kernel's segment-test routine."""
+    log("case: segment test, 2^16 masks x 2 polarities")
+    masks = np.arange(1 << 16, dtype=np.uint32)
+    bits = ((masks[:, None] >> np.arange(16)) & 1).astype(np.int32)
+    expect = np.array([oracle.run9(int(m)) for m in masks], dtype=np.uint8)
+    for sign in (+1, -1):
+        circ = np.empty((len(masks), 17), np.uint8)
+        circ[:, 0] = 128
+        circ[:, 1:] = 128 + sign * 20 * bits
+        dev = torch.from_numpy(circ).cuda()
+        out = torch.empty(len(masks), dtype=torch.uint8, device="cuda")
+        for t_lo, t_hi, want_lo, want_hi in [(20, 20, expect, expect), (7, 21, expect, 0 * expect),
+                                             (20, 255, expect, 0 * expect)]:
+            hip.of_test_segment(dev.data_ptr(), len(masks), t_lo, t_hi, out.data_ptr(),
+                                hip.stream_ptr())
+            got = out.cpu().numpy()
+            assert np.array_equal(got & 1, want_lo), (sign, t_lo)
+            assert np.array_equal(got >> 1, want_hi), (sign, t_hi)
+
+
+def test_segment_test_random(hip):
+    log("case: segment test, random circles and thresholds")
+    rng = np.random.Generator(np.random.PCG64(5))
+    n = 20000
+    circ = rng.integers(0, 256, (n, 17)).astype(np.uint8)
+    circ[: n // 2, 1:] = np.clip(circ[: n // 2, :1].astype(int) + rng.integers(-40, 41, (n // 2, 16)),
+                                 0, 255)
+    dev = torch.from_numpy(circ).cuda()
+    out = torch.empty(n, dtype=torch.uint8, device="cuda")
+    import bruteforce as bf
+    for t_lo, t_hi in [(7, 20), (1, 1), (30, 90)]:
+        hip.of_test_segment(dev.data_ptr(), n, t_lo, t_hi, out.data_ptr(), hip.stream_ptr())
+        got = out.cpu().numpy()
+        for i in range(0, n, 7):
+            patch = np.zeros((7, 7), np.uint8)
+            patch[3, 3] = circ[i, 0]
+            for k, (dx, dy) in enumerate(bf.CIRCLE):
+                patch[3 + dy, 3 + dx] = circ[i, 1 + k]
+            assert (got[i] & 1) == oracle.segment_test(patch, 3, 3, t_lo), (i, t_lo)
+            assert (got[i] >> 1) == oracle.segment_test(patch, 3, 3, t_hi), (i, t_hi)
+
+
+# ----------------------------------------------------------------- pyramid --
+
+@pytest.mark.parametrize("W,H,L,pad", [(1920, 1080, 8, 0), (641, 479, 4, 3), (3840, 2160, 12, 0)])
+def test_pyramid_build(hip, W, H, L, pad):
+    log(f"case: pyramid {W}x{H} L={L} pad={pad}")
+    img = make_frame(FrameSpec(W, H, 11, 50, 3.0))
+    host = np.zeros((H, W + pad), np.uint8)
+    host[:, :W] = img
+    dev = torch.from_numpy(host).cuda()[:, :W]
+    kw = _kw(n_levels=L, n_features=2000 if L < 12 else 5000)
+    p = hip.params(**kw)
+    d = hip.of_pyramid_desc_get(W, H, p)
+    buf = torch.zeros(d.total_bytes, dtype=torch.uint8, device="cuda")
+    hip.of_pyramid_build(hip.image_of(dev), p, buf.data_ptr(), hip.stream_ptr())
+    host_buf = buf.cpu().numpy()
+    ref = oracle.pyramid(img, oracle.params(**kw))
+    for l in range(L):
+        lv = host_buf[d.offset[l]: d.offset[l] + d.stride[l] * d.height[l]]
+        lv = lv.reshape(d.height[l], d.stride[l])[:, : d.width[l]]
+        assert np.array_equal(lv, ref[l]), f"level {l}"
+
+
+# ------------------------------------------------------- detection: small --
+
+SMALL = [(96, 80, 1), (97, 83, 2), (150, 126, 3), (320, 240, 3), (641, 479, 4), (64, 64, 1)]
+PARAMS = [dict(cell=30, fast_t_min=7), dict(cell=0, fast_t_min=20), dict(cell=16, fast_t_min=9),
+          dict(cell=0, fast_t_min=5)]
+
+
+@pytest.mark.parametrize("W,H,seed", SMALL)
+@pytest.mark.parametrize("pk", range(len(PARAMS)))
+def test_small_frames_plain_and_batch(hip, W, H, seed, pk):
+    L = 1 if min(W, H) < 100 else (2 if min(W, H) < 200 else 4)
+    kw = _kw(n_levels=L, n_features=400, **PARAMS[pk])
+    log(f"case: small {W}x{H} seed={seed} {kw}")
+    img = make_frame(FrameSpec(W, H, seed, 12, 3.0))
+    ref = oracle.detect(img, oracle.params(**kw))
+    assert_same_keypoints(run_plain(hip, img, kw), ref, "plain")
+    assert_same_keypoints(run_batch(hip, [img], kw)[0], ref, "batch")
+
+
+def test_more_features_than_candidates(hip):
+    kw = _kw(n_levels=2, n_features=4000, cell=30)
+    log(f"case: quota above candidates {kw}")
+    img = make_frame(FrameSpec(200, 160, 3, 6, 2.0))
+    ref = oracle.detect(img, oracle.params(**kw))
+    assert len(ref) < 4000
+    assert_same_keypoints(run_batch(hip, [img], kw)[0], ref, "batch")
+    assert_same_keypoints(run_plain(hip, img, kw), ref, "plain")
+
+
+def test_constant_and_square(hip):
+    log("case: constant frame and the square example")
+    kw = _kw(n_levels=1, cell=0, fast_t_min=20, n_features=500)
+    const = np.full((120, 140), 77, np.uint8)
+    assert len(run_batch(hip, [const], kw)[0]) == 0
+    assert len(run_plain(hip, const, kw)) == 0
+    sq = np.full((64, 64), 60, np.uint8)
+    sq[20:44, 20:44] = 160
+    got = run_batch(hip, [sq], kw)[0]
+    assert [(int(k["x"]), int(k["y"])) for k in got] == [(21, 21), (42, 21), (21, 42), (42, 42)]
+    assert set(got["score"].tolist()) == {45_358_400_000_000}
+
+
+@pytest.mark.parametrize("L", [1, 4])
+def test_fig6_pattern_frames(hip, L):
+    from test_oracle_pins import _fig6_cases
+    for case, pos, corner in _fig6_cases():
+        kw = _kw(n_levels=L, cell=0, fast_t_min=20, n_features=4000 if L == 1 else 8000)
+        log(f"case: fig6 {case} L={L}")
+        img = fig6_pattern_image(pos)
+        ref = oracle.detect(img, oracle.params(**kw))
+        assert_same_keypoints(run_batch(hip, [img], kw)[0], ref, f"fig6 {case}")
+
+
+def test_strided_and_unaligned_frames(hip):
+    kw = _kw(n_levels=3, n_features=600)
+    log("case: strided / unaligned frames")
+    imgs = [make_frame(FrameSpec(331, 250, 40 + i, 20, 3.0)) for i in range(3)]
+    host = np.zeros((3, 250, 400), np.uint8)
+    for i in range(3):
+        host[i, :, 1 + i: 1 + i + 331] = imgs[i]
+    dev = torch.from_numpy(host).cuda()
+    frames = [dev[i, :, 1 + i: 1 + i + 331] for i in range(3)]
+    det = hip.Detector([im.shape for im in imgs], hip.params(**kw))
+    det.detect_batch(frames)
+    res = det.results()
+    refs = [oracle.detect(im, oracle.params(**kw)) for im in imgs]
+    for i in range(3):
+        assert_same_keypoints(res[i], refs[i], f"strided {i}")
+    det1 = hip.Detector([imgs[1].shape], hip.params(**kw))
+    det1.detect_plain(frames[1])
+    assert_same_keypoints(det1.results()[0], refs[1], "strided plain")
+
+
+# ------------------------------------------------- detection: the workloads --
+
+def test_c1_plain_and_batch(hip):
+    spec = CONFIGS["c1"]["frames"][0]
+    kw = CONFIGS["c1"]["params"]
+    log(f"case: c1 {spec}")
+    img = make_frame(spec)
+    ref = oracle.detect(img, oracle.params(**kw))
+    assert len(ref) > 50
+    assert_same_keypoints(run_plain(hip, img, kw), ref, "c1 plain")
+    assert_same_keypoints(run_batch(hip, [img], kw)[0], ref, "c1 batch")
+
+
+def test_c2_plain_and_fused(hip):
+    spec = CONFIGS["c2"]["frames"][0]
+    kw = CONFIGS["c2"]["params"]
+    log(f"case: c2 {spec}")
+    img = make_frame(spec)
+    ref = oracle.detect(img, oracle.params(**kw))
+    assert len(ref) == 2000
+    assert_same_keypoints(run_plain(hip, img, kw), ref, "c2 plain")
+    assert_same_keypoints(run_batch(hip, [img], kw)[0], ref, "c2 fused")
+
+
+@pytest.mark.parametrize("tune", [dict(mark_grid=0, det_grid=0), dict(mark_words=1, mark_rows=4),
+                                  dict(mark_words=2, mark_rows=64, det_cells_x=8, det_cells_y=4),
+                                  dict(det_cells_x=1, det_cells_y=1, mark_grid=7, det_grid=3)])
+def test_c2_tunings_agree(hip, tune):
+    spec = CONFIGS["c2"]["frames"][0]
+    kw = CONFIGS["c2"]["params"]
+    log(f"case: c2 tuning {tune}")
+    img = make_frame(spec)
+    ref = oracle.detect(img, oracle.params(**kw))
+    assert_same_keypoints(run_batch(hip, [img], kw, hip.tuning(**tune))[0], ref, str(tune))
+
+
+def test_c3_batch(hip):
+    specs = CONFIGS["c3"]["frames"]
+    kw = CONFIGS["c3"]["params"]
+    log(f"case: c3 batch of {len(specs)}")
+    refs = detect_many(specs, kw)
+    res = run_batch(hip, [make_frame(s) for s in specs], kw)
+    for i, (g, r) in enumerate(zip(res, refs)):
+        assert_same_keypoints(g, r, f"c3 frame {i}")
+
+
+def test_c4_batch(hip):
+    specs = CONFIGS["c4"]["frames"]
+    kw = CONFIGS["c4"]["params"]
+    log(f"case: c4 batch of {len(specs)}")
+    refs = detect_many(specs, kw)
+    res = run_batch(hip, [make_frame(s) for s in specs], kw)
+    for i, (g, r) in enumerate(zip(res, refs)):
+        assert_same_keypoints(g, r, f"c4 frame {i}")
+
+
+def test_batch_equals_alone(hip):
+    kw = _kw(n_levels=4, n_features=800)
+    log("case: batch vs alone")
+    specs = [FrameSpec(w, h, 70 + i, 40, 2.5) for i, (w, h) in
+             enumerate([(400, 300), (257, 199), (512, 384), (333, 333)])]
+    imgs = [make_frame(s) for s in specs]
+    together = run_batch(hip, imgs, kw)
+    for i, img in enumerate(imgs):
+        alone = run_batch(hip, [img], kw)[0]
+        assert_same_keypoints(together[i], alone, f"frame {i} in batch")
+        assert_same_keypoints(alone, oracle.detect(img, oracle.params(**kw)), f"frame {i}")
+
+
+def test_graph_replay(hip):
+    """The batched sequence captured in a HIP graph: every replay (with eager work and
+    syncs in between, and new frame contents) equals the eager result."""
+    kw = CONFIGS["c2"]["params"]
+    log("case: graph capture and replay")
+    specs = [FrameSpec(960, 540, 90 + i, 60, 3.0) for i in range(4)]
+    imgs = [make_frame(s) for s in specs]
+    slots = [torch.empty_like(torch.from_numpy(imgs[0])).cuda() for _ in range(2)]
+    det = hip.Detector([imgs[0].shape] * 2, hip.params(**kw))
+    for s, im in zip(slots, imgs[:2]):
+        s.copy_(torch.from_numpy(im))
+    torch.cuda.synchronize()
+    det.detect_batch(slots)  # warm-up, loads the kernels
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    stream = torch.cuda.Stream()
+    with torch.cuda.stream(stream):
+        with torch.cuda.graph(g, stream=stream):
+            det.detect_batch(slots, stream=stream)
+    refs = {i: oracle.detect(imgs[i], oracle.params(**kw)) for i in range(4)}
+    for rep, pair in enumerate([(0, 1), (2, 3), (1, 0), (3, 2)]):
+        for s, i in zip(slots, pair):
+            s.copy_(torch.from_numpy(imgs[i]))
+        x = torch.randn(1000, device="cuda").sum()  # eager work between replays
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        res = det.results()
+        for k, i in enumerate(pair):
+            assert_same_keypoints(res[k], refs[i], f"replay {rep} slot {k}")
+        del x
