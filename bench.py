@@ -1,0 +1,180 @@
+#!/usr/bin/env python
+"""Oriented FAST over an 8-level pyramid of a 1920x1080 frame on one MI355X.
+
+One step = the whole hot path (pyramid, segment test, Harris, NMS, cell and level
+selection, orientation) over one synthetic 1920x1080 frame, through the C ABI, with the
+frame already resident in HBM.  `value` is frames/s of the fused path (one launch per
+step over all levels, replayed from a HIP graph); the plain path (one launch per level
+and step, eager) is timed beside it.  Prints one JSON line.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+# int32 VALU peak: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz (one op per lane per clock).
+ALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
+# Algorithmic integer ops: 11 per resampled pixel (four Q8 taps, one rounding) and 32 per
+# segment-tested pixel (each circle pixel against I_p - t and I_p + t, Eq. 1).
+OPS_RESAMPLE, OPS_SEGMENT = 11, 32
+
+
+def level_work(shapes, p):
+    """(resampled level pixels, segment-tested pixels) of one step."""
+    from paper_2506_07164_amd import ofhip
+    res = seg = 0
+    B = p.patch_radius
+    for (H, W) in shapes:
+        d = ofhip.of_pyramid_desc_get(W, H, p)
+        for l in range(d.n_levels):
+            w, h = d.width[l], d.height[l]
+            if l > 0:
+                res += w * h
+            seg += (w - 2 * B) * (h - 2 * B)
+    return res, seg
+
+
+def cpu_baseline(img, kw, budget_s=15.0):
+    """The oracle as it stands, one thread, on as many copies of the frame as fit."""
+    import oracle
+    p = oracle.params(**kw)
+    n, t0 = 0, time.perf_counter()
+    while True:
+        oracle.detect(img, p)
+        n += 1
+        el = time.perf_counter() - t0
+        if el > budget_s or n >= 16:
+            break
+    return {"value": n / el, "unit": "frames/s", "cores": 1, "kind": "oracle",
+            "sample": f"{n} frames of the 1920x1080 8-level workload, single-threaded C oracle"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=2000)
+    ap.add_argument("--warmup", type=int, default=50)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU: this build has no multi-GPU path "
+              "(frames shard across GPUs with no exchange; see DESIGN.md)", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    from paper_2506_07164_amd import ofhip
+    from synth import CONFIGS, make_frame
+
+    spec = CONFIGS["c2"]["frames"][0]
+    kw = CONFIGS["c2"]["params"]
+    img = make_frame(spec)
+    p = ofhip.params(**kw)
+    frame = torch.from_numpy(img).cuda()
+    print(f"# workload {spec.width}x{spec.height} L={kw['n_levels']} N={kw['n_features']}",
+          file=sys.stderr, flush=True)
+
+    fused = ofhip.Detector([img.shape], p)
+    plain = ofhip.Detector([img.shape], p)
+    stream = torch.cuda.Stream()
+
+    # warm-up (eager), then capture the fused step in a graph on `stream`
+    with torch.cuda.stream(stream):
+        for _ in range(max(1, args.warmup)):
+            fused.detect_batch([frame], stream=stream)
+            plain.detect_plain(frame, stream=stream)
+    torch.cuda.synchronize()
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.stream(stream):
+        with torch.cuda.graph(graph, stream=stream):
+            fused.detect_batch([frame], stream=stream)
+    for _ in range(args.warmup):
+        graph.replay()
+    torch.cuda.synchronize()
+
+    # timed: fused path, graph replays
+    K = args.steps
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(K):
+        graph.replay()
+    torch.cuda.synchronize()
+    t_fused = time.perf_counter() - t0
+    print(f"# fused {K} steps {t_fused * 1e3:.1f} ms", file=sys.stderr, flush=True)
+
+    # timed: plain path, eager launches
+    Kp = max(1, K // 4)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    with torch.cuda.stream(stream):
+        for _ in range(Kp):
+            plain.detect_plain(frame, stream=stream)
+    torch.cuda.synchronize()
+    t_plain = time.perf_counter() - t0
+    print(f"# plain {Kp} steps {t_plain * 1e3:.1f} ms", file=sys.stderr, flush=True)
+
+    # per-step kernel durations: HIP events around each launch on its stream
+    Kq = max(1, min(K, 1000))
+    ofhip.of_profile_enable(True)
+    with torch.cuda.stream(stream):
+        for _ in range(Kq):
+            fused.detect_batch([frame], stream=stream)
+    torch.cuda.synchronize()
+    prof = ofhip.of_profile_read()
+    ofhip.of_profile_enable(False)
+    step_us = {k: (ms / n * 1e3 if n else 0.0) for k, (ms, n) in prof.items()}
+    print("# fused step means (us): " + ", ".join(f"{k}={v:.2f}" for k, v in step_us.items()),
+          file=sys.stderr, flush=True)
+
+    # correctness of what was timed: same keypoints from both paths
+    got_f = fused.results()[0]
+    got_p = plain.results()[0]
+    assert len(got_f) == len(got_p) == kw["n_features"]
+    for k in ("x", "y", "level", "score", "m10", "m01"):
+        assert np.array_equal(got_f[k], got_p[k]), k
+
+    res_px, seg_px = level_work([img.shape], p)
+    t_mark = step_us["segment_test"] * 1e-6
+    ops = OPS_RESAMPLE * res_px + OPS_SEGMENT * seg_px
+    achieved = ops / t_mark / 1e12 if t_mark > 0 else 0.0
+    roofline = {"bound": "alu", "achieved": round(achieved, 3), "peak": round(ALU_PEAK_TOPS, 2),
+                "unit": "TOP/s", "frac": round(achieved / ALU_PEAK_TOPS, 4), "traffic": None,
+                "kernel": "k_mark<fused> (pyramid + segment test)",
+                "kernel_us": round(step_us["segment_test"], 3)}
+
+    fused_fps = K / t_fused
+    out = {
+        "metric": "frames/sec 1920x1080 8-level Oriented FAST (batched vs plain), HBM GB/s %",
+        "value": round(fused_fps, 1),
+        "unit": "frames/s",
+        "n_gpus": 1,
+        "steps": K,
+        "warmup": args.warmup,
+        "ms_per_step": round(t_fused / K * 1e3, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u8/int32/int64",
+        "data": "synthetic",
+        "config": {"workload": "c2: one 1920x1080 frame, 8-level 1.2 pyramid, FAST 20/7 per "
+                               "30x30 cell, 2000 keypoints, fused path (graph)",
+                   "frames_per_step": 1},
+        "plain_fps": round(Kp / t_plain, 1),
+        "step_us": {k: round(v, 3) for k, v in step_us.items()},
+        "hbm_algorithmic_gbps": round((img.nbytes + 32 * kw["n_features"]) * fused_fps / 1e9, 2),
+        "roofline": roofline,
+    }
+    out["hbm_algorithmic_frac"] = round(out["hbm_algorithmic_gbps"] / 8000.0, 5)
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(img, kw)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

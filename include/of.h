@@ -145,6 +145,17 @@ int of_tuning_default(const of_image* frames, int32_t n, const of_params* params
 int of_test_segment(const uint8_t* circles, int32_t n, int32_t t_lo, int32_t t_hi,
                     uint8_t* out, hipStream_t stream);
 
+/* Step timing.  While enabled (host call, not during graph capture), of_detect and
+ * of_detect_batch record a HIP event on their stream before and after each step launch:
+ * step 0 prologue, 1 pyramid, 2 segment test, 3 Harris/NMS/cells, 4 level selection,
+ * 5 orientation.  of_profile_read waits for the recorded events, writes the summed
+ * milliseconds and launch counts of the first n steps (host arrays) and clears them.
+ * Events come from a fixed pool created on the first enable; launches beyond the pool
+ * are not timed (their count is still reported in launches[]). */
+#define OF_PROFILE_STEPS 6
+int of_profile_enable(int on);
+int of_profile_read(double* ms, int64_t* launches, int32_t n);
+
 const char* of_status_string(int status);
 int of_last_hip_error(void); /* hipError_t of the last OF_EHIP on this thread */
 

@@ -3,6 +3,8 @@
 // of_kernels.hip; this file only checks arguments and queues launches.
 #include <string.h>
 
+#include <mutex>
+
 #include "of_kernels.h"
 
 using namespace ofk;
@@ -10,6 +12,38 @@ using namespace ofk;
 namespace {
 
 thread_local int g_last_hip = 0;
+
+// ------------------------------------------------------------ step profiling --
+
+constexpr int kEventPool = 8192;
+
+struct Profiler {
+  std::mutex mu;
+  bool on = false;
+  bool created = false;
+  hipEvent_t ev[2 * kEventPool];
+  int step_of[kEventPool];
+  int used = 0;
+  int64_t launches[OF_PROFILE_STEPS] = {};
+};
+
+Profiler g_prof;
+
+// Runs `launch` between two events when profiling is on.
+template <class F>
+hipError_t timed(int step, hipStream_t s, F&& launch) {
+  if (!g_prof.on) return launch();
+  std::lock_guard<std::mutex> lk(g_prof.mu);
+  g_prof.launches[step] += 1;
+  if (g_prof.used >= kEventPool) return launch();
+  const int k = g_prof.used++;
+  g_prof.step_of[k] = step;
+  hipError_t e = hipEventRecord(g_prof.ev[2 * k], s);
+  if (e != hipSuccess) return e;
+  e = launch();
+  if (e != hipSuccess) return e;
+  return hipEventRecord(g_prof.ev[2 * k + 1], s);
+}
 
 int hip_fail(hipError_t e) {
   g_last_hip = (int)e;
@@ -271,7 +305,7 @@ int of_detect(const of_image* in, const of_params* params, void* ws, size_t ws_b
   }
   PrologueArgs* pa = new PrologueArgs;
   fill_prologue(pa, in, 1, p, t, ws, c->lay, out, nullptr, count);
-  hipError_t e = launch_prologue(*pa, stream);
+  hipError_t e = timed(0, stream, [&] { return launch_prologue(*pa, stream); });
   delete pa;
   const int L = p.n_levels;
   // levels 1.. from the input frame, one launch per level
@@ -286,29 +320,29 @@ int of_detect(const of_image* in, const of_params* params, void* ws, size_t ws_b
     a.lv[0].w = c->geo[0].W[l];
     a.lv[0].h = c->geo[0].H[l];
     a.lv[0].stride = level_stride(c->geo[0].W[l]);
-    e = launch_pyramid(a, 1, a.lv[0].w, a.lv[0].h, stream);
+    e = timed(1, stream, [&] { return launch_pyramid(a, 1, a.lv[0].w, a.lv[0].h, stream); });
   }
   KArgs k = kargs(ws, c->lay, t, p);
   k.persistent = 0;
   for (int l = 0; l < L && e == hipSuccess; ++l) {
     k.entry = l;
     k.total = c->es[l].mark_tiles;
-    e = launch_mark(k, false, k.total, stream);
+    e = timed(2, stream, [&] { return launch_mark(k, false, k.total, stream); });
   }
   for (int l = 0; l < L && e == hipSuccess; ++l) {
     k.entry = l;
     k.total = c->es[l].det_tiles;
-    e = launch_detect(k, k.total, stream);
+    e = timed(3, stream, [&] { return launch_detect(k, k.total, stream); });
   }
   for (int l = 0; l < L && e == hipSuccess; ++l) {
     k.entry = l;
     k.total = 1;
-    e = launch_select(k, 1, stream);
+    e = timed(4, stream, [&] { return launch_select(k, 1, stream); });
   }
   if (e == hipSuccess) {
     k.entry = -1;
     k.total = c->lay.orient_blocks;
-    e = launch_orient(k, k.total, stream);
+    e = timed(5, stream, [&] { return launch_orient(k, k.total, stream); });
   }
   delete c;
   return e == hipSuccess ? OF_OK : hip_fail(e);
@@ -344,21 +378,21 @@ int of_detect_batch(const of_image* frames, int32_t n, const of_params* params, 
   if (e == hipSuccess) {
     k.total = c->lay.mark_tiles;
     k.persistent = t.mark_grid > 0 && t.mark_grid < k.total;
-    e = launch_mark(k, true, k.persistent ? t.mark_grid : k.total, stream);
+    e = timed(2, stream, [&] { return launch_mark(k, true, k.persistent ? t.mark_grid : k.total, stream); });
   }
   if (e == hipSuccess) {
     k.total = c->lay.det_tiles;
     k.persistent = t.det_grid > 0 && t.det_grid < k.total;
-    e = launch_detect(k, k.persistent ? t.det_grid : k.total, stream);
+    e = timed(3, stream, [&] { return launch_detect(k, k.persistent ? t.det_grid : k.total, stream); });
   }
   if (e == hipSuccess) {
     k.persistent = 0;
     k.total = c->lay.n_entries;
-    e = launch_select(k, k.total, stream);
+    e = timed(4, stream, [&] { return launch_select(k, k.total, stream); });
   }
   if (e == hipSuccess) {
     k.total = c->lay.orient_blocks;
-    e = launch_orient(k, k.total, stream);
+    e = timed(5, stream, [&] { return launch_orient(k, k.total, stream); });
   }
   delete c;
   return e == hipSuccess ? OF_OK : hip_fail(e);
@@ -370,6 +404,42 @@ int of_test_segment(const uint8_t* circles, int32_t n, int32_t t_lo, int32_t t_h
   if (n == 0) return OF_OK;
   hipError_t e = launch_test_segment(circles, n, t_lo, t_hi, out, stream);
   return e == hipSuccess ? OF_OK : hip_fail(e);
+}
+
+int of_profile_enable(int on) {
+  std::lock_guard<std::mutex> lk(g_prof.mu);
+  if (on && !g_prof.created) {
+    for (int i = 0; i < 2 * kEventPool; ++i) {
+      hipError_t e = hipEventCreate(&g_prof.ev[i]);
+      if (e != hipSuccess) {
+        for (int j = 0; j < i; ++j) (void)hipEventDestroy(g_prof.ev[j]);
+        return hip_fail(e);
+      }
+    }
+    g_prof.created = true;
+  }
+  g_prof.on = on != 0;
+  return OF_OK;
+}
+
+int of_profile_read(double* ms, int64_t* launches, int32_t n) {
+  if (!ms || !launches || n < 0 || n > OF_PROFILE_STEPS) return OF_EINVAL;
+  std::lock_guard<std::mutex> lk(g_prof.mu);
+  double acc[OF_PROFILE_STEPS] = {};
+  for (int k = 0; k < g_prof.used; ++k) {
+    float t = 0.f;
+    hipError_t e = hipEventSynchronize(g_prof.ev[2 * k + 1]);
+    if (e == hipSuccess) e = hipEventElapsedTime(&t, g_prof.ev[2 * k], g_prof.ev[2 * k + 1]);
+    if (e != hipSuccess) return hip_fail(e);
+    acc[g_prof.step_of[k]] += t;
+  }
+  for (int i = 0; i < n; ++i) {
+    ms[i] = acc[i];
+    launches[i] = g_prof.launches[i];
+  }
+  g_prof.used = 0;
+  for (int i = 0; i < OF_PROFILE_STEPS; ++i) g_prof.launches[i] = 0;
+  return OF_OK;
 }
 
 const char* of_status_string(int status) {

@@ -151,14 +151,20 @@ OF_HD void entry_size(const FrameGeom& g, const of_params& p, const Tune& t, int
     s->det_tx = cdiv(W - 2 * B, t.det_w);
     s->det_ty = cdiv(H - 2 * B, t.det_h);
   }
-  // Emitted candidates: at most K per cell, and never more than the NMS survivors,
-  // which are pairwise non-adjacent (at most ceil(w/2) ceil(h/2) in the valid region).
-  // Both bounds hold for any tiling, so the workspace does not depend on the tuning.
+  // Emitted candidates never outnumber the NMS survivors, which are pairwise
+  // non-adjacent: at most ceil(w/2) ceil(h/2) over the valid region, for any tiling.
+  // With cells, a cell lies inside one tile and emits at most K_l, which bounds it too;
+  // without cells every tile emits up to K_l of its own, so only the survivor bound
+  // holds.  Neither depends on the tuning, so neither does the workspace.
   {
     const int64_t surv = (int64_t)cdiv(W - 2 * B, 2) * cdiv(H - 2 * B, 2);
-    const int64_t nvx = (W - 1 - B) / cs - B / cs + 1, nvy = (H - 1 - B) / cs - B / cs + 1;
-    const int64_t cells = nvx * nvy * g.kcell[l];
-    s->cand_cap = surv < cells ? surv : cells;
+    int64_t cap = surv;
+    if (p.cell > 0) {
+      const int64_t nvx = (W - 1 - B) / cs - B / cs + 1, nvy = (H - 1 - B) / cs - B / cs + 1;
+      const int64_t cells = nvx * nvy * g.kcell[l];
+      cap = surv < cells ? surv : cells;
+    }
+    s->cand_cap = cap;
   }
   s->det_tiles = s->det_tx * s->det_ty;
   s->sel_cap = g.quota[l];

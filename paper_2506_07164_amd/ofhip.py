@@ -75,6 +75,8 @@ def lib() -> ctypes.CDLL:
                                       i64p, i32, vp, P(OfTuning), vp]
         L.of_tuning_default.argtypes = [P(OfImage), i32, P(OfParams), P(OfTuning)]
         L.of_test_segment.argtypes = [vp, i32, i32, i32, vp, vp]
+        L.of_profile_enable.argtypes = [ctypes.c_int]
+        L.of_profile_read.argtypes = [P(ctypes.c_double), i64p, i32]
         L.of_status_string.argtypes = [ctypes.c_int]
         L.of_status_string.restype = ctypes.c_char_p
         L.of_last_hip_error.argtypes = []
@@ -161,6 +163,23 @@ def of_detect_batch(images, p: OfParams, ws_ptr: int, ws_bytes: int, out_ptr: in
 def of_test_segment(circles_ptr: int, n: int, t_lo: int, t_hi: int, out_ptr: int,
                     stream: int) -> None:
     _check(lib().of_test_segment(circles_ptr, n, t_lo, t_hi, out_ptr, stream), "of_test_segment")
+
+
+OF_PROFILE_STEPS = 6
+PROFILE_STEP_NAMES = ["prologue", "pyramid", "segment_test", "harris_nms_cells", "select",
+                      "orient"]
+
+
+def of_profile_enable(on: bool) -> None:
+    _check(lib().of_profile_enable(1 if on else 0), "of_profile_enable")
+
+
+def of_profile_read():
+    """{step name: (total ms, launches)} since the last read (waits for the events)."""
+    ms = (ctypes.c_double * OF_PROFILE_STEPS)()
+    n = (ctypes.c_int64 * OF_PROFILE_STEPS)()
+    _check(lib().of_profile_read(ms, n, OF_PROFILE_STEPS), "of_profile_read")
+    return {PROFILE_STEP_NAMES[i]: (ms[i], n[i]) for i in range(OF_PROFILE_STEPS)}
 
 
 # ----------------------------------------------------------- torch helpers --
