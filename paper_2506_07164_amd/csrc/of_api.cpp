@@ -188,6 +188,18 @@ void fill_prologue(PrologueArgs* pa, const of_image* frames, int n, const of_par
   pa->lay = lay;
   pa->out = out;
   pa->counts = counts;
+  // FNV-1a over every byte the plan depends on (the struct is zero-filled first, so
+  // padding is deterministic); the prologue rebuilds the plan when this changes.
+  uint64_t h = 1469598103934665603ull;
+  const uint8_t* b = (const uint8_t*)pa;
+  for (size_t i = 0; i < sizeof(*pa); ++i) h = (h ^ b[i]) * 1099511628211ull;
+  pa->sig = h ^ 0x4f46504c414e3031ull;
+}
+
+int prologue_grid(const WsLayout& lay) {
+  const int64_t items = lay.flag_bytes / 16 + 2 * (int64_t)lay.n_entries;
+  const int64_t g = 1 + items / (1024 * 8);
+  return (int)(g < 64 ? g : 64);
 }
 
 KArgs kargs(void* ws, const WsLayout& lay, const Tune& t, const of_params& p) {
@@ -198,12 +210,31 @@ KArgs kargs(void* ws, const WsLayout& lay, const Tune& t, const of_params& p) {
   k.mark_base = (const int32_t*)(b + lay.off_mark_base);
   k.det_base = (const int32_t*)(b + lay.off_det_base);
   k.orient_base = (const int32_t*)(b + lay.off_orient_base);
+  k.rank_base = (const int32_t*)(b + lay.off_rank_base);
+  k.rank_path = 1;
   k.qctr = (uint32_t*)(b + lay.off_hdr);
   k.n_entries = lay.n_entries;
   k.entry = -1;
   k.cell = p.cell;
   k.t = t;
   return k;
+}
+
+// Level selection + orientation: ranks by counting for every level, and the radix
+// select + separate orientation only when some level could exceed kRankCap candidates.
+hipError_t launch_selection(KArgs k, const WsLayout& lay, hipStream_t stream) {
+  k.entry = -1;
+  k.persistent = 0;
+  hipError_t e = timed(4, stream, [&] { return launch_select_orient(k, lay.rank_slots, stream); });
+  if (e == hipSuccess && lay.max_cand_cap > kRankCap) {
+    k.total = lay.n_entries;
+    e = timed(4, stream, [&] { return launch_select(k, lay.n_entries, stream); });
+    if (e == hipSuccess) {
+      k.total = lay.orient_blocks;
+      e = timed(5, stream, [&] { return launch_orient(k, lay.orient_blocks, stream); });
+    }
+  }
+  return e;
 }
 
 }  // namespace
@@ -305,7 +336,7 @@ int of_detect(const of_image* in, const of_params* params, void* ws, size_t ws_b
   }
   PrologueArgs* pa = new PrologueArgs;
   fill_prologue(pa, in, 1, p, t, ws, c->lay, out, nullptr, count);
-  hipError_t e = timed(0, stream, [&] { return launch_prologue(*pa, stream); });
+  hipError_t e = timed(0, stream, [&] { return launch_prologue(*pa, prologue_grid(c->lay), stream); });
   delete pa;
   const int L = p.n_levels;
   // levels 1.. from the input frame, one launch per level
@@ -334,16 +365,7 @@ int of_detect(const of_image* in, const of_params* params, void* ws, size_t ws_b
     k.total = c->es[l].det_tiles;
     e = timed(3, stream, [&] { return launch_detect(k, k.total, stream); });
   }
-  for (int l = 0; l < L && e == hipSuccess; ++l) {
-    k.entry = l;
-    k.total = 1;
-    e = timed(4, stream, [&] { return launch_select(k, 1, stream); });
-  }
-  if (e == hipSuccess) {
-    k.entry = -1;
-    k.total = c->lay.orient_blocks;
-    e = timed(5, stream, [&] { return launch_orient(k, k.total, stream); });
-  }
+  if (e == hipSuccess) e = launch_selection(k, c->lay, stream);
   delete c;
   return e == hipSuccess ? OF_OK : hip_fail(e);
 }
@@ -372,7 +394,7 @@ int of_detect_batch(const of_image* frames, int32_t n, const of_params* params, 
   }
   PrologueArgs* pa = new PrologueArgs;
   fill_prologue(pa, frames, n, p, t, ws, c->lay, out, out_offset, counts);
-  hipError_t e = launch_prologue(*pa, stream);
+  hipError_t e = timed(0, stream, [&] { return launch_prologue(*pa, prologue_grid(c->lay), stream); });
   delete pa;
   KArgs k = kargs(ws, c->lay, t, p);
   if (e == hipSuccess) {
@@ -385,15 +407,7 @@ int of_detect_batch(const of_image* frames, int32_t n, const of_params* params, 
     k.persistent = t.det_grid > 0 && t.det_grid < k.total;
     e = timed(3, stream, [&] { return launch_detect(k, k.persistent ? t.det_grid : k.total, stream); });
   }
-  if (e == hipSuccess) {
-    k.persistent = 0;
-    k.total = c->lay.n_entries;
-    e = timed(4, stream, [&] { return launch_select(k, k.total, stream); });
-  }
-  if (e == hipSuccess) {
-    k.total = c->lay.orient_blocks;
-    e = timed(5, stream, [&] { return launch_orient(k, k.total, stream); });
-  }
+  if (e == hipSuccess) e = launch_selection(k, c->lay, stream);
   delete c;
   return e == hipSuccess ? OF_OK : hip_fail(e);
 }

@@ -12,6 +12,7 @@ struct FrameIn {
 };
 
 struct PrologueArgs {
+  uint64_t sig;                // hash of this struct (sig = 0) plus a tag; caches the plan
   of_params p;
   Tune t;
   int32_t n;
@@ -29,13 +30,14 @@ struct KArgs {
   const int32_t* mark_base;    // exclusive prefix of tiles per entry (n_entries + 1)
   const int32_t* det_base;
   const int32_t* orient_base;
+  const int32_t* rank_base;    // exclusive prefix of ranked candidate slots per entry
   uint32_t* qctr;              // queue counters: [0] segment-test tiles, [2] Harris tiles
   int32_t n_entries;
   int32_t total;               // tiles (or blocks) of this launch
   int32_t entry;               // >= 0: one entry only, tile = blockIdx.x
   int32_t persistent;          // 1: blocks draw tiles from qctr until exhausted
   int32_t cell;                // params.cell
-  int32_t pad;
+  int32_t rank_path;           // 1: k_select_orient ranks levels with <= kRankCap candidates
   Tune t;
 };
 
@@ -50,10 +52,11 @@ struct PyrArgs {
   PyrLevel lv[kMaxLevels];
 };
 
-hipError_t launch_prologue(const PrologueArgs& a, hipStream_t s);
+hipError_t launch_prologue(const PrologueArgs& a, int grid, hipStream_t s);
 hipError_t launch_pyramid(const PyrArgs& a, int n_levels, int max_w, int max_h, hipStream_t s);
 hipError_t launch_mark(const KArgs& a, bool fused, int grid, hipStream_t s);
 hipError_t launch_detect(const KArgs& a, int grid, hipStream_t s);
+hipError_t launch_select_orient(const KArgs& a, int slots, hipStream_t s);
 hipError_t launch_select(const KArgs& a, int grid, hipStream_t s);
 hipError_t launch_orient(const KArgs& a, int grid, hipStream_t s);
 hipError_t launch_test_segment(const uint8_t* circles, int n, int t_lo, int t_hi, uint8_t* out,

@@ -1,20 +1,68 @@
 // of_kernels.hip -- gfx950 kernels of the Oriented FAST pipeline.
 //
 // Steps (one launch each, over every level of every frame of a call):
-//   k_prologue  -- per-(frame, level) plan, tile prefix sums, zeroed counters and flags
-//   k_pyramid   -- fixed-point bilinear levels (plain path and of_pyramid_build)
-//   k_mark      -- segment test (Eq. 1, run of 9 of 16) at both thresholds over LDS
-//                  tiles; the fused form resamples its tile from the input frame
-//   k_detect    -- cell-aligned tiles: candidates at each cell's threshold, Harris R'
-//                  (Sec. 3.2 / Eq. 4, 7x7 window), 3x3 NMS, per-cell top-K
-//   k_select    -- per-level top-N_l by (R' desc, y asc, x asc), sorted
-//   k_orient    -- intensity-centroid moments over the disk and atan2
+//   k_prologue       -- per-(frame, level) plan (cached behind a signature), zeroed
+//                       counters and cell flags
+//   k_pyramid        -- fixed-point bilinear levels (plain path and of_pyramid_build)
+//   k_mark           -- segment test (Eq. 1, run of 9 of 16) at both thresholds over LDS
+//                       tiles; the fused form resamples its tile from the input frame
+//   k_detect         -- cell-aligned tiles: candidates at each cell's threshold, Harris R'
+//                       (Sec. 3.2 / Eq. 4, 7x7 window), 3x3 NMS, per-cell top-K
+//   k_select_orient  -- per-level top-N_l by (R' desc, y asc, x asc) through rank counts,
+//                       fused with the intensity-centroid orientation of each winner
+//   k_select, k_orient -- radix-select fallback for levels with very many candidates
 // Wave64 throughout; nothing here is a dense contraction, so there is no MFMA use.
 #include <hip/hip_runtime.h>
 
 #include "of_kernels.h"
 
 namespace ofk {
+
+template <class T>
+using gptr = __attribute__((address_space(1))) T*;
+
+template <class T>
+__device__ __forceinline__ gptr<T> G(T* p) {
+  return (gptr<T>)p;
+}
+
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+
+// 16-byte candidate records and 32-byte keypoints move as native vectors (class types
+// cannot be copied across address spaces).
+__device__ __forceinline__ Cand load_cand(gptr<const Cand> p) {
+  const u32x4 v = *(gptr<const u32x4>)p;
+  Cand c;
+  c.score = (int64_t)(((uint64_t)v.y << 32) | v.x);
+  c.pos = v.z;
+  c.pad = 0;
+  return c;
+}
+
+__device__ __forceinline__ void store_cand(gptr<Cand> p, int64_t score, uint32_t pos) {
+  u32x4 v;
+  v.x = (uint32_t)(uint64_t)score;
+  v.y = (uint32_t)((uint64_t)score >> 32);
+  v.z = pos;
+  v.w = 0u;
+  *(gptr<u32x4>)p = v;
+}
+
+__device__ __forceinline__ void store_keypoint(gptr<of_keypoint> p, int x, int y, int level,
+                                               int m10, int m01, float angle, int64_t score) {
+  u32x4 a, b;
+  a.x = (uint32_t)x;
+  a.y = (uint32_t)y;
+  a.z = (uint32_t)level;
+  a.w = (uint32_t)m10;
+  b.x = (uint32_t)m01;
+  b.y = __float_as_uint(angle);
+  b.z = (uint32_t)(uint64_t)score;
+  b.w = (uint32_t)((uint64_t)score >> 32);
+  gptr<u32x4> q = (gptr<u32x4>)p;
+  q[0] = a;
+  q[1] = b;
+}
 
 // ---------------------------------------------------------------- helpers --
 
@@ -33,7 +81,7 @@ __device__ __forceinline__ bool better(int64_t sa, uint32_t pa, int64_t sb, uint
   return sa > sb || (sa == sb && pa < pb);
 }
 
-// Last entry e with base[e] <= g (base is an exclusive prefix of n + 1 values).
+// Last index e with base[e] <= g, base non-decreasing with n + 1 entries.
 __device__ __forceinline__ int find_entry(const int32_t* base, int n, int g) {
   int lo = 0, hi = n - 1;
   while (lo < hi) {
@@ -43,11 +91,16 @@ __device__ __forceinline__ int find_entry(const int32_t* base, int n, int g) {
   return lo;
 }
 
-// Segment test at two thresholds from the centre value and the 16 circle differences
-// d[i] = I_i - I_p.  A bright run of 9 at threshold t exists iff
-// max_s min_{k<9} d[s+k] >= t; a dark run iff -(min_s max_{k<9} d[s+k]) >= t.  Both
-// scores come from 3-input min/max over cyclic windows (3 x 3 = 9 positions).
-// Returns bit 0 = corner at t_lo, bit 1 = corner at t_hi.
+__device__ __forceinline__ int wave_sum(int v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+// Segment test at two thresholds from the 16 circle differences d[i] = I_i - I_p.
+// A bright run of 9 at threshold t exists iff max_s min_{k<9} d[s+k] >= t; a dark run
+// iff -(min_s max_{k<9} d[s+k]) >= t.  Both come from 3-input min/max over cyclic
+// windows (3 x 3 = 9 positions).  Returns bit 0 = corner at t_lo, bit 1 = at t_hi.
 __device__ __forceinline__ uint32_t segment_test2(const int (&d)[16], int t_lo, int t_hi) {
   int mn3[16], mx3[16];
 #pragma unroll
@@ -61,11 +114,11 @@ __device__ __forceinline__ uint32_t segment_test2(const int (&d)[16], int t_lo, 
     sb = max(sb, imin3(mn3[i], mn3[(i + 3) & 15], mn3[(i + 6) & 15]));
     sd = min(sd, imax3(mx3[i], mx3[(i + 3) & 15], mx3[(i + 6) & 15]));
   }
-  int s = max(sb, -sd);
+  const int s = max(sb, -sd);
   return (s >= t_lo ? 1u : 0u) | (s >= t_hi ? 2u : 0u);
 }
 
-// Circle differences around pixel c of an 8-bit tile with row pitch P.  Positions 1..16
+// Circle differences around pixel c of an LDS tile with row pitch P.  Positions 1..16
 // of the radius-3 Bresenham circle, clockwise from the top, y down.
 __device__ __forceinline__ void circle_diffs(const uint8_t* c, int P, int (&d)[16]) {
   const int p = c[0];
@@ -88,20 +141,21 @@ __device__ __forceinline__ void circle_diffs(const uint8_t* c, int P, int (&d)[1
 }
 
 // Copy rows [y0, y1) x cols [x0, x1) of an 8-bit image into LDS (row pitch lp, origin
-// (x0, y0)).  x0 is a multiple of 4; whole 32-bit words are used when the source row
-// allows it, single bytes at a ragged right edge.
-__device__ __forceinline__ void stage_rows(uint8_t* lds, int lp, const uint8_t* src, int stride,
-                                           int row_limit, int x0, int x1, int y0, int y1) {
+// (x0, y0)); x0 is a multiple of 4.  Whole 32-bit words where the source row allows,
+// bytes at a ragged right edge.  Loads of one thread are independent, so they overlap.
+__device__ __forceinline__ void stage_rows(uint8_t* lds, int lp, gptr<const uint8_t> src,
+                                           int stride, int row_limit, int x0, int x1, int y0,
+                                           int y1) {
   const bool aligned = ((((uintptr_t)src) | (uintptr_t)stride) & 3) == 0;
   const int nw = (x1 - x0 + 3) >> 2;
-  const int nrow = y1 - y0;
-  for (int i = threadIdx.x; i < nw * nrow; i += blockDim.x) {
+  const int total = nw * (y1 - y0);
+  for (int i = threadIdx.x; i < total; i += blockDim.x) {
     const int r = i / nw, w = i - r * nw;
     const int x = x0 + 4 * w;
-    const uint8_t* s = src + (size_t)(y0 + r) * stride + x;
+    gptr<const uint8_t> s = src + (size_t)(y0 + r) * stride + x;
     uint8_t* d = lds + r * lp + 4 * w;
     if (aligned && x + 4 <= row_limit) {
-      *(uint32_t*)d = *(const uint32_t*)s;
+      *(uint32_t*)d = *(gptr<const uint32_t>)s;
     } else {
       for (int k = 0; k < 4 && x + k < x1; ++k) d[k] = s[k];
     }
@@ -162,18 +216,18 @@ __device__ void block_scan_u32(const uint32_t* cnt, uint32_t* pre, int n, uint32
   uint32_t carry = 0;
   for (int base = 0; base < n; base += blockDim.x) {
     const int i = base + threadIdx.x;
-    uint32_t v = i < n ? cnt[i] : 0u;
+    const uint32_t v = i < n ? cnt[i] : 0u;
     uint32_t inc = v;
 #pragma unroll
     for (int o = 1; o < 64; o <<= 1) {
-      uint32_t t = __shfl_up(inc, o, 64);
+      const uint32_t t = __shfl_up(inc, o, 64);
       if (lane >= o) inc += t;
     }
     if (lane == 63) s_wsum[wave] = inc;
     __syncthreads();
     uint32_t woff = 0, total = 0;
     for (int w = 0; w < nwave; ++w) {
-      uint32_t s = s_wsum[w];
+      const uint32_t s = s_wsum[w];
       if (w < wave) woff += s;
       total += s;
     }
@@ -185,11 +239,90 @@ __device__ void block_scan_u32(const uint32_t* cnt, uint32_t* pre, int n, uint32
   __syncthreads();
 }
 
+// Intensity-centroid moments over the disk dx^2 + dy^2 <= r^2 around (x, y), one wave
+// cooperating: lanes cover rows of the disk, all loads of a batch are issued first.
+__device__ __forceinline__ void wave_moments(gptr<const uint8_t> lvl, int stride, int x, int y,
+                                             int r, int lane, int* m10, int* m01) {
+  const int span = 2 * r + 1;
+  const int cspan = min(span, 64);
+  const int rows_per = 64 / cspan;
+  const int lr = lane / cspan, lc = lane - lr * cspan;
+  const int r2 = r * r;
+  int a = 0, b = 0;
+  if (lr < rows_per) {
+    for (int c0 = 0; c0 < span; c0 += cspan) {
+      const int dx = c0 + lc - r;
+      for (int k0 = 0; k0 * rows_per < span; k0 += 16) {
+        int v[16];
+#pragma unroll
+        for (int k = 0; k < 16; ++k) {
+          const int dy = (k0 + k) * rows_per + lr - r;
+          const bool in = dy <= r && dx <= r && dx * dx + dy * dy <= r2;
+          v[k] = in ? (int)lvl[(size_t)(y + dy) * stride + x + dx] : 0;
+        }
+#pragma unroll
+        for (int k = 0; k < 16; ++k) {
+          const int dy = (k0 + k) * rows_per + lr - r;
+          a += dx * v[k];
+          b += dy * v[k];
+        }
+      }
+    }
+  }
+  *m10 = wave_sum(a);
+  *m01 = wave_sum(b);
+}
+
+// Tile index: blockIdx.x once, or from the queue counter, drawn one tile ahead so the
+// atomic's round trip overlaps the current tile.
+__device__ __forceinline__ void queue_start(const KArgs& a, uint32_t* ctr, int* s_next) {
+  if (a.persistent && threadIdx.x == 0) *s_next = (int)atomicAdd(ctr, 1u);
+}
+
+__device__ __forceinline__ int queue_take(const KArgs& a, int iter, uint32_t* ctr, int* s_next) {
+  if (!a.persistent) return iter == 0 ? (int)blockIdx.x : a.total;
+  __syncthreads();
+  const int g = *s_next;
+  __syncthreads();
+  if (threadIdx.x == 0 && g < a.total) *s_next = (int)atomicAdd(ctr, 1u);
+  return g;
+}
+
+// Copy of an exclusive prefix (n + 1 values) into LDS for entry lookups.
+__device__ __forceinline__ void load_bases(int32_t* s_base, const int32_t* base, int n) {
+  for (int i = threadIdx.x; i <= n; i += blockDim.x) s_base[i] = G(base)[i];
+  __syncthreads();
+}
+
 // ---------------------------------------------------------------- prologue --
 
+// Every block zeroes a share of the counters and cell flags.  Block 0 also checks the
+// signature of the call shape stored in the workspace and rebuilds the plan only when
+// it changed (new frames, sizes, pointers, parameters or tuning).
 __global__ __launch_bounds__(1024) void k_prologue(PrologueArgs a) {
   __shared__ int64_t s_scan[1024];
   __shared__ int64_t s_tot;
+  __shared__ int s_same;
+  uint8_t* ws = a.ws;
+  uint32_t* qctr = (uint32_t*)(ws + a.lay.off_hdr);
+  uint64_t* sig = (uint64_t*)(ws + a.lay.off_hdr + 128);
+  {
+    uint32_t* counters = (uint32_t*)(ws + a.lay.off_counters);
+    const int64_t ncnt = 2 * (int64_t)a.lay.n_entries;
+    uint4* fl = (uint4*)(ws + a.lay.off_flags);
+    const int64_t nq = a.lay.flag_bytes / 16;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    const int64_t t0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    for (int64_t k = t0; k < ncnt; k += stride) G(counters)[k] = 0u;
+    const u32x4 zero = {0u, 0u, 0u, 0u};
+    for (int64_t k = t0; k < nq; k += stride) ((gptr<u32x4>)G(fl))[k] = zero;
+  }
+  if (blockIdx.x != 0) return;
+  if (threadIdx.x < 32) G(qctr)[threadIdx.x] = 0u;
+  if (threadIdx.x == 0) s_same = *G(sig) == a.sig;
+  __syncthreads();
+  if (s_same) return;
+
   const int L = a.p.n_levels;
   const int nL = a.n * L;
   const int i = threadIdx.x;
@@ -202,20 +335,19 @@ __global__ __launch_bounds__(1024) void k_prologue(PrologueArgs a) {
     frame_geom(a.f[f].w, a.f[f].h, a.p, &g);
     entry_size(g, a.p, a.t, l, &s);
   }
-  // exclusive prefix of one quantity over the entries
   auto scan = [&](int64_t v) -> int64_t {
     s_scan[i] = i < nL ? v : 0;
     __syncthreads();
     for (int o = 1; o < 1024; o <<= 1) {
-      int64_t t = i >= o ? s_scan[i - o] : 0;
+      const int64_t t = i >= o ? s_scan[i - o] : 0;
       __syncthreads();
       s_scan[i] += t;
       __syncthreads();
     }
-    int64_t incl = s_scan[i];
+    const int64_t incl = s_scan[i];
     if (i == 1023) s_tot = incl;
     __syncthreads();
-    int64_t r = incl - (i < nL ? v : 0);
+    const int64_t r = incl - (i < nL ? v : 0);
     __syncthreads();
     return r;
   };
@@ -228,16 +360,17 @@ __global__ __launch_bounds__(1024) void k_prologue(PrologueArgs a) {
   const int64_t o_flag = scan(s.flag_bytes);
   const int64_t o_bm = scan(s.bm_words);
   const int64_t o_cand = scan(s.cand_cap);
+  const int64_t o_rank = scan(s.cand_cap < kRankCap ? s.cand_cap : kRankCap);
+  const int64_t t_rank = s_tot;
   const int64_t o_sel = scan(s.sel_cap);
   const int64_t o_lvl = scan(s.lvl_bytes);
 
-  uint8_t* ws = a.ws;
   LevelPlan* plan = (LevelPlan*)(ws + a.lay.off_plan);
   int32_t* mark_base = (int32_t*)(ws + a.lay.off_mark_base);
   int32_t* det_base = (int32_t*)(ws + a.lay.off_det_base);
   int32_t* or_base = (int32_t*)(ws + a.lay.off_orient_base);
+  int32_t* rank_base = (int32_t*)(ws + a.lay.off_rank_base);
   uint32_t* counters = (uint32_t*)(ws + a.lay.off_counters);
-  uint32_t* qctr = (uint32_t*)(ws + a.lay.off_hdr);
 
   if (i < nL) {
     LevelPlan P;
@@ -292,19 +425,17 @@ __global__ __launch_bounds__(1024) void k_prologue(PrologueArgs a) {
     mark_base[i] = (int32_t)o_mark;
     det_base[i] = (int32_t)o_det;
     or_base[i] = (int32_t)o_or;
-    counters[i] = 0;
-    counters[a.lay.n_entries + i] = 0;
+    rank_base[i] = (int32_t)o_rank;
   }
   if (i == 0) {
     mark_base[nL] = (int32_t)t_mark;
     det_base[nL] = (int32_t)t_det;
     or_base[nL] = (int32_t)t_or;
+    rank_base[nL] = (int32_t)t_rank;
   }
-  if (i < 64) qctr[i] = 0;
-  // zero the cell flags
-  uint4* fl = (uint4*)(ws + a.lay.off_flags);
-  const int64_t nq = a.lay.flag_bytes / 16;
-  for (int64_t k = i; k < nq; k += blockDim.x) fl[k] = make_uint4(0, 0, 0, 0);
+  __threadfence();
+  __syncthreads();
+  if (i == 0) *sig = a.sig;
 }
 
 // ----------------------------------------------------------------- pyramid --
@@ -313,7 +444,7 @@ __global__ __launch_bounds__(1024) void k_prologue(PrologueArgs a) {
 // and rows are computed once in LDS.  Weights are Q8; one rounding at the end.
 __global__ __launch_bounds__(256) void k_pyramid(PyrArgs a) {
   __shared__ uint32_t xt[64], yt[16];
-  const PyrLevel& L = a.lv[blockIdx.z];
+  const PyrLevel L = a.lv[blockIdx.z];
   const int bx = blockIdx.x * 64, by = blockIdx.y * 16;
   if (bx >= L.w || by >= L.h) return;
   const int t = threadIdx.x;
@@ -323,39 +454,41 @@ __global__ __launch_bounds__(256) void k_pyramid(PyrArgs a) {
   const int lx = t & 63;
   const int x = bx + lx;
   if (x >= L.w) return;
+  gptr<const uint8_t> src = G(a.src);
   const uint32_t tx = xt[lx];
   const int x0 = tx >> 9, wx = tx & 511;
   const int x1 = min(x0 + 1, a.src_w - 1);
+  int v[4][4];
+  int wy[4];
 #pragma unroll
   for (int k = 0; k < 4; ++k) {
-    const int ly = (t >> 6) * 4 + k;
-    const int y = by + ly;
-    if (y >= L.h) break;
+    const int ly = min((t >> 6) * 4 + k, L.h - 1 - by);
     const uint32_t ty = yt[ly];
-    const int y0 = ty >> 9, wy = ty & 511;
+    const int y0 = ty >> 9;
+    wy[k] = ty & 511;
     const int y1 = min(y0 + 1, a.src_h - 1);
-    const uint8_t* r0 = a.src + (size_t)y0 * a.src_stride;
-    const uint8_t* r1 = a.src + (size_t)y1 * a.src_stride;
-    const int top = (256 - wx) * r0[x0] + wx * r0[x1];
-    const int bot = (256 - wx) * r1[x0] + wx * r1[x1];
-    L.dst[(size_t)y * L.stride + x] = (uint8_t)(((256 - wy) * top + wy * bot + 32768) >> 16);
+    v[k][0] = src[(size_t)y0 * a.src_stride + x0];
+    v[k][1] = src[(size_t)y0 * a.src_stride + x1];
+    v[k][2] = src[(size_t)y1 * a.src_stride + x0];
+    v[k][3] = src[(size_t)y1 * a.src_stride + x1];
+  }
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    const int y = by + (t >> 6) * 4 + k;
+    if (y >= L.h) break;
+    const int top = (256 - wx) * v[k][0] + wx * v[k][1];
+    const int bot = (256 - wx) * v[k][2] + wx * v[k][3];
+    G(L.dst)[(size_t)y * L.stride + x] = (uint8_t)(((256 - wy[k]) * top + wy[k] * bot + 32768) >> 16);
   }
 }
 
 // ------------------------------------------------------------ segment test --
 
-// Next tile index: blockIdx.x once, or drawn from the queue counter until exhausted.
-__device__ __forceinline__ int next_tile(const KArgs& a, int iter, uint32_t* ctr, int* s_tile) {
-  if (!a.persistent) return iter == 0 ? (int)blockIdx.x : a.total;
-  if (threadIdx.x == 0) *s_tile = (int)atomicAdd(ctr, 1u);
-  __syncthreads();
-  return *s_tile;
-}
-
 template <bool FUSED>
 __global__ __launch_bounds__(256) void k_mark(KArgs a) {
   extern __shared__ __align__(16) uint8_t smem[];
-  __shared__ int s_tile, s_qn;
+  __shared__ int s_next, s_qn;
+  __shared__ int32_t s_base[kMaxEntries + 1];
   const MarkLds M = mark_lds(a.t);
   const int TWW = a.t.mark_words;
   uint8_t* pix = smem;
@@ -365,13 +498,15 @@ __global__ __launch_bounds__(256) void k_mark(KArgs a) {
   uint32_t* xt = (uint32_t*)(smem + M.off_xt);
   uint32_t* yt = (uint32_t*)(smem + M.off_yt);
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nwave = blockDim.x >> 6;
+  if (a.entry < 0) load_bases(s_base, a.mark_base, a.n_entries);
+  queue_start(a, a.qctr + 0, &s_next);
 
   for (int iter = 0;; ++iter) {
-    const int g = uniform(next_tile(a, iter, a.qctr + 0, &s_tile));
+    const int g = uniform(queue_take(a, iter, a.qctr + 0, &s_next));
     if (g >= a.total) break;
-    const int e = a.entry >= 0 ? a.entry : uniform(find_entry(a.mark_base, a.n_entries, g));
-    const int t = a.entry >= 0 ? g : g - a.mark_base[e];
-    const LevelPlan& P = a.plan[e];
+    const int e = a.entry >= 0 ? a.entry : uniform(find_entry(s_base, a.n_entries, g));
+    const int t = a.entry >= 0 ? g : g - s_base[e];
+    const LevelPlan P = a.plan[e];
     const int W = P.W, H = P.H, B = P.B;
     const int tx = t % P.mark_tx, ty = t / P.mark_tx;
     const int x_t0 = tx * M.tw, x_t1 = min(W, x_t0 + M.tw);
@@ -385,36 +520,65 @@ __global__ __launch_bounds__(256) void k_mark(KArgs a) {
       for (int i = threadIdx.x; i < nx; i += blockDim.x) xt[i] = resample_tap(ox + i, P.base_w, W);
       for (int j = threadIdx.x; j < ny; j += blockDim.x) yt[j] = resample_tap(oy + j, P.base_h, H);
       __syncthreads();
-      const int bw1 = P.base_w - 1, bh1 = P.base_h - 1;
-      for (int j = wave; j < ny; j += nwave) {
-        const uint32_t tyy = yt[j];
-        const int y0 = tyy >> 9, wy = tyy & 511;
-        const uint8_t* r0 = P.base + (size_t)y0 * P.base_stride;
-        const uint8_t* r1 = P.base + (size_t)min(y0 + 1, bh1) * P.base_stride;
-        for (int i = lane; i < nx; i += 64) {
-          const uint32_t txx = xt[i];
-          const int x0 = txx >> 9, wx = txx & 511;
-          const int x1 = min(x0 + 1, bw1);
-          const int top = (256 - wx) * r0[x0] + wx * r0[x1];
-          const int bot = (256 - wx) * r1[x0] + wx * r1[x1];
-          pix[j * M.pitch + i] = (uint8_t)(((256 - wy) * top + wy * bot + 32768) >> 16);
+      // two rows per wave per pass, up to 5 columns per lane: 40 gathers in flight
+      gptr<const uint8_t> base = G(P.base);
+      const int bs = P.base_stride, bw1 = P.base_w - 1, bh1 = P.base_h - 1;
+      for (int j0 = wave; j0 < ny; j0 += 2 * nwave) {
+        int v[2][5][4];
+        int wyr[2];
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+          const int j = min(j0 + h * nwave, ny - 1);
+          const uint32_t tyy = yt[j];
+          const int y0 = tyy >> 9;
+          wyr[h] = tyy & 511;
+          gptr<const uint8_t> r0 = base + (size_t)y0 * bs;
+          gptr<const uint8_t> r1 = base + (size_t)min(y0 + 1, bh1) * bs;
+#pragma unroll
+          for (int c = 0; c < 5; ++c) {
+            const int i = min(lane + 64 * c, nx - 1);
+            const uint32_t txx = xt[i];
+            const int x0 = txx >> 9;
+            const int x1 = min(x0 + 1, bw1);
+            v[h][c][0] = r0[x0];
+            v[h][c][1] = r0[x1];
+            v[h][c][2] = r1[x0];
+            v[h][c][3] = r1[x1];
+          }
+        }
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+          const int j = j0 + h * nwave;
+          if (j >= ny) break;
+          const int wy = wyr[h];
+#pragma unroll
+          for (int c = 0; c < 5; ++c) {
+            const int i = lane + 64 * c;
+            if (i < nx) {
+              const int wx = xt[i] & 511;
+              const int top = (256 - wx) * v[h][c][0] + wx * v[h][c][1];
+              const int bot = (256 - wx) * v[h][c][2] + wx * v[h][c][3];
+              pix[j * M.pitch + i] = (uint8_t)(((256 - wy) * top + wy * bot + 32768) >> 16);
+            }
+          }
         }
       }
       __syncthreads();
       // the tile's own pixels go to the level buffer for the later steps
       const int lx0 = x_t0 - ox;
       const int nwd = (x_t1 - x_t0 + 3) >> 2;
+      gptr<uint8_t> lw = G(P.lvl_w);
       for (int i = threadIdx.x; i < nwd * (y_t1 - y_t0); i += blockDim.x) {
         const int r = i / nwd, w = i - r * nwd;
         const int y = y_t0 + r;
-        *(uint32_t*)(P.lvl_w + (size_t)y * P.lvl_stride + x_t0 + 4 * w) =
+        *(gptr<uint32_t>)(lw + (size_t)y * P.lvl_stride + x_t0 + 4 * w) =
             *(const uint32_t*)(pix + (y - oy) * M.pitch + lx0 + 4 * w);
       }
     } else {
       const int limit = P.level == 0 ? W : P.lvl_stride;
-      stage_rows(pix, M.pitch, P.lvl, P.lvl_stride, limit, ox, ex, oy, ey);
+      stage_rows(pix, M.pitch, G(P.lvl), P.lvl_stride, limit, ox, ex, oy, ey);
     }
-    for (int i = threadIdx.x; i < 2 * M.th * 2 * TWW; i += blockDim.x) bml[i] = 0u;  // lo and hi
+    for (int i = threadIdx.x; i < 2 * M.th * 2 * TWW; i += blockDim.x) bml[i] = 0u;  // lo, hi
     if (threadIdx.x == 0) s_qn = 0;
     __syncthreads();
 
@@ -440,16 +604,17 @@ __global__ __launch_bounds__(256) void k_mark(KArgs a) {
       }
       const uint64_t m = __ballot(pass);
       if (m) {
-        int base = 0;
-        if (lane == 0) base = atomicAdd(&s_qn, __popcll(m));
-        base = __shfl(base, 0, 64);
-        if (pass) queue[base + lanes_below(m)] = (uint16_t)(lx | (ly << 9));
+        int qb = 0;
+        if (lane == 0) qb = atomicAdd(&s_qn, __popcll(m));
+        qb = __shfl(qb, 0, 64);
+        if (pass) queue[qb + lanes_below(m)] = (uint16_t)(lx | (ly << 9));
       }
     }
     __syncthreads();
 
     // 3. full segment test of the queued pixels at both thresholds
     const int qn = s_qn;
+    gptr<uint8_t> flags = G(P.flags);
     for (int q = threadIdx.x; q < qn; q += blockDim.x) {
       const int ent = queue[q];
       const int lx = ent & 511, ly = ent >> 9;
@@ -463,7 +628,7 @@ __global__ __launch_bounds__(256) void k_mark(KArgs a) {
         atomicOr(&bml[word], 1u << (bit & 31));
         if (r & 2u) {
           atomicOr(&bmh[word], 1u << (bit & 31));
-          P.flags[(y / P.cs) * P.ncx + x / P.cs] = 1;
+          flags[(y / P.cs) * P.ncx + x / P.cs] = 1;
         }
       }
     }
@@ -472,13 +637,13 @@ __global__ __launch_bounds__(256) void k_mark(KArgs a) {
     // 4. bitmap words of the tile rows (zero outside the valid region)
     const int w0 = x_t0 >> 5;
     const int nwd = min(2 * TWW, P.wpr - w0);
+    gptr<uint32_t> glo = G(P.bm_lo), ghi = G(P.bm_hi);
     for (int i = threadIdx.x; i < nwd * (y_t1 - y_t0); i += blockDim.x) {
       const int r = i / nwd, k = i - r * nwd;
       const size_t gi = (size_t)(y_t0 + r) * P.wpr + w0 + k;
-      P.bm_lo[gi] = bml[r * 2 * TWW + k];
-      P.bm_hi[gi] = bmh[r * 2 * TWW + k];
+      glo[gi] = bml[r * 2 * TWW + k];
+      ghi[gi] = bmh[r * 2 * TWW + k];
     }
-    __syncthreads();
   }
 }
 
@@ -486,11 +651,13 @@ __global__ __launch_bounds__(256) void k_mark(KArgs a) {
 
 __global__ __launch_bounds__(256) void k_detect(KArgs a) {
   extern __shared__ __align__(16) uint8_t smem[];
-  __shared__ int s_tile, s_ns, s_ne, s_base;
+  __shared__ int s_next, s_ns, s_ne, s_base_out;
   __shared__ uint32_t s_wsum[16];
+  __shared__ int32_t s_base[kMaxEntries + 1];
   const DetLds D = det_lds(a.t, a.cell);
   uint8_t* pix = smem;
   uint64_t* cw = (uint64_t*)(smem + D.off_cw);
+  uint32_t* ucnt = (uint32_t*)(smem + D.off_ucnt);
   uint32_t* cpre = (uint32_t*)(smem + D.off_cpre);
   int64_t* crs = (int64_t*)(smem + D.off_crs);
   uint32_t* cpos = (uint32_t*)(smem + D.off_cpos);
@@ -502,15 +669,19 @@ __global__ __launch_bounds__(256) void k_detect(KArgs a) {
   uint32_t* ccnt = (uint32_t*)(smem + D.off_ccnt);
   uint32_t* coff = (uint32_t*)(smem + D.off_coff);
   uint32_t* cfill = (uint32_t*)(smem + D.off_cfill);
-  uint32_t* ucnt = (uint32_t*)(smem + D.off_ucnt);
+  uint32_t* wlo = (uint32_t*)(smem + D.off_wlo);
+  uint32_t* whi = (uint32_t*)(smem + D.off_whi);
+  uint8_t* lfl = smem + D.off_lfl;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nwave = blockDim.x >> 6;
+  if (a.entry < 0) load_bases(s_base, a.det_base, a.n_entries);
+  queue_start(a, a.qctr + 2, &s_next);
 
   for (int iter = 0;; ++iter) {
-    const int g = uniform(next_tile(a, iter, a.qctr + 2, &s_tile));
+    const int g = uniform(queue_take(a, iter, a.qctr + 2, &s_next));
     if (g >= a.total) break;
-    const int e = a.entry >= 0 ? a.entry : uniform(find_entry(a.det_base, a.n_entries, g));
-    const int t = a.entry >= 0 ? g : g - a.det_base[e];
-    const LevelPlan& P = a.plan[e];
+    const int e = a.entry >= 0 ? a.entry : uniform(find_entry(s_base, a.n_entries, g));
+    const int t = a.entry >= 0 ? g : g - s_base[e];
+    const LevelPlan P = a.plan[e];
     const int W = P.W, H = P.H, B = P.B, cs = P.cs;
     const int tx = t % P.det_tx, ty = t / P.det_tx;
     int vx0, vx1, vy0, vy1, cxa = 0, cya = 0, nlcx = 1, nlcy = 1;
@@ -536,14 +707,33 @@ __global__ __launch_bounds__(256) void k_detect(KArgs a) {
     const int sx1 = min(W, vx1 + 5), sy1 = min(H, vy1 + 5);
     const int nwr = (rw + 63) >> 6;
     const int nunits = rh * nwr;
+    // bitmap words and cells touched by the tile and its 1-pixel ring
+    const int bw0 = rx0 >> 5, nbw = ((rx0 + rw - 1) >> 5) - bw0 + 1;
+    const int fcx0 = rx0 / cs, fcy0 = ry0 / cs;
+    const int nfx = (rx0 + rw - 1) / cs - fcx0 + 1, nfy = (ry0 + rh - 1) / cs - fcy0 + 1;
 
-    // 1. stage the level pixels of the tile with a 5-pixel halo
-    stage_rows(pix, D.pitch, P.lvl, P.lvl_stride, P.level == 0 ? W : P.lvl_stride, sx0, sx1,
+    // 1. one batch of independent loads: pixels (5-pixel halo), bitmap words, flags
+    stage_rows(pix, D.pitch, G(P.lvl), P.lvl_stride, P.level == 0 ? W : P.lvl_stride, sx0, sx1,
                sy0, sy1);
+    {
+      gptr<const uint32_t> glo = G((const uint32_t*)P.bm_lo), ghi = G((const uint32_t*)P.bm_hi);
+      for (int i = threadIdx.x; i < rh * nbw; i += blockDim.x) {
+        const int r = i / nbw, k = i - r * nbw;
+        const size_t gi = (size_t)(ry0 + r) * P.wpr + bw0 + k;
+        wlo[i] = glo[gi];
+        whi[i] = ghi[gi];
+      }
+      gptr<const uint8_t> gfl = G((const uint8_t*)P.flags);
+      for (int i = threadIdx.x; i < nfx * nfy; i += blockDim.x) {
+        const int r = i / nfx, k = i - r * nfx;
+        lfl[i] = gfl[(fcy0 + r) * P.ncx + fcx0 + k];
+      }
+    }
     if (threadIdx.x == 0) {
       s_ns = 0;
       s_ne = 0;
     }
+    __syncthreads();
     // 2. candidate words over tile + ring: corner at the threshold of its own cell
     for (int u = wave; u < nunits; u += nwave) {
       const int j = u / nwr, k = u - j * nwr;
@@ -551,12 +741,12 @@ __global__ __launch_bounds__(256) void k_detect(KArgs a) {
       const int x = rx0 + lxr, y = ry0 + j;
       bool c = false;
       if (lxr < rw && x >= B && x < W - B && y >= B && y < H - B) {
-        const size_t wi = (size_t)y * P.wpr + (x >> 5);
+        const int wi = j * nbw + (x >> 5) - bw0;
         const uint32_t bit = 1u << (x & 31);
-        if (P.bm_hi[wi] & bit) {
+        if (whi[wi] & bit) {
           c = true;
-        } else if (P.bm_lo[wi] & bit) {
-          c = P.flags[(y / cs) * P.ncx + x / cs] == 0;
+        } else if (wlo[wi] & bit) {
+          c = lfl[(y / cs - fcy0) * nfx + x / cs - fcx0] == 0;
         }
       }
       const uint64_t m = __ballot(c);
@@ -670,25 +860,73 @@ __global__ __launch_bounds__(256) void k_detect(KArgs a) {
       }
       __syncthreads();
       const int ne = s_ne;
-      if (threadIdx.x == 0) s_base = (int)atomicAdd(P.cand_count, (uint32_t)ne);
+      if (threadIdx.x == 0) s_base_out = (int)atomicAdd(P.cand_count, (uint32_t)ne);
       __syncthreads();
-      const int base = s_base;
+      const int base = s_base_out;
+      gptr<Cand> out = G(P.cand);
       for (int i = threadIdx.x; i < ne; i += blockDim.x) {
         if (base + i < P.cand_cap) {
           const int s = emit[i];
-          Cand cd;
-          cd.score = srs[s];
-          cd.pos = spos[s];
-          cd.pad = 0;
-          P.cand[base + i] = cd;
+          store_cand(out + base + i, srs[s], spos[s]);
         }
       }
     }
-    __syncthreads();
   }
 }
 
-// ---------------------------------------------------------- level selection --
+// ------------------------------------------- level selection + orientation --
+
+// One wave per candidate slot.  A candidate's rank is the number of candidates of its
+// level that rank above it; ranks of the N_l best are exactly their sorted positions, so
+// the wave that holds rank < N_l computes the orientation and writes its keypoint at
+// out[level prefix + rank].  Levels whose candidate count exceeds kRankCap are left to
+// the radix-select path.
+__global__ __launch_bounds__(256) void k_select_orient(KArgs a) {
+  __shared__ int32_t s_base[kMaxEntries + 1];
+  load_bases(s_base, a.rank_base, a.n_entries);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int slot = (int)blockIdx.x * (blockDim.x >> 6) + wave;
+  if (slot >= s_base[a.n_entries]) return;
+  const int e = uniform(find_entry(s_base, a.n_entries, slot));
+  const int i = slot - s_base[e];
+  const LevelPlan P = a.plan[e];
+  gptr<const uint32_t> counts = G((const uint32_t*)P.cand_count) - e;  // all entries
+  const int C = min((int)counts[e], P.cand_cap);
+  if (P.level == 0 && i == 0 && lane == 0) {
+    int total = 0;
+    for (int l = 0; l < P.n_levels; ++l) {
+      const LevelPlan& Q = a.plan[P.entry0 + l];
+      total += min(min((int)counts[P.entry0 + l], Q.cand_cap), Q.quota);
+    }
+    *G(P.count_out) = total;
+  }
+  if (i >= C || C > kRankCap) return;
+  gptr<const Cand> cand = G((const Cand*)P.cand);
+  const Cand me = load_cand(cand + i);
+  int cnt = 0;
+  for (int j0 = 0; j0 < C; j0 += 64) {
+    const int j = j0 + lane;
+    if (j < C) {
+      const Cand o = load_cand(cand + j);
+      cnt += better(o.score, o.pos, me.score, me.pos) ? 1 : 0;
+    }
+  }
+  const int rank = wave_sum(cnt);
+  if (rank >= P.quota) return;
+  int prefix = 0;
+  for (int l = 0; l < P.level; ++l) {
+    const LevelPlan& Q = a.plan[P.entry0 + l];
+    prefix += min(min((int)counts[P.entry0 + l], Q.cand_cap), Q.quota);
+  }
+  const int x = (int)(me.pos & 0xffff), y = (int)(me.pos >> 16);
+  int m10, m01;
+  wave_moments(G(P.lvl), P.lvl_stride, x, y, P.B, lane, &m10, &m01);
+  if (lane == 0)
+    store_keypoint(G(P.out) + prefix + rank, x, y, P.level, m10, m01,
+                   atan2f((float)m01, (float)m10), me.score);
+}
+
+// ----------------------------------------------- radix-select fallback path --
 
 __device__ __forceinline__ uint64_t score_key(int64_t s) {
   return (uint64_t)s ^ 0x8000000000000000ull;
@@ -701,15 +939,15 @@ __device__ void bitonic_best_first(int64_t* sc, uint32_t* ps, int n) {
       for (int i = threadIdx.x; i < n; i += blockDim.x) {
         const int ixj = i ^ j;
         if (ixj > i) {
-          const int64_t a = sc[i], b = sc[ixj];
-          const uint32_t pa = ps[i], pb = ps[ixj];
+          const int64_t x = sc[i], y = sc[ixj];
+          const uint32_t px = ps[i], py = ps[ixj];
           const bool first_half = (i & k) == 0;
-          const bool swap = first_half ? better(b, pb, a, pa) : better(a, pa, b, pb);
+          const bool swap = first_half ? better(y, py, x, px) : better(x, px, y, py);
           if (swap) {
-            sc[i] = b;
-            sc[ixj] = a;
-            ps[i] = pb;
-            ps[ixj] = pa;
+            sc[i] = y;
+            sc[ixj] = x;
+            ps[i] = py;
+            ps[ixj] = px;
           }
         }
       }
@@ -718,6 +956,8 @@ __device__ void bitonic_best_first(int64_t* sc, uint32_t* ps, int n) {
   }
 }
 
+// Levels with more than kRankCap candidates: the N-th best score by radix select (8
+// bits at a time), ties at that score by the smallest positions, then a sort.
 __global__ __launch_bounds__(1024) void k_select(KArgs a) {
   __shared__ int64_t sc[kSortCap];
   __shared__ uint32_t ps[kSortCap];
@@ -725,23 +965,25 @@ __global__ __launch_bounds__(1024) void k_select(KArgs a) {
   __shared__ uint64_t s_prefix;
   __shared__ uint32_t s_k, s_n, s_eq;
   const int e = a.entry >= 0 ? a.entry : (int)blockIdx.x;
-  const LevelPlan& P = a.plan[e];
+  const LevelPlan P = a.plan[e];
   const int N = P.quota;
-  const int C = min((int)*P.cand_count, P.cand_cap);
+  const int C = min((int)*G(P.cand_count), P.cand_cap);
+  if (a.rank_path && C <= kRankCap) return;  // handled by k_select_orient
   const int nout = min(C, N);
   if (N <= 0 || C <= 0) {
-    if (threadIdx.x == 0) *P.sel_count = 0;
+    if (threadIdx.x == 0) *G(P.sel_count) = 0;
     return;
   }
+  gptr<const Cand> cand = G((const Cand*)P.cand);
   int nsort;
   if (C <= kSortCap) {
     nsort = C;
     for (int i = threadIdx.x; i < C; i += blockDim.x) {
-      sc[i] = P.cand[i].score;
-      ps[i] = P.cand[i].pos;
+      const Cand cd = load_cand(cand + i);
+      sc[i] = cd.score;
+      ps[i] = cd.pos;
     }
   } else {
-    // radix select of the N-th best score, 8 bits at a time from the top
     if (threadIdx.x == 0) {
       s_prefix = 0;
       s_k = (uint32_t)N;
@@ -752,7 +994,7 @@ __global__ __launch_bounds__(1024) void k_select(KArgs a) {
       __syncthreads();
       const uint64_t prefix = s_prefix;
       for (int i = threadIdx.x; i < C; i += blockDim.x) {
-        const uint64_t u = score_key(P.cand[i].score);
+        const uint64_t u = score_key(load_cand(cand + i).score);
         if ((u & mask) == prefix) atomicAdd(&hist[(u >> shift) & 255u], 1u);
       }
       __syncthreads();
@@ -773,12 +1015,11 @@ __global__ __launch_bounds__(1024) void k_select(KArgs a) {
       __syncthreads();
     }
     const uint64_t T = s_prefix;
-    const uint32_t k_eq = s_k;  // how many entries with score key == T are taken
-    // ties at T: the k_eq smallest positions, again by radix select
+    const uint32_t k_eq = s_k;
     if (threadIdx.x == 0) s_eq = 0;
     __syncthreads();
     for (int i = threadIdx.x; i < C; i += blockDim.x)
-      if (score_key(P.cand[i].score) == T) atomicAdd(&s_eq, 1u);
+      if (score_key(load_cand(cand + i).score) == T) atomicAdd(&s_eq, 1u);
     __syncthreads();
     uint32_t pcut = 0xffffffffu;
     if (s_eq > k_eq) {
@@ -792,7 +1033,7 @@ __global__ __launch_bounds__(1024) void k_select(KArgs a) {
         __syncthreads();
         const uint32_t pp = (uint32_t)s_prefix;
         for (int i = threadIdx.x; i < C; i += blockDim.x) {
-          const Cand cd = P.cand[i];
+          const Cand cd = load_cand(cand + i);
           if (score_key(cd.score) == T && (cd.pos & pmask) == pp)
             atomicAdd(&hist[(cd.pos >> shift) & 255u], 1u);
         }
@@ -818,7 +1059,7 @@ __global__ __launch_bounds__(1024) void k_select(KArgs a) {
     if (threadIdx.x == 0) s_n = 0;
     __syncthreads();
     for (int i = threadIdx.x; i < C; i += blockDim.x) {
-      const Cand cd = P.cand[i];
+      const Cand cd = load_cand(cand + i);
       const uint64_t u = score_key(cd.score);
       if (u > T || (u == T && cd.pos <= pcut)) {
         const uint32_t slot = atomicAdd(&s_n, 1u);
@@ -839,77 +1080,46 @@ __global__ __launch_bounds__(1024) void k_select(KArgs a) {
   }
   __syncthreads();
   bitonic_best_first(sc, ps, n2);
-  for (int i = threadIdx.x; i < nout; i += blockDim.x) {
-    Cand cd;
-    cd.score = sc[i];
-    cd.pos = ps[i];
-    cd.pad = 0;
-    P.sel[i] = cd;
-  }
-  if (threadIdx.x == 0) *P.sel_count = (uint32_t)nout;
+  gptr<Cand> sel = G(P.sel);
+  for (int i = threadIdx.x; i < nout; i += blockDim.x) store_cand(sel + i, sc[i], ps[i]);
+  if (threadIdx.x == 0) *G(P.sel_count) = (uint32_t)nout;
 }
 
-// -------------------------------------------------------------- orientation --
-
-// Four waves, each takes four keypoints in turn; lanes cover rows of the disk
-// dx^2 + dy^2 <= r^2 around the keypoint on its own level.
+// Orientation of the radix-selected keypoints: one wave per keypoint.
 __global__ __launch_bounds__(256) void k_orient(KArgs a) {
   const int b = (int)blockIdx.x;
   const int e = a.entry >= 0 ? a.entry : find_entry(a.orient_base, a.n_entries, b);
   const int chunk = a.entry >= 0 ? b : b - a.orient_base[e];
-  const LevelPlan& P = a.plan[e];
+  const LevelPlan P = a.plan[e];
+  gptr<const uint32_t> counts = G((const uint32_t*)P.cand_count) - e;
+  const int C = min((int)counts[e], P.cand_cap);
+  if (a.rank_path && C <= kRankCap) return;  // written by k_select_orient
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int nsel = (int)*P.sel_count;
+  const int nsel = (int)*G(P.sel_count);
   int prefix = 0;
-  for (int l = 0; l < P.level; ++l) prefix += (int)*a.plan[P.entry0 + l].sel_count;
-  if (P.level == 0 && chunk == 0 && threadIdx.x == 0) {
-    int total = 0;
-    for (int l = 0; l < P.n_levels; ++l) total += (int)*a.plan[P.entry0 + l].sel_count;
-    *P.count_out = total;
+  for (int l = 0; l < P.level; ++l) {
+    const LevelPlan& Q = a.plan[P.entry0 + l];
+    prefix += min(min((int)counts[P.entry0 + l], Q.cand_cap), Q.quota);
   }
-  const int r = P.B;
-  const int span = 2 * r + 1;
-  const int cspan = min(span, 64);
-  const int rows_per = 64 / cspan;
-  const int lr = lane / cspan, lc = lane - lr * cspan;
-  const int r2 = r * r;
+  if (!a.rank_path && P.level == 0 && chunk == 0 && threadIdx.x == 0) {
+    int total = 0;
+    for (int l = 0; l < P.n_levels; ++l) {
+      const LevelPlan& Q = a.plan[P.entry0 + l];
+      total += min(min((int)counts[P.entry0 + l], Q.cand_cap), Q.quota);
+    }
+    *G(P.count_out) = total;
+  }
+  gptr<const Cand> sel = G((const Cand*)P.sel);
   for (int kk = 0; kk < kOrientPerBlock / 4; ++kk) {
     const int i = chunk * kOrientPerBlock + wave * (kOrientPerBlock / 4) + kk;
     if (i >= nsel) break;
-    const Cand cd = P.sel[i];
+    const Cand cd = load_cand(sel + i);
     const int x = (int)(cd.pos & 0xffff), y = (int)(cd.pos >> 16);
-    int m10 = 0, m01 = 0;
-    if (lr < rows_per) {
-      for (int row0 = 0; row0 < span; row0 += rows_per) {
-        const int dy = row0 + lr - r;
-        if (dy > r) break;
-        const uint8_t* rowp = P.lvl + (size_t)(y + dy) * P.lvl_stride + x;
-        for (int c0 = 0; c0 < span; c0 += cspan) {
-          const int dx = c0 + lc - r;
-          if (dx <= r && dx * dx + dy * dy <= r2) {
-            const int v = rowp[dx];
-            m10 += dx * v;
-            m01 += dy * v;
-          }
-        }
-      }
-    }
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) {
-      m10 += __shfl_xor(m10, o, 64);
-      m01 += __shfl_xor(m01, o, 64);
-    }
-    if (lane == 0) {
-      of_keypoint k;
-      k.x = x;
-      k.y = y;
-      k.level = P.level;
-      k.m10 = m10;
-      k.m01 = m01;
-      k.angle = atan2f((float)m01, (float)m10);
-      k.score = cd.score;
-      P.out[prefix + i] = k;
-    }
+    int m10, m01;
+    wave_moments(G(P.lvl), P.lvl_stride, x, y, P.B, lane, &m10, &m01);
+    if (lane == 0)
+      store_keypoint(G(P.out) + prefix + i, x, y, P.level, m10, m01,
+                     atan2f((float)m01, (float)m10), cd.score);
   }
 }
 
@@ -927,8 +1137,8 @@ __global__ __launch_bounds__(256) void k_test_segment(const uint8_t* circles, in
 
 // ----------------------------------------------------------------- launches --
 
-hipError_t launch_prologue(const PrologueArgs& a, hipStream_t s) {
-  hipLaunchKernelGGL(k_prologue, dim3(1), dim3(1024), 0, s, a);
+hipError_t launch_prologue(const PrologueArgs& a, int grid, hipStream_t s) {
+  hipLaunchKernelGGL(k_prologue, dim3(grid), dim3(1024), 0, s, a);
   return hipGetLastError();
 }
 
@@ -950,6 +1160,11 @@ hipError_t launch_mark(const KArgs& a, bool fused, int grid, hipStream_t s) {
 hipError_t launch_detect(const KArgs& a, int grid, hipStream_t s) {
   const DetLds D = det_lds(a.t, a.cell);
   hipLaunchKernelGGL(k_detect, dim3(grid), dim3(256), D.bytes, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_select_orient(const KArgs& a, int slots, hipStream_t s) {
+  hipLaunchKernelGGL(k_select_orient, dim3(cdiv(slots, 4)), dim3(256), 0, s, a);
   return hipGetLastError();
 }
 

@@ -21,6 +21,7 @@ constexpr int kSortCap = 4096;                       // candidates sorted in LDS
 constexpr int kOrientPerBlock = 16;                  // keypoints per orientation block
 constexpr int kMaxDetW = 256, kMaxDetH = 128;        // Harris/NMS tile limits (pixels)
 constexpr int kCandCache = 1024;                     // Harris scores cached per tile
+constexpr int kRankCap = 16384;                      // levels ranked by counting, not radix
 
 struct Tune {
   int32_t mark_words, mark_rows;
@@ -177,9 +178,9 @@ OF_HD void entry_size(const FrameGeom& g, const of_params& p, const Tune& t, int
 
 // Region sizes of a whole call; offsets are from the workspace base (256-aligned).
 struct WsLayout {
-  int64_t off_hdr, off_plan, off_mark_base, off_det_base, off_orient_base, off_counters;
-  int64_t off_flags, off_bm, off_cand, off_sel, off_lvl, total;
-  int32_t n_entries, mark_tiles, det_tiles, orient_blocks;
+  int64_t off_hdr, off_plan, off_mark_base, off_det_base, off_orient_base, off_rank_base;
+  int64_t off_counters, off_flags, off_bm, off_cand, off_sel, off_lvl, total;
+  int32_t n_entries, mark_tiles, det_tiles, orient_blocks, rank_slots, max_cand_cap;
   int64_t flag_bytes, bm_words, cand_entries, sel_entries, lvl_bytes;
 };
 
@@ -191,17 +192,20 @@ OF_HD void ws_layout_accumulate(WsLayout* w, const EntrySize& s) {
   w->flag_bytes += s.flag_bytes;
   w->bm_words += s.bm_words;
   w->cand_entries += s.cand_cap;
+  w->rank_slots += (int32_t)(s.cand_cap < kRankCap ? s.cand_cap : kRankCap);
+  if (s.cand_cap > w->max_cand_cap) w->max_cand_cap = (int32_t)s.cand_cap;
   w->sel_entries += s.sel_cap;
   w->lvl_bytes += s.lvl_bytes;
 }
 
 OF_HD void ws_layout_finish(WsLayout* w) {
   int64_t o = 0;
-  w->off_hdr = o;          o += 256;  // queue counters
+  w->off_hdr = o;          o += 256;  // queue counters [0, 128), plan signature at 128
   w->off_plan = o;         o = align_up(o + (int64_t)w->n_entries * sizeof(LevelPlan), 256);
   w->off_mark_base = o;    o = align_up(o + 4 * ((int64_t)w->n_entries + 1), 256);
   w->off_det_base = o;     o = align_up(o + 4 * ((int64_t)w->n_entries + 1), 256);
   w->off_orient_base = o;  o = align_up(o + 4 * ((int64_t)w->n_entries + 1), 256);
+  w->off_rank_base = o;    o = align_up(o + 4 * ((int64_t)w->n_entries + 1), 256);
   w->off_counters = o;     o = align_up(o + 8 * (int64_t)w->n_entries, 256);
   w->off_flags = o;        o = align_up(o + w->flag_bytes, 256);
   w->off_bm = o;           o = align_up(o + 4 * w->bm_words, 256);
@@ -262,7 +266,7 @@ struct DetLds {
   int32_t nwr, nunits;       // 64-bit candidate words per ring row, total words
   int32_t max_surv, max_cells;
   int32_t off_cw, off_ucnt, off_cpre, off_cpos, off_crs, off_spos, off_srs, off_scell, off_order,
-      off_emit, off_ccnt, off_coff, off_cfill, bytes;
+      off_emit, off_ccnt, off_coff, off_cfill, off_wlo, off_whi, off_lfl, bytes;
 };
 
 OF_HD DetLds det_lds(const Tune& t, int32_t cell) {
@@ -295,6 +299,11 @@ OF_HD DetLds det_lds(const Tune& t, int32_t cell) {
   d.off_ccnt = o;   o += (int32_t)align_up(4 * d.max_cells, 16);
   d.off_coff = o;   o += (int32_t)align_up(4 * d.max_cells, 16);
   d.off_cfill = o;  o += (int32_t)align_up(4 * d.max_cells, 16);
+  const int32_t nbw = cdiv(d.mtw + 2, 32) + 1;        // bitmap words per ring row
+  d.off_wlo = o;    o += (int32_t)align_up(4 * nbw * (d.mth + 2), 16);
+  d.off_whi = o;    o += (int32_t)align_up(4 * nbw * (d.mth + 2), 16);
+  const int32_t nfl = cell > 0 ? (t.det_cx + 2) * (t.det_cy + 2) : 4;  // cells of the ring
+  d.off_lfl = o;    o += (int32_t)align_up(nfl, 16);
   d.bytes = o;
   return d;
 }

@@ -214,7 +214,7 @@ def test_c2_plain_and_fused(hip):
 
 
 @pytest.mark.parametrize("tune", [dict(mark_grid=0, det_grid=0), dict(mark_words=1, mark_rows=4),
-                                  dict(mark_words=2, mark_rows=64, det_cells_x=8, det_cells_y=2),
+                                  dict(mark_words=2, mark_rows=64, det_cells_x=8, det_cells_y=1),
                                   dict(det_cells_x=1, det_cells_y=1, mark_grid=7, det_grid=3)])
 def test_c2_tunings_agree(hip, tune):
     spec = CONFIGS["c2"]["frames"][0]
