@@ -142,22 +142,42 @@ __device__ __forceinline__ void circle_diffs(const uint8_t* c, int P, int (&d)[1
 
 // Copy rows [y0, y1) x cols [x0, x1) of an 8-bit image into LDS (row pitch lp, origin
 // (x0, y0)); x0 is a multiple of 4.  Whole 32-bit words where the source row allows,
-// bytes at a ragged right edge.  Loads of one thread are independent, so they overlap.
+// bytes at a ragged right edge.  Each thread issues eight loads before it stores any,
+// so a tile costs one or two memory round trips instead of one per word.
+__device__ __forceinline__ uint32_t load_word(gptr<const uint8_t> s, bool whole, int n) {
+  if (whole) return *(gptr<const uint32_t>)s;
+  uint32_t v = 0;
+  for (int k = 0; k < n; ++k) v |= (uint32_t)s[k] << (8 * k);
+  return v;
+}
+
 __device__ __forceinline__ void stage_rows(uint8_t* lds, int lp, gptr<const uint8_t> src,
                                            int stride, int row_limit, int x0, int x1, int y0,
                                            int y1) {
+  constexpr int U = 8;
   const bool aligned = ((((uintptr_t)src) | (uintptr_t)stride) & 3) == 0;
   const int nw = (x1 - x0 + 3) >> 2;
   const int total = nw * (y1 - y0);
-  for (int i = threadIdx.x; i < total; i += blockDim.x) {
-    const int r = i / nw, w = i - r * nw;
-    const int x = x0 + 4 * w;
-    gptr<const uint8_t> s = src + (size_t)(y0 + r) * stride + x;
-    uint8_t* d = lds + r * lp + 4 * w;
-    if (aligned && x + 4 <= row_limit) {
-      *(uint32_t*)d = *(gptr<const uint32_t>)s;
-    } else {
-      for (int k = 0; k < 4 && x + k < x1; ++k) d[k] = s[k];
+  for (int base = 0; base < total; base += U * (int)blockDim.x) {
+    uint32_t v[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int i = base + u * (int)blockDim.x + (int)threadIdx.x;
+      v[u] = 0;
+      if (i < total) {
+        const int r = i / nw, w = i - r * nw;
+        const int x = x0 + 4 * w;
+        v[u] = load_word(src + (size_t)(y0 + r) * stride + x, aligned && x + 4 <= row_limit,
+                         min(4, x1 - x));
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int i = base + u * (int)blockDim.x + (int)threadIdx.x;
+      if (i < total) {
+        const int r = i / nw, w = i - r * nw;
+        *(uint32_t*)(lds + r * lp + 4 * w) = v[u];
+      }
     }
   }
 }
@@ -273,19 +293,25 @@ __device__ __forceinline__ void wave_moments(gptr<const uint8_t> lvl, int stride
   *m01 = wave_sum(b);
 }
 
-// Tile index: blockIdx.x once, or from the queue counter, drawn one tile ahead so the
-// atomic's round trip overlaps the current tile.
+// Tile index: blockIdx.x once, or from the queue counter.  The next index is drawn
+// when a tile starts and parked in LDS only when it ends, so the atomic's round trip
+// overlaps the tile instead of stalling the block.
 __device__ __forceinline__ void queue_start(const KArgs& a, uint32_t* ctr, int* s_next) {
   if (a.persistent && threadIdx.x == 0) *s_next = (int)atomicAdd(ctr, 1u);
 }
 
-__device__ __forceinline__ int queue_take(const KArgs& a, int iter, uint32_t* ctr, int* s_next) {
+__device__ __forceinline__ int queue_take(const KArgs& a, int iter, int* s_next) {
   if (!a.persistent) return iter == 0 ? (int)blockIdx.x : a.total;
   __syncthreads();
-  const int g = *s_next;
-  __syncthreads();
-  if (threadIdx.x == 0 && g < a.total) *s_next = (int)atomicAdd(ctr, 1u);
-  return g;
+  return *s_next;
+}
+
+__device__ __forceinline__ int queue_prefetch(const KArgs& a, int g, uint32_t* ctr) {
+  return (a.persistent && threadIdx.x == 0 && g < a.total) ? (int)atomicAdd(ctr, 1u) : 0;
+}
+
+__device__ __forceinline__ void queue_park(const KArgs& a, int next, int* s_next) {
+  if (a.persistent && threadIdx.x == 0) *s_next = next;
 }
 
 // Copy of an exclusive prefix (n + 1 values) into LDS for entry lookups.
@@ -487,7 +513,7 @@ __global__ __launch_bounds__(256) void k_pyramid(PyrArgs a) {
 template <bool FUSED>
 __global__ __launch_bounds__(256) void k_mark(KArgs a) {
   extern __shared__ __align__(16) uint8_t smem[];
-  __shared__ int s_next, s_qn;
+  __shared__ int s_next, s_qcnt[4];
   __shared__ int32_t s_base[kMaxEntries + 1];
   const MarkLds M = mark_lds(a.t);
   const int TWW = a.t.mark_words;
@@ -502,8 +528,10 @@ __global__ __launch_bounds__(256) void k_mark(KArgs a) {
   queue_start(a, a.qctr + 0, &s_next);
 
   for (int iter = 0;; ++iter) {
-    const int g = uniform(queue_take(a, iter, a.qctr + 0, &s_next));
+    const int g = uniform(queue_take(a, iter, &s_next));
     if (g >= a.total) break;
+    __syncthreads();  // every thread has read s_next
+    const int next = queue_prefetch(a, g, a.qctr + 0);
     const int e = a.entry >= 0 ? a.entry : uniform(find_entry(s_base, a.n_entries, g));
     const int t = a.entry >= 0 ? g : g - s_base[e];
     const LevelPlan P = a.plan[e];
@@ -579,14 +607,17 @@ __global__ __launch_bounds__(256) void k_mark(KArgs a) {
       stage_rows(pix, M.pitch, G(P.lvl), P.lvl_stride, limit, ox, ex, oy, ey);
     }
     for (int i = threadIdx.x; i < 2 * M.th * 2 * TWW; i += blockDim.x) bml[i] = 0u;  // lo, hi
-    if (threadIdx.x == 0) s_qn = 0;
     __syncthreads();
 
     // 2. compass pre-test at fast_t_min: a run of 9 holds two cyclically adjacent
     //    compass points (positions 1/5/9/13), so (n|s) & (e|w) per polarity is necessary.
+    //    Each wave appends the pixels that pass to its own quarter of the queue.
     const int tlo = P.fast_t_min, thi = P.fast_t;
     const int ya = max(y_t0, B), yb = min(y_t1, H - B);
     const int units = max(0, yb - ya) * TWW;
+    const int qseg = M.qseg;  // launches use 4 waves per block
+    uint16_t* myq = queue + wave * qseg;
+    int qn = 0;
     for (int u = wave; u < units; u += nwave) {
       const int y = ya + u / TWW;
       const int x = x_t0 + 64 * (u % TWW) + lane;
@@ -603,20 +634,26 @@ __global__ __launch_bounds__(256) void k_mark(KArgs a) {
         pass = b | d;
       }
       const uint64_t m = __ballot(pass);
-      if (m) {
-        int qb = 0;
-        if (lane == 0) qb = atomicAdd(&s_qn, __popcll(m));
-        qb = __shfl(qb, 0, 64);
-        if (pass) queue[qb + lanes_below(m)] = (uint16_t)(lx | (ly << 9));
-      }
+      if (pass) myq[qn + lanes_below(m)] = (uint16_t)(lx | (ly << 9));
+      qn += __popcll(m);
     }
+    if (lane == 0) s_qcnt[wave] = qn;
     __syncthreads();
 
     // 3. full segment test of the queued pixels at both thresholds
-    const int qn = s_qn;
+    int qoff[4];
+    int qtot = 0;
+#pragma unroll
+    for (int w = 0; w < 4; ++w) {
+      qoff[w] = qtot;
+      qtot += w < nwave ? s_qcnt[w] : 0;
+    }
     gptr<uint8_t> flags = G(P.flags);
-    for (int q = threadIdx.x; q < qn; q += blockDim.x) {
-      const int ent = queue[q];
+    for (int q = threadIdx.x; q < qtot; q += blockDim.x) {
+      int w = 0;
+#pragma unroll
+      for (int k = 1; k < 4; ++k) w += q >= qoff[k] ? 1 : 0;
+      const int ent = queue[w * qseg + (q - qoff[w])];
       const int lx = ent & 511, ly = ent >> 9;
       int d[16];
       circle_diffs(pix + ly * M.pitch + lx, M.pitch, d);
@@ -644,6 +681,7 @@ __global__ __launch_bounds__(256) void k_mark(KArgs a) {
       glo[gi] = bml[r * 2 * TWW + k];
       ghi[gi] = bmh[r * 2 * TWW + k];
     }
+    queue_park(a, next, &s_next);
   }
 }
 
@@ -677,8 +715,10 @@ __global__ __launch_bounds__(256) void k_detect(KArgs a) {
   queue_start(a, a.qctr + 2, &s_next);
 
   for (int iter = 0;; ++iter) {
-    const int g = uniform(queue_take(a, iter, a.qctr + 2, &s_next));
+    const int g = uniform(queue_take(a, iter, &s_next));
     if (g >= a.total) break;
+    __syncthreads();  // every thread has read s_next
+    const int next = queue_prefetch(a, g, a.qctr + 2);
     const int e = a.entry >= 0 ? a.entry : uniform(find_entry(s_base, a.n_entries, g));
     const int t = a.entry >= 0 ? g : g - s_base[e];
     const LevelPlan P = a.plan[e];
@@ -712,19 +752,45 @@ __global__ __launch_bounds__(256) void k_detect(KArgs a) {
     const int fcx0 = rx0 / cs, fcy0 = ry0 / cs;
     const int nfx = (rx0 + rw - 1) / cs - fcx0 + 1, nfy = (ry0 + rh - 1) / cs - fcy0 + 1;
 
-    // 1. one batch of independent loads: pixels (5-pixel halo), bitmap words, flags
-    stage_rows(pix, D.pitch, G(P.lvl), P.lvl_stride, P.level == 0 ? W : P.lvl_stride, sx0, sx1,
-               sy0, sy1);
+    // 1. one batch of independent loads: bitmap words, flags, pixels (5-pixel halo)
     {
       gptr<const uint32_t> glo = G((const uint32_t*)P.bm_lo), ghi = G((const uint32_t*)P.bm_hi);
-      for (int i = threadIdx.x; i < rh * nbw; i += blockDim.x) {
+      gptr<const uint8_t> gfl = G((const uint8_t*)P.flags);
+      const int nbm = rh * nbw, nfl = nfx * nfy;
+      uint32_t vlo[2], vhi[2], vfl[2];
+#pragma unroll
+      for (int u = 0; u < 2; ++u) {
+        const int i = u * (int)blockDim.x + (int)threadIdx.x;
+        vlo[u] = vhi[u] = vfl[u] = 0;
+        if (i < nbm) {
+          const int r = i / nbw, k = i - r * nbw;
+          const size_t gi = (size_t)(ry0 + r) * P.wpr + bw0 + k;
+          vlo[u] = glo[gi];
+          vhi[u] = ghi[gi];
+        }
+        if (i < nfl) {
+          const int r = i / nfx, k = i - r * nfx;
+          vfl[u] = gfl[(fcy0 + r) * P.ncx + fcx0 + k];
+        }
+      }
+      stage_rows(pix, D.pitch, G(P.lvl), P.lvl_stride, P.level == 0 ? W : P.lvl_stride, sx0,
+                 sx1, sy0, sy1);
+#pragma unroll
+      for (int u = 0; u < 2; ++u) {
+        const int i = u * (int)blockDim.x + (int)threadIdx.x;
+        if (i < nbm) {
+          wlo[i] = vlo[u];
+          whi[i] = vhi[u];
+        }
+        if (i < nfl) lfl[i] = (uint8_t)vfl[u];
+      }
+      for (int i = 2 * (int)blockDim.x + (int)threadIdx.x; i < nbm; i += blockDim.x) {
         const int r = i / nbw, k = i - r * nbw;
         const size_t gi = (size_t)(ry0 + r) * P.wpr + bw0 + k;
         wlo[i] = glo[gi];
         whi[i] = ghi[gi];
       }
-      gptr<const uint8_t> gfl = G((const uint8_t*)P.flags);
-      for (int i = threadIdx.x; i < nfx * nfy; i += blockDim.x) {
+      for (int i = 2 * (int)blockDim.x + (int)threadIdx.x; i < nfl; i += blockDim.x) {
         const int r = i / nfx, k = i - r * nfx;
         lfl[i] = gfl[(fcy0 + r) * P.ncx + fcx0 + k];
       }
@@ -776,36 +842,44 @@ __global__ __launch_bounds__(256) void k_detect(KArgs a) {
       crs[i] = harris_lds(pix, D.pitch, (int)(pos & 0xffff) - sx0, (int)(pos >> 16) - sy0);
     }
     __syncthreads();
-    // 4. NMS: a tile candidate survives when it ranks above every candidate neighbour
-    for (int u = wave; u < nunits; u += nwave) {
-      const int j = u / nwr, k = u - j * nwr;
-      const uint64_t m = cw[u];
-      const int lxr = 64 * k + lane;
-      if (!((m >> lane) & 1ull) || j == 0 || j == rh - 1 || lxr == 0 || lxr >= rw - 1) continue;
-      const int x = rx0 + lxr, y = ry0 + j;
-      const uint32_t idx = cpre[u] + lanes_below(m);
-      const int64_t R = idx < (uint32_t)kCandCache
-                            ? crs[idx]
-                            : harris_lds_uncached(pix, D.pitch, x - sx0, y - sy0);
-      const uint32_t pos = ((uint32_t)y << 16) | (uint32_t)x;
+    // 4. NMS: a tile candidate survives when it ranks above every candidate neighbour.
+    //    One thread per candidate; neighbours are found through the candidate words.
+    for (int ci = threadIdx.x; ci < ncand; ci += blockDim.x) {
+      uint32_t pos;
+      if (ci < kCandCache) {
+        pos = cpos[ci];
+      } else {  // beyond the cache: locate the ci-th candidate in raster order
+        int lo = 0, hi = nunits - 1;
+        while (lo < hi) {
+          const int mid = (lo + hi + 1) >> 1;
+          if (cpre[mid] <= (uint32_t)ci) lo = mid; else hi = mid - 1;
+        }
+        uint64_t m = cw[lo];
+        for (uint32_t k = cpre[lo]; k < (uint32_t)ci; ++k) m &= m - 1ull;
+        const int j = lo / nwr, k = lo - j * nwr;
+        pos = ((uint32_t)(ry0 + j) << 16) | (uint32_t)(rx0 + 64 * k + __builtin_ctzll(m));
+      }
+      const int x = (int)(pos & 0xffff), y = (int)(pos >> 16);
+      const int lxr = x - rx0, j = y - ry0;
+      if (j == 0 || j == rh - 1 || lxr == 0 || lxr >= rw - 1) continue;  // ring only
+      const int64_t R = ci < kCandCache ? crs[ci]
+                                        : harris_lds_uncached(pix, D.pitch, x - sx0, y - sy0);
       bool alive = true;
-      for (int dy = -1; dy <= 1 && alive; ++dy) {
-        for (int dx = -1; dx <= 1; ++dx) {
-          if (dx == 0 && dy == 0) continue;
-          const int qj = j + dy, ql = lxr + dx;
-          const int qu = qj * nwr + (ql >> 6);
-          const uint64_t qm = cw[qu];
-          const int qb = ql & 63;
-          if (!((qm >> qb) & 1ull)) continue;
+#pragma unroll
+      for (int nb = 0; nb < 8; ++nb) {
+        const int dx = nb < 3 ? nb - 1 : (nb < 5 ? (nb == 3 ? -1 : 1) : nb - 6);
+        const int dy = nb < 3 ? -1 : (nb < 5 ? 0 : 1);
+        const int ql = lxr + dx;
+        const int qu = (j + dy) * nwr + (ql >> 6);
+        const uint64_t qm = cw[qu];
+        const int qb = ql & 63;
+        if ((qm >> qb) & 1ull) {
           const uint32_t qidx = cpre[qu] + (uint32_t)__popcll(qm & ((1ull << qb) - 1ull));
           const int qx = x + dx, qy = y + dy;
           const int64_t Rq = qidx < (uint32_t)kCandCache
                                  ? crs[qidx]
                                  : harris_lds_uncached(pix, D.pitch, qx - sx0, qy - sy0);
-          if (!better(R, pos, Rq, ((uint32_t)qy << 16) | (uint32_t)qx)) {
-            alive = false;
-            break;
-          }
+          alive = alive && better(R, pos, Rq, ((uint32_t)qy << 16) | (uint32_t)qx);
         }
       }
       if (alive) {
@@ -871,6 +945,7 @@ __global__ __launch_bounds__(256) void k_detect(KArgs a) {
         }
       }
     }
+    queue_park(a, next, &s_next);
   }
 }
 
@@ -904,11 +979,17 @@ __global__ __launch_bounds__(256) void k_select_orient(KArgs a) {
   gptr<const Cand> cand = G((const Cand*)P.cand);
   const Cand me = load_cand(cand + i);
   int cnt = 0;
-  for (int j0 = 0; j0 < C; j0 += 64) {
-    const int j = j0 + lane;
-    if (j < C) {
-      const Cand o = load_cand(cand + j);
-      cnt += better(o.score, o.pos, me.score, me.pos) ? 1 : 0;
+  for (int j0 = 0; j0 < C; j0 += 4 * 64) {
+    Cand o[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int j = min(j0 + u * 64 + lane, C - 1);
+      o[u] = load_cand(cand + j);
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int j = j0 + u * 64 + lane;
+      cnt += (j < C && better(o[u].score, o[u].pos, me.score, me.pos)) ? 1 : 0;
     }
   }
   const int rank = wave_sum(cnt);

@@ -237,7 +237,7 @@ OF_HD uint32_t resample_tap(int32_t i, int32_t n_src, int32_t n_dst) {
 // Segment-test tile: pixels (tile + 3-pixel halo, 4-aligned origin), the queue of
 // pixels that pass the compass pre-test, both bitmaps, and the resample tap tables.
 struct MarkLds {
-  int32_t tw, th, pitch, rows;
+  int32_t tw, th, pitch, rows, qseg;
   int32_t off_queue, off_bml, off_bmh, off_xt, off_yt, bytes;
 };
 
@@ -248,7 +248,9 @@ OF_HD MarkLds mark_lds(const Tune& t) {
   m.pitch = m.tw + 8;
   m.rows = m.th + 6;
   int32_t o = (int32_t)align_up((int64_t)m.pitch * m.rows, 16);
-  m.off_queue = o;  o += (int32_t)align_up(2 * m.tw * m.th, 16);
+  // four per-wave queue segments; a wave owns at most ceil(rows * words / 4) wave-rows
+  m.qseg = 64 * cdiv(m.th * t.mark_words, 4);
+  m.off_queue = o;  o += (int32_t)align_up(2 * 4 * m.qseg, 16);
   m.off_bml = o;    o += 4 * m.th * 2 * t.mark_words;
   m.off_bmh = o;    o += 4 * m.th * 2 * t.mark_words;
   m.off_xt = o;     o += 4 * m.pitch;
