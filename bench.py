@@ -61,6 +61,8 @@ def main():
     ap.add_argument("--steps", type=int, default=2000)
     ap.add_argument("--warmup", type=int, default=50)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-tune", action="store_true", help="library default launch shape")
+    ap.add_argument("--tune-verbose", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path "
@@ -84,16 +86,24 @@ def main():
     plain = ofhip.Detector([img.shape], p)
     stream = torch.cuda.Stream()
 
+    # launch shape of the fused path from the autotuner (outside the timed region)
+    tune_fields = None
+    if not args.no_tune:
+        from paper_2506_07164_amd.tune import autotune
+        tune_fields = autotune([frame], p, verbose=args.tune_verbose)
+        print(f"# tuning {tune_fields}", file=sys.stderr, flush=True)
+    tune = ofhip.tuning(**tune_fields) if tune_fields else None
+
     # warm-up (eager), then capture the fused step in a graph on `stream`
     with torch.cuda.stream(stream):
         for _ in range(max(1, args.warmup)):
-            fused.detect_batch([frame], stream=stream)
+            fused.detect_batch([frame], tune=tune, stream=stream)
             plain.detect_plain(frame, stream=stream)
     torch.cuda.synchronize()
     graph = torch.cuda.CUDAGraph()
     with torch.cuda.stream(stream):
         with torch.cuda.graph(graph, stream=stream):
-            fused.detect_batch([frame], stream=stream)
+            fused.detect_batch([frame], tune=tune, stream=stream)
     for _ in range(args.warmup):
         graph.replay()
     torch.cuda.synchronize()
@@ -124,7 +134,7 @@ def main():
     ofhip.of_profile_enable(True)
     with torch.cuda.stream(stream):
         for _ in range(Kq):
-            fused.detect_batch([frame], stream=stream)
+            fused.detect_batch([frame], tune=tune, stream=stream)
     torch.cuda.synchronize()
     prof = ofhip.of_profile_read()
     ofhip.of_profile_enable(False)
@@ -166,6 +176,7 @@ def main():
                                "30x30 cell, 2000 keypoints, fused path (graph)",
                    "frames_per_step": 1},
         "plain_fps": round(Kp / t_plain, 1),
+        "tuning": tune_fields,
         "step_us": {k: round(v, 3) for k, v in step_us.items()},
         "hbm_algorithmic_gbps": round((img.nbytes + 32 * kw["n_features"]) * fused_fps / 1e9, 2),
         "roofline": roofline,

@@ -1,0 +1,111 @@
+"""Autotuner for the batched path: tile shapes and persistent grid sizes.
+
+For a batch shape (frame sizes + detector parameters) it times candidate launch shapes
+of of_detect_batch on the device and keeps the fastest.  The search is coordinate
+descent over (segment-test tile, Harris/NMS tile, grids) from the library defaults;
+every candidate is timed with HIP events over a few calls after a warm-up.  Results are
+cached in a JSON file keyed by GPU name, frame sizes and parameters.  Outputs do not
+depend on the tuning (the parity tests check that), so tuning only moves time.
+"""
+from __future__ import annotations
+
+import json
+import os
+
+from . import ofhip
+
+CACHE = os.environ.get("OF_TUNE_CACHE", os.path.join(os.path.dirname(os.path.abspath(__file__)),
+                                                      "tune_cache.json"))
+
+FIELDS = ("mark_words", "mark_rows", "det_cells_x", "det_cells_y", "det_w", "det_h",
+          "mark_grid", "det_grid")
+
+
+def _key(shapes, p, device_name):
+    return json.dumps({"dev": device_name, "shapes": [list(s) for s in shapes],
+                       "params": [getattr(p, f) for f, _ in ofhip.OfParams._fields_]},
+                      sort_keys=True)
+
+
+def _as_tuning(d):
+    return ofhip.tuning(**{k: int(v) for k, v in d.items()})
+
+
+def time_tuning(det, frames, tune, calls=20, warmup=3):
+    """Mean milliseconds per of_detect_batch call (HIP events on the current stream)."""
+    import torch
+    for _ in range(warmup):
+        det.detect_batch(frames, tune=tune)
+    s, e = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    s.record()
+    for _ in range(calls):
+        det.detect_batch(frames, tune=tune)
+    e.record()
+    e.synchronize()
+    return s.elapsed_time(e) / calls
+
+
+def candidates(p, n_cus):
+    marks = [dict(mark_words=w, mark_rows=r) for w in (1, 2, 4) for r in (8, 16, 32)
+             if w * r <= 96]
+    if p.cell > 0:
+        dets = [dict(det_cells_x=cx, det_cells_y=cy) for cx, cy in
+                ((1, 1), (2, 1), (4, 1), (2, 2), (8, 1), (4, 2))
+                if cx * p.cell <= 256 and cy * p.cell <= 128]
+    else:
+        dets = [dict(det_w=w, det_h=h) for w, h in ((64, 32), (128, 32), (128, 64), (256, 32))]
+    grids = [dict(mark_grid=0, det_grid=0)] + [
+        dict(mark_grid=m * n_cus, det_grid=d * n_cus) for m, d in ((2, 2), (4, 3), (8, 4))]
+    return marks, dets, grids
+
+
+def autotune(frames, p, calls=20, use_cache=True, verbose=False):
+    """Best tuning (as a dict of of_tuning fields) for these frames and parameters."""
+    import torch
+    name = torch.cuda.get_device_name()
+    shapes = [tuple(f.shape) for f in frames]
+    key = _key(shapes, p, name)
+    cache = {}
+    if use_cache and os.path.exists(CACHE):
+        try:
+            with open(CACHE) as fh:
+                cache = json.load(fh)
+        except (OSError, ValueError):
+            cache = {}
+        if key in cache:
+            return cache[key]["tuning"]
+    n_cus = torch.cuda.get_device_properties(0).multi_processor_count
+    det = ofhip.Detector(shapes, p)
+    best = {}
+    default = ofhip.of_tuning_default([ofhip.image_of(f) for f in frames], p)
+    for f in FIELDS:
+        best[f] = getattr(default, f)
+    marks, dets, grids = candidates(p, n_cus)
+    log = []
+
+    def trial(upd):
+        cand = dict(best, **upd)
+        try:
+            ms = time_tuning(det, frames, _as_tuning(cand), calls)
+        except ofhip.OfError:
+            return None
+        log.append((cand, ms))
+        if verbose:
+            print(f"  {cand} -> {ms * 1e3:.1f} us", flush=True)
+        return ms
+
+    best_ms = trial({})
+    for group in (grids, marks, dets, grids):
+        for upd in group:
+            ms = trial(upd)
+            if ms is not None and ms < best_ms:
+                best_ms = ms
+                best.update(upd)
+    result = {"tuning": best, "ms": best_ms, "trials": len(log)}
+    if use_cache:
+        cache[key] = result
+        tmp = CACHE + ".tmp%d" % os.getpid()
+        with open(tmp, "w") as fh:
+            json.dump(cache, fh, indent=1)
+        os.replace(tmp, CACHE)
+    return best
