@@ -66,7 +66,7 @@ def main():
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path "
-              "(frames shard across GPUs with no exchange; see DESIGN.md)", file=sys.stderr)
+              "(frames shard across GPUs with no exchange between them)", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
