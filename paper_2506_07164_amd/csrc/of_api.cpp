@@ -93,7 +93,7 @@ int device_cus() {
 }
 
 // Defaults: 256 x 16 segment-test tiles; Harris/NMS tiles of about 120 x 30 pixels
-// (whole cells); persistent grids of a few blocks per compute unit.
+// (whole cells).
 Tune default_tune(const of_params& p) {
   Tune t;
   t.mark_words = 4;
@@ -106,8 +106,11 @@ Tune default_tune(const of_params& p) {
   }
   t.det_w = 128;
   t.det_h = 32;
-  t.mark_grid = 6 * device_cus();
-  t.det_grid = 4 * device_cus();
+  // One block per tile by default: a shared queue counter hit from all eight XCDs
+  // costs more than the hardware dispatcher on this chip (the tuner can still pick a
+  // persistent grid).
+  t.mark_grid = 0;
+  t.det_grid = 0;
   return t;
 }
 

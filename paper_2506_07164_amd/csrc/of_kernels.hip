@@ -141,9 +141,9 @@ __device__ __forceinline__ void circle_diffs(const uint8_t* c, int P, int (&d)[1
 }
 
 // Copy rows [y0, y1) x cols [x0, x1) of an 8-bit image into LDS (row pitch lp, origin
-// (x0, y0)); x0 is a multiple of 4.  Whole 32-bit words where the source row allows,
-// bytes at a ragged right edge.  Each thread issues eight loads before it stores any,
-// so a tile costs one or two memory round trips instead of one per word.
+// (x0, y0)); x0 is a multiple of 4.  Waves take rows (row base in scalar registers),
+// lanes take 32-bit words; each wave keeps four rows of loads in flight.  Whole words
+// where the source row allows, bytes at a ragged right edge.
 __device__ __forceinline__ uint32_t load_word(gptr<const uint8_t> s, bool whole, int n) {
   if (whole) return *(gptr<const uint32_t>)s;
   uint32_t v = 0;
@@ -154,30 +154,28 @@ __device__ __forceinline__ uint32_t load_word(gptr<const uint8_t> s, bool whole,
 __device__ __forceinline__ void stage_rows(uint8_t* lds, int lp, gptr<const uint8_t> src,
                                            int stride, int row_limit, int x0, int x1, int y0,
                                            int y1) {
-  constexpr int U = 8;
+  constexpr int U = 4;
   const bool aligned = ((((uintptr_t)src) | (uintptr_t)stride) & 3) == 0;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nwave = blockDim.x >> 6;
   const int nw = (x1 - x0 + 3) >> 2;
-  const int total = nw * (y1 - y0);
-  for (int base = 0; base < total; base += U * (int)blockDim.x) {
-    uint32_t v[U];
+  const int nrow = y1 - y0;
+  for (int r0 = wave * U; r0 < nrow; r0 += nwave * U) {
+    for (int w0 = 0; w0 < nw; w0 += 64) {
+      const int w = w0 + lane;
+      const int x = x0 + 4 * w;
+      const bool in_x = w < nw;
+      const bool whole = aligned && x + 4 <= row_limit;
+      const int nb = min(4, x1 - x);
+      uint32_t v[U];
 #pragma unroll
-    for (int u = 0; u < U; ++u) {
-      const int i = base + u * (int)blockDim.x + (int)threadIdx.x;
-      v[u] = 0;
-      if (i < total) {
-        const int r = i / nw, w = i - r * nw;
-        const int x = x0 + 4 * w;
-        v[u] = load_word(src + (size_t)(y0 + r) * stride + x, aligned && x + 4 <= row_limit,
-                         min(4, x1 - x));
+      for (int u = 0; u < U; ++u) {
+        v[u] = 0;
+        if (in_x && r0 + u < nrow)
+          v[u] = load_word(src + (size_t)(y0 + r0 + u) * stride + x, whole, nb);
       }
-    }
 #pragma unroll
-    for (int u = 0; u < U; ++u) {
-      const int i = base + u * (int)blockDim.x + (int)threadIdx.x;
-      if (i < total) {
-        const int r = i / nw, w = i - r * nw;
-        *(uint32_t*)(lds + r * lp + 4 * w) = v[u];
-      }
+      for (int u = 0; u < U; ++u)
+        if (in_x && r0 + u < nrow) *(uint32_t*)(lds + (r0 + u) * lp + 4 * w) = v[u];
     }
   }
 }
@@ -228,6 +226,50 @@ __device__ __forceinline__ int64_t harris_lds(const uint8_t* pix, int P, int cx,
 // Out-of-line Harris for the rare candidates beyond the per-tile score cache.
 __device__ __noinline__ int64_t harris_lds_uncached(const uint8_t* pix, int P, int cx, int cy) {
   return harris_lds(pix, P, cx, cy);
+}
+
+// Harris R' of candidates by groups of 8 lanes: lane s < 7 of a group forms the Sobel
+// gradients (Eq. 4) at the 7 pixels of window row dy = s - 3 from 3 staged rows and
+// sums gx^2, gy^2, gx*gy; the 7 row sums are added across the group and R' is formed
+// by lane 0.  Every lane of the block runs the same number of rounds.
+__device__ __forceinline__ void harris_groups(const uint8_t* pix, int P, const uint32_t* cpos,
+                                              int64_t* crs, int n, int sx0, int sy0) {
+  const int s = threadIdx.x & 7;
+  const int groups = blockDim.x >> 3;
+  for (int cb = 0; cb < n; cb += groups) {
+    const int c = cb + (threadIdx.x >> 3);
+    int sxx = 0, syy = 0, sxy = 0;
+    if (c < n && s < 7) {
+      const uint32_t pos = cpos[c];
+      const int cx = (int)(pos & 0xffff) - sx0, cy = (int)(pos >> 16) - sy0;
+      const uint8_t* r0 = pix + (cy + s - 4) * P + (cx - 4);
+      int a[9], b[9], d[9];
+#pragma unroll
+      for (int k = 0; k < 9; ++k) {
+        a[k] = r0[k];
+        b[k] = r0[P + k];
+        d[k] = r0[2 * P + k];
+      }
+#pragma unroll
+      for (int k = 1; k < 8; ++k) {
+        const int gx = (a[k + 1] - a[k - 1]) + 2 * (b[k + 1] - b[k - 1]) + (d[k + 1] - d[k - 1]);
+        const int gy = (d[k - 1] + 2 * d[k] + d[k + 1]) - (a[k - 1] + 2 * a[k] + a[k + 1]);
+        sxx += gx * gx;
+        syy += gy * gy;
+        sxy += gx * gy;
+      }
+    }
+#pragma unroll
+    for (int o = 1; o < 8; o <<= 1) {
+      sxx += __shfl_xor(sxx, o, 8);
+      syy += __shfl_xor(syy, o, 8);
+      sxy += __shfl_xor(sxy, o, 8);
+    }
+    if (c < n && s == 0) {
+      const int64_t A = sxx, B = syy, C = sxy;
+      crs[c] = 25 * (A * B - C * C) - (A + B) * (A + B);
+    }
+  }
 }
 
 // Exclusive scan of cnt[0..n) into pre[0..n], pre[n] = total, by the whole block.
@@ -548,42 +590,47 @@ __global__ __launch_bounds__(256) void k_mark(KArgs a) {
       for (int i = threadIdx.x; i < nx; i += blockDim.x) xt[i] = resample_tap(ox + i, P.base_w, W);
       for (int j = threadIdx.x; j < ny; j += blockDim.x) yt[j] = resample_tap(oy + j, P.base_h, H);
       __syncthreads();
-      // two rows per wave per pass, up to 5 columns per lane: 40 gathers in flight
+      // Column taps stay in registers (lane owns columns lane + 64c); each wave takes two
+      // consecutive output rows at a time with their base-row pointers in scalar
+      // registers, so a tap costs its load and the blend only (40 gathers in flight).
       gptr<const uint8_t> base = G(P.base);
       const int bs = P.base_stride, bw1 = P.base_w - 1, bh1 = P.base_h - 1;
-      for (int j0 = wave; j0 < ny; j0 += 2 * nwave) {
+      int cx0[5], cx1[5], cwx[5];
+#pragma unroll
+      for (int c = 0; c < 5; ++c) {
+        const uint32_t txx = xt[min(lane + 64 * c, nx - 1)];
+        cx0[c] = txx >> 9;
+        cx1[c] = min(cx0[c] + 1, bw1);
+        cwx[c] = txx & 511;
+      }
+      for (int j0 = 2 * wave; j0 < ny; j0 += 2 * nwave) {
         int v[2][5][4];
         int wyr[2];
 #pragma unroll
         for (int h = 0; h < 2; ++h) {
-          const int j = min(j0 + h * nwave, ny - 1);
-          const uint32_t tyy = yt[j];
+          const uint32_t tyy = (uint32_t)uniform((int)yt[min(j0 + h, ny - 1)]);
           const int y0 = tyy >> 9;
           wyr[h] = tyy & 511;
           gptr<const uint8_t> r0 = base + (size_t)y0 * bs;
           gptr<const uint8_t> r1 = base + (size_t)min(y0 + 1, bh1) * bs;
 #pragma unroll
           for (int c = 0; c < 5; ++c) {
-            const int i = min(lane + 64 * c, nx - 1);
-            const uint32_t txx = xt[i];
-            const int x0 = txx >> 9;
-            const int x1 = min(x0 + 1, bw1);
-            v[h][c][0] = r0[x0];
-            v[h][c][1] = r0[x1];
-            v[h][c][2] = r1[x0];
-            v[h][c][3] = r1[x1];
+            v[h][c][0] = r0[cx0[c]];
+            v[h][c][1] = r0[cx1[c]];
+            v[h][c][2] = r1[cx0[c]];
+            v[h][c][3] = r1[cx1[c]];
           }
         }
 #pragma unroll
         for (int h = 0; h < 2; ++h) {
-          const int j = j0 + h * nwave;
+          const int j = j0 + h;
           if (j >= ny) break;
           const int wy = wyr[h];
 #pragma unroll
           for (int c = 0; c < 5; ++c) {
             const int i = lane + 64 * c;
             if (i < nx) {
-              const int wx = xt[i] & 511;
+              const int wx = cwx[c];
               const int top = (256 - wx) * v[h][c][0] + wx * v[h][c][1];
               const int bot = (256 - wx) * v[h][c][2] + wx * v[h][c][3];
               pix[j * M.pitch + i] = (uint8_t)(((256 - wy) * top + wy * bot + 32768) >> 16);
@@ -596,11 +643,14 @@ __global__ __launch_bounds__(256) void k_mark(KArgs a) {
       const int lx0 = x_t0 - ox;
       const int nwd = (x_t1 - x_t0 + 3) >> 2;
       gptr<uint8_t> lw = G(P.lvl_w);
-      for (int i = threadIdx.x; i < nwd * (y_t1 - y_t0); i += blockDim.x) {
-        const int r = i / nwd, w = i - r * nwd;
+      for (int r = wave; r < y_t1 - y_t0; r += nwave) {
         const int y = y_t0 + r;
-        *(gptr<uint32_t>)(lw + (size_t)y * P.lvl_stride + x_t0 + 4 * w) =
-            *(const uint32_t*)(pix + (y - oy) * M.pitch + lx0 + 4 * w);
+        for (int w0 = 0; w0 < nwd; w0 += 64) {
+          const int w = w0 + lane;
+          if (w < nwd)
+            *(gptr<uint32_t>)(lw + (size_t)y * P.lvl_stride + x_t0 + 4 * w) =
+                *(const uint32_t*)(pix + (y - oy) * M.pitch + lx0 + 4 * w);
+        }
       }
     } else {
       const int limit = P.level == 0 ? W : P.lvl_stride;
@@ -675,11 +725,15 @@ __global__ __launch_bounds__(256) void k_mark(KArgs a) {
     const int w0 = x_t0 >> 5;
     const int nwd = min(2 * TWW, P.wpr - w0);
     gptr<uint32_t> glo = G(P.bm_lo), ghi = G(P.bm_hi);
-    for (int i = threadIdx.x; i < nwd * (y_t1 - y_t0); i += blockDim.x) {
-      const int r = i / nwd, k = i - r * nwd;
-      const size_t gi = (size_t)(y_t0 + r) * P.wpr + w0 + k;
-      glo[gi] = bml[r * 2 * TWW + k];
-      ghi[gi] = bmh[r * 2 * TWW + k];
+    {
+      const int k = threadIdx.x & 7;  // at most 8 words per tile row
+      for (int r = threadIdx.x >> 3; r < y_t1 - y_t0; r += blockDim.x >> 3) {
+        if (k < nwd) {
+          const size_t gi = (size_t)(y_t0 + r) * P.wpr + w0 + k;
+          glo[gi] = bml[r * 2 * TWW + k];
+          ghi[gi] = bmh[r * 2 * TWW + k];
+        }
+      }
     }
     queue_park(a, next, &s_next);
   }
@@ -801,46 +855,47 @@ __global__ __launch_bounds__(256) void k_detect(KArgs a) {
     }
     __syncthreads();
     // 2. candidate words over tile + ring: corner at the threshold of its own cell
-    for (int u = wave; u < nunits; u += nwave) {
-      const int j = u / nwr, k = u - j * nwr;
-      const int lxr = 64 * k + lane;
-      const int x = rx0 + lxr, y = ry0 + j;
-      bool c = false;
-      if (lxr < rw && x >= B && x < W - B && y >= B && y < H - B) {
-        const int wi = j * nbw + (x >> 5) - bw0;
-        const uint32_t bit = 1u << (x & 31);
-        if (whi[wi] & bit) {
-          c = true;
-        } else if (wlo[wi] & bit) {
-          c = lfl[(y / cs - fcy0) * nfx + x / cs - fcx0] == 0;
+    for (int j = wave; j < rh; j += nwave) {
+      const int y = ry0 + j;
+      const bool yok = y >= B && y < H - B;
+      for (int k = 0; k < nwr; ++k) {
+        const int lxr = 64 * k + lane;
+        const int x = rx0 + lxr;
+        bool c = false;
+        if (yok && lxr < rw && x >= B && x < W - B) {
+          const int wi = j * nbw + (x >> 5) - bw0;
+          const uint32_t bit = 1u << (x & 31);
+          if (whi[wi] & bit) {
+            c = true;
+          } else if (wlo[wi] & bit) {
+            c = lfl[(y / cs - fcy0) * nfx + x / cs - fcx0] == 0;
+          }
         }
-      }
-      const uint64_t m = __ballot(c);
-      if (lane == 0) {
-        cw[u] = m;
-        ucnt[u] = (uint32_t)__popcll(m);
+        const uint64_t m = __ballot(c);
+        if (lane == 0) {
+          cw[j * nwr + k] = m;
+          ucnt[j * nwr + k] = (uint32_t)__popcll(m);
+        }
       }
     }
     __syncthreads();
     block_scan_u32(ucnt, cpre, nunits, s_wsum);
     const int ncand = (int)cpre[nunits];
     // 3. cached candidate positions (raster order) and their Harris scores
-    for (int u = wave; u < nunits; u += nwave) {
-      const uint64_t m = cw[u];
-      if ((m >> lane) & 1ull) {
-        const uint32_t idx = cpre[u] + lanes_below(m);
-        if (idx < (uint32_t)kCandCache) {
-          const int j = u / nwr, k = u - j * nwr;
-          cpos[idx] = ((uint32_t)(ry0 + j) << 16) | (uint32_t)(rx0 + 64 * k + lane);
+    for (int j = wave; j < rh; j += nwave) {
+      for (int k = 0; k < nwr; ++k) {
+        const int u = j * nwr + k;
+        const uint64_t m = cw[u];
+        if ((m >> lane) & 1ull) {
+          const uint32_t idx = cpre[u] + lanes_below(m);
+          if (idx < (uint32_t)kCandCache)
+            cpos[idx] = ((uint32_t)(ry0 + j) << 16) | (uint32_t)(rx0 + 64 * k + lane);
         }
       }
     }
     __syncthreads();
     const int ncache = min(ncand, kCandCache);
-    for (int i = threadIdx.x; i < ncache; i += blockDim.x) {
-      const uint32_t pos = cpos[i];
-      crs[i] = harris_lds(pix, D.pitch, (int)(pos & 0xffff) - sx0, (int)(pos >> 16) - sy0);
-    }
+    harris_groups(pix, D.pitch, cpos, crs, ncache, sx0, sy0);
     __syncthreads();
     // 4. NMS: a tile candidate survives when it ranks above every candidate neighbour.
     //    One thread per candidate; neighbours are found through the candidate words.
