@@ -552,13 +552,17 @@ __global__ __launch_bounds__(256) void k_pyramid(PyrArgs a) {
 
 // ------------------------------------------------------------ segment test --
 
-template <bool FUSED>
+// One block per segment-test tile of 64*TWW x mark_rows level pixels.  TWW fixes the
+// LDS row pitch at compile time, so every circle and compass offset below is a
+// ds_read immediate.
+template <bool FUSED, int TWW>
 __global__ __launch_bounds__(256) void k_mark(KArgs a) {
+  constexpr int TW = 64 * TWW;
+  constexpr int PITCH = TW + 8;
   extern __shared__ __align__(16) uint8_t smem[];
   __shared__ int s_next, s_qcnt[4];
   __shared__ int32_t s_base[kMaxEntries + 1];
   const MarkLds M = mark_lds(a.t);
-  const int TWW = a.t.mark_words;
   uint8_t* pix = smem;
   uint16_t* queue = (uint16_t*)(smem + M.off_queue);
   uint32_t* bml = (uint32_t*)(smem + M.off_bml);
@@ -579,7 +583,7 @@ __global__ __launch_bounds__(256) void k_mark(KArgs a) {
     const LevelPlan P = a.plan[e];
     const int W = P.W, H = P.H, B = P.B;
     const int tx = t % P.mark_tx, ty = t / P.mark_tx;
-    const int x_t0 = tx * M.tw, x_t1 = min(W, x_t0 + M.tw);
+    const int x_t0 = tx * TW, x_t1 = min(W, x_t0 + TW);
     const int y_t0 = ty * M.th, y_t1 = min(H, y_t0 + M.th);
     const int ox = max(0, x_t0 - 4), oy = max(0, y_t0 - 3);
     const int ex = min(W, x_t1 + 3), ey = min(H, y_t1 + 3);
@@ -592,19 +596,20 @@ __global__ __launch_bounds__(256) void k_mark(KArgs a) {
       __syncthreads();
       // Column taps stay in registers (lane owns columns lane + 64c); each wave takes two
       // consecutive output rows at a time with their base-row pointers in scalar
-      // registers, so a tap costs its load and the blend only (40 gathers in flight).
+      // registers, so a tap costs its load and the blend only.
       gptr<const uint8_t> base = G(P.base);
       const int bs = P.base_stride, bw1 = P.base_w - 1, bh1 = P.base_h - 1;
-      int cx0[5], cx1[5], cwx[5];
+      constexpr int NC = TWW + 1;  // columns per lane: nx <= TW + 7
+      int cx0[NC], cx1[NC], cwx[NC];
 #pragma unroll
-      for (int c = 0; c < 5; ++c) {
+      for (int c = 0; c < NC; ++c) {
         const uint32_t txx = xt[min(lane + 64 * c, nx - 1)];
         cx0[c] = txx >> 9;
         cx1[c] = min(cx0[c] + 1, bw1);
         cwx[c] = txx & 511;
       }
       for (int j0 = 2 * wave; j0 < ny; j0 += 2 * nwave) {
-        int v[2][5][4];
+        int v[2][NC][4];
         int wyr[2];
 #pragma unroll
         for (int h = 0; h < 2; ++h) {
@@ -614,7 +619,7 @@ __global__ __launch_bounds__(256) void k_mark(KArgs a) {
           gptr<const uint8_t> r0 = base + (size_t)y0 * bs;
           gptr<const uint8_t> r1 = base + (size_t)min(y0 + 1, bh1) * bs;
 #pragma unroll
-          for (int c = 0; c < 5; ++c) {
+          for (int c = 0; c < NC; ++c) {
             v[h][c][0] = r0[cx0[c]];
             v[h][c][1] = r0[cx1[c]];
             v[h][c][2] = r1[cx0[c]];
@@ -626,14 +631,15 @@ __global__ __launch_bounds__(256) void k_mark(KArgs a) {
           const int j = j0 + h;
           if (j >= ny) break;
           const int wy = wyr[h];
+          uint8_t* prow = pix + j * PITCH;
 #pragma unroll
-          for (int c = 0; c < 5; ++c) {
+          for (int c = 0; c < NC; ++c) {
             const int i = lane + 64 * c;
             if (i < nx) {
               const int wx = cwx[c];
               const int top = (256 - wx) * v[h][c][0] + wx * v[h][c][1];
               const int bot = (256 - wx) * v[h][c][2] + wx * v[h][c][3];
-              pix[j * M.pitch + i] = (uint8_t)(((256 - wy) * top + wy * bot + 32768) >> 16);
+              prow[i] = (uint8_t)(((256 - wy) * top + wy * bot + 32768) >> 16);
             }
           }
         }
@@ -649,45 +655,53 @@ __global__ __launch_bounds__(256) void k_mark(KArgs a) {
           const int w = w0 + lane;
           if (w < nwd)
             *(gptr<uint32_t>)(lw + (size_t)y * P.lvl_stride + x_t0 + 4 * w) =
-                *(const uint32_t*)(pix + (y - oy) * M.pitch + lx0 + 4 * w);
+                *(const uint32_t*)(pix + (y - oy) * PITCH + lx0 + 4 * w);
         }
       }
     } else {
       const int limit = P.level == 0 ? W : P.lvl_stride;
-      stage_rows(pix, M.pitch, G(P.lvl), P.lvl_stride, limit, ox, ex, oy, ey);
+      stage_rows(pix, PITCH, G(P.lvl), P.lvl_stride, limit, ox, ex, oy, ey);
     }
     for (int i = threadIdx.x; i < 2 * M.th * 2 * TWW; i += blockDim.x) bml[i] = 0u;  // lo, hi
     __syncthreads();
 
     // 2. compass pre-test at fast_t_min: a run of 9 holds two cyclically adjacent
-    //    compass points (positions 1/5/9/13), so (n|s) & (e|w) per polarity is necessary.
-    //    Each wave appends the pixels that pass to its own quarter of the queue.
+    //    compass points (positions 1/5/9/13), so (n|s) & (e|w) per polarity is
+    //    necessary; (n >= hi | s >= hi) & (e >= hi | w >= hi) is
+    //    min(max(n, s), max(e, w)) >= hi, and likewise for dark.  Each wave takes rows
+    //    and appends the pixels that pass to its own quarter of the queue.
     const int tlo = P.fast_t_min, thi = P.fast_t;
-    const int ya = max(y_t0, B), yb = min(y_t1, H - B);
-    const int units = max(0, yb - ya) * TWW;
-    const int qseg = M.qseg;  // launches use 4 waves per block
-    uint16_t* myq = queue + wave * qseg;
-    int qn = 0;
-    for (int u = wave; u < units; u += nwave) {
-      const int y = ya + u / TWW;
-      const int x = x_t0 + 64 * (u % TWW) + lane;
-      const bool valid = x >= B && x < W - B;
-      const int lx = x - ox, ly = y - oy;
-      bool pass = false;
-      if (valid) {
-        const uint8_t* c = pix + ly * M.pitch + lx;
-        const int p = c[0];
-        const int vn = c[-3 * M.pitch], vs = c[3 * M.pitch], ve = c[3], vw = c[-3];
-        const int hi = p + tlo, lo = p - tlo;
-        const bool b = ((vn >= hi) | (vs >= hi)) & ((ve >= hi) | (vw >= hi));
-        const bool d = ((vn <= lo) | (vs <= lo)) & ((ve <= lo) | (vw <= lo));
-        pass = b | d;
+    {
+      const int ya = max(y_t0, B), yb = min(y_t1, H - B);
+      uint16_t* myq = queue + wave * M.qseg;
+      int qn = 0;
+      int lxk[TWW];
+      bool vk[TWW];
+#pragma unroll
+      for (int k = 0; k < TWW; ++k) {
+        const int x = x_t0 + 64 * k + lane;
+        lxk[k] = x - ox;
+        vk[k] = x >= B && x < W - B;
       }
-      const uint64_t m = __ballot(pass);
-      if (pass) myq[qn + lanes_below(m)] = (uint16_t)(lx | (ly << 9));
-      qn += __popcll(m);
+      for (int y = ya + wave; y < yb; y += nwave) {
+        const int ly = y - oy;
+        const uint8_t* rowp = pix + (ly - 3) * PITCH;  // compass north row
+#pragma unroll
+        for (int k = 0; k < TWW; ++k) {
+          const uint8_t* c = rowp + lxk[k];
+          const int vn = c[0], vw = c[3 * PITCH - 3], p = c[3 * PITCH], ve = c[3 * PITCH + 3];
+          const int vs = c[6 * PITCH];
+          const bool pass = vk[k] && (min(max(vn, vs), max(ve, vw)) >= p + tlo ||
+                                      max(min(vn, vs), min(ve, vw)) <= p - tlo);
+          const uint64_t m = __ballot(pass);
+          if (m) {
+            if (pass) myq[qn + lanes_below(m)] = (uint16_t)(lxk[k] | (ly << 9));
+            qn += __popcll(m);
+          }
+        }
+      }
+      if (lane == 0) s_qcnt[wave] = qn;
     }
-    if (lane == 0) s_qcnt[wave] = qn;
     __syncthreads();
 
     // 3. full segment test of the queued pixels at both thresholds
@@ -703,10 +717,27 @@ __global__ __launch_bounds__(256) void k_mark(KArgs a) {
       int w = 0;
 #pragma unroll
       for (int k = 1; k < 4; ++k) w += q >= qoff[k] ? 1 : 0;
-      const int ent = queue[w * qseg + (q - qoff[w])];
+      const int ent = queue[w * M.qseg + (q - qoff[w])];
       const int lx = ent & 511, ly = ent >> 9;
+      const uint8_t* c0 = pix + (ly - 3) * PITCH + (lx - 3);  // top-left of the 7x7 box
+      const int p = c0[3 * PITCH + 3];
       int d[16];
-      circle_diffs(pix + ly * M.pitch + lx, M.pitch, d);
+      d[0] = c0[3] - p;
+      d[1] = c0[4] - p;
+      d[2] = c0[PITCH + 5] - p;
+      d[3] = c0[2 * PITCH + 6] - p;
+      d[4] = c0[3 * PITCH + 6] - p;
+      d[5] = c0[4 * PITCH + 6] - p;
+      d[6] = c0[5 * PITCH + 5] - p;
+      d[7] = c0[6 * PITCH + 4] - p;
+      d[8] = c0[6 * PITCH + 3] - p;
+      d[9] = c0[6 * PITCH + 2] - p;
+      d[10] = c0[5 * PITCH + 1] - p;
+      d[11] = c0[4 * PITCH] - p;
+      d[12] = c0[3 * PITCH] - p;
+      d[13] = c0[2 * PITCH] - p;
+      d[14] = c0[PITCH + 1] - p;
+      d[15] = c0[2] - p;
       const uint32_t r = segment_test2(d, tlo, thi);
       if (r) {
         const int x = ox + lx, y = oy + ly;
@@ -1284,12 +1315,22 @@ hipError_t launch_pyramid(const PyrArgs& a, int n_levels, int max_w, int max_h, 
   return hipGetLastError();
 }
 
+template <int TWW>
+void launch_mark_w(const KArgs& a, bool fused, int grid, int bytes, hipStream_t s) {
+  if (fused)
+    hipLaunchKernelGGL((k_mark<true, TWW>), dim3(grid), dim3(256), bytes, s, a);
+  else
+    hipLaunchKernelGGL((k_mark<false, TWW>), dim3(grid), dim3(256), bytes, s, a);
+}
+
 hipError_t launch_mark(const KArgs& a, bool fused, int grid, hipStream_t s) {
   const MarkLds M = mark_lds(a.t);
-  if (fused)
-    hipLaunchKernelGGL(k_mark<true>, dim3(grid), dim3(256), M.bytes, s, a);
-  else
-    hipLaunchKernelGGL(k_mark<false>, dim3(grid), dim3(256), M.bytes, s, a);
+  switch (a.t.mark_words) {
+    case 1: launch_mark_w<1>(a, fused, grid, M.bytes, s); break;
+    case 2: launch_mark_w<2>(a, fused, grid, M.bytes, s); break;
+    case 3: launch_mark_w<3>(a, fused, grid, M.bytes, s); break;
+    default: launch_mark_w<4>(a, fused, grid, M.bytes, s); break;
+  }
   return hipGetLastError();
 }
 
