@@ -885,27 +885,39 @@ __global__ __launch_bounds__(256) void k_detect(KArgs a) {
       s_ne = 0;
     }
     __syncthreads();
-    // 2. candidate words over tile + ring: corner at the threshold of its own cell
-    for (int j = wave; j < rh; j += nwave) {
-      const int y = ry0 + j;
-      const bool yok = y >= B && y < H - B;
-      for (int k = 0; k < nwr; ++k) {
+    // 2. candidate words over tile + ring: corner at the threshold of its own cell.
+    //    Cell columns of a lane's pixels are fixed for the tile (nwr <= 5 words), cell
+    //    rows advance with the row, so no division runs per pixel.
+    {
+      int lcx[5];
+      bool xok[5];
+#pragma unroll
+      for (int k = 0; k < 5; ++k) {
         const int lxr = 64 * k + lane;
         const int x = rx0 + lxr;
-        bool c = false;
-        if (yok && lxr < rw && x >= B && x < W - B) {
-          const int wi = j * nbw + (x >> 5) - bw0;
-          const uint32_t bit = 1u << (x & 31);
-          if (whi[wi] & bit) {
-            c = true;
-          } else if (wlo[wi] & bit) {
-            c = lfl[(y / cs - fcy0) * nfx + x / cs - fcx0] == 0;
+        xok[k] = k < nwr && lxr < rw && x >= B && x < W - B;
+        lcx[k] = xok[k] ? x / cs - fcx0 : 0;
+      }
+      for (int j = wave; j < rh; j += nwave) {
+        const int y = ry0 + j;
+        const bool yok = y >= B && y < H - B;
+        const uint8_t* frow = lfl + (y / cs - fcy0) * nfx;
+        const uint32_t* rlo = wlo + j * nbw - bw0;
+        const uint32_t* rhi = whi + j * nbw - bw0;
+#pragma unroll
+        for (int k = 0; k < 5; ++k) {
+          if (k >= nwr) break;
+          const int x = rx0 + 64 * k + lane;
+          bool c = false;
+          if (yok && xok[k]) {
+            const uint32_t bit = 1u << (x & 31);
+            c = (rhi[x >> 5] & bit) != 0 || ((rlo[x >> 5] & bit) != 0 && frow[lcx[k]] == 0);
           }
-        }
-        const uint64_t m = __ballot(c);
-        if (lane == 0) {
-          cw[j * nwr + k] = m;
-          ucnt[j * nwr + k] = (uint32_t)__popcll(m);
+          const uint64_t m = __ballot(c);
+          if (lane == 0) {
+            cw[j * nwr + k] = m;
+            ucnt[j * nwr + k] = (uint32_t)__popcll(m);
+          }
         }
       }
     }
@@ -1064,19 +1076,19 @@ __global__ __launch_bounds__(256) void k_select_orient(KArgs a) {
   if (i >= C || C > kRankCap) return;
   gptr<const Cand> cand = G((const Cand*)P.cand);
   const Cand me = load_cand(cand + i);
+  // Count better candidates, 8 loads in flight per lane; a wave whose partial count
+  // already reaches the quota cannot be selected and stops early.
   int cnt = 0;
-  for (int j0 = 0; j0 < C; j0 += 4 * 64) {
-    Cand o[4];
+  for (int j0 = 0; j0 < C; j0 += 8 * 64) {
+    Cand o[8];
 #pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      const int j = min(j0 + u * 64 + lane, C - 1);
-      o[u] = load_cand(cand + j);
-    }
+    for (int u = 0; u < 8; ++u) o[u] = load_cand(cand + min(j0 + u * 64 + lane, C - 1));
 #pragma unroll
-    for (int u = 0; u < 4; ++u) {
+    for (int u = 0; u < 8; ++u) {
       const int j = j0 + u * 64 + lane;
       cnt += (j < C && better(o[u].score, o[u].pos, me.score, me.pos)) ? 1 : 0;
     }
+    if (j0 + 8 * 64 < C && wave_sum(cnt) >= P.quota) return;
   }
   const int rank = wave_sum(cnt);
   if (rank >= P.quota) return;
