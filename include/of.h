@@ -91,8 +91,9 @@ typedef struct {
   int64_t total_bytes;
 } of_pyramid_desc;
 
-/* Launch shape of the batched path (tile sizes, persistent grid sizes).  Any field set
- * to 0 takes the default; of_tuning_default() reports the defaults for a batch. */
+/* Launch shape of the batched path (tile sizes, grid sizes, pyramid pass).  Tile fields
+ * set to 0 take the default; grid and pyr_pass fields take the default when negative.
+ * of_tuning_default() reports the defaults for a batch.  det_w and det_h must be even. */
 typedef struct {
   int32_t mark_words; /* segment-test tile width in 64-pixel words, 1..4 */
   int32_t mark_rows;  /* segment-test tile height, 4..64 */
@@ -100,6 +101,8 @@ typedef struct {
   int32_t det_w, det_h;             /* Harris/NMS tile in pixels when cell == 0; <= 256 x 128 */
   int32_t mark_grid;  /* workgroups of the persistent segment-test launch (0 = one per tile) */
   int32_t det_grid;   /* workgroups of the persistent Harris/NMS launch (0 = one per tile) */
+  int32_t pyr_pass;   /* 1 = resample the levels in a pass of their own before the segment
+                         test; 0 = the segment-test tiles resample their own pixels */
 } of_tuning;
 
 /* Host only.  Level sizes, strides and offsets of the pyramid of a W x H frame. */

@@ -111,6 +111,7 @@ Tune default_tune(const of_params& p) {
   // persistent grid).
   t.mark_grid = 0;
   t.det_grid = 0;
+  t.pyr_pass = 0;
   return t;
 }
 
@@ -125,6 +126,7 @@ int resolve_tune(const of_tuning* user, const of_params& p, Tune* out) {
     if (user->det_h) t.det_h = user->det_h;
     if (user->mark_grid >= 0) t.mark_grid = user->mark_grid;
     if (user->det_grid >= 0) t.det_grid = user->det_grid;
+    if (user->pyr_pass >= 0) t.pyr_pass = user->pyr_pass != 0;
   }
   if (t.mark_words < 1 || t.mark_words > 4 || t.mark_rows < 4 || t.mark_rows > 64)
     return OF_EINVAL;
@@ -133,8 +135,13 @@ int resolve_tune(const of_tuning* user, const of_params& p, Tune* out) {
         t.det_cy * p.cell > kMaxDetH)
       return OF_EINVAL;
   }
-  if (t.det_w < 8 || t.det_w > kMaxDetW || t.det_h < 8 || t.det_h > kMaxDetH) return OF_EINVAL;
-  if (mark_lds(t).bytes > 65536 || det_lds(t, p.cell).bytes > 65536) return OF_EINVAL;
+  // det_w, det_h even: tiles then start on the 2x2 blocks that own the output slots
+  if (t.det_w < 8 || t.det_w > kMaxDetW || t.det_h < 8 || t.det_h > kMaxDetH ||
+      (t.det_w & 1) || (t.det_h & 1))
+    return OF_EINVAL;
+  const int32_t bases = base_table_bytes(kMaxEntries);
+  if (mark_lds(t).bytes + bases > 65536 || det_lds(t, p.cell).bytes + bases > 65536)
+    return OF_EINVAL;
   *out = t;
   return OF_OK;
 }
@@ -214,6 +221,7 @@ KArgs kargs(void* ws, const WsLayout& lay, const Tune& t, const of_params& p) {
   k.det_base = (const int32_t*)(b + lay.off_det_base);
   k.orient_base = (const int32_t*)(b + lay.off_orient_base);
   k.rank_base = (const int32_t*)(b + lay.off_rank_base);
+  k.pyr_base = (const int32_t*)(b + lay.off_pyr_base);
   k.rank_path = 1;
   k.qctr = (uint32_t*)(b + lay.off_hdr);
   k.n_entries = lay.n_entries;
@@ -319,6 +327,7 @@ int of_tuning_default(const of_image* frames, int32_t n, const of_params* params
   out->det_h = t.det_h;
   out->mark_grid = t.mark_grid;
   out->det_grid = t.det_grid;
+  out->pyr_pass = t.pyr_pass;
   return OF_OK;
 }
 
@@ -400,10 +409,15 @@ int of_detect_batch(const of_image* frames, int32_t n, const of_params* params, 
   hipError_t e = timed(0, stream, [&] { return launch_prologue(*pa, prologue_grid(c->lay), stream); });
   delete pa;
   KArgs k = kargs(ws, c->lay, t, p);
+  const bool fused = !t.pyr_pass || c->lay.pyr_blocks == 0;
+  if (e == hipSuccess && !fused) {
+    k.total = c->lay.pyr_blocks;
+    e = timed(1, stream, [&] { return launch_pyramid_batch(k, c->lay.pyr_blocks, stream); });
+  }
   if (e == hipSuccess) {
     k.total = c->lay.mark_tiles;
     k.persistent = t.mark_grid > 0 && t.mark_grid < k.total;
-    e = timed(2, stream, [&] { return launch_mark(k, true, k.persistent ? t.mark_grid : k.total, stream); });
+    e = timed(2, stream, [&] { return launch_mark(k, fused, k.persistent ? t.mark_grid : k.total, stream); });
   }
   if (e == hipSuccess) {
     k.total = c->lay.det_tiles;

@@ -31,6 +31,7 @@ struct KArgs {
   const int32_t* det_base;
   const int32_t* orient_base;
   const int32_t* rank_base;    // exclusive prefix of ranked candidate slots per entry
+  const int32_t* pyr_base;     // exclusive prefix of resample blocks per entry
   uint32_t* qctr;              // queue counters: [0] segment-test tiles, [2] Harris tiles
   int32_t n_entries;
   int32_t total;               // tiles (or blocks) of this launch
@@ -54,6 +55,7 @@ struct PyrArgs {
 
 hipError_t launch_prologue(const PrologueArgs& a, int grid, hipStream_t s);
 hipError_t launch_pyramid(const PyrArgs& a, int n_levels, int max_w, int max_h, hipStream_t s);
+hipError_t launch_pyramid_batch(const KArgs& a, int blocks, hipStream_t s);
 hipError_t launch_mark(const KArgs& a, bool fused, int grid, hipStream_t s);
 hipError_t launch_detect(const KArgs& a, int grid, hipStream_t s);
 hipError_t launch_select_orient(const KArgs& a, int slots, hipStream_t s);

@@ -151,32 +151,40 @@ __device__ __forceinline__ uint32_t load_word(gptr<const uint8_t> s, bool whole,
   return v;
 }
 
+// Rows [y0, y1) x columns [x0, x1) of a level into LDS (row pitch lp), as 32-bit words.
+// The block's threads take the words in order, U per thread per pass, so a tile of up
+// to U * blockDim words costs one round trip to memory.
+template <int U>
 __device__ __forceinline__ void stage_rows(uint8_t* lds, int lp, gptr<const uint8_t> src,
                                            int stride, int row_limit, int x0, int x1, int y0,
                                            int y1) {
-  constexpr int U = 4;
   const bool aligned = ((((uintptr_t)src) | (uintptr_t)stride) & 3) == 0;
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nwave = blockDim.x >> 6;
   const int nw = (x1 - x0 + 3) >> 2;
-  const int nrow = y1 - y0;
-  for (int r0 = wave * U; r0 < nrow; r0 += nwave * U) {
-    for (int w0 = 0; w0 < nw; w0 += 64) {
-      const int w = w0 + lane;
+  const int total = nw * (y1 - y0);
+  const int bd = (int)blockDim.x;
+  const int drow = bd / nw, dw = bd - drow * nw;  // advance of (row, word) per bd words
+  int row = (int)threadIdx.x / nw;
+  int w = (int)threadIdx.x - row * nw;
+  for (int base = 0; base < total; base += U * bd) {
+    uint32_t v[U];
+    int off[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
       const int x = x0 + 4 * w;
-      const bool in_x = w < nw;
-      const bool whole = aligned && x + 4 <= row_limit;
-      const int nb = min(4, x1 - x);
-      uint32_t v[U];
-#pragma unroll
-      for (int u = 0; u < U; ++u) {
-        v[u] = 0;
-        if (in_x && r0 + u < nrow)
-          v[u] = load_word(src + (size_t)(y0 + r0 + u) * stride + x, whole, nb);
+      off[u] = base + u * bd + (int)threadIdx.x < total ? row * lp + 4 * w : -1;
+      v[u] = off[u] >= 0 ? load_word(src + (size_t)(y0 + row) * stride + x,
+                                     aligned && x + 4 <= row_limit, min(4, x1 - x))
+                         : 0u;
+      row += drow;
+      w += dw;
+      if (w >= nw) {
+        w -= nw;
+        ++row;
       }
-#pragma unroll
-      for (int u = 0; u < U; ++u)
-        if (in_x && r0 + u < nrow) *(uint32_t*)(lds + (r0 + u) * lp + 4 * w) = v[u];
     }
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+      if (off[u] >= 0) *(uint32_t*)(lds + off[u]) = v[u];
   }
 }
 
@@ -272,6 +280,15 @@ __device__ __forceinline__ void harris_groups(const uint8_t* pix, int P, const u
   }
 }
 
+// Block barrier that orders LDS accesses only.  __syncthreads() also waits for the
+// block's global stores to complete; tiles that never read back their own global
+// stores use this one so that stores drain while the next step runs.
+__device__ __forceinline__ void lds_barrier() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+  __builtin_amdgcn_s_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
 // Exclusive scan of cnt[0..n) into pre[0..n], pre[n] = total, by the whole block.
 __device__ void block_scan_u32(const uint32_t* cnt, uint32_t* pre, int n, uint32_t* s_wsum) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nwave = blockDim.x >> 6;
@@ -286,7 +303,7 @@ __device__ void block_scan_u32(const uint32_t* cnt, uint32_t* pre, int n, uint32
       if (lane >= o) inc += t;
     }
     if (lane == 63) s_wsum[wave] = inc;
-    __syncthreads();
+    lds_barrier();
     uint32_t woff = 0, total = 0;
     for (int w = 0; w < nwave; ++w) {
       const uint32_t s = s_wsum[w];
@@ -295,10 +312,10 @@ __device__ void block_scan_u32(const uint32_t* cnt, uint32_t* pre, int n, uint32
     }
     if (i < n) pre[i] = carry + woff + inc - v;
     carry += total;
-    __syncthreads();
+    lds_barrier();
   }
   if (threadIdx.x == 0) pre[n] = carry;
-  __syncthreads();
+  lds_barrier();
 }
 
 // Intensity-centroid moments over the disk dx^2 + dy^2 <= r^2 around (x, y), one wave
@@ -344,7 +361,7 @@ __device__ __forceinline__ void queue_start(const KArgs& a, uint32_t* ctr, int* 
 
 __device__ __forceinline__ int queue_take(const KArgs& a, int iter, int* s_next) {
   if (!a.persistent) return iter == 0 ? (int)blockIdx.x : a.total;
-  __syncthreads();
+  lds_barrier();
   return *s_next;
 }
 
@@ -359,7 +376,7 @@ __device__ __forceinline__ void queue_park(const KArgs& a, int next, int* s_next
 // Copy of an exclusive prefix (n + 1 values) into LDS for entry lookups.
 __device__ __forceinline__ void load_bases(int32_t* s_base, const int32_t* base, int n) {
   for (int i = threadIdx.x; i <= n; i += blockDim.x) s_base[i] = G(base)[i];
-  __syncthreads();
+  lds_barrier();
 }
 
 // ---------------------------------------------------------------- prologue --
@@ -432,12 +449,15 @@ __global__ __launch_bounds__(1024) void k_prologue(PrologueArgs a) {
   const int64_t t_rank = s_tot;
   const int64_t o_sel = scan(s.sel_cap);
   const int64_t o_lvl = scan(s.lvl_bytes);
+  const int64_t o_pyr = scan(s.pyr_blocks);
+  const int64_t t_pyr = s_tot;
 
   LevelPlan* plan = (LevelPlan*)(ws + a.lay.off_plan);
   int32_t* mark_base = (int32_t*)(ws + a.lay.off_mark_base);
   int32_t* det_base = (int32_t*)(ws + a.lay.off_det_base);
   int32_t* or_base = (int32_t*)(ws + a.lay.off_orient_base);
   int32_t* rank_base = (int32_t*)(ws + a.lay.off_rank_base);
+  int32_t* pyr_base = (int32_t*)(ws + a.lay.off_pyr_base);
   uint32_t* counters = (uint32_t*)(ws + a.lay.off_counters);
 
   if (i < nL) {
@@ -475,6 +495,8 @@ __global__ __launch_bounds__(1024) void k_prologue(PrologueArgs a) {
     P.cand = (Cand*)(ws + a.lay.off_cand) + o_cand;
     P.cand_count = counters + i;
     P.cand_cap = (int32_t)s.cand_cap;
+    P.kslot = s.kslot;
+    P.slot_w = s.slot_w;
     P.sel = (Cand*)(ws + a.lay.off_sel) + o_sel;
     P.sel_count = counters + a.lay.n_entries + i;
     P.mark_tx = s.mark_tx;
@@ -494,12 +516,14 @@ __global__ __launch_bounds__(1024) void k_prologue(PrologueArgs a) {
     det_base[i] = (int32_t)o_det;
     or_base[i] = (int32_t)o_or;
     rank_base[i] = (int32_t)o_rank;
+    pyr_base[i] = (int32_t)o_pyr;
   }
   if (i == 0) {
     mark_base[nL] = (int32_t)t_mark;
     det_base[nL] = (int32_t)t_det;
     or_base[nL] = (int32_t)t_or;
     rank_base[nL] = (int32_t)t_rank;
+    pyr_base[nL] = (int32_t)t_pyr;
   }
   __threadfence();
   __syncthreads();
@@ -508,46 +532,69 @@ __global__ __launch_bounds__(1024) void k_prologue(PrologueArgs a) {
 
 // ----------------------------------------------------------------- pyramid --
 
-// One block = 64 x 16 output pixels of level blockIdx.z; the tap tables of its columns
-// and rows are computed once in LDS.  Weights are Q8; one rounding at the end.
+// One block = 64 x 16 output pixels of one level; the tap tables of its columns and rows
+// are computed once in LDS.  Weights are Q8; one rounding at the end.
+__device__ __forceinline__ void resample_block(gptr<const uint8_t> src, int src_w, int src_h,
+                                               int src_stride, gptr<uint8_t> dst, int w, int h,
+                                               int stride, int bx, int by, uint32_t* xt,
+                                               uint32_t* yt) {
+  const int t = threadIdx.x;
+  if (t < 64 && bx + t < w) xt[t] = resample_tap(bx + t, src_w, w);
+  if (t >= 64 && t < 80 && by + t - 64 < h) yt[t - 64] = resample_tap(by + t - 64, src_h, h);
+  lds_barrier();
+  const int lx = t & 63;
+  const int x = bx + lx;
+  if (x >= w) return;
+  const uint32_t tx = xt[lx];
+  const int x0 = tx >> 9, wx = tx & 511;
+  const int x1 = min(x0 + 1, src_w - 1);
+  int v[4][4];
+  int wy[4];
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    const int ly = min((t >> 6) * 4 + k, h - 1 - by);
+    const uint32_t ty = yt[ly];
+    const int y0 = ty >> 9;
+    wy[k] = ty & 511;
+    const int y1 = min(y0 + 1, src_h - 1);
+    v[k][0] = src[(size_t)y0 * src_stride + x0];
+    v[k][1] = src[(size_t)y0 * src_stride + x1];
+    v[k][2] = src[(size_t)y1 * src_stride + x0];
+    v[k][3] = src[(size_t)y1 * src_stride + x1];
+  }
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    const int y = by + (t >> 6) * 4 + k;
+    if (y >= h) break;
+    const int top = (256 - wx) * v[k][0] + wx * v[k][1];
+    const int bot = (256 - wx) * v[k][2] + wx * v[k][3];
+    dst[(size_t)y * stride + x] = (uint8_t)(((256 - wy[k]) * top + wy[k] * bot + 32768) >> 16);
+  }
+}
+
+// Levels of one frame: blockIdx.z is the level.
 __global__ __launch_bounds__(256) void k_pyramid(PyrArgs a) {
   __shared__ uint32_t xt[64], yt[16];
   const PyrLevel L = a.lv[blockIdx.z];
   const int bx = blockIdx.x * 64, by = blockIdx.y * 16;
   if (bx >= L.w || by >= L.h) return;
-  const int t = threadIdx.x;
-  if (t < 64 && bx + t < L.w) xt[t] = resample_tap(bx + t, a.src_w, L.w);
-  if (t >= 64 && t < 80 && by + t - 64 < L.h) yt[t - 64] = resample_tap(by + t - 64, a.src_h, L.h);
-  __syncthreads();
-  const int lx = t & 63;
-  const int x = bx + lx;
-  if (x >= L.w) return;
-  gptr<const uint8_t> src = G(a.src);
-  const uint32_t tx = xt[lx];
-  const int x0 = tx >> 9, wx = tx & 511;
-  const int x1 = min(x0 + 1, a.src_w - 1);
-  int v[4][4];
-  int wy[4];
-#pragma unroll
-  for (int k = 0; k < 4; ++k) {
-    const int ly = min((t >> 6) * 4 + k, L.h - 1 - by);
-    const uint32_t ty = yt[ly];
-    const int y0 = ty >> 9;
-    wy[k] = ty & 511;
-    const int y1 = min(y0 + 1, a.src_h - 1);
-    v[k][0] = src[(size_t)y0 * a.src_stride + x0];
-    v[k][1] = src[(size_t)y0 * a.src_stride + x1];
-    v[k][2] = src[(size_t)y1 * a.src_stride + x0];
-    v[k][3] = src[(size_t)y1 * a.src_stride + x1];
-  }
-#pragma unroll
-  for (int k = 0; k < 4; ++k) {
-    const int y = by + (t >> 6) * 4 + k;
-    if (y >= L.h) break;
-    const int top = (256 - wx) * v[k][0] + wx * v[k][1];
-    const int bot = (256 - wx) * v[k][2] + wx * v[k][3];
-    G(L.dst)[(size_t)y * L.stride + x] = (uint8_t)(((256 - wy[k]) * top + wy[k] * bot + 32768) >> 16);
-  }
+  resample_block(G(a.src), a.src_w, a.src_h, a.src_stride, G(L.dst), L.w, L.h, L.stride, bx, by,
+                 xt, yt);
+}
+
+// Levels >= 1 of every frame of a batch: blocks are numbered through pyr_base.
+__global__ __launch_bounds__(256) void k_pyramid_batch(KArgs a) {
+  __shared__ uint32_t xt[64], yt[16];
+  __shared__ int32_t s_base[kMaxEntries + 1];
+  load_bases(s_base, a.pyr_base, a.n_entries);
+  const int g = (int)blockIdx.x;
+  const int e = uniform(find_entry(s_base, a.n_entries, g));
+  const int b = g - s_base[e];
+  const LevelPlan P = a.plan[e];
+  const int nbx = (P.W + 63) >> 6;
+  const int by = b / nbx, bx = b - by * nbx;
+  resample_block(G(P.base), P.base_w, P.base_h, P.base_stride, G(P.lvl_w), P.W, P.H,
+                 P.lvl_stride, bx * 64, by * 16, xt, yt);
 }
 
 // ------------------------------------------------------------ segment test --
@@ -556,12 +603,11 @@ __global__ __launch_bounds__(256) void k_pyramid(PyrArgs a) {
 // LDS row pitch at compile time, so every circle and compass offset below is a
 // ds_read immediate.
 template <bool FUSED, int TWW>
-__global__ __launch_bounds__(256) void k_mark(KArgs a) {
+__global__ __launch_bounds__(256, 4) void k_mark(KArgs a) {
   constexpr int TW = 64 * TWW;
   constexpr int PITCH = TW + 8;
   extern __shared__ __align__(16) uint8_t smem[];
   __shared__ int s_next, s_qcnt[4];
-  __shared__ int32_t s_base[kMaxEntries + 1];
   const MarkLds M = mark_lds(a.t);
   uint8_t* pix = smem;
   uint16_t* queue = (uint16_t*)(smem + M.off_queue);
@@ -569,6 +615,7 @@ __global__ __launch_bounds__(256) void k_mark(KArgs a) {
   uint32_t* bmh = (uint32_t*)(smem + M.off_bmh);
   uint32_t* xt = (uint32_t*)(smem + M.off_xt);
   uint32_t* yt = (uint32_t*)(smem + M.off_yt);
+  int32_t* s_base = (int32_t*)(smem + M.bytes);
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nwave = blockDim.x >> 6;
   if (a.entry < 0) load_bases(s_base, a.mark_base, a.n_entries);
   queue_start(a, a.qctr + 0, &s_next);
@@ -576,7 +623,7 @@ __global__ __launch_bounds__(256) void k_mark(KArgs a) {
   for (int iter = 0;; ++iter) {
     const int g = uniform(queue_take(a, iter, &s_next));
     if (g >= a.total) break;
-    __syncthreads();  // every thread has read s_next
+    lds_barrier();  // every thread has read s_next
     const int next = queue_prefetch(a, g, a.qctr + 0);
     const int e = a.entry >= 0 ? a.entry : uniform(find_entry(s_base, a.n_entries, g));
     const int t = a.entry >= 0 ? g : g - s_base[e];
@@ -593,7 +640,7 @@ __global__ __launch_bounds__(256) void k_mark(KArgs a) {
     if (FUSED && P.level > 0) {
       for (int i = threadIdx.x; i < nx; i += blockDim.x) xt[i] = resample_tap(ox + i, P.base_w, W);
       for (int j = threadIdx.x; j < ny; j += blockDim.x) yt[j] = resample_tap(oy + j, P.base_h, H);
-      __syncthreads();
+      lds_barrier();
       // Column taps stay in registers (lane owns columns lane + 64c); each wave takes two
       // consecutive output rows at a time with their base-row pointers in scalar
       // registers, so a tap costs its load and the blend only.
@@ -644,7 +691,7 @@ __global__ __launch_bounds__(256) void k_mark(KArgs a) {
           }
         }
       }
-      __syncthreads();
+      lds_barrier();
       // the tile's own pixels go to the level buffer for the later steps
       const int lx0 = x_t0 - ox;
       const int nwd = (x_t1 - x_t0 + 3) >> 2;
@@ -660,10 +707,10 @@ __global__ __launch_bounds__(256) void k_mark(KArgs a) {
       }
     } else {
       const int limit = P.level == 0 ? W : P.lvl_stride;
-      stage_rows(pix, PITCH, G(P.lvl), P.lvl_stride, limit, ox, ex, oy, ey);
+      stage_rows<8>(pix, PITCH, G(P.lvl), P.lvl_stride, limit, ox, ex, oy, ey);
     }
     for (int i = threadIdx.x; i < 2 * M.th * 2 * TWW; i += blockDim.x) bml[i] = 0u;  // lo, hi
-    __syncthreads();
+    lds_barrier();
 
     // 2. compass pre-test at fast_t_min: a run of 9 holds two cyclically adjacent
     //    compass points (positions 1/5/9/13), so (n|s) & (e|w) per polarity is
@@ -702,7 +749,7 @@ __global__ __launch_bounds__(256) void k_mark(KArgs a) {
       }
       if (lane == 0) s_qcnt[wave] = qn;
     }
-    __syncthreads();
+    lds_barrier();
 
     // 3. full segment test of the queued pixels at both thresholds
     int qoff[4];
@@ -750,7 +797,7 @@ __global__ __launch_bounds__(256) void k_mark(KArgs a) {
         }
       }
     }
-    __syncthreads();
+    lds_barrier();
 
     // 4. bitmap words of the tile rows (zero outside the valid region)
     const int w0 = x_t0 >> 5;
@@ -772,37 +819,58 @@ __global__ __launch_bounds__(256) void k_mark(KArgs a) {
 
 // ------------------------------------------------------- Harris / NMS / cells --
 
-__global__ __launch_bounds__(256) void k_detect(KArgs a) {
+// Bits [a, b) of a 32-bit word, 0 <= a <= b <= 32.
+__device__ __forceinline__ uint32_t bit_range(int a, int b) {
+  const uint32_t hi = b >= 32 ? 0xffffffffu : ((1u << b) - 1u);
+  return a >= 32 ? 0u : hi & ~((1u << a) - 1u);
+}
+
+// Candidate word: pixels x0 .. x0+31 of row y that are corners at the threshold of
+// their own cell (hi: fast_t; lo: fast_t_min, used where the cell has no fast_t
+// corner), restricted to the columns [xa, xb).
+__device__ __forceinline__ uint32_t candidate_word(uint32_t lo, uint32_t hi, int x0, int xa,
+                                                   int xb, const uint8_t* frow, int cs) {
+  const int a = max(x0, xa), b = min(x0 + 32, xb);
+  if (a >= b) return 0u;
+  uint32_t fm = 0;  // pixels whose cell holds a fast_t corner
+  for (int c = a / cs; c * cs < b; ++c)
+    if (frow[c]) fm |= bit_range(max(c * cs, a) - x0, min(c * cs + cs, b) - x0);
+  return (hi | (lo & ~fm)) & bit_range(a - x0, b - x0);
+}
+
+// One block per Harris/NMS tile (whole cells, or det_w x det_h pixels when the level is
+// one cell).  Candidates of the tile and a 1-pixel ring are found word-parallel from
+// the segment-test bitmaps, scored with Harris from LDS, suppressed against their
+// candidate neighbours, and the per-cell best are written to the cells' fixed slots.
+__global__ __launch_bounds__(256, 4) void k_detect(KArgs a) {
   extern __shared__ __align__(16) uint8_t smem[];
-  __shared__ int s_next, s_ns, s_ne, s_base_out;
+  __shared__ int s_next, s_ns, s_ne;
   __shared__ uint32_t s_wsum[16];
-  __shared__ int32_t s_base[kMaxEntries + 1];
   const DetLds D = det_lds(a.t, a.cell);
   uint8_t* pix = smem;
-  uint64_t* cw = (uint64_t*)(smem + D.off_cw);
+  uint32_t* cw = (uint32_t*)(smem + D.off_cw);
   uint32_t* ucnt = (uint32_t*)(smem + D.off_ucnt);
   uint32_t* cpre = (uint32_t*)(smem + D.off_cpre);
   int64_t* crs = (int64_t*)(smem + D.off_crs);
   uint32_t* cpos = (uint32_t*)(smem + D.off_cpos);
-  int64_t* srs = (int64_t*)(smem + D.off_srs);
-  uint32_t* spos = (uint32_t*)(smem + D.off_spos);
+  uint16_t* sci = (uint16_t*)(smem + D.off_sci);
   uint16_t* scell = (uint16_t*)(smem + D.off_scell);
-  uint16_t* order = (uint16_t*)(smem + D.off_order);
-  uint16_t* emit = (uint16_t*)(smem + D.off_emit);
+  uint16_t* order = (uint16_t*)(smem + D.off_order);  // cells: grouped survivors; else block flags
   uint32_t* ccnt = (uint32_t*)(smem + D.off_ccnt);
   uint32_t* coff = (uint32_t*)(smem + D.off_coff);
   uint32_t* cfill = (uint32_t*)(smem + D.off_cfill);
-  uint32_t* wlo = (uint32_t*)(smem + D.off_wlo);
-  uint32_t* whi = (uint32_t*)(smem + D.off_whi);
+  uint32_t* ckept = (uint32_t*)(smem + D.off_ckept);
   uint8_t* lfl = smem + D.off_lfl;
+  int32_t* s_base = (int32_t*)(smem + D.bytes);
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nwave = blockDim.x >> 6;
+  const int bd = (int)blockDim.x, tid = (int)threadIdx.x;
   if (a.entry < 0) load_bases(s_base, a.det_base, a.n_entries);
   queue_start(a, a.qctr + 2, &s_next);
 
   for (int iter = 0;; ++iter) {
     const int g = uniform(queue_take(a, iter, &s_next));
     if (g >= a.total) break;
-    __syncthreads();  // every thread has read s_next
+    lds_barrier();  // every thread has read s_next
     const int next = queue_prefetch(a, g, a.qctr + 2);
     const int e = a.entry >= 0 ? a.entry : uniform(find_entry(s_base, a.n_entries, g));
     const int t = a.entry >= 0 ? g : g - s_base[e];
@@ -826,30 +894,37 @@ __global__ __launch_bounds__(256) void k_detect(KArgs a) {
       vy0 = P.det_y0 + ty * a.t.det_h;
       vy1 = min(vy0 + a.t.det_h, P.det_yend);
     }
+    // tile + 1-pixel ring (candidates), + 5-pixel halo (staged pixels)
     const int rx0 = vx0 - 1, ry0 = vy0 - 1;
     const int rw = vx1 - vx0 + 2, rh = vy1 - vy0 + 2;
     const int sx0 = max(0, vx0 - 5) & ~3, sy0 = max(0, vy0 - 5);
     const int sx1 = min(W, vx1 + 5), sy1 = min(H, vy1 + 5);
-    const int nwr = (rw + 63) >> 6;
-    const int nunits = rh * nwr;
-    // bitmap words and cells touched by the tile and its 1-pixel ring
+    // candidate words: the 32-bit bitmap words that hold ring columns, per ring row
     const int bw0 = rx0 >> 5, nbw = ((rx0 + rw - 1) >> 5) - bw0 + 1;
+    const int nunits = rh * nbw;
     const int fcx0 = rx0 / cs, fcy0 = ry0 / cs;
     const int nfx = (rx0 + rw - 1) / cs - fcx0 + 1, nfy = (ry0 + rh - 1) / cs - fcy0 + 1;
+    const int ncell = nlcx * nlcy;
+    const int nvx = P.det_xend - P.det_x0;
+    const int nbx = (vx1 - vx0 + 1) >> 1, nby = (vy1 - vy0 + 1) >> 1;  // 2x2 blocks
 
-    // 1. one batch of independent loads: bitmap words, flags, pixels (5-pixel halo)
+    // 1. one batch of independent loads: the thread's bitmap words (kept in registers),
+    //    cell flags and pixels
+    gptr<const uint32_t> glo = G((const uint32_t*)P.bm_lo), ghi = G((const uint32_t*)P.bm_hi);
+    uint32_t vlo[2], vhi[2];
+    int vr[2], vk[2];
     {
-      gptr<const uint32_t> glo = G((const uint32_t*)P.bm_lo), ghi = G((const uint32_t*)P.bm_hi);
       gptr<const uint8_t> gfl = G((const uint8_t*)P.flags);
-      const int nbm = rh * nbw, nfl = nfx * nfy;
-      uint32_t vlo[2], vhi[2], vfl[2];
+      const int nfl = nfx * nfy;
+      uint32_t vfl[2];
 #pragma unroll
       for (int u = 0; u < 2; ++u) {
-        const int i = u * (int)blockDim.x + (int)threadIdx.x;
+        const int i = u * bd + tid;
         vlo[u] = vhi[u] = vfl[u] = 0;
-        if (i < nbm) {
-          const int r = i / nbw, k = i - r * nbw;
-          const size_t gi = (size_t)(ry0 + r) * P.wpr + bw0 + k;
+        vr[u] = i / nbw;
+        vk[u] = i - vr[u] * nbw;
+        if (i < nunits) {
+          const size_t gi = (size_t)(ry0 + vr[u]) * P.wpr + bw0 + vk[u];
           vlo[u] = glo[gi];
           vhi[u] = ghi[gi];
         }
@@ -858,191 +933,213 @@ __global__ __launch_bounds__(256) void k_detect(KArgs a) {
           vfl[u] = gfl[(fcy0 + r) * P.ncx + fcx0 + k];
         }
       }
-      stage_rows(pix, D.pitch, G(P.lvl), P.lvl_stride, P.level == 0 ? W : P.lvl_stride, sx0,
-                 sx1, sy0, sy1);
+      stage_rows<10>(pix, D.pitch, G(P.lvl), P.lvl_stride, P.level == 0 ? W : P.lvl_stride, sx0,
+                     sx1, sy0, sy1);
 #pragma unroll
       for (int u = 0; u < 2; ++u) {
-        const int i = u * (int)blockDim.x + (int)threadIdx.x;
-        if (i < nbm) {
-          wlo[i] = vlo[u];
-          whi[i] = vhi[u];
-        }
+        const int i = u * bd + tid;
         if (i < nfl) lfl[i] = (uint8_t)vfl[u];
       }
-      for (int i = 2 * (int)blockDim.x + (int)threadIdx.x; i < nbm; i += blockDim.x) {
-        const int r = i / nbw, k = i - r * nbw;
-        const size_t gi = (size_t)(ry0 + r) * P.wpr + bw0 + k;
-        wlo[i] = glo[gi];
-        whi[i] = ghi[gi];
-      }
-      for (int i = 2 * (int)blockDim.x + (int)threadIdx.x; i < nfl; i += blockDim.x) {
+      for (int i = 2 * bd + tid; i < nfl; i += bd) {
         const int r = i / nfx, k = i - r * nfx;
         lfl[i] = gfl[(fcy0 + r) * P.ncx + fcx0 + k];
       }
     }
-    if (threadIdx.x == 0) {
+    if (tid == 0) {
       s_ns = 0;
       s_ne = 0;
     }
-    __syncthreads();
-    // 2. candidate words over tile + ring: corner at the threshold of its own cell.
-    //    Cell columns of a lane's pixels are fixed for the tile (nwr <= 5 words), cell
-    //    rows advance with the row, so no division runs per pixel.
-    {
-      int lcx[5];
-      bool xok[5];
-#pragma unroll
-      for (int k = 0; k < 5; ++k) {
-        const int lxr = 64 * k + lane;
-        const int x = rx0 + lxr;
-        xok[k] = k < nwr && lxr < rw && x >= B && x < W - B;
-        lcx[k] = xok[k] ? x / cs - fcx0 : 0;
+    if (a.cell > 0) {
+      for (int c = tid; c < ncell; c += bd) {
+        ccnt[c] = 0;
+        cfill[c] = 0;
+        ckept[c] = 0;
       }
-      for (int j = wave; j < rh; j += nwave) {
-        const int y = ry0 + j;
-        const bool yok = y >= B && y < H - B;
-        const uint8_t* frow = lfl + (y / cs - fcy0) * nfx;
-        const uint32_t* rlo = wlo + j * nbw - bw0;
-        const uint32_t* rhi = whi + j * nbw - bw0;
+    } else {
+      for (int i = tid; i < nbx * nby; i += bd) order[i] = 0;
+    }
+    lds_barrier();
+
+    // 2. candidate words, 32 pixels per thread and step, and their counts
+    const int xa = max(rx0, B), xb = min(rx0 + rw, W - B);
+    uint32_t cwr[2];
 #pragma unroll
-        for (int k = 0; k < 5; ++k) {
-          if (k >= nwr) break;
-          const int x = rx0 + 64 * k + lane;
-          bool c = false;
-          if (yok && xok[k]) {
-            const uint32_t bit = 1u << (x & 31);
-            c = (rhi[x >> 5] & bit) != 0 || ((rlo[x >> 5] & bit) != 0 && frow[lcx[k]] == 0);
-          }
-          const uint64_t m = __ballot(c);
-          if (lane == 0) {
-            cw[j * nwr + k] = m;
-            ucnt[j * nwr + k] = (uint32_t)__popcll(m);
-          }
-        }
+    for (int u = 0; u < 2; ++u) {
+      const int i = u * bd + tid;
+      cwr[u] = 0;
+      if (i < nunits) {
+        const int y = ry0 + vr[u];
+        if (y >= B && y < H - B)
+          cwr[u] = candidate_word(vlo[u], vhi[u], (bw0 + vk[u]) << 5, xa, xb,
+                                  lfl + (y / cs - fcy0) * nfx - fcx0, cs);
+        cw[i] = cwr[u];
+        ucnt[i] = (uint32_t)__popc(cwr[u]);
       }
     }
-    __syncthreads();
+    for (int i = 2 * bd + tid; i < nunits; i += bd) {
+      const int r = i / nbw, k = i - r * nbw;
+      const int y = ry0 + r;
+      uint32_t c = 0;
+      if (y >= B && y < H - B) {
+        const size_t gi = (size_t)y * P.wpr + bw0 + k;
+        c = candidate_word(glo[gi], ghi[gi], (bw0 + k) << 5, xa, xb,
+                           lfl + (y / cs - fcy0) * nfx - fcx0, cs);
+      }
+      cw[i] = c;
+      ucnt[i] = (uint32_t)__popc(c);
+    }
+    lds_barrier();
     block_scan_u32(ucnt, cpre, nunits, s_wsum);
     const int ncand = (int)cpre[nunits];
+
     // 3. cached candidate positions (raster order) and their Harris scores
-    for (int j = wave; j < rh; j += nwave) {
-      for (int k = 0; k < nwr; ++k) {
-        const int u = j * nwr + k;
-        const uint64_t m = cw[u];
-        if ((m >> lane) & 1ull) {
-          const uint32_t idx = cpre[u] + lanes_below(m);
-          if (idx < (uint32_t)kCandCache)
-            cpos[idx] = ((uint32_t)(ry0 + j) << 16) | (uint32_t)(rx0 + 64 * k + lane);
-        }
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+      const int i = u * bd + tid;
+      uint32_t m = cwr[u];
+      if (i < nunits && m) {
+        uint32_t idx = cpre[i];
+        const uint32_t yx = ((uint32_t)(ry0 + vr[u]) << 16) | (uint32_t)((bw0 + vk[u]) << 5);
+        for (; m && idx < (uint32_t)kCandCache; m &= m - 1u) cpos[idx++] = yx + __builtin_ctz(m);
       }
     }
-    __syncthreads();
+    for (int i = 2 * bd + tid; i < nunits; i += bd) {
+      uint32_t m = cw[i];
+      uint32_t idx = cpre[i];
+      const int r = i / nbw, k = i - r * nbw;
+      const uint32_t yx = ((uint32_t)(ry0 + r) << 16) | (uint32_t)((bw0 + k) << 5);
+      for (; m && idx < (uint32_t)kCandCache; m &= m - 1u) cpos[idx++] = yx + __builtin_ctz(m);
+    }
+    lds_barrier();
     const int ncache = min(ncand, kCandCache);
     harris_groups(pix, D.pitch, cpos, crs, ncache, sx0, sy0);
-    __syncthreads();
-    // 4. NMS: a tile candidate survives when it ranks above every candidate neighbour.
-    //    One thread per candidate; neighbours are found through the candidate words.
-    for (int ci = threadIdx.x; ci < ncand; ci += blockDim.x) {
-      uint32_t pos;
-      if (ci < kCandCache) {
-        pos = cpos[ci];
-      } else {  // beyond the cache: locate the ci-th candidate in raster order
-        int lo = 0, hi = nunits - 1;
-        while (lo < hi) {
-          const int mid = (lo + hi + 1) >> 1;
-          if (cpre[mid] <= (uint32_t)ci) lo = mid; else hi = mid - 1;
-        }
-        uint64_t m = cw[lo];
-        for (uint32_t k = cpre[lo]; k < (uint32_t)ci; ++k) m &= m - 1ull;
-        const int j = lo / nwr, k = lo - j * nwr;
-        pos = ((uint32_t)(ry0 + j) << 16) | (uint32_t)(rx0 + 64 * k + __builtin_ctzll(m));
+    lds_barrier();
+
+    // Position and R' of candidate ci (raster order); beyond the cache the position is
+    // found from the word prefix counts and R' is recomputed from the staged pixels.
+    auto cand_pos = [&](int ci) -> uint32_t {
+      if (ci < kCandCache) return cpos[ci];
+      int lo = 0, hi = nunits - 1;
+      while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (cpre[mid] <= (uint32_t)ci) lo = mid; else hi = mid - 1;
       }
+      uint32_t m = cw[lo];
+      for (uint32_t k = cpre[lo]; k < (uint32_t)ci; ++k) m &= m - 1u;
+      const int r = lo / nbw, k = lo - r * nbw;
+      return ((uint32_t)(ry0 + r) << 16) | (uint32_t)(((bw0 + k) << 5) + __builtin_ctz(m));
+    };
+    auto cand_score = [&](int ci, uint32_t pos) -> int64_t {
+      return ci < kCandCache ? crs[ci]
+                             : harris_lds_uncached(pix, D.pitch, (int)(pos & 0xffff) - sx0,
+                                                   (int)(pos >> 16) - sy0);
+    };
+
+    // 4. NMS: a tile candidate survives when it ranks above every candidate neighbour.
+    for (int ci = tid; ci < ncand; ci += bd) {
+      const uint32_t pos = cand_pos(ci);
       const int x = (int)(pos & 0xffff), y = (int)(pos >> 16);
-      const int lxr = x - rx0, j = y - ry0;
-      if (j == 0 || j == rh - 1 || lxr == 0 || lxr >= rw - 1) continue;  // ring only
-      const int64_t R = ci < kCandCache ? crs[ci]
-                                        : harris_lds_uncached(pix, D.pitch, x - sx0, y - sy0);
+      if (x < vx0 || x >= vx1 || y < vy0 || y >= vy1) continue;  // ring only
+      const int64_t R = cand_score(ci, pos);
       bool alive = true;
 #pragma unroll
       for (int nb = 0; nb < 8; ++nb) {
         const int dx = nb < 3 ? nb - 1 : (nb < 5 ? (nb == 3 ? -1 : 1) : nb - 6);
         const int dy = nb < 3 ? -1 : (nb < 5 ? 0 : 1);
-        const int ql = lxr + dx;
-        const int qu = (j + dy) * nwr + (ql >> 6);
-        const uint64_t qm = cw[qu];
-        const int qb = ql & 63;
-        if ((qm >> qb) & 1ull) {
-          const uint32_t qidx = cpre[qu] + (uint32_t)__popcll(qm & ((1ull << qb) - 1ull));
-          const int qx = x + dx, qy = y + dy;
-          const int64_t Rq = qidx < (uint32_t)kCandCache
-                                 ? crs[qidx]
-                                 : harris_lds_uncached(pix, D.pitch, qx - sx0, qy - sy0);
-          alive = alive && better(R, pos, Rq, ((uint32_t)qy << 16) | (uint32_t)qx);
+        const int qx = x + dx, qy = y + dy;
+        const int qu = (qy - ry0) * nbw + (qx >> 5) - bw0;
+        const uint32_t qm = cw[qu];
+        const int qb = qx & 31;
+        if ((qm >> qb) & 1u) {
+          const int qi = (int)(cpre[qu] + (uint32_t)__popc(qm & ((1u << qb) - 1u)));
+          const uint32_t qpos = ((uint32_t)qy << 16) | (uint32_t)qx;
+          alive = alive && better(R, pos, cand_score(qi, qpos), qpos);
         }
       }
       if (alive) {
         const int si = atomicAdd(&s_ns, 1);
-        srs[si] = R;
-        spos[si] = pos;
+        sci[si] = (uint16_t)ci;
         scell[si] = a.cell > 0 ? (uint16_t)((y / cs - cya) * nlcx + (x / cs - cxa)) : 0;
       }
     }
-    __syncthreads();
+    lds_barrier();
     const int ns = s_ns;
-    // 5. per-cell top-K (K = quota when the whole level is one cell)
+    // 5. per-cell top-K (K = quota when the whole level is one cell), written to fixed
+    //    slots: K' = min(K, survivors a cell can hold) per cell, or one per 2x2 block
+    //    when there are no cells.  Slots left empty get the sentinel.
+    const int K = P.kcell;
+    gptr<Cand> out = G(P.cand);
     if (ns > 0) {
-      const int K = P.kcell;
-      const int ncell = nlcx * nlcy;
-      for (int c = threadIdx.x; c < ncell; c += blockDim.x) {
-        ccnt[c] = 0;
-        cfill[c] = 0;
-      }
-      __syncthreads();
-      for (int s = threadIdx.x; s < ns; s += blockDim.x) atomicAdd(&ccnt[scell[s]], 1u);
-      __syncthreads();
-      if (threadIdx.x == 0) {
-        uint32_t o = 0;
-        for (int c = 0; c < ncell; ++c) {
-          coff[c] = o;
-          o += ccnt[c];
+      if (a.cell > 0) {
+        for (int s2 = tid; s2 < ns; s2 += bd) atomicAdd(&ccnt[scell[s2]], 1u);
+        lds_barrier();
+        if (tid == 0) {
+          uint32_t o = 0;
+          for (int c = 0; c < ncell; ++c) {
+            coff[c] = o;
+            o += ccnt[c];
+          }
         }
+        lds_barrier();
+        for (int s2 = tid; s2 < ns; s2 += bd) {
+          const int c = scell[s2];
+          order[coff[c] + atomicAdd(&cfill[c], 1u)] = (uint16_t)s2;
+        }
+        lds_barrier();
       }
-      __syncthreads();
-      for (int s = threadIdx.x; s < ns; s += blockDim.x) {
+      for (int s = tid; s < ns; s += bd) {
+        const int ci = sci[s];
+        const uint32_t pos = cand_pos(ci);
+        const int64_t R = cand_score(ci, pos);
         const int c = scell[s];
-        order[coff[c] + atomicAdd(&cfill[c], 1u)] = (uint16_t)s;
-      }
-      __syncthreads();
-      for (int s = threadIdx.x; s < ns; s += blockDim.x) {
-        const int c = scell[s];
-        const uint32_t n = ccnt[c];
+        const int n = a.cell > 0 ? (int)ccnt[c] : ns;
         bool keep = true;
-        if ((int)n > K) {
-          const int64_t R = srs[s];
-          const uint32_t pos = spos[s];
+        if (n > K) {
           int rank = 0;
-          const uint32_t o = coff[c];
-          for (uint32_t q = 0; q < n && rank < K; ++q) {
-            const int s2 = order[o + q];
-            rank += better(srs[s2], spos[s2], R, pos) ? 1 : 0;
+          const int o = a.cell > 0 ? (int)coff[c] : 0;
+          for (int q = 0; q < n && rank < K; ++q) {
+            const int s2 = a.cell > 0 ? order[o + q] : q;
+            const int ci2 = sci[s2];
+            const uint32_t pos2 = cand_pos(ci2);
+            rank += better(cand_score(ci2, pos2), pos2, R, pos) ? 1 : 0;
           }
           keep = rank < K;
         }
-        if (keep) emit[atomicAdd(&s_ne, 1)] = (uint16_t)s;
-      }
-      __syncthreads();
-      const int ne = s_ne;
-      if (threadIdx.x == 0) s_base_out = (int)atomicAdd(P.cand_count, (uint32_t)ne);
-      __syncthreads();
-      const int base = s_base_out;
-      gptr<Cand> out = G(P.cand);
-      for (int i = threadIdx.x; i < ne; i += blockDim.x) {
-        if (base + i < P.cand_cap) {
-          const int s = emit[i];
-          store_cand(out + base + i, srs[s], spos[s]);
+        if (keep) {
+          const int x = (int)(pos & 0xffff), y = (int)(pos >> 16);
+          int slot;
+          if (a.cell > 0) {
+            const int r = (int)atomicAdd(&ckept[c], 1u);
+            slot = ((y / cs - P.det_y0) * nvx + (x / cs - P.det_x0)) * P.kslot + r;
+          } else {
+            slot = ((y - B) >> 1) * P.slot_w + ((x - B) >> 1);
+            order[((y - vy0) >> 1) * nbx + ((x - vx0) >> 1)] = 1;
+          }
+          store_cand(out + slot, R, pos);
+          atomicAdd(&s_ne, 1);
         }
       }
     }
+    lds_barrier();
+    if (a.cell > 0) {
+      const int ks = P.kslot;
+      for (int i = tid; i < ncell * ks; i += bd) {
+        const int c = ks == 1 ? i : i / ks;
+        const int r = i - c * ks;
+        if (r >= (int)ckept[c]) {
+          const int lcy = c / nlcx, lcx = c - lcy * nlcx;
+          const int slot = ((cya + lcy - P.det_y0) * nvx + (cxa + lcx - P.det_x0)) * ks + r;
+          store_cand(out + slot, INT64_MIN, kNoPos);
+        }
+      }
+    } else {
+      const int srow = (vy0 - B) >> 1, scol = (vx0 - B) >> 1;
+      for (int by = wave; by < nby; by += nwave)
+        for (int bx = lane; bx < nbx; bx += 64)
+          if (!order[by * nbx + bx])
+            store_cand(out + (size_t)(srow + by) * P.slot_w + scol + bx, INT64_MIN, kNoPos);
+    }
+    if (tid == 0 && s_ne > 0) atomicAdd(P.cand_count, (uint32_t)s_ne);
     queue_park(a, next, &s_next);
   }
 }
@@ -1064,18 +1161,17 @@ __global__ __launch_bounds__(256) void k_select_orient(KArgs a) {
   const int i = slot - s_base[e];
   const LevelPlan P = a.plan[e];
   gptr<const uint32_t> counts = G((const uint32_t*)P.cand_count) - e;  // all entries
-  const int C = min((int)counts[e], P.cand_cap);
+  const int C = P.cand_cap;  // slots; empty ones hold the sentinel
   if (P.level == 0 && i == 0 && lane == 0) {
     int total = 0;
-    for (int l = 0; l < P.n_levels; ++l) {
-      const LevelPlan& Q = a.plan[P.entry0 + l];
-      total += min(min((int)counts[P.entry0 + l], Q.cand_cap), Q.quota);
-    }
+    for (int l = 0; l < P.n_levels; ++l)
+      total += min((int)counts[P.entry0 + l], a.plan[P.entry0 + l].quota);
     *G(P.count_out) = total;
   }
   if (i >= C || C > kRankCap) return;
   gptr<const Cand> cand = G((const Cand*)P.cand);
   const Cand me = load_cand(cand + i);
+  if (me.pos == kNoPos) return;
   // Count better candidates, 8 loads in flight per lane; a wave whose partial count
   // already reaches the quota cannot be selected and stops early.
   int cnt = 0;
@@ -1093,10 +1189,8 @@ __global__ __launch_bounds__(256) void k_select_orient(KArgs a) {
   const int rank = wave_sum(cnt);
   if (rank >= P.quota) return;
   int prefix = 0;
-  for (int l = 0; l < P.level; ++l) {
-    const LevelPlan& Q = a.plan[P.entry0 + l];
-    prefix += min(min((int)counts[P.entry0 + l], Q.cand_cap), Q.quota);
-  }
+  for (int l = 0; l < P.level; ++l)
+    prefix += min((int)counts[P.entry0 + l], a.plan[P.entry0 + l].quota);
   const int x = (int)(me.pos & 0xffff), y = (int)(me.pos >> 16);
   int m10, m01;
   wave_moments(G(P.lvl), P.lvl_stride, x, y, P.B, lane, &m10, &m01);
@@ -1146,22 +1240,31 @@ __global__ __launch_bounds__(1024) void k_select(KArgs a) {
   const int e = a.entry >= 0 ? a.entry : (int)blockIdx.x;
   const LevelPlan P = a.plan[e];
   const int N = P.quota;
-  const int C = min((int)*G(P.cand_count), P.cand_cap);
+  const int C = P.cand_cap;  // slots; empty ones hold the sentinel and are skipped
   if (a.rank_path && C <= kRankCap) return;  // handled by k_select_orient
-  const int nout = min(C, N);
-  if (N <= 0 || C <= 0) {
+  const int nfill = (int)*G(P.cand_count);
+  const int nout = min(nfill, N);
+  if (nout <= 0) {
     if (threadIdx.x == 0) *G(P.sel_count) = 0;
     return;
   }
   gptr<const Cand> cand = G((const Cand*)P.cand);
   int nsort;
-  if (C <= kSortCap) {
-    nsort = C;
+  if (nfill <= kSortCap) {  // every filled slot fits: gather them all
+    if (threadIdx.x == 0) s_n = 0;
+    __syncthreads();
     for (int i = threadIdx.x; i < C; i += blockDim.x) {
       const Cand cd = load_cand(cand + i);
-      sc[i] = cd.score;
-      ps[i] = cd.pos;
+      if (cd.pos != kNoPos) {
+        const uint32_t slot = atomicAdd(&s_n, 1u);
+        if (slot < (uint32_t)kSortCap) {
+          sc[slot] = cd.score;
+          ps[slot] = cd.pos;
+        }
+      }
     }
+    __syncthreads();
+    nsort = min((int)s_n, kSortCap);
   } else {
     if (threadIdx.x == 0) {
       s_prefix = 0;
@@ -1173,8 +1276,9 @@ __global__ __launch_bounds__(1024) void k_select(KArgs a) {
       __syncthreads();
       const uint64_t prefix = s_prefix;
       for (int i = threadIdx.x; i < C; i += blockDim.x) {
-        const uint64_t u = score_key(load_cand(cand + i).score);
-        if ((u & mask) == prefix) atomicAdd(&hist[(u >> shift) & 255u], 1u);
+        const Cand cd = load_cand(cand + i);
+        const uint64_t u = score_key(cd.score);
+        if (cd.pos != kNoPos && (u & mask) == prefix) atomicAdd(&hist[(u >> shift) & 255u], 1u);
       }
       __syncthreads();
       if (threadIdx.x == 0) {
@@ -1197,8 +1301,10 @@ __global__ __launch_bounds__(1024) void k_select(KArgs a) {
     const uint32_t k_eq = s_k;
     if (threadIdx.x == 0) s_eq = 0;
     __syncthreads();
-    for (int i = threadIdx.x; i < C; i += blockDim.x)
-      if (score_key(load_cand(cand + i).score) == T) atomicAdd(&s_eq, 1u);
+    for (int i = threadIdx.x; i < C; i += blockDim.x) {
+      const Cand cd = load_cand(cand + i);
+      if (cd.pos != kNoPos && score_key(cd.score) == T) atomicAdd(&s_eq, 1u);
+    }
     __syncthreads();
     uint32_t pcut = 0xffffffffu;
     if (s_eq > k_eq) {
@@ -1213,7 +1319,7 @@ __global__ __launch_bounds__(1024) void k_select(KArgs a) {
         const uint32_t pp = (uint32_t)s_prefix;
         for (int i = threadIdx.x; i < C; i += blockDim.x) {
           const Cand cd = load_cand(cand + i);
-          if (score_key(cd.score) == T && (cd.pos & pmask) == pp)
+          if (cd.pos != kNoPos && score_key(cd.score) == T && (cd.pos & pmask) == pp)
             atomicAdd(&hist[(cd.pos >> shift) & 255u], 1u);
         }
         __syncthreads();
@@ -1240,7 +1346,7 @@ __global__ __launch_bounds__(1024) void k_select(KArgs a) {
     for (int i = threadIdx.x; i < C; i += blockDim.x) {
       const Cand cd = load_cand(cand + i);
       const uint64_t u = score_key(cd.score);
-      if (u > T || (u == T && cd.pos <= pcut)) {
+      if (cd.pos != kNoPos && (u > T || (u == T && cd.pos <= pcut))) {
         const uint32_t slot = atomicAdd(&s_n, 1u);
         if (slot < (uint32_t)kSortCap) {
           sc[slot] = cd.score;
@@ -1271,21 +1377,16 @@ __global__ __launch_bounds__(256) void k_orient(KArgs a) {
   const int chunk = a.entry >= 0 ? b : b - a.orient_base[e];
   const LevelPlan P = a.plan[e];
   gptr<const uint32_t> counts = G((const uint32_t*)P.cand_count) - e;
-  const int C = min((int)counts[e], P.cand_cap);
-  if (a.rank_path && C <= kRankCap) return;  // written by k_select_orient
+  if (a.rank_path && P.cand_cap <= kRankCap) return;  // written by k_select_orient
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int nsel = (int)*G(P.sel_count);
   int prefix = 0;
-  for (int l = 0; l < P.level; ++l) {
-    const LevelPlan& Q = a.plan[P.entry0 + l];
-    prefix += min(min((int)counts[P.entry0 + l], Q.cand_cap), Q.quota);
-  }
+  for (int l = 0; l < P.level; ++l)
+    prefix += min((int)counts[P.entry0 + l], a.plan[P.entry0 + l].quota);
   if (!a.rank_path && P.level == 0 && chunk == 0 && threadIdx.x == 0) {
     int total = 0;
-    for (int l = 0; l < P.n_levels; ++l) {
-      const LevelPlan& Q = a.plan[P.entry0 + l];
-      total += min(min((int)counts[P.entry0 + l], Q.cand_cap), Q.quota);
-    }
+    for (int l = 0; l < P.n_levels; ++l)
+      total += min((int)counts[P.entry0 + l], a.plan[P.entry0 + l].quota);
     *G(P.count_out) = total;
   }
   gptr<const Cand> sel = G((const Cand*)P.sel);
@@ -1327,6 +1428,11 @@ hipError_t launch_pyramid(const PyrArgs& a, int n_levels, int max_w, int max_h, 
   return hipGetLastError();
 }
 
+hipError_t launch_pyramid_batch(const KArgs& a, int blocks, hipStream_t s) {
+  hipLaunchKernelGGL(k_pyramid_batch, dim3(blocks), dim3(256), 0, s, a);
+  return hipGetLastError();
+}
+
 template <int TWW>
 void launch_mark_w(const KArgs& a, bool fused, int grid, int bytes, hipStream_t s) {
   if (fused)
@@ -1336,19 +1442,19 @@ void launch_mark_w(const KArgs& a, bool fused, int grid, int bytes, hipStream_t 
 }
 
 hipError_t launch_mark(const KArgs& a, bool fused, int grid, hipStream_t s) {
-  const MarkLds M = mark_lds(a.t);
+  const int bytes = mark_lds(a.t).bytes + base_table_bytes(a.n_entries);
   switch (a.t.mark_words) {
-    case 1: launch_mark_w<1>(a, fused, grid, M.bytes, s); break;
-    case 2: launch_mark_w<2>(a, fused, grid, M.bytes, s); break;
-    case 3: launch_mark_w<3>(a, fused, grid, M.bytes, s); break;
-    default: launch_mark_w<4>(a, fused, grid, M.bytes, s); break;
+    case 1: launch_mark_w<1>(a, fused, grid, bytes, s); break;
+    case 2: launch_mark_w<2>(a, fused, grid, bytes, s); break;
+    case 3: launch_mark_w<3>(a, fused, grid, bytes, s); break;
+    default: launch_mark_w<4>(a, fused, grid, bytes, s); break;
   }
   return hipGetLastError();
 }
 
 hipError_t launch_detect(const KArgs& a, int grid, hipStream_t s) {
-  const DetLds D = det_lds(a.t, a.cell);
-  hipLaunchKernelGGL(k_detect, dim3(grid), dim3(256), D.bytes, s, a);
+  const int bytes = det_lds(a.t, a.cell).bytes + base_table_bytes(a.n_entries);
+  hipLaunchKernelGGL(k_detect, dim3(grid), dim3(256), bytes, s, a);
   return hipGetLastError();
 }
 

@@ -22,11 +22,13 @@ constexpr int kOrientPerBlock = 16;                  // keypoints per orientatio
 constexpr int kMaxDetW = 256, kMaxDetH = 128;        // Harris/NMS tile limits (pixels)
 constexpr int kCandCache = 1024;                     // Harris scores cached per tile
 constexpr int kRankCap = 16384;                      // levels ranked by counting, not radix
+constexpr uint32_t kNoPos = 0xffffffffu;              // position of an empty candidate slot
 
 struct Tune {
   int32_t mark_words, mark_rows;
   int32_t det_cx, det_cy, det_w, det_h;
   int32_t mark_grid, det_grid;
+  int32_t pyr_pass;  // 1: levels are resampled by a separate pass before the segment test
 };
 
 // One ranked candidate: R' and (y << 16 | x) in level coordinates.
@@ -51,9 +53,10 @@ struct LevelPlan {
   uint32_t* bm_hi;             //   wpr words per row; lo = corner at fast_t_min
   int32_t wpr;
   uint8_t* flags;              // ncx * ncy bytes: 1 = cell holds a fast_t corner
-  Cand* cand;                  // cell winners emitted by the Harris/NMS tiles
-  uint32_t* cand_count;
-  int32_t cand_cap;
+  Cand* cand;                  // candidate slots written by the Harris/NMS tiles
+  uint32_t* cand_count;        // filled slots
+  int32_t cand_cap;            // slots (filled or holding the kNoPos sentinel)
+  int32_t kslot;               // slots per cell (cell > 0)
   Cand* sel;                   // level selection, sorted, quota entries
   uint32_t* sel_count;
   int32_t mark_tx, mark_ty;    // segment-test tile grid (covers the whole level)
@@ -61,6 +64,7 @@ struct LevelPlan {
   int32_t det_x0, det_y0;      // first cell column/row (cell > 0) or first pixel (cell == 0)
   int32_t det_xend, det_yend;  // one past the last cell column/row, or W-B / H-B
   int32_t orient_blocks;       // orientation blocks of this level
+  int32_t slot_w;              // output slots per row of 2x2 blocks (no cells)
   int32_t entry0;              // plan index of this frame's level 0
   of_keypoint* out;            // this frame's output
   int32_t* count_out;
@@ -126,6 +130,9 @@ struct EntrySize {
   int64_t lvl_bytes;
   // tile grids
   int32_t mark_tx, mark_ty, det_tx, det_ty, det_x0, det_y0, det_xend, det_yend, wpr;
+  int32_t slot_w;       // slots per row of 2x2 blocks (no cells)
+  int32_t kslot;        // slots per cell (cells): K_l capped by the survivors a cell holds
+  int32_t pyr_blocks;   // 64 x 16 resample blocks of a level >= 1
 };
 
 OF_HD void entry_size(const FrameGeom& g, const of_params& p, const Tune& t, int l,
@@ -152,26 +159,30 @@ OF_HD void entry_size(const FrameGeom& g, const of_params& p, const Tune& t, int
     s->det_tx = cdiv(W - 2 * B, t.det_w);
     s->det_ty = cdiv(H - 2 * B, t.det_h);
   }
-  // Emitted candidates never outnumber the NMS survivors, which are pairwise
-  // non-adjacent: at most ceil(w/2) ceil(h/2) over the valid region, for any tiling.
-  // With cells, a cell lies inside one tile and emits at most K_l, which bounds it too;
-  // without cells every tile emits up to K_l of its own, so only the survivor bound
-  // holds.  Neither depends on the tuning, so neither does the workspace.
+  // Output slots of the Harris/NMS tiles, fixed for any tiling so that no block needs
+  // a returned atomic to place its results.  With cells: K_l slots per cell of the
+  // valid region, cell-major.  Without cells: one slot per 2x2 block of the valid
+  // region, which can hold at most one NMS survivor (all four pixels are neighbours).
+  // NMS survivors are never neighbours, so a cs x cs cell holds at most ceil(cs/2)^2 of
+  // them and K_l beyond that needs no slots.  Unused slots hold a sentinel that ranks
+  // below every real candidate.
   {
-    const int64_t surv = (int64_t)cdiv(W - 2 * B, 2) * cdiv(H - 2 * B, 2);
-    int64_t cap = surv;
+    s->slot_w = cdiv(W - 2 * B, 2);
+    const int64_t hc = cdiv(cs, 2);
+    s->kslot = (int32_t)(g.kcell[l] < hc * hc ? g.kcell[l] : hc * hc);
     if (p.cell > 0) {
-      const int64_t nvx = (W - 1 - B) / cs - B / cs + 1, nvy = (H - 1 - B) / cs - B / cs + 1;
-      const int64_t cells = nvx * nvy * g.kcell[l];
-      cap = surv < cells ? surv : cells;
+      const int64_t nvx = s->det_xend - s->det_x0, nvy = s->det_yend - s->det_y0;
+      s->cand_cap = nvx * nvy * s->kslot;
+    } else {
+      s->cand_cap = (int64_t)s->slot_w * cdiv(H - 2 * B, 2);
     }
-    s->cand_cap = cap;
   }
   s->det_tiles = s->det_tx * s->det_ty;
   s->sel_cap = g.quota[l];
   int32_t ob = cdiv(g.quota[l], kOrientPerBlock);
   s->orient_blocks = ob < 1 ? 1 : ob;
   s->lvl_bytes = l == 0 ? 0 : align_up((int64_t)level_stride(W) * H, 256);
+  s->pyr_blocks = l == 0 ? 0 : cdiv(W, 64) * cdiv(H, 16);
 }
 
 // ------------------------------------------------------------ workspace layout --
@@ -179,8 +190,9 @@ OF_HD void entry_size(const FrameGeom& g, const of_params& p, const Tune& t, int
 // Region sizes of a whole call; offsets are from the workspace base (256-aligned).
 struct WsLayout {
   int64_t off_hdr, off_plan, off_mark_base, off_det_base, off_orient_base, off_rank_base;
+  int64_t off_pyr_base;
   int64_t off_counters, off_flags, off_bm, off_cand, off_sel, off_lvl, total;
-  int32_t n_entries, mark_tiles, det_tiles, orient_blocks, rank_slots, max_cand_cap;
+  int32_t n_entries, mark_tiles, det_tiles, orient_blocks, rank_slots, max_cand_cap, pyr_blocks;
   int64_t flag_bytes, bm_words, cand_entries, sel_entries, lvl_bytes;
 };
 
@@ -189,6 +201,7 @@ OF_HD void ws_layout_accumulate(WsLayout* w, const EntrySize& s) {
   w->mark_tiles += s.mark_tiles;
   w->det_tiles += s.det_tiles;
   w->orient_blocks += s.orient_blocks;
+  w->pyr_blocks += s.pyr_blocks;
   w->flag_bytes += s.flag_bytes;
   w->bm_words += s.bm_words;
   w->cand_entries += s.cand_cap;
@@ -206,6 +219,7 @@ OF_HD void ws_layout_finish(WsLayout* w) {
   w->off_det_base = o;     o = align_up(o + 4 * ((int64_t)w->n_entries + 1), 256);
   w->off_orient_base = o;  o = align_up(o + 4 * ((int64_t)w->n_entries + 1), 256);
   w->off_rank_base = o;    o = align_up(o + 4 * ((int64_t)w->n_entries + 1), 256);
+  w->off_pyr_base = o;     o = align_up(o + 4 * ((int64_t)w->n_entries + 1), 256);
   w->off_counters = o;     o = align_up(o + 8 * (int64_t)w->n_entries, 256);
   w->off_flags = o;        o = align_up(o + w->flag_bytes, 256);
   w->off_bm = o;           o = align_up(o + 4 * w->bm_words, 256);
@@ -259,16 +273,17 @@ OF_HD MarkLds mark_lds(const Tune& t) {
   return m;
 }
 
-// Harris/NMS tile: staged pixels (tile + 5-pixel halo), candidate words of the tile
-// plus a 1-pixel ring, their prefix counts, the Harris score cache, survivors, cell
-// buckets and the emit list.
+// Harris/NMS tile: staged pixels (tile + 5-pixel halo), 32-bit candidate words of the
+// tile plus a 1-pixel ring and their prefix counts, the Harris score cache, survivors
+// (candidate index, cell), the cell-grouped survivor list (or 2x2 block flags when the
+// level is one cell), per-cell counters and the cell flags of the ring.
 struct DetLds {
   int32_t mtw, mth;          // largest tile (pixels)
   int32_t pitch, rows;       // staged pixels
-  int32_t nwr, nunits;       // 64-bit candidate words per ring row, total words
+  int32_t nbw, nunits;       // candidate words per ring row (at most), total words
   int32_t max_surv, max_cells;
-  int32_t off_cw, off_ucnt, off_cpre, off_cpos, off_crs, off_spos, off_srs, off_scell, off_order,
-      off_emit, off_ccnt, off_coff, off_cfill, off_wlo, off_whi, off_lfl, bytes;
+  int32_t off_cw, off_ucnt, off_cpre, off_crs, off_cpos, off_sci, off_scell, off_order, off_ccnt,
+      off_coff, off_cfill, off_ckept, off_lfl, bytes;
 };
 
 OF_HD DetLds det_lds(const Tune& t, int32_t cell) {
@@ -284,30 +299,31 @@ OF_HD DetLds det_lds(const Tune& t, int32_t cell) {
   }
   d.pitch = (int32_t)align_up(d.mtw + 10 + 3, 4);
   d.rows = d.mth + 10;
-  d.nwr = cdiv(d.mtw + 2, 64);
-  d.nunits = (d.mth + 2) * d.nwr;
+  d.nbw = cdiv(d.mtw + 2, 32) + 1;
+  d.nunits = (d.mth + 2) * d.nbw;
   d.max_surv = cdiv(d.mtw, 2) * cdiv(d.mth, 2);
   int32_t o = (int32_t)align_up((int64_t)d.pitch * d.rows, 16);
-  d.off_cw = o;     o += 8 * d.nunits;
+  d.off_cw = o;     o += (int32_t)align_up(4 * d.nunits, 16);
   d.off_ucnt = o;   o += (int32_t)align_up(4 * d.nunits, 16);
   d.off_cpre = o;   o += (int32_t)align_up(4 * (d.nunits + 1), 16);
   d.off_crs = o;    o += 8 * kCandCache;
   d.off_cpos = o;   o += 4 * kCandCache;
-  d.off_srs = o;    o += (int32_t)align_up(8 * d.max_surv, 16);
-  d.off_spos = o;   o += (int32_t)align_up(4 * d.max_surv, 16);
+  d.off_sci = o;    o += (int32_t)align_up(2 * d.max_surv, 16);
   d.off_scell = o;  o += (int32_t)align_up(2 * d.max_surv, 16);
   d.off_order = o;  o += (int32_t)align_up(2 * d.max_surv, 16);
-  d.off_emit = o;   o += (int32_t)align_up(2 * d.max_surv, 16);
   d.off_ccnt = o;   o += (int32_t)align_up(4 * d.max_cells, 16);
   d.off_coff = o;   o += (int32_t)align_up(4 * d.max_cells, 16);
   d.off_cfill = o;  o += (int32_t)align_up(4 * d.max_cells, 16);
-  const int32_t nbw = cdiv(d.mtw + 2, 32) + 1;        // bitmap words per ring row
-  d.off_wlo = o;    o += (int32_t)align_up(4 * nbw * (d.mth + 2), 16);
-  d.off_whi = o;    o += (int32_t)align_up(4 * nbw * (d.mth + 2), 16);
+  d.off_ckept = o;  o += (int32_t)align_up(4 * d.max_cells, 16);
   const int32_t nfl = cell > 0 ? (t.det_cx + 2) * (t.det_cy + 2) : 4;  // cells of the ring
   d.off_lfl = o;    o += (int32_t)align_up(nfl, 16);
-  d.bytes = o;
+  d.bytes = o;      // + the entry base table of the launch
   return d;
+}
+
+// LDS of the entry base table that tile kernels keep after their own layout.
+OF_HD int32_t base_table_bytes(int32_t n_entries) {
+  return (int32_t)align_up(4 * ((int64_t)n_entries + 1), 16);
 }
 
 }  // namespace ofk

@@ -47,7 +47,7 @@ class OfPyramidDesc(ctypes.Structure):
 class OfTuning(ctypes.Structure):
     _fields_ = [(n, ctypes.c_int32) for n in (
         "mark_words", "mark_rows", "det_cells_x", "det_cells_y", "det_w", "det_h",
-        "mark_grid", "det_grid")]
+        "mark_grid", "det_grid", "pyr_pass")]
 
 
 KEYPOINT_DTYPE = np.dtype([("x", "<i4"), ("y", "<i4"), ("level", "<i4"), ("m10", "<i4"),
@@ -108,6 +108,7 @@ def tuning(**kw) -> OfTuning:
     t = OfTuning()
     t.mark_grid = -1
     t.det_grid = -1
+    t.pyr_pass = -1
     for k, v in kw.items():
         setattr(t, k, v)
     return t

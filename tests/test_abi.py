@@ -94,7 +94,8 @@ def test_detect_argument_errors_before_any_launch(lib):
     # tuning outside its ranges
     imgs = (ofhip.OfImage * 1)(img)
     offs = (ctypes.c_int64 * 1)(0)
-    for kw in (dict(mark_words=5), dict(mark_rows=65), dict(det_w=300), dict(det_h=4)):
+    for kw in (dict(mark_words=5), dict(mark_rows=65), dict(det_w=300), dict(det_h=4),
+               dict(det_w=129), dict(det_h=33)):
         t = ofhip.tuning(**kw)
         assert lib.of_detect_batch(imgs, 1, ctypes.byref(p), 0x1000, 1 << 30, 0x1000, offs, 100,
                                    0x1000, ctypes.byref(t), None) == ofhip.OF_EINVAL, kw

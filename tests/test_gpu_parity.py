@@ -215,7 +215,9 @@ def test_c2_plain_and_fused(hip):
 
 @pytest.mark.parametrize("tune", [dict(mark_grid=0, det_grid=0), dict(mark_words=1, mark_rows=4),
                                   dict(mark_words=2, mark_rows=64, det_cells_x=8, det_cells_y=1),
-                                  dict(det_cells_x=1, det_cells_y=1, mark_grid=7, det_grid=3)])
+                                  dict(det_cells_x=1, det_cells_y=1, mark_grid=7, det_grid=3),
+                                  dict(pyr_pass=1), dict(pyr_pass=1, mark_words=1, mark_rows=8,
+                                                         mark_grid=64)])
 def test_c2_tunings_agree(hip, tune):
     spec = CONFIGS["c2"]["frames"][0]
     kw = CONFIGS["c2"]["params"]
@@ -225,14 +227,32 @@ def test_c2_tunings_agree(hip, tune):
     assert_same_keypoints(run_batch(hip, [img], kw, hip.tuning(**tune))[0], ref, str(tune))
 
 
+@pytest.mark.parametrize("tune", [dict(det_w=8, det_h=8), dict(det_w=64, det_h=32),
+                                  dict(det_w=64, det_h=16, pyr_pass=1, det_grid=5)])
+def test_whole_level_cell_tunings_agree(hip, tune):
+    """cell = 0 (one cell per level, K = N_l): output slots per 2x2 block, any tiling."""
+    kw = _kw(n_levels=3, cell=0, fast_t=8, fast_t_min=8, n_features=400)
+    spec = FrameSpec(641, 479, 5, 60, 2.0, texture_amp=6)
+    log(f"case: whole-level cells {spec} {tune}")
+    img = make_frame(spec)
+    ref = oracle.detect(img, oracle.params(**kw))
+    assert len(ref) == 400
+    assert_same_keypoints(run_batch(hip, [img], kw, hip.tuning(**tune))[0], ref, str(tune))
+
+
 def test_c3_batch(hip):
     specs = CONFIGS["c3"]["frames"]
     kw = CONFIGS["c3"]["params"]
     log(f"case: c3 batch of {len(specs)}")
     refs = detect_many(specs, kw)
-    res = run_batch(hip, [make_frame(s) for s in specs], kw)
+    imgs = [make_frame(s) for s in specs]
+    res = run_batch(hip, imgs, kw)
     for i, (g, r) in enumerate(zip(res, refs)):
         assert_same_keypoints(g, r, f"c3 frame {i}")
+    log("case: c3 batch, separate pyramid pass")
+    res = run_batch(hip, imgs, kw, hip.tuning(pyr_pass=1))
+    for i, (g, r) in enumerate(zip(res, refs)):
+        assert_same_keypoints(g, r, f"c3 frame {i} (pyramid pass)")
 
 
 def test_c4_batch(hip):
