@@ -18,6 +18,8 @@ import time
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
+import hashlib
+
 # int32 VALU peak: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz (one op per lane per clock).
 ALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
 # Algorithmic integer ops: 11 per resampled pixel (four Q8 taps, one rounding) and 32 per
@@ -38,6 +40,47 @@ def level_work(shapes, p):
                 res += w * h
             seg += (w - 2 * B) * (h - 2 * B)
     return res, seg
+
+
+KERNEL_SOURCES = ("paper_2506_07164_amd/csrc/of_kernels.hip", "paper_2506_07164_amd/csrc/of_plan.h")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_mark_fused_1080p_8level_traffic.txt")
+COPY_MIB = 256
+PROFILE_REPEAT = 10
+
+
+def kernel_source_hash():
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic():
+    """HBM bytes per launch of the segment-test kernel from the committed counter summary
+    (FETCH_SIZE + WRITE_SIZE, each scaled by the same counter on a plain copy), or None
+    when the kernel sources changed since the counters were taken."""
+    try:
+        with open(TRAFFIC_FILE) as fh:
+            kv = dict(l.strip().split("=", 1) for l in fh if "=" in l and not l.startswith("#"))
+    except OSError:
+        return None
+    if kv.get("kernel_src_sha") != kernel_source_hash():
+        return None
+    return int(float(kv["traffic_bytes_per_launch"]))
+
+
+def calibrate_copy():
+    """A plain device-to-device copy of known size, for scaling the HBM byte counters."""
+    import torch
+    n = COPY_MIB << 20
+    src = torch.full((n,), 7, dtype=torch.uint8, device="cuda")
+    dst = torch.empty_like(src)
+    torch.cuda.synchronize()
+    for _ in range(5):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes": n, "copies": 5}), flush=True)
 
 
 def cpu_baseline(img, kw, budget_s=15.0):
@@ -63,11 +106,18 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-tune", action="store_true", help="library default launch shape")
     ap.add_argument("--tune-verbose", action="store_true")
+    ap.add_argument("--no-batched", action="store_true", help="skip the 16-frame batched figure")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help=f"only run a {COPY_MIB} MiB device copy (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path "
               "(frames shard across GPUs with no exchange between them)", file=sys.stderr)
         sys.exit(2)
+
+    if args.calibrate_copy:
+        calibrate_copy()
+        return
 
     import numpy as np
     import torch
@@ -129,9 +179,11 @@ def main():
     t_plain = time.perf_counter() - t0
     print(f"# plain {Kp} steps {t_plain * 1e3:.1f} ms", file=sys.stderr, flush=True)
 
-    # per-step kernel durations: HIP events around each launch on its stream
-    Kq = max(1, min(K, 1000))
-    ofhip.of_profile_enable(True)
+    # per-step kernel durations: HIP events on the launching stream; repeatable launches
+    # (segment test, selection) are issued PROFILE_REPEAT times back to back between
+    # their events, so the mean is the kernel's duration without the event overhead
+    Kq = max(1, min(K, 500))
+    ofhip.of_profile_enable(PROFILE_REPEAT)
     with torch.cuda.stream(stream):
         for _ in range(Kq):
             fused.detect_batch([frame], tune=tune, stream=stream)
@@ -149,14 +201,45 @@ def main():
     for k in ("x", "y", "level", "score", "m10", "m01"):
         assert np.array_equal(got_f[k], got_p[k]), k
 
+    # batched form: 16 copies of the frame (distinct buffers) in one call, graph replays
+    batched = None
+    if not args.no_batched:
+        nb = 16
+        bframes = [frame.clone() for _ in range(nb)]
+        bdet = ofhip.Detector([img.shape] * nb, p)
+        with torch.cuda.stream(stream):
+            for _ in range(3):
+                bdet.detect_batch(bframes, tune=tune, stream=stream)
+        torch.cuda.synchronize()
+        bgraph = torch.cuda.CUDAGraph()
+        with torch.cuda.stream(stream):
+            with torch.cuda.graph(bgraph, stream=stream):
+                bdet.detect_batch(bframes, tune=tune, stream=stream)
+        for _ in range(5):
+            bgraph.replay()
+        torch.cuda.synchronize()
+        Kb = max(1, K // 16)
+        t0 = time.perf_counter()
+        for _ in range(Kb):
+            bgraph.replay()
+        torch.cuda.synchronize()
+        t_b = time.perf_counter() - t0
+        bres = bdet.results()
+        for k in ("x", "y", "level", "score", "m10", "m01"):
+            assert all(np.array_equal(r[k], got_f[k]) for r in bres), k
+        batched = {"frames_per_call": nb, "calls": Kb, "fps": round(nb * Kb / t_b, 1)}
+        print(f"# batched {nb} frames x {Kb} calls {t_b * 1e3:.1f} ms", file=sys.stderr, flush=True)
+
     res_px, seg_px = level_work([img.shape], p)
     t_mark = step_us["segment_test"] * 1e-6
     ops = OPS_RESAMPLE * res_px + OPS_SEGMENT * seg_px
     achieved = ops / t_mark / 1e12 if t_mark > 0 else 0.0
     roofline = {"bound": "alu", "achieved": round(achieved, 3), "peak": round(ALU_PEAK_TOPS, 2),
-                "unit": "TOP/s", "frac": round(achieved / ALU_PEAK_TOPS, 4), "traffic": None,
-                "kernel": "k_mark<fused> (pyramid + segment test)",
-                "kernel_us": round(step_us["segment_test"], 3)}
+                "unit": "TOP/s", "frac": round(achieved / ALU_PEAK_TOPS, 4),
+                "traffic": measured_traffic(),
+                "kernel": "k_mark<true,4> (pyramid resample + segment test, all levels)",
+                "kernel_us": round(step_us["segment_test"], 3),
+                "kernel_src_sha": kernel_source_hash()}
 
     fused_fps = K / t_fused
     out = {
@@ -176,6 +259,7 @@ def main():
                                "30x30 cell, 2000 keypoints, fused path (graph)",
                    "frames_per_step": 1},
         "plain_fps": round(Kp / t_plain, 1),
+        "batched": batched,
         "tuning": tune_fields,
         "step_us": {k: round(v, 3) for k, v in step_us.items()},
         "hbm_algorithmic_gbps": round((img.nbytes + 32 * kw["n_features"]) * fused_fps / 1e9, 2),

@@ -154,7 +154,11 @@ int of_test_segment(const uint8_t* circles, int32_t n, int32_t t_lo, int32_t t_h
  * 5 orientation.  of_profile_read waits for the recorded events, writes the summed
  * milliseconds and launch counts of the first n steps (host arrays) and clears them.
  * Events come from a fixed pool created on the first enable; launches beyond the pool
- * are not timed (their count is still reported in launches[]). */
+ * are not timed (their count is still reported in launches[]).  on > 1 also issues each
+ * repeatable launch (pyramid, segment test without a persistent grid, level selection:
+ * launches that give the same results when issued again) `on` times back to back
+ * between its events, so that ms / launches is the kernel's own duration; results are
+ * unchanged.  on = 0 disables. */
 #define OF_PROFILE_STEPS 6
 int of_profile_enable(int on);
 int of_profile_read(double* ms, int64_t* launches, int32_t n);

@@ -20,6 +20,7 @@ constexpr int kEventPool = 8192;
 struct Profiler {
   std::mutex mu;
   bool on = false;
+  int repeat = 1;   // back-to-back issues of a repeatable launch between its events
   bool created = false;
   hipEvent_t ev[2 * kEventPool];
   int step_of[kEventPool];
@@ -29,18 +30,22 @@ struct Profiler {
 
 Profiler g_prof;
 
-// Runs `launch` between two events when profiling is on.
+// Runs `launch` between two events when profiling is on.  A repeatable launch (one
+// that gives the same results when issued again: it neither accumulates nor draws from
+// a queue) is issued `repeat` times back to back, so the events measure the kernel and
+// not the event overhead.
 template <class F>
-hipError_t timed(int step, hipStream_t s, F&& launch) {
+hipError_t timed(int step, hipStream_t s, F&& launch, bool repeatable = false) {
   if (!g_prof.on) return launch();
   std::lock_guard<std::mutex> lk(g_prof.mu);
-  g_prof.launches[step] += 1;
+  const int times = repeatable ? g_prof.repeat : 1;
+  g_prof.launches[step] += times;
   if (g_prof.used >= kEventPool) return launch();
   const int k = g_prof.used++;
   g_prof.step_of[k] = step;
   hipError_t e = hipEventRecord(g_prof.ev[2 * k], s);
   if (e != hipSuccess) return e;
-  e = launch();
+  for (int r = 0; r < times && e == hipSuccess; ++r) e = launch();
   if (e != hipSuccess) return e;
   return hipEventRecord(g_prof.ev[2 * k + 1], s);
 }
@@ -92,14 +97,14 @@ int device_cus() {
   return cus;
 }
 
-// Defaults: 256 x 16 segment-test tiles; Harris/NMS tiles of about 120 x 30 pixels
-// (whole cells).
+// Defaults: 256 x 16 segment-test tiles; Harris/NMS tiles of about 240 x 30 pixels
+// (whole cells), or 128 x 32 pixels when the level is one cell.
 Tune default_tune(const of_params& p) {
   Tune t;
   t.mark_words = 4;
   t.mark_rows = 16;
   if (p.cell > 0) {
-    t.det_cx = 120 / p.cell > 0 ? 120 / p.cell : 1;
+    t.det_cx = 240 / p.cell > 0 ? 240 / p.cell : 1;
     t.det_cy = 30 / p.cell > 0 ? 30 / p.cell : 1;
   } else {
     t.det_cx = t.det_cy = 1;
@@ -112,6 +117,10 @@ Tune default_tune(const of_params& p) {
   t.mark_grid = 0;
   t.det_grid = 0;
   t.pyr_pass = 0;
+  // narrower Harris tiles where large cells would exceed the LDS budget
+  while (p.cell > 0 && t.det_cx > 1 &&
+         det_lds(t, p.cell).bytes + base_table_bytes(kMaxEntries) > 65536)
+    --t.det_cx;
   return t;
 }
 
@@ -236,7 +245,8 @@ KArgs kargs(void* ws, const WsLayout& lay, const Tune& t, const of_params& p) {
 hipError_t launch_selection(KArgs k, const WsLayout& lay, hipStream_t stream) {
   k.entry = -1;
   k.persistent = 0;
-  hipError_t e = timed(4, stream, [&] { return launch_select_orient(k, lay.rank_slots, stream); });
+  hipError_t e = timed(4, stream, [&] { return launch_select_orient(k, lay.rank_slots, stream); },
+                       true);
   if (e == hipSuccess && lay.max_cand_cap > kRankCap) {
     k.total = lay.n_entries;
     e = timed(4, stream, [&] { return launch_select(k, lay.n_entries, stream); });
@@ -363,14 +373,14 @@ int of_detect(const of_image* in, const of_params* params, void* ws, size_t ws_b
     a.lv[0].w = c->geo[0].W[l];
     a.lv[0].h = c->geo[0].H[l];
     a.lv[0].stride = level_stride(c->geo[0].W[l]);
-    e = timed(1, stream, [&] { return launch_pyramid(a, 1, a.lv[0].w, a.lv[0].h, stream); });
+    e = timed(1, stream, [&] { return launch_pyramid(a, 1, a.lv[0].w, a.lv[0].h, stream); }, true);
   }
   KArgs k = kargs(ws, c->lay, t, p);
   k.persistent = 0;
   for (int l = 0; l < L && e == hipSuccess; ++l) {
     k.entry = l;
     k.total = c->es[l].mark_tiles;
-    e = timed(2, stream, [&] { return launch_mark(k, false, k.total, stream); });
+    e = timed(2, stream, [&] { return launch_mark(k, false, k.total, stream); }, true);
   }
   for (int l = 0; l < L && e == hipSuccess; ++l) {
     k.entry = l;
@@ -412,12 +422,13 @@ int of_detect_batch(const of_image* frames, int32_t n, const of_params* params, 
   const bool fused = !t.pyr_pass || c->lay.pyr_blocks == 0;
   if (e == hipSuccess && !fused) {
     k.total = c->lay.pyr_blocks;
-    e = timed(1, stream, [&] { return launch_pyramid_batch(k, c->lay.pyr_blocks, stream); });
+    e = timed(1, stream, [&] { return launch_pyramid_batch(k, c->lay.pyr_blocks, stream); }, true);
   }
   if (e == hipSuccess) {
     k.total = c->lay.mark_tiles;
     k.persistent = t.mark_grid > 0 && t.mark_grid < k.total;
-    e = timed(2, stream, [&] { return launch_mark(k, fused, k.persistent ? t.mark_grid : k.total, stream); });
+    e = timed(2, stream, [&] { return launch_mark(k, fused, k.persistent ? t.mark_grid : k.total, stream); },
+              !k.persistent);
   }
   if (e == hipSuccess) {
     k.total = c->lay.det_tiles;
@@ -450,6 +461,7 @@ int of_profile_enable(int on) {
     g_prof.created = true;
   }
   g_prof.on = on != 0;
+  g_prof.repeat = on > 1 ? on : 1;
   return OF_OK;
 }
 

@@ -854,7 +854,8 @@ __global__ __launch_bounds__(256, 4) void k_detect(KArgs a) {
   int64_t* crs = (int64_t*)(smem + D.off_crs);
   uint32_t* cpos = (uint32_t*)(smem + D.off_cpos);
   uint16_t* sci = (uint16_t*)(smem + D.off_sci);
-  uint16_t* scell = (uint16_t*)(smem + D.off_scell);
+  uint16_t* scell = (uint16_t*)(smem + D.off_scell);  // cell of each survivor (multi only)
+  const bool multi = D.max_cells > 1;
   uint16_t* order = (uint16_t*)(smem + D.off_order);  // cells: grouped survivors; else block flags
   uint32_t* ccnt = (uint32_t*)(smem + D.off_ccnt);
   uint32_t* coff = (uint32_t*)(smem + D.off_coff);
@@ -1059,7 +1060,7 @@ __global__ __launch_bounds__(256, 4) void k_detect(KArgs a) {
       if (alive) {
         const int si = atomicAdd(&s_ns, 1);
         sci[si] = (uint16_t)ci;
-        scell[si] = a.cell > 0 ? (uint16_t)((y / cs - cya) * nlcx + (x / cs - cxa)) : 0;
+        if (multi) scell[si] = (uint16_t)((y / cs - cya) * nlcx + (x / cs - cxa));
       }
     }
     lds_barrier();
@@ -1071,7 +1072,7 @@ __global__ __launch_bounds__(256, 4) void k_detect(KArgs a) {
     gptr<Cand> out = G(P.cand);
     if (ns > 0) {
       if (a.cell > 0) {
-        for (int s2 = tid; s2 < ns; s2 += bd) atomicAdd(&ccnt[scell[s2]], 1u);
+        for (int s2 = tid; s2 < ns; s2 += bd) atomicAdd(&ccnt[multi ? scell[s2] : 0], 1u);
         lds_barrier();
         if (tid == 0) {
           uint32_t o = 0;
@@ -1082,7 +1083,7 @@ __global__ __launch_bounds__(256, 4) void k_detect(KArgs a) {
         }
         lds_barrier();
         for (int s2 = tid; s2 < ns; s2 += bd) {
-          const int c = scell[s2];
+          const int c = multi ? scell[s2] : 0;
           order[coff[c] + atomicAdd(&cfill[c], 1u)] = (uint16_t)s2;
         }
         lds_barrier();
@@ -1091,7 +1092,7 @@ __global__ __launch_bounds__(256, 4) void k_detect(KArgs a) {
         const int ci = sci[s];
         const uint32_t pos = cand_pos(ci);
         const int64_t R = cand_score(ci, pos);
-        const int c = scell[s];
+        const int c = multi ? scell[s] : 0;
         const int n = a.cell > 0 ? (int)ccnt[c] : ns;
         bool keep = true;
         if (n > K) {

@@ -275,7 +275,7 @@ OF_HD MarkLds mark_lds(const Tune& t) {
 
 // Harris/NMS tile: staged pixels (tile + 5-pixel halo), 32-bit candidate words of the
 // tile plus a 1-pixel ring and their prefix counts, the Harris score cache, survivors
-// (candidate index, cell), the cell-grouped survivor list (or 2x2 block flags when the
+// (candidate index; cell only when the tile holds several), the cell-grouped survivor list (or 2x2 block flags when the
 // level is one cell), per-cell counters and the cell flags of the ring.
 struct DetLds {
   int32_t mtw, mth;          // largest tile (pixels)
@@ -297,7 +297,9 @@ OF_HD DetLds det_lds(const Tune& t, int32_t cell) {
     d.mth = t.det_h;
     d.max_cells = 1;
   }
+  // odd number of 32-bit words per row: the rows of a Harris window fall in distinct banks
   d.pitch = (int32_t)align_up(d.mtw + 10 + 3, 4);
+  if ((d.pitch >> 2) % 2 == 0) d.pitch += 4;
   d.rows = d.mth + 10;
   d.nbw = cdiv(d.mtw + 2, 32) + 1;
   d.nunits = (d.mth + 2) * d.nbw;
@@ -309,7 +311,7 @@ OF_HD DetLds det_lds(const Tune& t, int32_t cell) {
   d.off_crs = o;    o += 8 * kCandCache;
   d.off_cpos = o;   o += 4 * kCandCache;
   d.off_sci = o;    o += (int32_t)align_up(2 * d.max_surv, 16);
-  d.off_scell = o;  o += (int32_t)align_up(2 * d.max_surv, 16);
+  d.off_scell = o;  o += d.max_cells > 1 ? (int32_t)align_up(2 * d.max_surv, 16) : 0;
   d.off_order = o;  o += (int32_t)align_up(2 * d.max_surv, 16);
   d.off_ccnt = o;   o += (int32_t)align_up(4 * d.max_cells, 16);
   d.off_coff = o;   o += (int32_t)align_up(4 * d.max_cells, 16);

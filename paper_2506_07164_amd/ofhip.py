@@ -171,8 +171,10 @@ PROFILE_STEP_NAMES = ["prologue", "pyramid", "segment_test", "harris_nms_cells",
                       "orient"]
 
 
-def of_profile_enable(on: bool) -> None:
-    _check(lib().of_profile_enable(1 if on else 0), "of_profile_enable")
+def of_profile_enable(on) -> None:
+    """False/0 off, True/1 events per step launch, n > 1 also repeats each repeatable
+    launch n times between its events (kernel-only durations)."""
+    _check(lib().of_profile_enable(int(on)), "of_profile_enable")
 
 
 def of_profile_read():

@@ -107,3 +107,16 @@ def test_workspace_independent_of_tuning_and_monotone(lib):
     a = ofhip.of_workspace_size([ofhip.OfImage(None, 1920, 1080, 1920)], p)
     b = ofhip.of_workspace_size([ofhip.OfImage(None, 1920, 1080, 1920)] * 2, p)
     assert b > a > 1920 * 1080
+
+
+def test_default_tuning_valid_for_every_cell_size(lib):
+    """The library's default launch shape fits its LDS limits for every accepted cell
+    size: a call with a too-small workspace gets past tuning and stops at ENOSPACE."""
+    img = ofhip.OfImage(0x1000, 1000, 800, 1024)
+    imgs = (ofhip.OfImage * 1)(img)
+    offs = (ctypes.c_int64 * 1)(0)
+    for cell in [0] + list(range(8, 129)):
+        p = ofhip.params(n_levels=3, cell=cell, n_features=500)
+        st = lib.of_detect_batch(imgs, 1, ctypes.byref(p), 0x1000, 16, 0x1000, offs, 500, 0x1000,
+                                 None, None)
+        assert st == ofhip.OF_ENOSPACE, (cell, st)

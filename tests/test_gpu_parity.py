@@ -240,6 +240,19 @@ def test_whole_level_cell_tunings_agree(hip, tune):
     assert_same_keypoints(run_batch(hip, [img], kw, hip.tuning(**tune))[0], ref, str(tune))
 
 
+@pytest.mark.parametrize("cell", [8, 64, 100, 128])
+def test_cell_sizes(hip, cell):
+    """Default launch shapes across cell sizes: narrow cells (many per tile) to cells
+    wider than a tile budget of 240 pixels (one cell per tile, no per-survivor cell)."""
+    kw = _kw(n_levels=3, cell=cell, n_features=600)
+    spec = FrameSpec(700, 500, 11 + cell, 80, 2.5)
+    log(f"case: cell {cell} {spec}")
+    img = make_frame(spec)
+    ref = oracle.detect(img, oracle.params(**kw))
+    assert_same_keypoints(run_batch(hip, [img], kw)[0], ref, f"cell {cell} batch")
+    assert_same_keypoints(run_plain(hip, img, kw), ref, f"cell {cell} plain")
+
+
 def test_c3_batch(hip):
     specs = CONFIGS["c3"]["frames"]
     kw = CONFIGS["c3"]["params"]
