@@ -94,6 +94,39 @@ def harris_map(img, r=3):
     return R
 
 
+def harris_sliding(img, r=3):
+    """R' map by sliding column sums: per column, running sums of the products over
+    2r+1 rows, then running sums of those column sums over 2r+1 columns (the structure
+    of Alg. 3, written from its description)."""
+    gx, gy = sobel_separable(img)
+    H, W = img.shape
+    n = 2 * r + 1
+    prods = [gx * gx, gy * gy, gx * gy]
+    boxes = []
+    for p in prods:
+        col = np.zeros((H, W), np.int64)
+        acc = np.zeros(W, np.int64)
+        for y in range(H):
+            acc += p[y]
+            if y >= n:
+                acc -= p[y - n]
+            col[y] = acc            # rows y-n+1 .. y
+        box = np.zeros((H, W), np.int64)
+        for y in range(H):
+            run = 0
+            for x in range(W):
+                run += int(col[y, x])
+                if x >= n:
+                    run -= int(col[y, x - n])
+                box[y, x] = run     # columns x-n+1 .. x
+        boxes.append(box)
+
+    def R(x, y):
+        a, b, c = (int(bx[y + r, x + r]) for bx in boxes)
+        return 25 * (a * b - c * c) - (a + b) ** 2
+    return R
+
+
 def level_keypoints(lvl, t_hi, t_lo, cell, K, N, B=15):
     """Candidates, survivors and the kept keypoints [(R', y, x)] of one level."""
     Hl, Wl = lvl.shape

@@ -163,15 +163,18 @@ def test_harris_constant_and_edge():
 
 @pytest.mark.parametrize("seed", range(4))
 def test_harris_separable_and_mirror(seed):
-    """2D kernels (oracle) equal the separable form of Eq. (4) (brute force), and R' is
-    unchanged by mirroring the image (a sign flip of G_x)."""
+    """2D kernels (oracle) equal the separable form of Eq. (4) and the sliding
+    column-sum form of Alg. 3 (brute force), and R' is unchanged by mirroring the image
+    (a sign flip of G_x)."""
     img = _rng_img(24, 24, seed)
     R = bf.harris_map(img)
+    S = bf.harris_sliding(img)
     mir = np.ascontiguousarray(img[:, ::-1])
     for y in range(4, 20):
         for x in range(4, 20):
             v = oracle.harris(img, x, y)
             assert v == R(x, y)
+            assert v == S(x, y)
             assert v == oracle.harris(mir, 23 - x, y)
 
 
