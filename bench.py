@@ -107,6 +107,7 @@ def main():
     ap.add_argument("--no-tune", action="store_true", help="library default launch shape")
     ap.add_argument("--tune-verbose", action="store_true")
     ap.add_argument("--no-batched", action="store_true", help="skip the 16-frame batched figure")
+    ap.add_argument("--no-serve", action="store_true", help="skip the served (32-stream) figure")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help=f"only run a {COPY_MIB} MiB device copy (counter calibration)")
     args = ap.parse_args()
@@ -167,6 +168,16 @@ def main():
     torch.cuda.synchronize()
     t_fused = time.perf_counter() - t0
     print(f"# fused {K} steps {t_fused * 1e3:.1f} ms", file=sys.stderr, flush=True)
+
+    # timed: fused path, eager calls (no graph), same K
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    with torch.cuda.stream(stream):
+        for _ in range(K):
+            fused.detect_batch([frame], tune=tune, stream=stream)
+    torch.cuda.synchronize()
+    t_fused_eager = time.perf_counter() - t0
+    print(f"# fused eager {K} steps {t_fused_eager * 1e3:.1f} ms", file=sys.stderr, flush=True)
 
     # timed: plain path, eager launches
     Kp = max(1, K // 4)
@@ -230,6 +241,26 @@ def main():
         batched = {"frames_per_call": nb, "calls": Kb, "fps": round(nb * Kb / t_b, 1)}
         print(f"# batched {nb} frames x {Kb} calls {t_b * 1e3:.1f} ms", file=sys.stderr, flush=True)
 
+    # served form: 32 camera streams (720x540..1920x1080, 30 fps Poisson each), continuous
+    # batching; latency from arrival to host-visible keypoints
+    served = None
+    if not args.no_serve:
+        from paper_2506_07164_amd import serve
+        from synth import stream_schedule
+        pool = serve.camera_pool(32, 2)
+        server = serve.Server(p, hbm_budget=4 << 30, max_batch=16, lanes=3)
+        frame_of = lambda s_, k_: (pool[(s_, k_ % 2)][0], (s_, k_ % 2))
+        serve.run_schedule(server, stream_schedule(32, 0.2, 30.0), frame_of, rate_scale=4.0)
+        served = {"workload": "32 streams x 30 fps Poisson, 720x540..1920x1080, 8 levels, N=2000",
+                  "runs": []}
+        for scale in (1.0, 32.0):
+            res, wall = serve.run_schedule(server, stream_schedule(32, 1.0, 30.0), frame_of,
+                                           rate_scale=scale)
+            row = serve.summarize(res, wall, 32 * 30.0 * scale)
+            row["scale"] = scale
+            served["runs"].append(row)
+        print(f"# served {served['runs']}", file=sys.stderr, flush=True)
+
     res_px, seg_px = level_work([img.shape], p)
     t_mark = step_us["segment_test"] * 1e-6
     ops = OPS_RESAMPLE * res_px + OPS_SEGMENT * seg_px
@@ -241,7 +272,9 @@ def main():
                 "kernel_us": round(step_us["segment_test"], 3),
                 "kernel_src_sha": kernel_source_hash()}
 
-    fused_fps = K / t_fused
+    mode = "graph" if t_fused <= t_fused_eager else "eager"
+    t_best = min(t_fused, t_fused_eager)
+    fused_fps = K / t_best
     out = {
         "metric": "frames/sec 1920x1080 8-level Oriented FAST (batched vs plain), HBM GB/s %",
         "value": round(fused_fps, 1),
@@ -249,17 +282,19 @@ def main():
         "n_gpus": 1,
         "steps": K,
         "warmup": args.warmup,
-        "ms_per_step": round(t_fused / K * 1e3, 4),
+        "ms_per_step": round(t_best / K * 1e3, 4),
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "u8/int32/int64",
         "data": "synthetic",
         "config": {"workload": "c2: one 1920x1080 frame, 8-level 1.2 pyramid, FAST 20/7 per "
-                               "30x30 cell, 2000 keypoints, fused path (graph)",
-                   "frames_per_step": 1},
+                               "30x30 cell, 2000 keypoints, fused path",
+                   "frames_per_step": 1, "launch": mode},
+        "fused_fps": {"graph": round(K / t_fused, 1), "eager": round(K / t_fused_eager, 1)},
         "plain_fps": round(Kp / t_plain, 1),
         "batched": batched,
+        "served": served,
         "tuning": tune_fields,
         "step_us": {k: round(v, 3) for k, v in step_us.items()},
         "hbm_algorithmic_gbps": round((img.nbytes + 32 * kw["n_features"]) * fused_fps / 1e9, 2),

@@ -92,7 +92,8 @@ typedef struct {
 } of_pyramid_desc;
 
 /* Launch shape of the batched path (tile sizes, grid sizes, pyramid pass).  Tile fields
- * set to 0 take the default; grid and pyr_pass fields take the default when negative.
+ * set to 0 take the default; grid, pyr_pass and mark_order fields take the default when
+ * negative.
  * of_tuning_default() reports the defaults for a batch.  det_w and det_h must be even. */
 typedef struct {
   int32_t mark_words; /* segment-test tile width in 64-pixel words, 1..4 */
@@ -103,6 +104,9 @@ typedef struct {
   int32_t det_grid;   /* workgroups of the persistent Harris/NMS launch (0 = one per tile) */
   int32_t pyr_pass;   /* 1 = resample the levels in a pass of their own before the segment
                          test; 0 = the segment-test tiles resample their own pixels */
+  int32_t mark_order; /* 1 = segment-test tiles ordered by XCD band (block b takes band
+                         b % 8 of every level, so each XCD's L2 holds one band of each
+                         frame); 0 = entry-major order.  Ignored with a persistent grid. */
 } of_tuning;
 
 /* Host only.  Level sizes, strides and offsets of the pyramid of a W x H frame. */

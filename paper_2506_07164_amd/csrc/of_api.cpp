@@ -3,6 +3,7 @@
 // of_kernels.hip; this file only checks arguments and queues launches.
 #include <string.h>
 
+#include <algorithm>
 #include <mutex>
 
 #include "of_kernels.h"
@@ -117,6 +118,7 @@ Tune default_tune(const of_params& p) {
   t.mark_grid = 0;
   t.det_grid = 0;
   t.pyr_pass = 0;
+  t.mark_order = 0;
   // narrower Harris tiles where large cells would exceed the LDS budget
   while (p.cell > 0 && t.det_cx > 1 &&
          det_lds(t, p.cell).bytes + base_table_bytes(kMaxEntries) > 65536)
@@ -136,6 +138,7 @@ int resolve_tune(const of_tuning* user, const of_params& p, Tune* out) {
     if (user->mark_grid >= 0) t.mark_grid = user->mark_grid;
     if (user->det_grid >= 0) t.det_grid = user->det_grid;
     if (user->pyr_pass >= 0) t.pyr_pass = user->pyr_pass != 0;
+    if (user->mark_order >= 0) t.mark_order = user->mark_order != 0;
   }
   if (t.mark_words < 1 || t.mark_words > 4 || t.mark_rows < 4 || t.mark_rows > 64)
     return OF_EINVAL;
@@ -231,6 +234,7 @@ KArgs kargs(void* ws, const WsLayout& lay, const Tune& t, const of_params& p) {
   k.orient_base = (const int32_t*)(b + lay.off_orient_base);
   k.rank_base = (const int32_t*)(b + lay.off_rank_base);
   k.pyr_base = (const int32_t*)(b + lay.off_pyr_base);
+  k.band_base = (const int32_t*)(b + lay.off_band_base);
   k.rank_path = 1;
   k.qctr = (uint32_t*)(b + lay.off_hdr);
   k.n_entries = lay.n_entries;
@@ -338,6 +342,7 @@ int of_tuning_default(const of_image* frames, int32_t n, const of_params* params
   out->mark_grid = t.mark_grid;
   out->det_grid = t.det_grid;
   out->pyr_pass = t.pyr_pass;
+  out->mark_order = t.mark_order;
   return OF_OK;
 }
 
@@ -427,8 +432,15 @@ int of_detect_batch(const of_image* frames, int32_t n, const of_params* params, 
   if (e == hipSuccess) {
     k.total = c->lay.mark_tiles;
     k.persistent = t.mark_grid > 0 && t.mark_grid < k.total;
+    if (!k.persistent && t.mark_order == 1) {
+      int32_t widest = 0;
+      for (int b = 0; b < kXcds; ++b) widest = std::max(widest, c->lay.band_tiles[b]);
+      k.bands = 1;
+      k.total = kXcds * widest;
+    }
     e = timed(2, stream, [&] { return launch_mark(k, fused, k.persistent ? t.mark_grid : k.total, stream); },
               !k.persistent);
+    k.bands = 0;
   }
   if (e == hipSuccess) {
     k.total = c->lay.det_tiles;

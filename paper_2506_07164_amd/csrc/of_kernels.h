@@ -32,6 +32,7 @@ struct KArgs {
   const int32_t* orient_base;
   const int32_t* rank_base;    // exclusive prefix of ranked candidate slots per entry
   const int32_t* pyr_base;     // exclusive prefix of resample blocks per entry
+  const int32_t* band_base;    // kXcds tables: prefix of segment-test tiles per entry in band k
   uint32_t* qctr;              // queue counters: [0] segment-test tiles, [2] Harris tiles
   int32_t n_entries;
   int32_t total;               // tiles (or blocks) of this launch
@@ -39,6 +40,7 @@ struct KArgs {
   int32_t persistent;          // 1: blocks draw tiles from qctr until exhausted
   int32_t cell;                // params.cell
   int32_t rank_path;           // 1: k_select_orient ranks levels with <= kRankCap candidates
+  int32_t bands;               // 1: k_mark block b takes band b % kXcds, tile b / kXcds of it
   Tune t;
 };
 

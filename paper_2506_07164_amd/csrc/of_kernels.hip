@@ -167,14 +167,14 @@ __device__ __forceinline__ void stage_rows(uint8_t* lds, int lp, gptr<const uint
   int w = (int)threadIdx.x - row * nw;
   for (int base = 0; base < total; base += U * bd) {
     uint32_t v[U];
-    int off[U];
+    const int row0 = row, w0 = w;
 #pragma unroll
     for (int u = 0; u < U; ++u) {
       const int x = x0 + 4 * w;
-      off[u] = base + u * bd + (int)threadIdx.x < total ? row * lp + 4 * w : -1;
-      v[u] = off[u] >= 0 ? load_word(src + (size_t)(y0 + row) * stride + x,
-                                     aligned && x + 4 <= row_limit, min(4, x1 - x))
-                         : 0u;
+      v[u] = base + u * bd + (int)threadIdx.x < total
+                 ? load_word(src + (size_t)(y0 + row) * stride + x, aligned && x + 4 <= row_limit,
+                             min(4, x1 - x))
+                 : 0u;
       row += drow;
       w += dw;
       if (w >= nw) {
@@ -182,9 +182,18 @@ __device__ __forceinline__ void stage_rows(uint8_t* lds, int lp, gptr<const uint
         ++row;
       }
     }
+    row = row0;  // replay the walk for the stores: addresses are not kept in registers
+    w = w0;
 #pragma unroll
-    for (int u = 0; u < U; ++u)
-      if (off[u] >= 0) *(uint32_t*)(lds + off[u]) = v[u];
+    for (int u = 0; u < U; ++u) {
+      if (base + u * bd + (int)threadIdx.x < total) *(uint32_t*)(lds + row * lp + 4 * w) = v[u];
+      row += drow;
+      w += dw;
+      if (w >= nw) {
+        w -= nw;
+        ++row;
+      }
+    }
   }
 }
 
@@ -229,11 +238,6 @@ __device__ __forceinline__ int64_t harris_lds(const uint8_t* pix, int P, int cx,
   }
   const int64_t a = sxx, b = syy, c = sxy;
   return 25 * (a * b - c * c) - (a + b) * (a + b);
-}
-
-// Out-of-line Harris for the rare candidates beyond the per-tile score cache.
-__device__ __noinline__ int64_t harris_lds_uncached(const uint8_t* pix, int P, int cx, int cy) {
-  return harris_lds(pix, P, cx, cy);
 }
 
 // Harris R' of candidates by groups of 8 lanes: lane s < 7 of a group forms the Sobel
@@ -451,6 +455,13 @@ __global__ __launch_bounds__(1024) void k_prologue(PrologueArgs a) {
   const int64_t o_lvl = scan(s.lvl_bytes);
   const int64_t o_pyr = scan(s.pyr_blocks);
   const int64_t t_pyr = s_tot;
+  int32_t* band_base = (int32_t*)(ws + a.lay.off_band_base);
+  for (int k = 0; k < kXcds; ++k) {
+    const int32_t rows = band_row0(s.mark_ty, k + 1) - band_row0(s.mark_ty, k);
+    const int64_t o_band = scan(i < nL ? (int64_t)s.mark_tx * rows : 0);
+    if (i < nL) band_base[k * (nL + 1) + i] = (int32_t)o_band;
+    if (i == 0) band_base[k * (nL + 1) + nL] = (int32_t)s_tot;
+  }
 
   LevelPlan* plan = (LevelPlan*)(ws + a.lay.off_plan);
   int32_t* mark_base = (int32_t*)(ws + a.lay.off_mark_base);
@@ -603,7 +614,7 @@ __global__ __launch_bounds__(256) void k_pyramid_batch(KArgs a) {
 // LDS row pitch at compile time, so every circle and compass offset below is a
 // ds_read immediate.
 template <bool FUSED, int TWW>
-__global__ __launch_bounds__(256, 4) void k_mark(KArgs a) {
+__global__ __launch_bounds__(256, TWW <= 2 ? 5 : 4) void k_mark(KArgs a) {
   constexpr int TW = 64 * TWW;
   constexpr int PITCH = TW + 8;
   extern __shared__ __align__(16) uint8_t smem[];
@@ -617,19 +628,28 @@ __global__ __launch_bounds__(256, 4) void k_mark(KArgs a) {
   uint32_t* yt = (uint32_t*)(smem + M.off_yt);
   int32_t* s_base = (int32_t*)(smem + M.bytes);
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nwave = blockDim.x >> 6;
-  if (a.entry < 0) load_bases(s_base, a.mark_base, a.n_entries);
+  // XCD bands: block b runs on XCD b % kXcds and takes tile b / kXcds of band b % kXcds
+  // (the same rows of every level of every frame), so each XCD's L2 holds one band of
+  // the frames that its tiles resample from.
+  const int band = a.bands ? (int)(blockIdx.x % kXcds) : 0;
+  if (a.entry < 0)
+    load_bases(s_base, a.bands ? a.band_base + band * (a.n_entries + 1) : a.mark_base,
+               a.n_entries);
   queue_start(a, a.qctr + 0, &s_next);
 
   for (int iter = 0;; ++iter) {
-    const int g = uniform(queue_take(a, iter, &s_next));
-    if (g >= a.total) break;
+    const int g0 = uniform(queue_take(a, iter, &s_next));
+    if (g0 >= a.total) break;
+    const int g = a.bands ? g0 / kXcds : g0;
+    if (a.bands && g >= s_base[a.n_entries]) break;  // band holds fewer tiles
     lds_barrier();  // every thread has read s_next
-    const int next = queue_prefetch(a, g, a.qctr + 0);
+    const int next = queue_prefetch(a, g0, a.qctr + 0);
     const int e = a.entry >= 0 ? a.entry : uniform(find_entry(s_base, a.n_entries, g));
     const int t = a.entry >= 0 ? g : g - s_base[e];
     const LevelPlan P = a.plan[e];
     const int W = P.W, H = P.H, B = P.B;
-    const int tx = t % P.mark_tx, ty = t / P.mark_tx;
+    const int tx = t % P.mark_tx;
+    const int ty = t / P.mark_tx + (a.bands ? band_row0(P.mark_ty, band) : 0);
     const int x_t0 = tx * TW, x_t1 = min(W, x_t0 + TW);
     const int y_t0 = ty * M.th, y_t1 = min(H, y_t0 + M.th);
     const int ox = max(0, x_t0 - 4), oy = max(0, y_t0 - 3);
@@ -861,6 +881,8 @@ __global__ __launch_bounds__(256, 4) void k_detect(KArgs a) {
   uint32_t* coff = (uint32_t*)(smem + D.off_coff);
   uint32_t* cfill = (uint32_t*)(smem + D.off_cfill);
   uint32_t* ckept = (uint32_t*)(smem + D.off_ckept);
+  int64_t* cbest = (int64_t*)(smem + D.off_cbest);
+  uint32_t* cwin = (uint32_t*)(smem + D.off_cwin);
   uint8_t* lfl = smem + D.off_lfl;
   int32_t* s_base = (int32_t*)(smem + D.bytes);
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nwave = blockDim.x >> 6;
@@ -950,11 +972,15 @@ __global__ __launch_bounds__(256, 4) void k_detect(KArgs a) {
       s_ns = 0;
       s_ne = 0;
     }
+    // one survivor kept per cell: the cell's winner is found with LDS atomics
+    const bool best1 = a.cell > 0 && P.kcell == 1;
     if (a.cell > 0) {
       for (int c = tid; c < ncell; c += bd) {
         ccnt[c] = 0;
         cfill[c] = 0;
         ckept[c] = 0;
+        cbest[c] = INT64_MIN;
+        cwin[c] = kNoPos;
       }
     } else {
       for (int i = tid; i < nbx * nby; i += bd) order[i] = 0;
@@ -989,9 +1015,46 @@ __global__ __launch_bounds__(256, 4) void k_detect(KArgs a) {
       cw[i] = c;
       ucnt[i] = (uint32_t)__popc(c);
     }
-    lds_barrier();
-    block_scan_u32(ucnt, cpre, nunits, s_wsum);
-    const int ncand = (int)cpre[nunits];
+    // prefix counts of the candidate words (raster order)
+    uint32_t pre[2];
+    int ncand;
+    if (nunits <= 2 * bd) {
+      // words tid and tid + bd are in registers: one wave scan per half, one barrier
+      uint32_t inc0 = (uint32_t)__popc(cwr[0]), inc1 = (uint32_t)__popc(cwr[1]);
+#pragma unroll
+      for (int o = 1; o < 64; o <<= 1) {
+        const uint32_t t0 = __shfl_up(inc0, o, 64), t1 = __shfl_up(inc1, o, 64);
+        if (lane >= o) {
+          inc0 += t0;
+          inc1 += t1;
+        }
+      }
+      if (lane == 63) {
+        s_wsum[wave] = inc0;
+        s_wsum[8 + wave] = inc1;
+      }
+      lds_barrier();
+      uint32_t off0 = 0, off1 = 0, tot0 = 0, tot1 = 0;
+      for (int w = 0; w < nwave; ++w) {
+        const uint32_t a0 = s_wsum[w], a1 = s_wsum[8 + w];
+        off0 += w < wave ? a0 : 0u;
+        off1 += w < wave ? a1 : 0u;
+        tot0 += a0;
+        tot1 += a1;
+      }
+      pre[0] = off0 + inc0 - (uint32_t)__popc(cwr[0]);
+      pre[1] = tot0 + off1 + inc1 - (uint32_t)__popc(cwr[1]);
+      if (tid < nunits) cpre[tid] = pre[0];
+      if (bd + tid < nunits) cpre[bd + tid] = pre[1];
+      if (tid == 0) cpre[nunits] = tot0 + tot1;
+      ncand = (int)(tot0 + tot1);
+    } else {
+      lds_barrier();
+      block_scan_u32(ucnt, cpre, nunits, s_wsum);
+      ncand = (int)cpre[nunits];
+      pre[0] = tid < nunits ? cpre[tid] : 0u;
+      pre[1] = bd + tid < nunits ? cpre[bd + tid] : 0u;
+    }
 
     // 3. cached candidate positions (raster order) and their Harris scores
 #pragma unroll
@@ -999,7 +1062,7 @@ __global__ __launch_bounds__(256, 4) void k_detect(KArgs a) {
       const int i = u * bd + tid;
       uint32_t m = cwr[u];
       if (i < nunits && m) {
-        uint32_t idx = cpre[i];
+        uint32_t idx = pre[u];
         const uint32_t yx = ((uint32_t)(ry0 + vr[u]) << 16) | (uint32_t)((bw0 + vk[u]) << 5);
         for (; m && idx < (uint32_t)kCandCache; m &= m - 1u) cpos[idx++] = yx + __builtin_ctz(m);
       }
@@ -1031,9 +1094,8 @@ __global__ __launch_bounds__(256, 4) void k_detect(KArgs a) {
       return ((uint32_t)(ry0 + r) << 16) | (uint32_t)(((bw0 + k) << 5) + __builtin_ctz(m));
     };
     auto cand_score = [&](int ci, uint32_t pos) -> int64_t {
-      return ci < kCandCache ? crs[ci]
-                             : harris_lds_uncached(pix, D.pitch, (int)(pos & 0xffff) - sx0,
-                                                   (int)(pos >> 16) - sy0);
+      if (ci < kCandCache) return crs[ci];
+      return harris_lds(pix, D.pitch, (int)(pos & 0xffff) - sx0, (int)(pos >> 16) - sy0);
     };
 
     // 4. NMS: a tile candidate survives when it ranks above every candidate neighbour.
@@ -1043,7 +1105,7 @@ __global__ __launch_bounds__(256, 4) void k_detect(KArgs a) {
       if (x < vx0 || x >= vx1 || y < vy0 || y >= vy1) continue;  // ring only
       const int64_t R = cand_score(ci, pos);
       bool alive = true;
-#pragma unroll
+#pragma unroll 1
       for (int nb = 0; nb < 8; ++nb) {
         const int dx = nb < 3 ? nb - 1 : (nb < 5 ? (nb == 3 ? -1 : 1) : nb - 6);
         const int dy = nb < 3 ? -1 : (nb < 5 ? 0 : 1);
@@ -1059,8 +1121,10 @@ __global__ __launch_bounds__(256, 4) void k_detect(KArgs a) {
       }
       if (alive) {
         const int si = atomicAdd(&s_ns, 1);
+        const int c = multi ? (y / cs - cya) * nlcx + (x / cs - cxa) : 0;
         sci[si] = (uint16_t)ci;
-        if (multi) scell[si] = (uint16_t)((y / cs - cya) * nlcx + (x / cs - cxa));
+        if (multi) scell[si] = (uint16_t)c;
+        if (best1) atomicMax((long long*)&cbest[c], (long long)R);
       }
     }
     lds_barrier();
@@ -1070,6 +1134,30 @@ __global__ __launch_bounds__(256, 4) void k_detect(KArgs a) {
     //    when there are no cells.  Slots left empty get the sentinel.
     const int K = P.kcell;
     gptr<Cand> out = G(P.cand);
+    if (best1) {
+      // K = 1: among the survivors holding their cell's best R', the smallest (y, x) wins
+      for (int s = tid; s < ns; s += bd) {
+        const int ci = sci[s];
+        const uint32_t pos = cand_pos(ci);
+        const int c = multi ? scell[s] : 0;
+        if (cand_score(ci, pos) == cbest[c]) atomicMin(&cwin[c], pos);
+      }
+      lds_barrier();
+      for (int c0 = 0; c0 < ncell; c0 += bd) {
+        const int c = c0 + tid;
+        bool filled = false;
+        if (c < ncell) {
+          const int lcy = c / nlcx, lcx = c - lcy * nlcx;
+          const int slot = (cya + lcy - P.det_y0) * nvx + (cxa + lcx - P.det_x0);
+          filled = cwin[c] != kNoPos;
+          store_cand(out + slot, filled ? cbest[c] : INT64_MIN, cwin[c]);
+        }
+        const uint64_t m = __ballot(filled);
+        if (lane == 0 && m) atomicAdd(P.cand_count, (uint32_t)__popcll(m));
+      }
+      queue_park(a, next, &s_next);
+      continue;
+    }
     if (ns > 0) {
       if (a.cell > 0) {
         for (int s2 = tid; s2 < ns; s2 += bd) atomicAdd(&ccnt[multi ? scell[s2] : 0], 1u);

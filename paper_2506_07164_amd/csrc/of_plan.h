@@ -29,7 +29,13 @@ struct Tune {
   int32_t det_cx, det_cy, det_w, det_h;
   int32_t mark_grid, det_grid;
   int32_t pyr_pass;  // 1: levels are resampled by a separate pass before the segment test
+  int32_t mark_order;  // 1: segment-test tiles in XCD bands (block b on XCD b % 8)
 };
+
+constexpr int kXcds = 8;  // blocks are dispatched to the XCDs round-robin by block index
+
+// First tile row of band k when a level's mark_ty tile rows are split over the XCDs.
+OF_HD int32_t band_row0(int32_t mark_ty, int32_t k) { return (mark_ty * k) / kXcds; }
 
 // One ranked candidate: R' and (y << 16 | x) in level coordinates.
 struct Cand {
@@ -191,8 +197,10 @@ OF_HD void entry_size(const FrameGeom& g, const of_params& p, const Tune& t, int
 struct WsLayout {
   int64_t off_hdr, off_plan, off_mark_base, off_det_base, off_orient_base, off_rank_base;
   int64_t off_pyr_base;
+  int64_t off_band_base;   // kXcds prefix tables of segment-test tiles per entry, by band
   int64_t off_counters, off_flags, off_bm, off_cand, off_sel, off_lvl, total;
   int32_t n_entries, mark_tiles, det_tiles, orient_blocks, rank_slots, max_cand_cap, pyr_blocks;
+  int32_t band_tiles[kXcds];
   int64_t flag_bytes, bm_words, cand_entries, sel_entries, lvl_bytes;
 };
 
@@ -202,6 +210,8 @@ OF_HD void ws_layout_accumulate(WsLayout* w, const EntrySize& s) {
   w->det_tiles += s.det_tiles;
   w->orient_blocks += s.orient_blocks;
   w->pyr_blocks += s.pyr_blocks;
+  for (int k = 0; k < kXcds; ++k)
+    w->band_tiles[k] += s.mark_tx * (band_row0(s.mark_ty, k + 1) - band_row0(s.mark_ty, k));
   w->flag_bytes += s.flag_bytes;
   w->bm_words += s.bm_words;
   w->cand_entries += s.cand_cap;
@@ -220,6 +230,7 @@ OF_HD void ws_layout_finish(WsLayout* w) {
   w->off_orient_base = o;  o = align_up(o + 4 * ((int64_t)w->n_entries + 1), 256);
   w->off_rank_base = o;    o = align_up(o + 4 * ((int64_t)w->n_entries + 1), 256);
   w->off_pyr_base = o;     o = align_up(o + 4 * ((int64_t)w->n_entries + 1), 256);
+  w->off_band_base = o;    o = align_up(o + 4 * kXcds * ((int64_t)w->n_entries + 1), 256);
   w->off_counters = o;     o = align_up(o + 8 * (int64_t)w->n_entries, 256);
   w->off_flags = o;        o = align_up(o + w->flag_bytes, 256);
   w->off_bm = o;           o = align_up(o + 4 * w->bm_words, 256);
@@ -283,7 +294,7 @@ struct DetLds {
   int32_t nbw, nunits;       // candidate words per ring row (at most), total words
   int32_t max_surv, max_cells;
   int32_t off_cw, off_ucnt, off_cpre, off_crs, off_cpos, off_sci, off_scell, off_order, off_ccnt,
-      off_coff, off_cfill, off_ckept, off_lfl, bytes;
+      off_coff, off_cfill, off_ckept, off_cbest, off_cwin, off_lfl, bytes;
 };
 
 OF_HD DetLds det_lds(const Tune& t, int32_t cell) {
@@ -317,6 +328,8 @@ OF_HD DetLds det_lds(const Tune& t, int32_t cell) {
   d.off_coff = o;   o += (int32_t)align_up(4 * d.max_cells, 16);
   d.off_cfill = o;  o += (int32_t)align_up(4 * d.max_cells, 16);
   d.off_ckept = o;  o += (int32_t)align_up(4 * d.max_cells, 16);
+  d.off_cbest = o;  o += (int32_t)align_up(8 * d.max_cells, 16);   // K = 1: best R' per cell
+  d.off_cwin = o;   o += (int32_t)align_up(4 * d.max_cells, 16);   // K = 1: its position
   const int32_t nfl = cell > 0 ? (t.det_cx + 2) * (t.det_cy + 2) : 4;  // cells of the ring
   d.off_lfl = o;    o += (int32_t)align_up(nfl, 16);
   d.bytes = o;      // + the entry base table of the launch

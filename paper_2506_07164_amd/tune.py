@@ -18,7 +18,7 @@ CACHE = os.environ.get("OF_TUNE_CACHE", os.path.join(os.path.dirname(os.path.abs
                                                       "tune_cache.json"))
 
 FIELDS = ("mark_words", "mark_rows", "det_cells_x", "det_cells_y", "det_w", "det_h",
-          "mark_grid", "det_grid", "pyr_pass")
+          "mark_grid", "det_grid", "pyr_pass", "mark_order")
 
 
 def _key(shapes, p, device_name):
@@ -46,15 +46,17 @@ def time_tuning(det, frames, tune, calls=20, warmup=3):
 
 
 def candidates(p, n_cus):
-    marks = [dict(mark_words=w, mark_rows=r) for w in (1, 2, 4) for r in (8, 16, 32)
-             if w * r <= 96]
+    marks = [dict(mark_words=w, mark_rows=r) for w in (1, 2, 4) for r in (8, 16, 24, 32, 48)
+             if 16 <= w * r <= 128]
     if p.cell > 0:
         dets = [dict(det_cells_x=cx, det_cells_y=cy) for cx, cy in
                 ((1, 1), (2, 1), (4, 1), (2, 2), (8, 1), (4, 2))
                 if cx * p.cell <= 256 and cy * p.cell <= 128]
     else:
         dets = [dict(det_w=w, det_h=h) for w, h in ((64, 32), (128, 32), (128, 64), (256, 32))]
-    grids = [dict(mark_grid=0, det_grid=0, pyr_pass=0), dict(mark_grid=0, det_grid=0, pyr_pass=1)]
+    grids = [dict(mark_grid=0, det_grid=0, pyr_pass=0, mark_order=0),
+             dict(mark_grid=0, det_grid=0, pyr_pass=0, mark_order=1),
+             dict(mark_grid=0, det_grid=0, pyr_pass=1, mark_order=1)]
     grids += [dict(mark_grid=m * n_cus, det_grid=d * n_cus) for m, d in ((2, 2), (4, 3))]
     return marks, dets, grids
 

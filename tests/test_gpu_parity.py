@@ -217,7 +217,9 @@ def test_c2_plain_and_fused(hip):
                                   dict(mark_words=2, mark_rows=64, det_cells_x=8, det_cells_y=1),
                                   dict(det_cells_x=1, det_cells_y=1, mark_grid=7, det_grid=3),
                                   dict(pyr_pass=1), dict(pyr_pass=1, mark_words=1, mark_rows=8,
-                                                         mark_grid=64)])
+                                                         mark_grid=64),
+                                  dict(mark_order=1), dict(mark_order=1, mark_words=2, mark_rows=48),
+                                  dict(mark_order=1, mark_words=3, mark_rows=5, pyr_pass=1)])
 def test_c2_tunings_agree(hip, tune):
     spec = CONFIGS["c2"]["frames"][0]
     kw = CONFIGS["c2"]["params"]
@@ -266,6 +268,10 @@ def test_c3_batch(hip):
     res = run_batch(hip, imgs, kw, hip.tuning(pyr_pass=1))
     for i, (g, r) in enumerate(zip(res, refs)):
         assert_same_keypoints(g, r, f"c3 frame {i} (pyramid pass)")
+    log("case: c3 batch, XCD-band tile order")
+    res = run_batch(hip, imgs, kw, hip.tuning(mark_order=1))
+    for i, (g, r) in enumerate(zip(res, refs)):
+        assert_same_keypoints(g, r, f"c3 frame {i} (bands)")
 
 
 def test_c4_batch(hip):
