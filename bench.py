@@ -22,9 +22,17 @@ import hashlib
 
 # int32 VALU peak: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz (one op per lane per clock).
 ALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
-# Algorithmic integer ops: 11 per resampled pixel (four Q8 taps, one rounding) and 32 per
-# segment-tested pixel (each circle pixel against I_p - t and I_p + t, Eq. 1).
+# Algorithmic integer ops per unit of each step:
+#  resample: 11 per level pixel (four Q8 taps, one rounding);
+#  segment test: 32 per tested pixel (each circle pixel against I_p - t and I_p + t, Eq. 1);
+#  Harris + NMS: per FAST candidate, Sobel G_x and G_y (6 ops each) and the three
+#    products accumulated (6) at the 49 window pixels, R' (8), and 8 neighbour compares (3);
+#  orientation: per kept keypoint, dx*I and dy*I accumulated over the 709-pixel disk.
 OPS_RESAMPLE, OPS_SEGMENT = 11, 32
+OPS_HARRIS_NMS = 49 * 18 + 8 + 8 * 3
+OPS_ORIENT = 709 * 4
+STEP_KERNELS = {"pyramid": "k_pyramid_batch", "segment_test": "k_mark",
+                "harris_nms_cells": "k_detect", "select": "k_select_orient"}
 
 
 def level_work(shapes, p):
@@ -43,7 +51,8 @@ def level_work(shapes, p):
 
 
 KERNEL_SOURCES = ("paper_2506_07164_amd/csrc/of_kernels.hip", "paper_2506_07164_amd/csrc/of_plan.h")
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_mark_fused_1080p_8level_traffic.txt")
+def traffic_file(kernel):
+    return os.path.join(ROOT, "profiles", f"{kernel}_1080p_8level_traffic.txt")
 COPY_MIB = 256
 PROFILE_REPEAT = 10
 
@@ -56,16 +65,18 @@ def kernel_source_hash():
     return h.hexdigest()[:16]
 
 
-def measured_traffic():
-    """HBM bytes per launch of the segment-test kernel from the committed counter summary
-    (FETCH_SIZE + WRITE_SIZE, each scaled by the same counter on a plain copy), or None
-    when the kernel sources changed since the counters were taken."""
+def measured_traffic(kernel, tuning):
+    """HBM bytes per launch of `kernel` from the committed counter summary (FETCH_SIZE +
+    WRITE_SIZE, each scaled by the same counter on a plain copy), or None when the
+    kernel sources or the launch shape changed since the counters were taken."""
     try:
-        with open(TRAFFIC_FILE) as fh:
+        with open(traffic_file(kernel)) as fh:
             kv = dict(l.strip().split("=", 1) for l in fh if "=" in l and not l.startswith("#"))
     except OSError:
         return None
     if kv.get("kernel_src_sha") != kernel_source_hash():
+        return None
+    if kv.get("tuning") != json.dumps(tuning, sort_keys=True):
         return None
     return int(float(kv["traffic_bytes_per_launch"]))
 
@@ -105,9 +116,14 @@ def main():
     ap.add_argument("--warmup", type=int, default=50)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-tune", action="store_true", help="library default launch shape")
+    ap.add_argument("--tuning", type=str, default=None,
+                    help="launch shape as JSON (of_tuning fields), instead of the autotuner")
     ap.add_argument("--tune-verbose", action="store_true")
+    ap.add_argument("--retune", action="store_true", help="search again, ignoring stored results")
     ap.add_argument("--no-batched", action="store_true", help="skip the 16-frame batched figure")
     ap.add_argument("--no-serve", action="store_true", help="skip the served (32-stream) figure")
+    ap.add_argument("--no-plain", action="store_true",
+                    help="skip the plain path (profiles of the fused kernels alone)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help=f"only run a {COPY_MIB} MiB device copy (counter calibration)")
     args = ap.parse_args()
@@ -139,9 +155,11 @@ def main():
 
     # launch shape of the fused path from the autotuner (outside the timed region)
     tune_fields = None
-    if not args.no_tune:
+    if args.tuning:
+        tune_fields = {k: int(v) for k, v in json.loads(args.tuning).items()}
+    elif not args.no_tune:
         from paper_2506_07164_amd.tune import autotune
-        tune_fields = autotune([frame], p, verbose=args.tune_verbose)
+        tune_fields = autotune([frame], p, use_cache=not args.retune, verbose=args.tune_verbose)
         print(f"# tuning {tune_fields}", file=sys.stderr, flush=True)
     tune = ofhip.tuning(**tune_fields) if tune_fields else None
 
@@ -149,7 +167,8 @@ def main():
     with torch.cuda.stream(stream):
         for _ in range(max(1, args.warmup)):
             fused.detect_batch([frame], tune=tune, stream=stream)
-            plain.detect_plain(frame, stream=stream)
+            if not args.no_plain:
+                plain.detect_plain(frame, stream=stream)
     torch.cuda.synchronize()
     graph = torch.cuda.CUDAGraph()
     with torch.cuda.stream(stream):
@@ -181,14 +200,16 @@ def main():
 
     # timed: plain path, eager launches
     Kp = max(1, K // 4)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    with torch.cuda.stream(stream):
-        for _ in range(Kp):
-            plain.detect_plain(frame, stream=stream)
-    torch.cuda.synchronize()
-    t_plain = time.perf_counter() - t0
-    print(f"# plain {Kp} steps {t_plain * 1e3:.1f} ms", file=sys.stderr, flush=True)
+    t_plain = None
+    if not args.no_plain:
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        with torch.cuda.stream(stream):
+            for _ in range(Kp):
+                plain.detect_plain(frame, stream=stream)
+        torch.cuda.synchronize()
+        t_plain = time.perf_counter() - t0
+        print(f"# plain {Kp} steps {t_plain * 1e3:.1f} ms", file=sys.stderr, flush=True)
 
     # per-step kernel durations: HIP events on the launching stream; repeatable launches
     # (segment test, selection) are issued PROFILE_REPEAT times back to back between
@@ -207,10 +228,11 @@ def main():
 
     # correctness of what was timed: same keypoints from both paths
     got_f = fused.results()[0]
-    got_p = plain.results()[0]
-    assert len(got_f) == len(got_p) == kw["n_features"]
-    for k in ("x", "y", "level", "score", "m10", "m01"):
-        assert np.array_equal(got_f[k], got_p[k]), k
+    assert len(got_f) == kw["n_features"]
+    if not args.no_plain:
+        got_p = plain.results()[0]
+        for k in ("x", "y", "level", "score", "m10", "m01"):
+            assert np.array_equal(got_f[k], got_p[k]), k
 
     # batched form: 16 copies of the frame (distinct buffers) in one call, graph replays
     batched = None
@@ -261,16 +283,29 @@ def main():
             served["runs"].append(row)
         print(f"# served {served['runs']}", file=sys.stderr, flush=True)
 
+    # algorithmic work of each step launch, the dominant (longest) step's roofline
     res_px, seg_px = level_work([img.shape], p)
-    t_mark = step_us["segment_test"] * 1e-6
-    ops = OPS_RESAMPLE * res_px + OPS_SEGMENT * seg_px
-    achieved = ops / t_mark / 1e12 if t_mark > 0 else 0.0
-    roofline = {"bound": "alu", "achieved": round(achieved, 3), "peak": round(ALU_PEAK_TOPS, 2),
-                "unit": "TOP/s", "frac": round(achieved / ALU_PEAK_TOPS, 4),
-                "traffic": measured_traffic(),
-                "kernel": "k_mark<true,4> (pyramid resample + segment test, all levels)",
-                "kernel_us": round(step_us["segment_test"], 3),
-                "kernel_src_sha": kernel_source_hash()}
+    cands = int(fused.candidates([frame]).sum())
+    eff = ofhip.of_tuning_default([ofhip.image_of(frame)], p) if tune is None else tune
+    split = bool(eff.pyr_pass)
+    step_ops = {"pyramid": OPS_RESAMPLE * res_px if split else 0,
+                "segment_test": OPS_SEGMENT * seg_px + (0 if split else OPS_RESAMPLE * res_px),
+                "harris_nms_cells": OPS_HARRIS_NMS * cands,
+                "select": OPS_ORIENT * int(len(got_f))}
+    steps = {}
+    for k, ops in step_ops.items():
+        us = step_us.get(k, 0.0)
+        if us > 0 and ops > 0:
+            tops = ops / (us * 1e-6) / 1e12
+            steps[k] = {"kernel": STEP_KERNELS[k], "us": round(us, 3), "ops": ops,
+                        "tops": round(tops, 3), "frac": round(tops / ALU_PEAK_TOPS, 4)}
+    dom = max(steps, key=lambda k: steps[k]["us"])
+    roofline = {"bound": "alu", "achieved": steps[dom]["tops"], "peak": round(ALU_PEAK_TOPS, 2),
+                "unit": "TOP/s", "frac": steps[dom]["frac"],
+                "traffic": measured_traffic(STEP_KERNELS[dom], tune_fields),
+                "kernel": STEP_KERNELS[dom], "kernel_us": steps[dom]["us"],
+                "kernel_src_sha": kernel_source_hash(), "steps": steps,
+                "fast_candidates": cands}
 
     mode = "graph" if t_fused <= t_fused_eager else "eager"
     t_best = min(t_fused, t_fused_eager)
@@ -292,7 +327,7 @@ def main():
                                "30x30 cell, 2000 keypoints, fused path",
                    "frames_per_step": 1, "launch": mode},
         "fused_fps": {"graph": round(K / t_fused, 1), "eager": round(K / t_fused_eager, 1)},
-        "plain_fps": round(Kp / t_plain, 1),
+        "plain_fps": round(Kp / t_plain, 1) if t_plain else None,
         "batched": batched,
         "served": served,
         "tuning": tune_fields,

@@ -146,6 +146,14 @@ int of_detect_batch(const of_image* frames, int32_t n, const of_params* params, 
 int of_tuning_default(const of_image* frames, int32_t n, const of_params* params,
                       of_tuning* out);
 
+/* Statistics of the last detection on `ws` (same frames and params as that call):
+ * copies, on `stream`, the number of FAST candidates of every (frame, level) -- pixels
+ * of the valid region that pass the segment test (Sec. 3.1, Eq. 1) at their cell's
+ * threshold -- to `out` (device int32, n * n_levels, frame-major).  Enqueue it after
+ * the detection on the same stream.  OF_EINVAL on bad arguments. */
+int of_candidate_counts(const of_image* frames, int32_t n, const of_params* params,
+                        const void* ws, int32_t* out, hipStream_t stream);
+
 /* Test entry point for the segment test alone: for each of n pixels, `circles` holds 17
  * bytes (the centre, then circle positions 1..16 clockwise from the top) and out[i]
  * gets bit 0 = corner at t_lo, bit 1 = corner at t_hi.  Device pointers. */
@@ -153,7 +161,8 @@ int of_test_segment(const uint8_t* circles, int32_t n, int32_t t_lo, int32_t t_h
                     uint8_t* out, hipStream_t stream);
 
 /* Step timing.  While enabled (host call, not during graph capture), of_detect and
- * of_detect_batch record a HIP event on their stream before and after each step launch:
+ * of_detect_batch attach two HIP events to each step launch's dispatch on their stream,
+ * recorded as the kernel begins and as it ends:
  * step 0 prologue, 1 pyramid, 2 segment test, 3 Harris/NMS/cells, 4 level selection,
  * 5 orientation.  of_profile_read waits for the recorded events, writes the summed
  * milliseconds and launch counts of the first n steps (host arrays) and clears them.

@@ -31,10 +31,10 @@ struct Profiler {
 
 Profiler g_prof;
 
-// Runs `launch` between two events when profiling is on.  A repeatable launch (one
-// that gives the same results when issued again: it neither accumulates nor draws from
-// a queue) is issued `repeat` times back to back, so the events measure the kernel and
-// not the event overhead.
+// Runs `launch` with profiling events attached to its dispatch (start as the kernel
+// begins, stop as it ends).  A repeatable launch (one that gives the same results when
+// issued again: it neither accumulates nor draws from a queue) is issued `repeat` times
+// back to back, start on the first dispatch and stop on the last.
 template <class F>
 hipError_t timed(int step, hipStream_t s, F&& launch, bool repeatable = false) {
   if (!g_prof.on) return launch();
@@ -44,11 +44,14 @@ hipError_t timed(int step, hipStream_t s, F&& launch, bool repeatable = false) {
   if (g_prof.used >= kEventPool) return launch();
   const int k = g_prof.used++;
   g_prof.step_of[k] = step;
-  hipError_t e = hipEventRecord(g_prof.ev[2 * k], s);
-  if (e != hipSuccess) return e;
-  for (int r = 0; r < times && e == hipSuccess; ++r) e = launch();
-  if (e != hipSuccess) return e;
-  return hipEventRecord(g_prof.ev[2 * k + 1], s);
+  hipError_t e = hipSuccess;
+  for (int r = 0; r < times && e == hipSuccess; ++r) {
+    set_launch_events(r == 0 ? g_prof.ev[2 * k] : nullptr,
+                      r == times - 1 ? g_prof.ev[2 * k + 1] : nullptr);
+    e = launch();
+  }
+  set_launch_events(nullptr, nullptr);
+  return e;
 }
 
 int hip_fail(hipError_t e) {
@@ -449,6 +452,21 @@ int of_detect_batch(const of_image* frames, int32_t n, const of_params* params, 
   }
   if (e == hipSuccess) e = launch_selection(k, c->lay, stream);
   delete c;
+  return e == hipSuccess ? OF_OK : hip_fail(e);
+}
+
+int of_candidate_counts(const of_image* frames, int32_t n, const of_params* params,
+                        const void* ws, int32_t* out, hipStream_t stream) {
+  int st = check_frames(frames, n, params);
+  if (st) return st;
+  if (!ws || !out) return OF_EINVAL;
+  CallPlan* c = new CallPlan;
+  plan_call(frames, n, *params, default_tune(*params), c);
+  const int64_t off = c->lay.off_counters + 8 * (int64_t)c->lay.n_entries;
+  const size_t bytes = 4 * (size_t)c->lay.n_entries;
+  delete c;
+  hipError_t e = hipMemcpyAsync(out, (const uint8_t*)ws + off, bytes, hipMemcpyDeviceToDevice,
+                                stream);
   return e == hipSuccess ? OF_OK : hip_fail(e);
 }
 

@@ -55,6 +55,14 @@ struct PyrArgs {
   PyrLevel lv[kMaxLevels];
 };
 
+struct LaunchEvents {
+  hipEvent_t start, stop;
+};
+
+// The next launch records `start` as it begins and `stop` as it ends (either may be
+// null); later launches record nothing.
+void set_launch_events(hipEvent_t start, hipEvent_t stop);
+
 hipError_t launch_prologue(const PrologueArgs& a, int grid, hipStream_t s);
 hipError_t launch_pyramid(const PyrArgs& a, int n_levels, int max_w, int max_h, hipStream_t s);
 hipError_t launch_pyramid_batch(const KArgs& a, int blocks, hipStream_t s);

@@ -14,6 +14,8 @@
 // Wave64 throughout; nothing here is a dense contraction, so there is no MFMA use.
 #include <hip/hip_runtime.h>
 
+#include <hip/hip_ext.h>
+
 #include "of_kernels.h"
 
 namespace ofk {
@@ -397,7 +399,7 @@ __global__ __launch_bounds__(1024) void k_prologue(PrologueArgs a) {
   uint64_t* sig = (uint64_t*)(ws + a.lay.off_hdr + 128);
   {
     uint32_t* counters = (uint32_t*)(ws + a.lay.off_counters);
-    const int64_t ncnt = 2 * (int64_t)a.lay.n_entries;
+    const int64_t ncnt = 3 * (int64_t)a.lay.n_entries;
     uint4* fl = (uint4*)(ws + a.lay.off_flags);
     const int64_t nq = a.lay.flag_bytes / 16;
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
@@ -510,6 +512,7 @@ __global__ __launch_bounds__(1024) void k_prologue(PrologueArgs a) {
     P.slot_w = s.slot_w;
     P.sel = (Cand*)(ws + a.lay.off_sel) + o_sel;
     P.sel_count = counters + a.lay.n_entries + i;
+    P.ncand_count = counters + 2 * a.lay.n_entries + i;
     P.mark_tx = s.mark_tx;
     P.mark_ty = s.mark_ty;
     P.det_tx = s.det_tx;
@@ -864,7 +867,7 @@ __device__ __forceinline__ uint32_t candidate_word(uint32_t lo, uint32_t hi, int
 // candidate neighbours, and the per-cell best are written to the cells' fixed slots.
 __global__ __launch_bounds__(256, 4) void k_detect(KArgs a) {
   extern __shared__ __align__(16) uint8_t smem[];
-  __shared__ int s_next, s_ns, s_ne;
+  __shared__ int s_next, s_ns, s_ne, s_nin;
   __shared__ uint32_t s_wsum[16];
   const DetLds D = det_lds(a.t, a.cell);
   uint8_t* pix = smem;
@@ -971,6 +974,7 @@ __global__ __launch_bounds__(256, 4) void k_detect(KArgs a) {
     if (tid == 0) {
       s_ns = 0;
       s_ne = 0;
+      s_nin = 0;
     }
     // one survivor kept per cell: the cell's winner is found with LDS atomics
     const bool best1 = a.cell > 0 && P.kcell == 1;
@@ -1099,10 +1103,19 @@ __global__ __launch_bounds__(256, 4) void k_detect(KArgs a) {
     };
 
     // 4. NMS: a tile candidate survives when it ranks above every candidate neighbour.
-    for (int ci = tid; ci < ncand; ci += bd) {
-      const uint32_t pos = cand_pos(ci);
+    for (int ci0 = 0; ci0 < ncand; ci0 += bd) {
+      const int ci = ci0 + tid;
+      uint32_t pos = 0;
+      bool inside = false;
+      if (ci < ncand) {
+        pos = cand_pos(ci);
+        const int x = (int)(pos & 0xffff), y = (int)(pos >> 16);
+        inside = x >= vx0 && x < vx1 && y >= vy0 && y < vy1;  // not the ring
+      }
+      const uint64_t im = __ballot(inside);
+      if (lane == 0 && im) atomicAdd(&s_nin, (int)__popcll(im));
+      if (!inside) continue;
       const int x = (int)(pos & 0xffff), y = (int)(pos >> 16);
-      if (x < vx0 || x >= vx1 || y < vy0 || y >= vy1) continue;  // ring only
       const int64_t R = cand_score(ci, pos);
       bool alive = true;
 #pragma unroll 1
@@ -1129,6 +1142,7 @@ __global__ __launch_bounds__(256, 4) void k_detect(KArgs a) {
     }
     lds_barrier();
     const int ns = s_ns;
+    if (tid == 0 && s_nin > 0) atomicAdd(P.ncand_count, (uint32_t)s_nin);
     // 5. per-cell top-K (K = quota when the whole level is one cell), written to fixed
     //    slots: K' = min(K, survivors a cell can hold) per cell, or one per 2x2 block
     //    when there are no cells.  Slots left empty get the sentinel.
@@ -1506,28 +1520,45 @@ __global__ __launch_bounds__(256) void k_test_segment(const uint8_t* circles, in
 
 // ----------------------------------------------------------------- launches --
 
+// Events attached to the next launch (profiling): recorded by the dispatch itself, so
+// they time the kernel alone.
+thread_local LaunchEvents g_launch_ev;
+
+void set_launch_events(hipEvent_t start, hipEvent_t stop) { g_launch_ev = {start, stop}; }
+
+#define OF_LAUNCH(KERNEL, GRID, BLOCK, SHMEM, STREAM, ...)                                   \
+  do {                                                                                      \
+    if (g_launch_ev.start || g_launch_ev.stop) {                                            \
+      hipExtLaunchKernelGGL(KERNEL, GRID, BLOCK, SHMEM, STREAM, g_launch_ev.start,          \
+                            g_launch_ev.stop, 0, __VA_ARGS__);                              \
+      g_launch_ev = {};                                                                     \
+    } else {                                                                                \
+      hipLaunchKernelGGL(KERNEL, GRID, BLOCK, SHMEM, STREAM, __VA_ARGS__);                  \
+    }                                                                                       \
+  } while (0)
+
 hipError_t launch_prologue(const PrologueArgs& a, int grid, hipStream_t s) {
-  hipLaunchKernelGGL(k_prologue, dim3(grid), dim3(1024), 0, s, a);
+  OF_LAUNCH(k_prologue, dim3(grid), dim3(1024), 0, s, a);
   return hipGetLastError();
 }
 
 hipError_t launch_pyramid(const PyrArgs& a, int n_levels, int max_w, int max_h, hipStream_t s) {
   dim3 grid(cdiv(max_w, 64), cdiv(max_h, 16), n_levels);
-  hipLaunchKernelGGL(k_pyramid, grid, dim3(256), 0, s, a);
+  OF_LAUNCH(k_pyramid, grid, dim3(256), 0, s, a);
   return hipGetLastError();
 }
 
 hipError_t launch_pyramid_batch(const KArgs& a, int blocks, hipStream_t s) {
-  hipLaunchKernelGGL(k_pyramid_batch, dim3(blocks), dim3(256), 0, s, a);
+  OF_LAUNCH(k_pyramid_batch, dim3(blocks), dim3(256), 0, s, a);
   return hipGetLastError();
 }
 
 template <int TWW>
 void launch_mark_w(const KArgs& a, bool fused, int grid, int bytes, hipStream_t s) {
   if (fused)
-    hipLaunchKernelGGL((k_mark<true, TWW>), dim3(grid), dim3(256), bytes, s, a);
+    OF_LAUNCH((k_mark<true, TWW>), dim3(grid), dim3(256), bytes, s, a);
   else
-    hipLaunchKernelGGL((k_mark<false, TWW>), dim3(grid), dim3(256), bytes, s, a);
+    OF_LAUNCH((k_mark<false, TWW>), dim3(grid), dim3(256), bytes, s, a);
 }
 
 hipError_t launch_mark(const KArgs& a, bool fused, int grid, hipStream_t s) {
@@ -1543,28 +1574,28 @@ hipError_t launch_mark(const KArgs& a, bool fused, int grid, hipStream_t s) {
 
 hipError_t launch_detect(const KArgs& a, int grid, hipStream_t s) {
   const int bytes = det_lds(a.t, a.cell).bytes + base_table_bytes(a.n_entries);
-  hipLaunchKernelGGL(k_detect, dim3(grid), dim3(256), bytes, s, a);
+  OF_LAUNCH(k_detect, dim3(grid), dim3(256), bytes, s, a);
   return hipGetLastError();
 }
 
 hipError_t launch_select_orient(const KArgs& a, int slots, hipStream_t s) {
-  hipLaunchKernelGGL(k_select_orient, dim3(cdiv(slots, 4)), dim3(256), 0, s, a);
+  OF_LAUNCH(k_select_orient, dim3(cdiv(slots, 4)), dim3(256), 0, s, a);
   return hipGetLastError();
 }
 
 hipError_t launch_select(const KArgs& a, int grid, hipStream_t s) {
-  hipLaunchKernelGGL(k_select, dim3(grid), dim3(1024), 0, s, a);
+  OF_LAUNCH(k_select, dim3(grid), dim3(1024), 0, s, a);
   return hipGetLastError();
 }
 
 hipError_t launch_orient(const KArgs& a, int grid, hipStream_t s) {
-  hipLaunchKernelGGL(k_orient, dim3(grid), dim3(256), 0, s, a);
+  OF_LAUNCH(k_orient, dim3(grid), dim3(256), 0, s, a);
   return hipGetLastError();
 }
 
 hipError_t launch_test_segment(const uint8_t* circles, int n, int t_lo, int t_hi, uint8_t* out,
                                hipStream_t s) {
-  hipLaunchKernelGGL(k_test_segment, dim3(cdiv(n, 256)), dim3(256), 0, s, circles, n, t_lo, t_hi,
+  OF_LAUNCH(k_test_segment, dim3(cdiv(n, 256)), dim3(256), 0, s, circles, n, t_lo, t_hi,
                      out);
   return hipGetLastError();
 }

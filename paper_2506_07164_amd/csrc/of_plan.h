@@ -65,6 +65,7 @@ struct LevelPlan {
   int32_t kslot;               // slots per cell (cell > 0)
   Cand* sel;                   // level selection, sorted, quota entries
   uint32_t* sel_count;
+  uint32_t* ncand_count;       // FAST candidates of the level (statistics)
   int32_t mark_tx, mark_ty;    // segment-test tile grid (covers the whole level)
   int32_t det_tx, det_ty;      // Harris/NMS tile grid (covers the valid region)
   int32_t det_x0, det_y0;      // first cell column/row (cell > 0) or first pixel (cell == 0)
@@ -231,7 +232,8 @@ OF_HD void ws_layout_finish(WsLayout* w) {
   w->off_rank_base = o;    o = align_up(o + 4 * ((int64_t)w->n_entries + 1), 256);
   w->off_pyr_base = o;     o = align_up(o + 4 * ((int64_t)w->n_entries + 1), 256);
   w->off_band_base = o;    o = align_up(o + 4 * kXcds * ((int64_t)w->n_entries + 1), 256);
-  w->off_counters = o;     o = align_up(o + 8 * (int64_t)w->n_entries, 256);
+  // counters per entry: filled candidate slots, selected (radix path), FAST candidates
+  w->off_counters = o;     o = align_up(o + 12 * (int64_t)w->n_entries, 256);
   w->off_flags = o;        o = align_up(o + w->flag_bytes, 256);
   w->off_bm = o;           o = align_up(o + 4 * w->bm_words, 256);
   w->off_cand = o;         o = align_up(o + (int64_t)sizeof(Cand) * w->cand_entries, 256);

@@ -75,6 +75,7 @@ def lib() -> ctypes.CDLL:
                                       i64p, i32, vp, P(OfTuning), vp]
         L.of_tuning_default.argtypes = [P(OfImage), i32, P(OfParams), P(OfTuning)]
         L.of_test_segment.argtypes = [vp, i32, i32, i32, vp, vp]
+        L.of_candidate_counts.argtypes = [P(OfImage), i32, P(OfParams), vp, vp, vp]
         L.of_profile_enable.argtypes = [ctypes.c_int]
         L.of_profile_read.argtypes = [P(ctypes.c_double), i64p, i32]
         L.of_status_string.argtypes = [ctypes.c_int]
@@ -162,6 +163,13 @@ def of_detect_batch(images, p: OfParams, ws_ptr: int, ws_bytes: int, out_ptr: in
            "of_detect_batch")
 
 
+def of_candidate_counts(images, p: OfParams, ws_ptr: int, out_ptr: int, stream: int) -> None:
+    n = len(images)
+    arr = (OfImage * n)(*images)
+    _check(lib().of_candidate_counts(arr, n, ctypes.byref(p), ws_ptr, out_ptr, stream),
+           "of_candidate_counts")
+
+
 def of_test_segment(circles_ptr: int, n: int, t_lo: int, t_hi: int, out_ptr: int,
                     stream: int) -> None:
     _check(lib().of_test_segment(circles_ptr, n, t_lo, t_hi, out_ptr, stream), "of_test_segment")
@@ -242,6 +250,14 @@ class Detector:
         of_detect_batch([image_of(f) for f in frames], self.p, self.ws.data_ptr(),
                         self.ws.numel(), self.out.data_ptr(), self.offsets, self.cap,
                         self.counts.data_ptr(), tune, stream_ptr(stream))
+
+    def candidates(self, frames, stream=None):
+        """FAST candidates per (frame, level) of the last detection (synchronises)."""
+        torch = _torch()
+        out = torch.zeros(self.n * self.p.n_levels, dtype=torch.int32, device=self.ws.device)
+        of_candidate_counts([image_of(f) for f in frames], self.p, self.ws.data_ptr(),
+                            out.data_ptr(), stream_ptr(stream))
+        return out.cpu().numpy().reshape(self.n, self.p.n_levels)
 
     def results(self):
         """Per frame, a structured numpy array of its keypoints (synchronises)."""

@@ -16,6 +16,9 @@ from . import ofhip
 
 CACHE = os.environ.get("OF_TUNE_CACHE", os.path.join(os.path.dirname(os.path.abspath(__file__)),
                                                       "tune_cache.json"))
+# Results of this tuner shipped with the library for known devices and workloads,
+# consulted after the local cache.
+SHIPPED = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tuned.json")
 
 FIELDS = ("mark_words", "mark_rows", "det_cells_x", "det_cells_y", "det_w", "det_h",
           "mark_grid", "det_grid", "pyr_pass", "mark_order")
@@ -61,21 +64,33 @@ def candidates(p, n_cus):
     return marks, dets, grids
 
 
-def autotune(frames, p, calls=20, use_cache=True, verbose=False):
-    """Best tuning (as a dict of of_tuning fields) for these frames and parameters."""
+def device_key():
+    """Architecture and compute-unit count of device 0, e.g. 'gfx950/256'."""
     import torch
-    name = torch.cuda.get_device_name()
+    prop = torch.cuda.get_device_properties(0)
+    return f"{prop.gcnArchName.split(':')[0]}/{prop.multi_processor_count}"
+
+
+def autotune(frames, p, calls=20, use_cache=True, verbose=False):
+    """Best tuning (as a dict of of_tuning fields) for these frames and parameters:
+    from the local cache, else from the shipped results, else searched.  The result of
+    a search is written to the local cache (also when use_cache is False)."""
+    import torch
+    name = device_key()
     shapes = [tuple(f.shape) for f in frames]
     key = _key(shapes, p, name)
     cache = {}
-    if use_cache and os.path.exists(CACHE):
-        try:
-            with open(CACHE) as fh:
-                cache = json.load(fh)
-        except (OSError, ValueError):
-            cache = {}
-        if key in cache:
-            return cache[key]["tuning"]
+    if use_cache:
+        for path in (CACHE, SHIPPED):
+            try:
+                with open(path) as fh:
+                    found = json.load(fh)
+            except (OSError, ValueError):
+                continue
+            if path == CACHE:
+                cache = found
+            if key in found:
+                return found[key]["tuning"]
     n_cus = torch.cuda.get_device_properties(0).multi_processor_count
     det = ofhip.Detector(shapes, p)
     best = {}
@@ -104,10 +119,15 @@ def autotune(frames, p, calls=20, use_cache=True, verbose=False):
                 best_ms = ms
                 best.update(upd)
     result = {"tuning": best, "ms": best_ms, "trials": len(log)}
-    if use_cache:
-        cache[key] = result
-        tmp = CACHE + ".tmp%d" % os.getpid()
-        with open(tmp, "w") as fh:
-            json.dump(cache, fh, indent=1)
-        os.replace(tmp, CACHE)
+    if not use_cache:
+        try:
+            with open(CACHE) as fh:
+                cache = json.load(fh)
+        except (OSError, ValueError):
+            cache = {}
+    cache[key] = result
+    tmp = CACHE + ".tmp%d" % os.getpid()
+    with open(tmp, "w") as fh:
+        json.dump(cache, fh, indent=1)
+    os.replace(tmp, CACHE)
     return best

@@ -328,3 +328,25 @@ def test_graph_replay(hip):
         for k, i in enumerate(pair):
             assert_same_keypoints(res[k], refs[i], f"replay {rep} slot {k}")
         del x
+
+
+@pytest.mark.parametrize("which", ["c2", "cell0"])
+def test_candidate_counts_match_oracle(hip, which):
+    """FAST candidates per level (pixels of the valid region passing the segment test at
+    their cell's threshold), read back with of_candidate_counts, equal the oracle's."""
+    if which == "c2":
+        spec, kw = CONFIGS["c2"]["frames"][0], CONFIGS["c2"]["params"]
+    else:
+        spec, kw = FrameSpec(641, 479, 5, 60, 2.0, texture_amp=6), \
+            _kw(n_levels=3, cell=0, fast_t=8, fast_t_min=8, n_features=400)
+    log(f"case: candidate counts {which}")
+    img = make_frame(spec)
+    p = oracle.params(**kw)
+    want = [int(oracle.level_detect(lvl, p, level=l)["cand"].sum())
+            for l, lvl in enumerate(oracle.pyramid(img, p))]
+    frame = torch.from_numpy(img).cuda()
+    det = hip.Detector([img.shape], hip.params(**kw))
+    det.detect_batch([frame])
+    assert det.candidates([frame])[0].tolist() == want
+    det.detect_plain(frame)
+    assert det.candidates([frame])[0].tolist() == want
