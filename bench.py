@@ -122,6 +122,10 @@ def main():
     ap.add_argument("--retune", action="store_true", help="search again, ignoring stored results")
     ap.add_argument("--no-batched", action="store_true", help="skip the 16-frame batched figure")
     ap.add_argument("--no-serve", action="store_true", help="skip the served (32-stream) figure")
+    ap.add_argument("--no-configs", action="store_true",
+                    help="skip the 64-frame mixed and 16 x 4K batched figures")
+    ap.add_argument("--no-patterns", action="store_true",
+                    help="skip the Fig. 6/7 pattern benchmark (1024x1024, 625 copies per case)")
     ap.add_argument("--no-plain", action="store_true",
                     help="skip the plain path (profiles of the fused kernels alone)")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -284,6 +288,61 @@ def main():
         print(f"# served {served['runs']}", file=sys.stderr, flush=True)
 
     # algorithmic work of each step launch, the dominant (longest) step's roofline
+    # batched workloads: 64 mixed frames (16 each of 720x540 .. 1920x1080, 8 levels) and
+    # 16 frames of 3840x2160 (12 levels, N = 5000), one call per batch, eager
+    configs = None
+    if not args.no_configs:
+        configs = {}
+        for name in ("c3", "c4"):
+            specs = CONFIGS[name]["frames"]
+            ckw = CONFIGS[name]["params"]
+            cp = ofhip.params(**ckw)
+            frames = [torch.from_numpy(make_frame(sp)).cuda() for sp in specs]
+            cdet = ofhip.Detector([tuple(f.shape) for f in frames], cp)
+            with torch.cuda.stream(stream):
+                for _ in range(3):
+                    cdet.detect_batch(frames, stream=stream)
+            torch.cuda.synchronize()
+            calls = 20
+            t0 = time.perf_counter()
+            with torch.cuda.stream(stream):
+                for _ in range(calls):
+                    cdet.detect_batch(frames, stream=stream)
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t0
+            configs[name] = {"frames_per_call": len(frames), "calls": calls,
+                             "ms_per_call": round(dt / calls * 1e3, 3),
+                             "fps": round(len(frames) * calls / dt, 1),
+                             "keypoints": int(sum(len(r) for r in cdet.results()))}
+            del frames, cdet
+            print(f"# {name}: {configs[name]}", file=sys.stderr, flush=True)
+
+    # Fig. 6/7 pattern benchmark: 1024x1024 frames holding 625 copies of one segment-test
+    # pattern, 1 and 4 levels, fused path, one frame per call
+    patterns = None
+    if not args.no_patterns:
+        from synth import FIG6_CASES, fig6_pattern_image
+        patterns = {}
+        for levels in (1, 4):
+            pp = ofhip.params(n_levels=levels, fast_t=20, fast_t_min=20, cell=0, n_features=2000)
+            for case, pos, _ in FIG6_CASES:
+                pf = torch.from_numpy(fig6_pattern_image(pos)).cuda()
+                pdet = ofhip.Detector([tuple(pf.shape)], pp)
+                with torch.cuda.stream(stream):
+                    for _ in range(10):
+                        pdet.detect_batch([pf], stream=stream)
+                torch.cuda.synchronize()
+                calls = 200
+                t0 = time.perf_counter()
+                with torch.cuda.stream(stream):
+                    for _ in range(calls):
+                        pdet.detect_batch([pf], stream=stream)
+                torch.cuda.synchronize()
+                dt = time.perf_counter() - t0
+                patterns[f"{case}_L{levels}"] = {"us": round(dt / calls * 1e6, 2),
+                                                  "keypoints": len(pdet.results()[0])}
+        print(f"# patterns: {patterns}", file=sys.stderr, flush=True)
+
     res_px, seg_px = level_work([img.shape], p)
     cands = int(fused.candidates([frame]).sum())
     eff = ofhip.of_tuning_default([ofhip.image_of(frame)], p) if tune is None else tune
@@ -330,6 +389,8 @@ def main():
         "plain_fps": round(Kp / t_plain, 1) if t_plain else None,
         "batched": batched,
         "served": served,
+        "batched_configs": configs,
+        "fig7_patterns": patterns,
         "tuning": tune_fields,
         "step_us": {k: round(v, 3) for k, v in step_us.items()},
         "hbm_algorithmic_gbps": round((img.nbytes + 32 * kw["n_features"]) * fused_fps / 1e9, 2),

@@ -154,6 +154,49 @@ int of_tuning_default(const of_image* frames, int32_t n, const of_params* params
 int of_candidate_counts(const of_image* frames, int32_t n, const of_params* params,
                         const void* ws, int32_t* out, hipStream_t stream);
 
+/* Ablation ladder: the same step computed the way earlier designs do, to measure the
+ * gain of each design decision.  One call covers n pyramid levels (1 <= n <= 64, host
+ * arrays of device image descriptors and device output pointers) in one launch.
+ *
+ * of_ablate_fast: the FAST-9 segment test (Sec. 3.1, Eq. 1: bright I_i >= I_p + t, dark
+ * I_i <= I_p - t, corner iff 9 contiguous of the 16 circle pixels are bright or dark)
+ * of every pixel of each level at threshold t:
+ *   OF_AB_FAST_BRANCHY      one thread per pixel, global reads, a branch per circle
+ *                           pixel counting the current run (the scheme Alg. 1 sketches)
+ *   OF_AB_FAST_MASKS        global reads, bright and dark 16-bit masks and a shift-and
+ *                           test for nine contiguous bits (the binary encoding of
+ *                           Sec. 5.1 / Alg. 2)
+ *   OF_AB_FAST_MASKS_LDS    the same reading 64 x 16 tiles staged in LDS
+ *   OF_AB_FAST_MINMAX_LDS   the production scheme: LDS tiles, exact compass pre-test as a
+ *                           wave-wide early-out, min/max windows
+ * outs[i] (device, width * height bytes, row pitch = width) gets 1 for corners of the
+ * region x, y in [border, size - border) and 0 elsewhere.  border >= 3, 1 <= t <= 255.
+ *
+ * of_ablate_harris: R' = 25 (Sxx Syy - Sxy^2) - (Sxx + Syy)^2 over the 7x7 window of
+ * Sobel gradients (Sec. 3.2, Eqs. 2-4) at counts[i] positions pos[i][k] = (y << 16 | x)
+ * of level i (device):
+ *   OF_AB_HARRIS_2D          one thread per position, 2D Sobel at each window pixel
+ *   OF_AB_HARRIS_SEPARABLE   one thread per position, separable Sobel row by row (Eq. 4)
+ *   OF_AB_HARRIS_GROUPS      8 lanes per position, one window row each (production)
+ * outs[i][k] (device int64) gets R', or 0 when x or y is closer than 4 to the border.
+ *   OF_AB_HARRIS_DENSE_SLIDING  R' at every pixel by sliding column and row sums (the
+ *                           structure of Alg. 3); pos and counts are ignored (may be NULL)
+ *                           and outs[i] holds width * height int64.
+ * Both return OF_EINVAL on bad arguments and launch nothing then. */
+#define OF_AB_FAST_BRANCHY 0
+#define OF_AB_FAST_MASKS 1
+#define OF_AB_FAST_MASKS_LDS 2
+#define OF_AB_FAST_MINMAX_LDS 3
+#define OF_AB_HARRIS_2D 0
+#define OF_AB_HARRIS_SEPARABLE 1
+#define OF_AB_HARRIS_GROUPS 2
+#define OF_AB_HARRIS_DENSE_SLIDING 3
+int of_ablate_fast(const of_image* levels, int32_t n, int32_t t, int32_t border,
+                   int32_t variant, uint8_t* const* outs, hipStream_t stream);
+int of_ablate_harris(const of_image* levels, int32_t n, const uint32_t* const* pos,
+                     const int32_t* counts, int32_t variant, int64_t* const* outs,
+                     hipStream_t stream);
+
 /* Test entry point for the segment test alone: for each of n pixels, `circles` holds 17
  * bytes (the centre, then circle positions 1..16 clockwise from the top) and out[i]
  * gets bit 0 = corner at t_lo, bit 1 = corner at t_hi.  Device pointers. */
@@ -164,7 +207,7 @@ int of_test_segment(const uint8_t* circles, int32_t n, int32_t t_lo, int32_t t_h
  * of_detect_batch attach two HIP events to each step launch's dispatch on their stream,
  * recorded as the kernel begins and as it ends:
  * step 0 prologue, 1 pyramid, 2 segment test, 3 Harris/NMS/cells, 4 level selection,
- * 5 orientation.  of_profile_read waits for the recorded events, writes the summed
+ * 5 orientation; the ablation entry points are steps 6 (segment test) and 7 (Harris).  of_profile_read waits for the recorded events, writes the summed
  * milliseconds and launch counts of the first n steps (host arrays) and clears them.
  * Events come from a fixed pool created on the first enable; launches beyond the pool
  * are not timed (their count is still reported in launches[]).  on > 1 also issues each
@@ -172,7 +215,7 @@ int of_test_segment(const uint8_t* circles, int32_t n, int32_t t_lo, int32_t t_h
  * launches that give the same results when issued again) `on` times back to back
  * between its events, so that ms / launches is the kernel's own duration; results are
  * unchanged.  on = 0 disables. */
-#define OF_PROFILE_STEPS 6
+#define OF_PROFILE_STEPS 8
 int of_profile_enable(int on);
 int of_profile_read(double* ms, int64_t* launches, int32_t n);
 

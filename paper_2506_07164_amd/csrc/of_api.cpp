@@ -247,11 +247,42 @@ KArgs kargs(void* ws, const WsLayout& lay, const Tune& t, const of_params& p) {
   return k;
 }
 
+enum BaseKind { kMarkTiles, kMarkBands, kDetTiles, kRankSlots, kPyrBlocks };
+
+// The launch's prefix table (units per entry), copied into the kernel arguments when the
+// call has at most kSmallEntries entries; the kernels then skip loading it.
+void set_small_bases(KArgs& k, const CallPlan& c, BaseKind kind) {
+  const int n = c.lay.n_entries;
+  k.small = n <= kSmallEntries;
+  if (!k.small) return;
+  const int rows = kind == kMarkBands ? kXcds : 1;
+  for (int r = 0; r < rows; ++r) {
+    int32_t* b = k.sbase + r * (kSmallEntries + 1);
+    int32_t acc = 0;
+    for (int e = 0; e < n; ++e) {
+      b[e] = acc;
+      const EntrySize& s = c.es[e];
+      switch (kind) {
+        case kMarkTiles: acc += s.mark_tiles; break;
+        case kMarkBands:
+          acc += s.mark_tx * (band_row0(s.mark_ty, r + 1) - band_row0(s.mark_ty, r));
+          break;
+        case kDetTiles: acc += s.det_tiles; break;
+        case kRankSlots: acc += (int32_t)(s.cand_cap < kRankCap ? s.cand_cap : kRankCap); break;
+        case kPyrBlocks: acc += s.pyr_blocks; break;
+      }
+    }
+    b[n] = acc;
+  }
+}
+
 // Level selection + orientation: ranks by counting for every level, and the radix
 // select + separate orientation only when some level could exceed kRankCap candidates.
-hipError_t launch_selection(KArgs k, const WsLayout& lay, hipStream_t stream) {
+hipError_t launch_selection(KArgs k, const CallPlan& c, hipStream_t stream) {
+  const WsLayout& lay = c.lay;
   k.entry = -1;
   k.persistent = 0;
+  set_small_bases(k, c, kRankSlots);
   hipError_t e = timed(4, stream, [&] { return launch_select_orient(k, lay.rank_slots, stream); },
                        true);
   if (e == hipSuccess && lay.max_cand_cap > kRankCap) {
@@ -395,7 +426,7 @@ int of_detect(const of_image* in, const of_params* params, void* ws, size_t ws_b
     k.total = c->es[l].det_tiles;
     e = timed(3, stream, [&] { return launch_detect(k, k.total, stream); });
   }
-  if (e == hipSuccess) e = launch_selection(k, c->lay, stream);
+  if (e == hipSuccess) e = launch_selection(k, *c, stream);
   delete c;
   return e == hipSuccess ? OF_OK : hip_fail(e);
 }
@@ -430,16 +461,19 @@ int of_detect_batch(const of_image* frames, int32_t n, const of_params* params, 
   const bool fused = !t.pyr_pass || c->lay.pyr_blocks == 0;
   if (e == hipSuccess && !fused) {
     k.total = c->lay.pyr_blocks;
+    set_small_bases(k, *c, kPyrBlocks);
     e = timed(1, stream, [&] { return launch_pyramid_batch(k, c->lay.pyr_blocks, stream); }, true);
   }
   if (e == hipSuccess) {
     k.total = c->lay.mark_tiles;
     k.persistent = t.mark_grid > 0 && t.mark_grid < k.total;
+    set_small_bases(k, *c, kMarkTiles);
     if (!k.persistent && t.mark_order == 1) {
       int32_t widest = 0;
       for (int b = 0; b < kXcds; ++b) widest = std::max(widest, c->lay.band_tiles[b]);
       k.bands = 1;
       k.total = kXcds * widest;
+      set_small_bases(k, *c, kMarkBands);
     }
     e = timed(2, stream, [&] { return launch_mark(k, fused, k.persistent ? t.mark_grid : k.total, stream); },
               !k.persistent);
@@ -447,10 +481,11 @@ int of_detect_batch(const of_image* frames, int32_t n, const of_params* params, 
   }
   if (e == hipSuccess) {
     k.total = c->lay.det_tiles;
+    set_small_bases(k, *c, kDetTiles);
     k.persistent = t.det_grid > 0 && t.det_grid < k.total;
     e = timed(3, stream, [&] { return launch_detect(k, k.persistent ? t.det_grid : k.total, stream); });
   }
-  if (e == hipSuccess) e = launch_selection(k, c->lay, stream);
+  if (e == hipSuccess) e = launch_selection(k, *c, stream);
   delete c;
   return e == hipSuccess ? OF_OK : hip_fail(e);
 }
@@ -467,6 +502,69 @@ int of_candidate_counts(const of_image* frames, int32_t n, const of_params* para
   delete c;
   hipError_t e = hipMemcpyAsync(out, (const uint8_t*)ws + off, bytes, hipMemcpyDeviceToDevice,
                                 stream);
+  return e == hipSuccess ? OF_OK : hip_fail(e);
+}
+
+static bool ab_level_ok(const of_image& L) {
+  return L.data && L.width >= 1 && L.height >= 1 && L.width <= 16384 && L.height <= 16384 &&
+         L.stride >= L.width;
+}
+
+int of_ablate_fast(const of_image* levels, int32_t n, int32_t t, int32_t border,
+                   int32_t variant, uint8_t* const* outs, hipStream_t stream) {
+  if (!levels || !outs || n < 1 || n > kAbMaxLevels) return OF_EINVAL;
+  if (t < 1 || t > 255 || border < 3 || variant < 0 || variant > OF_AB_FAST_MINMAX_LDS)
+    return OF_EINVAL;
+  AbArgs a;
+  memset(&a, 0, sizeof(a));
+  a.n_levels = n;
+  a.t = t;
+  a.B = border;
+  int32_t base = 0;
+  for (int i = 0; i < n; ++i) {
+    if (!ab_level_ok(levels[i]) || !outs[i]) return OF_EINVAL;
+    AbLevel& L = a.lv[i];
+    L.img = levels[i].data;
+    L.out = outs[i];
+    L.W = levels[i].width;
+    L.H = levels[i].height;
+    L.stride = levels[i].stride;
+    L.base = base;
+    base += ablate_fast_blocks(variant, L.W, L.H);
+  }
+  hipError_t e = timed(6, stream, [&] { return launch_ablate_fast(a, variant, stream); }, true);
+  return e == hipSuccess ? OF_OK : hip_fail(e);
+}
+
+int of_ablate_harris(const of_image* levels, int32_t n, const uint32_t* const* pos,
+                     const int32_t* counts, int32_t variant, int64_t* const* outs,
+                     hipStream_t stream) {
+  if (!levels || !outs || n < 1 || n > kAbMaxLevels) return OF_EINVAL;
+  if (variant < 0 || variant > OF_AB_HARRIS_DENSE_SLIDING) return OF_EINVAL;
+  const bool dense = variant == OF_AB_HARRIS_DENSE_SLIDING;
+  if (!dense && (!pos || !counts)) return OF_EINVAL;
+  AbArgs a;
+  memset(&a, 0, sizeof(a));
+  a.n_levels = n;
+  int32_t base = 0;
+  for (int i = 0; i < n; ++i) {
+    if (!ab_level_ok(levels[i]) || !outs[i]) return OF_EINVAL;
+    AbLevel& L = a.lv[i];
+    L.img = levels[i].data;
+    L.out = outs[i];
+    L.W = levels[i].width;
+    L.H = levels[i].height;
+    L.stride = levels[i].stride;
+    if (!dense) {
+      if (counts[i] < 0 || (counts[i] > 0 && !pos[i])) return OF_EINVAL;
+      L.pos = pos[i];
+      L.n = counts[i];
+    }
+    L.base = base;
+    base += ablate_harris_blocks(variant, L.W, L.H, L.n);
+  }
+  if (base == 0) return OF_OK;  // no positions to score
+  hipError_t e = timed(7, stream, [&] { return launch_ablate_harris(a, variant, stream); }, true);
   return e == hipSuccess ? OF_OK : hip_fail(e);
 }
 

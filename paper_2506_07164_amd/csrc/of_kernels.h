@@ -5,6 +5,8 @@
 
 namespace ofk {
 
+constexpr int kSmallEntries = 16;
+
 struct FrameIn {
   const uint8_t* data;
   int32_t w, h, stride, pad;
@@ -42,6 +44,10 @@ struct KArgs {
   int32_t rank_path;           // 1: k_select_orient ranks levels with <= kRankCap candidates
   int32_t bands;               // 1: k_mark block b takes band b % kXcds, tile b / kXcds of it
   Tune t;
+  // Batches of at most kSmallEntries entries carry the launch's prefix table here (one row,
+  // or kXcds rows for the band order), so blocks find their entry without a memory load.
+  int32_t small;
+  int32_t sbase[kXcds * (kSmallEntries + 1)];
 };
 
 struct PyrLevel {
@@ -71,6 +77,26 @@ hipError_t launch_detect(const KArgs& a, int grid, hipStream_t s);
 hipError_t launch_select_orient(const KArgs& a, int slots, hipStream_t s);
 hipError_t launch_select(const KArgs& a, int grid, hipStream_t s);
 hipError_t launch_orient(const KArgs& a, int grid, hipStream_t s);
+// Levels of one ablation launch (in the kernel arguments).
+constexpr int kAbMaxLevels = 64;
+struct AbLevel {
+  const uint8_t* img;
+  void* out;               // uint8 map (FAST), int64 scores or map (Harris)
+  const uint32_t* pos;     // Harris positions (point variants)
+  int32_t W, H, stride, n; // n: Harris positions
+  int32_t base;            // first block of this level
+  int32_t pad;
+};
+struct AbArgs {
+  int32_t n_levels, t, B, pad;
+  AbLevel lv[kAbMaxLevels];
+};
+
+hipError_t launch_ablate_fast(const AbArgs& a, int variant, hipStream_t s);
+hipError_t launch_ablate_harris(const AbArgs& a, int variant, hipStream_t s);
+// Blocks a level needs in an ablation launch (the launch functions and the host agree).
+int ablate_fast_blocks(int variant, int W, int H);
+int ablate_harris_blocks(int variant, int W, int H, int n);
 hipError_t launch_test_segment(const uint8_t* circles, int n, int t_lo, int t_hi, uint8_t* out,
                                hipStream_t s);
 

@@ -93,6 +93,24 @@ __device__ __forceinline__ int find_entry(const int32_t* base, int n, int g) {
   return lo;
 }
 
+// Entry of tile g and the entry's first tile, from row `row` of the prefix table in the
+// kernel arguments (batches of at most kSmallEntries entries).  Unrolled with constant
+// indices: scalar loads of the argument segment, no search through memory.
+__device__ __forceinline__ void small_entry(const KArgs& a, int row, int g, int* e, int* start) {
+  const int32_t* b = a.sbase + row * (kSmallEntries + 1);
+  int ee = 0, st = 0;
+#pragma unroll
+  for (int i = 1; i < kSmallEntries; ++i) {
+    const int32_t bi = b[i];
+    if (i < a.n_entries && g >= bi) {
+      ee = i;
+      st = bi;
+    }
+  }
+  *e = ee;
+  *start = st;
+}
+
 __device__ __forceinline__ int wave_sum(int v) {
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
@@ -600,10 +618,17 @@ __global__ __launch_bounds__(256) void k_pyramid(PyrArgs a) {
 __global__ __launch_bounds__(256) void k_pyramid_batch(KArgs a) {
   __shared__ uint32_t xt[64], yt[16];
   __shared__ int32_t s_base[kMaxEntries + 1];
-  load_bases(s_base, a.pyr_base, a.n_entries);
   const int g = (int)blockIdx.x;
-  const int e = uniform(find_entry(s_base, a.n_entries, g));
-  const int b = g - s_base[e];
+  int e, b;
+  if (a.small) {
+    int st;
+    small_entry(a, 0, g, &e, &st);
+    b = g - st;
+  } else {
+    load_bases(s_base, a.pyr_base, a.n_entries);
+    e = uniform(find_entry(s_base, a.n_entries, g));
+    b = g - s_base[e];
+  }
   const LevelPlan P = a.plan[e];
   const int nbx = (P.W + 63) >> 6;
   const int by = b / nbx, bx = b - by * nbx;
@@ -635,7 +660,7 @@ __global__ __launch_bounds__(256, TWW <= 2 ? 5 : 4) void k_mark(KArgs a) {
   // (the same rows of every level of every frame), so each XCD's L2 holds one band of
   // the frames that its tiles resample from.
   const int band = a.bands ? (int)(blockIdx.x % kXcds) : 0;
-  if (a.entry < 0)
+  if (a.entry < 0 && !a.small)
     load_bases(s_base, a.bands ? a.band_base + band * (a.n_entries + 1) : a.mark_base,
                a.n_entries);
   queue_start(a, a.qctr + 0, &s_next);
@@ -644,11 +669,23 @@ __global__ __launch_bounds__(256, TWW <= 2 ? 5 : 4) void k_mark(KArgs a) {
     const int g0 = uniform(queue_take(a, iter, &s_next));
     if (g0 >= a.total) break;
     const int g = a.bands ? g0 / kXcds : g0;
-    if (a.bands && g >= s_base[a.n_entries]) break;  // band holds fewer tiles
+    if (a.bands && g >= (a.small ? a.sbase[band * (kSmallEntries + 1) + a.n_entries]
+                                 : s_base[a.n_entries]))
+      break;  // band holds fewer tiles
     lds_barrier();  // every thread has read s_next
     const int next = queue_prefetch(a, g0, a.qctr + 0);
-    const int e = a.entry >= 0 ? a.entry : uniform(find_entry(s_base, a.n_entries, g));
-    const int t = a.entry >= 0 ? g : g - s_base[e];
+    int e, t;
+    if (a.entry >= 0) {
+      e = a.entry;
+      t = g;
+    } else if (a.small) {
+      int st;
+      small_entry(a, band, g, &e, &st);
+      t = g - st;
+    } else {
+      e = uniform(find_entry(s_base, a.n_entries, g));
+      t = g - s_base[e];
+    }
     const LevelPlan P = a.plan[e];
     const int W = P.W, H = P.H, B = P.B;
     const int tx = t % P.mark_tx;
@@ -664,7 +701,7 @@ __global__ __launch_bounds__(256, TWW <= 2 ? 5 : 4) void k_mark(KArgs a) {
       for (int i = threadIdx.x; i < nx; i += blockDim.x) xt[i] = resample_tap(ox + i, P.base_w, W);
       for (int j = threadIdx.x; j < ny; j += blockDim.x) yt[j] = resample_tap(oy + j, P.base_h, H);
       lds_barrier();
-      // Column taps stay in registers (lane owns columns lane + 64c); each wave takes two
+      // Column taps stay in registers (lane owns columns lane + 64c); each wave takes RPI
       // consecutive output rows at a time with their base-row pointers in scalar
       // registers, so a tap costs its load and the blend only.
       gptr<const uint8_t> base = G(P.base);
@@ -678,11 +715,12 @@ __global__ __launch_bounds__(256, TWW <= 2 ? 5 : 4) void k_mark(KArgs a) {
         cx1[c] = min(cx0[c] + 1, bw1);
         cwx[c] = txx & 511;
       }
-      for (int j0 = 2 * wave; j0 < ny; j0 += 2 * nwave) {
-        int v[2][NC][4];
-        int wyr[2];
+      constexpr int RPI = TWW == 1 ? 4 : (TWW == 2 ? 3 : 2);  // rows per wave and round trip
+      for (int j0 = RPI * wave; j0 < ny; j0 += RPI * nwave) {
+        int v[RPI][NC][4];
+        int wyr[RPI];
 #pragma unroll
-        for (int h = 0; h < 2; ++h) {
+        for (int h = 0; h < RPI; ++h) {
           const uint32_t tyy = (uint32_t)uniform((int)yt[min(j0 + h, ny - 1)]);
           const int y0 = tyy >> 9;
           wyr[h] = tyy & 511;
@@ -697,7 +735,7 @@ __global__ __launch_bounds__(256, TWW <= 2 ? 5 : 4) void k_mark(KArgs a) {
           }
         }
 #pragma unroll
-        for (int h = 0; h < 2; ++h) {
+        for (int h = 0; h < RPI; ++h) {
           const int j = j0 + h;
           if (j >= ny) break;
           const int wy = wyr[h];
@@ -890,7 +928,7 @@ __global__ __launch_bounds__(256, 4) void k_detect(KArgs a) {
   int32_t* s_base = (int32_t*)(smem + D.bytes);
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nwave = blockDim.x >> 6;
   const int bd = (int)blockDim.x, tid = (int)threadIdx.x;
-  if (a.entry < 0) load_bases(s_base, a.det_base, a.n_entries);
+  if (a.entry < 0 && !a.small) load_bases(s_base, a.det_base, a.n_entries);
   queue_start(a, a.qctr + 2, &s_next);
 
   for (int iter = 0;; ++iter) {
@@ -898,8 +936,18 @@ __global__ __launch_bounds__(256, 4) void k_detect(KArgs a) {
     if (g >= a.total) break;
     lds_barrier();  // every thread has read s_next
     const int next = queue_prefetch(a, g, a.qctr + 2);
-    const int e = a.entry >= 0 ? a.entry : uniform(find_entry(s_base, a.n_entries, g));
-    const int t = a.entry >= 0 ? g : g - s_base[e];
+    int e, t;
+    if (a.entry >= 0) {
+      e = a.entry;
+      t = g;
+    } else if (a.small) {
+      int st;
+      small_entry(a, 0, g, &e, &st);
+      t = g - st;
+    } else {
+      e = uniform(find_entry(s_base, a.n_entries, g));
+      t = g - s_base[e];
+    }
     const LevelPlan P = a.plan[e];
     const int W = P.W, H = P.H, B = P.B, cs = P.cs;
     const int tx = t % P.det_tx, ty = t / P.det_tx;
@@ -1256,12 +1304,21 @@ __global__ __launch_bounds__(256, 4) void k_detect(KArgs a) {
 // the radix-select path.
 __global__ __launch_bounds__(256) void k_select_orient(KArgs a) {
   __shared__ int32_t s_base[kMaxEntries + 1];
-  load_bases(s_base, a.rank_base, a.n_entries);
+  if (!a.small) load_bases(s_base, a.rank_base, a.n_entries);
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int slot = (int)blockIdx.x * (blockDim.x >> 6) + wave;
-  if (slot >= s_base[a.n_entries]) return;
-  const int e = uniform(find_entry(s_base, a.n_entries, slot));
-  const int i = slot - s_base[e];
+  int e, i;
+  if (a.small) {
+    if (slot >= a.sbase[a.n_entries]) return;
+    int st;
+    small_entry(a, 0, slot, &e, &st);
+    e = uniform(e);
+    i = slot - st;
+  } else {
+    if (slot >= s_base[a.n_entries]) return;
+    e = uniform(find_entry(s_base, a.n_entries, slot));
+    i = slot - s_base[e];
+  }
   const LevelPlan P = a.plan[e];
   gptr<const uint32_t> counts = G((const uint32_t*)P.cand_count) - e;  // all entries
   const int C = P.cand_cap;  // slots; empty ones hold the sentinel
@@ -1520,6 +1577,364 @@ __global__ __launch_bounds__(256) void k_test_segment(const uint8_t* circles, in
 
 // ----------------------------------------------------------------- launches --
 
+// ----------------------------------------------------------------- ablation --
+// Kernels of the ablation ladder.  Each computes one step of one pyramid level the way
+// an earlier design does, so that the gain of every design decision can be measured on
+// the same inputs: FAST with branchy per-circle-pixel logic and global reads, with
+// bright/dark bit masks (global, then LDS), and the production scheme (LDS, compass
+// pre-test, min/max windows); Harris per candidate with 2D Sobel, separable Sobel, 8
+// lanes per candidate, and a dense map from sliding column sums.
+
+// Level of block g and the block's index within it (the level table is in the kernel
+// arguments: scalar loads, no memory search).
+__device__ __forceinline__ int ab_level(const AbArgs& a, int g, int* local) {
+  int e = 0;
+#pragma unroll
+  for (int i = 1; i < kAbMaxLevels; ++i)
+    if (i < a.n_levels && g >= a.lv[i].base) e = i;
+  *local = g - a.lv[e].base;
+  return e;
+}
+
+__constant__ int8_t kCircleX[16] = {0, 1, 2, 3, 3, 3, 2, 1, 0, -1, -2, -3, -3, -3, -2, -1};
+__constant__ int8_t kCircleY[16] = {-3, -3, -2, -1, 0, 1, 2, 3, 3, 3, 2, 1, 0, -1, -2, -3};
+
+// Nine contiguous set bits on the 16-bit circle, with wrap-around: 2, 4, 8, then 9.
+__device__ __forceinline__ bool run9_bits(uint32_t m) {
+  const uint32_t x = m | (m << 16);
+  uint32_t a = x & (x >> 1);
+  a &= a >> 2;
+  a &= a >> 4;
+  a &= x >> 8;
+  return (a & 0xffffu) != 0;
+}
+
+// Branchy: per circle pixel, classify and count the current bright or dark run while
+// walking the circle once and a half (a run of nine that wraps is seen whole).
+__global__ __launch_bounds__(256) void k_ab_fast_branchy(AbArgs a) {
+  int b;
+  const AbLevel& L = a.lv[ab_level(a, (int)blockIdx.x, &b)];
+  const uint8_t* img = L.img;
+  uint8_t* out = (uint8_t*)L.out;
+  const int W = L.W, H = L.H, stride = L.stride, t = a.t, B = a.B;
+  const int bx = b % cdiv(W, 64), by = b / cdiv(W, 64);
+  const int x = bx * 64 + (int)(threadIdx.x & 63);
+  const int y = by * 4 + (int)(threadIdx.x >> 6);
+  if (x >= W || y >= H) return;
+  uint8_t r = 0;
+  if (x >= B && x < W - B && y >= B && y < H - B) {
+    gptr<const uint8_t> g = G(img);
+    const int p = g[(size_t)y * stride + x];
+    int rb = 0, rd = 0;
+    for (int k = 0; k < 25; ++k) {
+      const int i = k & 15;
+      const int v = g[(size_t)(y + kCircleY[i]) * stride + x + kCircleX[i]];
+      if (v >= p + t) {
+        ++rb;
+        rd = 0;
+      } else if (v <= p - t) {
+        ++rd;
+        rb = 0;
+      } else {
+        rb = rd = 0;
+      }
+      if (rb >= 9 || rd >= 9) {
+        r = 1;
+        break;
+      }
+    }
+  }
+  G(out)[(size_t)y * W + x] = r;
+}
+
+template <bool LDS>
+__global__ __launch_bounds__(256) void k_ab_fast_masks(AbArgs a) {
+  int b;
+  const AbLevel& L = a.lv[ab_level(a, (int)blockIdx.x, &b)];
+  const uint8_t* img = L.img;
+  uint8_t* out = (uint8_t*)L.out;
+  const int W = L.W, H = L.H, stride = L.stride, t = a.t, B = a.B;
+  const int bx = b % cdiv(W, 64), by = b / cdiv(W, 64);
+  // a block covers 64 x 16 pixels, 4 rows per thread; LDS: the block's pixels and a
+  // 3-pixel halo, staged first
+  __shared__ uint8_t tile[22][72];
+  const int lx = (int)(threadIdx.x & 63), ly0 = (int)(threadIdx.x >> 6) * 4;
+  const int x = bx * 64 + lx;
+  gptr<const uint8_t> g = G(img);
+  if (LDS) {
+    const int x0 = bx * 64 - 3, y0 = by * 16 - 3;
+    for (int i = (int)threadIdx.x; i < 22 * 70; i += 256) {
+      const int r = i / 70, c = i - r * 70;
+      const int gx = x0 + c, gy = y0 + r;
+      tile[r][c] = (gx >= 0 && gx < W && gy >= 0 && gy < H) ? g[(size_t)gy * stride + gx] : 0;
+    }
+    lds_barrier();
+  }
+  for (int k = 0; k < 4; ++k) {
+    const int ly = ly0 + k, y = by * 16 + ly;
+    if (x >= W || y >= H) continue;
+    uint8_t r = 0;
+    if (x >= B && x < W - B && y >= B && y < H - B) {
+      const int p = LDS ? tile[ly + 3][lx + 3] : g[(size_t)y * stride + x];
+      uint32_t mb = 0, md = 0;
+#pragma unroll
+      for (int i = 0; i < 16; ++i) {
+        constexpr int8_t cx[16] = {0, 1, 2, 3, 3, 3, 2, 1, 0, -1, -2, -3, -3, -3, -2, -1};
+        constexpr int8_t cy[16] = {-3, -3, -2, -1, 0, 1, 2, 3, 3, 3, 2, 1, 0, -1, -2, -3};
+        const int v = LDS ? tile[ly + 3 + cy[i]][lx + 3 + cx[i]]
+                          : g[(size_t)(y + cy[i]) * stride + x + cx[i]];
+        mb |= (v >= p + t ? 1u : 0u) << i;
+        md |= (v <= p - t ? 1u : 0u) << i;
+      }
+      r = (run9_bits(mb) || run9_bits(md)) ? 1 : 0;
+    }
+    G(out)[(size_t)y * W + x] = r;
+  }
+}
+
+// Production scheme on one level: LDS tile (64 x 16 pixels, 4 rows per thread), exact
+// compass pre-test as a wave-wide early-out, min/max windows (the segment-test kernel
+// without pyramid, queue and bitmaps).
+__global__ __launch_bounds__(256) void k_ab_fast_minmax(AbArgs a) {
+  int b;
+  const AbLevel& L = a.lv[ab_level(a, (int)blockIdx.x, &b)];
+  const uint8_t* img = L.img;
+  uint8_t* out = (uint8_t*)L.out;
+  const int W = L.W, H = L.H, stride = L.stride, t = a.t, B = a.B;
+  const int bx = b % cdiv(W, 64), by = b / cdiv(W, 64);
+  __shared__ uint8_t tile[22][72];
+  const int lx = (int)(threadIdx.x & 63), ly0 = (int)(threadIdx.x >> 6) * 4;
+  const int x = bx * 64 + lx;
+  gptr<const uint8_t> g = G(img);
+  const int x0 = bx * 64 - 3, y0 = by * 16 - 3;
+  for (int i = (int)threadIdx.x; i < 22 * 70; i += 256) {
+    const int r = i / 70, c = i - r * 70;
+    const int gx = x0 + c, gy = y0 + r;
+    tile[r][c] = (gx >= 0 && gx < W && gy >= 0 && gy < H) ? g[(size_t)gy * stride + gx] : 0;
+  }
+  lds_barrier();
+  for (int k = 0; k < 4; ++k) {
+    const int ly = ly0 + k, y = by * 16 + ly;
+    const bool in = x < W && y < H && x >= B && x < W - B && y >= B && y < H - B;
+    bool pass = false;
+    int p = 0;
+    if (in) {
+      const uint8_t* c = &tile[ly + 3][lx + 3];
+      p = c[0];
+      const int vn = c[-3 * 72], vs = c[3 * 72], ve = c[3], vw = c[-3];
+      pass = min(max(vn, vs), max(ve, vw)) >= p + t || max(min(vn, vs), min(ve, vw)) <= p - t;
+    }
+    uint8_t r = 0;
+    if (__ballot(pass) != 0 && pass) {
+      int d[16];
+#pragma unroll
+      for (int i = 0; i < 16; ++i) {
+        constexpr int8_t cx[16] = {0, 1, 2, 3, 3, 3, 2, 1, 0, -1, -2, -3, -3, -3, -2, -1};
+        constexpr int8_t cy[16] = {-3, -3, -2, -1, 0, 1, 2, 3, 3, 3, 2, 1, 0, -1, -2, -3};
+        d[i] = (int)tile[ly + 3 + cy[i]][lx + 3 + cx[i]] - p;
+      }
+      r = (uint8_t)(segment_test2(d, t, t) & 1u);
+    }
+    if (x < W && y < H) G(out)[(size_t)y * W + x] = r;
+  }
+}
+
+// Harris at candidate positions.  variant 0: one thread, 2D Sobel per window pixel;
+// 1: one thread, separable Sobel over the 9 x 9 neighbourhood row by row; 2: 8 lanes,
+// one window row each, sums added across the group.  Out-of-range positions get 0.
+__device__ __forceinline__ bool harris_in(int x, int y, int W, int H) {
+  return x >= 4 && y >= 4 && x < W - 4 && y < H - 4;
+}
+
+__global__ __launch_bounds__(256) void k_ab_harris_2d(AbArgs a) {
+  int b;
+  const AbLevel& L = a.lv[ab_level(a, (int)blockIdx.x, &b)];
+  const uint8_t* img = L.img;
+  int64_t* out = (int64_t*)L.out;
+  const uint32_t* pos = L.pos;
+  const int W = L.W, H = L.H, stride = L.stride, n = L.n;
+  const int i = b * (int)blockDim.x + (int)threadIdx.x;
+  if (i >= n) return;
+  const uint32_t ps = G(pos)[i];
+  const int x = (int)(ps & 0xffff), y = (int)(ps >> 16);
+  int64_t R = 0;
+  if (harris_in(x, y, W, H)) {
+    gptr<const uint8_t> g = G(img);
+    int sxx = 0, syy = 0, sxy = 0;
+    for (int dy = -3; dy <= 3; ++dy)
+      for (int dx = -3; dx <= 3; ++dx) {
+        auto I = [&](int u, int v) { return (int)g[(size_t)(y + dy + v) * stride + x + dx + u]; };
+        const int gx = (I(1, -1) + 2 * I(1, 0) + I(1, 1)) - (I(-1, -1) + 2 * I(-1, 0) + I(-1, 1));
+        const int gy = (I(-1, 1) + 2 * I(0, 1) + I(1, 1)) - (I(-1, -1) + 2 * I(0, -1) + I(1, -1));
+        sxx += gx * gx;
+        syy += gy * gy;
+        sxy += gx * gy;
+      }
+    const int64_t A = sxx, Bv = syy, C = sxy;
+    R = 25 * (A * Bv - C * C) - (A + Bv) * (A + Bv);
+  }
+  G(out)[i] = R;
+}
+
+__global__ __launch_bounds__(256) void k_ab_harris_sep(AbArgs a) {
+  int b;
+  const AbLevel& L = a.lv[ab_level(a, (int)blockIdx.x, &b)];
+  const uint8_t* img = L.img;
+  int64_t* out = (int64_t*)L.out;
+  const uint32_t* pos = L.pos;
+  const int W = L.W, H = L.H, stride = L.stride, n = L.n;
+  const int i = b * (int)blockDim.x + (int)threadIdx.x;
+  if (i >= n) return;
+  const uint32_t ps = G(pos)[i];
+  const int x = (int)(ps & 0xffff), y = (int)(ps >> 16);
+  int64_t R = 0;
+  if (harris_in(x, y, W, H)) {
+    gptr<const uint8_t> g = G(img);
+    int hx[3][7], hs[3][7];  // rolling rows of [-1 0 1] and [1 2 1] along x
+    int sxx = 0, syy = 0, sxy = 0;
+    for (int r = 0; r < 9; ++r) {
+      int a[9];
+#pragma unroll
+      for (int k = 0; k < 9; ++k) a[k] = g[(size_t)(y - 4 + r) * stride + x - 4 + k];
+      const int slot = r % 3;
+#pragma unroll
+      for (int k = 0; k < 7; ++k) {
+        hx[slot][k] = a[k + 2] - a[k];
+        hs[slot][k] = a[k] + 2 * a[k + 1] + a[k + 2];
+      }
+      if (r >= 2) {  // window row r - 1 (rows r - 2, r - 1, r are held)
+        const int s0 = (r - 2) % 3, s1 = (r - 1) % 3, s2 = r % 3;
+#pragma unroll
+        for (int k = 0; k < 7; ++k) {
+          const int gx = hx[s0][k] + 2 * hx[s1][k] + hx[s2][k];
+          const int gy = hs[s2][k] - hs[s0][k];
+          sxx += gx * gx;
+          syy += gy * gy;
+          sxy += gx * gy;
+        }
+      }
+    }
+    const int64_t A = sxx, Bv = syy, C = sxy;
+    R = 25 * (A * Bv - C * C) - (A + Bv) * (A + Bv);
+  }
+  G(out)[i] = R;
+}
+
+__global__ __launch_bounds__(256) void k_ab_harris_groups(AbArgs a) {
+  int b;
+  const AbLevel& L = a.lv[ab_level(a, (int)blockIdx.x, &b)];
+  const uint8_t* img = L.img;
+  int64_t* out = (int64_t*)L.out;
+  const uint32_t* pos = L.pos;
+  const int W = L.W, H = L.H, stride = L.stride, n = L.n;
+  const int c = b * (int)(blockDim.x >> 3) + (int)(threadIdx.x >> 3);
+  const int s = (int)(threadIdx.x & 7);
+  int sxx = 0, syy = 0, sxy = 0;
+  bool ok = false;
+  if (c < n) {
+    const uint32_t ps = G(pos)[c];
+    const int x = (int)(ps & 0xffff), y = (int)(ps >> 16);
+    ok = harris_in(x, y, W, H);
+    if (ok && s < 7) {
+      gptr<const uint8_t> r0 = G(img) + (size_t)(y + s - 4) * stride + (x - 4);
+      int a[9], b[9], d[9];
+#pragma unroll
+      for (int k = 0; k < 9; ++k) {
+        a[k] = r0[k];
+        b[k] = r0[stride + k];
+        d[k] = r0[2 * stride + k];
+      }
+#pragma unroll
+      for (int k = 1; k < 8; ++k) {
+        const int gx = (a[k + 1] - a[k - 1]) + 2 * (b[k + 1] - b[k - 1]) + (d[k + 1] - d[k - 1]);
+        const int gy = (d[k - 1] + 2 * d[k] + d[k + 1]) - (a[k - 1] + 2 * a[k] + a[k + 1]);
+        sxx += gx * gx;
+        syy += gy * gy;
+        sxy += gx * gy;
+      }
+    }
+  }
+#pragma unroll
+  for (int o = 1; o < 8; o <<= 1) {
+    sxx += __shfl_xor(sxx, o, 8);
+    syy += __shfl_xor(syy, o, 8);
+    sxy += __shfl_xor(sxy, o, 8);
+  }
+  if (c < n && s == 0) {
+    const int64_t A = sxx, Bv = syy, C = sxy;
+    G(out)[c] = ok ? 25 * (A * Bv - C * C) - (A + Bv) * (A + Bv) : 0;
+  }
+}
+
+// Dense R' over the whole level by sliding sums: per 64 x 32 output tile, Sobel at every
+// pixel of the tile and a 3-pixel ring (LDS), products summed down 7-row columns, then
+// along 7-column rows.  Pixels closer than 4 to the border get 0.
+__global__ __launch_bounds__(256) void k_ab_harris_dense(AbArgs a) {
+  int b;
+  const AbLevel& L = a.lv[ab_level(a, (int)blockIdx.x, &b)];
+  const uint8_t* img = L.img;
+  int64_t* out = (int64_t*)L.out;
+  const int W = L.W, H = L.H, stride = L.stride;
+  constexpr int TW = 64, TH = 32, GW = TW + 6, GH = TH + 6, PW = TW + 8, PH = TH + 8;
+  __shared__ uint8_t pix[PH][PW];
+  __shared__ int16_t sgx[GH][GW], sgy[GH][GW];
+  __shared__ int32_t col[3][TH][GW];
+  const int tx0 = (b % cdiv(W, TW)) * TW, ty0 = (b / cdiv(W, TW)) * TH;
+  gptr<const uint8_t> g = G(img);
+  for (int i = (int)threadIdx.x; i < PH * PW; i += 256) {
+    const int r = i / PW, c = i - r * PW;
+    const int gx = min(max(tx0 - 4 + c, 0), W - 1), gy = min(max(ty0 - 4 + r, 0), H - 1);
+    pix[r][c] = g[(size_t)gy * stride + gx];
+  }
+  lds_barrier();
+  for (int i = (int)threadIdx.x; i < GH * GW; i += 256) {
+    const int r = i / GW, c = i - r * GW;
+    auto I = [&](int u, int v) { return (int)pix[r + 1 + v][c + 1 + u]; };
+    sgx[r][c] = (int16_t)((I(1, -1) + 2 * I(1, 0) + I(1, 1)) - (I(-1, -1) + 2 * I(-1, 0) + I(-1, 1)));
+    sgy[r][c] = (int16_t)((I(-1, 1) + 2 * I(0, 1) + I(1, 1)) - (I(-1, -1) + 2 * I(0, -1) + I(1, -1)));
+  }
+  lds_barrier();
+  // column sums: one thread per (column, product), sliding down the rows
+  for (int i = (int)threadIdx.x; i < 3 * GW; i += 256) {
+    const int k = i / GW, c = i - k * GW;
+    auto prod = [&](int r) {
+      const int a = sgx[r][c], b = sgy[r][c];
+      return k == 0 ? a * a : (k == 1 ? b * b : a * b);
+    };
+    int acc = 0;
+    for (int r = 0; r < 7; ++r) acc += prod(r);
+    col[k][0][c] = acc;
+    for (int r = 1; r < TH; ++r) {
+      acc += prod(r + 6) - prod(r - 1);
+      col[k][r][c] = acc;
+    }
+  }
+  lds_barrier();
+  // row sums: one thread per output row segment of 8 pixels, sliding along the row
+  for (int i = (int)threadIdx.x; i < TH * (TW / 8); i += 256) {
+    const int r = i / (TW / 8), c0 = (i - r * (TW / 8)) * 8;
+    int a = 0, b = 0, d = 0;
+    for (int c = c0; c < c0 + 7; ++c) {
+      a += col[0][r][c];
+      b += col[1][r][c];
+      d += col[2][r][c];
+    }
+    for (int c = c0; c < c0 + 8; ++c) {
+      if (c > c0) {
+        a += col[0][r][c + 6] - col[0][r][c - 1];
+        b += col[1][r][c + 6] - col[1][r][c - 1];
+        d += col[2][r][c + 6] - col[2][r][c - 1];
+      }
+      const int x = tx0 + c, y = ty0 + r;
+      if (x < W && y < H) {
+        const int64_t A = a, Bv = b, C = d;
+        G(out)[(size_t)y * W + x] =
+            harris_in(x, y, W, H) ? 25 * (A * Bv - C * C) - (A + Bv) * (A + Bv) : 0;
+      }
+    }
+  }
+}
+
 // Events attached to the next launch (profiling): recorded by the dispatch itself, so
 // they time the kernel alone.
 thread_local LaunchEvents g_launch_ev;
@@ -1597,6 +2012,47 @@ hipError_t launch_test_segment(const uint8_t* circles, int n, int t_lo, int t_hi
                                hipStream_t s) {
   OF_LAUNCH(k_test_segment, dim3(cdiv(n, 256)), dim3(256), 0, s, circles, n, t_lo, t_hi,
                      out);
+  return hipGetLastError();
+}
+
+int ablate_fast_blocks(int variant, int W, int H) {
+  return cdiv(W, 64) * cdiv(H, variant == 0 ? 4 : 16);
+}
+
+int ablate_harris_blocks(int variant, int W, int H, int n) {
+  switch (variant) {
+    case 0:
+    case 1: return cdiv(n, 256);
+    case 2: return cdiv(n, 32);
+    default: return cdiv(W, 64) * cdiv(H, 32);
+  }
+}
+
+static int ab_total(const AbArgs& a, int variant, bool fast) {
+  const AbLevel& L = a.lv[a.n_levels - 1];
+  return L.base + (fast ? ablate_fast_blocks(variant, L.W, L.H)
+                        : ablate_harris_blocks(variant, L.W, L.H, L.n));
+}
+
+hipError_t launch_ablate_fast(const AbArgs& a, int variant, hipStream_t s) {
+  const dim3 grid(ab_total(a, variant, true));
+  switch (variant) {
+    case 0: OF_LAUNCH(k_ab_fast_branchy, grid, dim3(256), 0, s, a); break;
+    case 1: OF_LAUNCH((k_ab_fast_masks<false>), grid, dim3(256), 0, s, a); break;
+    case 2: OF_LAUNCH((k_ab_fast_masks<true>), grid, dim3(256), 0, s, a); break;
+    default: OF_LAUNCH(k_ab_fast_minmax, grid, dim3(256), 0, s, a); break;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_ablate_harris(const AbArgs& a, int variant, hipStream_t s) {
+  const dim3 grid(ab_total(a, variant, false));
+  switch (variant) {
+    case 0: OF_LAUNCH(k_ab_harris_2d, grid, dim3(256), 0, s, a); break;
+    case 1: OF_LAUNCH(k_ab_harris_sep, grid, dim3(256), 0, s, a); break;
+    case 2: OF_LAUNCH(k_ab_harris_groups, grid, dim3(256), 0, s, a); break;
+    default: OF_LAUNCH(k_ab_harris_dense, grid, dim3(256), 0, s, a); break;
+  }
   return hipGetLastError();
 }
 

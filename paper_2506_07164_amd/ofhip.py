@@ -76,6 +76,8 @@ def lib() -> ctypes.CDLL:
         L.of_tuning_default.argtypes = [P(OfImage), i32, P(OfParams), P(OfTuning)]
         L.of_test_segment.argtypes = [vp, i32, i32, i32, vp, vp]
         L.of_candidate_counts.argtypes = [P(OfImage), i32, P(OfParams), vp, vp, vp]
+        L.of_ablate_fast.argtypes = [P(OfImage), i32, i32, i32, i32, P(vp), vp]
+        L.of_ablate_harris.argtypes = [P(OfImage), i32, P(vp), P(i32), i32, P(vp), vp]
         L.of_profile_enable.argtypes = [ctypes.c_int]
         L.of_profile_read.argtypes = [P(ctypes.c_double), i64p, i32]
         L.of_status_string.argtypes = [ctypes.c_int]
@@ -170,14 +172,37 @@ def of_candidate_counts(images, p: OfParams, ws_ptr: int, out_ptr: int, stream: 
            "of_candidate_counts")
 
 
+AB_FAST = {"branchy": 0, "masks": 1, "masks_lds": 2, "minmax_lds": 3}
+AB_HARRIS = {"2d": 0, "separable": 1, "groups": 2, "dense_sliding": 3}
+
+
+def of_ablate_fast(levels, t: int, border: int, variant: int, out_ptrs, stream: int) -> None:
+    """levels: OfImage list (device images); out_ptrs: device uint8 maps, one per level."""
+    n = len(levels)
+    arr = (OfImage * n)(*levels)
+    outs = (ctypes.c_void_p * n)(*out_ptrs)
+    _check(lib().of_ablate_fast(arr, n, t, border, variant, outs, stream), "of_ablate_fast")
+
+
+def of_ablate_harris(levels, pos_ptrs, counts, variant: int, out_ptrs, stream: int) -> None:
+    """pos_ptrs/counts: device (y << 16 | x) arrays and their lengths, one per level (None
+    for the dense variant); out_ptrs: device int64 outputs."""
+    n = len(levels)
+    arr = (OfImage * n)(*levels)
+    outs = (ctypes.c_void_p * n)(*out_ptrs)
+    pp = (ctypes.c_void_p * n)(*pos_ptrs) if pos_ptrs is not None else None
+    cc = (ctypes.c_int32 * n)(*counts) if counts is not None else None
+    _check(lib().of_ablate_harris(arr, n, pp, cc, variant, outs, stream), "of_ablate_harris")
+
+
 def of_test_segment(circles_ptr: int, n: int, t_lo: int, t_hi: int, out_ptr: int,
                     stream: int) -> None:
     _check(lib().of_test_segment(circles_ptr, n, t_lo, t_hi, out_ptr, stream), "of_test_segment")
 
 
-OF_PROFILE_STEPS = 6
+OF_PROFILE_STEPS = 8
 PROFILE_STEP_NAMES = ["prologue", "pyramid", "segment_test", "harris_nms_cells", "select",
-                      "orient"]
+                      "orient", "ablate_fast", "ablate_harris"]
 
 
 def of_profile_enable(on) -> None:

@@ -114,6 +114,17 @@ _CIRCLE = [(0, -3), (1, -3), (2, -2), (3, -1), (3, 0), (3, 1), (2, 2), (1, 3),
            (0, 3), (-1, 3), (-2, 2), (-3, 1), (-3, 0), (-3, -1), (-2, -2), (-1, -3)]
 
 
+# The five segment-test patterns of Fig. 6 as read from its caption: case, bright circle
+# positions (1..16 clockwise from the top), and whether the centre is a FAST-9 corner.
+FIG6_CASES = (
+    ("a", (1, 2, 3, 4, 5, 6, 7, 8, 9), True),
+    ("b", (6, 7, 8, 9, 10, 11, 12, 13, 14, 15, 16, 1), True),
+    ("c", (12, 13, 14, 15, 16, 1, 2, 3, 4), True),
+    ("d", (1, 2, 3, 4, 5, 6, 7, 8), False),
+    ("e", (1, 3, 5, 7, 9, 11, 13, 15), False),
+)
+
+
 def fig6_pattern_image(bright_positions, size: int = 1024, copies: int = 25,
                        base: int = 100, bright: int = 200) -> np.ndarray:
     """Tile ``copies x copies`` copies of one segment-test pattern over a flat frame.

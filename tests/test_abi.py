@@ -120,3 +120,30 @@ def test_default_tuning_valid_for_every_cell_size(lib):
         st = lib.of_detect_batch(imgs, 1, ctypes.byref(p), 0x1000, 16, 0x1000, offs, 500, 0x1000,
                                  None, None)
         assert st == ofhip.OF_ENOSPACE, (cell, st)
+
+
+def test_ablation_entry_points_validate_before_launch(lib):
+    img = ofhip.OfImage(0x1000, 64, 48, 64)
+    bad_img = ofhip.OfImage(0x1000, 64, 48, 32)
+    one = (ctypes.c_void_p * 1)(0x1000)
+    null = (ctypes.c_void_p * 1)(None)
+    for lv, t, b, v in ((bad_img, 20, 15, 0), (img, 0, 15, 0), (img, 256, 15, 0),
+                        (img, 20, 2, 0), (img, 20, 15, 4), (img, 20, 15, -1)):
+        arr = (ofhip.OfImage * 1)(lv)
+        assert lib.of_ablate_fast(arr, 1, t, b, v, one, None) == ofhip.OF_EINVAL, (t, b, v)
+    arr = (ofhip.OfImage * 1)(img)
+    assert lib.of_ablate_fast(None, 1, 20, 15, 0, one, None) == ofhip.OF_EINVAL
+    assert lib.of_ablate_fast(arr, 0, 20, 15, 0, one, None) == ofhip.OF_EINVAL
+    assert lib.of_ablate_fast(arr, 65, 20, 15, 0, one, None) == ofhip.OF_EINVAL
+    assert lib.of_ablate_fast(arr, 1, 20, 15, 0, null, None) == ofhip.OF_EINVAL
+    cnt = (ctypes.c_int32 * 1)(10)
+    neg = (ctypes.c_int32 * 1)(-1)
+    zero = (ctypes.c_int32 * 1)(0)
+    assert lib.of_ablate_harris(arr, 1, one, cnt, 4, one, None) == ofhip.OF_EINVAL
+    assert lib.of_ablate_harris(arr, 1, None, cnt, 0, one, None) == ofhip.OF_EINVAL
+    assert lib.of_ablate_harris(arr, 1, null, cnt, 0, one, None) == ofhip.OF_EINVAL
+    assert lib.of_ablate_harris(arr, 1, one, neg, 0, one, None) == ofhip.OF_EINVAL
+    bad = (ofhip.OfImage * 1)(bad_img)
+    assert lib.of_ablate_harris(bad, 1, None, None, 3, one, None) == ofhip.OF_EINVAL
+    # nothing to score: returns before any launch
+    assert lib.of_ablate_harris(arr, 1, null, zero, 0, one, None) == ofhip.OF_OK

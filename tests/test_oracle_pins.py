@@ -60,6 +60,12 @@ def _fig6_cases():
     return cases
 
 
+def test_fig6_cases_of_the_generator_match_the_fixture():
+    """The benchmark's input list (synth) holds the same patterns as the cited fixture."""
+    from synth import FIG6_CASES
+    assert [(c, tuple(p), bool(k)) for c, p, k in _fig6_cases()] == list(FIG6_CASES)
+
+
 @pytest.mark.parametrize("case,pos,corner", _fig6_cases())
 def test_fig6_patterns(case, pos, corner):
     img = np.full((9, 9), 100, np.uint8)
