@@ -63,6 +63,12 @@ def _lib():
         lib.ofref_harris.restype = ctypes.c_int64
         lib.ofref_moments.argtypes = [u8p, i32, i32, i32, i32, i32p, i32p]
         lib.ofref_moments.restype = None
+        i8p = ctypes.POINTER(ctypes.c_int8)
+        lib.ofref_brief_tables.argtypes = [i8p, i8p, i32p]
+        lib.ofref_brief_tables.restype = None
+        lib.ofref_describe.argtypes = [u8p, i32, i32, i32, i32, i32, i8p, i32p,
+                                       ctypes.POINTER(ctypes.c_uint8)]
+        lib.ofref_describe.restype = None
         lib.ofref_level_detect.argtypes = [u8p, i32, i32, i32, P(Params), i32, i32, i32,
                                            u8p, u8p, i64p, u8p, vp]
         lib.ofref_pyramid_level.argtypes = [u8p, i32, i32, i32, P(Params), i32, u8p]
@@ -141,6 +147,32 @@ def moments(img, x: int, y: int, r: int = 15):
     a, b = ctypes.c_int32(), ctypes.c_int32()
     _lib().ofref_moments(_u8(img), img.strides[0], x, y, r, ctypes.byref(a), ctypes.byref(b))
     return a.value, b.value
+
+
+def brief_tables(pattern):
+    """(rot [30, 256, 4] int8, centres [30, 2] int32): the steered copies of `pattern`."""
+    pattern = np.ascontiguousarray(pattern, dtype=np.int8)
+    rot = np.zeros((30, 256, 4), np.int8)
+    centres = np.zeros((30, 2), np.int32)
+    _lib().ofref_brief_tables(pattern.ctypes.data_as(ctypes.POINTER(ctypes.c_int8)),
+                              rot.ctypes.data_as(ctypes.POINTER(ctypes.c_int8)),
+                              centres.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)))
+    return rot, centres
+
+
+def describe(img, keypoints, rot, centres) -> np.ndarray:
+    """rBRIEF of each keypoint (fields x, y, m10, m01) on level image `img`: (n, 32) uint8."""
+    img = _img(img)
+    rot = np.ascontiguousarray(rot, dtype=np.int8)
+    centres = np.ascontiguousarray(centres, dtype=np.int32)
+    out = np.zeros((len(keypoints), 32), np.uint8)
+    for i, kp in enumerate(keypoints):
+        _lib().ofref_describe(_u8(img), img.strides[0], int(kp["x"]), int(kp["y"]),
+                              int(kp["m10"]), int(kp["m01"]),
+                              rot.ctypes.data_as(ctypes.POINTER(ctypes.c_int8)),
+                              centres.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
+                              out[i].ctypes.data_as(ctypes.POINTER(ctypes.c_uint8)))
+    return out
 
 
 def level_detect(lvl, p: Params, level: int = 0, k_cell: int | None = None,

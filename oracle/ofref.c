@@ -191,6 +191,72 @@ int64_t ofref_harris(const uint8_t* img, int32_t stride, int32_t x, int32_t y, i
 
 /* Reading: intensity centroid over the disk dx^2 + dy^2 <= r^2 on the keypoint's level:
  * m10 = sum dx I, m01 = sum dy I (y down); angle = atan2(m01, m10). */
+/* Round half to even of a double (the values here are small). */
+static int32_t round_half_even(double v) {
+  double f = floor(v);
+  double r = v - f;
+  int32_t i = (int32_t)f;
+  if (r > 0.5) return i + 1;
+  if (r < 0.5) return i;
+  return (i % 2 == 0) ? i : i + 1;
+}
+
+void ofref_brief_tables(const int8_t* pattern, int8_t* rot, int32_t* centres) {
+  const double pi = 3.14159265358979323846;
+  for (int32_t k = 0; k < 15; ++k) {
+    /* the exact value where the cosine is rational (0, 60, 120 degrees) */
+    double c = k == 0 ? 1.0 : (k == 5 ? 0.5 : (k == 10 ? -0.5 : cos(2.0 * pi * k / 30.0)));
+    double s = k == 0 ? 0.0 : sin(2.0 * pi * k / 30.0);
+    centres[2 * k] = round_half_even(c * 16384.0);
+    centres[2 * k + 1] = round_half_even(s * 16384.0);
+    for (int32_t i = 0; i < 256; ++i) {
+      for (int32_t j = 0; j < 4; j += 2) {
+        const double x = pattern[4 * i + j], y = pattern[4 * i + j + 1];
+        rot[((size_t)k * 256 + i) * 4 + j] = (int8_t)round_half_even(c * x - s * y);
+        rot[((size_t)k * 256 + i) * 4 + j + 1] = (int8_t)round_half_even(s * x + c * y);
+      }
+    }
+  }
+  /* a half turn further: the exact negation (rounding half to even is odd-symmetric) */
+  for (int32_t k = 15; k < 30; ++k) {
+    centres[2 * k] = -centres[2 * (k - 15)];
+    centres[2 * k + 1] = -centres[2 * (k - 15) + 1];
+    for (int32_t i = 0; i < 256 * 4; ++i)
+      rot[(size_t)k * 256 * 4 + i] = (int8_t)-rot[(size_t)(k - 15) * 256 * 4 + i];
+  }
+}
+
+/* 5x5 binomial smoothing sum at (x, y): separable weights 1 4 6 4 1, not normalised
+ * (the tests compare two sums, so no rounding enters). */
+static int32_t smooth5(const uint8_t* img, int32_t stride, int32_t x, int32_t y) {
+  static const int32_t w[5] = {1, 4, 6, 4, 1};
+  int32_t s = 0;
+  for (int32_t v = -2; v <= 2; ++v)
+    for (int32_t u = -2; u <= 2; ++u)
+      s += w[u + 2] * w[v + 2] * img[(size_t)(y + v) * stride + (x + u)];
+  return s;
+}
+
+void ofref_describe(const uint8_t* img, int32_t stride, int32_t x, int32_t y, int32_t m10,
+                    int32_t m01, const int8_t* rot, const int32_t* centres, uint8_t* out) {
+  int32_t bin = 0;
+  int64_t best = 0;
+  for (int32_t k = 0; k < 30; ++k) {
+    int64_t d = (int64_t)m10 * centres[2 * k] + (int64_t)m01 * centres[2 * k + 1];
+    if (k == 0 || d > best) {
+      best = d;
+      bin = k;
+    }
+  }
+  const int8_t* t = rot + (size_t)bin * 256 * 4;
+  for (int32_t i = 0; i < 32; ++i) out[i] = 0;
+  for (int32_t i = 0; i < 256; ++i) {
+    int32_t s1 = smooth5(img, stride, x + t[4 * i], y + t[4 * i + 1]);
+    int32_t s2 = smooth5(img, stride, x + t[4 * i + 2], y + t[4 * i + 3]);
+    if (s1 < s2) out[i >> 3] |= (uint8_t)(1u << (i & 7));
+  }
+}
+
 void ofref_moments(const uint8_t* img, int32_t stride, int32_t x, int32_t y, int32_t r,
                    int32_t* m10, int32_t* m01) {
   int32_t a = 0, b = 0;

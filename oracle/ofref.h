@@ -74,6 +74,24 @@ int ofref_segment_test(const uint8_t* img, int32_t stride, int32_t x, int32_t y,
 int64_t ofref_harris(const uint8_t* img, int32_t stride, int32_t x, int32_t y, int32_t block);
 
 /* Moments over the disk of radius r centred on (x, y). */
+/* Steered rBRIEF tables: for bin k of 30 (12 degrees each, angle measured like
+ * atan2(m01, m10) with y down), the pattern's points rotated by 2 pi k / 30 and rounded
+ * half to even: rot[k][i] = (x1, y1, x2, y2) of pair i; centres[k] = the bin's
+ * direction, round(2^14 (cos, sin)).  The cosine is taken exactly where it is rational
+ * (1/2 at 60 and 300 degrees, -1/2 at 120 and 240) and bins 15..29 are the exact
+ * negations of bins 0..14.  pattern: 256 * 4 int8 (input). */
+void ofref_brief_tables(const int8_t* pattern, int8_t* rot, int32_t* centres);
+
+/* rBRIEF (the descriptor ORB attaches to each oriented keypoint, Sec. 1): the angle
+ * bin is the k maximising m10 * centres[k][0] + m01 * centres[k][1] (ties: smallest k);
+ * bit i of out (byte i / 8, bit i % 8) is set iff S(p + a_i) < S(p + b_i), with
+ * (a_i, b_i) = rot[k][i] = (x1, y1, x2, y2) and S the 5x5 binomial smoothing
+ * sum_{|u|,|v| <= 2} w_u w_v I(y + v, x + u), w = (1, 4, 6, 4, 1).  Every point of rot
+ * must lie within 13 of (x, y) and (x, y) at least 15 from the border.  rot: 30 * 256
+ * * 4 int8, centres: 30 * 2 int32 (inputs). */
+void ofref_describe(const uint8_t* img, int32_t stride, int32_t x, int32_t y, int32_t m10,
+                    int32_t m01, const int8_t* rot, const int32_t* centres, uint8_t* out);
+
 void ofref_moments(const uint8_t* img, int32_t stride, int32_t x, int32_t y, int32_t r,
                    int32_t* m10, int32_t* m01);
 

@@ -146,6 +146,26 @@ def fig6_pattern_image(bright_positions, size: int = 1024, copies: int = 25,
     return img
 
 
+# rBRIEF input.  ORB's learned test pattern is not available, so the 256 point pairs are
+# drawn here (BRIEF's isotropic Gaussian sampling, sigma = 31/5), kept inside the disk of
+# radius 13 so that every rotation plus the 5x5 smoothing stays within the border of 15.
+BRIEF_RADIUS = 13
+
+
+def brief_pattern(seed: int = 4242) -> np.ndarray:
+    """256 test pairs (x1, y1, x2, y2), int8, every point inside the disk of radius 13."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    out = np.zeros((256, 4), np.int8)
+    for i in range(256):
+        for j in (0, 2):
+            while True:
+                p = np.rint(rng.normal(0.0, 31.0 / 5.0, 2))
+                if p[0] * p[0] + p[1] * p[1] <= BRIEF_RADIUS * BRIEF_RADIUS:
+                    break
+            out[i, j], out[i, j + 1] = int(p[0]), int(p[1])
+    return out
+
+
 def stream_schedule(n_streams: int, duration_s: float, rate_hz: float, seed: int = 3000):
     """Poisson arrivals for ``n_streams`` cameras: list of (t_arrival, stream, frame_idx)."""
     events = []

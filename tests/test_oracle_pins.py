@@ -364,3 +364,89 @@ def test_param_validation():
     assert oracle.check(640, 480, oracle.params(n_levels=16))  # level 15 is 42x31
     assert not oracle.check(600, 460, oracle.params(n_levels=16))  # level 15 is 39x30
     assert not oracle.check(640, 480, oracle.params(n_levels=17))
+
+
+# ------------------------------------------------------------------ rBRIEF ------
+
+def test_brief_tables_closed_forms():
+    """Bin 0 is the pattern itself, bin 15 its exact negation (180 degrees); bin 5 (60
+    degrees, cos = 1/2) rounds the half-way values to even, written out by hand."""
+    from synth import brief_pattern
+    pat = np.array([[1, 0, 2, 0], [0, 1, -3, 2]] + [[0, 0, 0, 0]] * 254, np.int8)
+    rot, cen = oracle.brief_tables(pat)
+    assert (rot[0] == pat).all() and (rot[15] == -pat).all()
+    assert tuple(cen[0]) == (16384, 0) and tuple(cen[15]) == (-16384, 0)
+    assert tuple(cen[5]) == (8192, 14189)                       # round(2^14 (1/2, sqrt(3)/2))
+    # (1,0) -> (0.5, 0.866) -> (0, 1); (2,0) -> (1, 1.732) -> (1, 2)
+    assert rot[5, 0].tolist() == [0, 1, 1, 2]
+    # 240 degrees: (1,0) -> (-0.5, -0.866) -> (0, -1) (ties to even in both directions)
+    assert rot[20, 0].tolist() == [0, -1, -1, -2]
+    assert (rot[15:] == -rot[:15]).all() and (cen[15:] == -cen[:15]).all()
+    # (0,1) -> (-0.866, 0.5) -> (-1, 0); (-3,2) -> (-1.5-1.732, -2.598+1) -> (-3, -2)
+    assert rot[5, 1].tolist() == [-1, 0, -3, -2]
+    real = brief_pattern()
+    assert (np.abs(real.astype(int)) <= 13).all()
+    assert ((real[:, 0::2].astype(int) ** 2 + real[:, 1::2].astype(int) ** 2) <= 169).all()
+    rr, _ = oracle.brief_tables(real)
+    assert (np.abs(rr.astype(int)) <= 13).all()
+
+
+def _kp(x, y, m10, m01):
+    a = np.zeros(1, oracle.KEYPOINT_DTYPE)
+    a["x"], a["y"], a["m10"], a["m01"] = x, y, m10, m01
+    return a
+
+
+def test_brief_descriptor_closed_forms():
+    """A constant patch sets no bit; on a horizontal ramp (smoothing keeps it a ramp)
+    the bits of bin 0 are x1 < x2, on a vertical ramp y1 < y2."""
+    from synth import brief_pattern
+    pat = brief_pattern()
+    rot, cen = oracle.brief_tables(pat)
+    bits = lambda d: np.unpackbits(d[0], bitorder="little")
+    flat = np.full((40, 40), 90, np.uint8)
+    assert not oracle.describe(flat, _kp(20, 20, 5, 0), rot, cen).any()
+    ramp_x = np.tile(np.arange(40, dtype=np.uint8) + 10, (40, 1))
+    ramp_y = np.ascontiguousarray(ramp_x.T)
+    np.testing.assert_array_equal(bits(oracle.describe(ramp_x, _kp(20, 20, 7, 0), rot, cen)),
+                                  (pat[:, 0] < pat[:, 2]).astype(np.uint8))
+    np.testing.assert_array_equal(bits(oracle.describe(ramp_y, _kp(20, 20, 7, 0), rot, cen)),
+                                  (pat[:, 1] < pat[:, 3]).astype(np.uint8))
+
+
+def test_brief_bins_and_180_degree_rotation():
+    """The bin follows the angle of (m10, m01) in 12 degree steps; rotating the image by
+    180 degrees (and negating the moments) leaves the descriptor unchanged."""
+    from synth import brief_pattern
+    rot, cen = oracle.brief_tables(brief_pattern())
+    rng = np.random.default_rng(3)
+    img = rng.integers(0, 256, (48, 52), dtype=np.uint8)
+    img180 = np.ascontiguousarray(img[::-1, ::-1])
+    for k in range(30):
+        a = 2 * np.pi * k / 30 + 0.05
+        m10, m01 = int(round(1e5 * np.cos(a))), int(round(1e5 * np.sin(a)))
+        d = oracle.describe(img, _kp(25, 22, m10, m01), rot, cen)
+        # the same descriptor as from the table of bin k directly
+        t = rot[k].astype(int)
+        assert d[0].tolist() == oracle.describe(img, _kp(25, 22, int(cen[k][0]),
+                                                         int(cen[k][1])), rot, cen)[0].tolist()
+        d180 = oracle.describe(img180, _kp(52 - 1 - 25, 48 - 1 - 22, -m10, -m01), rot, cen)
+        np.testing.assert_array_equal(d, d180)
+
+
+def test_brief_smoothing_matches_library_convolution():
+    """The tests compare 5x5 binomial sums; scipy's correlate gives the same comparisons."""
+    from scipy.ndimage import correlate
+    from synth import brief_pattern
+    pat = brief_pattern()
+    rot, cen = oracle.brief_tables(pat)
+    rng = np.random.default_rng(9)
+    img = rng.integers(0, 256, (60, 64), dtype=np.uint8)
+    w = np.array([1, 4, 6, 4, 1])
+    S = correlate(img.astype(np.int64), np.outer(w, w), mode="constant")
+    for (x, y, m10, m01) in [(30, 30, 100, 3), (20, 40, -50, 80), (44, 17, 0, -9)]:
+        d = oracle.describe(img, _kp(x, y, m10, m01), rot, cen)
+        k = int(np.argmax(m10 * cen[:, 0].astype(np.int64) + m01 * cen[:, 1].astype(np.int64)))
+        t = rot[k].astype(int)
+        want = (S[y + t[:, 1], x + t[:, 0]] < S[y + t[:, 3], x + t[:, 2]]).astype(np.uint8)
+        np.testing.assert_array_equal(np.unpackbits(d[0], bitorder="little"), want)
