@@ -288,6 +288,22 @@ def main():
         print(f"# served {served['runs']}", file=sys.stderr, flush=True)
 
     # algorithmic work of each step launch, the dominant (longest) step's roofline
+    # rBRIEF of the 2000 keypoints (one launch; the pattern is a seeded input)
+    from synth import brief_pattern
+    rot, cen = ofhip.of_brief_tables(brief_pattern())
+    rot_d, cen_d = torch.from_numpy(rot).cuda(), torch.from_numpy(cen).cuda()
+    fused.detect_batch([frame], tune=tune, stream=stream)
+    torch.cuda.synchronize()
+    for _ in range(5):
+        fused.describe([frame], rot_d, cen_d, tune=tune)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(200):
+        fused.describe([frame], rot_d, cen_d, tune=tune)
+    torch.cuda.synchronize()
+    describe_us = (time.perf_counter() - t0) / 200 * 1e6
+    print(f"# describe 2000 keypoints: {describe_us:.1f} us per call", file=sys.stderr, flush=True)
+
     # batched workloads: 64 mixed frames (16 each of 720x540 .. 1920x1080, 8 levels) and
     # 16 frames of 3840x2160 (12 levels, N = 5000), one call per batch, eager
     configs = None
@@ -389,6 +405,7 @@ def main():
         "plain_fps": round(Kp / t_plain, 1) if t_plain else None,
         "batched": batched,
         "served": served,
+        "describe_us": round(describe_us, 2),
         "batched_configs": configs,
         "fig7_patterns": patterns,
         "tuning": tune_fields,

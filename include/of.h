@@ -154,6 +154,29 @@ int of_tuning_default(const of_image* frames, int32_t n, const of_params* params
 int of_candidate_counts(const of_image* frames, int32_t n, const of_params* params,
                         const void* ws, int32_t* out, hipStream_t stream);
 
+/* Steered rBRIEF, the descriptor ORB attaches to each oriented keypoint (Sec. 1).
+ *
+ * of_brief_tables (host only): the 256 test pairs of `pattern` (host, 256 x 4 int8,
+ * (x1, y1, x2, y2), every point within 13 of the origin) rotated to 30 angle bins of
+ * 12 degrees, rounded half to even (host, rot: 30 x 256 x 4 int8), and the bins'
+ * centre directions round(2^14 (cos, sin)) (host, centres: 30 x 2 int32).  The cosine is
+ * exact where rational (bins 5 and 10) and bins 15..29 negate bins 0..14.
+ *
+ * of_describe: 256-bit descriptors of the keypoints of the last detection on `ws` (same
+ * frames, params and tuning as that call, and the same kps / kp_offset / counts buffers
+ * it wrote).  Per keypoint the bin is the k maximising m10 * centres[k][0] +
+ * m01 * centres[k][1] (ties: smallest k), and bit i (byte i / 8, bit i % 8) is set iff
+ * the 5x5 binomial sum (weights 1 4 6 4 1 per axis) on the keypoint's level at p + a_i
+ * is smaller than at p + b_i, (a_i, b_i) = rot[k][i].  rot and centres are device copies
+ * of of_brief_tables' output; desc (device) holds 32 bytes per keypoint slot, indexed
+ * like kps.  Slots beyond counts[f] are not written; if ws does not hold the plan of
+ * that detection nothing is written.  OF_EINVAL on bad arguments (nothing launched). */
+int of_brief_tables(const int8_t* pattern, int8_t* rot, int32_t* centres);
+int of_describe(const of_image* frames, int32_t n, const of_params* params,
+                const of_tuning* tuning, const void* ws, const of_keypoint* kps,
+                const int64_t* kp_offset, const int32_t* counts, const int8_t* rot,
+                const int32_t* centres, uint8_t* desc, hipStream_t stream);
+
 /* Ablation ladder: the same step computed the way earlier designs do, to measure the
  * gain of each design decision.  One call covers n pyramid levels (1 <= n <= 64, host
  * arrays of device image descriptors and device output pointers) in one launch.

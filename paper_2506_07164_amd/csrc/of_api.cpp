@@ -4,6 +4,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <cmath>
 #include <mutex>
 
 #include "of_kernels.h"
@@ -565,6 +566,75 @@ int of_ablate_harris(const of_image* levels, int32_t n, const uint32_t* const* p
   }
   if (base == 0) return OF_OK;  // no positions to score
   hipError_t e = timed(7, stream, [&] { return launch_ablate_harris(a, variant, stream); }, true);
+  return e == hipSuccess ? OF_OK : hip_fail(e);
+}
+
+int of_brief_tables(const int8_t* pattern, int8_t* rot, int32_t* centres) {
+  if (!pattern || !rot || !centres) return OF_EINVAL;
+  // std::nearbyint rounds half to even in the default rounding mode
+  const double turn = 6.283185307179586476925286766559;
+  for (int k = 0; k < 15; ++k) {
+    double c = std::cos(turn * k / 30.0), s = std::sin(turn * k / 30.0);
+    if (k == 0) {
+      c = 1.0;
+      s = 0.0;
+    } else if (k == 5 || k == 10) {
+      c = k == 5 ? 0.5 : -0.5;  // the rational cosines, exactly
+    }
+    centres[2 * k] = (int32_t)std::nearbyint(16384.0 * c);
+    centres[2 * k + 1] = (int32_t)std::nearbyint(16384.0 * s);
+    centres[2 * (k + 15)] = -centres[2 * k];
+    centres[2 * (k + 15) + 1] = -centres[2 * k + 1];
+    for (int i = 0; i < 256; ++i) {
+      for (int j = 0; j < 2; ++j) {
+        const double px = pattern[4 * i + 2 * j], py = pattern[4 * i + 2 * j + 1];
+        const int8_t rx = (int8_t)std::nearbyint(c * px - s * py);
+        const int8_t ry = (int8_t)std::nearbyint(s * px + c * py);
+        int8_t* a = rot + ((size_t)k * 256 + i) * 4 + 2 * j;
+        int8_t* b = rot + ((size_t)(k + 15) * 256 + i) * 4 + 2 * j;
+        a[0] = rx;
+        a[1] = ry;
+        b[0] = (int8_t)-rx;  // half a turn further: exact negation
+        b[1] = (int8_t)-ry;
+      }
+    }
+  }
+  return OF_OK;
+}
+
+int of_describe(const of_image* frames, int32_t n, const of_params* params,
+                const of_tuning* tuning, const void* ws, const of_keypoint* kps,
+                const int64_t* kp_offset, const int32_t* counts, const int8_t* rot,
+                const int32_t* centres, uint8_t* desc, hipStream_t stream) {
+  int st = check_frames(frames, n, params);
+  if (st) return st;
+  if (!ws || !kps || !kp_offset || !counts || !rot || !centres || !desc) return OF_EINVAL;
+  Tune t;
+  st = resolve_tune(tuning, *params, &t);
+  if (st) return st;
+  CallPlan* c = new CallPlan;
+  plan_call(frames, n, *params, t, c);
+  PrologueArgs* pa = new PrologueArgs;
+  fill_prologue(pa, frames, n, *params, t, const_cast<void*>(ws), c->lay,
+                const_cast<of_keypoint*>(kps), kp_offset, const_cast<int32_t*>(counts));
+  DescArgs a;
+  memset(&a, 0, sizeof(a));
+  const uint8_t* b = (const uint8_t*)ws;
+  a.plan = (const LevelPlan*)(b + c->lay.off_plan);
+  a.ws_sig = (const uint64_t*)(b + c->lay.off_hdr + 128);
+  a.sig = pa->sig;
+  a.n = n;
+  a.L = params->n_levels;
+  a.cap = params->n_features;
+  a.kps = kps;
+  a.counts = counts;
+  a.rot = rot;
+  a.centres = centres;
+  a.desc = desc;
+  for (int f = 0; f < n; ++f) a.off[f] = kp_offset[f];
+  delete pa;
+  delete c;
+  hipError_t e = launch_describe(a, stream);
   return e == hipSuccess ? OF_OK : hip_fail(e);
 }
 

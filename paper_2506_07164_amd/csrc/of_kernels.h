@@ -77,6 +77,23 @@ hipError_t launch_detect(const KArgs& a, int grid, hipStream_t s);
 hipError_t launch_select_orient(const KArgs& a, int slots, hipStream_t s);
 hipError_t launch_select(const KArgs& a, int grid, hipStream_t s);
 hipError_t launch_orient(const KArgs& a, int grid, hipStream_t s);
+// Arguments of the rBRIEF launch: keypoints of n frames (cap slots each) described on
+// the levels of the plan in the workspace, which must carry signature `sig`.
+struct DescArgs {
+  const LevelPlan* plan;
+  const uint64_t* ws_sig;
+  uint64_t sig;
+  int32_t n, L, cap, pad;
+  const of_keypoint* kps;
+  const int32_t* counts;
+  const int8_t* rot;       // 30 x 256 x 4
+  const int32_t* centres;  // 30 x 2
+  uint8_t* desc;           // 32 bytes per keypoint slot, indexed like kps
+  int64_t off[kMaxBatch];  // first keypoint of each frame
+};
+
+hipError_t launch_describe(const DescArgs& a, hipStream_t s);
+
 // Levels of one ablation launch (in the kernel arguments).
 constexpr int kAbMaxLevels = 64;
 struct AbLevel {

@@ -1577,6 +1577,88 @@ __global__ __launch_bounds__(256) void k_test_segment(const uint8_t* circles, in
 
 // ----------------------------------------------------------------- launches --
 
+// ------------------------------------------------------------------- rBRIEF --
+
+// One wave per keypoint slot.  The angle bin is the largest dot product of (m10, m01)
+// with the 30 bin centres (lane k takes centre k; ties to the smaller k); the 31 x 31
+// patch around the keypoint is staged in LDS; lane l evaluates tests l, l + 64, l + 128
+// and l + 192 of the bin's rotated pattern (5x5 binomial sums compared), and the four
+// ballots are the 256-bit descriptor.  Slots beyond the frame's count, or a workspace
+// that does not hold the expected plan, are left untouched.
+__global__ __launch_bounds__(256) void k_describe(DescArgs a) {
+  __shared__ uint8_t patch[4][31 * 32];
+  const int lane = (int)(threadIdx.x & 63), wave = (int)(threadIdx.x >> 6);
+  const int slot = (int)blockIdx.x * 4 + wave;
+  const int f = slot / a.cap, i = slot - f * a.cap;
+  if (f >= a.n || i >= G(a.counts)[f] || *G(a.ws_sig) != a.sig) return;
+  const u32x4 k0 = *(gptr<const u32x4>)(G(a.kps) + a.off[f] + i);        // x, y, level, m10
+  const int x = (int)k0.x, y = (int)k0.y, level = (int)k0.z, m10 = (int)k0.w;
+  const int m01 = *(gptr<const int32_t>)((gptr<const uint8_t>)(G(a.kps) + a.off[f] + i) + 16);
+  if (level < 0 || level >= a.L) return;
+  const LevelPlan P = a.plan[f * a.L + level];
+  if (x < 15 || y < 15 || x >= P.W - 15 || y >= P.H - 15) return;
+  // angle bin: max over lanes of (dot, -k), packed into one 64-bit key
+  uint64_t key = 0;
+  if (lane < 30) {
+    const int64_t d = (int64_t)m10 * G(a.centres)[2 * lane] +
+                      (int64_t)m01 * G(a.centres)[2 * lane + 1];
+    key = ((uint64_t)(d + (1ll << 40)) << 5) | (uint64_t)(31 - lane);
+  }
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    const uint64_t other = __shfl_xor(key, o, 64);
+    key = other > key ? other : key;
+  }
+  const int bin = 31 - (int)(key & 31);
+  // the 31 x 31 patch (row pitch 32)
+  uint8_t* pt = patch[wave];
+  gptr<const uint8_t> lvl = G(P.lvl);
+  uint8_t v[16];
+#pragma unroll
+  for (int k = 0; k < 16; ++k) {
+    const int idx = lane + 64 * k;
+    v[k] = idx < 961 ? lvl[(size_t)(y - 15 + idx / 31) * P.lvl_stride + x - 15 + idx % 31] : 0;
+  }
+#pragma unroll
+  for (int k = 0; k < 16; ++k) {
+    const int idx = lane + 64 * k;
+    if (idx < 961) pt[(idx / 31) * 32 + idx % 31] = v[k];
+  }
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront", "local");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront", "local");
+  auto smooth = [&](int u, int w) {  // 5x5 binomial sum at patch offset (u, w)
+    const uint8_t* c = pt + (15 + w - 2) * 32 + 15 + u - 2;
+    int s = 0;
+#pragma unroll
+    for (int b = 0; b < 5; ++b) {
+      const int wb = b == 2 ? 6 : (b == 1 || b == 3 ? 4 : 1);
+      const int r = c[0] + 4 * c[1] + 6 * c[2] + 4 * c[3] + c[4];
+      s += wb * r;
+      c += 32;
+    }
+    return s;
+  };
+  gptr<const uint32_t> tbl = (gptr<const uint32_t>)(G(a.rot) + (size_t)bin * 256 * 4);
+  uint64_t words[4];
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    const uint32_t t = tbl[r * 64 + lane];
+    // table points lie within 13 of the keypoint; clamped so that no entry reads outside
+    // the patch
+    const int x1 = min(max((int)(int8_t)(t & 0xff), -13), 13);
+    const int y1 = min(max((int)(int8_t)((t >> 8) & 0xff), -13), 13);
+    const int x2 = min(max((int)(int8_t)((t >> 16) & 0xff), -13), 13);
+    const int y2 = min(max((int)(int8_t)(t >> 24), -13), 13);
+    words[r] = __ballot(smooth(x1, y1) < smooth(x2, y2));
+  }
+  if (lane == 0) {
+    gptr<uint64_t> d = (gptr<uint64_t>)(G(a.desc) + (size_t)(a.off[f] + i) * 32);
+#pragma unroll
+    for (int r = 0; r < 4; ++r) d[r] = words[r];
+  }
+}
+
 // ----------------------------------------------------------------- ablation --
 // Kernels of the ablation ladder.  Each computes one step of one pyramid level the way
 // an earlier design does, so that the gain of every design decision can be measured on
@@ -2053,6 +2135,11 @@ hipError_t launch_ablate_harris(const AbArgs& a, int variant, hipStream_t s) {
     case 2: OF_LAUNCH(k_ab_harris_groups, grid, dim3(256), 0, s, a); break;
     default: OF_LAUNCH(k_ab_harris_dense, grid, dim3(256), 0, s, a); break;
   }
+  return hipGetLastError();
+}
+
+hipError_t launch_describe(const DescArgs& a, hipStream_t s) {
+  OF_LAUNCH(k_describe, dim3(cdiv(a.n * a.cap, 4)), dim3(256), 0, s, a);
   return hipGetLastError();
 }
 

@@ -76,6 +76,9 @@ def lib() -> ctypes.CDLL:
         L.of_tuning_default.argtypes = [P(OfImage), i32, P(OfParams), P(OfTuning)]
         L.of_test_segment.argtypes = [vp, i32, i32, i32, vp, vp]
         L.of_candidate_counts.argtypes = [P(OfImage), i32, P(OfParams), vp, vp, vp]
+        L.of_brief_tables.argtypes = [vp, vp, vp]
+        L.of_describe.argtypes = [P(OfImage), i32, P(OfParams), P(OfTuning), vp, vp, i64p, vp,
+                                  vp, vp, vp, vp]
         L.of_ablate_fast.argtypes = [P(OfImage), i32, i32, i32, i32, P(vp), vp]
         L.of_ablate_harris.argtypes = [P(OfImage), i32, P(vp), P(i32), i32, P(vp), vp]
         L.of_profile_enable.argtypes = [ctypes.c_int]
@@ -170,6 +173,27 @@ def of_candidate_counts(images, p: OfParams, ws_ptr: int, out_ptr: int, stream: 
     arr = (OfImage * n)(*images)
     _check(lib().of_candidate_counts(arr, n, ctypes.byref(p), ws_ptr, out_ptr, stream),
            "of_candidate_counts")
+
+
+def of_brief_tables(pattern):
+    """(rot [30, 256, 4] int8, centres [30, 2] int32) for a 256 x 4 int8 test pattern."""
+    pattern = np.ascontiguousarray(pattern, dtype=np.int8)
+    assert pattern.shape == (256, 4)
+    rot = np.zeros((30, 256, 4), np.int8)
+    centres = np.zeros((30, 2), np.int32)
+    _check(lib().of_brief_tables(pattern.ctypes.data, rot.ctypes.data, centres.ctypes.data),
+           "of_brief_tables")
+    return rot, centres
+
+
+def of_describe(images, p: OfParams, tune, ws_ptr: int, kps_ptr: int, kp_offsets, counts_ptr: int,
+                rot_ptr: int, centres_ptr: int, desc_ptr: int, stream: int) -> None:
+    n = len(images)
+    arr = (OfImage * n)(*images)
+    offs = (ctypes.c_int64 * n)(*[int(o) for o in kp_offsets])
+    _check(lib().of_describe(arr, n, ctypes.byref(p), ctypes.byref(tune) if tune is not None
+                             else None, ws_ptr, kps_ptr, offs, counts_ptr, rot_ptr,
+                             centres_ptr, desc_ptr, stream), "of_describe")
 
 
 AB_FAST = {"branchy": 0, "masks": 1, "masks_lds": 2, "minmax_lds": 3}
@@ -283,6 +307,16 @@ class Detector:
         of_candidate_counts([image_of(f) for f in frames], self.p, self.ws.data_ptr(),
                             out.data_ptr(), stream_ptr(stream))
         return out.cpu().numpy().reshape(self.n, self.p.n_levels)
+
+    def describe(self, frames, rot, centres, tune: OfTuning | None = None, stream=None):
+        """rBRIEF of the last detection's keypoints: device (n * cap, 32) uint8; rot and
+        centres are device tensors from of_brief_tables."""
+        torch = _torch()
+        desc = torch.zeros((self.n * self.cap, 32), dtype=torch.uint8, device=self.ws.device)
+        of_describe([image_of(f) for f in frames], self.p, tune, self.ws.data_ptr(),
+                    self.out.data_ptr(), self.offsets, self.counts.data_ptr(), rot.data_ptr(),
+                    centres.data_ptr(), desc.data_ptr(), stream_ptr(stream))
+        return desc
 
     def results(self):
         """Per frame, a structured numpy array of its keypoints (synchronises)."""

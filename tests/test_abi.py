@@ -4,6 +4,7 @@ import ctypes
 import os
 import re
 
+import numpy as np
 import pytest
 
 import oracle
@@ -147,3 +148,34 @@ def test_ablation_entry_points_validate_before_launch(lib):
     assert lib.of_ablate_harris(bad, 1, None, None, 3, one, None) == ofhip.OF_EINVAL
     # nothing to score: returns before any launch
     assert lib.of_ablate_harris(arr, 1, null, zero, 0, one, None) == ofhip.OF_OK
+
+
+def test_brief_tables_match_the_oracle(lib):
+    """The library's steered tables (its own host code) equal the oracle's."""
+    import oracle
+    from synth import brief_pattern
+    for seed in (4242, 7):
+        pat = brief_pattern(seed)
+        got = ofhip.of_brief_tables(pat)
+        want = oracle.brief_tables(pat)
+        np.testing.assert_array_equal(got[0], want[0])
+        np.testing.assert_array_equal(got[1], want[1])
+
+
+def test_describe_validates_before_launch(lib):
+    p = ofhip.params(n_levels=2, cell=30, n_features=100)
+    imgs = (ofhip.OfImage * 1)(ofhip.OfImage(0x1000, 200, 150, 200))
+    offs = (ctypes.c_int64 * 1)(0)
+    ok = [imgs, 1, ctypes.byref(p), None, 0x1000, 0x1000, offs, 0x1000, 0x1000, 0x1000, 0x1000,
+          None]
+    for k in (4, 5, 6, 7, 8, 9, 10):  # each device pointer / host array null in turn
+        args = list(ok)
+        args[k] = None
+        assert lib.of_describe(*args) == ofhip.OF_EINVAL, k
+    args = list(ok)
+    args[1] = 0
+    assert lib.of_describe(*args) == ofhip.OF_EINVAL
+    bad = ofhip.tuning(mark_words=9)
+    args = list(ok)
+    args[3] = ctypes.byref(bad)
+    assert lib.of_describe(*args) == ofhip.OF_EINVAL

@@ -1,0 +1,78 @@
+"""rBRIEF on the GPU (steered 256-bit descriptors) against the oracle, bit for bit."""
+import numpy as np
+import pytest
+
+import oracle
+from synth import CONFIGS, FrameSpec, brief_pattern, make_frame
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+def log(msg):
+    print(msg, flush=True)
+
+
+@pytest.fixture(scope="module")
+def env():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2506_07164_amd import ofhip
+    rot, cen = ofhip.of_brief_tables(brief_pattern())
+    return ofhip, torch.from_numpy(rot).cuda(), torch.from_numpy(cen).cuda(), rot, cen
+
+
+def _oracle_desc(img, kw, kps, rot, cen):
+    p = oracle.params(**kw)
+    levels = oracle.pyramid(img, p)
+    out = np.zeros((len(kps), 32), np.uint8)
+    for l in range(p.n_levels):
+        sel = np.nonzero(kps["level"] == l)[0]
+        if len(sel):
+            out[sel] = oracle.describe(levels[l], kps[sel], rot, cen)
+    return out
+
+
+@pytest.mark.parametrize("which", ["c2", "small", "batch"])
+def test_describe_equals_oracle(env, which):
+    ofhip, rot_d, cen_d, rot, cen = env
+    if which == "c2":
+        specs, kw = [CONFIGS["c2"]["frames"][0]], CONFIGS["c2"]["params"]
+    elif which == "small":
+        specs = [FrameSpec(400, 300, 5, 60, 2.0)]
+        kw = dict(n_levels=3, fast_t=20, fast_t_min=7, cell=0, n_features=300)
+    else:
+        specs = [FrameSpec(w, h, 80 + i, 50, 2.5) for i, (w, h) in
+                 enumerate([(640, 480), (333, 257), (720, 540)])]
+        kw = dict(n_levels=5, fast_t=20, fast_t_min=7, cell=30, n_features=700)
+    log(f"case: describe {which}")
+    imgs = [make_frame(s) for s in specs]
+    frames = [torch.from_numpy(i).cuda() for i in imgs]
+    det = ofhip.Detector([i.shape for i in imgs], ofhip.params(**kw))
+    det.detect_batch(frames)
+    got = det.describe(frames, rot_d, cen_d).cpu().numpy()
+    res = det.results()
+    for f, img in enumerate(imgs):
+        want = _oracle_desc(img, kw, res[f], rot, cen)
+        o = det.offsets[f]
+        np.testing.assert_array_equal(got[o:o + len(res[f])], want, err_msg=f"frame {f}")
+        assert not got[o + len(res[f]):o + det.cap].any()   # slots beyond the count
+    if which == "small":
+        # plain path on the same workspace
+        det.detect_plain(frames[0])
+        got = det.describe(frames, rot_d, cen_d).cpu().numpy()
+        np.testing.assert_array_equal(got[:len(res[0])], _oracle_desc(imgs[0], kw, res[0], rot, cen))
+
+
+def test_describe_with_another_plan_writes_nothing(env):
+    ofhip, rot_d, cen_d, rot, cen = env
+    kw = dict(n_levels=3, fast_t=20, fast_t_min=7, cell=30, n_features=300)
+    img = make_frame(FrameSpec(400, 300, 6, 60, 2.0))
+    frame = torch.from_numpy(img).cuda()
+    det = ofhip.Detector([img.shape], ofhip.params(**kw))
+    det.detect_batch([frame], tune=ofhip.tuning(mark_rows=8))
+    # a different launch shape than the detection used: the plan signature differs
+    got = det.describe([frame], rot_d, cen_d, tune=ofhip.tuning(mark_rows=16))
+    assert not got.cpu().numpy().any()
+    got = det.describe([frame], rot_d, cen_d, tune=ofhip.tuning(mark_rows=8))
+    assert got.cpu().numpy().any()
