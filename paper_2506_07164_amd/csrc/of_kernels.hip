@@ -527,6 +527,7 @@ __global__ __launch_bounds__(1024) void k_prologue(PrologueArgs a) {
     P.cand_count = counters + i;
     P.cand_cap = (int32_t)s.cand_cap;
     P.kslot = s.kslot;
+    P.compact = a.p.cell == 0 && s.cand_cap > kRankCap;
     P.slot_w = s.slot_w;
     P.sel = (Cand*)(ws + a.lay.off_sel) + o_sel;
     P.sel_count = counters + a.lay.n_entries + i;
@@ -1262,6 +1263,9 @@ __global__ __launch_bounds__(256, 4) void k_detect(KArgs a) {
           if (a.cell > 0) {
             const int r = (int)atomicAdd(&ckept[c], 1u);
             slot = ((y / cs - P.det_y0) * nvx + (x / cs - P.det_x0)) * P.kslot + r;
+          } else if (P.compact) {  // listed here, appended below
+            order[atomicAdd(&s_ne, 1)] = (uint16_t)s;
+            continue;
           } else {
             slot = ((y - B) >> 1) * P.slot_w + ((x - B) >> 1);
             order[((y - vy0) >> 1) * nbx + ((x - vx0) >> 1)] = 1;
@@ -1272,6 +1276,21 @@ __global__ __launch_bounds__(256, 4) void k_detect(KArgs a) {
       }
     }
     lds_barrier();
+    if (P.compact) {
+      // Levels with more candidate slots than the rank path takes: the kept survivors
+      // are appended after the level's filled count (one reserving atomic per tile), so
+      // the radix select reads filled entries only.
+      if (tid == 0) s_ns = s_ne > 0 ? (int)atomicAdd(P.cand_count, (uint32_t)s_ne) : 0;
+      lds_barrier();
+      const int base = s_ns, ne = s_ne;
+      for (int k = tid; k < ne; k += bd) {
+        const int ci = sci[order[k]];
+        const uint32_t pos = cand_pos(ci);
+        if (base + k < P.cand_cap) store_cand(out + base + k, cand_score(ci, pos), pos);
+      }
+      queue_park(a, next, &s_next);
+      continue;
+    }
     if (a.cell > 0) {
       const int ks = P.kslot;
       for (int i = tid; i < ncell * ks; i += bd) {
@@ -1400,9 +1419,10 @@ __global__ __launch_bounds__(1024) void k_select(KArgs a) {
   const int e = a.entry >= 0 ? a.entry : (int)blockIdx.x;
   const LevelPlan P = a.plan[e];
   const int N = P.quota;
-  const int C = P.cand_cap;  // slots; empty ones hold the sentinel and are skipped
-  if (a.rank_path && C <= kRankCap) return;  // handled by k_select_orient
+  if (a.rank_path && P.cand_cap <= kRankCap) return;  // handled by k_select_orient
   const int nfill = (int)*G(P.cand_count);
+  // slots (empty ones hold the sentinel and are skipped), or the appended entries
+  const int C = P.compact ? min(nfill, P.cand_cap) : P.cand_cap;
   const int nout = min(nfill, N);
   if (nout <= 0) {
     if (threadIdx.x == 0) *G(P.sel_count) = 0;

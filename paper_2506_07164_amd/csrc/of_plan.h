@@ -63,6 +63,7 @@ struct LevelPlan {
   uint32_t* cand_count;        // filled slots
   int32_t cand_cap;            // slots (filled or holding the kNoPos sentinel)
   int32_t kslot;               // slots per cell (cell > 0)
+  int32_t compact;             // 1: no fixed slots; tiles append (level past kRankCap, cell 0)
   Cand* sel;                   // level selection, sorted, quota entries
   uint32_t* sel_count;
   uint32_t* ncand_count;       // FAST candidates of the level (statistics)
