@@ -153,7 +153,7 @@ def main():
     print(f"# workload {spec.width}x{spec.height} L={kw['n_levels']} N={kw['n_features']}",
           file=sys.stderr, flush=True)
 
-    fused = ofhip.Detector([img.shape], p)
+    fused = ofhip.Detector([img.shape], p, resident=True)
     plain = ofhip.Detector([img.shape], p)
     stream = torch.cuda.Stream()
 

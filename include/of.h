@@ -92,8 +92,8 @@ typedef struct {
 } of_pyramid_desc;
 
 /* Launch shape of the batched path (tile sizes, grid sizes, pyramid pass).  Tile fields
- * set to 0 take the default; grid, pyr_pass and mark_order fields take the default when
- * negative.
+ * set to 0 take the default; grid, pyr_pass, mark_order and plan_resident fields take
+ * the default when negative.
  * of_tuning_default() reports the defaults for a batch.  det_w and det_h must be even. */
 typedef struct {
   int32_t mark_words; /* segment-test tile width in 64-pixel words, 1..4 */
@@ -107,6 +107,13 @@ typedef struct {
   int32_t mark_order; /* 1 = segment-test tiles ordered by XCD band (block b takes band
                          b % 8 of every level, so each XCD's L2 holds one band of each
                          frame); 0 = entry-major order.  Ignored with a persistent grid. */
+  int32_t plan_resident; /* 1 = the caller keeps `ws` for this library's calls only: the
+                         plan (built by a first launch whenever the frames, sizes,
+                         parameters or tuning change) is then reused without that launch
+                         when this workspace already holds it.  Every kernel checks the
+                         plan's signature; if ws was overwritten in between, nothing is
+                         computed and every frame's count reads -1.  0 = always re-check
+                         with a launch of its own (any workspace). */
 } of_tuning;
 
 /* Host only.  Level sizes, strides and offsets of the pyramid of a W x H frame. */

@@ -55,6 +55,36 @@ hipError_t timed(int step, hipStream_t s, F&& launch, bool repeatable = false) {
   return e;
 }
 
+// Last plan built on each workspace (by any call's prologue), for calls that keep their
+// plan resident: the prologue is skipped when the workspace already holds this plan.
+struct ResidentPlans {
+  std::mutex mu;
+  const void* ws[64] = {};
+  uint64_t sig[64] = {};
+  int next = 0;
+};
+
+ResidentPlans g_resident;
+
+bool resident_holds(const void* ws, uint64_t sig) {
+  std::lock_guard<std::mutex> lk(g_resident.mu);
+  for (int i = 0; i < 64; ++i)
+    if (g_resident.ws[i] == ws) return g_resident.sig[i] == sig;
+  return false;
+}
+
+void resident_record(const void* ws, uint64_t sig) {
+  std::lock_guard<std::mutex> lk(g_resident.mu);
+  for (int i = 0; i < 64; ++i)
+    if (g_resident.ws[i] == ws) {
+      g_resident.sig[i] = sig;
+      return;
+    }
+  g_resident.ws[g_resident.next] = ws;
+  g_resident.sig[g_resident.next] = sig;
+  g_resident.next = (g_resident.next + 1) % 64;
+}
+
 int hip_fail(hipError_t e) {
   g_last_hip = (int)e;
   return OF_EHIP;
@@ -123,6 +153,7 @@ Tune default_tune(const of_params& p) {
   t.det_grid = 0;
   t.pyr_pass = 0;
   t.mark_order = 0;
+  t.plan_resident = 0;
   // narrower Harris tiles where large cells would exceed the LDS budget
   while (p.cell > 0 && t.det_cx > 1 &&
          det_lds(t, p.cell).bytes + base_table_bytes(kMaxEntries) > 65536)
@@ -143,6 +174,7 @@ int resolve_tune(const of_tuning* user, const of_params& p, Tune* out) {
     if (user->det_grid >= 0) t.det_grid = user->det_grid;
     if (user->pyr_pass >= 0) t.pyr_pass = user->pyr_pass != 0;
     if (user->mark_order >= 0) t.mark_order = user->mark_order != 0;
+    if (user->plan_resident >= 0) t.plan_resident = user->plan_resident != 0;
   }
   if (t.mark_words < 1 || t.mark_words > 4 || t.mark_rows < 4 || t.mark_rows > 64)
     return OF_EINVAL;
@@ -238,6 +270,9 @@ KArgs kargs(void* ws, const WsLayout& lay, const Tune& t, const of_params& p) {
   k.orient_base = (const int32_t*)(b + lay.off_orient_base);
   k.rank_base = (const int32_t*)(b + lay.off_rank_base);
   k.pyr_base = (const int32_t*)(b + lay.off_pyr_base);
+  k.counters = (uint32_t*)(b + lay.off_counters);
+  k.flags = b + lay.off_flags;
+  k.flag_bytes = lay.flag_bytes;
   k.band_base = (const int32_t*)(b + lay.off_band_base);
   k.rank_path = 1;
   k.qctr = (uint32_t*)(b + lay.off_hdr);
@@ -378,6 +413,7 @@ int of_tuning_default(const of_image* frames, int32_t n, const of_params* params
   out->det_grid = t.det_grid;
   out->pyr_pass = t.pyr_pass;
   out->mark_order = t.mark_order;
+  out->plan_resident = t.plan_resident;
   return OF_OK;
 }
 
@@ -399,6 +435,7 @@ int of_detect(const of_image* in, const of_params* params, void* ws, size_t ws_b
   PrologueArgs* pa = new PrologueArgs;
   fill_prologue(pa, in, 1, p, t, ws, c->lay, out, nullptr, count);
   hipError_t e = timed(0, stream, [&] { return launch_prologue(*pa, prologue_grid(c->lay), stream); });
+  resident_record(ws, pa->sig);
   delete pa;
   const int L = p.n_levels;
   // levels 1.. from the input frame, one launch per level
@@ -456,9 +493,18 @@ int of_detect_batch(const of_image* frames, int32_t n, const of_params* params, 
   }
   PrologueArgs* pa = new PrologueArgs;
   fill_prologue(pa, frames, n, p, t, ws, c->lay, out, out_offset, counts);
-  hipError_t e = timed(0, stream, [&] { return launch_prologue(*pa, prologue_grid(c->lay), stream); });
+  const uint64_t sig = pa->sig;
+  hipError_t e = hipSuccess;
+  if (!(t.plan_resident && resident_holds(ws, sig))) {
+    e = timed(0, stream, [&] { return launch_prologue(*pa, prologue_grid(c->lay), stream); });
+    resident_record(ws, sig);
+  }
   delete pa;
   KArgs k = kargs(ws, c->lay, t, p);
+  k.sig = sig;
+  k.ws_sig = (const uint64_t*)((const uint8_t*)ws + c->lay.off_hdr + 128);
+  k.frame_counts = counts;
+  k.n_frames = n;
   const bool fused = !t.pyr_pass || c->lay.pyr_blocks == 0;
   if (e == hipSuccess && !fused) {
     k.total = c->lay.pyr_blocks;

@@ -44,6 +44,18 @@ struct KArgs {
   int32_t rank_path;           // 1: k_select_orient ranks levels with <= kRankCap candidates
   int32_t bands;               // 1: k_mark block b takes band b % kXcds, tile b / kXcds of it
   Tune t;
+  // Batched path: the plan signature the workspace must hold (blocks of a workspace with
+  // another plan do nothing; the selection then sets every frame's count to -1), and
+  // the state each call leaves zeroed for the next: k_mark clears the counters, the
+  // selection clears the cell flags and the segment-test queue counter.
+  uint64_t sig;
+  const uint64_t* ws_sig;      // null: no check (plain path)
+  uint32_t* counters;          // 3 per entry
+  uint8_t* flags;
+  int64_t flag_bytes;          // multiple of 16
+  int32_t* frame_counts;
+  int32_t n_frames;
+  int32_t pad2;
   // Batches of at most kSmallEntries entries carry the launch's prefix table here (one row,
   // or kXcds rows for the band order), so blocks find their entry without a memory load.
   int32_t small;

@@ -93,6 +93,11 @@ __device__ __forceinline__ int find_entry(const int32_t* base, int n, int g) {
   return lo;
 }
 
+// The workspace holds the plan this launch was made for (always true on the plain path).
+__device__ __forceinline__ bool plan_ok(const KArgs& a) {
+  return a.ws_sig == nullptr || *G(a.ws_sig) == a.sig;
+}
+
 // Entry of tile g and the entry's first tile, from row `row` of the prefix table in the
 // kernel arguments (batches of at most kSmallEntries entries).  Unrolled with constant
 // indices: scalar loads of the argument segment, no search through memory.
@@ -619,6 +624,7 @@ __global__ __launch_bounds__(256) void k_pyramid(PyrArgs a) {
 __global__ __launch_bounds__(256) void k_pyramid_batch(KArgs a) {
   __shared__ uint32_t xt[64], yt[16];
   __shared__ int32_t s_base[kMaxEntries + 1];
+  if (!plan_ok(a)) return;
   const int g = (int)blockIdx.x;
   int e, b;
   if (a.small) {
@@ -660,6 +666,11 @@ __global__ __launch_bounds__(256, TWW <= 2 ? 5 : 4) void k_mark(KArgs a) {
   // XCD bands: block b runs on XCD b % kXcds and takes tile b / kXcds of band b % kXcds
   // (the same rows of every level of every frame), so each XCD's L2 holds one band of
   // the frames that its tiles resample from.
+  if (!plan_ok(a)) return;
+  if (a.entry < 0 && blockIdx.x == 0) {  // counters of this call (read after this kernel)
+    for (int i = threadIdx.x; i < 3 * a.n_entries; i += blockDim.x) G(a.counters)[i] = 0u;
+    if (threadIdx.x == 0) G(a.qctr)[2] = 0u;
+  }
   const int band = a.bands ? (int)(blockIdx.x % kXcds) : 0;
   if (a.entry < 0 && !a.small)
     load_bases(s_base, a.bands ? a.band_base + band * (a.n_entries + 1) : a.mark_base,
@@ -929,6 +940,7 @@ __global__ __launch_bounds__(256, 4) void k_detect(KArgs a) {
   int32_t* s_base = (int32_t*)(smem + D.bytes);
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nwave = blockDim.x >> 6;
   const int bd = (int)blockDim.x, tid = (int)threadIdx.x;
+  if (!plan_ok(a)) return;
   if (a.entry < 0 && !a.small) load_bases(s_base, a.det_base, a.n_entries);
   queue_start(a, a.qctr + 2, &s_next);
 
@@ -1323,6 +1335,19 @@ __global__ __launch_bounds__(256, 4) void k_detect(KArgs a) {
 // the radix-select path.
 __global__ __launch_bounds__(256) void k_select_orient(KArgs a) {
   __shared__ int32_t s_base[kMaxEntries + 1];
+  if (!plan_ok(a)) {
+    if (blockIdx.x == 0 && (int)threadIdx.x < a.n_frames) G(a.frame_counts)[threadIdx.x] = -1;
+    return;
+  }
+  if (a.flags) {  // cell flags and the segment-test queue counter, zero for the next call
+    const int64_t nq = a.flag_bytes / 16;
+    const int64_t per = (nq + gridDim.x - 1) / gridDim.x;
+    const int64_t q0 = (int64_t)blockIdx.x * per, q1 = min(q0 + per, nq);
+    const u32x4 zero = {0u, 0u, 0u, 0u};
+    for (int64_t q = q0 + threadIdx.x; q < q1; q += blockDim.x)
+      ((gptr<u32x4>)G(a.flags))[q] = zero;
+    if (blockIdx.x == 0 && threadIdx.x == 0) G(a.qctr)[0] = 0u;
+  }
   if (!a.small) load_bases(s_base, a.rank_base, a.n_entries);
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int slot = (int)blockIdx.x * (blockDim.x >> 6) + wave;

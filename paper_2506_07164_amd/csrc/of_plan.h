@@ -30,6 +30,7 @@ struct Tune {
   int32_t mark_grid, det_grid;
   int32_t pyr_pass;  // 1: levels are resampled by a separate pass before the segment test
   int32_t mark_order;  // 1: segment-test tiles in XCD bands (block b on XCD b % 8)
+  int32_t plan_resident;  // 1: skip the prologue when this workspace holds this plan
 };
 
 constexpr int kXcds = 8;  // blocks are dispatched to the XCDs round-robin by block index

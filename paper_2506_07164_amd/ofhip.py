@@ -47,7 +47,7 @@ class OfPyramidDesc(ctypes.Structure):
 class OfTuning(ctypes.Structure):
     _fields_ = [(n, ctypes.c_int32) for n in (
         "mark_words", "mark_rows", "det_cells_x", "det_cells_y", "det_w", "det_h",
-        "mark_grid", "det_grid", "pyr_pass", "mark_order")]
+        "mark_grid", "det_grid", "pyr_pass", "mark_order", "plan_resident")]
 
 
 KEYPOINT_DTYPE = np.dtype([("x", "<i4"), ("y", "<i4"), ("level", "<i4"), ("m10", "<i4"),
@@ -116,6 +116,7 @@ def tuning(**kw) -> OfTuning:
     t.det_grid = -1
     t.pyr_pass = -1
     t.mark_order = -1
+    t.plan_resident = -1
     for k, v in kw.items():
         setattr(t, k, v)
     return t
@@ -277,9 +278,12 @@ def keypoints_to_numpy(raw, count: int) -> np.ndarray:
 class Detector:
     """Owns a workspace and output buffers for repeated detection on fixed shapes."""
 
-    def __init__(self, shapes, p: OfParams, device="cuda"):
+    def __init__(self, shapes, p: OfParams, device="cuda", resident: bool = False):
+        """resident: the workspace belongs to this detector alone, so batched calls keep
+        their plan resident (of_tuning.plan_resident) and skip re-planning."""
         torch = _torch()
         self.p = p
+        self.resident = resident
         self.shapes = list(shapes)  # [(H, W), ...]
         self.n = len(self.shapes)
         dummy = [OfImage(None, w, h, w) for h, w in self.shapes]
@@ -294,11 +298,20 @@ class Detector:
         of_detect(image_of(frame), self.p, self.ws.data_ptr(), self.ws.numel(),
                   self.out.data_ptr(), self.cap, self.counts.data_ptr(), stream_ptr(stream))
 
+    def _tune(self, tune):
+        if not self.resident:
+            return tune
+        t = OfTuning()
+        ctypes.memmove(ctypes.byref(t), ctypes.byref(tune if tune is not None else tuning()),
+                       ctypes.sizeof(OfTuning))
+        t.plan_resident = 1
+        return t
+
     def detect_batch(self, frames, tune: OfTuning | None = None, stream=None):
         assert len(frames) == self.n
         of_detect_batch([image_of(f) for f in frames], self.p, self.ws.data_ptr(),
                         self.ws.numel(), self.out.data_ptr(), self.offsets, self.cap,
-                        self.counts.data_ptr(), tune, stream_ptr(stream))
+                        self.counts.data_ptr(), self._tune(tune), stream_ptr(stream))
 
     def candidates(self, frames, stream=None):
         """FAST candidates per (frame, level) of the last detection (synchronises)."""
@@ -313,7 +326,7 @@ class Detector:
         centres are device tensors from of_brief_tables."""
         torch = _torch()
         desc = torch.zeros((self.n * self.cap, 32), dtype=torch.uint8, device=self.ws.device)
-        of_describe([image_of(f) for f in frames], self.p, tune, self.ws.data_ptr(),
+        of_describe([image_of(f) for f in frames], self.p, self._tune(tune), self.ws.data_ptr(),
                     self.out.data_ptr(), self.offsets, self.counts.data_ptr(), rot.data_ptr(),
                     centres.data_ptr(), desc.data_ptr(), stream_ptr(stream))
         return desc

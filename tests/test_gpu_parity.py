@@ -350,3 +350,46 @@ def test_candidate_counts_match_oracle(hip, which):
     assert det.candidates([frame])[0].tolist() == want
     det.detect_plain(frame)
     assert det.candidates([frame])[0].tolist() == want
+
+
+def test_resident_plan(hip):
+    """plan_resident: identical results call after call (state left zeroed for the next
+    call), in a graph with new frame contents, with persistent grids; an overwritten
+    workspace yields count -1 instead of a result."""
+    kw = CONFIGS["c2"]["params"]
+    log("case: resident plan")
+    specs = [FrameSpec(960, 540, 120 + i, 60, 3.0) for i in range(3)]
+    imgs = [make_frame(s) for s in specs]
+    refs = [oracle.detect(i, oracle.params(**kw)) for i in imgs]
+    slot = torch.from_numpy(imgs[0]).cuda()
+    det = hip.Detector([imgs[0].shape], hip.params(**kw), resident=True)
+    for k in range(3):
+        slot.copy_(torch.from_numpy(imgs[k]))
+        det.detect_batch([slot])
+        assert_same_keypoints(det.results()[0], refs[k], f"resident call {k}")
+    for tune in (dict(mark_grid=64, det_grid=32), dict(mark_order=1, pyr_pass=1)):
+        for k in range(2):
+            slot.copy_(torch.from_numpy(imgs[k]))
+            det.detect_batch([slot], tune=hip.tuning(**tune))
+            assert_same_keypoints(det.results()[0], refs[k], f"resident {tune} {k}")
+    stream = torch.cuda.Stream()
+    g = torch.cuda.CUDAGraph()
+    torch.cuda.synchronize()
+    with torch.cuda.stream(stream):
+        det.detect_batch([slot], stream=stream)
+        torch.cuda.synchronize()
+        with torch.cuda.graph(g, stream=stream):
+            det.detect_batch([slot], stream=stream)
+    for k in (2, 0, 1):
+        slot.copy_(torch.from_numpy(imgs[k]))
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        assert_same_keypoints(det.results()[0], refs[k], f"resident graph replay {k}")
+    det.ws.zero_()
+    det.detect_batch([slot])
+    assert det.counts.cpu().tolist() == [-1]
+    plain = hip.Detector([imgs[0].shape], hip.params(**kw))
+    plain.ws = det.ws  # a non-resident call on the same workspace re-plans it
+    plain.detect_batch([slot])
+    assert_same_keypoints(plain.results()[0], refs[1], "after re-plan")
