@@ -93,9 +93,11 @@ __device__ __forceinline__ int find_entry(const int32_t* base, int n, int g) {
   return lo;
 }
 
-// The workspace holds the plan this launch was made for (always true on the plain path).
-__device__ __forceinline__ bool plan_ok(const KArgs& a) {
-  return a.ws_sig == nullptr || *G(a.ws_sig) == a.sig;
+// Signature of the plan the workspace holds (the expected one on the plain path).  Read
+// first and compared only before the plan's pointers are used, so the check costs no
+// round trip of its own.
+__device__ __forceinline__ uint64_t held_sig(const KArgs& a) {
+  return a.ws_sig == nullptr ? a.sig : *G(a.ws_sig);
 }
 
 // Entry of tile g and the entry's first tile, from row `row` of the prefix table in the
@@ -624,7 +626,7 @@ __global__ __launch_bounds__(256) void k_pyramid(PyrArgs a) {
 __global__ __launch_bounds__(256) void k_pyramid_batch(KArgs a) {
   __shared__ uint32_t xt[64], yt[16];
   __shared__ int32_t s_base[kMaxEntries + 1];
-  if (!plan_ok(a)) return;
+  const uint64_t wsig = held_sig(a);
   const int g = (int)blockIdx.x;
   int e, b;
   if (a.small) {
@@ -637,6 +639,7 @@ __global__ __launch_bounds__(256) void k_pyramid_batch(KArgs a) {
     b = g - s_base[e];
   }
   const LevelPlan P = a.plan[e];
+  if (wsig != a.sig) return;  // not the plan this launch was made for
   const int nbx = (P.W + 63) >> 6;
   const int by = b / nbx, bx = b - by * nbx;
   resample_block(G(P.base), P.base_w, P.base_h, P.base_stride, G(P.lvl_w), P.W, P.H,
@@ -666,7 +669,7 @@ __global__ __launch_bounds__(256, TWW <= 2 ? 5 : 4) void k_mark(KArgs a) {
   // XCD bands: block b runs on XCD b % kXcds and takes tile b / kXcds of band b % kXcds
   // (the same rows of every level of every frame), so each XCD's L2 holds one band of
   // the frames that its tiles resample from.
-  if (!plan_ok(a)) return;
+  const uint64_t wsig = held_sig(a);
   if (a.entry < 0 && blockIdx.x == 0) {  // counters of this call (read after this kernel)
     for (int i = threadIdx.x; i < 3 * a.n_entries; i += blockDim.x) G(a.counters)[i] = 0u;
     if (threadIdx.x == 0) G(a.qctr)[2] = 0u;
@@ -699,6 +702,7 @@ __global__ __launch_bounds__(256, TWW <= 2 ? 5 : 4) void k_mark(KArgs a) {
       t = g - s_base[e];
     }
     const LevelPlan P = a.plan[e];
+    if (wsig != a.sig) break;  // not the plan this launch was made for
     const int W = P.W, H = P.H, B = P.B;
     const int tx = t % P.mark_tx;
     const int ty = t / P.mark_tx + (a.bands ? band_row0(P.mark_ty, band) : 0);
@@ -940,7 +944,7 @@ __global__ __launch_bounds__(256, 4) void k_detect(KArgs a) {
   int32_t* s_base = (int32_t*)(smem + D.bytes);
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nwave = blockDim.x >> 6;
   const int bd = (int)blockDim.x, tid = (int)threadIdx.x;
-  if (!plan_ok(a)) return;
+  const uint64_t wsig = held_sig(a);
   if (a.entry < 0 && !a.small) load_bases(s_base, a.det_base, a.n_entries);
   queue_start(a, a.qctr + 2, &s_next);
 
@@ -962,6 +966,7 @@ __global__ __launch_bounds__(256, 4) void k_detect(KArgs a) {
       t = g - s_base[e];
     }
     const LevelPlan P = a.plan[e];
+    if (wsig != a.sig) break;  // not the plan this launch was made for
     const int W = P.W, H = P.H, B = P.B, cs = P.cs;
     const int tx = t % P.det_tx, ty = t / P.det_tx;
     int vx0, vx1, vy0, vy1, cxa = 0, cya = 0, nlcx = 1, nlcy = 1;
@@ -1335,8 +1340,9 @@ __global__ __launch_bounds__(256, 4) void k_detect(KArgs a) {
 // the radix-select path.
 __global__ __launch_bounds__(256) void k_select_orient(KArgs a) {
   __shared__ int32_t s_base[kMaxEntries + 1];
-  if (!plan_ok(a)) {
-    if (blockIdx.x == 0 && (int)threadIdx.x < a.n_frames) G(a.frame_counts)[threadIdx.x] = -1;
+  const uint64_t wsig = held_sig(a);
+  if (blockIdx.x == 0 && wsig != a.sig) {  // not the plan this launch was made for
+    if ((int)threadIdx.x < a.n_frames) G(a.frame_counts)[threadIdx.x] = -1;
     return;
   }
   if (a.flags) {  // cell flags and the segment-test queue counter, zero for the next call
@@ -1364,6 +1370,7 @@ __global__ __launch_bounds__(256) void k_select_orient(KArgs a) {
     i = slot - s_base[e];
   }
   const LevelPlan P = a.plan[e];
+  if (wsig != a.sig) return;
   gptr<const uint32_t> counts = G((const uint32_t*)P.cand_count) - e;  // all entries
   const int C = P.cand_cap;  // slots; empty ones hold the sentinel
   if (P.level == 0 && i == 0 && lane == 0) {
@@ -1376,19 +1383,24 @@ __global__ __launch_bounds__(256) void k_select_orient(KArgs a) {
   gptr<const Cand> cand = G((const Cand*)P.cand);
   const Cand me = load_cand(cand + i);
   if (me.pos == kNoPos) return;
-  // Count better candidates, 8 loads in flight per lane; a wave whose partial count
-  // already reaches the quota cannot be selected and stops early.
+  // Count better candidates, 12 slots in flight per lane (score and position only); a
+  // wave whose partial count already reaches the quota cannot be selected and stops.
   int cnt = 0;
-  for (int j0 = 0; j0 < C; j0 += 8 * 64) {
-    Cand o[8];
+  for (int j0 = 0; j0 < C; j0 += 12 * 64) {
+    int64_t sc[12];
+    uint32_t ps[12];
 #pragma unroll
-    for (int u = 0; u < 8; ++u) o[u] = load_cand(cand + min(j0 + u * 64 + lane, C - 1));
-#pragma unroll
-    for (int u = 0; u < 8; ++u) {
-      const int j = j0 + u * 64 + lane;
-      cnt += (j < C && better(o[u].score, o[u].pos, me.score, me.pos)) ? 1 : 0;
+    for (int u = 0; u < 12; ++u) {
+      gptr<const Cand> q = cand + min(j0 + u * 64 + lane, C - 1);
+      sc[u] = *(gptr<const int64_t>)q;
+      ps[u] = *((gptr<const uint32_t>)q + 2);
     }
-    if (j0 + 8 * 64 < C && wave_sum(cnt) >= P.quota) return;
+#pragma unroll
+    for (int u = 0; u < 12; ++u) {
+      const int j = j0 + u * 64 + lane;
+      cnt += (j < C && better(sc[u], ps[u], me.score, me.pos)) ? 1 : 0;
+    }
+    if (j0 + 12 * 64 < C && wave_sum(cnt) >= P.quota) return;
   }
   const int rank = wave_sum(cnt);
   if (rank >= P.quota) return;
