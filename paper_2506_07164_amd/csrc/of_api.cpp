@@ -276,6 +276,7 @@ KArgs kargs(void* ws, const WsLayout& lay, const Tune& t, const of_params& p) {
   k.band_base = (const int32_t*)(b + lay.off_band_base);
   k.rank_path = 1;
   k.qctr = (uint32_t*)(b + lay.off_hdr);
+  k.ws_sig = (const uint64_t*)(b + lay.off_hdr + 128);
   k.n_entries = lay.n_entries;
   k.entry = -1;
   k.cell = p.cell;
@@ -291,17 +292,18 @@ void set_small_bases(KArgs& k, const CallPlan& c, BaseKind kind) {
   const int n = c.lay.n_entries;
   k.small = n <= kSmallEntries;
   if (!k.small) return;
-  const int rows = kind == kMarkBands ? kXcds : 1;
+  const int rows = kind == kMarkBands || kind == kMarkTiles ? kXcds : 1;
   for (int r = 0; r < rows; ++r) {
     int32_t* b = k.sbase + r * (kSmallEntries + 1);
-    int32_t acc = 0;
+    int32_t acc = 0, rot = 0;
     for (int e = 0; e < n; ++e) {
       b[e] = acc;
       const EntrySize& s = c.es[e];
       switch (kind) {
         case kMarkTiles: acc += s.mark_tiles; break;
         case kMarkBands:
-          acc += s.mark_tx * (band_row0(s.mark_ty, r + 1) - band_row0(s.mark_ty, r));
+          acc += s.mark_tx * band_rows(s.mark_ty, rot, r);
+          rot = (rot + s.mark_ty % kXcds) % kXcds;
           break;
         case kDetTiles: acc += s.det_tiles; break;
         case kRankSlots: acc += (int32_t)(s.cand_cap < kRankCap ? s.cand_cap : kRankCap); break;
@@ -309,6 +311,8 @@ void set_small_bases(KArgs& k, const CallPlan& c, BaseKind kind) {
       }
     }
     b[n] = acc;
+    for (int e = n + 1; e < kSmallEntries; ++e) b[e] = INT32_MAX;  // never reached
+    b[kSmallEntries] = acc;
   }
 }
 
@@ -436,6 +440,7 @@ int of_detect(const of_image* in, const of_params* params, void* ws, size_t ws_b
   fill_prologue(pa, in, 1, p, t, ws, c->lay, out, nullptr, count);
   hipError_t e = timed(0, stream, [&] { return launch_prologue(*pa, prologue_grid(c->lay), stream); });
   resident_record(ws, pa->sig);
+  const uint64_t sig = pa->sig;
   delete pa;
   const int L = p.n_levels;
   // levels 1.. from the input frame, one launch per level
@@ -453,6 +458,7 @@ int of_detect(const of_image* in, const of_params* params, void* ws, size_t ws_b
     e = timed(1, stream, [&] { return launch_pyramid(a, 1, a.lv[0].w, a.lv[0].h, stream); }, true);
   }
   KArgs k = kargs(ws, c->lay, t, p);
+  k.sig = sig;
   k.persistent = 0;
   for (int l = 0; l < L && e == hipSuccess; ++l) {
     k.entry = l;
@@ -502,7 +508,6 @@ int of_detect_batch(const of_image* frames, int32_t n, const of_params* params, 
   delete pa;
   KArgs k = kargs(ws, c->lay, t, p);
   k.sig = sig;
-  k.ws_sig = (const uint64_t*)((const uint8_t*)ws + c->lay.off_hdr + 128);
   k.frame_counts = counts;
   k.n_frames = n;
   const bool fused = !t.pyr_pass || c->lay.pyr_blocks == 0;

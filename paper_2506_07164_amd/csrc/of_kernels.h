@@ -28,37 +28,42 @@ struct PrologueArgs {
 
 // Arguments of the tile kernels, selection and orientation.
 struct KArgs {
+  // Read by every block before its first tile, together (the first cache lines of the
+  // argument segment).
   LevelPlan* plan;
+  // The plan signature the workspace must hold: blocks of a workspace with another plan
+  // do nothing (the selection then sets every frame's count to -1).
+  const uint64_t* ws_sig;      // the workspace's copy, written by the prologue
+  uint64_t sig;
+  int32_t n_entries;
+  int32_t total;               // tiles (or blocks) of this launch
+  int32_t entry;               // >= 0: one entry only, tile = blockIdx.x
+  int32_t persistent;          // 1: blocks draw tiles from qctr until exhausted
+  int32_t bands;               // 1: k_mark block b takes band b % kXcds, tile b / kXcds of it
+  int32_t small;               // 1: the prefix table of this launch is in sbase
+  uint32_t* qctr;              // queue counters: [0] segment-test tiles, [2] Harris tiles
+  int32_t cell;                // params.cell
+  int32_t rank_path;           // 1: k_select_orient ranks levels with <= kRankCap candidates
+  Tune t;
+  int32_t pad;
+  // The state each call leaves zeroed for the next: k_mark clears the counters, the
+  // selection clears the cell flags and the segment-test queue counter.
+  uint32_t* counters;          // 3 per entry
+  uint8_t* flags;
+  int64_t flag_bytes;          // multiple of 16
+  int32_t* frame_counts;
   const int32_t* mark_base;    // exclusive prefix of tiles per entry (n_entries + 1)
   const int32_t* det_base;
   const int32_t* orient_base;
   const int32_t* rank_base;    // exclusive prefix of ranked candidate slots per entry
   const int32_t* pyr_base;     // exclusive prefix of resample blocks per entry
   const int32_t* band_base;    // kXcds tables: prefix of segment-test tiles per entry in band k
-  uint32_t* qctr;              // queue counters: [0] segment-test tiles, [2] Harris tiles
-  int32_t n_entries;
-  int32_t total;               // tiles (or blocks) of this launch
-  int32_t entry;               // >= 0: one entry only, tile = blockIdx.x
-  int32_t persistent;          // 1: blocks draw tiles from qctr until exhausted
-  int32_t cell;                // params.cell
-  int32_t rank_path;           // 1: k_select_orient ranks levels with <= kRankCap candidates
-  int32_t bands;               // 1: k_mark block b takes band b % kXcds, tile b / kXcds of it
-  Tune t;
-  // Batched path: the plan signature the workspace must hold (blocks of a workspace with
-  // another plan do nothing; the selection then sets every frame's count to -1), and
-  // the state each call leaves zeroed for the next: k_mark clears the counters, the
-  // selection clears the cell flags and the segment-test queue counter.
-  uint64_t sig;
-  const uint64_t* ws_sig;      // null: no check (plain path)
-  uint32_t* counters;          // 3 per entry
-  uint8_t* flags;
-  int64_t flag_bytes;          // multiple of 16
-  int32_t* frame_counts;
   int32_t n_frames;
-  int32_t pad2;
-  // Batches of at most kSmallEntries entries carry the launch's prefix table here (one row,
-  // or kXcds rows for the band order), so blocks find their entry without a memory load.
-  int32_t small;
+  // Batches of at most kSmallEntries entries carry the launch's prefix table here, so
+  // blocks find their entry without a memory load: entries 0 .. n_entries - 1, INT32_MAX
+  // up to index kSmallEntries - 1 and the launch's total at index kSmallEntries.  The
+  // segment-test launch fills kXcds rows (one per band, or the same row kXcds times),
+  // the others row 0.
   int32_t sbase[kXcds * (kSmallEntries + 1)];
 };
 

@@ -93,25 +93,68 @@ __device__ __forceinline__ int find_entry(const int32_t* base, int n, int g) {
   return lo;
 }
 
-// Signature of the plan the workspace holds (the expected one on the plain path).  Read
-// first and compared only before the plan's pointers are used, so the check costs no
-// round trip of its own.
-__device__ __forceinline__ uint64_t held_sig(const KArgs& a) {
-  return a.ws_sig == nullptr ? a.sig : *G(a.ws_sig);
+// Launch-wide values every block needs before its first tile.  They are read together,
+// before any branch depends on them, so their scalar loads share one trip to memory
+// rather than forming a chain of dependent trips (each a full memory latency at kernel
+// start, when the caches are cold).  b is row `row` of the small-batch prefix table.
+// Threads per block of the tile kernels, the selection and the helpers below (their
+// launches use exactly this; a constant saves reading the launch size from memory).
+constexpr int kBlock = 256;
+
+struct Head {
+  LevelPlan* plan;
+  const uint64_t* ws_sig;
+  uint64_t sig;
+  int32_t n_entries, total, entry, persistent, bands, small;
+  uint32_t* qctr;
+  int32_t cell;
+  Tune t;
+  uint32_t* counters;
+  uint8_t* flags;
+  int32_t b[kSmallEntries + 1];
+};
+
+__device__ __forceinline__ Head read_head(const KArgs& a, int row) {
+  Head h;
+  h.plan = a.plan;
+  h.ws_sig = a.ws_sig;
+  h.sig = a.sig;
+  h.n_entries = a.n_entries;
+  h.total = a.total;
+  h.entry = a.entry;
+  h.persistent = a.persistent;
+  h.bands = a.bands;
+  h.small = a.small;
+  h.qctr = a.qctr;
+  h.cell = a.cell;
+  h.t = a.t;
+  h.counters = a.counters;
+  h.flags = a.flags;
+#pragma unroll
+  for (int i = 0; i <= kSmallEntries; ++i) h.b[i] = a.sbase[row * (kSmallEntries + 1) + i];
+  // every value in a scalar register here: no load is left for after a branch
+  asm volatile("" ::"s"(h.plan), "s"(h.ws_sig), "s"(h.sig), "s"(h.n_entries), "s"(h.total),
+               "s"(h.entry), "s"(h.persistent), "s"(h.bands), "s"(h.small), "s"(h.qctr),
+               "s"(h.cell), "s"(h.counters), "s"(h.flags));
+  asm volatile("" ::"s"(h.t.mark_words), "s"(h.t.mark_rows), "s"(h.t.det_cx), "s"(h.t.det_cy),
+               "s"(h.t.det_w), "s"(h.t.det_h));
+  asm volatile("" ::"s"(h.b[0]), "s"(h.b[1]), "s"(h.b[2]), "s"(h.b[3]), "s"(h.b[4]),
+               "s"(h.b[5]), "s"(h.b[6]), "s"(h.b[7]), "s"(h.b[8]));
+  asm volatile("" ::"s"(h.b[9]), "s"(h.b[10]), "s"(h.b[11]), "s"(h.b[12]), "s"(h.b[13]),
+               "s"(h.b[14]), "s"(h.b[15]), "s"(h.b[16]));
+  return h;
 }
 
-// Entry of tile g and the entry's first tile, from row `row` of the prefix table in the
-// kernel arguments (batches of at most kSmallEntries entries).  Unrolled with constant
-// indices: scalar loads of the argument segment, no search through memory.
-__device__ __forceinline__ void small_entry(const KArgs& a, int row, int g, int* e, int* start) {
-  const int32_t* b = a.sbase + row * (kSmallEntries + 1);
+// Entry of unit g and the entry's first unit, from a small-batch prefix row (entries
+// past the last hold INT32_MAX).  Unrolled: the row is in scalar registers.
+__device__ __forceinline__ void small_entry(const int32_t (&b)[kSmallEntries + 1], int g, int* e,
+                                            int* start) {
   int ee = 0, st = 0;
 #pragma unroll
   for (int i = 1; i < kSmallEntries; ++i) {
-    const int32_t bi = b[i];
-    if (i < a.n_entries && g >= bi) {
+    if (g >= b[i]) {
       ee = i;
-      st = bi;
+      st = b[i];
     }
   }
   *e = ee;
@@ -178,9 +221,15 @@ __device__ __forceinline__ uint32_t load_word(gptr<const uint8_t> s, bool whole,
   return v;
 }
 
+// Bytes p[0] (low) and p[1] (high) with one 16-bit load at any alignment.
+typedef uint16_t u16_any_align __attribute__((aligned(1)));
+__device__ __forceinline__ uint32_t load_pair(gptr<const uint8_t> p) {
+  return *(gptr<const u16_any_align>)p;
+}
+
 // Rows [y0, y1) x columns [x0, x1) of a level into LDS (row pitch lp), as 32-bit words.
 // The block's threads take the words in order, U per thread per pass, so a tile of up
-// to U * blockDim words costs one round trip to memory.
+// to U * kBlock words costs one round trip to memory.
 template <int U>
 __device__ __forceinline__ void stage_rows(uint8_t* lds, int lp, gptr<const uint8_t> src,
                                            int stride, int row_limit, int x0, int x1, int y0,
@@ -188,7 +237,7 @@ __device__ __forceinline__ void stage_rows(uint8_t* lds, int lp, gptr<const uint
   const bool aligned = ((((uintptr_t)src) | (uintptr_t)stride) & 3) == 0;
   const int nw = (x1 - x0 + 3) >> 2;
   const int total = nw * (y1 - y0);
-  const int bd = (int)blockDim.x;
+  const int bd = kBlock;
   const int drow = bd / nw, dw = bd - drow * nw;  // advance of (row, word) per bd words
   int row = (int)threadIdx.x / nw;
   int w = (int)threadIdx.x - row * nw;
@@ -274,7 +323,7 @@ __device__ __forceinline__ int64_t harris_lds(const uint8_t* pix, int P, int cx,
 __device__ __forceinline__ void harris_groups(const uint8_t* pix, int P, const uint32_t* cpos,
                                               int64_t* crs, int n, int sx0, int sy0) {
   const int s = threadIdx.x & 7;
-  const int groups = blockDim.x >> 3;
+  const int groups = kBlock >> 3;
   for (int cb = 0; cb < n; cb += groups) {
     const int c = cb + (threadIdx.x >> 3);
     int sxx = 0, syy = 0, sxy = 0;
@@ -322,9 +371,9 @@ __device__ __forceinline__ void lds_barrier() {
 
 // Exclusive scan of cnt[0..n) into pre[0..n], pre[n] = total, by the whole block.
 __device__ void block_scan_u32(const uint32_t* cnt, uint32_t* pre, int n, uint32_t* s_wsum) {
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nwave = blockDim.x >> 6;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nwave = kBlock >> 6;
   uint32_t carry = 0;
-  for (int base = 0; base < n; base += blockDim.x) {
+  for (int base = 0; base < n; base += kBlock) {
     const int i = base + threadIdx.x;
     const uint32_t v = i < n ? cnt[i] : 0u;
     uint32_t inc = v;
@@ -386,27 +435,27 @@ __device__ __forceinline__ void wave_moments(gptr<const uint8_t> lvl, int stride
 // Tile index: blockIdx.x once, or from the queue counter.  The next index is drawn
 // when a tile starts and parked in LDS only when it ends, so the atomic's round trip
 // overlaps the tile instead of stalling the block.
-__device__ __forceinline__ void queue_start(const KArgs& a, uint32_t* ctr, int* s_next) {
-  if (a.persistent && threadIdx.x == 0) *s_next = (int)atomicAdd(ctr, 1u);
+__device__ __forceinline__ void queue_start(const Head& h, uint32_t* ctr, int* s_next) {
+  if (h.persistent && threadIdx.x == 0) *s_next = (int)atomicAdd(ctr, 1u);
 }
 
-__device__ __forceinline__ int queue_take(const KArgs& a, int iter, int* s_next) {
-  if (!a.persistent) return iter == 0 ? (int)blockIdx.x : a.total;
+__device__ __forceinline__ int queue_take(const Head& h, int iter, int* s_next) {
+  if (!h.persistent) return iter == 0 ? (int)blockIdx.x : h.total;
   lds_barrier();
   return *s_next;
 }
 
-__device__ __forceinline__ int queue_prefetch(const KArgs& a, int g, uint32_t* ctr) {
-  return (a.persistent && threadIdx.x == 0 && g < a.total) ? (int)atomicAdd(ctr, 1u) : 0;
+__device__ __forceinline__ int queue_prefetch(const Head& h, int g, uint32_t* ctr) {
+  return (h.persistent && threadIdx.x == 0 && g < h.total) ? (int)atomicAdd(ctr, 1u) : 0;
 }
 
-__device__ __forceinline__ void queue_park(const KArgs& a, int next, int* s_next) {
-  if (a.persistent && threadIdx.x == 0) *s_next = next;
+__device__ __forceinline__ void queue_park(const Head& h, int next, int* s_next) {
+  if (h.persistent && threadIdx.x == 0) *s_next = next;
 }
 
 // Copy of an exclusive prefix (n + 1 values) into LDS for entry lookups.
 __device__ __forceinline__ void load_bases(int32_t* s_base, const int32_t* base, int n) {
-  for (int i = threadIdx.x; i <= n; i += blockDim.x) s_base[i] = G(base)[i];
+  for (int i = threadIdx.x; i <= n; i += kBlock) s_base[i] = G(base)[i];
   lds_barrier();
 }
 
@@ -482,9 +531,10 @@ __global__ __launch_bounds__(1024) void k_prologue(PrologueArgs a) {
   const int64_t o_lvl = scan(s.lvl_bytes);
   const int64_t o_pyr = scan(s.pyr_blocks);
   const int64_t t_pyr = s_tot;
+  const int32_t rot = (int32_t)(scan(s.mark_ty % kXcds) % kXcds);
   int32_t* band_base = (int32_t*)(ws + a.lay.off_band_base);
   for (int k = 0; k < kXcds; ++k) {
-    const int32_t rows = band_row0(s.mark_ty, k + 1) - band_row0(s.mark_ty, k);
+    const int32_t rows = band_rows(s.mark_ty, rot, k);
     const int64_t o_band = scan(i < nL ? (int64_t)s.mark_tx * rows : 0);
     if (i < nL) band_base[k * (nL + 1) + i] = (int32_t)o_band;
     if (i == 0) band_base[k * (nL + 1) + nL] = (int32_t)s_tot;
@@ -541,6 +591,7 @@ __global__ __launch_bounds__(1024) void k_prologue(PrologueArgs a) {
     P.ncand_count = counters + 2 * a.lay.n_entries + i;
     P.mark_tx = s.mark_tx;
     P.mark_ty = s.mark_ty;
+    P.band_rot = rot;
     P.det_tx = s.det_tx;
     P.det_ty = s.det_ty;
     P.det_x0 = s.det_x0;
@@ -626,20 +677,21 @@ __global__ __launch_bounds__(256) void k_pyramid(PyrArgs a) {
 __global__ __launch_bounds__(256) void k_pyramid_batch(KArgs a) {
   __shared__ uint32_t xt[64], yt[16];
   __shared__ int32_t s_base[kMaxEntries + 1];
-  const uint64_t wsig = held_sig(a);
+  const Head h = read_head(a, 0);
+  const uint64_t wsig = *G(h.ws_sig);  // compared before the plan's pointers are used
   const int g = (int)blockIdx.x;
   int e, b;
-  if (a.small) {
+  if (h.small) {
     int st;
-    small_entry(a, 0, g, &e, &st);
+    small_entry(h.b, g, &e, &st);
     b = g - st;
   } else {
-    load_bases(s_base, a.pyr_base, a.n_entries);
-    e = uniform(find_entry(s_base, a.n_entries, g));
+    load_bases(s_base, a.pyr_base, h.n_entries);
+    e = uniform(find_entry(s_base, h.n_entries, g));
     b = g - s_base[e];
   }
-  const LevelPlan P = a.plan[e];
-  if (wsig != a.sig) return;  // not the plan this launch was made for
+  const LevelPlan P = h.plan[e];
+  if (wsig != h.sig) return;  // not the plan this launch was made for
   const int nbx = (P.W + 63) >> 6;
   const int by = b / nbx, bx = b - by * nbx;
   resample_block(G(P.base), P.base_w, P.base_h, P.base_stride, G(P.lvl_w), P.W, P.H,
@@ -652,60 +704,58 @@ __global__ __launch_bounds__(256) void k_pyramid_batch(KArgs a) {
 // LDS row pitch at compile time, so every circle and compass offset below is a
 // ds_read immediate.
 template <bool FUSED, int TWW>
-__global__ __launch_bounds__(256, TWW <= 2 ? 5 : 4) void k_mark(KArgs a) {
+__global__ __launch_bounds__(256, 4) void k_mark(KArgs a) {
   constexpr int TW = 64 * TWW;
   constexpr int PITCH = TW + 8;
   extern __shared__ __align__(16) uint8_t smem[];
   __shared__ int s_next, s_qcnt[4];
-  const MarkLds M = mark_lds(a.t);
+  const int band = (int)(blockIdx.x % kXcds);  // used in the band order only
+  const Head h = read_head(a, band);
+  const MarkLds M = mark_lds(h.t);
   uint8_t* pix = smem;
   uint16_t* queue = (uint16_t*)(smem + M.off_queue);
   uint32_t* bml = (uint32_t*)(smem + M.off_bml);
   uint32_t* bmh = (uint32_t*)(smem + M.off_bmh);
-  uint32_t* xt = (uint32_t*)(smem + M.off_xt);
-  uint32_t* yt = (uint32_t*)(smem + M.off_yt);
   int32_t* s_base = (int32_t*)(smem + M.bytes);
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nwave = blockDim.x >> 6;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nwave = kBlock >> 6;
   // XCD bands: block b runs on XCD b % kXcds and takes tile b / kXcds of band b % kXcds
   // (the same rows of every level of every frame), so each XCD's L2 holds one band of
   // the frames that its tiles resample from.
-  const uint64_t wsig = held_sig(a);
-  if (a.entry < 0 && blockIdx.x == 0) {  // counters of this call (read after this kernel)
-    for (int i = threadIdx.x; i < 3 * a.n_entries; i += blockDim.x) G(a.counters)[i] = 0u;
-    if (threadIdx.x == 0) G(a.qctr)[2] = 0u;
+  const uint64_t wsig = *G(h.ws_sig);  // compared before the plan's pointers are used
+  if (h.entry < 0 && blockIdx.x == 0) {  // counters of this call (read after this kernel)
+    for (int i = threadIdx.x; i < 3 * h.n_entries; i += kBlock) G(h.counters)[i] = 0u;
+    if (threadIdx.x == 0) G(h.qctr)[2] = 0u;
   }
-  const int band = a.bands ? (int)(blockIdx.x % kXcds) : 0;
-  if (a.entry < 0 && !a.small)
-    load_bases(s_base, a.bands ? a.band_base + band * (a.n_entries + 1) : a.mark_base,
-               a.n_entries);
-  queue_start(a, a.qctr + 0, &s_next);
+  if (h.entry < 0 && !h.small)
+    load_bases(s_base, h.bands ? a.band_base + band * (h.n_entries + 1) : a.mark_base,
+               h.n_entries);
+  queue_start(h, h.qctr + 0, &s_next);
 
   for (int iter = 0;; ++iter) {
-    const int g0 = uniform(queue_take(a, iter, &s_next));
-    if (g0 >= a.total) break;
-    const int g = a.bands ? g0 / kXcds : g0;
-    if (a.bands && g >= (a.small ? a.sbase[band * (kSmallEntries + 1) + a.n_entries]
-                                 : s_base[a.n_entries]))
+    const int g0 = uniform(queue_take(h, iter, &s_next));
+    if (g0 >= h.total) break;
+    const int g = h.bands ? g0 / kXcds : g0;
+    if (h.bands && g >= (h.small ? h.b[kSmallEntries] : s_base[h.n_entries]))
       break;  // band holds fewer tiles
-    lds_barrier();  // every thread has read s_next
-    const int next = queue_prefetch(a, g0, a.qctr + 0);
+    if (h.persistent) lds_barrier();  // every thread has read s_next
+    const int next = queue_prefetch(h, g0, h.qctr + 0);
     int e, t;
-    if (a.entry >= 0) {
-      e = a.entry;
+    if (h.entry >= 0) {
+      e = h.entry;
       t = g;
-    } else if (a.small) {
+    } else if (h.small) {
       int st;
-      small_entry(a, band, g, &e, &st);
+      small_entry(h.b, g, &e, &st);
       t = g - st;
     } else {
-      e = uniform(find_entry(s_base, a.n_entries, g));
+      e = uniform(find_entry(s_base, h.n_entries, g));
       t = g - s_base[e];
     }
-    const LevelPlan P = a.plan[e];
-    if (wsig != a.sig) break;  // not the plan this launch was made for
+    const LevelPlan P = h.plan[e];
+    if (wsig != h.sig) break;  // not the plan this launch was made for
     const int W = P.W, H = P.H, B = P.B;
     const int tx = t % P.mark_tx;
-    const int ty = t / P.mark_tx + (a.bands ? band_row0(P.mark_ty, band) : 0);
+    const int ty = t / P.mark_tx + (h.bands ? band_row0(P.mark_ty, P.band_rot, band) : 0);
     const int x_t0 = tx * TW, x_t1 = min(W, x_t0 + TW);
     const int y_t0 = ty * M.th, y_t1 = min(H, y_t0 + M.th);
     const int ox = max(0, x_t0 - 4), oy = max(0, y_t0 - 3);
@@ -714,40 +764,50 @@ __global__ __launch_bounds__(256, TWW <= 2 ? 5 : 4) void k_mark(KArgs a) {
 
     // 1. level pixels of the tile and its 3-pixel halo
     if (FUSED && P.level > 0) {
-      for (int i = threadIdx.x; i < nx; i += blockDim.x) xt[i] = resample_tap(ox + i, P.base_w, W);
-      for (int j = threadIdx.x; j < ny; j += blockDim.x) yt[j] = resample_tap(oy + j, P.base_h, H);
-      lds_barrier();
-      // Column taps stay in registers (lane owns columns lane + 64c); each wave takes RPI
-      // consecutive output rows at a time with their base-row pointers in scalar
-      // registers, so a tap costs its load and the blend only.
+      // Taps in registers: lane owns columns lane + 64c (x0 and weight), and lane j holds
+      // the row tap of tile row j (j + 64 in the second value), read per row with
+      // readlane.  A column tap keeps x0 + 1 inside the source row (at the right border
+      // x0 = w - 2 with weight 256: the same value as x0 = x1 = w - 1), so one 16-bit
+      // load fetches both horizontal neighbours.  Each wave takes RPI consecutive rows
+      // per round trip; the tile's own pixels also go straight to the level buffer.
       gptr<const uint8_t> base = G(P.base);
-      const int bs = P.base_stride, bw1 = P.base_w - 1, bh1 = P.base_h - 1;
+      const int bs = P.base_stride, bw = P.base_w, bh1 = P.base_h - 1;
       constexpr int NC = TWW + 1;  // columns per lane: nx <= TW + 7
-      int cx0[NC], cx1[NC], cwx[NC];
+      uint32_t cx[NC];
+      int cwx[NC];
 #pragma unroll
       for (int c = 0; c < NC; ++c) {
-        const uint32_t txx = xt[min(lane + 64 * c, nx - 1)];
-        cx0[c] = txx >> 9;
-        cx1[c] = min(cx0[c] + 1, bw1);
-        cwx[c] = txx & 511;
+        const uint32_t txx = resample_tap(ox + min(lane + 64 * c, nx - 1), bw, W);
+        int x0 = (int)(txx >> 9), wx = (int)(txx & 511);
+        if (x0 >= bw - 1) {
+          x0 = bw - 2;
+          wx = 256;
+        }
+        cx[c] = (uint32_t)x0;
+        cwx[c] = wx;
       }
-      constexpr int RPI = TWW == 1 ? 4 : (TWW == 2 ? 3 : 2);  // rows per wave and round trip
+      const uint32_t ty_a = resample_tap(oy + min(lane, ny - 1), P.base_h, H);
+      const uint32_t ty_b = resample_tap(oy + min(lane + 64, ny - 1), P.base_h, H);
+      gptr<uint8_t> lw = G(P.lvl_w) + (size_t)oy * P.lvl_stride + ox;
+      const int lx0 = x_t0 - ox, lx1 = x_t1 - ox, ly0 = y_t0 - oy, ly1 = y_t1 - oy;
+      // 2 * RPI * NC loads in flight; the most that fit the registers without spilling
+      constexpr int RPI = TWW == 1 ? 6 : (TWW == 2 ? 5 : (TWW == 3 ? 3 : 2));
       for (int j0 = RPI * wave; j0 < ny; j0 += RPI * nwave) {
-        int v[RPI][NC][4];
+        uint32_t v[RPI][NC][2];
         int wyr[RPI];
 #pragma unroll
         for (int h = 0; h < RPI; ++h) {
-          const uint32_t tyy = (uint32_t)uniform((int)yt[min(j0 + h, ny - 1)]);
-          const int y0 = tyy >> 9;
-          wyr[h] = tyy & 511;
+          const int j = min(j0 + h, ny - 1);
+          const uint32_t tyy =
+              (uint32_t)__builtin_amdgcn_readlane((int)(j < 64 ? ty_a : ty_b), j & 63);
+          const int y0 = (int)(tyy >> 9);
+          wyr[h] = (int)(tyy & 511);
           gptr<const uint8_t> r0 = base + (size_t)y0 * bs;
           gptr<const uint8_t> r1 = base + (size_t)min(y0 + 1, bh1) * bs;
 #pragma unroll
           for (int c = 0; c < NC; ++c) {
-            v[h][c][0] = r0[cx0[c]];
-            v[h][c][1] = r0[cx1[c]];
-            v[h][c][2] = r1[cx0[c]];
-            v[h][c][3] = r1[cx1[c]];
+            v[h][c][0] = load_pair(r0 + cx[c]);
+            v[h][c][1] = load_pair(r1 + cx[c]);
           }
         }
 #pragma unroll
@@ -755,38 +815,27 @@ __global__ __launch_bounds__(256, TWW <= 2 ? 5 : 4) void k_mark(KArgs a) {
           const int j = j0 + h;
           if (j >= ny) break;
           const int wy = wyr[h];
-          uint8_t* prow = pix + j * PITCH;
+          const bool own = j >= ly0 && j < ly1;
 #pragma unroll
           for (int c = 0; c < NC; ++c) {
             const int i = lane + 64 * c;
             if (i < nx) {
               const int wx = cwx[c];
-              const int top = (256 - wx) * v[h][c][0] + wx * v[h][c][1];
-              const int bot = (256 - wx) * v[h][c][2] + wx * v[h][c][3];
-              prow[i] = (uint8_t)(((256 - wy) * top + wy * bot + 32768) >> 16);
+              const uint32_t t = v[h][c][0], b = v[h][c][1];
+              const int top = (256 - wx) * (int)(t & 255u) + wx * (int)(t >> 8);
+              const int bot = (256 - wx) * (int)(b & 255u) + wx * (int)(b >> 8);
+              const uint8_t px = (uint8_t)(((256 - wy) * top + wy * bot + 32768) >> 16);
+              pix[j * PITCH + i] = px;
+              if (own && i >= lx0 && i < lx1) lw[(size_t)j * P.lvl_stride + i] = px;
             }
           }
-        }
-      }
-      lds_barrier();
-      // the tile's own pixels go to the level buffer for the later steps
-      const int lx0 = x_t0 - ox;
-      const int nwd = (x_t1 - x_t0 + 3) >> 2;
-      gptr<uint8_t> lw = G(P.lvl_w);
-      for (int r = wave; r < y_t1 - y_t0; r += nwave) {
-        const int y = y_t0 + r;
-        for (int w0 = 0; w0 < nwd; w0 += 64) {
-          const int w = w0 + lane;
-          if (w < nwd)
-            *(gptr<uint32_t>)(lw + (size_t)y * P.lvl_stride + x_t0 + 4 * w) =
-                *(const uint32_t*)(pix + (y - oy) * PITCH + lx0 + 4 * w);
         }
       }
     } else {
       const int limit = P.level == 0 ? W : P.lvl_stride;
       stage_rows<8>(pix, PITCH, G(P.lvl), P.lvl_stride, limit, ox, ex, oy, ey);
     }
-    for (int i = threadIdx.x; i < 2 * M.th * 2 * TWW; i += blockDim.x) bml[i] = 0u;  // lo, hi
+    for (int i = threadIdx.x; i < 2 * M.th * 2 * TWW; i += kBlock) bml[i] = 0u;  // lo, hi
     lds_barrier();
 
     // 2. compass pre-test at fast_t_min: a run of 9 holds two cyclically adjacent
@@ -837,7 +886,7 @@ __global__ __launch_bounds__(256, TWW <= 2 ? 5 : 4) void k_mark(KArgs a) {
       qtot += w < nwave ? s_qcnt[w] : 0;
     }
     gptr<uint8_t> flags = G(P.flags);
-    for (int q = threadIdx.x; q < qtot; q += blockDim.x) {
+    for (int q = threadIdx.x; q < qtot; q += kBlock) {
       int w = 0;
 #pragma unroll
       for (int k = 1; k < 4; ++k) w += q >= qoff[k] ? 1 : 0;
@@ -882,7 +931,7 @@ __global__ __launch_bounds__(256, TWW <= 2 ? 5 : 4) void k_mark(KArgs a) {
     gptr<uint32_t> glo = G(P.bm_lo), ghi = G(P.bm_hi);
     {
       const int k = threadIdx.x & 7;  // at most 8 words per tile row
-      for (int r = threadIdx.x >> 3; r < y_t1 - y_t0; r += blockDim.x >> 3) {
+      for (int r = threadIdx.x >> 3; r < y_t1 - y_t0; r += kBlock >> 3) {
         if (k < nwd) {
           const size_t gi = (size_t)(y_t0 + r) * P.wpr + w0 + k;
           glo[gi] = bml[r * 2 * TWW + k];
@@ -890,7 +939,7 @@ __global__ __launch_bounds__(256, TWW <= 2 ? 5 : 4) void k_mark(KArgs a) {
         }
       }
     }
-    queue_park(a, next, &s_next);
+    queue_park(h, next, &s_next);
   }
 }
 
@@ -923,7 +972,8 @@ __global__ __launch_bounds__(256, 4) void k_detect(KArgs a) {
   extern __shared__ __align__(16) uint8_t smem[];
   __shared__ int s_next, s_ns, s_ne, s_nin;
   __shared__ uint32_t s_wsum[16];
-  const DetLds D = det_lds(a.t, a.cell);
+  const Head h = read_head(a, 0);
+  const DetLds D = det_lds(h.t, h.cell);
   uint8_t* pix = smem;
   uint32_t* cw = (uint32_t*)(smem + D.off_cw);
   uint32_t* ucnt = (uint32_t*)(smem + D.off_ucnt);
@@ -942,38 +992,38 @@ __global__ __launch_bounds__(256, 4) void k_detect(KArgs a) {
   uint32_t* cwin = (uint32_t*)(smem + D.off_cwin);
   uint8_t* lfl = smem + D.off_lfl;
   int32_t* s_base = (int32_t*)(smem + D.bytes);
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nwave = blockDim.x >> 6;
-  const int bd = (int)blockDim.x, tid = (int)threadIdx.x;
-  const uint64_t wsig = held_sig(a);
-  if (a.entry < 0 && !a.small) load_bases(s_base, a.det_base, a.n_entries);
-  queue_start(a, a.qctr + 2, &s_next);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nwave = kBlock >> 6;
+  const int bd = (int)kBlock, tid = (int)threadIdx.x;
+  const uint64_t wsig = *G(h.ws_sig);  // compared before the plan's pointers are used
+  if (h.entry < 0 && !h.small) load_bases(s_base, a.det_base, h.n_entries);
+  queue_start(h, h.qctr + 2, &s_next);
 
   for (int iter = 0;; ++iter) {
-    const int g = uniform(queue_take(a, iter, &s_next));
-    if (g >= a.total) break;
-    lds_barrier();  // every thread has read s_next
-    const int next = queue_prefetch(a, g, a.qctr + 2);
+    const int g = uniform(queue_take(h, iter, &s_next));
+    if (g >= h.total) break;
+    if (h.persistent) lds_barrier();  // every thread has read s_next
+    const int next = queue_prefetch(h, g, h.qctr + 2);
     int e, t;
-    if (a.entry >= 0) {
-      e = a.entry;
+    if (h.entry >= 0) {
+      e = h.entry;
       t = g;
-    } else if (a.small) {
+    } else if (h.small) {
       int st;
-      small_entry(a, 0, g, &e, &st);
+      small_entry(h.b, g, &e, &st);
       t = g - st;
     } else {
-      e = uniform(find_entry(s_base, a.n_entries, g));
+      e = uniform(find_entry(s_base, h.n_entries, g));
       t = g - s_base[e];
     }
-    const LevelPlan P = a.plan[e];
-    if (wsig != a.sig) break;  // not the plan this launch was made for
+    const LevelPlan P = h.plan[e];
+    if (wsig != h.sig) break;  // not the plan this launch was made for
     const int W = P.W, H = P.H, B = P.B, cs = P.cs;
     const int tx = t % P.det_tx, ty = t / P.det_tx;
     int vx0, vx1, vy0, vy1, cxa = 0, cya = 0, nlcx = 1, nlcy = 1;
-    if (a.cell > 0) {
-      cxa = P.det_x0 + tx * a.t.det_cx;
-      cya = P.det_y0 + ty * a.t.det_cy;
-      const int cxb = min(cxa + a.t.det_cx, P.det_xend), cyb = min(cya + a.t.det_cy, P.det_yend);
+    if (h.cell > 0) {
+      cxa = P.det_x0 + tx * h.t.det_cx;
+      cya = P.det_y0 + ty * h.t.det_cy;
+      const int cxb = min(cxa + h.t.det_cx, P.det_xend), cyb = min(cya + h.t.det_cy, P.det_yend);
       nlcx = cxb - cxa;
       nlcy = cyb - cya;
       vx0 = max(cxa * cs, B);
@@ -981,10 +1031,10 @@ __global__ __launch_bounds__(256, 4) void k_detect(KArgs a) {
       vy0 = max(cya * cs, B);
       vy1 = min(cyb * cs, H - B);
     } else {
-      vx0 = P.det_x0 + tx * a.t.det_w;
-      vx1 = min(vx0 + a.t.det_w, P.det_xend);
-      vy0 = P.det_y0 + ty * a.t.det_h;
-      vy1 = min(vy0 + a.t.det_h, P.det_yend);
+      vx0 = P.det_x0 + tx * h.t.det_w;
+      vx1 = min(vx0 + h.t.det_w, P.det_xend);
+      vy0 = P.det_y0 + ty * h.t.det_h;
+      vy1 = min(vy0 + h.t.det_h, P.det_yend);
     }
     // tile + 1-pixel ring (candidates), + 5-pixel halo (staged pixels)
     const int rx0 = vx0 - 1, ry0 = vy0 - 1;
@@ -1043,8 +1093,8 @@ __global__ __launch_bounds__(256, 4) void k_detect(KArgs a) {
       s_nin = 0;
     }
     // one survivor kept per cell: the cell's winner is found with LDS atomics
-    const bool best1 = a.cell > 0 && P.kcell == 1;
-    if (a.cell > 0) {
+    const bool best1 = h.cell > 0 && P.kcell == 1;
+    if (h.cell > 0) {
       for (int c = tid; c < ncell; c += bd) {
         ccnt[c] = 0;
         cfill[c] = 0;
@@ -1235,11 +1285,11 @@ __global__ __launch_bounds__(256, 4) void k_detect(KArgs a) {
         const uint64_t m = __ballot(filled);
         if (lane == 0 && m) atomicAdd(P.cand_count, (uint32_t)__popcll(m));
       }
-      queue_park(a, next, &s_next);
+      queue_park(h, next, &s_next);
       continue;
     }
     if (ns > 0) {
-      if (a.cell > 0) {
+      if (h.cell > 0) {
         for (int s2 = tid; s2 < ns; s2 += bd) atomicAdd(&ccnt[multi ? scell[s2] : 0], 1u);
         lds_barrier();
         if (tid == 0) {
@@ -1261,13 +1311,13 @@ __global__ __launch_bounds__(256, 4) void k_detect(KArgs a) {
         const uint32_t pos = cand_pos(ci);
         const int64_t R = cand_score(ci, pos);
         const int c = multi ? scell[s] : 0;
-        const int n = a.cell > 0 ? (int)ccnt[c] : ns;
+        const int n = h.cell > 0 ? (int)ccnt[c] : ns;
         bool keep = true;
         if (n > K) {
           int rank = 0;
-          const int o = a.cell > 0 ? (int)coff[c] : 0;
+          const int o = h.cell > 0 ? (int)coff[c] : 0;
           for (int q = 0; q < n && rank < K; ++q) {
-            const int s2 = a.cell > 0 ? order[o + q] : q;
+            const int s2 = h.cell > 0 ? order[o + q] : q;
             const int ci2 = sci[s2];
             const uint32_t pos2 = cand_pos(ci2);
             rank += better(cand_score(ci2, pos2), pos2, R, pos) ? 1 : 0;
@@ -1277,7 +1327,7 @@ __global__ __launch_bounds__(256, 4) void k_detect(KArgs a) {
         if (keep) {
           const int x = (int)(pos & 0xffff), y = (int)(pos >> 16);
           int slot;
-          if (a.cell > 0) {
+          if (h.cell > 0) {
             const int r = (int)atomicAdd(&ckept[c], 1u);
             slot = ((y / cs - P.det_y0) * nvx + (x / cs - P.det_x0)) * P.kslot + r;
           } else if (P.compact) {  // listed here, appended below
@@ -1305,10 +1355,10 @@ __global__ __launch_bounds__(256, 4) void k_detect(KArgs a) {
         const uint32_t pos = cand_pos(ci);
         if (base + k < P.cand_cap) store_cand(out + base + k, cand_score(ci, pos), pos);
       }
-      queue_park(a, next, &s_next);
+      queue_park(h, next, &s_next);
       continue;
     }
-    if (a.cell > 0) {
+    if (h.cell > 0) {
       const int ks = P.kslot;
       for (int i = tid; i < ncell * ks; i += bd) {
         const int c = ks == 1 ? i : i / ks;
@@ -1327,7 +1377,7 @@ __global__ __launch_bounds__(256, 4) void k_detect(KArgs a) {
             store_cand(out + (size_t)(srow + by) * P.slot_w + scol + bx, INT64_MIN, kNoPos);
     }
     if (tid == 0 && s_ne > 0) atomicAdd(P.cand_count, (uint32_t)s_ne);
-    queue_park(a, next, &s_next);
+    queue_park(h, next, &s_next);
   }
 }
 
@@ -1340,37 +1390,38 @@ __global__ __launch_bounds__(256, 4) void k_detect(KArgs a) {
 // the radix-select path.
 __global__ __launch_bounds__(256) void k_select_orient(KArgs a) {
   __shared__ int32_t s_base[kMaxEntries + 1];
-  const uint64_t wsig = held_sig(a);
-  if (blockIdx.x == 0 && wsig != a.sig) {  // not the plan this launch was made for
+  const Head h = read_head(a, 0);
+  const uint64_t wsig = *G(h.ws_sig);  // compared before the plan's pointers are used
+  if (blockIdx.x == 0 && wsig != h.sig) {  // not the plan this launch was made for
     if ((int)threadIdx.x < a.n_frames) G(a.frame_counts)[threadIdx.x] = -1;
     return;
   }
-  if (a.flags) {  // cell flags and the segment-test queue counter, zero for the next call
+  if (h.flags) {  // cell flags and the segment-test queue counter, zero for the next call
     const int64_t nq = a.flag_bytes / 16;
     const int64_t per = (nq + gridDim.x - 1) / gridDim.x;
     const int64_t q0 = (int64_t)blockIdx.x * per, q1 = min(q0 + per, nq);
     const u32x4 zero = {0u, 0u, 0u, 0u};
-    for (int64_t q = q0 + threadIdx.x; q < q1; q += blockDim.x)
-      ((gptr<u32x4>)G(a.flags))[q] = zero;
-    if (blockIdx.x == 0 && threadIdx.x == 0) G(a.qctr)[0] = 0u;
+    for (int64_t q = q0 + threadIdx.x; q < q1; q += kBlock)
+      ((gptr<u32x4>)G(h.flags))[q] = zero;
+    if (blockIdx.x == 0 && threadIdx.x == 0) G(h.qctr)[0] = 0u;
   }
-  if (!a.small) load_bases(s_base, a.rank_base, a.n_entries);
+  if (!h.small) load_bases(s_base, a.rank_base, h.n_entries);
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int slot = (int)blockIdx.x * (blockDim.x >> 6) + wave;
+  const int slot = (int)blockIdx.x * (kBlock >> 6) + wave;
   int e, i;
-  if (a.small) {
-    if (slot >= a.sbase[a.n_entries]) return;
+  if (h.small) {
+    if (slot >= h.b[kSmallEntries]) return;
     int st;
-    small_entry(a, 0, slot, &e, &st);
+    small_entry(h.b, slot, &e, &st);
     e = uniform(e);
     i = slot - st;
   } else {
-    if (slot >= s_base[a.n_entries]) return;
-    e = uniform(find_entry(s_base, a.n_entries, slot));
+    if (slot >= s_base[h.n_entries]) return;
+    e = uniform(find_entry(s_base, h.n_entries, slot));
     i = slot - s_base[e];
   }
-  const LevelPlan P = a.plan[e];
-  if (wsig != a.sig) return;
+  const LevelPlan P = h.plan[e];
+  if (wsig != h.sig) return;
   gptr<const uint32_t> counts = G((const uint32_t*)P.cand_count) - e;  // all entries
   const int C = P.cand_cap;  // slots; empty ones hold the sentinel
   if (P.level == 0 && i == 0 && lane == 0) {
@@ -1454,7 +1505,9 @@ __global__ __launch_bounds__(1024) void k_select(KArgs a) {
   __shared__ uint64_t s_prefix;
   __shared__ uint32_t s_k, s_n, s_eq;
   const int e = a.entry >= 0 ? a.entry : (int)blockIdx.x;
+  const uint64_t wsig = *G(a.ws_sig);
   const LevelPlan P = a.plan[e];
+  if (wsig != a.sig) return;  // not the plan this launch was made for
   const int N = P.quota;
   if (a.rank_path && P.cand_cap <= kRankCap) return;  // handled by k_select_orient
   const int nfill = (int)*G(P.cand_count);
@@ -1592,7 +1645,9 @@ __global__ __launch_bounds__(256) void k_orient(KArgs a) {
   const int b = (int)blockIdx.x;
   const int e = a.entry >= 0 ? a.entry : find_entry(a.orient_base, a.n_entries, b);
   const int chunk = a.entry >= 0 ? b : b - a.orient_base[e];
+  const uint64_t wsig = *G(a.ws_sig);
   const LevelPlan P = a.plan[e];
+  if (wsig != a.sig) return;  // not the plan this launch was made for
   gptr<const uint32_t> counts = G((const uint32_t*)P.cand_count) - e;
   if (a.rank_path && P.cand_cap <= kRankCap) return;  // written by k_select_orient
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;

@@ -36,7 +36,20 @@ struct Tune {
 constexpr int kXcds = 8;  // blocks are dispatched to the XCDs round-robin by block index
 
 // First tile row of band k when a level's mark_ty tile rows are split over the XCDs.
-OF_HD int32_t band_row0(int32_t mark_ty, int32_t k) { return (mark_ty * k) / kXcds; }
+// Every band takes mark_ty / 8 consecutive rows; the mark_ty % 8 rows left over go one
+// each to bands rot, rot + 1, ... (mod 8).  rot carries on from entry to entry (the sum
+// of the leftovers of the entries before, mod 8), so the leftovers of a batch of levels
+// spread over all XCDs instead of piling onto the same few.
+OF_HD int32_t band_row0(int32_t mark_ty, int32_t rot, int32_t k) {
+  const int32_t q = mark_ty / kXcds, r = mark_ty % kXcds, hi = rot + r;
+  int32_t c = k - rot < 0 ? 0 : (k - rot < r ? k - rot : r);  // bands rot .. min(hi, 8) - 1
+  if (hi > kXcds) c += k < hi - kXcds ? k : hi - kXcds;      // wrapped: bands 0 .. hi - 9
+  return q * k + c;
+}
+
+OF_HD int32_t band_rows(int32_t mark_ty, int32_t rot, int32_t k) {
+  return band_row0(mark_ty, rot, k + 1) - band_row0(mark_ty, rot, k);
+}
 
 // One ranked candidate: R' and (y << 16 | x) in level coordinates.
 struct Cand {
@@ -69,6 +82,7 @@ struct LevelPlan {
   uint32_t* sel_count;
   uint32_t* ncand_count;       // FAST candidates of the level (statistics)
   int32_t mark_tx, mark_ty;    // segment-test tile grid (covers the whole level)
+  int32_t band_rot;            // first band that takes one of the leftover tile rows
   int32_t det_tx, det_ty;      // Harris/NMS tile grid (covers the valid region)
   int32_t det_x0, det_y0;      // first cell column/row (cell > 0) or first pixel (cell == 0)
   int32_t det_xend, det_yend;  // one past the last cell column/row, or W-B / H-B
@@ -204,6 +218,7 @@ struct WsLayout {
   int64_t off_counters, off_flags, off_bm, off_cand, off_sel, off_lvl, total;
   int32_t n_entries, mark_tiles, det_tiles, orient_blocks, rank_slots, max_cand_cap, pyr_blocks;
   int32_t band_tiles[kXcds];
+  int32_t band_rot;        // rotation of the next entry's leftover rows
   int64_t flag_bytes, bm_words, cand_entries, sel_entries, lvl_bytes;
 };
 
@@ -213,8 +228,8 @@ OF_HD void ws_layout_accumulate(WsLayout* w, const EntrySize& s) {
   w->det_tiles += s.det_tiles;
   w->orient_blocks += s.orient_blocks;
   w->pyr_blocks += s.pyr_blocks;
-  for (int k = 0; k < kXcds; ++k)
-    w->band_tiles[k] += s.mark_tx * (band_row0(s.mark_ty, k + 1) - band_row0(s.mark_ty, k));
+  for (int k = 0; k < kXcds; ++k) w->band_tiles[k] += s.mark_tx * band_rows(s.mark_ty, w->band_rot, k);
+  w->band_rot = (w->band_rot + s.mark_ty % kXcds) % kXcds;
   w->flag_bytes += s.flag_bytes;
   w->bm_words += s.bm_words;
   w->cand_entries += s.cand_cap;
@@ -264,10 +279,10 @@ OF_HD uint32_t resample_tap(int32_t i, int32_t n_src, int32_t n_dst) {
 // ------------------------------------------------------------- LDS layouts --
 
 // Segment-test tile: pixels (tile + 3-pixel halo, 4-aligned origin), the queue of
-// pixels that pass the compass pre-test, both bitmaps, and the resample tap tables.
+// pixels that pass the compass pre-test and both bitmaps.
 struct MarkLds {
   int32_t tw, th, pitch, rows, qseg;
-  int32_t off_queue, off_bml, off_bmh, off_xt, off_yt, bytes;
+  int32_t off_queue, off_bml, off_bmh, bytes;
 };
 
 OF_HD MarkLds mark_lds(const Tune& t) {
@@ -282,8 +297,6 @@ OF_HD MarkLds mark_lds(const Tune& t) {
   m.off_queue = o;  o += (int32_t)align_up(2 * 4 * m.qseg, 16);
   m.off_bml = o;    o += 4 * m.th * 2 * t.mark_words;
   m.off_bmh = o;    o += 4 * m.th * 2 * t.mark_words;
-  m.off_xt = o;     o += 4 * m.pitch;
-  m.off_yt = o;     o += 4 * m.rows;
   m.bytes = (int32_t)align_up(o, 16);
   return m;
 }

@@ -49,8 +49,8 @@ def time_tuning(det, frames, tune, calls=20, warmup=3):
 
 
 def candidates(p, n_cus):
-    marks = [dict(mark_words=w, mark_rows=r) for w in (1, 2, 4) for r in (8, 16, 24, 32, 48)
-             if 16 <= w * r <= 128]
+    marks = [dict(mark_words=w, mark_rows=r) for w in (1, 2, 4)
+             for r in (8, 16, 24, 32, 40, 48, 56, 64) if 16 <= w * r <= 128]
     if p.cell > 0:
         dets = [dict(det_cells_x=cx, det_cells_y=cy) for cx, cy in
                 ((1, 1), (2, 1), (4, 1), (2, 2), (8, 1), (4, 2))
