@@ -704,7 +704,7 @@ __global__ __launch_bounds__(256) void k_pyramid_batch(KArgs a) {
 // LDS row pitch at compile time, so every circle and compass offset below is a
 // ds_read immediate.
 template <bool FUSED, int TWW>
-__global__ __launch_bounds__(256, 4) void k_mark(KArgs a) {
+__global__ __launch_bounds__(256, 5) void k_mark(KArgs a) {
   constexpr int TW = 64 * TWW;
   constexpr int PITCH = TW + 8;
   extern __shared__ __align__(16) uint8_t smem[];
@@ -773,11 +773,12 @@ __global__ __launch_bounds__(256, 4) void k_mark(KArgs a) {
       gptr<const uint8_t> base = G(P.base);
       const int bs = P.base_stride, bw = P.base_w, bh1 = P.base_h - 1;
       constexpr int NC = TWW + 1;  // columns per lane: nx <= TW + 7
+      const double rw = 1.0 / (double)(2 * W), rh = 1.0 / (double)(2 * H);
       uint32_t cx[NC];
       int cwx[NC];
 #pragma unroll
       for (int c = 0; c < NC; ++c) {
-        const uint32_t txx = resample_tap(ox + min(lane + 64 * c, nx - 1), bw, W);
+        const uint32_t txx = resample_tap_r(ox + min(lane + 64 * c, nx - 1), bw, W, rw);
         int x0 = (int)(txx >> 9), wx = (int)(txx & 511);
         if (x0 >= bw - 1) {
           x0 = bw - 2;
@@ -786,8 +787,9 @@ __global__ __launch_bounds__(256, 4) void k_mark(KArgs a) {
         cx[c] = (uint32_t)x0;
         cwx[c] = wx;
       }
-      const uint32_t ty_a = resample_tap(oy + min(lane, ny - 1), P.base_h, H);
-      const uint32_t ty_b = resample_tap(oy + min(lane + 64, ny - 1), P.base_h, H);
+      const uint32_t ty_a = resample_tap_r(oy + min(lane, ny - 1), P.base_h, H, rh);
+      const uint32_t ty_b = ny > 64 ? resample_tap_r(oy + min(lane + 64, ny - 1), P.base_h, H, rh)
+                                    : 0u;
       gptr<uint8_t> lw = G(P.lvl_w) + (size_t)oy * P.lvl_stride + ox;
       const int lx0 = x_t0 - ox, lx1 = x_t1 - ox, ly0 = y_t0 - oy, ly1 = y_t1 - oy;
       // 2 * RPI * NC loads in flight; the most that fit the registers without spilling

@@ -276,6 +276,32 @@ OF_HD uint32_t resample_tap(int32_t i, int32_t n_src, int32_t n_dst) {
   return ((uint32_t)i0 << 9) | (uint32_t)q;
 }
 
+
+// The same tap with both divisions by den = 2 n_dst done as a multiply by rden, the double
+// nearest 1 / den, and one correction step.  Exact: num / den < 2^25 and num * rden is
+// within 2^-27 of num / den, while a non-integer num / den sits at least 1 / den >= 2^-16
+// from the next integer, so the truncated product is the floor or (num / den an integer)
+// one less, which the remainder test fixes; the same holds for 256 r / den < 256.
+OF_HD uint32_t resample_tap_r(int32_t i, int32_t n_src, int32_t n_dst, double rden) {
+  const int32_t num = (2 * i + 1) * n_src - n_dst;
+  const int32_t den = 2 * n_dst;
+  int32_t i0 = (int32_t)((double)num * rden);
+  int32_t r = num - i0 * den;
+  if (r >= den) {
+    ++i0;
+    r -= den;
+  }
+  const int32_t a = 256 * r;
+  int32_t q = (int32_t)((double)a * rden);
+  int32_t rr = a - q * den;
+  if (rr >= den) {
+    ++q;
+    rr -= den;
+  }
+  if (2 * rr > den || (2 * rr == den && (q & 1))) ++q;
+  return ((uint32_t)i0 << 9) | (uint32_t)q;
+}
+
 // ------------------------------------------------------------- LDS layouts --
 
 // Segment-test tile: pixels (tile + 3-pixel halo, 4-aligned origin), the queue of
