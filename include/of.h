@@ -92,8 +92,8 @@ typedef struct {
 } of_pyramid_desc;
 
 /* Launch shape of the batched path (tile sizes, grid sizes, pyramid pass).  Tile fields
- * set to 0 take the default; grid, pyr_pass, mark_order and plan_resident fields take
- * the default when negative.
+ * set to 0 take the default; grid, pyr_pass, mark_order, plan_resident and det_order
+ * fields take the default when negative.
  * of_tuning_default() reports the defaults for a batch.  det_w and det_h must be even. */
 typedef struct {
   int32_t mark_words; /* segment-test tile width in 64-pixel words, 1..4 */
@@ -114,6 +114,11 @@ typedef struct {
                          plan's signature; if ws was overwritten in between, nothing is
                          computed and every frame's count reads -1.  0 = always re-check
                          with a launch of its own (any workspace). */
+  int32_t det_order;  /* 1 = Harris/NMS tiles ordered by XCD band like the segment-test
+                         tiles (block b takes band b % 8 of the tile rows of every level),
+                         so with mark_order 1 a tile mostly reads pixels and bitmaps that
+                         its own XCD's L2 holds from the segment test; 0 = entry-major
+                         order.  Ignored with a persistent grid. */
 } of_tuning;
 
 /* Host only.  Level sizes, strides and offsets of the pyramid of a W x H frame. */

@@ -154,6 +154,7 @@ Tune default_tune(const of_params& p) {
   t.pyr_pass = 0;
   t.mark_order = 0;
   t.plan_resident = 0;
+  t.det_order = 0;
   // narrower Harris tiles where large cells would exceed the LDS budget
   while (p.cell > 0 && t.det_cx > 1 &&
          det_lds(t, p.cell).bytes + base_table_bytes(kMaxEntries) > 65536)
@@ -175,6 +176,7 @@ int resolve_tune(const of_tuning* user, const of_params& p, Tune* out) {
     if (user->pyr_pass >= 0) t.pyr_pass = user->pyr_pass != 0;
     if (user->mark_order >= 0) t.mark_order = user->mark_order != 0;
     if (user->plan_resident >= 0) t.plan_resident = user->plan_resident != 0;
+    if (user->det_order >= 0) t.det_order = user->det_order != 0;
   }
   if (t.mark_words < 1 || t.mark_words > 4 || t.mark_rows < 4 || t.mark_rows > 64)
     return OF_EINVAL;
@@ -274,6 +276,7 @@ KArgs kargs(void* ws, const WsLayout& lay, const Tune& t, const of_params& p) {
   k.flags = b + lay.off_flags;
   k.flag_bytes = lay.flag_bytes;
   k.band_base = (const int32_t*)(b + lay.off_band_base);
+  k.det_band_base = (const int32_t*)(b + lay.off_det_band_base);
   k.rank_path = 1;
   k.qctr = (uint32_t*)(b + lay.off_hdr);
   k.ws_sig = (const uint64_t*)(b + lay.off_hdr + 128);
@@ -284,7 +287,7 @@ KArgs kargs(void* ws, const WsLayout& lay, const Tune& t, const of_params& p) {
   return k;
 }
 
-enum BaseKind { kMarkTiles, kMarkBands, kDetTiles, kRankSlots, kPyrBlocks };
+enum BaseKind { kMarkTiles, kMarkBands, kDetTiles, kDetBands, kRankSlots, kPyrBlocks };
 
 // The launch's prefix table (units per entry), copied into the kernel arguments when the
 // call has at most kSmallEntries entries; the kernels then skip loading it.
@@ -292,10 +295,11 @@ void set_small_bases(KArgs& k, const CallPlan& c, BaseKind kind) {
   const int n = c.lay.n_entries;
   k.small = n <= kSmallEntries;
   if (!k.small) return;
-  const int rows = kind == kMarkBands || kind == kMarkTiles ? kXcds : 1;
+  // the tile kernels read row blockIdx % kXcds (their band, or a copy of row 0)
+  const int rows = kind == kRankSlots || kind == kPyrBlocks ? 1 : kXcds;
   for (int r = 0; r < rows; ++r) {
     int32_t* b = k.sbase + r * (kSmallEntries + 1);
-    int32_t acc = 0, rot = 0;
+    int32_t acc = 0, rot = 0, drot = 0;
     for (int e = 0; e < n; ++e) {
       b[e] = acc;
       const EntrySize& s = c.es[e];
@@ -306,6 +310,10 @@ void set_small_bases(KArgs& k, const CallPlan& c, BaseKind kind) {
           rot = (rot + s.mark_ty % kXcds) % kXcds;
           break;
         case kDetTiles: acc += s.det_tiles; break;
+        case kDetBands:
+          acc += s.det_tx * band_rows(s.det_ty, drot, r);
+          drot = (drot + s.det_ty % kXcds) % kXcds;
+          break;
         case kRankSlots: acc += (int32_t)(s.cand_cap < kRankCap ? s.cand_cap : kRankCap); break;
         case kPyrBlocks: acc += s.pyr_blocks; break;
       }
@@ -418,6 +426,7 @@ int of_tuning_default(const of_image* frames, int32_t n, const of_params* params
   out->pyr_pass = t.pyr_pass;
   out->mark_order = t.mark_order;
   out->plan_resident = t.plan_resident;
+  out->det_order = t.det_order;
   return OF_OK;
 }
 
@@ -535,7 +544,15 @@ int of_detect_batch(const of_image* frames, int32_t n, const of_params* params, 
     k.total = c->lay.det_tiles;
     set_small_bases(k, *c, kDetTiles);
     k.persistent = t.det_grid > 0 && t.det_grid < k.total;
+    if (!k.persistent && t.det_order == 1) {
+      int32_t widest = 0;
+      for (int b = 0; b < kXcds; ++b) widest = std::max(widest, c->lay.det_band_tiles[b]);
+      k.bands = 1;
+      k.total = kXcds * widest;
+      set_small_bases(k, *c, kDetBands);
+    }
     e = timed(3, stream, [&] { return launch_detect(k, k.persistent ? t.det_grid : k.total, stream); });
+    k.bands = 0;
   }
   if (e == hipSuccess) e = launch_selection(k, *c, stream);
   delete c;

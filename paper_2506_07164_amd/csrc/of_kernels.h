@@ -39,7 +39,7 @@ struct KArgs {
   int32_t total;               // tiles (or blocks) of this launch
   int32_t entry;               // >= 0: one entry only, tile = blockIdx.x
   int32_t persistent;          // 1: blocks draw tiles from qctr until exhausted
-  int32_t bands;               // 1: k_mark block b takes band b % kXcds, tile b / kXcds of it
+  int32_t bands;               // 1: block b takes band b % kXcds, tile b / kXcds of it
   int32_t small;               // 1: the prefix table of this launch is in sbase
   uint32_t* qctr;              // queue counters: [0] segment-test tiles, [2] Harris tiles
   int32_t cell;                // params.cell
@@ -58,6 +58,7 @@ struct KArgs {
   const int32_t* rank_base;    // exclusive prefix of ranked candidate slots per entry
   const int32_t* pyr_base;     // exclusive prefix of resample blocks per entry
   const int32_t* band_base;    // kXcds tables: prefix of segment-test tiles per entry in band k
+  const int32_t* det_band_base;  // the same for Harris/NMS tiles
   int32_t n_frames;
   // Batches of at most kSmallEntries entries carry the launch's prefix table here, so
   // blocks find their entry without a memory load: entries 0 .. n_entries - 1, INT32_MAX

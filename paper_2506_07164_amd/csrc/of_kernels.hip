@@ -539,6 +539,14 @@ __global__ __launch_bounds__(1024) void k_prologue(PrologueArgs a) {
     if (i < nL) band_base[k * (nL + 1) + i] = (int32_t)o_band;
     if (i == 0) band_base[k * (nL + 1) + nL] = (int32_t)s_tot;
   }
+  const int32_t drot = (int32_t)(scan(s.det_ty % kXcds) % kXcds);
+  int32_t* det_band_base = (int32_t*)(ws + a.lay.off_det_band_base);
+  for (int k = 0; k < kXcds; ++k) {
+    const int32_t rows = band_rows(s.det_ty, drot, k);
+    const int64_t o_band = scan(i < nL ? (int64_t)s.det_tx * rows : 0);
+    if (i < nL) det_band_base[k * (nL + 1) + i] = (int32_t)o_band;
+    if (i == 0) det_band_base[k * (nL + 1) + nL] = (int32_t)s_tot;
+  }
 
   LevelPlan* plan = (LevelPlan*)(ws + a.lay.off_plan);
   int32_t* mark_base = (int32_t*)(ws + a.lay.off_mark_base);
@@ -592,6 +600,7 @@ __global__ __launch_bounds__(1024) void k_prologue(PrologueArgs a) {
     P.mark_tx = s.mark_tx;
     P.mark_ty = s.mark_ty;
     P.band_rot = rot;
+    P.det_band_rot = drot;
     P.det_tx = s.det_tx;
     P.det_ty = s.det_ty;
     P.det_x0 = s.det_x0;
@@ -974,7 +983,8 @@ __global__ __launch_bounds__(256, 4) void k_detect(KArgs a) {
   extern __shared__ __align__(16) uint8_t smem[];
   __shared__ int s_next, s_ns, s_ne, s_nin;
   __shared__ uint32_t s_wsum[16];
-  const Head h = read_head(a, 0);
+  const int band = (int)(blockIdx.x % kXcds);  // used in the band order only
+  const Head h = read_head(a, band);
   const DetLds D = det_lds(h.t, h.cell);
   uint8_t* pix = smem;
   uint32_t* cw = (uint32_t*)(smem + D.off_cw);
@@ -997,14 +1007,19 @@ __global__ __launch_bounds__(256, 4) void k_detect(KArgs a) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nwave = kBlock >> 6;
   const int bd = (int)kBlock, tid = (int)threadIdx.x;
   const uint64_t wsig = *G(h.ws_sig);  // compared before the plan's pointers are used
-  if (h.entry < 0 && !h.small) load_bases(s_base, a.det_base, h.n_entries);
+  if (h.entry < 0 && !h.small)
+    load_bases(s_base, h.bands ? a.det_band_base + band * (h.n_entries + 1) : a.det_base,
+               h.n_entries);
   queue_start(h, h.qctr + 2, &s_next);
 
   for (int iter = 0;; ++iter) {
-    const int g = uniform(queue_take(h, iter, &s_next));
-    if (g >= h.total) break;
+    const int g0 = uniform(queue_take(h, iter, &s_next));
+    if (g0 >= h.total) break;
+    const int g = h.bands ? g0 / kXcds : g0;
+    if (h.bands && g >= (h.small ? h.b[kSmallEntries] : s_base[h.n_entries]))
+      break;  // band holds fewer tiles
     if (h.persistent) lds_barrier();  // every thread has read s_next
-    const int next = queue_prefetch(h, g, h.qctr + 2);
+    const int next = queue_prefetch(h, g0, h.qctr + 2);
     int e, t;
     if (h.entry >= 0) {
       e = h.entry;
@@ -1020,7 +1035,8 @@ __global__ __launch_bounds__(256, 4) void k_detect(KArgs a) {
     const LevelPlan P = h.plan[e];
     if (wsig != h.sig) break;  // not the plan this launch was made for
     const int W = P.W, H = P.H, B = P.B, cs = P.cs;
-    const int tx = t % P.det_tx, ty = t / P.det_tx;
+    const int tx = t % P.det_tx;
+    const int ty = t / P.det_tx + (h.bands ? band_row0(P.det_ty, P.det_band_rot, band) : 0);
     int vx0, vx1, vy0, vy1, cxa = 0, cya = 0, nlcx = 1, nlcy = 1;
     if (h.cell > 0) {
       cxa = P.det_x0 + tx * h.t.det_cx;

@@ -31,6 +31,7 @@ struct Tune {
   int32_t pyr_pass;  // 1: levels are resampled by a separate pass before the segment test
   int32_t mark_order;  // 1: segment-test tiles in XCD bands (block b on XCD b % 8)
   int32_t plan_resident;  // 1: skip the prologue when this workspace holds this plan
+  int32_t det_order;  // 1: Harris/NMS tiles in the segment test's XCD bands
 };
 
 constexpr int kXcds = 8;  // blocks are dispatched to the XCDs round-robin by block index
@@ -83,6 +84,7 @@ struct LevelPlan {
   uint32_t* ncand_count;       // FAST candidates of the level (statistics)
   int32_t mark_tx, mark_ty;    // segment-test tile grid (covers the whole level)
   int32_t band_rot;            // first band that takes one of the leftover tile rows
+  int32_t det_band_rot;        // the same for the Harris/NMS tile rows
   int32_t det_tx, det_ty;      // Harris/NMS tile grid (covers the valid region)
   int32_t det_x0, det_y0;      // first cell column/row (cell > 0) or first pixel (cell == 0)
   int32_t det_xend, det_yend;  // one past the last cell column/row, or W-B / H-B
@@ -215,10 +217,13 @@ struct WsLayout {
   int64_t off_hdr, off_plan, off_mark_base, off_det_base, off_orient_base, off_rank_base;
   int64_t off_pyr_base;
   int64_t off_band_base;   // kXcds prefix tables of segment-test tiles per entry, by band
+  int64_t off_det_band_base;  // the same for Harris/NMS tiles
   int64_t off_counters, off_flags, off_bm, off_cand, off_sel, off_lvl, total;
   int32_t n_entries, mark_tiles, det_tiles, orient_blocks, rank_slots, max_cand_cap, pyr_blocks;
   int32_t band_tiles[kXcds];
+  int32_t det_band_tiles[kXcds];
   int32_t band_rot;        // rotation of the next entry's leftover rows
+  int32_t det_band_rot;    // the same for Harris/NMS tile rows
   int64_t flag_bytes, bm_words, cand_entries, sel_entries, lvl_bytes;
 };
 
@@ -228,8 +233,12 @@ OF_HD void ws_layout_accumulate(WsLayout* w, const EntrySize& s) {
   w->det_tiles += s.det_tiles;
   w->orient_blocks += s.orient_blocks;
   w->pyr_blocks += s.pyr_blocks;
-  for (int k = 0; k < kXcds; ++k) w->band_tiles[k] += s.mark_tx * band_rows(s.mark_ty, w->band_rot, k);
+  for (int k = 0; k < kXcds; ++k) {
+    w->band_tiles[k] += s.mark_tx * band_rows(s.mark_ty, w->band_rot, k);
+    w->det_band_tiles[k] += s.det_tx * band_rows(s.det_ty, w->det_band_rot, k);
+  }
   w->band_rot = (w->band_rot + s.mark_ty % kXcds) % kXcds;
+  w->det_band_rot = (w->det_band_rot + s.det_ty % kXcds) % kXcds;
   w->flag_bytes += s.flag_bytes;
   w->bm_words += s.bm_words;
   w->cand_entries += s.cand_cap;
@@ -249,6 +258,7 @@ OF_HD void ws_layout_finish(WsLayout* w) {
   w->off_rank_base = o;    o = align_up(o + 4 * ((int64_t)w->n_entries + 1), 256);
   w->off_pyr_base = o;     o = align_up(o + 4 * ((int64_t)w->n_entries + 1), 256);
   w->off_band_base = o;    o = align_up(o + 4 * kXcds * ((int64_t)w->n_entries + 1), 256);
+  w->off_det_band_base = o;  o = align_up(o + 4 * kXcds * ((int64_t)w->n_entries + 1), 256);
   // counters per entry: filled candidate slots, selected (radix path), FAST candidates
   w->off_counters = o;     o = align_up(o + 12 * (int64_t)w->n_entries, 256);
   w->off_flags = o;        o = align_up(o + w->flag_bytes, 256);

@@ -47,7 +47,7 @@ class OfPyramidDesc(ctypes.Structure):
 class OfTuning(ctypes.Structure):
     _fields_ = [(n, ctypes.c_int32) for n in (
         "mark_words", "mark_rows", "det_cells_x", "det_cells_y", "det_w", "det_h",
-        "mark_grid", "det_grid", "pyr_pass", "mark_order", "plan_resident")]
+        "mark_grid", "det_grid", "pyr_pass", "mark_order", "plan_resident", "det_order")]
 
 
 KEYPOINT_DTYPE = np.dtype([("x", "<i4"), ("y", "<i4"), ("level", "<i4"), ("m10", "<i4"),
@@ -117,6 +117,7 @@ def tuning(**kw) -> OfTuning:
     t.pyr_pass = -1
     t.mark_order = -1
     t.plan_resident = -1
+    t.det_order = -1
     for k, v in kw.items():
         setattr(t, k, v)
     return t

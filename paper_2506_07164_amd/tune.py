@@ -21,7 +21,7 @@ CACHE = os.environ.get("OF_TUNE_CACHE", os.path.join(os.path.dirname(os.path.abs
 SHIPPED = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tuned.json")
 
 FIELDS = ("mark_words", "mark_rows", "det_cells_x", "det_cells_y", "det_w", "det_h",
-          "mark_grid", "det_grid", "pyr_pass", "mark_order")
+          "mark_grid", "det_grid", "pyr_pass", "mark_order", "det_order")
 
 
 def _key(shapes, p, device_name):
@@ -57,9 +57,10 @@ def candidates(p, n_cus):
                 if cx * p.cell <= 256 and cy * p.cell <= 128]
     else:
         dets = [dict(det_w=w, det_h=h) for w, h in ((64, 32), (128, 32), (128, 64), (256, 32))]
-    grids = [dict(mark_grid=0, det_grid=0, pyr_pass=0, mark_order=0),
-             dict(mark_grid=0, det_grid=0, pyr_pass=0, mark_order=1),
-             dict(mark_grid=0, det_grid=0, pyr_pass=1, mark_order=1)]
+    grids = [dict(mark_grid=0, det_grid=0, pyr_pass=0, mark_order=0, det_order=0),
+             dict(mark_grid=0, det_grid=0, pyr_pass=0, mark_order=1, det_order=0),
+             dict(mark_grid=0, det_grid=0, pyr_pass=0, mark_order=1, det_order=1),
+             dict(mark_grid=0, det_grid=0, pyr_pass=1, mark_order=1, det_order=1)]
     grids += [dict(mark_grid=m * n_cus, det_grid=d * n_cus) for m, d in ((2, 2), (4, 3))]
     return marks, dets, grids
 

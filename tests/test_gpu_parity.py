@@ -219,7 +219,11 @@ def test_c2_plain_and_fused(hip):
                                   dict(pyr_pass=1), dict(pyr_pass=1, mark_words=1, mark_rows=8,
                                                          mark_grid=64),
                                   dict(mark_order=1), dict(mark_order=1, mark_words=2, mark_rows=48),
-                                  dict(mark_order=1, mark_words=3, mark_rows=5, pyr_pass=1)])
+                                  dict(mark_order=1, mark_words=3, mark_rows=5, pyr_pass=1),
+                                  dict(det_order=1),
+                                  dict(mark_order=1, det_order=1, mark_words=2, mark_rows=56),
+                                  dict(mark_order=1, det_order=1, det_cells_x=2, det_cells_y=3,
+                                       mark_rows=7)])
 def test_c2_tunings_agree(hip, tune):
     spec = CONFIGS["c2"]["frames"][0]
     kw = CONFIGS["c2"]["params"]
@@ -230,7 +234,9 @@ def test_c2_tunings_agree(hip, tune):
 
 
 @pytest.mark.parametrize("tune", [dict(det_w=8, det_h=8), dict(det_w=64, det_h=32),
-                                  dict(det_w=64, det_h=16, pyr_pass=1, det_grid=5)])
+                                  dict(det_w=64, det_h=16, pyr_pass=1, det_grid=5),
+                                  dict(det_w=64, det_h=32, mark_order=1, det_order=1),
+                                  dict(det_w=8, det_h=10, mark_rows=9, det_order=1)])
 def test_whole_level_cell_tunings_agree(hip, tune):
     """cell = 0 (one cell per level, K = N_l): output slots per 2x2 block, any tiling."""
     kw = _kw(n_levels=3, cell=0, fast_t=8, fast_t_min=8, n_features=400)
@@ -269,7 +275,7 @@ def test_c3_batch(hip):
     for i, (g, r) in enumerate(zip(res, refs)):
         assert_same_keypoints(g, r, f"c3 frame {i} (pyramid pass)")
     log("case: c3 batch, XCD-band tile order")
-    res = run_batch(hip, imgs, kw, hip.tuning(mark_order=1))
+    res = run_batch(hip, imgs, kw, hip.tuning(mark_order=1, det_order=1))
     for i, (g, r) in enumerate(zip(res, refs)):
         assert_same_keypoints(g, r, f"c3 frame {i} (bands)")
 
@@ -367,7 +373,8 @@ def test_resident_plan(hip):
         slot.copy_(torch.from_numpy(imgs[k]))
         det.detect_batch([slot])
         assert_same_keypoints(det.results()[0], refs[k], f"resident call {k}")
-    for tune in (dict(mark_grid=64, det_grid=32), dict(mark_order=1, pyr_pass=1)):
+    for tune in (dict(mark_grid=64, det_grid=32), dict(mark_order=1, pyr_pass=1),
+                 dict(mark_order=1, det_order=1)):
         for k in range(2):
             slot.copy_(torch.from_numpy(imgs[k]))
             det.detect_batch([slot], tune=hip.tuning(**tune))
