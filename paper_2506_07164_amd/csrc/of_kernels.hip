@@ -223,6 +223,7 @@ __device__ __forceinline__ uint32_t load_word(gptr<const uint8_t> s, bool whole,
 
 // Bytes p[0] (low) and p[1] (high) with one 16-bit load at any alignment.
 typedef uint16_t u16_any_align __attribute__((aligned(1)));
+typedef uint32_t u32_any_align __attribute__((aligned(1)));
 __device__ __forceinline__ uint32_t load_pair(gptr<const uint8_t> p) {
   return *(gptr<const u16_any_align>)p;
 }
@@ -398,32 +399,61 @@ __device__ void block_scan_u32(const uint32_t* cnt, uint32_t* pre, int n, uint32
   lds_barrier();
 }
 
-// Intensity-centroid moments over the disk dx^2 + dy^2 <= r^2 around (x, y), one wave
-// cooperating: lanes cover rows of the disk, all loads of a batch are issued first.
+// m10 = sum dx I and m01 = sum dy I over the disk dx^2 + dy^2 <= r^2 around (x, y), by
+// one wave.  For r <= 15 the 2r+1 square box is read with one 32-bit load per lane and
+// box row: lane (row group lane / 8, column group lane % 8) reads 4 consecutive pixels
+// starting at box column min(4 (lane % 8), 2r - 3), so every load stays inside the box,
+// and counts only the pixels no lower column group holds; rows lane / 8 + 8k past the
+// box are not read.  Larger radii take rows and columns in passes of 8 loads.
 __device__ __forceinline__ void wave_moments(gptr<const uint8_t> lvl, int stride, int x, int y,
                                              int r, int lane, int* m10, int* m01) {
   const int span = 2 * r + 1;
-  const int cspan = min(span, 64);
-  const int rows_per = 64 / cspan;
-  const int lr = lane / cspan, lc = lane - lr * cspan;
   const int r2 = r * r;
   int a = 0, b = 0;
-  if (lr < rows_per) {
-    for (int c0 = 0; c0 < span; c0 += cspan) {
-      const int dx = c0 + lc - r;
-      for (int k0 = 0; k0 * rows_per < span; k0 += 16) {
-        int v[16];
+  if (r <= 15) {
+    const int lr = lane >> 3, lc4 = (lane & 7) * 4;
+    const int c0 = min(lc4, span - 4);  // first box column of this lane's load
+    gptr<const uint8_t> base = lvl + (size_t)(y - r) * stride + (x - r + c0);
+    uint32_t v[4];
 #pragma unroll
-        for (int k = 0; k < 16; ++k) {
-          const int dy = (k0 + k) * rows_per + lr - r;
-          const bool in = dy <= r && dx <= r && dx * dx + dy * dy <= r2;
-          v[k] = in ? (int)lvl[(size_t)(y + dy) * stride + x + dx] : 0;
-        }
+    for (int k = 0; k < 4; ++k) {
+      const int row = lr + 8 * k;
+      v[k] = row < span ? *(gptr<const u32_any_align>)(base + (size_t)row * stride) : 0u;
+    }
 #pragma unroll
-        for (int k = 0; k < 16; ++k) {
-          const int dy = (k0 + k) * rows_per + lr - r;
-          a += dx * v[k];
-          b += dy * v[k];
+    for (int k = 0; k < 4; ++k) {
+      const int dy = lr + 8 * k - r;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int c = c0 + q;
+        const int dx = c - r;
+        const int px = (int)((v[k] >> (8 * q)) & 255u);
+        const bool in = c >= lc4 && dx * dx + dy * dy <= r2;  // rows past the box read 0
+        a += in ? dx * px : 0;
+        b += in ? dy * px : 0;
+      }
+    }
+  } else {
+    const int cspan = min(span, 64);
+    const int rows_per = 64 / cspan;
+    const int lr = lane / cspan, lc = lane - lr * cspan;
+    if (lr < rows_per) {
+      for (int c0 = 0; c0 < span; c0 += cspan) {
+        const int dx = c0 + lc - r;
+        for (int k0 = 0; k0 * rows_per < span; k0 += 8) {
+          int v[8];
+#pragma unroll
+          for (int k = 0; k < 8; ++k) {
+            const int dy = (k0 + k) * rows_per + lr - r;
+            const bool in = dy <= r && dx <= r && dx * dx + dy * dy <= r2;
+            v[k] = in ? (int)lvl[(size_t)(y + dy) * stride + x + dx] : 0;
+          }
+#pragma unroll
+          for (int k = 0; k < 8; ++k) {
+            const int dy = (k0 + k) * rows_per + lr - r;
+            a += dx * v[k];
+            b += dy * v[k];
+          }
         }
       }
     }
@@ -1452,24 +1482,25 @@ __global__ __launch_bounds__(256) void k_select_orient(KArgs a) {
   gptr<const Cand> cand = G((const Cand*)P.cand);
   const Cand me = load_cand(cand + i);
   if (me.pos == kNoPos) return;
-  // Count better candidates, 12 slots in flight per lane (score and position only); a
-  // wave whose partial count already reaches the quota cannot be selected and stops.
+  // Count better candidates, 8 slots in flight per lane (score and position only, few
+  // registers: every slot's wave of a call stays resident); a wave whose partial count
+  // already reaches the quota cannot be selected and stops.
   int cnt = 0;
-  for (int j0 = 0; j0 < C; j0 += 12 * 64) {
-    int64_t sc[12];
-    uint32_t ps[12];
+  for (int j0 = 0; j0 < C; j0 += 8 * 64) {
+    int64_t sc[8];
+    uint32_t ps[8];
 #pragma unroll
-    for (int u = 0; u < 12; ++u) {
+    for (int u = 0; u < 8; ++u) {
       gptr<const Cand> q = cand + min(j0 + u * 64 + lane, C - 1);
       sc[u] = *(gptr<const int64_t>)q;
       ps[u] = *((gptr<const uint32_t>)q + 2);
     }
 #pragma unroll
-    for (int u = 0; u < 12; ++u) {
+    for (int u = 0; u < 8; ++u) {
       const int j = j0 + u * 64 + lane;
       cnt += (j < C && better(sc[u], ps[u], me.score, me.pos)) ? 1 : 0;
     }
-    if (j0 + 12 * 64 < C && wave_sum(cnt) >= P.quota) return;
+    if (j0 + 8 * 64 < C && wave_sum(cnt) >= P.quota) return;
   }
   const int rank = wave_sum(cnt);
   if (rank >= P.quota) return;
