@@ -246,8 +246,9 @@ int of_test_segment(const uint8_t* circles, int32_t n, int32_t t_lo, int32_t t_h
  * milliseconds and launch counts of the first n steps (host arrays) and clears them.
  * Events come from a fixed pool created on the first enable; launches beyond the pool
  * are not timed (their count is still reported in launches[]).  on > 1 also issues each
- * repeatable launch (pyramid, segment test without a persistent grid, level selection:
- * launches that give the same results when issued again) `on` times back to back
+ * repeatable launch (pyramid, segment test and Harris/NMS without a persistent grid,
+ * level selection: launches that give the same results when issued again, the
+ * Harris/NMS candidate counters being divided back afterwards) `on` times back to back
  * between its events, so that ms / launches is the kernel's own duration; results are
  * unchanged.  on = 0 disables. */
 #define OF_PROFILE_STEPS 8

@@ -34,15 +34,22 @@ Profiler g_prof;
 
 // Runs `launch` with profiling events attached to its dispatch (start as the kernel
 // begins, stop as it ends).  A repeatable launch (one that gives the same results when
-// issued again: it neither accumulates nor draws from a queue) is issued `repeat` times
-// back to back, start on the first dispatch and stop on the last.
+// issued again, or whose only accumulation the caller scales back: it does not draw
+// from a queue) is issued `repeat` times back to back, start on the first dispatch and
+// stop on the last; *issued reports how many times it ran.
 template <class F>
-hipError_t timed(int step, hipStream_t s, F&& launch, bool repeatable = false) {
+hipError_t timed(int step, hipStream_t s, F&& launch, bool repeatable = false,
+                 int* issued = nullptr) {
+  if (issued) *issued = 1;
   if (!g_prof.on) return launch();
   std::lock_guard<std::mutex> lk(g_prof.mu);
   const int times = repeatable ? g_prof.repeat : 1;
   g_prof.launches[step] += times;
-  if (g_prof.used >= kEventPool) return launch();
+  if (g_prof.used >= kEventPool) {
+    g_prof.launches[step] += 1 - times;
+    return launch();
+  }
+  if (issued) *issued = times;
   const int k = g_prof.used++;
   g_prof.step_of[k] = step;
   hipError_t e = hipSuccess;
@@ -136,8 +143,8 @@ int device_cus() {
 // (whole cells), or 128 x 32 pixels when the level is one cell.
 Tune default_tune(const of_params& p) {
   Tune t;
-  t.mark_words = 4;
-  t.mark_rows = 16;
+  t.mark_words = 2;
+  t.mark_rows = 56;
   if (p.cell > 0) {
     t.det_cx = 240 / p.cell > 0 ? 240 / p.cell : 1;
     t.det_cy = 30 / p.cell > 0 ? 30 / p.cell : 1;
@@ -152,7 +159,7 @@ Tune default_tune(const of_params& p) {
   t.mark_grid = 0;
   t.det_grid = 0;
   t.pyr_pass = 0;
-  t.mark_order = 0;
+  t.mark_order = 1;  // XCD bands: measured faster on every workload here
   t.plan_resident = 0;
   t.det_order = 0;
   // narrower Harris tiles where large cells would exceed the LDS budget
@@ -477,7 +484,9 @@ int of_detect(const of_image* in, const of_params* params, void* ws, size_t ws_b
   for (int l = 0; l < L && e == hipSuccess; ++l) {
     k.entry = l;
     k.total = c->es[l].det_tiles;
-    e = timed(3, stream, [&] { return launch_detect(k, k.total, stream); });
+    int issued = 1;
+    e = timed(3, stream, [&] { return launch_detect(k, k.total, stream); }, true, &issued);
+    if (e == hipSuccess && issued > 1) e = launch_scale_counters(k, issued, stream);
   }
   if (e == hipSuccess) e = launch_selection(k, *c, stream);
   delete c;
@@ -551,7 +560,12 @@ int of_detect_batch(const of_image* frames, int32_t n, const of_params* params, 
       k.total = kXcds * widest;
       set_small_bases(k, *c, kDetBands);
     }
-    e = timed(3, stream, [&] { return launch_detect(k, k.persistent ? t.det_grid : k.total, stream); });
+    // Repeated for profiling only without a persistent grid; its candidate counters are
+    // then divided back by the number of issues.
+    int issued = 1;
+    e = timed(3, stream, [&] { return launch_detect(k, k.persistent ? t.det_grid : k.total, stream); },
+              !k.persistent, &issued);
+    if (e == hipSuccess && issued > 1) e = launch_scale_counters(k, issued, stream);
     k.bands = 0;
   }
   if (e == hipSuccess) e = launch_selection(k, *c, stream);

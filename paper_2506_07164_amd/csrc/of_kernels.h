@@ -92,6 +92,7 @@ hipError_t launch_pyramid(const PyrArgs& a, int n_levels, int max_w, int max_h, 
 hipError_t launch_pyramid_batch(const KArgs& a, int blocks, hipStream_t s);
 hipError_t launch_mark(const KArgs& a, bool fused, int grid, hipStream_t s);
 hipError_t launch_detect(const KArgs& a, int grid, hipStream_t s);
+hipError_t launch_scale_counters(const KArgs& a, int times, hipStream_t s);
 hipError_t launch_select_orient(const KArgs& a, int slots, hipStream_t s);
 hipError_t launch_select(const KArgs& a, int grid, hipStream_t s);
 hipError_t launch_orient(const KArgs& a, int grid, hipStream_t s);

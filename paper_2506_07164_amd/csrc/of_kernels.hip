@@ -2236,6 +2236,24 @@ hipError_t launch_detect(const KArgs& a, int grid, hipStream_t s) {
   return hipGetLastError();
 }
 
+// Candidate counters of the entries (one, or all when entry < 0) divided by `times`:
+// after a Harris/NMS launch issued `times` times back to back for profiling, each count
+// is exactly `times` times its value (every issue adds the same amount).
+__global__ __launch_bounds__(256) void k_scale_counters(uint32_t* counters, int n, int entry,
+                                                        int times) {
+  const int i = (int)(blockIdx.x * blockDim.x + threadIdx.x);
+  const int e = entry >= 0 ? entry : i;
+  if ((entry >= 0 && i > 0) || e >= n) return;
+  G(counters)[e] /= (uint32_t)times;          // filled candidate slots
+  G(counters)[2 * n + e] /= (uint32_t)times;  // FAST candidates
+}
+
+hipError_t launch_scale_counters(const KArgs& a, int times, hipStream_t s) {
+  hipLaunchKernelGGL(k_scale_counters, dim3(cdiv(a.n_entries, 256)), dim3(256), 0, s, a.counters,
+                     a.n_entries, a.entry, times);
+  return hipGetLastError();
+}
+
 hipError_t launch_select_orient(const KArgs& a, int slots, hipStream_t s) {
   OF_LAUNCH(k_select_orient, dim3(cdiv(slots, 4)), dim3(256), 0, s, a);
   return hipGetLastError();

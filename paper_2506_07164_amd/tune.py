@@ -1,7 +1,8 @@
 """Autotuner for the batched path: tile shapes and persistent grid sizes.
 
 For a batch shape (frame sizes + detector parameters) it times candidate launch shapes
-of of_detect_batch on the device and keeps the fastest.  The search is coordinate
+of of_detect_batch on the device (with the plan resident in the workspace, as a detector
+that owns its workspace runs) and keeps the fastest.  The search is coordinate
 descent over (segment-test tile, Harris/NMS tile, grids) from the library defaults;
 every candidate is timed with HIP events over a few calls after a warm-up.  Results are
 cached in a JSON file keyed by GPU name, frame sizes and parameters.  Outputs do not
@@ -93,7 +94,7 @@ def autotune(frames, p, calls=20, use_cache=True, verbose=False):
             if key in found:
                 return found[key]["tuning"]
     n_cus = torch.cuda.get_device_properties(0).multi_processor_count
-    det = ofhip.Detector(shapes, p)
+    det = ofhip.Detector(shapes, p, resident=True)  # timed as bench.py runs it: plan resident
     best = {}
     default = ofhip.of_tuning_default([ofhip.image_of(f) for f in frames], p)
     for f in FIELDS:

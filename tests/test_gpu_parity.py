@@ -358,6 +358,39 @@ def test_candidate_counts_match_oracle(hip, which):
     assert det.candidates([frame])[0].tolist() == want
 
 
+@pytest.mark.parametrize("which", ["c2", "whole-level cells, appended candidates"])
+def test_profiling_repeats_keep_results(hip, which):
+    """of_profile_enable(n > 1) issues repeatable launches n times back to back for
+    timing, the Harris/NMS launch included (its candidate counters are divided back):
+    keypoints and candidate counts stay those of the oracle, batched and plain."""
+    if which == "c2":
+        spec, kw = CONFIGS["c2"]["frames"][0], CONFIGS["c2"]["params"]
+    else:  # levels past the rank cap: tiles append their survivors to a counted list
+        spec, kw = FrameSpec(700, 500, 9, 80, 2.0, texture_amp=6), \
+            _kw(n_levels=2, cell=0, fast_t=8, fast_t_min=8, n_features=3000)
+    log(f"case: profiling repeats, {which}")
+    img = make_frame(spec)
+    p = oracle.params(**kw)
+    ref = oracle.detect(img, p)
+    want = [int(oracle.level_detect(lvl, p, level=l)["cand"].sum())
+            for l, lvl in enumerate(oracle.pyramid(img, p))]
+    frame = torch.from_numpy(img).cuda()
+    det = hip.Detector([img.shape], hip.params(**kw))
+    hip.of_profile_enable(4)
+    try:
+        det.detect_batch([frame])
+        got, counts = det.results()[0], det.candidates([frame])[0].tolist()
+        det.detect_plain(frame)
+        got_plain, counts_plain = det.results()[0], det.candidates([frame])[0].tolist()
+        prof = hip.of_profile_read()
+    finally:
+        hip.of_profile_enable(0)
+    assert prof["harris_nms_cells"][1] > 0
+    assert_same_keypoints(got, ref, f"{which} batched, profiled")
+    assert_same_keypoints(got_plain, ref, f"{which} plain, profiled")
+    assert counts == want and counts_plain == want
+
+
 def test_resident_plan(hip):
     """plan_resident: identical results call after call (state left zeroed for the next
     call), in a graph with new frame contents, with persistent grids; an overwritten
