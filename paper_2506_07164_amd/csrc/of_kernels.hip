@@ -222,6 +222,18 @@ __device__ __forceinline__ uint32_t load_word(gptr<const uint8_t> s, bool whole,
 }
 
 // Bytes p[0] (low) and p[1] (high) with one 16-bit load at any alignment.
+typedef unsigned short u16x2 __attribute__((ext_vector_type(2)));
+
+// (lo, hi) as two 16-bit lanes (both < 2^16).
+__device__ __forceinline__ u16x2 pair16(uint32_t lo, uint32_t hi) {
+  return __builtin_bit_cast(u16x2, lo | (hi << 16));
+}
+
+// Bytes 0 and 1 of v as two 16-bit lanes.
+__device__ __forceinline__ u16x2 bytes16(uint32_t v) {
+  return __builtin_bit_cast(u16x2, __builtin_amdgcn_perm(0u, v, 0x0c010c00u));
+}
+
 typedef uint16_t u16_any_align __attribute__((aligned(1)));
 typedef uint32_t u32_any_align __attribute__((aligned(1)));
 __device__ __forceinline__ uint32_t load_pair(gptr<const uint8_t> p) {
@@ -814,7 +826,7 @@ __global__ __launch_bounds__(256, 5) void k_mark(KArgs a) {
       constexpr int NC = TWW + 1;  // columns per lane: nx <= TW + 7
       const double rw = 1.0 / (double)(2 * W), rh = 1.0 / (double)(2 * H);
       uint32_t cx[NC];
-      int cwx[NC];
+      u16x2 cwx[NC];  // (256 - wx, wx)
 #pragma unroll
       for (int c = 0; c < NC; ++c) {
         const uint32_t txx = resample_tap_r(ox + min(lane + 64 * c, nx - 1), bw, W, rw);
@@ -824,7 +836,7 @@ __global__ __launch_bounds__(256, 5) void k_mark(KArgs a) {
           wx = 256;
         }
         cx[c] = (uint32_t)x0;
-        cwx[c] = wx;
+        cwx[c] = pair16((uint32_t)(256 - wx), (uint32_t)wx);
       }
       const uint32_t ty_a = resample_tap_r(oy + min(lane, ny - 1), P.base_h, H, rh);
       const uint32_t ty_b = ny > 64 ? resample_tap_r(oy + min(lane + 64, ny - 1), P.base_h, H, rh)
@@ -835,14 +847,14 @@ __global__ __launch_bounds__(256, 5) void k_mark(KArgs a) {
       constexpr int RPI = TWW == 1 ? 6 : (TWW == 2 ? 5 : (TWW == 3 ? 3 : 2));
       for (int j0 = RPI * wave; j0 < ny; j0 += RPI * nwave) {
         uint32_t v[RPI][NC][2];
-        int wyr[RPI];
+        u16x2 wyr[RPI];  // (256 - wy, wy)
 #pragma unroll
         for (int h = 0; h < RPI; ++h) {
           const int j = min(j0 + h, ny - 1);
           const uint32_t tyy =
               (uint32_t)__builtin_amdgcn_readlane((int)(j < 64 ? ty_a : ty_b), j & 63);
           const int y0 = (int)(tyy >> 9);
-          wyr[h] = (int)(tyy & 511);
+          wyr[h] = pair16(256u - (tyy & 511u), tyy & 511u);
           gptr<const uint8_t> r0 = base + (size_t)y0 * bs;
           gptr<const uint8_t> r1 = base + (size_t)min(y0 + 1, bh1) * bs;
 #pragma unroll
@@ -855,17 +867,17 @@ __global__ __launch_bounds__(256, 5) void k_mark(KArgs a) {
         for (int h = 0; h < RPI; ++h) {
           const int j = j0 + h;
           if (j >= ny) break;
-          const int wy = wyr[h];
           const bool own = j >= ly0 && j < ly1;
 #pragma unroll
           for (int c = 0; c < NC; ++c) {
             const int i = lane + 64 * c;
             if (i < nx) {
-              const int wx = cwx[c];
-              const uint32_t t = v[h][c][0], b = v[h][c][1];
-              const int top = (256 - wx) * (int)(t & 255u) + wx * (int)(t >> 8);
-              const int bot = (256 - wx) * (int)(b & 255u) + wx * (int)(b >> 8);
-              const uint8_t px = (uint8_t)(((256 - wy) * top + wy * bot + 32768) >> 16);
+              // R4 with 16-bit dot products: top and bottom blends are at most 256 * 255,
+              // so they pack into one word for the vertical blend; all exact
+              const uint32_t top = __builtin_amdgcn_udot2(bytes16(v[h][c][0]), cwx[c], 0u, false);
+              const uint32_t bot = __builtin_amdgcn_udot2(bytes16(v[h][c][1]), cwx[c], 0u, false);
+              const uint8_t px = (uint8_t)(
+                  __builtin_amdgcn_udot2(pair16(top, bot), wyr[h], 32768u, false) >> 16);
               pix[j * PITCH + i] = px;
               if (own && i >= lx0 && i < lx1) lw[(size_t)j * P.lvl_stride + i] = px;
             }
@@ -897,20 +909,77 @@ __global__ __launch_bounds__(256, 5) void k_mark(KArgs a) {
         lxk[k] = x - ox;
         vk[k] = x >= B && x < W - B;
       }
-      for (int y = ya + wave; y < yb; y += nwave) {
-        const int ly = y - oy;
-        const uint8_t* rowp = pix + (ly - 3) * PITCH;  // compass north row
+      if constexpr (TWW % 2 == 0) {
+        // Two horizontally adjacent pixels per lane (columns x, x + 1 with x even) in
+        // 16-bit lanes: row words are read aligned and the compass pairs picked with
+        // byte permutes; bright holds iff sat(p + t - min(max(n,s), max(e,w))) == 0 and
+        // dark iff sat(max(min(n,s), min(e,w)) + t - p) == 0, both pixels at once.
+        constexpr int NP = TWW / 2;
+        int lxp[NP];
+        bool v0[NP], v1[NP];
 #pragma unroll
-        for (int k = 0; k < TWW; ++k) {
-          const uint8_t* c = rowp + lxk[k];
-          const int vn = c[0], vw = c[3 * PITCH - 3], p = c[3 * PITCH], ve = c[3 * PITCH + 3];
-          const int vs = c[6 * PITCH];
-          const bool pass = vk[k] && (min(max(vn, vs), max(ve, vw)) >= p + tlo ||
-                                      max(min(vn, vs), min(ve, vw)) <= p - tlo);
-          const uint64_t m = __ballot(pass);
-          if (m) {
-            if (pass) myq[qn + lanes_below(m)] = (uint16_t)(lxk[k] | (ly << 9));
-            qn += __popcll(m);
+        for (int q = 0; q < NP; ++q) {
+          const int x = x_t0 + 128 * q + 2 * lane;
+          lxp[q] = x - ox;  // even; ox is a multiple of 4
+          v0[q] = x >= B && x < W - B;
+          v1[q] = x + 1 >= B && x + 1 < W - B;
+        }
+        const u16x2 t2 = pair16((uint32_t)tlo, (uint32_t)tlo);
+        for (int y = ya + wave; y < yb; y += nwave) {
+          const int ly = y - oy;
+          const uint8_t* r0 = pix + ly * PITCH;
+#pragma unroll
+          for (int q = 0; q < NP; ++q) {
+            const int lx = lxp[q];
+            const uint32_t* wr = (const uint32_t*)(r0 + (lx & ~3));
+            const uint32_t wm = wr[-1], w0 = wr[0], w1 = wr[1];  // bytes lx-4.. lx+7 (aligned)
+            const uint32_t vn = *(const uint16_t*)(r0 - 3 * PITCH + lx);
+            const uint32_t vs = *(const uint16_t*)(r0 + 3 * PITCH + lx);
+            const bool odd = (lx & 2) != 0;  // lx % 4 == 2
+            const u16x2 pp = __builtin_bit_cast(
+                u16x2, __builtin_amdgcn_perm(0u, w0, odd ? 0x0c030c02u : 0x0c010c00u));
+            const u16x2 pw = __builtin_bit_cast(
+                u16x2, __builtin_amdgcn_perm(w0, wm, odd ? 0x0c040c03u : 0x0c020c01u));
+            const u16x2 pe = __builtin_bit_cast(
+                u16x2, __builtin_amdgcn_perm(w1, w0, odd ? 0x0c060c05u : 0x0c040c03u));
+            const u16x2 pn = bytes16(vn), ps = bytes16(vs);
+            const u16x2 hb = __builtin_elementwise_min(__builtin_elementwise_max(pn, ps),
+                                                       __builtin_elementwise_max(pe, pw));
+            const u16x2 hd = __builtin_elementwise_max(__builtin_elementwise_min(pn, ps),
+                                                       __builtin_elementwise_min(pe, pw));
+            const u16x2 zb = __builtin_elementwise_sub_sat(pp + t2, hb);
+            const u16x2 zd = __builtin_elementwise_sub_sat(hd + t2, pp);
+            const uint32_t z = __builtin_bit_cast(uint32_t, __builtin_elementwise_min(zb, zd));
+            const bool pass0 = v0[q] && (z & 0xffffu) == 0u;
+            const bool pass1 = v1[q] && z < 0x10000u;
+            const uint64_t m0 = __ballot(pass0);
+            if (m0) {
+              if (pass0) myq[qn + lanes_below(m0)] = (uint16_t)(lx | (ly << 9));
+              qn += __popcll(m0);
+            }
+            const uint64_t m1 = __ballot(pass1);
+            if (m1) {
+              if (pass1) myq[qn + lanes_below(m1)] = (uint16_t)((lx + 1) | (ly << 9));
+              qn += __popcll(m1);
+            }
+          }
+        }
+      } else {
+        for (int y = ya + wave; y < yb; y += nwave) {
+          const int ly = y - oy;
+          const uint8_t* rowp = pix + (ly - 3) * PITCH;  // compass north row
+#pragma unroll
+          for (int k = 0; k < TWW; ++k) {
+            const uint8_t* c = rowp + lxk[k];
+            const int vn = c[0], vw = c[3 * PITCH - 3], p = c[3 * PITCH], ve = c[3 * PITCH + 3];
+            const int vs = c[6 * PITCH];
+            const bool pass = vk[k] && (min(max(vn, vs), max(ve, vw)) >= p + tlo ||
+                                        max(min(vn, vs), min(ve, vw)) <= p - tlo);
+            const uint64_t m = __ballot(pass);
+            if (m) {
+              if (pass) myq[qn + lanes_below(m)] = (uint16_t)(lxk[k] | (ly << 9));
+              qn += __popcll(m);
+            }
           }
         }
       }
