@@ -1351,7 +1351,7 @@ __global__ __launch_bounds__(256, 4) void k_detect(KArgs a) {
       const int x = (int)(pos & 0xffff), y = (int)(pos >> 16);
       const int64_t R = cand_score(ci, pos);
       bool alive = true;
-#pragma unroll 1
+#pragma unroll  // the 8 neighbour lookups independent: their LDS reads overlap
       for (int nb = 0; nb < 8; ++nb) {
         const int dx = nb < 3 ? nb - 1 : (nb < 5 ? (nb == 3 ? -1 : 1) : nb - 6);
         const int dy = nb < 3 ? -1 : (nb < 5 ? 0 : 1);
