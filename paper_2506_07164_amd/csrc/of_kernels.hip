@@ -234,6 +234,16 @@ __device__ __forceinline__ u16x2 bytes16(uint32_t v) {
   return __builtin_bit_cast(u16x2, __builtin_amdgcn_perm(0u, v, 0x0c010c00u));
 }
 
+// R4's blend from the tap bytes: bytes 0, 1 of t (row y0) and b (row y0 + 1) with
+// weights wx = (256 - wx, wx) and wy = (256 - wy, wy), by 16-bit dot products: the
+// horizontal blends are at most 256 * 255, so they pack into one word for the vertical
+// blend; all exact.
+__device__ __forceinline__ uint32_t blend_q8(uint32_t t, uint32_t b, u16x2 wx, u16x2 wy) {
+  const uint32_t top = __builtin_amdgcn_udot2(bytes16(t), wx, 0u, false);
+  const uint32_t bot = __builtin_amdgcn_udot2(bytes16(b), wx, 0u, false);
+  return __builtin_amdgcn_udot2(pair16(top, bot), wy, 32768u, false) >> 16;
+}
+
 typedef uint16_t u16_any_align __attribute__((aligned(1)));
 typedef uint32_t u32_any_align __attribute__((aligned(1)));
 __device__ __forceinline__ uint32_t load_pair(gptr<const uint8_t> p) {
@@ -815,36 +825,48 @@ __global__ __launch_bounds__(256, 5) void k_mark(KArgs a) {
 
     // 1. level pixels of the tile and its 3-pixel halo
     if (FUSED && P.level > 0) {
-      // Taps in registers: lane owns columns lane + 64c (x0 and weight), and lane j holds
-      // the row tap of tile row j (j + 64 in the second value), read per row with
-      // readlane.  A column tap keeps x0 + 1 inside the source row (at the right border
-      // x0 = w - 2 with weight 256: the same value as x0 = x1 = w - 1), so one 16-bit
-      // load fetches both horizontal neighbours.  Each wave takes RPI consecutive rows
-      // per round trip; the tile's own pixels also go straight to the level buffer.
+      // Taps in registers: lane owns the columns 4 + lane + 64c (c < TWW: the tile's
+      // width from the left halo's end), and lane j holds the row tap of tile row j
+      // (j + 64 in the second value), read per row with readlane.  The 7 other columns
+      // (the left halo and the last 3) are spread over the lanes by (row, column) instead,
+      // so no lane slot holds a column for a few lanes only.  A column tap keeps x0 + 1
+      // inside the source row (at the right border x0 = w - 2 with weight 256: the same
+      // value as x0 = x1 = w - 1), so one 16-bit load fetches both horizontal neighbours.
+      // Each wave takes RPI consecutive rows per round trip; the tile's own pixels also
+      // go straight to the level buffer.
       gptr<const uint8_t> base = G(P.base);
       const int bs = P.base_stride, bw = P.base_w, bh1 = P.base_h - 1;
-      constexpr int NC = TWW + 1;  // columns per lane: nx <= TW + 7
+      constexpr int NC = TWW;  // tile columns per lane
       const double rw = 1.0 / (double)(2 * W), rh = 1.0 / (double)(2 * H);
-      uint32_t cx[NC];
-      u16x2 cwx[NC];  // (256 - wx, wx)
-#pragma unroll
-      for (int c = 0; c < NC; ++c) {
-        const uint32_t txx = resample_tap_r(ox + min(lane + 64 * c, nx - 1), bw, W, rw);
-        int x0 = (int)(txx >> 9), wx = (int)(txx & 511);
-        if (x0 >= bw - 1) {
-          x0 = bw - 2;
+      auto col_tap = [&](int i, uint32_t* x0, u16x2* w) {
+        const uint32_t txx = resample_tap_r(ox + min(i, nx - 1), bw, W, rw);
+        int xx = (int)(txx >> 9), wx = (int)(txx & 511);
+        if (xx >= bw - 1) {
+          xx = bw - 2;
           wx = 256;
         }
-        cx[c] = (uint32_t)x0;
-        cwx[c] = pair16((uint32_t)(256 - wx), (uint32_t)wx);
-      }
+        *x0 = (uint32_t)xx;
+        *w = pair16((uint32_t)(256 - wx), (uint32_t)wx);  // (256 - wx, wx)
+      };
+      uint32_t cx[NC];
+      u16x2 cwx[NC];
+#pragma unroll
+      for (int c = 0; c < NC; ++c) col_tap(4 + lane + 64 * c, &cx[c], &cwx[c]);
+      // 2 * RPI * NC loads in flight, plus 2 for the side columns; the most that fit the
+      // registers without spilling
+      constexpr int RPI = TWW == 1 ? 6 : (TWW == 2 ? 5 : (TWW == 3 ? 3 : 2));
+      static_assert(7 * RPI <= 64, "side columns of a round exceed the wave");
+      const int hrow = lane / 7, hk = lane - 7 * hrow;
+      const int hcol = hk < 4 ? hk : TW + hk;  // side column of this lane
+      uint32_t hx;
+      u16x2 hwx;
+      col_tap(hcol, &hx, &hwx);
+      const bool hlane = lane < 7 * RPI && hcol < nx;
       const uint32_t ty_a = resample_tap_r(oy + min(lane, ny - 1), P.base_h, H, rh);
       const uint32_t ty_b = ny > 64 ? resample_tap_r(oy + min(lane + 64, ny - 1), P.base_h, H, rh)
                                     : 0u;
       gptr<uint8_t> lw = G(P.lvl_w) + (size_t)oy * P.lvl_stride + ox;
       const int lx0 = x_t0 - ox, lx1 = x_t1 - ox, ly0 = y_t0 - oy, ly1 = y_t1 - oy;
-      // 2 * RPI * NC loads in flight; the most that fit the registers without spilling
-      constexpr int RPI = TWW == 1 ? 6 : (TWW == 2 ? 5 : (TWW == 3 ? 3 : 2));
       for (int j0 = RPI * wave; j0 < ny; j0 += RPI * nwave) {
         uint32_t v[RPI][NC][2];
         u16x2 wyr[RPI];  // (256 - wy, wy)
@@ -863,6 +885,16 @@ __global__ __launch_bounds__(256, 5) void k_mark(KArgs a) {
             v[h][c][1] = load_pair(r1 + cx[c]);
           }
         }
+        // side columns: lane takes row j0 + hrow
+        const int hj = min(j0 + hrow, ny - 1);
+        const int hta = __shfl((int)ty_a, hj & 63, 64), htb = __shfl((int)ty_b, hj & 63, 64);
+        const uint32_t hty = (uint32_t)(hj < 64 ? hta : htb);
+        uint32_t hv0 = 0, hv1 = 0;
+        if (hlane) {
+          const int y0 = (int)(hty >> 9);
+          hv0 = load_pair(base + (size_t)y0 * bs + hx);
+          hv1 = load_pair(base + (size_t)min(y0 + 1, bh1) * bs + hx);
+        }
 #pragma unroll
         for (int h = 0; h < RPI; ++h) {
           const int j = j0 + h;
@@ -870,18 +902,21 @@ __global__ __launch_bounds__(256, 5) void k_mark(KArgs a) {
           const bool own = j >= ly0 && j < ly1;
 #pragma unroll
           for (int c = 0; c < NC; ++c) {
-            const int i = lane + 64 * c;
+            const int i = 4 + lane + 64 * c;
             if (i < nx) {
-              // R4 with 16-bit dot products: top and bottom blends are at most 256 * 255,
-              // so they pack into one word for the vertical blend; all exact
-              const uint32_t top = __builtin_amdgcn_udot2(bytes16(v[h][c][0]), cwx[c], 0u, false);
-              const uint32_t bot = __builtin_amdgcn_udot2(bytes16(v[h][c][1]), cwx[c], 0u, false);
-              const uint8_t px = (uint8_t)(
-                  __builtin_amdgcn_udot2(pair16(top, bot), wyr[h], 32768u, false) >> 16);
+              const uint8_t px = (uint8_t)blend_q8(v[h][c][0], v[h][c][1], cwx[c], wyr[h]);
               pix[j * PITCH + i] = px;
               if (own && i >= lx0 && i < lx1) lw[(size_t)j * P.lvl_stride + i] = px;
             }
           }
+        }
+        if (hlane && j0 + hrow < ny) {
+          const int j = j0 + hrow;
+          const u16x2 wy = pair16(256u - (hty & 511u), hty & 511u);
+          const uint8_t px = (uint8_t)blend_q8(hv0, hv1, hwx, wy);
+          pix[j * PITCH + hcol] = px;
+          if (j >= ly0 && j < ly1 && hcol >= lx0 && hcol < lx1)
+            lw[(size_t)j * P.lvl_stride + hcol] = px;
         }
       }
     } else {
