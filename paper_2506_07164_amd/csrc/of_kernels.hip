@@ -1541,6 +1541,7 @@ __global__ __launch_bounds__(256, 4) void k_detect(KArgs a) {
 // out[level prefix + rank].  Levels whose candidate count exceeds kRankCap are left to
 // the radix-select path.
 __global__ __launch_bounds__(256) void k_select_orient(KArgs a) {
+  extern __shared__ __align__(16) uint8_t smem[];  // the level's R' when staged
   __shared__ int32_t s_base[kMaxEntries + 1];
   const Head h = read_head(a, 0);
   const uint64_t wsig = *G(h.ws_sig);  // compared before the plan's pointers are used
@@ -1559,52 +1560,85 @@ __global__ __launch_bounds__(256) void k_select_orient(KArgs a) {
   }
   if (!h.small) load_bases(s_base, a.rank_base, h.n_entries);
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int slot = (int)blockIdx.x * (kBlock >> 6) + wave;
-  int e, i;
-  if (h.small) {
-    if (slot >= h.b[kSmallEntries]) return;
-    int st;
-    small_entry(h.b, slot, &e, &st);
-    e = uniform(e);
-    i = slot - st;
-  } else {
-    if (slot >= s_base[h.n_entries]) return;
-    e = uniform(find_entry(s_base, h.n_entries, slot));
-    i = slot - s_base[e];
+  const int slot0 = (int)blockIdx.x * (kBlock >> 6), slot = slot0 + wave;
+  const int nslots = h.small ? h.b[kSmallEntries] : s_base[h.n_entries];
+  if (slot0 >= nslots) return;  // the whole block
+  auto entry_of = [&](int sl, int* e, int* i) {
+    if (h.small) {
+      int st;
+      small_entry(h.b, sl, e, &st);
+      *i = sl - st;
+    } else {
+      *e = find_entry(s_base, h.n_entries, sl);
+      *i = sl - s_base[*e];
+    }
+    *e = uniform(*e);
+  };
+  int e, i, e0 = 0, i0, eL = -1, iL;
+  entry_of(min(slot, nslots - 1), &e, &i);
+  if (a.sel_lds > 0) {  // the block's first and last slot
+    entry_of(slot0, &e0, &i0);
+    entry_of(min(slot0 + (kBlock >> 6) - 1, nslots - 1), &eL, &iL);
   }
+  const bool live = slot < nslots;
   const LevelPlan P = h.plan[e];
   if (wsig != h.sig) return;
   gptr<const uint32_t> counts = G((const uint32_t*)P.cand_count) - e;  // all entries
   const int C = P.cand_cap;  // slots; empty ones hold the sentinel
-  if (P.level == 0 && i == 0 && lane == 0) {
+  if (live && P.level == 0 && i == 0 && lane == 0) {
     int total = 0;
     for (int l = 0; l < P.n_levels; ++l)
       total += min((int)counts[P.entry0 + l], a.plan[P.entry0 + l].quota);
     *G(P.count_out) = total;
   }
-  if (i >= C || C > kRankCap) return;
   gptr<const Cand> cand = G((const Cand*)P.cand);
-  const Cand me = load_cand(cand + i);
-  if (me.pos == kNoPos) return;
-  // Count better candidates, 8 slots in flight per lane (score and position only, few
-  // registers: every slot's wave of a call stays resident); a wave whose partial count
-  // already reaches the quota cannot be selected and stops.
+  // A block whose slots all belong to one level that fits the LDS stages the level's
+  // R' once (one load per 256 slots per thread, all in flight) and ranks from there.
+  const bool staged = a.sel_lds > 0 && e0 == eL && C <= a.sel_lds;
+  Cand me;
+  me.score = INT64_MIN;
+  me.pos = kNoPos;
+  if (live && i < C && C <= kRankCap) me = load_cand(cand + i);
   int cnt = 0;
-  for (int j0 = 0; j0 < C; j0 += 8 * 64) {
-    int64_t sc[8];
-    uint32_t ps[8];
-#pragma unroll
-    for (int u = 0; u < 8; ++u) {
-      gptr<const Cand> q = cand + min(j0 + u * 64 + lane, C - 1);
-      sc[u] = *(gptr<const int64_t>)q;
-      ps[u] = *((gptr<const uint32_t>)q + 2);
+  if (staged) {
+    int64_t* s_sc = (int64_t*)smem;
+    for (int k = threadIdx.x; k < C; k += kBlock) s_sc[k] = *(gptr<const int64_t>)(cand + k);
+    lds_barrier();
+    if (me.pos == kNoPos) return;
+    bool tie = false;
+#pragma unroll 4
+    for (int j = lane; j < C; j += 64) {
+      const int64_t sj = s_sc[j];
+      cnt += sj > me.score ? 1 : 0;
+      tie = tie || (sj == me.score && j != i);
     }
-#pragma unroll
-    for (int u = 0; u < 8; ++u) {
-      const int j = j0 + u * 64 + lane;
-      cnt += (j < C && better(sc[u], ps[u], me.score, me.pos)) ? 1 : 0;
+    if (__ballot(tie)) {  // equal R' (rare): ordered by position
+      for (int j = lane; j < C; j += 64) {
+        const Cand o = load_cand(cand + j);
+        cnt += (o.score == me.score && o.pos < me.pos) ? 1 : 0;
+      }
     }
-    if (j0 + 8 * 64 < C && wave_sum(cnt) >= P.quota) return;
+  } else {
+    if (me.pos == kNoPos) return;
+    // Count better candidates, 8 slots in flight per lane (score and position only, few
+    // registers: every slot's wave of a call stays resident); a wave whose partial count
+    // already reaches the quota cannot be selected and stops.
+    for (int j0 = 0; j0 < C; j0 += 8 * 64) {
+      int64_t sc[8];
+      uint32_t ps[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        gptr<const Cand> q = cand + min(j0 + u * 64 + lane, C - 1);
+        sc[u] = *(gptr<const int64_t>)q;
+        ps[u] = *((gptr<const uint32_t>)q + 2);
+      }
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int j = j0 + u * 64 + lane;
+        cnt += (j < C && better(sc[u], ps[u], me.score, me.pos)) ? 1 : 0;
+      }
+      if (j0 + 8 * 64 < C && wave_sum(cnt) >= P.quota) return;
+    }
   }
   const int rank = wave_sum(cnt);
   if (rank >= P.quota) return;
@@ -2359,7 +2393,7 @@ hipError_t launch_scale_counters(const KArgs& a, int times, hipStream_t s) {
 }
 
 hipError_t launch_select_orient(const KArgs& a, int slots, hipStream_t s) {
-  OF_LAUNCH(k_select_orient, dim3(cdiv(slots, 4)), dim3(256), 0, s, a);
+  OF_LAUNCH(k_select_orient, dim3(cdiv(slots, 4)), dim3(256), 8 * a.sel_lds, s, a);
   return hipGetLastError();
 }
 

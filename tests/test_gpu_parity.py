@@ -157,6 +157,22 @@ def test_constant_and_square(hip):
     assert set(got["score"].tolist()) == {45_358_400_000_000}
 
 
+def test_equal_scores_across_cells(hip):
+    """Every 30x30 cell holds the same square, so all cell winners tie on R' and the
+    level's top N is decided by (y, x) alone, on the rank path with the level staged in
+    LDS and without it (a level too large to stage)."""
+    tile = np.full((30, 30), 70, np.uint8)
+    tile[9:21, 9:21] = 170
+    for reps, kw in (((9, 12), _kw(n_levels=1, cell=30, fast_t_min=20, n_features=40)),
+                     ((60, 80), _kw(n_levels=1, cell=30, fast_t_min=20, n_features=1500))):
+        img = np.ascontiguousarray(np.tile(tile, reps))
+        log(f"case: equal scores, {img.shape} {kw}")
+        ref = oracle.detect(img, oracle.params(**kw))
+        assert len(set(ref["score"].tolist())) <= 4
+        assert_same_keypoints(run_batch(hip, [img], kw)[0], ref, "batch")
+        assert_same_keypoints(run_plain(hip, img, kw), ref, "plain")
+
+
 @pytest.mark.parametrize("L", [1, 4])
 def test_fig6_pattern_frames(hip, L):
     from test_oracle_pins import _fig6_cases
