@@ -30,6 +30,29 @@ __device__ __forceinline__ gptr<T> G(T* p) {
 
 typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 
+// Read-only memory of a launch (the per-level plans and their signature, written by the
+// prologue): a wave-uniform address in the constant address space is read with scalar
+// loads, one request per wave, instead of a vector load per field that every wave of
+// the launch aims at the same few cache lines.
+template <class T>
+using cptr = const __attribute__((address_space(4))) T*;
+
+__device__ __forceinline__ LevelPlan plan_at(const LevelPlan* plan, int e) {
+  static_assert(sizeof(LevelPlan) % 4 == 0, "plan copied as 32-bit words");
+  LevelPlan P;
+  const cptr<uint32_t> src = (cptr<uint32_t>)plan +
+                             (size_t)__builtin_amdgcn_readfirstlane(e) * (sizeof(LevelPlan) / 4);
+  uint32_t* dst = (uint32_t*)&P;
+#pragma unroll
+  for (int i = 0; i < (int)(sizeof(LevelPlan) / 4); ++i) dst[i] = src[i];
+  return P;
+}
+
+__device__ __forceinline__ int32_t plan_quota(const LevelPlan* plan, int e) {
+  return ((cptr<LevelPlan>)plan)[e].quota;
+}
+
+
 // 16-byte candidate records and 32-byte keypoints move as native vectors (class types
 // cannot be copied across address spaces).
 __device__ __forceinline__ Cand load_cand(gptr<const Cand> p) {
@@ -739,7 +762,7 @@ __global__ __launch_bounds__(256) void k_pyramid_batch(KArgs a) {
   __shared__ uint32_t xt[64], yt[16];
   __shared__ int32_t s_base[kMaxEntries + 1];
   const Head h = read_head(a, 0);
-  const uint64_t wsig = *G(h.ws_sig);  // compared before the plan's pointers are used
+  const uint64_t wsig = *(cptr<uint64_t>)h.ws_sig;  // compared before the plan's pointers are used
   const int g = (int)blockIdx.x;
   int e, b;
   if (h.small) {
@@ -751,7 +774,7 @@ __global__ __launch_bounds__(256) void k_pyramid_batch(KArgs a) {
     e = uniform(find_entry(s_base, h.n_entries, g));
     b = g - s_base[e];
   }
-  const LevelPlan P = h.plan[e];
+  const LevelPlan P = plan_at(h.plan, e);
   if (wsig != h.sig) return;  // not the plan this launch was made for
   const int nbx = (P.W + 63) >> 6;
   const int by = b / nbx, bx = b - by * nbx;
@@ -764,14 +787,15 @@ __global__ __launch_bounds__(256) void k_pyramid_batch(KArgs a) {
 // One block per segment-test tile of 64*TWW x mark_rows level pixels.  TWW fixes the
 // LDS row pitch at compile time, so every circle and compass offset below is a
 // ds_read immediate.
-template <bool FUSED, int TWW>
+template <bool FUSED, int TWW, bool PERSIST>
 __global__ __launch_bounds__(256, 5) void k_mark(KArgs a) {
   constexpr int TW = 64 * TWW;
   constexpr int PITCH = TW + 8;
   extern __shared__ __align__(16) uint8_t smem[];
   __shared__ int s_next, s_qcnt[4];
   const int band = (int)(blockIdx.x % kXcds);  // used in the band order only
-  const Head h = read_head(a, band);
+  Head h = read_head(a, band);
+  h.persistent = PERSIST;  // one tile per block otherwise: straight-line code, no loop state
   const MarkLds M = mark_lds(h.t);
   uint8_t* pix = smem;
   uint16_t* queue = (uint16_t*)(smem + M.off_queue);
@@ -782,7 +806,7 @@ __global__ __launch_bounds__(256, 5) void k_mark(KArgs a) {
   // XCD bands: block b runs on XCD b % kXcds and takes tile b / kXcds of band b % kXcds
   // (the same rows of every level of every frame), so each XCD's L2 holds one band of
   // the frames that its tiles resample from.
-  const uint64_t wsig = *G(h.ws_sig);  // compared before the plan's pointers are used
+  const uint64_t wsig = *(cptr<uint64_t>)h.ws_sig;  // compared before the plan's pointers are used
   if (h.entry < 0 && blockIdx.x == 0) {  // counters of this call (read after this kernel)
     for (int i = threadIdx.x; i < 3 * h.n_entries; i += kBlock) G(h.counters)[i] = 0u;
     if (threadIdx.x == 0) G(h.qctr)[2] = 0u;
@@ -792,7 +816,7 @@ __global__ __launch_bounds__(256, 5) void k_mark(KArgs a) {
                h.n_entries);
   queue_start(h, h.qctr + 0, &s_next);
 
-  for (int iter = 0;; ++iter) {
+  for (int iter = 0; PERSIST || iter == 0; ++iter) {
     const int g0 = uniform(queue_take(h, iter, &s_next));
     if (g0 >= h.total) break;
     const int g = h.bands ? g0 / kXcds : g0;
@@ -812,7 +836,7 @@ __global__ __launch_bounds__(256, 5) void k_mark(KArgs a) {
       e = uniform(find_entry(s_base, h.n_entries, g));
       t = g - s_base[e];
     }
-    const LevelPlan P = h.plan[e];
+    const LevelPlan P = plan_at(h.plan, e);
     if (wsig != h.sig) break;  // not the plan this launch was made for
     const int W = P.W, H = P.H, B = P.B;
     const int tx = t % P.mark_tx;
@@ -1113,12 +1137,14 @@ __device__ __forceinline__ uint32_t candidate_word(uint32_t lo, uint32_t hi, int
 // one cell).  Candidates of the tile and a 1-pixel ring are found word-parallel from
 // the segment-test bitmaps, scored with Harris from LDS, suppressed against their
 // candidate neighbours, and the per-cell best are written to the cells' fixed slots.
+template <bool PERSIST>
 __global__ __launch_bounds__(256, 4) void k_detect(KArgs a) {
   extern __shared__ __align__(16) uint8_t smem[];
   __shared__ int s_next, s_ns, s_ne, s_nin;
   __shared__ uint32_t s_wsum[16];
   const int band = (int)(blockIdx.x % kXcds);  // used in the band order only
-  const Head h = read_head(a, band);
+  Head h = read_head(a, band);
+  h.persistent = PERSIST;  // one tile per block otherwise: straight-line code, no loop state
   const DetLds D = det_lds(h.t, h.cell);
   uint8_t* pix = smem;
   uint32_t* cw = (uint32_t*)(smem + D.off_cw);
@@ -1140,13 +1166,13 @@ __global__ __launch_bounds__(256, 4) void k_detect(KArgs a) {
   int32_t* s_base = (int32_t*)(smem + D.bytes);
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nwave = kBlock >> 6;
   const int bd = (int)kBlock, tid = (int)threadIdx.x;
-  const uint64_t wsig = *G(h.ws_sig);  // compared before the plan's pointers are used
+  const uint64_t wsig = *(cptr<uint64_t>)h.ws_sig;  // compared before the plan's pointers are used
   if (h.entry < 0 && !h.small)
     load_bases(s_base, h.bands ? a.det_band_base + band * (h.n_entries + 1) : a.det_base,
                h.n_entries);
   queue_start(h, h.qctr + 2, &s_next);
 
-  for (int iter = 0;; ++iter) {
+  for (int iter = 0; PERSIST || iter == 0; ++iter) {
     const int g0 = uniform(queue_take(h, iter, &s_next));
     if (g0 >= h.total) break;
     const int g = h.bands ? g0 / kXcds : g0;
@@ -1166,7 +1192,7 @@ __global__ __launch_bounds__(256, 4) void k_detect(KArgs a) {
       e = uniform(find_entry(s_base, h.n_entries, g));
       t = g - s_base[e];
     }
-    const LevelPlan P = h.plan[e];
+    const LevelPlan P = plan_at(h.plan, e);
     if (wsig != h.sig) break;  // not the plan this launch was made for
     const int W = P.W, H = P.H, B = P.B, cs = P.cs;
     const int tx = t % P.det_tx;
@@ -1544,7 +1570,7 @@ __global__ __launch_bounds__(256) void k_select_orient(KArgs a) {
   extern __shared__ __align__(16) uint8_t smem[];  // the level's R' when staged
   __shared__ int32_t s_base[kMaxEntries + 1];
   const Head h = read_head(a, 0);
-  const uint64_t wsig = *G(h.ws_sig);  // compared before the plan's pointers are used
+  const uint64_t wsig = *(cptr<uint64_t>)h.ws_sig;  // compared before the plan's pointers are used
   if (blockIdx.x == 0 && wsig != h.sig) {  // not the plan this launch was made for
     if ((int)threadIdx.x < a.n_frames) G(a.frame_counts)[threadIdx.x] = -1;
     return;
@@ -1581,14 +1607,14 @@ __global__ __launch_bounds__(256) void k_select_orient(KArgs a) {
     entry_of(min(slot0 + (kBlock >> 6) - 1, nslots - 1), &eL, &iL);
   }
   const bool live = slot < nslots;
-  const LevelPlan P = h.plan[e];
+  const LevelPlan P = plan_at(h.plan, e);
   if (wsig != h.sig) return;
   gptr<const uint32_t> counts = G((const uint32_t*)P.cand_count) - e;  // all entries
   const int C = P.cand_cap;  // slots; empty ones hold the sentinel
   if (live && P.level == 0 && i == 0 && lane == 0) {
     int total = 0;
     for (int l = 0; l < P.n_levels; ++l)
-      total += min((int)counts[P.entry0 + l], a.plan[P.entry0 + l].quota);
+      total += min((int)counts[P.entry0 + l], plan_quota(a.plan, P.entry0 + l));
     *G(P.count_out) = total;
   }
   gptr<const Cand> cand = G((const Cand*)P.cand);
@@ -1644,7 +1670,7 @@ __global__ __launch_bounds__(256) void k_select_orient(KArgs a) {
   if (rank >= P.quota) return;
   int prefix = 0;
   for (int l = 0; l < P.level; ++l)
-    prefix += min((int)counts[P.entry0 + l], a.plan[P.entry0 + l].quota);
+    prefix += min((int)counts[P.entry0 + l], plan_quota(a.plan, P.entry0 + l));
   const int x = (int)(me.pos & 0xffff), y = (int)(me.pos >> 16);
   int m10, m01;
   wave_moments(G(P.lvl), P.lvl_stride, x, y, P.B, lane, &m10, &m01);
@@ -1692,8 +1718,8 @@ __global__ __launch_bounds__(1024) void k_select(KArgs a) {
   __shared__ uint64_t s_prefix;
   __shared__ uint32_t s_k, s_n, s_eq;
   const int e = a.entry >= 0 ? a.entry : (int)blockIdx.x;
-  const uint64_t wsig = *G(a.ws_sig);
-  const LevelPlan P = a.plan[e];
+  const uint64_t wsig = *(cptr<uint64_t>)a.ws_sig;
+  const LevelPlan P = plan_at(a.plan, e);
   if (wsig != a.sig) return;  // not the plan this launch was made for
   const int N = P.quota;
   if (a.rank_path && P.cand_cap <= kRankCap) return;  // handled by k_select_orient
@@ -1832,8 +1858,8 @@ __global__ __launch_bounds__(256) void k_orient(KArgs a) {
   const int b = (int)blockIdx.x;
   const int e = a.entry >= 0 ? a.entry : find_entry(a.orient_base, a.n_entries, b);
   const int chunk = a.entry >= 0 ? b : b - a.orient_base[e];
-  const uint64_t wsig = *G(a.ws_sig);
-  const LevelPlan P = a.plan[e];
+  const uint64_t wsig = *(cptr<uint64_t>)a.ws_sig;
+  const LevelPlan P = plan_at(a.plan, e);
   if (wsig != a.sig) return;  // not the plan this launch was made for
   gptr<const uint32_t> counts = G((const uint32_t*)P.cand_count) - e;
   if (a.rank_path && P.cand_cap <= kRankCap) return;  // written by k_select_orient
@@ -1841,11 +1867,11 @@ __global__ __launch_bounds__(256) void k_orient(KArgs a) {
   const int nsel = (int)*G(P.sel_count);
   int prefix = 0;
   for (int l = 0; l < P.level; ++l)
-    prefix += min((int)counts[P.entry0 + l], a.plan[P.entry0 + l].quota);
+    prefix += min((int)counts[P.entry0 + l], plan_quota(a.plan, P.entry0 + l));
   if (!a.rank_path && P.level == 0 && chunk == 0 && threadIdx.x == 0) {
     int total = 0;
     for (int l = 0; l < P.n_levels; ++l)
-      total += min((int)counts[P.entry0 + l], a.plan[P.entry0 + l].quota);
+      total += min((int)counts[P.entry0 + l], plan_quota(a.plan, P.entry0 + l));
     *G(P.count_out) = total;
   }
   gptr<const Cand> sel = G((const Cand*)P.sel);
@@ -1889,12 +1915,12 @@ __global__ __launch_bounds__(256) void k_describe(DescArgs a) {
   const int lane = (int)(threadIdx.x & 63), wave = (int)(threadIdx.x >> 6);
   const int slot = (int)blockIdx.x * 4 + wave;
   const int f = slot / a.cap, i = slot - f * a.cap;
-  if (f >= a.n || i >= G(a.counts)[f] || *G(a.ws_sig) != a.sig) return;
+  if (f >= a.n || i >= G(a.counts)[f] || *(cptr<uint64_t>)a.ws_sig != a.sig) return;
   const u32x4 k0 = *(gptr<const u32x4>)(G(a.kps) + a.off[f] + i);        // x, y, level, m10
   const int x = (int)k0.x, y = (int)k0.y, level = (int)k0.z, m10 = (int)k0.w;
   const int m01 = *(gptr<const int32_t>)((gptr<const uint8_t>)(G(a.kps) + a.off[f] + i) + 16);
   if (level < 0 || level >= a.L) return;
-  const LevelPlan P = a.plan[f * a.L + level];
+  const LevelPlan P = plan_at(a.plan, f * a.L + level);
   if (x < 15 || y < 15 || x >= P.W - 15 || y >= P.H - 15) return;
   // angle bin: max over lanes of (dot, -k), packed into one 64-bit key
   uint64_t key = 0;
@@ -2351,10 +2377,14 @@ hipError_t launch_pyramid_batch(const KArgs& a, int blocks, hipStream_t s) {
 
 template <int TWW>
 void launch_mark_w(const KArgs& a, bool fused, int grid, int bytes, hipStream_t s) {
-  if (fused)
-    OF_LAUNCH((k_mark<true, TWW>), dim3(grid), dim3(256), bytes, s, a);
+  if (fused && a.persistent)
+    OF_LAUNCH((k_mark<true, TWW, true>), dim3(grid), dim3(256), bytes, s, a);
+  else if (fused)
+    OF_LAUNCH((k_mark<true, TWW, false>), dim3(grid), dim3(256), bytes, s, a);
+  else if (a.persistent)
+    OF_LAUNCH((k_mark<false, TWW, true>), dim3(grid), dim3(256), bytes, s, a);
   else
-    OF_LAUNCH((k_mark<false, TWW>), dim3(grid), dim3(256), bytes, s, a);
+    OF_LAUNCH((k_mark<false, TWW, false>), dim3(grid), dim3(256), bytes, s, a);
 }
 
 hipError_t launch_mark(const KArgs& a, bool fused, int grid, hipStream_t s) {
@@ -2370,7 +2400,10 @@ hipError_t launch_mark(const KArgs& a, bool fused, int grid, hipStream_t s) {
 
 hipError_t launch_detect(const KArgs& a, int grid, hipStream_t s) {
   const int bytes = det_lds(a.t, a.cell).bytes + base_table_bytes(a.n_entries);
-  OF_LAUNCH(k_detect, dim3(grid), dim3(256), bytes, s, a);
+  if (a.persistent)
+    OF_LAUNCH(k_detect<true>, dim3(grid), dim3(256), bytes, s, a);
+  else
+    OF_LAUNCH(k_detect<false>, dim3(grid), dim3(256), bytes, s, a);
   return hipGetLastError();
 }
 
