@@ -569,6 +569,9 @@ int of_detect_batch(const of_image* frames, int32_t n, const of_params* params, 
       k.total = kXcds * widest;
       set_small_bases(k, *c, kDetBands);
     }
+    // A grid that the device holds at once (launch bounds: 4 blocks per CU) runs its
+    // tiles last first.
+    k.det_rev = !k.persistent && (int64_t)k.total <= (int64_t)device_cus() * 4;
     // Repeated for profiling only without a persistent grid; its candidate counters are
     // then divided back by the number of issues.
     int issued = 1;
@@ -576,6 +579,7 @@ int of_detect_batch(const of_image* frames, int32_t n, const of_params* params, 
               !k.persistent, &issued);
     if (e == hipSuccess && issued > 1) e = launch_scale_counters(k, issued, stream);
     k.bands = 0;
+    k.det_rev = 0;
   }
   if (e == hipSuccess) e = launch_selection(k, *c, stream);
   delete c;

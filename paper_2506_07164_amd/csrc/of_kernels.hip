@@ -1175,9 +1175,13 @@ __global__ __launch_bounds__(256, 4) void k_detect(KArgs a) {
   for (int iter = 0; PERSIST || iter == 0; ++iter) {
     const int g0 = uniform(queue_take(h, iter, &s_next));
     if (g0 >= h.total) break;
-    const int g = h.bands ? g0 / kXcds : g0;
-    if (h.bands && g >= (h.small ? h.b[kSmallEntries] : s_base[h.n_entries]))
-      break;  // band holds fewer tiles
+    const int gb = h.bands ? g0 / kXcds : g0;
+    const int ng = h.bands ? (h.small ? h.b[kSmallEntries] : s_base[h.n_entries]) : h.total;
+    if (gb >= ng) break;  // band holds fewer tiles
+    // When every block of the grid is resident at once, last tile first: the coarsest
+    // levels, whose tiles hold the most candidates, then start on idle compute units
+    // instead of behind the set-up of three other blocks.
+    const int g = a.det_rev ? ng - 1 - gb : gb;
     if (h.persistent) lds_barrier();  // every thread has read s_next
     const int next = queue_prefetch(h, g0, h.qctr + 2);
     int e, t;
