@@ -184,10 +184,43 @@ __device__ __forceinline__ void small_entry(const int32_t (&b)[kSmallEntries + 1
   *start = st;
 }
 
+// Cross-lane sums by DPP (every lane of the wave active): lane exchanges inside rows of
+// 16 lanes ride on the adds, with no LDS round trip.  quad_perm [1,0,3,2] and
+// [2,3,0,1] give each lane its quad's sum, row_half_mirror pairs the two quads of an
+// 8-lane group, row_mirror the two halves of a row.
+template <int CTRL>
+__device__ __forceinline__ int dpp_add(int v) {
+  return v + __builtin_amdgcn_update_dpp(0, v, CTRL, 0xf, 0xf, false);
+}
+
+// Sum over each aligned group of 8 lanes, in every lane of the group.
+__device__ __forceinline__ int group8_sum(int v) {
+  v = dpp_add<0xB1>(v);   // quad_perm [1,0,3,2]
+  v = dpp_add<0x4E>(v);   // quad_perm [2,3,0,1]
+  return dpp_add<0x141>(v);  // row_half_mirror
+}
+
+// Inclusive prefix sum over the 64 lanes (every lane active): sums of 4 lanes from the
+// original values shifted right 1..3 within the row, then the row prefix doubled by
+// shifts of 4 and 8, then row 15's lane broadcast into rows 1 and 3 and lane 31 into
+// rows 2 and 3.  Lanes a shift moves out of a row add zero.
+__device__ __forceinline__ uint32_t wave_incl_scan(uint32_t v0) {
+  const int x = (int)v0;
+  int t = x + __builtin_amdgcn_update_dpp(0, x, 0x111, 0xf, 0xf, true);  // row_shr:1
+  t += __builtin_amdgcn_update_dpp(0, x, 0x112, 0xf, 0xf, true);         // row_shr:2
+  t += __builtin_amdgcn_update_dpp(0, x, 0x113, 0xf, 0xf, true);         // row_shr:3
+  t += __builtin_amdgcn_update_dpp(0, t, 0x114, 0xf, 0xe, false);        // row_shr:4
+  t += __builtin_amdgcn_update_dpp(0, t, 0x118, 0xf, 0xc, false);        // row_shr:8
+  t += __builtin_amdgcn_update_dpp(0, t, 0x142, 0xa, 0xf, false);        // row_bcast:15
+  t += __builtin_amdgcn_update_dpp(0, t, 0x143, 0xc, 0xf, false);        // row_bcast:31
+  return (uint32_t)t;
+}
+
+// Sum over the 64 lanes, wave-uniform: the four row sums read into scalar registers.
 __device__ __forceinline__ int wave_sum(int v) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-  return v;
+  v = dpp_add<0x140>(group8_sum(v));  // row_mirror
+  return __builtin_amdgcn_readlane(v, 0) + __builtin_amdgcn_readlane(v, 16) +
+         __builtin_amdgcn_readlane(v, 32) + __builtin_amdgcn_readlane(v, 48);
 }
 
 // Segment test at two thresholds from the 16 circle differences d[i] = I_i - I_p.
@@ -393,12 +426,9 @@ __device__ __forceinline__ void harris_groups(const uint8_t* pix, int P, const u
         sxy += gx * gy;
       }
     }
-#pragma unroll
-    for (int o = 1; o < 8; o <<= 1) {
-      sxx += __shfl_xor(sxx, o, 8);
-      syy += __shfl_xor(syy, o, 8);
-      sxy += __shfl_xor(sxy, o, 8);
-    }
+    sxx = group8_sum(sxx);
+    syy = group8_sum(syy);
+    sxy = group8_sum(sxy);
     if (c < n && s == 0) {
       const int64_t A = sxx, B = syy, C = sxy;
       crs[c] = 25 * (A * B - C * C) - (A + B) * (A + B);
@@ -422,12 +452,7 @@ __device__ void block_scan_u32(const uint32_t* cnt, uint32_t* pre, int n, uint32
   for (int base = 0; base < n; base += kBlock) {
     const int i = base + threadIdx.x;
     const uint32_t v = i < n ? cnt[i] : 0u;
-    uint32_t inc = v;
-#pragma unroll
-    for (int o = 1; o < 64; o <<= 1) {
-      const uint32_t t = __shfl_up(inc, o, 64);
-      if (lane >= o) inc += t;
-    }
+    const uint32_t inc = wave_incl_scan(v);
     if (lane == 63) s_wsum[wave] = inc;
     lds_barrier();
     uint32_t woff = 0, total = 0;
@@ -1322,15 +1347,8 @@ __global__ __launch_bounds__(256, 4) void k_detect(KArgs a) {
     int ncand;
     if (nunits <= 2 * bd) {
       // words tid and tid + bd are in registers: one wave scan per half, one barrier
-      uint32_t inc0 = (uint32_t)__popc(cwr[0]), inc1 = (uint32_t)__popc(cwr[1]);
-#pragma unroll
-      for (int o = 1; o < 64; o <<= 1) {
-        const uint32_t t0 = __shfl_up(inc0, o, 64), t1 = __shfl_up(inc1, o, 64);
-        if (lane >= o) {
-          inc0 += t0;
-          inc1 += t1;
-        }
-      }
+      const uint32_t inc0 = wave_incl_scan((uint32_t)__popc(cwr[0]));
+      const uint32_t inc1 = wave_incl_scan((uint32_t)__popc(cwr[1]));
       if (lane == 63) {
         s_wsum[wave] = inc0;
         s_wsum[8 + wave] = inc1;
@@ -2265,12 +2283,9 @@ __global__ __launch_bounds__(256) void k_ab_harris_groups(AbArgs a) {
       }
     }
   }
-#pragma unroll
-  for (int o = 1; o < 8; o <<= 1) {
-    sxx += __shfl_xor(sxx, o, 8);
-    syy += __shfl_xor(syy, o, 8);
-    sxy += __shfl_xor(sxy, o, 8);
-  }
+  sxx = group8_sum(sxx);
+  syy = group8_sum(syy);
+  sxy = group8_sum(sxy);
   if (c < n && s == 0) {
     const int64_t A = sxx, Bv = syy, C = sxy;
     G(out)[c] = ok ? 25 * (A * Bv - C * C) - (A + Bv) * (A + Bv) : 0;
