@@ -881,8 +881,7 @@ __global__ __launch_bounds__(256, 5) void k_mark(KArgs a) {
       // so no lane slot holds a column for a few lanes only.  A column tap keeps x0 + 1
       // inside the source row (at the right border x0 = w - 2 with weight 256: the same
       // value as x0 = x1 = w - 1), so one 16-bit load fetches both horizontal neighbours.
-      // Each wave takes RPI consecutive rows per round trip; the tile's own pixels also
-      // go straight to the level buffer.
+      // Each wave takes RPI consecutive rows per round trip.
       gptr<const uint8_t> base = G(P.base);
       const int bs = P.base_stride, bw = P.base_w, bh1 = P.base_h - 1;
       constexpr int NC = TWW;  // tile columns per lane
@@ -902,8 +901,8 @@ __global__ __launch_bounds__(256, 5) void k_mark(KArgs a) {
 #pragma unroll
       for (int c = 0; c < NC; ++c) col_tap(4 + lane + 64 * c, &cx[c], &cwx[c]);
       // 2 * RPI * NC loads in flight, plus 2 for the side columns; the most that fit the
-      // registers without spilling
-      constexpr int RPI = TWW == 1 ? 6 : (TWW == 2 ? 5 : (TWW == 3 ? 3 : 2));
+      // registers without spilling (a one-tile block keeps fewer values live)
+      constexpr int RPI = TWW == 1 ? 6 : (TWW == 2 ? (PERSIST ? 5 : 7) : (TWW == 3 ? 3 : 2));
       static_assert(7 * RPI <= 64, "side columns of a round exceed the wave");
       const int hrow = lane / 7, hk = lane - 7 * hrow;
       const int hcol = hk < 4 ? hk : TW + hk;  // side column of this lane
@@ -914,8 +913,6 @@ __global__ __launch_bounds__(256, 5) void k_mark(KArgs a) {
       const uint32_t ty_a = resample_tap_r(oy + min(lane, ny - 1), P.base_h, H, rh);
       const uint32_t ty_b = ny > 64 ? resample_tap_r(oy + min(lane + 64, ny - 1), P.base_h, H, rh)
                                     : 0u;
-      gptr<uint8_t> lw = G(P.lvl_w) + (size_t)oy * P.lvl_stride + ox;
-      const int lx0 = x_t0 - ox, lx1 = x_t1 - ox, ly0 = y_t0 - oy, ly1 = y_t1 - oy;
       for (int j0 = RPI * wave; j0 < ny; j0 += RPI * nwave) {
         uint32_t v[RPI][NC][2];
         u16x2 wyr[RPI];  // (256 - wy, wy)
@@ -948,24 +945,16 @@ __global__ __launch_bounds__(256, 5) void k_mark(KArgs a) {
         for (int h = 0; h < RPI; ++h) {
           const int j = j0 + h;
           if (j >= ny) break;
-          const bool own = j >= ly0 && j < ly1;
 #pragma unroll
           for (int c = 0; c < NC; ++c) {
             const int i = 4 + lane + 64 * c;
-            if (i < nx) {
-              const uint8_t px = (uint8_t)blend_q8(v[h][c][0], v[h][c][1], cwx[c], wyr[h]);
-              pix[j * PITCH + i] = px;
-              if (own && i >= lx0 && i < lx1) lw[(size_t)j * P.lvl_stride + i] = px;
-            }
+            if (i < nx) pix[j * PITCH + i] = (uint8_t)blend_q8(v[h][c][0], v[h][c][1], cwx[c], wyr[h]);
           }
         }
         if (hlane && j0 + hrow < ny) {
           const int j = j0 + hrow;
           const u16x2 wy = pair16(256u - (hty & 511u), hty & 511u);
-          const uint8_t px = (uint8_t)blend_q8(hv0, hv1, hwx, wy);
-          pix[j * PITCH + hcol] = px;
-          if (j >= ly0 && j < ly1 && hcol >= lx0 && hcol < lx1)
-            lw[(size_t)j * P.lvl_stride + hcol] = px;
+          pix[j * PITCH + hcol] = (uint8_t)blend_q8(hv0, hv1, hwx, wy);
         }
       }
     } else {
@@ -974,6 +963,25 @@ __global__ __launch_bounds__(256, 5) void k_mark(KArgs a) {
     }
     for (int i = threadIdx.x; i < 2 * M.th * 2 * TWW; i += kBlock) bml[i] = 0u;  // lo, hi
     lds_barrier();
+    if (FUSED && P.level > 0) {
+      // The tile's own pixels to the level buffer, 16 bytes per store (level rows are
+      // 64-byte aligned and tiles start at multiples of 64; a ragged right end goes
+      // byte by byte).  The stores drain while the pre-test runs.
+      const int ow = x_t1 - x_t0, nfull = ow >> 4;
+      gptr<uint8_t> lv = G(P.lvl_w) + (size_t)y_t0 * P.lvl_stride + x_t0;
+      const uint8_t* own = pix + (y_t0 - oy) * PITCH + (x_t0 - ox);  // 4-byte aligned
+      for (int q = threadIdx.x; q < (y_t1 - y_t0) * (TW / 16); q += kBlock) {
+        const int r = q / (TW / 16), k = q - r * (TW / 16);
+        const uint8_t* src = own + r * PITCH + 16 * k;
+        gptr<uint8_t> dst = lv + (size_t)r * P.lvl_stride + 16 * k;
+        if (k < nfull) {
+          const uint32_t* s4 = (const uint32_t*)src;
+          *(gptr<u32x4>)dst = u32x4{s4[0], s4[1], s4[2], s4[3]};
+        } else {
+          for (int b = 0; b < ow - 16 * k; ++b) dst[b] = src[b];
+        }
+      }
+    }
 
     // 2. compass pre-test at fast_t_min: a run of 9 holds two cyclically adjacent
     //    compass points (positions 1/5/9/13), so (n|s) & (e|w) per polarity is
