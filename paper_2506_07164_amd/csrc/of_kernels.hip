@@ -184,6 +184,24 @@ __device__ __forceinline__ void small_entry(const int32_t (&b)[kSmallEntries + 1
   *start = st;
 }
 
+// The same with the entry's end: its successor's first unit, or the launch's total.
+__device__ __forceinline__ void small_entry(const int32_t (&b)[kSmallEntries + 1], int g, int* e,
+                                            int* start, int* end) {
+  int ee = 0, st = 0, en = b[kSmallEntries];
+#pragma unroll
+  for (int i = 1; i < kSmallEntries; ++i) {
+    if (g >= b[i]) {
+      ee = i;
+      st = b[i];
+    } else {
+      en = min(en, b[i]);
+    }
+  }
+  *e = ee;
+  *start = st;
+  *end = en;
+}
+
 // Cross-lane sums by DPP (every lane of the wave active): lane exchanges inside rows of
 // 16 lanes ride on the adds, with no LDS round trip.  quad_perm [1,0,3,2] and
 // [2,3,0,1] give each lane its quad's sum, row_half_mirror pairs the two quads of an
@@ -1606,36 +1624,39 @@ __global__ __launch_bounds__(256) void k_select_orient(KArgs a) {
     return;
   }
   if (h.flags) {  // cell flags and the segment-test queue counter, zero for the next call
-    const int64_t nq = a.flag_bytes / 16;
-    const int64_t per = (nq + gridDim.x - 1) / gridDim.x;
-    const int64_t q0 = (int64_t)blockIdx.x * per, q1 = min(q0 + per, nq);
+    const int nq = (int)(a.flag_bytes / 16);
     const u32x4 zero = {0u, 0u, 0u, 0u};
-    for (int64_t q = q0 + threadIdx.x; q < q1; q += kBlock)
+    for (int q = (int)(blockIdx.x * kBlock + threadIdx.x); q < nq; q += (int)(gridDim.x * kBlock))
       ((gptr<u32x4>)G(h.flags))[q] = zero;
     if (blockIdx.x == 0 && threadIdx.x == 0) G(h.qctr)[0] = 0u;
   }
   if (!h.small) load_bases(s_base, a.rank_base, h.n_entries);
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int lane = threadIdx.x & 63, wave = uniform((int)(threadIdx.x >> 6));
   const int slot0 = (int)blockIdx.x * (kBlock >> 6), slot = slot0 + wave;
   const int nslots = h.small ? h.b[kSmallEntries] : s_base[h.n_entries];
   if (slot0 >= nslots) return;  // the whole block
-  auto entry_of = [&](int sl, int* e, int* i) {
+  // Entry of the block's first slot and where that entry's slots end; a wave's own slot
+  // falls in a later entry only at an entry boundary.
+  auto entry_of = [&](int sl, int* e, int* st, int* en) {
     if (h.small) {
-      int st;
-      small_entry(h.b, sl, e, &st);
-      *i = sl - st;
+      small_entry(h.b, sl, e, st, en);
     } else {
-      *e = find_entry(s_base, h.n_entries, sl);
-      *i = sl - s_base[*e];
+      *e = uniform(find_entry(s_base, h.n_entries, sl));
+      *st = s_base[*e];
+      *en = s_base[*e + 1];
     }
-    *e = uniform(*e);
   };
-  int e, i, e0 = 0, i0, eL = -1, iL;
-  entry_of(min(slot, nslots - 1), &e, &i);
-  if (a.sel_lds > 0) {  // the block's first and last slot
-    entry_of(slot0, &e0, &i0);
-    entry_of(min(slot0 + (kBlock >> 6) - 1, nslots - 1), &eL, &iL);
+  int e0, st0, en0;
+  entry_of(slot0, &e0, &st0, &en0);
+  const int ms = min(slot, nslots - 1);
+  int e = e0, i = ms - st0;
+  if (ms >= en0) {
+    int st, en;
+    entry_of(ms, &e, &st, &en);
+    i = ms - st;
   }
+  // the block's four slots in one entry
+  const bool one = min(slot0 + (kBlock >> 6) - 1, nslots - 1) < en0;
   const bool live = slot < nslots;
   const LevelPlan P = plan_at(h.plan, e);
   if (wsig != h.sig) return;
@@ -1650,7 +1671,7 @@ __global__ __launch_bounds__(256) void k_select_orient(KArgs a) {
   gptr<const Cand> cand = G((const Cand*)P.cand);
   // A block whose slots all belong to one level that fits the LDS stages the level's
   // R' once (one load per 256 slots per thread, all in flight) and ranks from there.
-  const bool staged = a.sel_lds > 0 && e0 == eL && C <= a.sel_lds;
+  const bool staged = a.sel_lds > 0 && one && C <= a.sel_lds;
   Cand me;
   me.score = INT64_MIN;
   me.pos = kNoPos;
