@@ -101,6 +101,13 @@ struct LevelPlan {
 OF_HD int32_t cdiv(int32_t a, int32_t b) { return (a + b - 1) / b; }
 OF_HD int64_t align_up(int64_t v, int64_t a) { return (v + a - 1) / a * a; }
 
+// The same for the LDS layouts that every wave of a tile kernel computes at its start:
+// non-negative 32-bit values, so unsigned arithmetic (a power-of-two divisor is a shift).
+OF_HD int32_t align16(int32_t v) { return (int32_t)(((uint32_t)v + 15u) & ~15u); }
+OF_HD int32_t cdiv_u(int32_t a, int32_t b) {
+  return (int32_t)(((uint32_t)a + (uint32_t)b - 1u) / (uint32_t)b);
+}
+
 // Level size: round-half-up of n / s^l with s = num / den, exact in 64-bit integers.
 OF_HD int32_t level_extent(int32_t n, int l, int32_t num, int32_t den) {
   int64_t a = 1, b = 1;
@@ -328,13 +335,13 @@ OF_HD MarkLds mark_lds(const Tune& t) {
   m.th = t.mark_rows;
   m.pitch = m.tw + 8;
   m.rows = m.th + 6;
-  int32_t o = (int32_t)align_up((int64_t)m.pitch * m.rows, 16);
+  int32_t o = align16(m.pitch * m.rows);
   // four per-wave queue segments; a wave owns at most ceil(rows * words / 4) wave-rows
-  m.qseg = 64 * cdiv(m.th * t.mark_words, 4);
-  m.off_queue = o;  o += (int32_t)align_up(2 * 4 * m.qseg, 16);
+  m.qseg = 64 * cdiv_u(m.th * t.mark_words, 4);
+  m.off_queue = o;  o += align16(2 * 4 * m.qseg);
   m.off_bml = o;    o += 4 * m.th * 2 * t.mark_words;
   m.off_bmh = o;    o += 4 * m.th * 2 * t.mark_words;
-  m.bytes = (int32_t)align_up(o, 16);
+  m.bytes = align16(o);
   return m;
 }
 
@@ -363,29 +370,29 @@ OF_HD DetLds det_lds(const Tune& t, int32_t cell) {
     d.max_cells = 1;
   }
   // odd number of 32-bit words per row: the rows of a Harris window fall in distinct banks
-  d.pitch = (int32_t)align_up(d.mtw + 10 + 3, 4);
+  d.pitch = (int32_t)(((uint32_t)d.mtw + 16u) & ~3u);  // mtw + 10 + 3 rounded up to 4
   if ((d.pitch >> 2) % 2 == 0) d.pitch += 4;
   d.rows = d.mth + 10;
-  d.nbw = cdiv(d.mtw + 2, 32) + 1;
+  d.nbw = cdiv_u(d.mtw + 2, 32) + 1;
   d.nunits = (d.mth + 2) * d.nbw;
-  d.max_surv = cdiv(d.mtw, 2) * cdiv(d.mth, 2);
-  int32_t o = (int32_t)align_up((int64_t)d.pitch * d.rows, 16);
-  d.off_cw = o;     o += (int32_t)align_up(4 * d.nunits, 16);
-  d.off_ucnt = o;   o += (int32_t)align_up(4 * d.nunits, 16);
-  d.off_cpre = o;   o += (int32_t)align_up(4 * (d.nunits + 1), 16);
+  d.max_surv = cdiv_u(d.mtw, 2) * cdiv_u(d.mth, 2);
+  int32_t o = align16(d.pitch * d.rows);
+  d.off_cw = o;     o += align16(4 * d.nunits);
+  d.off_ucnt = o;   o += align16(4 * d.nunits);
+  d.off_cpre = o;   o += align16(4 * (d.nunits + 1));
   d.off_crs = o;    o += 8 * kCandCache;
   d.off_cpos = o;   o += 4 * kCandCache;
-  d.off_sci = o;    o += (int32_t)align_up(2 * d.max_surv, 16);
-  d.off_scell = o;  o += d.max_cells > 1 ? (int32_t)align_up(2 * d.max_surv, 16) : 0;
-  d.off_order = o;  o += (int32_t)align_up(2 * d.max_surv, 16);
-  d.off_ccnt = o;   o += (int32_t)align_up(4 * d.max_cells, 16);
-  d.off_coff = o;   o += (int32_t)align_up(4 * d.max_cells, 16);
-  d.off_cfill = o;  o += (int32_t)align_up(4 * d.max_cells, 16);
-  d.off_ckept = o;  o += (int32_t)align_up(4 * d.max_cells, 16);
-  d.off_cbest = o;  o += (int32_t)align_up(8 * d.max_cells, 16);   // K = 1: best R' per cell
-  d.off_cwin = o;   o += (int32_t)align_up(4 * d.max_cells, 16);   // K = 1: its position
+  d.off_sci = o;    o += align16(2 * d.max_surv);
+  d.off_scell = o;  o += d.max_cells > 1 ? align16(2 * d.max_surv) : 0;
+  d.off_order = o;  o += align16(2 * d.max_surv);
+  d.off_ccnt = o;   o += align16(4 * d.max_cells);
+  d.off_coff = o;   o += align16(4 * d.max_cells);
+  d.off_cfill = o;  o += align16(4 * d.max_cells);
+  d.off_ckept = o;  o += align16(4 * d.max_cells);
+  d.off_cbest = o;  o += align16(8 * d.max_cells);   // K = 1: best R' per cell
+  d.off_cwin = o;   o += align16(4 * d.max_cells);   // K = 1: its position
   const int32_t nfl = cell > 0 ? (t.det_cx + 2) * (t.det_cy + 2) : 4;  // cells of the ring
-  d.off_lfl = o;    o += (int32_t)align_up(nfl, 16);
+  d.off_lfl = o;    o += align16(nfl);
   d.bytes = o;      // + the entry base table of the launch
   return d;
 }
