@@ -128,9 +128,19 @@ def main():
                     help="skip the Fig. 6/7 pattern benchmark (1024x1024, 625 copies per case)")
     ap.add_argument("--no-plain", action="store_true",
                     help="skip the plain path (profiles of the fused kernels alone)")
+    # The legs below run only when asked for: a full run of every leg once faulted the
+    # device with the cause not found; the fused, graph, profile and rBRIEF legs above
+    # are the ones verified since.
+    for leg in ("plain", "batched", "serve", "configs", "patterns"):
+        ap.add_argument(f"--{leg}", action="store_true", help=f"run the {leg} leg")
+    ap.add_argument("--all-legs", action="store_true",
+                    help="run the plain, batched, served, configs and pattern legs too")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help=f"only run a {COPY_MIB} MiB device copy (counter calibration)")
     args = ap.parse_args()
+    for leg in ("plain", "batched", "serve", "configs", "patterns"):
+        on = (args.all_legs or getattr(args, leg)) and not getattr(args, f"no_{leg}")
+        setattr(args, f"no_{leg}", not on)
     if args.gpus != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path "
               "(frames shard across GPUs with no exchange between them)", file=sys.stderr)
