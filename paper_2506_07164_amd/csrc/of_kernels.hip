@@ -413,43 +413,65 @@ __device__ __forceinline__ int64_t harris_lds(const uint8_t* pix, int P, int cx,
   return 25 * (a * b - c * c) - (a + b) * (a + b);
 }
 
+__device__ __forceinline__ void harris_window_row(const uint8_t* pix, int P, uint32_t pos, int sx0,
+                                                  int sy0, int s, int* sxx, int* syy, int* sxy) {
+  const int cx = (int)(pos & 0xffff) - sx0, cy = (int)(pos >> 16) - sy0;
+  const uint8_t* r0 = pix + (cy + s - 4) * P + (cx - 4);
+  int a[9], b[9], d[9];
+#pragma unroll
+  for (int k = 0; k < 9; ++k) {
+    a[k] = r0[k];
+    b[k] = r0[P + k];
+    d[k] = r0[2 * P + k];
+  }
+  int xx = 0, yy = 0, xy = 0;
+#pragma unroll
+  for (int k = 1; k < 8; ++k) {
+    const int gx = (a[k + 1] - a[k - 1]) + 2 * (b[k + 1] - b[k - 1]) + (d[k + 1] - d[k - 1]);
+    const int gy = (d[k - 1] + 2 * d[k] + d[k + 1]) - (a[k - 1] + 2 * a[k] + a[k + 1]);
+    xx += gx * gx;
+    yy += gy * gy;
+    xy += gx * gy;
+  }
+  *sxx = xx;
+  *syy = yy;
+  *sxy = xy;
+}
+
 // Harris R' of candidates by groups of 8 lanes: lane s < 7 of a group forms the Sobel
 // gradients (Eq. 4) at the 7 pixels of window row dy = s - 3 from 3 staged rows and
 // sums gx^2, gy^2, gx*gy; the 7 row sums are added across the group and R' is formed
-// by lane 0.  Every lane of the block runs the same number of rounds.
+// by lane 0.  A group takes two candidates per round (two independent chains of loads
+// and sums in flight; lane 7 and a missing second candidate compute on a valid row and
+// drop the result).  Every lane of the block runs the same number of rounds.
 __device__ __forceinline__ void harris_groups(const uint8_t* pix, int P, const uint32_t* cpos,
                                               int64_t* crs, int n, int sx0, int sy0) {
   const int s = threadIdx.x & 7;
   const int groups = kBlock >> 3;
-  for (int cb = 0; cb < n; cb += groups) {
-    const int c = cb + (threadIdx.x >> 3);
-    int sxx = 0, syy = 0, sxy = 0;
-    if (c < n && s < 7) {
-      const uint32_t pos = cpos[c];
-      const int cx = (int)(pos & 0xffff) - sx0, cy = (int)(pos >> 16) - sy0;
-      const uint8_t* r0 = pix + (cy + s - 4) * P + (cx - 4);
-      int a[9], b[9], d[9];
-#pragma unroll
-      for (int k = 0; k < 9; ++k) {
-        a[k] = r0[k];
-        b[k] = r0[P + k];
-        d[k] = r0[2 * P + k];
-      }
-#pragma unroll
-      for (int k = 1; k < 8; ++k) {
-        const int gx = (a[k + 1] - a[k - 1]) + 2 * (b[k + 1] - b[k - 1]) + (d[k + 1] - d[k - 1]);
-        const int gy = (d[k - 1] + 2 * d[k] + d[k + 1]) - (a[k - 1] + 2 * a[k] + a[k + 1]);
-        sxx += gx * gx;
-        syy += gy * gy;
-        sxy += gx * gy;
-      }
+  const int sr = min(s, 6);  // lane 7 reads window row 6 (dropped below)
+  for (int cb = 0; cb < n; cb += 2 * groups) {
+    const int c0 = cb + (threadIdx.x >> 3), c1 = c0 + groups;
+    int xx0 = 0, yy0 = 0, xy0 = 0, xx1 = 0, yy1 = 0, xy1 = 0;
+    if (c0 < n) {
+      const uint32_t p0 = cpos[c0], p1 = cpos[min(c1, n - 1)];
+      harris_window_row(pix, P, p0, sx0, sy0, sr, &xx0, &yy0, &xy0);
+      harris_window_row(pix, P, p1, sx0, sy0, sr, &xx1, &yy1, &xy1);
+      if (s == 7) xx0 = yy0 = xy0 = 0;
+      if (s == 7 || c1 >= n) xx1 = yy1 = xy1 = 0;
     }
-    sxx = group8_sum(sxx);
-    syy = group8_sum(syy);
-    sxy = group8_sum(sxy);
-    if (c < n && s == 0) {
-      const int64_t A = sxx, B = syy, C = sxy;
-      crs[c] = 25 * (A * B - C * C) - (A + B) * (A + B);
+    xx0 = group8_sum(xx0);
+    yy0 = group8_sum(yy0);
+    xy0 = group8_sum(xy0);
+    xx1 = group8_sum(xx1);
+    yy1 = group8_sum(yy1);
+    xy1 = group8_sum(xy1);
+    if (s == 0 && c0 < n) {
+      const int64_t A = xx0, B = yy0, C = xy0;
+      crs[c0] = 25 * (A * B - C * C) - (A + B) * (A + B);
+    }
+    if (s == 0 && c1 < n) {
+      const int64_t A = xx1, B = yy1, C = xy1;
+      crs[c1] = 25 * (A * B - C * C) - (A + B) * (A + B);
     }
   }
 }
