@@ -554,9 +554,13 @@ int of_detect_batch(const of_image* frames, int32_t n, const of_params* params, 
       k.total = kXcds * widest;
       set_small_bases(k, *c, kMarkBands);
     }
+    // A grid that the device holds at once (launch bounds: 5 blocks per CU) runs its
+    // tiles last first.
+    k.mark_rev = !k.persistent && (int64_t)k.total <= (int64_t)device_cus() * 5;
     e = timed(2, stream, [&] { return launch_mark(k, fused, k.persistent ? t.mark_grid : k.total, stream); },
               !k.persistent);
     k.bands = 0;
+    k.mark_rev = 0;
   }
   if (e == hipSuccess) {
     k.total = c->lay.det_tiles;

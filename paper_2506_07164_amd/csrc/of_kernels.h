@@ -62,7 +62,7 @@ struct KArgs {
   int32_t n_frames;
   int32_t sel_lds;             // level R' the selection stages in LDS (0: none)
   int32_t det_rev;             // 1: Harris/NMS tiles taken last first (grid resident at once)
-  int32_t pad2;
+  int32_t mark_rev;            // 1: segment-test tiles taken last first (grid resident at once)
   // Batches of at most kSmallEntries entries carry the launch's prefix table here, so
   // blocks find their entry without a memory load: entries 0 .. n_entries - 1, INT32_MAX
   // up to index kSmallEntries - 1 and the launch's total at index kSmallEntries.  The

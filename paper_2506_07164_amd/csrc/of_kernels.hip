@@ -884,9 +884,12 @@ __global__ __launch_bounds__(256, 5) void k_mark(KArgs a) {
   for (int iter = 0; PERSIST || iter == 0; ++iter) {
     const int g0 = uniform(queue_take(h, iter, &s_next));
     if (g0 >= h.total) break;
-    const int g = h.bands ? g0 / kXcds : g0;
-    if (h.bands && g >= (h.small ? h.b[kSmallEntries] : s_base[h.n_entries]))
-      break;  // band holds fewer tiles
+    const int gb = h.bands ? g0 / kXcds : g0;
+    const int ng = h.bands ? (h.small ? h.b[kSmallEntries] : s_base[h.n_entries]) : h.total;
+    if (gb >= ng) break;  // band holds fewer tiles
+    // When every block of the grid is resident at once, last tile first: tiles of the
+    // levels above 0 resample and take longer, and then start on idle compute units.
+    const int g = a.mark_rev ? ng - 1 - gb : gb;
     if (h.persistent) lds_barrier();  // every thread has read s_next
     const int next = queue_prefetch(h, g0, h.qctr + 0);
     int e, t;
