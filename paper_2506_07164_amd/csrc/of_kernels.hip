@@ -966,12 +966,13 @@ __global__ __launch_bounds__(256, 5) void k_mark(KArgs a) {
               (uint32_t)__builtin_amdgcn_readlane((int)(j < 64 ? ty_a : ty_b), j & 63);
           const int y0 = (int)(tyy >> 9);
           wyr[h] = pair16(256u - (tyy & 511u), tyy & 511u);
-          gptr<const uint8_t> r0 = base + (size_t)y0 * bs;
-          gptr<const uint8_t> r1 = base + (size_t)min(y0 + 1, bh1) * bs;
+          // 32-bit offsets from the frame's base: one scalar base and one vector offset
+          // per load, no 64-bit address arithmetic per lane
+          const uint32_t o0 = (uint32_t)(y0 * bs), o1 = (uint32_t)(min(y0 + 1, bh1) * bs);
 #pragma unroll
           for (int c = 0; c < NC; ++c) {
-            v[h][c][0] = load_pair(r0 + cx[c]);
-            v[h][c][1] = load_pair(r1 + cx[c]);
+            v[h][c][0] = load_pair(base + (o0 + cx[c]));
+            v[h][c][1] = load_pair(base + (o1 + cx[c]));
           }
         }
         // side columns: lane takes row j0 + hrow
@@ -981,8 +982,8 @@ __global__ __launch_bounds__(256, 5) void k_mark(KArgs a) {
         uint32_t hv0 = 0, hv1 = 0;
         if (hlane) {
           const int y0 = (int)(hty >> 9);
-          hv0 = load_pair(base + (size_t)y0 * bs + hx);
-          hv1 = load_pair(base + (size_t)min(y0 + 1, bh1) * bs + hx);
+          hv0 = load_pair(base + ((uint32_t)(y0 * bs) + hx));
+          hv1 = load_pair(base + ((uint32_t)(min(y0 + 1, bh1) * bs) + hx));
         }
 #pragma unroll
         for (int h = 0; h < RPI; ++h) {
