@@ -49,7 +49,9 @@ typedef struct ihipStream_t* hipStream_t;
 #define OF_MAX_BATCH 64  /* frames per of_detect_batch call */
 
 /* 8-bit grey frame, row-major, `stride` bytes between rows (stride >= width).
- * 1 <= width, height <= 16384. */
+ * 1 <= width, height <= 16384, and the frame spans at most 2^31 - 1 bytes:
+ * stride * (height - 1) + width <= 2147483647 (else OF_EINVAL from every call that
+ * reads frame pixels). */
 typedef struct {
   const uint8_t* data;
   int32_t width, height, stride;

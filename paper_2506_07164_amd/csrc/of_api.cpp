@@ -124,7 +124,11 @@ int check_frame_size(int32_t W, int32_t H, const of_params& p) {
 int check_image(const of_image* im, const of_params& p) {
   if (!im || !im->data) return OF_EINVAL;
   if (im->stride < im->width) return OF_EINVAL;
-  return check_frame_size(im->width, im->height, p);
+  int st = check_frame_size(im->width, im->height, p);
+  if (st) return st;
+  // The fused resample addresses the frame by 32-bit signed offsets from its first byte.
+  if ((int64_t)im->stride * (im->height - 1) + im->width > (int64_t)INT32_MAX) return OF_EINVAL;
+  return OF_OK;
 }
 
 int device_cus() {
@@ -707,6 +711,10 @@ int of_describe(const of_image* frames, int32_t n, const of_params* params,
                 const int32_t* centres, uint8_t* desc, hipStream_t stream) {
   int st = check_frames(frames, n, params);
   if (st) return st;
+  for (int f = 0; f < n; ++f) {
+    st = check_image(&frames[f], *params);
+    if (st) return st;
+  }
   if (!ws || !kps || !kp_offset || !counts || !rot || !centres || !desc) return OF_EINVAL;
   Tune t;
   st = resolve_tune(tuning, *params, &t);

@@ -92,6 +92,16 @@ def test_detect_argument_errors_before_any_launch(lib):
     bad = ofhip.OfImage(0x1000, 64, 64, 63)
     assert lib.of_detect(ctypes.byref(bad), ctypes.byref(p), 0x1000, 1 << 30, 0x1000, 100,
                          0x1000, None) == ofhip.OF_EINVAL
+    # a frame spanning more than 2^31 - 1 bytes (the resample's 32-bit offsets); the
+    # largest stride that still fits is accepted by the host-only size query
+    p1 = ofhip.params(n_levels=1, cell=0, n_features=100, fast_t_min=20)
+    tall = ofhip.OfImage(0x1000, 64, 16384, 131080)
+    assert 131080 * 16383 + 64 > 2**31 - 1 >= 131079 * 16383 + 64
+    assert lib.of_detect(ctypes.byref(tall), ctypes.byref(p1), 0x1000, 1 << 40, 0x1000, 100,
+                         0x1000, None) == ofhip.OF_EINVAL
+    assert lib.of_pyramid_build(ctypes.byref(tall), ctypes.byref(p1), 0x1000, None) \
+        == ofhip.OF_EINVAL
+    assert ofhip.of_workspace_size([ofhip.OfImage(None, 64, 16384, 131079)], p1) > 0
     # tuning outside its ranges
     imgs = (ofhip.OfImage * 1)(img)
     offs = (ctypes.c_int64 * 1)(0)
@@ -179,3 +189,8 @@ def test_describe_validates_before_launch(lib):
     args = list(ok)
     args[3] = ctypes.byref(bad)
     assert lib.of_describe(*args) == ofhip.OF_EINVAL
+    # stride below width; a frame spanning more than 2^31 - 1 bytes
+    for im in (ofhip.OfImage(0x1000, 200, 150, 199), ofhip.OfImage(0x1000, 200, 150, 1 << 30)):
+        args = list(ok)
+        args[0] = (ofhip.OfImage * 1)(im)
+        assert lib.of_describe(*args) == ofhip.OF_EINVAL
