@@ -134,6 +134,24 @@ def test_small_frames_plain_and_batch(hip, W, H, seed, pk):
     assert_same_keypoints(run_batch(hip, [img], kw)[0], ref, "batch")
 
 
+# Widest and tallest frames the calls accept, each shorter or narrower than one tile of
+# either detection kernel, and the most levels: the last level of the 480x480 frame is
+# 31x31, one valid pixel.  With 60 features the levels from 9 up have a quota of 0.
+EXTREME = [(16384, 40, 1, 1000, 0), (40, 16384, 1, 1000, 1), (480, 480, 16, 2000, 2),
+           (480, 480, 16, 60, 3)]
+
+
+@pytest.mark.parametrize("W,H,L,N,seed", EXTREME)
+def test_extreme_sizes(hip, W, H, L, N, seed):
+    kw = _kw(n_levels=L, n_features=N)
+    log(f"case: extreme {W}x{H} {kw}")
+    img = make_frame(FrameSpec(W, H, seed, max(12, max(W, H) // 40), 2.0, 40.0))
+    ref = oracle.detect(img, oracle.params(**kw))
+    assert len(ref) > 0
+    assert_same_keypoints(run_batch(hip, [img], kw)[0], ref, "batch")
+    assert_same_keypoints(run_plain(hip, img, kw), ref, "plain")
+
+
 def test_more_features_than_candidates(hip):
     kw = _kw(n_levels=2, n_features=4000, cell=30)
     log(f"case: quota above candidates {kw}")
