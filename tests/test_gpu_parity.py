@@ -152,6 +152,22 @@ def test_extreme_sizes(hip, W, H, L, N, seed):
     assert_same_keypoints(run_plain(hip, img, kw), ref, "plain")
 
 
+@pytest.mark.parametrize("W", [286, 287])
+def test_rank_cap_and_largest_quota(hip, W):
+    """One whole-level cell over uniform noise with a quota of 4096, the most a level
+    takes, and more survivors than that.  The 286x286 frame has exactly 16384 candidate
+    slots (one per 2x2 block of its 256x256 valid region), the most the rank-count
+    selection takes; 287x286 has one more column of blocks and goes to the radix select
+    with appended candidates."""
+    kw = _kw(n_levels=1, cell=0, fast_t_min=20, n_features=4096)
+    log(f"case: rank cap, {W}x286 noise {kw}")
+    img = np.random.default_rng(W).integers(0, 256, (286, W), dtype=np.uint8)
+    ref = oracle.detect(img, oracle.params(**kw))
+    assert len(ref) == 4096
+    assert_same_keypoints(run_batch(hip, [img], kw)[0], ref, "batch")
+    assert_same_keypoints(run_plain(hip, img, kw), ref, "plain")
+
+
 def test_more_features_than_candidates(hip):
     kw = _kw(n_levels=2, n_features=4000, cell=30)
     log(f"case: quota above candidates {kw}")
