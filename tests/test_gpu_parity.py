@@ -168,6 +168,19 @@ def test_rank_cap_and_largest_quota(hip, W):
     assert_same_keypoints(run_plain(hip, img, kw), ref, "plain")
 
 
+def test_smallest_frame(hip):
+    """31x31, the smallest frame the calls accept: one valid pixel, (15, 15)."""
+    img = np.full((31, 31), 60, np.uint8)
+    img[14:26, 14:26] = 170
+    for cell in (30, 0):
+        kw = _kw(n_levels=1, cell=cell, n_features=4)
+        log(f"case: smallest frame {kw}")
+        ref = oracle.detect(img, oracle.params(**kw))
+        assert len(ref) == 1
+        assert_same_keypoints(run_batch(hip, [img], kw)[0], ref, "batch")
+        assert_same_keypoints(run_plain(hip, img, kw), ref, "plain")
+
+
 def test_more_features_than_candidates(hip):
     kw = _kw(n_levels=2, n_features=4000, cell=30)
     log(f"case: quota above candidates {kw}")

@@ -334,6 +334,25 @@ def test_pipeline_matches_bruteforce(W, H, seed, L, cell, N):
         assert abs(float(g["angle"]) - w[5]) < 1e-12
 
 
+@pytest.mark.parametrize("cell", [30, 0])
+def test_smallest_frame_one_valid_pixel(cell):
+    """A 31x31 frame, the smallest the calls accept, has one pixel outside the 15-pixel
+    border: (15, 15).  A bright square with its corner there gives exactly one keypoint;
+    the frame is symmetric under transposition, so m10 = m01 and the angle is pi/4."""
+    img = np.full((31, 31), 60, np.uint8)
+    img[14:26, 14:26] = 170
+    p = oracle.params(n_levels=1, cell=cell, n_features=4, fast_t=20, fast_t_min=7)
+    got = oracle.detect(img, p)
+    want = bf.detect(img, 1, 20, 7, cell, 4)
+    assert len(got) == len(want) == 1
+    g = got[0]
+    assert (int(g["x"]), int(g["y"]), int(g["m10"]), int(g["m01"])) == want[0][:2] + want[0][3:5]
+    assert (int(g["x"]), int(g["y"])) == (15, 15) and int(g["m10"]) == int(g["m01"]) > 0
+    assert int(g["score"]) == want[0][6] > 0
+    assert abs(float(g["angle"]) - math.pi / 4) < 1e-6
+    assert len(oracle.detect(np.full((31, 31), 60, np.uint8), p)) == 0
+
+
 def test_level_stage_maps_match_bruteforce():
     img = make_frame(FrameSpec(96, 80, 9, 14, 3.0))
     p = oracle.params(n_levels=1, cell=30, n_features=1000, fast_t=20, fast_t_min=7)
