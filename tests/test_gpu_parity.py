@@ -181,6 +181,21 @@ def test_smallest_frame(hip):
         assert_same_keypoints(run_plain(hip, img, kw), ref, "plain")
 
 
+def test_batch_of_extremes(hip):
+    """One batch holding the smallest frame, the widest, the tallest and a 640x480 frame:
+    each frame's keypoints equal the oracle's for that frame alone."""
+    sq = np.full((31, 31), 60, np.uint8)
+    sq[14:26, 14:26] = 170
+    imgs = [sq, make_frame(FrameSpec(16384, 40, 11, 400, 2.0, 40.0)),
+            make_frame(FrameSpec(40, 16384, 12, 400, 2.0, 40.0)),
+            make_frame(FrameSpec(640, 480, 13, 30, 3.0))]
+    kw = _kw(n_levels=1, n_features=1000)
+    log(f"case: batch of extremes {[i.shape for i in imgs]} {kw}")
+    got = run_batch(hip, imgs, kw)
+    for i, img in enumerate(imgs):
+        assert_same_keypoints(got[i], oracle.detect(img, oracle.params(**kw)), f"frame {i}")
+
+
 def test_more_features_than_candidates(hip):
     kw = _kw(n_levels=2, n_features=4000, cell=30)
     log(f"case: quota above candidates {kw}")
