@@ -184,7 +184,9 @@ int of_candidate_counts(const of_image* frames, int32_t n, const of_params* para
  * is smaller than at p + b_i, (a_i, b_i) = rot[k][i].  rot and centres are device copies
  * of of_brief_tables' output; desc (device) holds 32 bytes per keypoint slot, indexed
  * like kps.  Slots beyond counts[f] are not written; if ws does not hold the plan of
- * that detection nothing is written.  OF_EINVAL on bad arguments (nothing launched). */
+ * that detection nothing is written.  The 31 x 31 patch must lie inside the level, so
+ * params->patch_radius (the detection border) must be at least 15.  OF_EINVAL on bad
+ * arguments (nothing launched). */
 int of_brief_tables(const int8_t* pattern, int8_t* rot, int32_t* centres);
 int of_describe(const of_image* frames, int32_t n, const of_params* params,
                 const of_tuning* tuning, const void* ws, const of_keypoint* kps,

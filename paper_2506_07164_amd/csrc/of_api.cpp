@@ -716,6 +716,9 @@ int of_describe(const of_image* frames, int32_t n, const of_params* params,
     if (st) return st;
   }
   if (!ws || !kps || !kp_offset || !counts || !rot || !centres || !desc) return OF_EINVAL;
+  // The descriptor reads the 31 x 31 patch around each keypoint, which stays inside its
+  // level only when the detection border (the patch radius) is at least 15.
+  if (params->patch_radius < 15) return OF_EINVAL;
   Tune t;
   st = resolve_tune(tuning, *params, &t);
   if (st) return st;

@@ -174,9 +174,9 @@ def moments(lvl, x, y, r=15):
     return m10, m01
 
 
-def detect(img, L, t_hi, t_lo, cell, N, B=15):
+def detect(img, L, t_hi, t_lo, cell, N, B=15, num=6, den=5):
     H, W = img.shape
-    sizes = level_sizes(W, H, L)
+    sizes = level_sizes(W, H, L, num, den)
     areas = [w * h for w, h in sizes]
     quota = [0] * L
     for l in range(1, L):

@@ -189,6 +189,11 @@ def test_describe_validates_before_launch(lib):
     args = list(ok)
     args[3] = ctypes.byref(bad)
     assert lib.of_describe(*args) == ofhip.OF_EINVAL
+    # a detection border below the descriptor's 15-pixel patch radius
+    small_r = ofhip.params(n_levels=2, cell=30, n_features=100, patch_radius=14)
+    args = list(ok)
+    args[2] = ctypes.byref(small_r)
+    assert lib.of_describe(*args) == ofhip.OF_EINVAL
     # stride below width; a frame spanning more than 2^31 - 1 bytes
     for im in (ofhip.OfImage(0x1000, 200, 150, 199), ofhip.OfImage(0x1000, 200, 150, 1 << 30)):
         args = list(ok)

@@ -196,6 +196,23 @@ def test_batch_of_extremes(hip):
         assert_same_keypoints(got[i], oracle.detect(img, oracle.params(**kw)), f"frame {i}")
 
 
+# Scales and patch radii other than 6/5 and 15: the radius is also the detection border,
+# and radii above 15 take the moments' multi-pass path.
+SCALES_RADII = [(641, 479, 4, 2, 1, 8), (641, 479, 6, 8, 7, 20), (320, 240, 3, 3, 2, 4),
+                (641, 479, 3, 6, 5, 31), (1920, 1080, 8, 6, 5, 48)]
+
+
+@pytest.mark.parametrize("W,H,L,num,den,r", SCALES_RADII)
+def test_other_scales_and_radii(hip, W, H, L, num, den, r):
+    kw = _kw(n_levels=L, scale_num=num, scale_den=den, patch_radius=r, n_features=1000)
+    log(f"case: scale {num}/{den} radius {r} {W}x{H} {kw}")
+    img = make_frame(FrameSpec(W, H, 20 + r, 40, 3.0))
+    ref = oracle.detect(img, oracle.params(**kw))
+    assert {int(k) for k in ref["level"]} == set(range(L))
+    assert_same_keypoints(run_batch(hip, [img], kw)[0], ref, "batch")
+    assert_same_keypoints(run_plain(hip, img, kw), ref, "plain")
+
+
 def test_more_features_than_candidates(hip):
     kw = _kw(n_levels=2, n_features=4000, cell=30)
     log(f"case: quota above candidates {kw}")

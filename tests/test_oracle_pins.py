@@ -353,6 +353,25 @@ def test_smallest_frame_one_valid_pixel(cell):
     assert len(oracle.detect(np.full((31, 31), 60, np.uint8), p)) == 0
 
 
+@pytest.mark.parametrize("W,H,seed,L,cell,N,num,den,B", [
+    (72, 64, 5, 2, 30, 40, 2, 1, 8), (90, 80, 6, 3, 16, 60, 8, 7, 20),
+    (60, 52, 7, 2, 30, 30, 3, 2, 4)])
+def test_pipeline_other_scales_and_radii(W, H, seed, L, cell, N, num, den, B):
+    """Scales 2, 8/7 and 3/2 with patch radii (and detection borders) 8, 20 and 4 against
+    the brute-force pipeline: level sizes, border, disk and moments all follow them."""
+    img = make_frame(FrameSpec(W, H, seed, 10, 3.0))
+    p = oracle.params(n_levels=L, scale_num=num, scale_den=den, cell=cell, n_features=N,
+                      fast_t=20, fast_t_min=7, patch_radius=B)
+    got = oracle.detect(img, p)
+    want = bf.detect(img, L, 20, 7, cell, N, B, num, den)
+    assert len(got) == len(want) > 0
+    assert {int(g["level"]) for g in got} == set(range(L))
+    for g, w in zip(got, want):
+        assert (int(g["x"]), int(g["y"]), int(g["level"]), int(g["m10"]), int(g["m01"])) == w[:5]
+        assert int(g["score"]) == w[6]
+        assert abs(float(g["angle"]) - w[5]) < 1e-12
+
+
 def test_level_stage_maps_match_bruteforce():
     img = make_frame(FrameSpec(96, 80, 9, 14, 3.0))
     p = oracle.params(n_levels=1, cell=30, n_features=1000, fast_t=20, fast_t_min=7)
