@@ -33,7 +33,7 @@ def _oracle_desc(img, kw, kps, rot, cen):
     return out
 
 
-@pytest.mark.parametrize("which", ["c2", "small", "batch"])
+@pytest.mark.parametrize("which", ["c2", "small", "batch", "scale_radius"])
 def test_describe_equals_oracle(env, which):
     ofhip, rot_d, cen_d, rot, cen = env
     if which == "c2":
@@ -41,6 +41,10 @@ def test_describe_equals_oracle(env, which):
     elif which == "small":
         specs = [FrameSpec(400, 300, 5, 60, 2.0)]
         kw = dict(n_levels=3, fast_t=20, fast_t_min=7, cell=0, n_features=300)
+    elif which == "scale_radius":  # scale 8/7, border 24: patches well inside the levels
+        specs = [FrameSpec(500, 400, 9, 60, 2.0)]
+        kw = dict(n_levels=3, scale_num=8, scale_den=7, patch_radius=24, fast_t=20,
+                  fast_t_min=7, cell=30, n_features=500)
     else:
         specs = [FrameSpec(w, h, 80 + i, 50, 2.5) for i, (w, h) in
                  enumerate([(640, 480), (333, 257), (720, 540)])]
