@@ -336,8 +336,9 @@ OF_HD MarkLds mark_lds(const Tune& t) {
   m.pitch = m.tw + 8;
   m.rows = m.th + 6;
   int32_t o = align16(m.pitch * m.rows);
-  // four per-wave queue segments; a wave owns at most ceil(rows * words / 4) wave-rows
-  m.qseg = 64 * cdiv_u(m.th * t.mark_words, 4);
+  // four per-wave queue segments: wave w tests tile rows w, w + 4, ..., at most
+  // ceil(rows / 4) of them, and each row appends at most 64 * mark_words pixels
+  m.qseg = 64 * t.mark_words * cdiv_u(m.th, 4);
   m.off_queue = o;  o += align16(2 * 4 * m.qseg);
   m.off_bml = o;    o += 4 * m.th * 2 * t.mark_words;
   m.off_bmh = o;    o += 4 * m.th * 2 * t.mark_words;

@@ -44,9 +44,10 @@ class Request:
 @dataclass
 class Result:
     request: Request
-    keypoints: np.ndarray       # KEYPOINT_DTYPE, canonical order
+    keypoints: np.ndarray       # KEYPOINT_DTYPE, canonical order (empty unless status "ok")
     t_done: float
     batch_size: int
+    status: str = "ok"          # "ok", "rejected: ..." (never admissible) or "error: ..."
 
     @property
     def latency(self) -> float:
@@ -84,6 +85,7 @@ class Server:
         self.resident = 0
         self.peak_resident = 0
         self.deferred = 0        # launches held back by the budget
+        self.failed = 0          # frames whose detection call returned an error
         self.batches = 0
         kp = ofhip.KEYPOINT_DTYPE.itemsize
         self.lanes = []
@@ -116,9 +118,27 @@ class Server:
         return sum(len(l.batch) for l in self.lanes if l.busy)
 
     # -- the loop -----------------------------------------------------------------
-    def launch(self, queue: collections.deque) -> bool:
+    def reject_oversized(self, queue: collections.deque, clock, done: list) -> int:
+        """Frames whose batch alone exceeds the HBM budget can never be admitted: each
+        leaves the queue at once with a "rejected" result instead of waiting forever."""
+        keep, k = collections.deque(), 0
+        while queue:
+            r = queue.popleft()
+            shp = tuple(r.host.shape)
+            if self.batch_bytes([shp]) > self.budget:
+                done.append(Result(r, np.empty(0, ofhip.KEYPOINT_DTYPE), clock(), 0,
+                                   "rejected: one frame exceeds the HBM budget"))
+                k += 1
+            else:
+                keep.append(r)
+        queue.extend(keep)
+        return k
+
+    def launch(self, queue: collections.deque, clock=None, done: list | None = None) -> bool:
         """Admits the oldest waiting frames into a batch on a free lane, within the
-        batch size and the HBM budget.  Returns True if a batch was launched."""
+        batch size and the HBM budget.  Returns True if a batch was launched.  If the
+        detection call fails, the batch's frames complete with an "error" result (when
+        ``done`` is given) or are put back at the head of the queue."""
         if not queue:
             return False
         lane = next((l for l in self.lanes if not l.busy), None)
@@ -139,21 +159,31 @@ class Server:
         torch = self.torch
         n = len(batch)
         kp = ofhip.KEYPOINT_DTYPE.itemsize
-        with torch.cuda.stream(lane.stream):
-            frames = [torch.empty(s, dtype=torch.uint8, device="cuda") for s in shapes]
-            for f, r in zip(frames, batch):
-                f.copy_(r.host, non_blocking=True)
-            ws = torch.empty(self._workspace_bytes(shapes), dtype=torch.uint8, device="cuda")
-            out = torch.empty(n * self.N * kp, dtype=torch.uint8, device="cuda")
-            counts = torch.empty(n, dtype=torch.int32, device="cuda")
-            offs = [i * self.N for i in range(n)]
-            ofhip.of_detect_batch([ofhip.image_of(f) for f in frames], self.p, ws.data_ptr(),
-                                  ws.numel(), out.data_ptr(), offs, self.N, counts.data_ptr(),
-                                  self.tune, lane.stream.cuda_stream)
-            lane.out_host[: n * self.N * kp].copy_(out, non_blocking=True)
-            lane.counts_host[:n].copy_(counts, non_blocking=True)
-            ev = torch.cuda.Event()
-            ev.record(lane.stream)
+        try:
+            with torch.cuda.stream(lane.stream):
+                frames = [torch.empty(s, dtype=torch.uint8, device="cuda") for s in shapes]
+                for f, r in zip(frames, batch):
+                    f.copy_(r.host, non_blocking=True)
+                ws = torch.empty(self._workspace_bytes(shapes), dtype=torch.uint8, device="cuda")
+                out = torch.empty(n * self.N * kp, dtype=torch.uint8, device="cuda")
+                counts = torch.empty(n, dtype=torch.int32, device="cuda")
+                offs = [i * self.N for i in range(n)]
+                ofhip.of_detect_batch([ofhip.image_of(f) for f in frames], self.p, ws.data_ptr(),
+                                      ws.numel(), out.data_ptr(), offs, self.N, counts.data_ptr(),
+                                      self.tune, lane.stream.cuda_stream)
+                lane.out_host[: n * self.N * kp].copy_(out, non_blocking=True)
+                lane.counts_host[:n].copy_(counts, non_blocking=True)
+                ev = torch.cuda.Event()
+                ev.record(lane.stream)
+        except ofhip.OfError as err:
+            self.failed += n
+            if done is None:
+                queue.extendleft(reversed(batch))
+            else:
+                t = clock() if clock else 0.0
+                for r in batch:
+                    done.append(Result(r, np.empty(0, ofhip.KEYPOINT_DTYPE), t, n, f"error: {err}"))
+            return False
         lane.busy, lane.batch, lane.event = True, batch, ev
         lane.device, lane.nbytes = [frames, ws, out, counts], nbytes
         self.resident += nbytes
@@ -204,7 +234,8 @@ def run_schedule(server: Server, arrivals, frame_of, rate_scale: float = 1.0):
             queue.append(Request(s, k, t / rate_scale, host, key))
             i += 1
         progressed = server.poll(clock, done) > 0
-        while server.launch(queue):
+        progressed = server.reject_oversized(queue, clock, done) > 0 or progressed
+        while server.launch(queue, clock, done):
             progressed = True
         if not progressed:
             nxt = arrivals[i][0] / rate_scale - clock() if i < len(arrivals) else 0.0

@@ -199,3 +199,14 @@ def test_describe_validates_before_launch(lib):
         args = list(ok)
         args[0] = (ofhip.OfImage * 1)(im)
         assert lib.of_describe(*args) == ofhip.OF_EINVAL
+
+
+def test_library_geometry_matches_hand_derived_fixture(lib):
+    """The library's level sizes and quotas (of_pyramid_desc_get) for the workloads of
+    tests/golden/level_geometry.txt."""
+    from test_oracle_pins import level_geometry_fixture
+    for name, W, H, L, N, cell, widths, heights, quotas, _, _ in level_geometry_fixture():
+        d = ofhip.of_pyramid_desc_get(W, H, ofhip.params(n_levels=L, n_features=N, cell=cell))
+        assert list(d.width[:L]) == widths, name
+        assert list(d.height[:L]) == heights, name
+        assert list(d.quota[:L]) == quotas, name

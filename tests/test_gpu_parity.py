@@ -328,6 +328,29 @@ def test_c2_tunings_agree(hip, tune):
     assert_same_keypoints(run_batch(hip, [img], kw, hip.tuning(**tune))[0], ref, str(tune))
 
 
+def _dense_noise_frame(W=400, H=300, seed=31):
+    """Left half uniform noise over 0..255 (the compass pre-test at t = 7 passes about 9
+    pixels in 10), right half 128 +- 10 (few t = 20 corners: cells fall back to t = 7)."""
+    rng = np.random.default_rng(seed)
+    img = rng.integers(0, 256, (H, W), dtype=np.int32)
+    img[:, W // 2:] = 128 + rng.integers(-10, 11, (H, W - W // 2))
+    return img.astype(np.uint8)
+
+
+@pytest.mark.parametrize("rows", [5, 6, 9, 13])
+@pytest.mark.parametrize("words", [2, 3, 4])
+def test_dense_noise_segment_tiles(hip, words, rows):
+    """Segment-test tiles whose rows are not a multiple of the 4 waves, on a frame where
+    almost every pixel passes the pre-test: each wave's queue fills to its worst case."""
+    kw = _kw(n_levels=3, n_features=600)
+    tune = dict(mark_words=words, mark_rows=rows)
+    log(f"case: dense noise 400x300 {kw} {tune}")
+    img = _dense_noise_frame()
+    ref = oracle.detect(img, oracle.params(**kw))
+    assert len(ref) > 500
+    assert_same_keypoints(run_batch(hip, [img], kw, hip.tuning(**tune))[0], ref, str(tune))
+
+
 @pytest.mark.parametrize("tune", [dict(det_w=8, det_h=8), dict(det_w=64, det_h=32),
                                   dict(det_w=64, det_h=16, pyr_pass=1, det_grid=5),
                                   dict(det_w=64, det_h=32, mark_order=1, det_order=1),

@@ -33,8 +33,8 @@ def test_run9_closed_form_count():
 
 
 def test_run9_matches_binary_encoding_formulation():
-    """Sec. 4.1's encoding: extend the 16 bits with their own low 8 bits to 24 bits,
-    then test the low 9 bits against 0x1FF over 16 right shifts."""
+    """Sec. 5.1's binary encoding (Alg. 2): extend the 16 bits with their own low 8 bits
+    to 24 bits, then test the low 9 bits against 0x1FF over 16 right shifts."""
     for m in range(1 << 16):
         ext = m | ((m & 0xFF) << 16)
         alg = any(((ext >> k) & 0x1FF) == 0x1FF for k in range(16))
@@ -196,6 +196,35 @@ def test_level_sizes_closed_form():
     A = g["width"].astype(np.int64) * g["height"]
     for l in range(1, 8):  # floor of the proportional share
         assert g["quota"][l] <= 2000 * A[l] / A.sum() < g["quota"][l] + 1
+
+
+def level_geometry_fixture():
+    """Rows of tests/golden/level_geometry.txt: (name, W, H, levels, N, cell, widths,
+    heights, quotas, cells, K)."""
+    rows = []
+    with open(os.path.join(GOLDEN, "level_geometry.txt")) as f:
+        for line in f:
+            line = line.split("#")[0].strip()
+            if not line:
+                continue
+            head, *cols = [c.strip() for c in line.split("|")]
+            name, W, H, L, N, cell = head.split()
+            rows.append((name, int(W), int(H), int(L), int(N), int(cell),
+                         *[[int(v) for v in c.split(",")] for c in cols]))
+    return rows
+
+
+@pytest.mark.parametrize("row", level_geometry_fixture(), ids=lambda r: r[0])
+def test_level_quotas_cells_and_keep_counts(row):
+    """Level sizes, area quotas N_l, cell counts and per-cell keep counts K_l of the
+    workloads against the hand-derived fixture."""
+    name, W, H, L, N, cell, widths, heights, quotas, cells, K = row
+    g = oracle.geometry(W, H, oracle.params(n_levels=L, n_features=N, cell=cell))
+    assert g["width"].tolist() == widths
+    assert g["height"].tolist() == heights
+    assert g["quota"].tolist() == quotas
+    assert g["n_cells"].tolist() == cells
+    assert g["k_cell"].tolist() == K
 
 
 def test_resample_identity_and_constant():

@@ -94,3 +94,23 @@ def test_frame_larger_than_budget_waits_not_spins(env):
     q = collections.deque([serve.Request(0, 0, 0.0, pool[(0, 0)][0])])
     assert not server.launch(q)
     assert len(q) == 1 and server.deferred == 1 and server.resident == 0
+
+
+def test_run_schedule_rejects_frames_over_budget(env):
+    """Driven through run_schedule: frames whose batch alone exceeds the budget complete
+    at once with a "rejected" status (the loop ends), the others are detected exactly."""
+    ofhip, serve, pool, refs = env
+    log("case: serve with frames larger than the budget")
+    server = serve.Server(ofhip.params(**KW), hbm_budget=1, max_batch=4, lanes=2)
+    small = server.batch_bytes([(240, 320)])
+    server.budget = small * 13 // 10  # only single 320x240 frames (streams 0 and 4) fit
+    sched = stream_schedule(8, 0.3, 30.0, seed=79)
+    res, _ = serve.run_schedule(server, sched, _frame_of(pool), rate_scale=4.0)
+    assert len(res) == len(sched)
+    for r in res:
+        if r.request.stream % 4 == 0:
+            assert r.status == "ok"
+            assert_same_keypoints(r.keypoints, refs[r.request.key], f"small {r.request.key}")
+        else:
+            assert r.status.startswith("rejected") and len(r.keypoints) == 0
+    assert server.resident == 0 and server.peak_resident <= server.budget
