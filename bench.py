@@ -4,24 +4,39 @@
 One step = the whole hot path (pyramid, segment test, Harris, NMS, cell and level
 selection, orientation) over one synthetic 1920x1080 frame, through the C ABI, with the
 frame already resident in HBM.  `value` is frames/s of the fused path (one launch per
-step over all levels, replayed from a HIP graph); the plain path (one launch per level
-and step, eager) is timed beside it.  Prints one JSON line.
+step over all levels): K steps between two device synchronisations, the faster of eager
+calls and HIP-graph replays.  Beside it, each measured with HIP events on the launching
+stream (median of at least 50 runs after 10 warm-ups):
+
+* the plain path (one launch per level and step) on the same frame;
+* batched calls: 16 copies of the 1080p frame, the 64-frame mixed batch, 16 frames of
+  3840x2160 at 12 levels, and the single 640x480 level with 500 keypoints;
+* the served form (32 camera streams, continuous batching): p50/p99 latency at the
+  offered 960 frames/s and saturated;
+* the Fig. 6/7 pattern frames (1024x1024, 625 copies of one pattern, 1 and 4 levels);
+* rBRIEF of the 2000 keypoints;
+* per-step kernel durations and the roofline of the longest step;
+* the CPU oracle: one thread on the 1080p frame, and frame-parallel over the host's
+  cores on the 64-frame and 16 x 4K batches.
+
+Prints one JSON line.
 """
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
+import statistics
 import sys
 import time
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-import hashlib
-
 # int32 VALU peak: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz (one op per lane per clock).
 ALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
+HBM_PEAK_GBPS = 8000.0
 # Algorithmic integer ops per unit of each step:
 #  resample: 11 per level pixel (four Q8 taps, one rounding);
 #  segment test: 32 per tested pixel (each circle pixel against I_p - t and I_p + t, Eq. 1);
@@ -33,6 +48,15 @@ OPS_HARRIS_NMS = 49 * 18 + 8 + 8 * 3
 OPS_ORIENT = 709 * 4
 STEP_KERNELS = {"pyramid": "k_pyramid_batch", "segment_test": "k_mark",
                 "harris_nms_cells": "k_detect", "select": "k_select_orient"}
+KERNEL_SOURCES = ("paper_2506_07164_amd/csrc/of_kernels.hip", "paper_2506_07164_amd/csrc/of_plan.h")
+COPY_MIB = 256
+PROFILE_REPEAT = 10
+EVENT_RUNS = 50   # timed runs per leg (median reported)
+EVENT_WARMUP = 10
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
 
 
 def level_work(shapes, p):
@@ -50,11 +74,8 @@ def level_work(shapes, p):
     return res, seg
 
 
-KERNEL_SOURCES = ("paper_2506_07164_amd/csrc/of_kernels.hip", "paper_2506_07164_amd/csrc/of_plan.h")
 def traffic_file(kernel):
     return os.path.join(ROOT, "profiles", f"{kernel}_1080p_8level_traffic.txt")
-COPY_MIB = 256
-PROFILE_REPEAT = 10
 
 
 def kernel_source_hash():
@@ -94,6 +115,60 @@ def calibrate_copy():
     print(json.dumps({"copy_bytes": n, "copies": 5}), flush=True)
 
 
+def event_median_ms(run, stream, runs=EVENT_RUNS, warmup=EVENT_WARMUP):
+    """Median milliseconds of `run()` (which queues work on `stream`) over `runs` runs,
+    each bracketed by HIP events recorded on `stream`."""
+    import torch
+    with torch.cuda.stream(stream):
+        for _ in range(warmup):
+            run()
+    torch.cuda.synchronize()
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+           for _ in range(runs)]
+    with torch.cuda.stream(stream):
+        for a, b in evs:
+            a.record(stream)
+            run()
+            b.record(stream)
+    torch.cuda.synchronize()
+    return statistics.median(a.elapsed_time(b) for a, b in evs)
+
+
+def capture(run, stream):
+    """A HIP graph of `run()` captured on `stream` (after one eager call)."""
+    import torch
+    with torch.cuda.stream(stream):
+        run()
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.stream(stream):
+        with torch.cuda.graph(g, stream=stream):
+            run()
+    torch.cuda.synchronize()
+    return g
+
+
+def cpu_worker_count():
+    """Host threads for the frame-parallel oracle: the cores this process may use, at
+    most 16 (a one-GPU machine's share of its host)."""
+    try:
+        n = len(os.sched_getaffinity(0))
+    except AttributeError:
+        n = os.cpu_count() or 1
+    return max(1, min(16, n))
+
+
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def cpu_baseline(img, kw, budget_s=15.0):
     """The oracle as it stands, one thread, on as many copies of the frame as fit."""
     import oracle
@@ -105,14 +180,31 @@ def cpu_baseline(img, kw, budget_s=15.0):
         el = time.perf_counter() - t0
         if el > budget_s or n >= 16:
             break
-    return {"value": n / el, "unit": "frames/s", "cores": 1, "kind": "oracle",
-            "sample": f"{n} frames of the 1920x1080 8-level workload, single-threaded C oracle"}
+    return {"value": round(n / el, 4), "unit": "frames/s", "cores": 1, "kind": "oracle",
+            "sample": f"{n} runs of the 1920x1080 8-level frame, single-threaded C oracle",
+            "cpu": cpu_model()}
+
+
+def cpu_baseline_parallel(name, imgs, kw):
+    """The oracle on every frame of a batch, one frame per thread across the host's
+    cores (the C oracle releases the interpreter lock while it runs)."""
+    import oracle
+    from concurrent.futures import ThreadPoolExecutor
+    p = oracle.params(**kw)
+    workers = cpu_worker_count()
+    t0 = time.perf_counter()
+    with ThreadPoolExecutor(workers) as ex:
+        list(ex.map(lambda im: oracle.detect(im, p), imgs))
+    el = time.perf_counter() - t0
+    return {"value": round(len(imgs) / el, 4), "unit": "frames/s", "cores": workers,
+            "kind": "oracle", "sample": f"the {len(imgs)}-frame {name} batch once, one frame "
+                                        f"per thread on {workers} threads", "cpu": cpu_model()}
 
 
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=2000)
+    ap.add_argument("--steps", type=int, default=500)
     ap.add_argument("--warmup", type=int, default=50)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-tune", action="store_true", help="library default launch shape")
@@ -120,27 +212,17 @@ def main():
                     help="launch shape as JSON (of_tuning fields), instead of the autotuner")
     ap.add_argument("--tune-verbose", action="store_true")
     ap.add_argument("--retune", action="store_true", help="search again, ignoring stored results")
-    ap.add_argument("--no-batched", action="store_true", help="skip the 16-frame batched figure")
-    ap.add_argument("--no-serve", action="store_true", help="skip the served (32-stream) figure")
-    ap.add_argument("--no-configs", action="store_true",
-                    help="skip the 64-frame mixed and 16 x 4K batched figures")
-    ap.add_argument("--no-patterns", action="store_true",
-                    help="skip the Fig. 6/7 pattern benchmark (1024x1024, 625 copies per case)")
-    ap.add_argument("--no-plain", action="store_true",
-                    help="skip the plain path (profiles of the fused kernels alone)")
-    # The legs below run only when asked for: a full run of every leg once faulted the
-    # device with the cause not found; the fused, graph, profile and rBRIEF legs above
-    # are the ones verified since.
-    for leg in ("plain", "batched", "serve", "configs", "patterns"):
-        ap.add_argument(f"--{leg}", action="store_true", help=f"run the {leg} leg")
-    ap.add_argument("--all-legs", action="store_true",
-                    help="run the plain, batched, served, configs and pattern legs too")
+    for leg in ("plain", "batched", "serve", "configs", "patterns", "describe"):
+        ap.add_argument(f"--no-{leg}", action="store_true", help=f"skip the {leg} leg")
+    ap.add_argument("--fused-only", action="store_true",
+                    help="only the fused leg and its profile (for profilers)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help=f"only run a {COPY_MIB} MiB device copy (counter calibration)")
     args = ap.parse_args()
-    for leg in ("plain", "batched", "serve", "configs", "patterns"):
-        on = (args.all_legs or getattr(args, leg)) and not getattr(args, f"no_{leg}")
-        setattr(args, f"no_{leg}", not on)
+    if args.fused_only:
+        for leg in ("plain", "batched", "serve", "configs", "patterns", "describe"):
+            setattr(args, f"no_{leg}", True)
+        args.no_cpu_baseline = True
     if args.gpus != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path "
               "(frames shard across GPUs with no exchange between them)", file=sys.stderr)
@@ -160,11 +242,9 @@ def main():
     img = make_frame(spec)
     p = ofhip.params(**kw)
     frame = torch.from_numpy(img).cuda()
-    print(f"# workload {spec.width}x{spec.height} L={kw['n_levels']} N={kw['n_features']}",
-          file=sys.stderr, flush=True)
+    log(f"# workload {spec.width}x{spec.height} L={kw['n_levels']} N={kw['n_features']}")
 
     fused = ofhip.Detector([img.shape], p, resident=True)
-    plain = ofhip.Detector([img.shape], p)
     stream = torch.cuda.Stream()
 
     # launch shape of the fused path from the autotuner (outside the timed region)
@@ -174,108 +254,105 @@ def main():
     elif not args.no_tune:
         from paper_2506_07164_amd.tune import autotune
         tune_fields = autotune([frame], p, use_cache=not args.retune, verbose=args.tune_verbose)
-        print(f"# tuning {tune_fields}", file=sys.stderr, flush=True)
+        log(f"# tuning {tune_fields}")
     tune = ofhip.tuning(**tune_fields) if tune_fields else None
+
+    def fused_step():
+        fused.detect_batch([frame], tune=tune, stream=stream)
 
     # warm-up (eager), then capture the fused step in a graph on `stream`
     with torch.cuda.stream(stream):
         for _ in range(max(1, args.warmup)):
-            fused.detect_batch([frame], tune=tune, stream=stream)
-            if not args.no_plain:
-                plain.detect_plain(frame, stream=stream)
+            fused_step()
     torch.cuda.synchronize()
-    graph = torch.cuda.CUDAGraph()
-    with torch.cuda.stream(stream):
-        with torch.cuda.graph(graph, stream=stream):
-            fused.detect_batch([frame], tune=tune, stream=stream)
+    graph = capture(fused_step, stream)
     for _ in range(args.warmup):
         graph.replay()
     torch.cuda.synchronize()
 
-    # timed: fused path, graph replays
+    # timed: exactly K steps between two synchronisations, eager calls then graph replays
     K = args.steps
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(K):
-        graph.replay()
-    torch.cuda.synchronize()
-    t_fused = time.perf_counter() - t0
-    print(f"# fused {K} steps {t_fused * 1e3:.1f} ms", file=sys.stderr, flush=True)
-
-    # timed: fused path, eager calls (no graph), same K
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     with torch.cuda.stream(stream):
         for _ in range(K):
-            fused.detect_batch([frame], tune=tune, stream=stream)
+            fused_step()
     torch.cuda.synchronize()
-    t_fused_eager = time.perf_counter() - t0
-    print(f"# fused eager {K} steps {t_fused_eager * 1e3:.1f} ms", file=sys.stderr, flush=True)
+    t_eager = time.perf_counter() - t0
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    with torch.cuda.stream(stream):
+        for _ in range(K):
+            graph.replay()
+    torch.cuda.synchronize()
+    t_graph = time.perf_counter() - t0
+    log(f"# fused {K} steps: eager {t_eager * 1e3:.2f} ms, graph {t_graph * 1e3:.2f} ms")
+    got_f = fused.results()[0]
+    assert len(got_f) == kw["n_features"]
 
-    # timed: plain path, eager launches
-    Kp = max(1, K // 4)
-    t_plain = None
+    with torch.cuda.stream(stream):
+        fused_ev_ms = event_median_ms(fused_step, stream)
+        fused_graph_ev_ms = event_median_ms(graph.replay, stream)
+
+    # plain path: one launch per level and step
+    plain_leg = None
     if not args.no_plain:
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        with torch.cuda.stream(stream):
-            for _ in range(Kp):
-                plain.detect_plain(frame, stream=stream)
-        torch.cuda.synchronize()
-        t_plain = time.perf_counter() - t0
-        print(f"# plain {Kp} steps {t_plain * 1e3:.1f} ms", file=sys.stderr, flush=True)
+        plain = ofhip.Detector([img.shape], p)
+        ms = event_median_ms(lambda: plain.detect_plain(frame, stream=stream), stream)
+        got_p = plain.results()[0]
+        for k in ("x", "y", "level", "score", "m10", "m01"):
+            assert np.array_equal(got_f[k], got_p[k]), k
+        plain_leg = {"ms_median": round(ms, 4), "fps": round(1e3 / ms, 1)}
+        log(f"# plain {plain_leg}")
+        del plain
 
-    # per-step kernel durations: HIP events on the launching stream; repeatable launches
-    # (segment test, selection) are issued PROFILE_REPEAT times back to back between
-    # their events, so the mean is the kernel's duration without the event overhead
-    Kq = max(1, min(K, 500))
+    # per-step kernel durations: HIP events attached to each dispatch on its stream;
+    # repeatable launches are issued PROFILE_REPEAT times back to back between their
+    # events, so the mean is the kernel's duration without the event overhead
+    Kq = 200
     ofhip.of_profile_enable(PROFILE_REPEAT)
     with torch.cuda.stream(stream):
         for _ in range(Kq):
-            fused.detect_batch([frame], tune=tune, stream=stream)
+            fused_step()
     torch.cuda.synchronize()
     prof = ofhip.of_profile_read()
     ofhip.of_profile_enable(False)
     step_us = {k: (ms / n * 1e3 if n else 0.0) for k, (ms, n) in prof.items()}
-    print("# fused step means (us): " + ", ".join(f"{k}={v:.2f}" for k, v in step_us.items()),
-          file=sys.stderr, flush=True)
+    log("# fused step means (us): " + ", ".join(f"{k}={v:.2f}" for k, v in step_us.items()))
+    assert len(fused.results()[0]) == kw["n_features"]
 
-    # correctness of what was timed: same keypoints from both paths
-    got_f = fused.results()[0]
-    assert len(got_f) == kw["n_features"]
-    if not args.no_plain:
-        got_p = plain.results()[0]
-        for k in ("x", "y", "level", "score", "m10", "m01"):
-            assert np.array_equal(got_f[k], got_p[k]), k
-
-    # batched form: 16 copies of the frame (distinct buffers) in one call, graph replays
+    # batched calls, each a graph replay of one of_detect_batch call
     batched = None
-    if not args.no_batched:
-        nb = 16
-        bframes = [frame.clone() for _ in range(nb)]
-        bdet = ofhip.Detector([img.shape] * nb, p)
-        with torch.cuda.stream(stream):
-            for _ in range(3):
-                bdet.detect_batch(bframes, tune=tune, stream=stream)
+    if not args.no_batched or not args.no_configs:
+        batched = {}
+        cases = []
+        if not args.no_batched:
+            cases.append(("b16_1080p", [spec] * 16, kw, True))
+        if not args.no_configs:
+            cases += [("c3_mixed64", CONFIGS["c3"]["frames"], CONFIGS["c3"]["params"], False),
+                      ("c4_4k16", CONFIGS["c4"]["frames"], CONFIGS["c4"]["params"], False),
+                      ("c1_640x480", CONFIGS["c1"]["frames"], CONFIGS["c1"]["params"], False)]
+        for name, specs, ckw, same in cases:
+            cp = ofhip.params(**ckw)
+            frames = ([frame.clone() for _ in specs] if same else
+                      [torch.from_numpy(make_frame(sp)).cuda() for sp in specs])
+            cdet = ofhip.Detector([tuple(f.shape) for f in frames], cp, resident=True)
+            ctune = tune if same else None
+            run = lambda: cdet.detect_batch(frames, tune=ctune, stream=stream)
+            g = capture(run, stream)
+            ms = event_median_ms(g.replay, stream)
+            ms_eager = event_median_ms(run, stream)
+            res = cdet.results()
+            if same:
+                for k in ("x", "y", "level", "score", "m10", "m01"):
+                    assert all(np.array_equal(r[k], got_f[k]) for r in res), k
+            batched[name] = {"frames_per_call": len(frames), "ms_median": round(ms, 4),
+                             "ms_median_eager": round(ms_eager, 4),
+                             "fps": round(len(frames) * 1e3 / ms, 1),
+                             "keypoints": int(sum(len(r) for r in res))}
+            log(f"# {name}: {batched[name]}")
+            del frames, cdet, g
         torch.cuda.synchronize()
-        bgraph = torch.cuda.CUDAGraph()
-        with torch.cuda.stream(stream):
-            with torch.cuda.graph(bgraph, stream=stream):
-                bdet.detect_batch(bframes, tune=tune, stream=stream)
-        for _ in range(5):
-            bgraph.replay()
-        torch.cuda.synchronize()
-        Kb = max(1, K // 16)
-        t0 = time.perf_counter()
-        for _ in range(Kb):
-            bgraph.replay()
-        torch.cuda.synchronize()
-        t_b = time.perf_counter() - t0
-        bres = bdet.results()
-        for k in ("x", "y", "level", "score", "m10", "m01"):
-            assert all(np.array_equal(r[k], got_f[k]) for r in bres), k
-        batched = {"frames_per_call": nb, "calls": Kb, "fps": round(nb * Kb / t_b, 1)}
-        print(f"# batched {nb} frames x {Kb} calls {t_b * 1e3:.1f} ms", file=sys.stderr, flush=True)
 
     # served form: 32 camera streams (720x540..1920x1080, 30 fps Poisson each), continuous
     # batching; latency from arrival to host-visible keypoints
@@ -292,59 +369,27 @@ def main():
         for scale in (1.0, 32.0):
             res, wall = serve.run_schedule(server, stream_schedule(32, 1.0, 30.0), frame_of,
                                            rate_scale=scale)
+            assert all(r.status == "ok" for r in res)
             row = serve.summarize(res, wall, 32 * 30.0 * scale)
             row["scale"] = scale
             served["runs"].append(row)
-        print(f"# served {served['runs']}", file=sys.stderr, flush=True)
+        log(f"# served {served['runs']}")
+        del pool, server
 
-    # algorithmic work of each step launch, the dominant (longest) step's roofline
     # rBRIEF of the 2000 keypoints (one launch; the pattern is a seeded input)
-    from synth import brief_pattern
-    rot, cen = ofhip.of_brief_tables(brief_pattern())
-    rot_d, cen_d = torch.from_numpy(rot).cuda(), torch.from_numpy(cen).cuda()
-    fused.detect_batch([frame], tune=tune, stream=stream)
-    torch.cuda.synchronize()
-    for _ in range(5):
-        fused.describe([frame], rot_d, cen_d, tune=tune)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(200):
-        fused.describe([frame], rot_d, cen_d, tune=tune)
-    torch.cuda.synchronize()
-    describe_us = (time.perf_counter() - t0) / 200 * 1e6
-    print(f"# describe 2000 keypoints: {describe_us:.1f} us per call", file=sys.stderr, flush=True)
-
-    # batched workloads: 64 mixed frames (16 each of 720x540 .. 1920x1080, 8 levels) and
-    # 16 frames of 3840x2160 (12 levels, N = 5000), one call per batch, eager
-    configs = None
-    if not args.no_configs:
-        configs = {}
-        for name in ("c3", "c4"):
-            specs = CONFIGS[name]["frames"]
-            ckw = CONFIGS[name]["params"]
-            cp = ofhip.params(**ckw)
-            frames = [torch.from_numpy(make_frame(sp)).cuda() for sp in specs]
-            cdet = ofhip.Detector([tuple(f.shape) for f in frames], cp)
-            with torch.cuda.stream(stream):
-                for _ in range(3):
-                    cdet.detect_batch(frames, stream=stream)
-            torch.cuda.synchronize()
-            calls = 20
-            t0 = time.perf_counter()
-            with torch.cuda.stream(stream):
-                for _ in range(calls):
-                    cdet.detect_batch(frames, stream=stream)
-            torch.cuda.synchronize()
-            dt = time.perf_counter() - t0
-            configs[name] = {"frames_per_call": len(frames), "calls": calls,
-                             "ms_per_call": round(dt / calls * 1e3, 3),
-                             "fps": round(len(frames) * calls / dt, 1),
-                             "keypoints": int(sum(len(r) for r in cdet.results()))}
-            del frames, cdet
-            print(f"# {name}: {configs[name]}", file=sys.stderr, flush=True)
+    describe_us = None
+    if not args.no_describe:
+        from synth import brief_pattern
+        rot, cen = ofhip.of_brief_tables(brief_pattern())
+        rot_d, cen_d = torch.from_numpy(rot).cuda(), torch.from_numpy(cen).cuda()
+        fused_step()
+        torch.cuda.synchronize()
+        describe_us = 1e3 * event_median_ms(
+            lambda: fused.describe([frame], rot_d, cen_d, tune=tune, stream=stream), stream)
+        log(f"# describe 2000 keypoints: {describe_us:.1f} us per call")
 
     # Fig. 6/7 pattern benchmark: 1024x1024 frames holding 625 copies of one segment-test
-    # pattern, 1 and 4 levels, fused path, one frame per call
+    # pattern, 1 and 4 levels, one frame per call
     patterns = None
     if not args.no_patterns:
         from synth import FIG6_CASES, fig6_pattern_image
@@ -353,22 +398,14 @@ def main():
             pp = ofhip.params(n_levels=levels, fast_t=20, fast_t_min=20, cell=0, n_features=2000)
             for case, pos, _ in FIG6_CASES:
                 pf = torch.from_numpy(fig6_pattern_image(pos)).cuda()
-                pdet = ofhip.Detector([tuple(pf.shape)], pp)
-                with torch.cuda.stream(stream):
-                    for _ in range(10):
-                        pdet.detect_batch([pf], stream=stream)
-                torch.cuda.synchronize()
-                calls = 200
-                t0 = time.perf_counter()
-                with torch.cuda.stream(stream):
-                    for _ in range(calls):
-                        pdet.detect_batch([pf], stream=stream)
-                torch.cuda.synchronize()
-                dt = time.perf_counter() - t0
-                patterns[f"{case}_L{levels}"] = {"us": round(dt / calls * 1e6, 2),
+                pdet = ofhip.Detector([tuple(pf.shape)], pp, resident=True)
+                ms = event_median_ms(lambda: pdet.detect_batch([pf], stream=stream), stream)
+                patterns[f"{case}_L{levels}"] = {"us": round(ms * 1e3, 2),
                                                   "keypoints": len(pdet.results()[0])}
-        print(f"# patterns: {patterns}", file=sys.stderr, flush=True)
+                del pdet
+        log(f"# patterns: {patterns}")
 
+    # roofline of the longest step
     res_px, seg_px = level_work([img.shape], p)
     cands = int(fused.candidates([frame]).sum())
     eff = ofhip.of_tuning_default([ofhip.image_of(frame)], p) if tune is None else tune
@@ -392,8 +429,8 @@ def main():
                 "kernel_src_sha": kernel_source_hash(), "steps": steps,
                 "fast_candidates": cands}
 
-    mode = "graph" if t_fused <= t_fused_eager else "eager"
-    t_best = min(t_fused, t_fused_eager)
+    mode = "graph" if t_graph <= t_eager else "eager"
+    t_best = min(t_graph, t_eager)
     fused_fps = K / t_best
     out = {
         "metric": "frames/sec 1920x1080 8-level Oriented FAST (batched vs plain), HBM GB/s %",
@@ -411,21 +448,29 @@ def main():
         "config": {"workload": "c2: one 1920x1080 frame, 8-level 1.2 pyramid, FAST 20/7 per "
                                "30x30 cell, 2000 keypoints, fused path",
                    "frames_per_step": 1, "launch": mode},
-        "fused_fps": {"graph": round(K / t_fused, 1), "eager": round(K / t_fused_eager, 1)},
-        "plain_fps": round(Kp / t_plain, 1) if t_plain else None,
+        "fused": {"fps_eager": round(K / t_eager, 1), "fps_graph": round(K / t_graph, 1),
+                  "ms_median_eager": round(fused_ev_ms, 4),
+                  "ms_median_graph": round(fused_graph_ev_ms, 4)},
+        "plain": plain_leg,
         "batched": batched,
         "served": served,
-        "describe_us": round(describe_us, 2),
-        "batched_configs": configs,
+        "describe_us": round(describe_us, 2) if describe_us else None,
         "fig7_patterns": patterns,
         "tuning": tune_fields,
         "step_us": {k: round(v, 3) for k, v in step_us.items()},
         "hbm_algorithmic_gbps": round((img.nbytes + 32 * kw["n_features"]) * fused_fps / 1e9, 2),
         "roofline": roofline,
     }
-    out["hbm_algorithmic_frac"] = round(out["hbm_algorithmic_gbps"] / 8000.0, 5)
+    out["hbm_algorithmic_frac"] = round(out["hbm_algorithmic_gbps"] / HBM_PEAK_GBPS, 5)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(img, kw)
+        log(f"# cpu baseline {out['cpu_baseline']}")
+        par = {}
+        for name in ("c3", "c4"):
+            imgs = [make_frame(s) for s in CONFIGS[name]["frames"]]
+            par[name] = cpu_baseline_parallel(name, imgs, CONFIGS[name]["params"])
+            log(f"# cpu baseline {name}: {par[name]}")
+        out["cpu_baseline_batched"] = par
     print(json.dumps(out), flush=True)
 
 

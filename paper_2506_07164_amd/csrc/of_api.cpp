@@ -295,6 +295,8 @@ KArgs kargs(void* ws, const WsLayout& lay, const Tune& t, const of_params& p) {
   k.entry = -1;
   k.cell = p.cell;
   k.t = t;
+  k.ml = mark_lds_launch(t, lay.n_entries);
+  k.dl = det_lds(t, p.cell);
   return k;
 }
 
@@ -345,9 +347,9 @@ hipError_t launch_selection(KArgs k, const CallPlan& c, hipStream_t stream) {
   // Stage each level's R' in LDS when every slot's wave of the call is resident at once
   // (latency then sets the time, and a staged level is ranked without round trips);
   // otherwise waves rank from memory and most stop early, which takes less work.
-  int32_t widest = 0;  // largest level the rank path takes
+  int32_t widest = 0;  // largest level the rank path takes (appended lists: up to the cap)
   for (int i = 0; i < lay.n_entries; ++i)
-    if (c.es[i].cand_cap <= kRankCap) widest = std::max(widest, (int32_t)c.es[i].cand_cap);
+    widest = std::max(widest, (int32_t)std::min<int64_t>(c.es[i].cand_cap, kRankCap));
   k.sel_lds = std::min(widest, kSelLdsCap);
   const int64_t blocks_per_cu = std::min<int64_t>(8, 163840 / (8 * (int64_t)k.sel_lds + 4352));
   if ((int64_t)lay.rank_slots > (int64_t)device_cus() * 4 * blocks_per_cu) k.sel_lds = 0;

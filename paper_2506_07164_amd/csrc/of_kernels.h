@@ -26,6 +26,73 @@ struct PrologueArgs {
   int32_t* counts;
 };
 
+// Plan of entry i = (frame f, level l) of a call, from the frame's geometry, the entry's
+// sizes and its offsets in the workspace regions (exclusive prefixes over the entries
+// before it).  Used by the prologue kernel and by the CPU launch model of the tests.
+struct EntryOffsets {
+  int64_t flag, bm, cand, sel, lvl;
+  int32_t band_rot, det_band_rot;
+  uint32_t* counters;  // the workspace's counter region
+};
+
+OF_HD void fill_level_plan(LevelPlan& P, const PrologueArgs& a, uint8_t* ws, const FrameGeom& g,
+                           const EntrySize& s, int i, int f, int l, const EntryOffsets& o) {
+  const int L = a.p.n_levels;
+  P.W = g.W[l];
+  P.H = g.H[l];
+  P.B = a.p.patch_radius;
+  P.level = l;
+  P.frame = f;
+  P.n_levels = L;
+  P.cs = g.cs[l];
+  P.ncx = g.ncx[l];
+  P.ncy = g.ncy[l];
+  P.quota = g.quota[l];
+  P.kcell = g.kcell[l];
+  P.fast_t = a.p.fast_t;
+  P.fast_t_min = a.p.fast_t_min;
+  P.base = a.f[f].data;
+  P.base_w = a.f[f].w;
+  P.base_h = a.f[f].h;
+  P.base_stride = a.f[f].stride;
+  if (l == 0) {
+    P.lvl = a.f[f].data;
+    P.lvl_w = nullptr;
+    P.lvl_stride = a.f[f].stride;
+  } else {
+    P.lvl_w = ws + a.lay.off_lvl + o.lvl;
+    P.lvl = P.lvl_w;
+    P.lvl_stride = level_stride(P.W);
+  }
+  P.wpr = s.wpr;
+  P.bm_lo = (uint32_t*)(ws + a.lay.off_bm) + o.bm;
+  P.bm_hi = P.bm_lo + (int64_t)s.wpr * P.H;
+  P.flags = ws + a.lay.off_flags + o.flag;
+  P.cand = (Cand*)(ws + a.lay.off_cand) + o.cand;
+  P.cand_count = o.counters + i;
+  P.cand_cap = (int32_t)s.cand_cap;
+  P.kslot = s.kslot;
+  P.compact = a.p.cell == 0 && s.cand_cap > kRankCap;
+  P.slot_w = s.slot_w;
+  P.sel = (Cand*)(ws + a.lay.off_sel) + o.sel;
+  P.sel_count = o.counters + a.lay.n_entries + i;
+  P.ncand_count = o.counters + 2 * a.lay.n_entries + i;
+  P.mark_tx = s.mark_tx;
+  P.mark_ty = s.mark_ty;
+  P.band_rot = o.band_rot;
+  P.det_band_rot = o.det_band_rot;
+  P.det_tx = s.det_tx;
+  P.det_ty = s.det_ty;
+  P.det_x0 = s.det_x0;
+  P.det_y0 = s.det_y0;
+  P.det_xend = s.det_xend;
+  P.det_yend = s.det_yend;
+  P.orient_blocks = s.orient_blocks;
+  P.entry0 = f * L;
+  P.out = a.out + a.f[f].out_off;
+  P.count_out = a.counts + f;
+}
+
 // Arguments of the tile kernels, selection and orientation.
 struct KArgs {
   // Read by every block before its first tile, together (the first cache lines of the
@@ -46,6 +113,8 @@ struct KArgs {
   int32_t rank_path;           // 1: k_select_orient ranks levels with <= kRankCap candidates
   Tune t;
   int32_t pad;
+  MarkLds ml;                  // LDS layouts of the tile kernels for this tuning (host-made)
+  DetLds dl;
   // The state each call leaves zeroed for the next: k_mark clears the counters, the
   // selection clears the cell flags and the segment-test queue counter.
   uint32_t* counters;          // 3 per entry

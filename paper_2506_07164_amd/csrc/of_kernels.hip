@@ -106,15 +106,6 @@ __device__ __forceinline__ bool better(int64_t sa, uint32_t pa, int64_t sb, uint
   return sa > sb || (sa == sb && pa < pb);
 }
 
-// Last index e with base[e] <= g, base non-decreasing with n + 1 entries.
-__device__ __forceinline__ int find_entry(const int32_t* base, int n, int g) {
-  int lo = 0, hi = n - 1;
-  while (lo < hi) {
-    int mid = (lo + hi + 1) >> 1;
-    if (base[mid] <= g) lo = mid; else hi = mid - 1;
-  }
-  return lo;
-}
 
 // Launch-wide values every block needs before its first tile.  They are read together,
 // before any branch depends on them, so their scalar loads share one trip to memory
@@ -284,15 +275,13 @@ __device__ __forceinline__ void circle_diffs(const uint8_t* c, int P, int (&d)[1
   d[15] = c[-3 * P - 1] - p;
 }
 
-// Copy rows [y0, y1) x cols [x0, x1) of an 8-bit image into LDS (row pitch lp, origin
-// (x0, y0)); x0 is a multiple of 4.  Waves take rows (row base in scalar registers),
-// lanes take 32-bit words; each wave keeps four rows of loads in flight.  Whole words
-// where the source row allows, bytes at a ragged right edge.
-__device__ __forceinline__ uint32_t load_word(gptr<const uint8_t> s, bool whole, int n) {
-  if (whole) return *(gptr<const uint32_t>)s;
-  uint32_t v = 0;
-  for (int k = 0; k < n; ++k) v |= (uint32_t)s[k] << (8 * k);
-  return v;
+// Bytes p[0..3] of a row as one little-endian word, zero past the row's last readable
+// byte (room = bytes left in the row, >= 1): one dword load at any alignment, moved back
+// so that it ends at the row's limit when fewer than 4 bytes remain.
+typedef uint32_t u32_any_align_g __attribute__((aligned(1)));
+__device__ __forceinline__ uint32_t load_word(gptr<const uint8_t> p, int room) {
+  const int back = room >= 4 ? 0 : 4 - room;
+  return *(gptr<const u32_any_align_g>)(p - back) >> (8 * back);
 }
 
 // Bytes p[0] (low) and p[1] (high) with one 16-bit load at any alignment.
@@ -324,61 +313,115 @@ __device__ __forceinline__ uint32_t load_pair(gptr<const uint8_t> p) {
   return *(gptr<const u16_any_align>)p;
 }
 
-// Rows [y0, y1) x columns [x0, x1) of a level into LDS (row pitch lp), as 32-bit words.
-// The block's threads take the words in order, U per thread per pass, so a tile of up
-// to U * kBlock words costs one round trip to memory.
+// Rows [y0, y1) x columns [x0, x1) of a level into LDS (row pitch lp), as 32-bit words
+// (x0 a multiple of 4; bytes past the row's readable limit read as zero).  The block's
+// threads take the words in order, U per thread per pass.  stage_issue loads the first
+// pass into registers and stage_store writes it to LDS (then loads and stores any
+// further passes), so that a caller can issue other loads in between and wait for all
+// of them at once: a tile of up to U * kBlock words costs one round trip to memory.
 template <int U>
-__device__ __forceinline__ void stage_rows(uint8_t* lds, int lp, gptr<const uint8_t> src,
-                                           int stride, int row_limit, int x0, int x1, int y0,
-                                           int y1) {
-  const bool aligned = ((((uintptr_t)src) | (uintptr_t)stride) & 3) == 0;
-  const int nw = (x1 - x0 + 3) >> 2;
-  const int total = nw * (y1 - y0);
-  const int bd = kBlock;
-  const int drow = bd / nw, dw = bd - drow * nw;  // advance of (row, word) per bd words
-  int row = (int)threadIdx.x / nw;
-  int w = (int)threadIdx.x - row * nw;
-  for (int base = 0; base < total; base += U * bd) {
-    uint32_t v[U];
-    const int row0 = row, w0 = w;
+struct Stage {
+  uint32_t v[U];
+  int nw, total, drow, dw;  // words per row, in all; walk advance per kBlock words
+  int row, w, i0;           // walk position of this thread's next word; first word of the pass
+};
+
+// Words i = i0 + u * kBlock + threadIdx.x of a pass: (row, word) advanced by (drow, dw)
+// per kBlock words, so only the first needs a division.  Every load is issued without a
+// branch (a word past the region re-reads its first word and is dropped), so the U loads
+// of a pass are all in flight before the first wait; a caller can issue other loads
+// between stage_issue and stage_store and wait for all of them at once.
+template <int U>
+__device__ __forceinline__ void stage_begin(Stage<U>& st, int x0, int x1, int y0, int y1) {
+  st.nw = (x1 - x0 + 3) >> 2;
+  st.total = st.nw * (y1 - y0);
+  st.drow = (int)((uint32_t)kBlock / (uint32_t)st.nw);
+  st.dw = kBlock - st.drow * st.nw;
+  st.row = (int)(threadIdx.x / (uint32_t)st.nw);
+  st.w = (int)threadIdx.x - st.row * st.nw;
+  st.i0 = 0;
+}
+
+template <int U>
+__device__ __forceinline__ void stage_issue(Stage<U>& st, gptr<const uint8_t> src, int stride,
+                                            int row_limit, int x0, int y0) {
+  int row = st.row, w = st.w;
+  const gptr<const uint8_t> first = src + (size_t)y0 * stride + x0;
 #pragma unroll
-    for (int u = 0; u < U; ++u) {
-      const int x = x0 + 4 * w;
-      v[u] = base + u * bd + (int)threadIdx.x < total
-                 ? load_word(src + (size_t)(y0 + row) * stride + x, aligned && x + 4 <= row_limit,
-                             min(4, x1 - x))
-                 : 0u;
-      row += drow;
-      w += dw;
-      if (w >= nw) {
-        w -= nw;
-        ++row;
-      }
-    }
-    row = row0;  // replay the walk for the stores: addresses are not kept in registers
-    w = w0;
-#pragma unroll
-    for (int u = 0; u < U; ++u) {
-      if (base + u * bd + (int)threadIdx.x < total) *(uint32_t*)(lds + row * lp + 4 * w) = v[u];
-      row += drow;
-      w += dw;
-      if (w >= nw) {
-        w -= nw;
-        ++row;
-      }
+  for (int u = 0; u < U; ++u) {
+    const bool in = st.i0 + u * kBlock + (int)threadIdx.x < st.total;
+    const int x = x0 + 4 * w;
+    const int room = in ? row_limit - x : 4;
+    const int back = room >= 4 ? 0 : 4 - room;
+    const gptr<const uint8_t> p = in ? src + (size_t)(y0 + row) * stride + (x - back) : first;
+    st.v[u] = *(gptr<const u32_any_align_g>)p >> (8 * back);
+    row += st.drow;
+    w += st.dw;
+    if (w >= st.nw) {
+      w -= st.nw;
+      ++row;
     }
   }
 }
 
-// Harris R' at LDS pixel (cx, cy): Sobel G_x, G_y (Eq. 4) at the 49 pixels of the 7x7
-// window, summed as Sxx, Syy, Sxy (int32), R' = 25 (Sxx Syy - Sxy^2) - (Sxx + Syy)^2.
-// Separable form: each of the 9 rows gives horizontal differences hd = I[c+1] - I[c-1]
-// and smoothings hs = I[c-1] + 2 I[c] + I[c+1]; two earlier rows stay in registers and
-// G_x = hd[r-1] + 2 hd[r] + hd[r+1], G_y = hs[r+1] - hs[r-1].
-__device__ __forceinline__ void harris_row(const uint8_t* row, int (&hd)[7], int (&hs)[7]) {
+template <int U>
+__device__ __forceinline__ void stage_store(Stage<U>& st, uint8_t* lds, int lp) {
+  int row = st.row, w = st.w;
+#pragma unroll
+  for (int u = 0; u < U; ++u) {
+    if (st.i0 + u * kBlock + (int)threadIdx.x < st.total)
+      *(uint32_t*)(lds + row * lp + 4 * w) = st.v[u];
+    row += st.drow;
+    w += st.dw;
+    if (w >= st.nw) {
+      w -= st.nw;
+      ++row;
+    }
+  }
+  st.row = row;
+  st.w = w;
+  st.i0 += U * kBlock;
+}
+
+// The passes left after the first (regions larger than U * kBlock words).
+template <int U>
+__device__ __forceinline__ void stage_rest(Stage<U>& st, uint8_t* lds, int lp,
+                                           gptr<const uint8_t> src, int stride, int row_limit,
+                                           int x0, int y0) {
+  while (st.i0 < st.total) {
+    stage_issue(st, src, stride, row_limit, x0, y0);
+    stage_store(st, lds, lp);
+  }
+}
+
+// A whole region, pass by pass.
+template <int U>
+__device__ __forceinline__ void stage_all(uint8_t* lds, int lp, gptr<const uint8_t> src,
+                                          int stride, int row_limit, int x0, int x1, int y0,
+                                          int y1) {
+  Stage<U> st;
+  stage_begin(st, x0, x1, y0, y1);
+  stage_rest(st, lds, lp, src, stride, row_limit, x0, y0);
+}
+
+// Harris R' at LDS pixel (cx, cy) by one lane: the 9 x 9 neighbourhood is read as three
+// aligned 32-bit words per row (bytes extracted by alignbyte), horizontal differences
+// hd = I[c+1] - I[c-1] and smoothings hs = I[c-1] + 2 I[c] + I[c+1] are formed per row,
+// and three rows are kept in registers for G_x = hd[r-1] + 2 hd[r] + hd[r+1] and
+// G_y = hs[r+1] - hs[r-1] (Eq. 4, separable).  pix and the row pitch P are 4-aligned.
+__device__ __forceinline__ void harris_row_words(const uint8_t* row, int s, int (&hd)[7],
+                                                 int (&hs)[7]) {
+  const uint32_t* w = (const uint32_t*)row;
+  const uint32_t w0 = w[0], w1 = w[1], w2 = w[2];
+  const uint32_t lo = __builtin_amdgcn_alignbyte(w1, w0, (uint32_t)s);  // bytes 0..3
+  const uint32_t mid = __builtin_amdgcn_alignbyte(w2, w1, (uint32_t)s);  // bytes 4..7
   int v[9];
 #pragma unroll
-  for (int k = 0; k < 9; ++k) v[k] = row[k];
+  for (int k = 0; k < 4; ++k) {
+    v[k] = (int)((lo >> (8 * k)) & 255u);
+    v[k + 4] = (int)((mid >> (8 * k)) & 255u);
+  }
+  v[8] = (int)((w2 >> (8 * s)) & 255u);
 #pragma unroll
   for (int c = 0; c < 7; ++c) {
     hd[c] = v[c + 2] - v[c];
@@ -386,16 +429,17 @@ __device__ __forceinline__ void harris_row(const uint8_t* row, int (&hd)[7], int
   }
 }
 
-__device__ __forceinline__ int64_t harris_lds(const uint8_t* pix, int P, int cx, int cy) {
+__device__ __forceinline__ int64_t harris_point(const uint8_t* pix, int P, int cx, int cy) {
+  const int a = cx - 4, s = a & 3;
+  const uint8_t* row = pix + (cy - 4) * P + (a - s);
   int hd0[7], hs0[7], hd1[7], hs1[7];
-  const uint8_t* row = pix + (cy - 4) * P + (cx - 4);
-  harris_row(row, hd0, hs0);
-  harris_row(row + P, hd1, hs1);
+  harris_row_words(row, s, hd0, hs0);
+  harris_row_words(row + P, s, hd1, hs1);
   int sxx = 0, syy = 0, sxy = 0;
-#pragma unroll 1
+#pragma unroll
   for (int r = 2; r < 9; ++r) {
     int hd2[7], hs2[7];
-    harris_row(row + r * P, hd2, hs2);
+    harris_row_words(row + r * P, s, hd2, hs2);
 #pragma unroll
     for (int c = 0; c < 7; ++c) {
       const int gx = hd0[c] + 2 * hd1[c] + hd2[c];
@@ -409,71 +453,8 @@ __device__ __forceinline__ int64_t harris_lds(const uint8_t* pix, int P, int cx,
       hs1[c] = hs2[c];
     }
   }
-  const int64_t a = sxx, b = syy, c = sxy;
-  return 25 * (a * b - c * c) - (a + b) * (a + b);
-}
-
-__device__ __forceinline__ void harris_window_row(const uint8_t* pix, int P, uint32_t pos, int sx0,
-                                                  int sy0, int s, int* sxx, int* syy, int* sxy) {
-  const int cx = (int)(pos & 0xffff) - sx0, cy = (int)(pos >> 16) - sy0;
-  const uint8_t* r0 = pix + (cy + s - 4) * P + (cx - 4);
-  int a[9], b[9], d[9];
-#pragma unroll
-  for (int k = 0; k < 9; ++k) {
-    a[k] = r0[k];
-    b[k] = r0[P + k];
-    d[k] = r0[2 * P + k];
-  }
-  int xx = 0, yy = 0, xy = 0;
-#pragma unroll
-  for (int k = 1; k < 8; ++k) {
-    const int gx = (a[k + 1] - a[k - 1]) + 2 * (b[k + 1] - b[k - 1]) + (d[k + 1] - d[k - 1]);
-    const int gy = (d[k - 1] + 2 * d[k] + d[k + 1]) - (a[k - 1] + 2 * a[k] + a[k + 1]);
-    xx += gx * gx;
-    yy += gy * gy;
-    xy += gx * gy;
-  }
-  *sxx = xx;
-  *syy = yy;
-  *sxy = xy;
-}
-
-// Harris R' of candidates by groups of 8 lanes: lane s < 7 of a group forms the Sobel
-// gradients (Eq. 4) at the 7 pixels of window row dy = s - 3 from 3 staged rows and
-// sums gx^2, gy^2, gx*gy; the 7 row sums are added across the group and R' is formed
-// by lane 0.  A group takes two candidates per round (two independent chains of loads
-// and sums in flight; lane 7 and a missing second candidate compute on a valid row and
-// drop the result).  Every lane of the block runs the same number of rounds.
-__device__ __forceinline__ void harris_groups(const uint8_t* pix, int P, const uint32_t* cpos,
-                                              int64_t* crs, int n, int sx0, int sy0) {
-  const int s = threadIdx.x & 7;
-  const int groups = kBlock >> 3;
-  const int sr = min(s, 6);  // lane 7 reads window row 6 (dropped below)
-  for (int cb = 0; cb < n; cb += 2 * groups) {
-    const int c0 = cb + (threadIdx.x >> 3), c1 = c0 + groups;
-    int xx0 = 0, yy0 = 0, xy0 = 0, xx1 = 0, yy1 = 0, xy1 = 0;
-    if (c0 < n) {
-      const uint32_t p0 = cpos[c0], p1 = cpos[min(c1, n - 1)];
-      harris_window_row(pix, P, p0, sx0, sy0, sr, &xx0, &yy0, &xy0);
-      harris_window_row(pix, P, p1, sx0, sy0, sr, &xx1, &yy1, &xy1);
-      if (s == 7) xx0 = yy0 = xy0 = 0;
-      if (s == 7 || c1 >= n) xx1 = yy1 = xy1 = 0;
-    }
-    xx0 = group8_sum(xx0);
-    yy0 = group8_sum(yy0);
-    xy0 = group8_sum(xy0);
-    xx1 = group8_sum(xx1);
-    yy1 = group8_sum(yy1);
-    xy1 = group8_sum(xy1);
-    if (s == 0 && c0 < n) {
-      const int64_t A = xx0, B = yy0, C = xy0;
-      crs[c0] = 25 * (A * B - C * C) - (A + B) * (A + B);
-    }
-    if (s == 0 && c1 < n) {
-      const int64_t A = xx1, B = yy1, C = xy1;
-      crs[c1] = 25 * (A * B - C * C) - (A + B) * (A + B);
-    }
-  }
+  const int64_t A = sxx, B = syy, C = sxy;
+  return 25 * (A * B - C * C) - (A + B) * (A + B);
 }
 
 // Block barrier that orders LDS accesses only.  __syncthreads() also waits for the
@@ -698,59 +679,8 @@ __global__ __launch_bounds__(1024) void k_prologue(PrologueArgs a) {
 
   if (i < nL) {
     LevelPlan P;
-    P.W = g.W[l];
-    P.H = g.H[l];
-    P.B = a.p.patch_radius;
-    P.level = l;
-    P.frame = f;
-    P.n_levels = L;
-    P.cs = g.cs[l];
-    P.ncx = g.ncx[l];
-    P.ncy = g.ncy[l];
-    P.quota = g.quota[l];
-    P.kcell = g.kcell[l];
-    P.fast_t = a.p.fast_t;
-    P.fast_t_min = a.p.fast_t_min;
-    P.base = a.f[f].data;
-    P.base_w = a.f[f].w;
-    P.base_h = a.f[f].h;
-    P.base_stride = a.f[f].stride;
-    if (l == 0) {
-      P.lvl = a.f[f].data;
-      P.lvl_w = nullptr;
-      P.lvl_stride = a.f[f].stride;
-    } else {
-      P.lvl_w = ws + a.lay.off_lvl + o_lvl;
-      P.lvl = P.lvl_w;
-      P.lvl_stride = level_stride(P.W);
-    }
-    P.wpr = s.wpr;
-    P.bm_lo = (uint32_t*)(ws + a.lay.off_bm) + o_bm;
-    P.bm_hi = P.bm_lo + (int64_t)s.wpr * P.H;
-    P.flags = ws + a.lay.off_flags + o_flag;
-    P.cand = (Cand*)(ws + a.lay.off_cand) + o_cand;
-    P.cand_count = counters + i;
-    P.cand_cap = (int32_t)s.cand_cap;
-    P.kslot = s.kslot;
-    P.compact = a.p.cell == 0 && s.cand_cap > kRankCap;
-    P.slot_w = s.slot_w;
-    P.sel = (Cand*)(ws + a.lay.off_sel) + o_sel;
-    P.sel_count = counters + a.lay.n_entries + i;
-    P.ncand_count = counters + 2 * a.lay.n_entries + i;
-    P.mark_tx = s.mark_tx;
-    P.mark_ty = s.mark_ty;
-    P.band_rot = rot;
-    P.det_band_rot = drot;
-    P.det_tx = s.det_tx;
-    P.det_ty = s.det_ty;
-    P.det_x0 = s.det_x0;
-    P.det_y0 = s.det_y0;
-    P.det_xend = s.det_xend;
-    P.det_yend = s.det_yend;
-    P.orient_blocks = s.orient_blocks;
-    P.entry0 = f * L;
-    P.out = a.out + a.f[f].out_off;
-    P.count_out = a.counts + f;
+    const EntryOffsets eo = {o_flag, o_bm, o_cand, o_sel, o_lvl, rot, drot, counters};
+    fill_level_plan(P, a, ws, g, s, i, f, l, eo);
     plan[i] = P;
     mark_base[i] = (int32_t)o_mark;
     det_base[i] = (int32_t)o_det;
@@ -836,7 +766,7 @@ __global__ __launch_bounds__(256) void k_pyramid_batch(KArgs a) {
     b = g - st;
   } else {
     load_bases(s_base, a.pyr_base, h.n_entries);
-    e = uniform(find_entry(s_base, h.n_entries, g));
+    e = uniform(prefix_entry(s_base, h.n_entries, g));
     b = g - s_base[e];
   }
   const LevelPlan P = plan_at(h.plan, e);
@@ -861,7 +791,7 @@ __global__ __launch_bounds__(256, 5) void k_mark(KArgs a) {
   const int band = (int)(blockIdx.x % kXcds);  // used in the band order only
   Head h = read_head(a, band);
   h.persistent = PERSIST;  // one tile per block otherwise: straight-line code, no loop state
-  const MarkLds M = mark_lds(h.t);
+  const MarkLds& M = a.ml;  // computed by the host
   uint8_t* pix = smem;
   uint16_t* queue = (uint16_t*)(smem + M.off_queue);
   uint32_t* bml = (uint32_t*)(smem + M.off_bml);
@@ -883,13 +813,11 @@ __global__ __launch_bounds__(256, 5) void k_mark(KArgs a) {
 
   for (int iter = 0; PERSIST || iter == 0; ++iter) {
     const int g0 = uniform(queue_take(h, iter, &s_next));
-    if (g0 >= h.total) break;
-    const int gb = h.bands ? g0 / kXcds : g0;
-    const int ng = h.bands ? (h.small ? h.b[kSmallEntries] : s_base[h.n_entries]) : h.total;
-    if (gb >= ng) break;  // band holds fewer tiles
-    // When every block of the grid is resident at once, last tile first: tiles of the
-    // levels above 0 resample and take longer, and then start on idle compute units.
-    const int g = a.mark_rev ? ng - 1 - gb : gb;
+    // in the band order a band may hold fewer tiles than the launch gives it blocks
+    const int g = launch_tile(g0, h.total, h.bands,
+                              h.bands ? (h.small ? h.b[kSmallEntries] : s_base[h.n_entries]) : 0,
+                              a.mark_rev);
+    if (g < 0) break;
     if (h.persistent) lds_barrier();  // every thread has read s_next
     const int next = queue_prefetch(h, g0, h.qctr + 0);
     int e, t;
@@ -901,7 +829,7 @@ __global__ __launch_bounds__(256, 5) void k_mark(KArgs a) {
       small_entry(h.b, g, &e, &st);
       t = g - st;
     } else {
-      e = uniform(find_entry(s_base, h.n_entries, g));
+      e = uniform(prefix_entry(s_base, h.n_entries, g));
       t = g - s_base[e];
     }
     const LevelPlan P = plan_at(h.plan, e);
@@ -909,10 +837,9 @@ __global__ __launch_bounds__(256, 5) void k_mark(KArgs a) {
     const int W = P.W, H = P.H, B = P.B;
     const int tx = t % P.mark_tx;
     const int ty = t / P.mark_tx + (h.bands ? band_row0(P.mark_ty, P.band_rot, band) : 0);
-    const int x_t0 = tx * TW, x_t1 = min(W, x_t0 + TW);
-    const int y_t0 = ty * M.th, y_t1 = min(H, y_t0 + M.th);
-    const int ox = max(0, x_t0 - 4), oy = max(0, y_t0 - 3);
-    const int ex = min(W, x_t1 + 3), ey = min(H, y_t1 + 3);
+    const MarkTile T = mark_tile(W, H, TW, M.th, tx, ty);
+    const int x_t0 = T.x_t0, x_t1 = T.x_t1, y_t0 = T.y_t0, y_t1 = T.y_t1;
+    const int ox = T.ox, oy = T.oy, ex = T.ex, ey = T.ey;
     const int nx = ex - ox, ny = ey - oy;
 
     // 1. level pixels of the tile and its 3-pixel halo
@@ -956,6 +883,38 @@ __global__ __launch_bounds__(256, 5) void k_mark(KArgs a) {
       const uint32_t ty_a = resample_tap_r(oy + min(lane, ny - 1), P.base_h, H, rh);
       const uint32_t ty_b = ny > 64 ? resample_tap_r(oy + min(lane + 64, ny - 1), P.base_h, H, rh)
                                     : 0u;
+      // The window of the frame the tile's taps fall in (taps are monotone: the first and
+      // last column and row bound it).  When it fits the LDS left by the tile, it is
+      // staged with coalesced word loads and the taps are read from there; otherwise each
+      // tap pair is a 16-bit gather from the frame.
+      uint32_t sx_lo, sx_hi;
+      u16x2 unused_w;
+      col_tap(0, &sx_lo, &unused_w);
+      col_tap(nx - 1, &sx_hi, &unused_w);
+      sx_lo = (uint32_t)uniform((int)sx_lo) & ~3u;
+      sx_hi = (uint32_t)uniform((int)sx_hi) + 1u;
+      const int sy_lo = uniform((int)(__builtin_amdgcn_readlane((int)ty_a, 0) >> 9));
+      const int yl = (int)((uint32_t)__builtin_amdgcn_readlane(
+                               (int)(ny - 1 < 64 ? ty_a : ty_b), (ny - 1) & 63) >> 9);
+      const int sy_hi = uniform(min(yl + 1, bh1));
+      const int sp = (int)(((sx_hi - sx_lo) | 3u) + 1u);  // window row pitch, multiple of 4
+      const bool staged = sp * (sy_hi - sy_lo + 1) <= M.src_bytes;
+      uint8_t* win = smem + M.off_src;
+      if (staged) {
+        stage_all<12>(win, sp, base, bs, bw, (int)sx_lo, (int)sx_hi + 1, sy_lo, sy_hi + 1);
+        lds_barrier();
+      }
+      typedef uint16_t u16_lds_any __attribute__((aligned(1)));
+      // The rows of the tile, with the two horizontal taps of source row y at column x
+      // read from the window (S) or the frame: one loop per source, chosen once.
+      auto resample_rows = [&](auto staged_c) {
+      constexpr bool S = decltype(staged_c)::value;
+      auto tap_pair = [&](int y, uint32_t x) -> uint32_t {
+        if constexpr (S)
+          return (uint32_t)*(const u16_lds_any*)(win + (y - sy_lo) * sp + (x - sx_lo));
+        else
+          return load_pair(base + ((uint32_t)(y * bs) + x));
+      };
       for (int j0 = RPI * wave; j0 < ny; j0 += RPI * nwave) {
         uint32_t v[RPI][NC][2];
         u16x2 wyr[RPI];  // (256 - wy, wy)
@@ -966,13 +925,10 @@ __global__ __launch_bounds__(256, 5) void k_mark(KArgs a) {
               (uint32_t)__builtin_amdgcn_readlane((int)(j < 64 ? ty_a : ty_b), j & 63);
           const int y0 = (int)(tyy >> 9);
           wyr[h] = pair16(256u - (tyy & 511u), tyy & 511u);
-          // 32-bit offsets from the frame's base: one scalar base and one vector offset
-          // per load, no 64-bit address arithmetic per lane
-          const uint32_t o0 = (uint32_t)(y0 * bs), o1 = (uint32_t)(min(y0 + 1, bh1) * bs);
 #pragma unroll
           for (int c = 0; c < NC; ++c) {
-            v[h][c][0] = load_pair(base + (o0 + cx[c]));
-            v[h][c][1] = load_pair(base + (o1 + cx[c]));
+            v[h][c][0] = tap_pair(y0, cx[c]);
+            v[h][c][1] = tap_pair(min(y0 + 1, bh1), cx[c]);
           }
         }
         // side columns: lane takes row j0 + hrow
@@ -982,8 +938,8 @@ __global__ __launch_bounds__(256, 5) void k_mark(KArgs a) {
         uint32_t hv0 = 0, hv1 = 0;
         if (hlane) {
           const int y0 = (int)(hty >> 9);
-          hv0 = load_pair(base + ((uint32_t)(y0 * bs) + hx));
-          hv1 = load_pair(base + ((uint32_t)(min(y0 + 1, bh1) * bs) + hx));
+          hv0 = tap_pair(y0, hx);
+          hv1 = tap_pair(min(y0 + 1, bh1), hx);
         }
 #pragma unroll
         for (int h = 0; h < RPI; ++h) {
@@ -1001,9 +957,14 @@ __global__ __launch_bounds__(256, 5) void k_mark(KArgs a) {
           pix[j * PITCH + hcol] = (uint8_t)blend_q8(hv0, hv1, hwx, wy);
         }
       }
+      };
+      if (staged)
+        resample_rows(std::integral_constant<bool, true>{});
+      else
+        resample_rows(std::integral_constant<bool, false>{});
     } else {
       const int limit = P.level == 0 ? W : P.lvl_stride;
-      stage_rows<8>(pix, PITCH, G(P.lvl), P.lvl_stride, limit, ox, ex, oy, ey);
+      stage_all<8>(pix, PITCH, G(P.lvl), P.lvl_stride, limit, ox, ex, oy, ey);
     }
     for (int i = threadIdx.x; i < 2 * M.th * 2 * TWW; i += kBlock) bml[i] = 0u;  // lo, hi
     lds_barrier();
@@ -1222,7 +1183,7 @@ __global__ __launch_bounds__(256, 4) void k_detect(KArgs a) {
   const int band = (int)(blockIdx.x % kXcds);  // used in the band order only
   Head h = read_head(a, band);
   h.persistent = PERSIST;  // one tile per block otherwise: straight-line code, no loop state
-  const DetLds D = det_lds(h.t, h.cell);
+  const DetLds& D = a.dl;  // computed by the host
   uint8_t* pix = smem;
   uint32_t* cw = (uint32_t*)(smem + D.off_cw);
   uint32_t* ucnt = (uint32_t*)(smem + D.off_ucnt);
@@ -1251,14 +1212,10 @@ __global__ __launch_bounds__(256, 4) void k_detect(KArgs a) {
 
   for (int iter = 0; PERSIST || iter == 0; ++iter) {
     const int g0 = uniform(queue_take(h, iter, &s_next));
-    if (g0 >= h.total) break;
-    const int gb = h.bands ? g0 / kXcds : g0;
-    const int ng = h.bands ? (h.small ? h.b[kSmallEntries] : s_base[h.n_entries]) : h.total;
-    if (gb >= ng) break;  // band holds fewer tiles
-    // When every block of the grid is resident at once, last tile first: the coarsest
-    // levels, whose tiles hold the most candidates, then start on idle compute units
-    // instead of behind the set-up of three other blocks.
-    const int g = a.det_rev ? ng - 1 - gb : gb;
+    const int g = launch_tile(g0, h.total, h.bands,
+                              h.bands ? (h.small ? h.b[kSmallEntries] : s_base[h.n_entries]) : 0,
+                              a.det_rev);
+    if (g < 0) break;
     if (h.persistent) lds_barrier();  // every thread has read s_next
     const int next = queue_prefetch(h, g0, h.qctr + 2);
     int e, t;
@@ -1270,7 +1227,7 @@ __global__ __launch_bounds__(256, 4) void k_detect(KArgs a) {
       small_entry(h.b, g, &e, &st);
       t = g - st;
     } else {
-      e = uniform(find_entry(s_base, h.n_entries, g));
+      e = uniform(prefix_entry(s_base, h.n_entries, g));
       t = g - s_base[e];
     }
     const LevelPlan P = plan_at(h.plan, e);
@@ -1278,33 +1235,13 @@ __global__ __launch_bounds__(256, 4) void k_detect(KArgs a) {
     const int W = P.W, H = P.H, B = P.B, cs = P.cs;
     const int tx = t % P.det_tx;
     const int ty = t / P.det_tx + (h.bands ? band_row0(P.det_ty, P.det_band_rot, band) : 0);
-    int vx0, vx1, vy0, vy1, cxa = 0, cya = 0, nlcx = 1, nlcy = 1;
-    if (h.cell > 0) {
-      cxa = P.det_x0 + tx * h.t.det_cx;
-      cya = P.det_y0 + ty * h.t.det_cy;
-      const int cxb = min(cxa + h.t.det_cx, P.det_xend), cyb = min(cya + h.t.det_cy, P.det_yend);
-      nlcx = cxb - cxa;
-      nlcy = cyb - cya;
-      vx0 = max(cxa * cs, B);
-      vx1 = min(cxb * cs, W - B);
-      vy0 = max(cya * cs, B);
-      vy1 = min(cyb * cs, H - B);
-    } else {
-      vx0 = P.det_x0 + tx * h.t.det_w;
-      vx1 = min(vx0 + h.t.det_w, P.det_xend);
-      vy0 = P.det_y0 + ty * h.t.det_h;
-      vy1 = min(vy0 + h.t.det_h, P.det_yend);
-    }
-    // tile + 1-pixel ring (candidates), + 5-pixel halo (staged pixels)
-    const int rx0 = vx0 - 1, ry0 = vy0 - 1;
-    const int rw = vx1 - vx0 + 2, rh = vy1 - vy0 + 2;
-    const int sx0 = max(0, vx0 - 5) & ~3, sy0 = max(0, vy0 - 5);
-    const int sx1 = min(W, vx1 + 5), sy1 = min(H, vy1 + 5);
-    // candidate words: the 32-bit bitmap words that hold ring columns, per ring row
-    const int bw0 = rx0 >> 5, nbw = ((rx0 + rw - 1) >> 5) - bw0 + 1;
-    const int nunits = rh * nbw;
-    const int fcx0 = rx0 / cs, fcy0 = ry0 / cs;
-    const int nfx = (rx0 + rw - 1) / cs - fcx0 + 1, nfy = (ry0 + rh - 1) / cs - fcy0 + 1;
+    const DetTile T = det_tile(P, h.t, h.cell, tx, ty);
+    const int vx0 = T.vx0, vx1 = T.vx1, vy0 = T.vy0, vy1 = T.vy1;
+    const int cxa = T.cxa, cya = T.cya, nlcx = T.nlcx, nlcy = T.nlcy;
+    const int rx0 = T.rx0, ry0 = T.ry0, rw = T.rw;
+    const int sx0 = T.sx0, sy0 = T.sy0, sx1 = T.sx1, sy1 = T.sy1;
+    const int bw0 = T.bw0, nbw = T.nbw, nunits = T.nunits;
+    const int fcx0 = T.fcx0, fcy0 = T.fcy0, nfx = T.nfx, nfy = T.nfy;
     const int ncell = nlcx * nlcy;
     const int nvx = P.det_xend - P.det_x0;
     const int nbx = (vx1 - vx0 + 1) >> 1, nby = (vy1 - vy0 + 1) >> 1;  // 2x2 blocks
@@ -1317,6 +1254,10 @@ __global__ __launch_bounds__(256, 4) void k_detect(KArgs a) {
     {
       gptr<const uint8_t> gfl = G((const uint8_t*)P.flags);
       const int nfl = nfx * nfy;
+      const int limit = P.level == 0 ? W : P.lvl_stride;
+      Stage<10> st;
+      stage_begin(st, sx0, sx1, sy0, sy1);
+      stage_issue(st, G(P.lvl), P.lvl_stride, limit, sx0, sy0);
       uint32_t vfl[2];
 #pragma unroll
       for (int u = 0; u < 2; ++u) {
@@ -1334,8 +1275,8 @@ __global__ __launch_bounds__(256, 4) void k_detect(KArgs a) {
           vfl[u] = gfl[(fcy0 + r) * P.ncx + fcx0 + k];
         }
       }
-      stage_rows<10>(pix, D.pitch, G(P.lvl), P.lvl_stride, P.level == 0 ? W : P.lvl_stride, sx0,
-                     sx1, sy0, sy1);
+      stage_store(st, pix, D.pitch);
+      stage_rest(st, pix, D.pitch, G(P.lvl), P.lvl_stride, limit, sx0, sy0);
 #pragma unroll
       for (int u = 0; u < 2; ++u) {
         const int i = u * bd + tid;
@@ -1448,7 +1389,10 @@ __global__ __launch_bounds__(256, 4) void k_detect(KArgs a) {
     }
     lds_barrier();
     const int ncache = min(ncand, kCandCache);
-    harris_groups(pix, D.pitch, cpos, crs, ncache, sx0, sy0);
+    for (int c = tid; c < ncache; c += bd) {
+      const uint32_t ps = cpos[c];
+      crs[c] = harris_point(pix, D.pitch, (int)(ps & 0xffff) - sx0, (int)(ps >> 16) - sy0);
+    }
     lds_barrier();
 
     // Position and R' of candidate ci (raster order); beyond the cache the position is
@@ -1467,7 +1411,7 @@ __global__ __launch_bounds__(256, 4) void k_detect(KArgs a) {
     };
     auto cand_score = [&](int ci, uint32_t pos) -> int64_t {
       if (ci < kCandCache) return crs[ci];
-      return harris_lds(pix, D.pitch, (int)(pos & 0xffff) - sx0, (int)(pos >> 16) - sy0);
+      return harris_point(pix, D.pitch, (int)(pos & 0xffff) - sx0, (int)(pos >> 16) - sy0);
     };
 
     // 4. NMS: a tile candidate survives when it ranks above every candidate neighbour.
@@ -1667,7 +1611,7 @@ __global__ __launch_bounds__(256) void k_select_orient(KArgs a) {
     if (h.small) {
       small_entry(h.b, sl, e, st, en);
     } else {
-      *e = uniform(find_entry(s_base, h.n_entries, sl));
+      *e = uniform(prefix_entry(s_base, h.n_entries, sl));
       *st = s_base[*e];
       *en = s_base[*e + 1];
     }
@@ -1687,13 +1631,14 @@ __global__ __launch_bounds__(256) void k_select_orient(KArgs a) {
   const LevelPlan P = plan_at(h.plan, e);
   if (wsig != h.sig) return;
   gptr<const uint32_t> counts = G((const uint32_t*)P.cand_count) - e;  // all entries
-  const int C = P.cand_cap;  // slots; empty ones hold the sentinel
+  const int C = ranked_candidates(P, counts[e]);  // empty slots hold the sentinel
   if (live && P.level == 0 && i == 0 && lane == 0) {
     int total = 0;
     for (int l = 0; l < P.n_levels; ++l)
       total += min((int)counts[P.entry0 + l], plan_quota(a.plan, P.entry0 + l));
     *G(P.count_out) = total;
   }
+  if (one && slot0 - st0 >= C) return;  // the block's slots are past the level's list
   gptr<const Cand> cand = G((const Cand*)P.cand);
   // A block whose slots all belong to one level that fits the LDS stages the level's
   // R' once (one load per 256 slots per thread, all in flight) and ranks from there.
@@ -1799,10 +1744,10 @@ __global__ __launch_bounds__(1024) void k_select(KArgs a) {
   const LevelPlan P = plan_at(a.plan, e);
   if (wsig != a.sig) return;  // not the plan this launch was made for
   const int N = P.quota;
-  if (a.rank_path && P.cand_cap <= kRankCap) return;  // handled by k_select_orient
   const int nfill = (int)*G(P.cand_count);
   // slots (empty ones hold the sentinel and are skipped), or the appended entries
-  const int C = P.compact ? min(nfill, P.cand_cap) : P.cand_cap;
+  const int C = ranked_candidates(P, (uint32_t)nfill);
+  if (a.rank_path && C <= kRankCap) return;  // handled by k_select_orient
   const int nout = min(nfill, N);
   if (nout <= 0) {
     if (threadIdx.x == 0) *G(P.sel_count) = 0;
@@ -1933,13 +1878,13 @@ __global__ __launch_bounds__(1024) void k_select(KArgs a) {
 // Orientation of the radix-selected keypoints: one wave per keypoint.
 __global__ __launch_bounds__(256) void k_orient(KArgs a) {
   const int b = (int)blockIdx.x;
-  const int e = a.entry >= 0 ? a.entry : find_entry(a.orient_base, a.n_entries, b);
+  const int e = a.entry >= 0 ? a.entry : prefix_entry(a.orient_base, a.n_entries, b);
   const int chunk = a.entry >= 0 ? b : b - a.orient_base[e];
   const uint64_t wsig = *(cptr<uint64_t>)a.ws_sig;
   const LevelPlan P = plan_at(a.plan, e);
   if (wsig != a.sig) return;  // not the plan this launch was made for
   gptr<const uint32_t> counts = G((const uint32_t*)P.cand_count) - e;
-  if (a.rank_path && P.cand_cap <= kRankCap) return;  // written by k_select_orient
+  if (a.rank_path && ranked_candidates(P, counts[e]) <= kRankCap) return;  // k_select_orient's
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int nsel = (int)*G(P.sel_count);
   int prefix = 0;
@@ -2462,7 +2407,7 @@ void launch_mark_w(const KArgs& a, bool fused, int grid, int bytes, hipStream_t 
 }
 
 hipError_t launch_mark(const KArgs& a, bool fused, int grid, hipStream_t s) {
-  const int bytes = mark_lds(a.t).bytes + base_table_bytes(a.n_entries);
+  const int bytes = a.ml.bytes + base_table_bytes(a.n_entries);
   switch (a.t.mark_words) {
     case 1: launch_mark_w<1>(a, fused, grid, bytes, s); break;
     case 2: launch_mark_w<2>(a, fused, grid, bytes, s); break;
@@ -2473,7 +2418,7 @@ hipError_t launch_mark(const KArgs& a, bool fused, int grid, hipStream_t s) {
 }
 
 hipError_t launch_detect(const KArgs& a, int grid, hipStream_t s) {
-  const int bytes = det_lds(a.t, a.cell).bytes + base_table_bytes(a.n_entries);
+  const int bytes = a.dl.bytes + base_table_bytes(a.n_entries);
   if (a.persistent)
     OF_LAUNCH(k_detect<true>, dim3(grid), dim3(256), bytes, s, a);
   else

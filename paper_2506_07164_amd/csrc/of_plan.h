@@ -218,6 +218,14 @@ OF_HD void entry_size(const FrameGeom& g, const of_params& p, const Tune& t, int
   s->pyr_blocks = l == 0 ? 0 : cdiv(W, 64) * cdiv(H, 16);
 }
 
+// Candidates the level selection ranks for a level: its slots (fixed slots, empty ones
+// holding the sentinel), or the survivors its tiles appended (a whole-level cell past the
+// rank cap: a dense list of `filled` entries).  Levels with at most kRankCap of them are
+// ranked by counting (k_select_orient); the rest take the radix select.
+OF_HD int32_t ranked_candidates(const LevelPlan& P, uint32_t filled) {
+  return P.compact ? ((int64_t)filled < P.cand_cap ? (int32_t)filled : P.cand_cap) : P.cand_cap;
+}
+
 // ------------------------------------------------------------ workspace layout --
 
 // Region sizes of a whole call; offsets are from the workspace base (256-aligned).
@@ -320,13 +328,117 @@ OF_HD uint32_t resample_tap_r(int32_t i, int32_t n_src, int32_t n_dst, double rd
   return ((uint32_t)i0 << 9) | (uint32_t)q;
 }
 
+// ------------------------------------------------------------- tile geometry --
+// The same functions place every tile in the kernels and in the CPU launch model of the
+// tests, so both check one arithmetic.
+
+// Tile (in the launch's numbering) that block or queue draw g0 takes, or -1 when it
+// takes none.  In the band order block b takes the (b / kXcds)-th tile of band
+// b % kXcds, which holds band_tiles; a grid the device holds at once runs its tiles last
+// first (rev).
+OF_HD int32_t launch_tile(int32_t g0, int32_t total, int32_t bands, int32_t band_tiles,
+                          int32_t rev) {
+  if (g0 >= total) return -1;
+  const int32_t gb = bands ? g0 / kXcds : g0;
+  const int32_t ng = bands ? band_tiles : total;
+  if (gb >= ng) return -1;
+  return rev ? ng - 1 - gb : gb;
+}
+
+// Last index e < n with base[e] <= g, for a non-decreasing exclusive prefix base.
+OF_HD int32_t prefix_entry(const int32_t* base, int32_t n, int32_t g) {
+  int32_t lo = 0, hi = n - 1;
+  while (lo < hi) {
+    const int32_t mid = (lo + hi + 1) >> 1;
+    if (base[mid] <= g) lo = mid; else hi = mid - 1;
+  }
+  return lo;
+}
+
+// Segment-test tile (tx, ty) of a W x H level: the tile's pixels [x_t0, x_t1) x
+// [y_t0, y_t1) and the staged region [ox, ex) x [oy, ey) with its 3-pixel halo (ox a
+// multiple of 4, one pixel more on the left).
+struct MarkTile {
+  int32_t x_t0, x_t1, y_t0, y_t1, ox, oy, ex, ey;
+};
+
+OF_HD MarkTile mark_tile(int32_t W, int32_t H, int32_t tw, int32_t th, int32_t tx, int32_t ty) {
+  MarkTile m;
+  m.x_t0 = tx * tw;
+  m.x_t1 = m.x_t0 + tw < W ? m.x_t0 + tw : W;
+  m.y_t0 = ty * th;
+  m.y_t1 = m.y_t0 + th < H ? m.y_t0 + th : H;
+  m.ox = m.x_t0 - 4 > 0 ? m.x_t0 - 4 : 0;
+  m.oy = m.y_t0 - 3 > 0 ? m.y_t0 - 3 : 0;
+  m.ex = m.x_t1 + 3 < W ? m.x_t1 + 3 : W;
+  m.ey = m.y_t1 + 3 < H ? m.y_t1 + 3 : H;
+  return m;
+}
+
+// Harris/NMS tile (tx, ty) of a level: its valid pixels [vx0, vx1) x [vy0, vy1) (whole
+// cells cxa.. / cya.. when there are cells), the 1-pixel ring of candidates around them
+// (origin rx0, ry0, size rw x rh), the staged pixels [sx0, sx1) x [sy0, sy1) (5-pixel
+// halo, sx0 a multiple of 4), the bitmap words that hold ring columns (bw0, nbw per
+// ring row, nunits in all) and the cell flags of the ring (fcx0, fcy0, nfx x nfy).
+struct DetTile {
+  int32_t vx0, vx1, vy0, vy1, cxa, cya, nlcx, nlcy;
+  int32_t rx0, ry0, rw, rh, sx0, sy0, sx1, sy1;
+  int32_t bw0, nbw, nunits, fcx0, fcy0, nfx, nfy;
+};
+
+OF_HD DetTile det_tile(const LevelPlan& P, const Tune& t, int32_t cell, int32_t tx, int32_t ty) {
+  DetTile d;
+  const int32_t W = P.W, H = P.H, B = P.B, cs = P.cs;
+  d.cxa = d.cya = 0;
+  d.nlcx = d.nlcy = 1;
+  if (cell > 0) {
+    d.cxa = P.det_x0 + tx * t.det_cx;
+    d.cya = P.det_y0 + ty * t.det_cy;
+    const int32_t cxb = d.cxa + t.det_cx < P.det_xend ? d.cxa + t.det_cx : P.det_xend;
+    const int32_t cyb = d.cya + t.det_cy < P.det_yend ? d.cya + t.det_cy : P.det_yend;
+    d.nlcx = cxb - d.cxa;
+    d.nlcy = cyb - d.cya;
+    d.vx0 = d.cxa * cs > B ? d.cxa * cs : B;
+    d.vx1 = cxb * cs < W - B ? cxb * cs : W - B;
+    d.vy0 = d.cya * cs > B ? d.cya * cs : B;
+    d.vy1 = cyb * cs < H - B ? cyb * cs : H - B;
+  } else {
+    d.vx0 = P.det_x0 + tx * t.det_w;
+    d.vx1 = d.vx0 + t.det_w < P.det_xend ? d.vx0 + t.det_w : P.det_xend;
+    d.vy0 = P.det_y0 + ty * t.det_h;
+    d.vy1 = d.vy0 + t.det_h < P.det_yend ? d.vy0 + t.det_h : P.det_yend;
+  }
+  d.rx0 = d.vx0 - 1;
+  d.ry0 = d.vy0 - 1;
+  d.rw = d.vx1 - d.vx0 + 2;
+  d.rh = d.vy1 - d.vy0 + 2;
+  d.sx0 = (d.vx0 - 5 > 0 ? d.vx0 - 5 : 0) & ~3;
+  d.sy0 = d.vy0 - 5 > 0 ? d.vy0 - 5 : 0;
+  d.sx1 = d.vx1 + 5 < W ? d.vx1 + 5 : W;
+  d.sy1 = d.vy1 + 5 < H ? d.vy1 + 5 : H;
+  d.bw0 = d.rx0 >> 5;
+  d.nbw = ((d.rx0 + d.rw - 1) >> 5) - d.bw0 + 1;
+  d.nunits = d.rh * d.nbw;
+  d.fcx0 = d.rx0 / cs;
+  d.fcy0 = d.ry0 / cs;
+  d.nfx = (d.rx0 + d.rw - 1) / cs - d.fcx0 + 1;
+  d.nfy = (d.ry0 + d.rh - 1) / cs - d.fcy0 + 1;
+  return d;
+}
+
 // ------------------------------------------------------------- LDS layouts --
 
+// LDS of the entry base table that tile kernels keep after their own layout.
+OF_HD int32_t base_table_bytes(int32_t n_entries) {
+  return (int32_t)align_up(4 * ((int64_t)n_entries + 1), 16);
+}
+
 // Segment-test tile: pixels (tile + 3-pixel halo, 4-aligned origin), the queue of
-// pixels that pass the compass pre-test and both bitmaps.
+// pixels that pass the compass pre-test, both bitmaps, and (launches only) a window of
+// the input frame that a resampled tile's taps fall in.
 struct MarkLds {
   int32_t tw, th, pitch, rows, qseg;
-  int32_t off_queue, off_bml, off_bmh, bytes;
+  int32_t off_queue, off_bml, off_bmh, off_src, src_bytes, bytes;
 };
 
 OF_HD MarkLds mark_lds(const Tune& t) {
@@ -342,7 +454,21 @@ OF_HD MarkLds mark_lds(const Tune& t) {
   m.off_queue = o;  o += align16(2 * 4 * m.qseg);
   m.off_bml = o;    o += 4 * m.th * 2 * t.mark_words;
   m.off_bmh = o;    o += 4 * m.th * 2 * t.mark_words;
-  m.bytes = align16(o);
+  m.off_src = align16(o);
+  m.src_bytes = 0;
+  m.bytes = m.off_src;
+  return m;
+}
+
+// The layout of a segment-test launch over n_entries (frame, level) pairs: the block's
+// LDS (with the entry table after it) is held to 32 KB so that 5 blocks share a compute
+// unit's 160 KB, and what the tile itself leaves of that is the input-frame window.
+constexpr int32_t kMarkLdsBudget = 32768 - 64;  // room for the static LDS variables
+OF_HD MarkLds mark_lds_launch(const Tune& t, int32_t n_entries) {
+  MarkLds m = mark_lds(t);
+  const int32_t room = kMarkLdsBudget - m.off_src - base_table_bytes(n_entries);
+  m.src_bytes = room > 0 ? (int32_t)((uint32_t)room & ~15u) : 0;
+  m.bytes = m.off_src + m.src_bytes;
   return m;
 }
 
@@ -398,9 +524,5 @@ OF_HD DetLds det_lds(const Tune& t, int32_t cell) {
   return d;
 }
 
-// LDS of the entry base table that tile kernels keep after their own layout.
-OF_HD int32_t base_table_bytes(int32_t n_entries) {
-  return (int32_t)align_up(4 * ((int64_t)n_entries + 1), 16);
-}
 
 }  // namespace ofk
