@@ -145,9 +145,10 @@ int of_detect(const of_image* in, const of_params* params, void* ws, size_t ws_b
               of_keypoint* out, int32_t cap, int32_t* count, hipStream_t stream);
 
 /* Batched path: n frames (host array of descriptors, 1 <= n <= OF_MAX_BATCH, sizes may
- * differ) through one launch per step: a persistent fused pyramid + segment-test kernel
- * over every level of every frame, a persistent Harris/NMS/cell-selection kernel, the
- * level selection and the orientation.  Frame i writes its keypoints (same order as
+ * differ) through one launch per step over every level of every frame: the fused
+ * pyramid + segment-test kernel, the Harris/NMS/cell-selection kernel (one block per
+ * tile, or a persistent grid drawing tiles from a queue with the tuning's grids), and
+ * the level selection with the orientation.  Frame i writes its keypoints (same order as
  * of_detect) at out + out_offset[i] (host array, in keypoints) and its count to
  * counts[i] (device).  cap_per_frame >= n_features is required and the caller keeps
  * the n output ranges disjoint.  `tuning` may be NULL (defaults). */

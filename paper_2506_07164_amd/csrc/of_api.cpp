@@ -214,6 +214,17 @@ struct CallPlan {
   FrameGeom geo[kMaxBatch];
 };
 
+// Host-side planning state of one call (about 140 KB): a single static instance, held
+// under its lock for the host part of a call, so that no call allocates host memory.
+// Calls from several threads take turns for that part only; their launches overlap.
+struct HostScratch {
+  std::mutex mu;
+  CallPlan c;
+  PrologueArgs pa;
+};
+
+HostScratch g_host;
+
 void plan_call(const of_image* frames, int n, const of_params& p, const Tune& t, CallPlan* c) {
   memset(&c->lay, 0, sizeof(c->lay));
   int64_t lvl = 0;
@@ -295,7 +306,7 @@ KArgs kargs(void* ws, const WsLayout& lay, const Tune& t, const of_params& p) {
   k.entry = -1;
   k.cell = p.cell;
   k.t = t;
-  k.ml = mark_lds_launch(t, lay.n_entries);
+  k.ml = mark_lds(t);
   k.dl = det_lds(t, p.cell);
   return k;
 }
@@ -424,10 +435,10 @@ int of_workspace_size(const of_image* frames, int32_t n, const of_params* params
   if (!bytes) return OF_EINVAL;
   int st = check_frames(frames, n, params);
   if (st) return st;
-  CallPlan* cp = new CallPlan;  // the layout does not depend on the tuning
+  std::lock_guard<std::mutex> lk(g_host.mu);
+  CallPlan* cp = &g_host.c;  // the layout does not depend on the tuning
   plan_call(frames, n, *params, default_tune(*params), cp);
   *bytes = (size_t)cp->lay.total;
-  delete cp;
   return OF_OK;
 }
 
@@ -461,18 +472,15 @@ int of_detect(const of_image* in, const of_params* params, void* ws, size_t ws_b
   if (!ws || !out || !count || cap < params->n_features) return OF_EINVAL;
   const of_params& p = *params;
   const Tune t = default_tune(p);
-  CallPlan* c = new CallPlan;
+  std::lock_guard<std::mutex> lk(g_host.mu);
+  CallPlan* c = &g_host.c;
   plan_call(in, 1, p, t, c);
-  if ((size_t)c->lay.total > ws_bytes) {
-    delete c;
-    return OF_ENOSPACE;
-  }
-  PrologueArgs* pa = new PrologueArgs;
+  if ((size_t)c->lay.total > ws_bytes) return OF_ENOSPACE;
+  PrologueArgs* pa = &g_host.pa;
   fill_prologue(pa, in, 1, p, t, ws, c->lay, out, nullptr, count);
   hipError_t e = timed(0, stream, [&] { return launch_prologue(*pa, prologue_grid(c->lay), stream); });
   resident_record(ws, pa->sig);
   const uint64_t sig = pa->sig;
-  delete pa;
   const int L = p.n_levels;
   // levels 1.. from the input frame, one launch per level
   for (int l = 1; l < L && e == hipSuccess; ++l) {
@@ -504,33 +512,34 @@ int of_detect(const of_image* in, const of_params* params, void* ws, size_t ws_b
     if (e == hipSuccess && issued > 1) e = launch_scale_counters(k, issued, stream);
   }
   if (e == hipSuccess) e = launch_selection(k, *c, stream);
-  delete c;
   return e == hipSuccess ? OF_OK : hip_fail(e);
 }
 
-int of_detect_batch(const of_image* frames, int32_t n, const of_params* params, void* ws,
-                    size_t ws_bytes, of_keypoint* out, const int64_t* out_offset,
-                    int32_t cap_per_frame, int32_t* counts, const of_tuning* tuning,
-                    hipStream_t stream) {
+}  // extern "C"
+
+namespace {
+
+// Validation of a batched call's arguments (everything but the workspace), on the host
+// before any launch.
+int check_batch(const of_image* frames, int32_t n, const of_params* params, of_keypoint* out,
+                const int64_t* out_offset, int32_t cap_per_frame, int32_t* counts,
+                const of_tuning* tuning, Tune* t) {
   int st = check_frames(frames, n, params);
   if (st) return st;
   for (int f = 0; f < n; ++f) {
     st = check_image(&frames[f], *params);
     if (st) return st;
   }
-  if (!ws || !out || !out_offset || !counts || cap_per_frame < params->n_features)
-    return OF_EINVAL;
-  const of_params& p = *params;
-  Tune t;
-  st = resolve_tune(tuning, p, &t);
-  if (st) return st;
-  CallPlan* c = new CallPlan;
-  plan_call(frames, n, p, t, c);
-  if ((size_t)c->lay.total > ws_bytes) {
-    delete c;
-    return OF_ENOSPACE;
-  }
-  PrologueArgs* pa = new PrologueArgs;
+  if (!out || !out_offset || !counts || cap_per_frame < params->n_features) return OF_EINVAL;
+  return resolve_tune(tuning, *params, t);
+}
+
+// The batched path on a workspace of ws_bytes (the caller holds g_host.mu; c holds the
+// call's plan).
+int detect_batch_planned(const of_image* frames, int32_t n, const of_params& p, const Tune& t,
+                         CallPlan* c, void* ws, of_keypoint* out, const int64_t* out_offset,
+                         int32_t* counts, hipStream_t stream) {
+  PrologueArgs* pa = &g_host.pa;
   fill_prologue(pa, frames, n, p, t, ws, c->lay, out, out_offset, counts);
   const uint64_t sig = pa->sig;
   hipError_t e = hipSuccess;
@@ -538,7 +547,6 @@ int of_detect_batch(const of_image* frames, int32_t n, const of_params* params, 
     e = timed(0, stream, [&] { return launch_prologue(*pa, prologue_grid(c->lay), stream); });
     resident_record(ws, sig);
   }
-  delete pa;
   KArgs k = kargs(ws, c->lay, t, p);
   k.sig = sig;
   k.frame_counts = counts;
@@ -592,8 +600,26 @@ int of_detect_batch(const of_image* frames, int32_t n, const of_params* params, 
     k.det_rev = 0;
   }
   if (e == hipSuccess) e = launch_selection(k, *c, stream);
-  delete c;
   return e == hipSuccess ? OF_OK : hip_fail(e);
+}
+
+}  // namespace
+
+extern "C" {
+
+int of_detect_batch(const of_image* frames, int32_t n, const of_params* params, void* ws,
+                    size_t ws_bytes, of_keypoint* out, const int64_t* out_offset,
+                    int32_t cap_per_frame, int32_t* counts, const of_tuning* tuning,
+                    hipStream_t stream) {
+  Tune t;
+  int st = check_batch(frames, n, params, out, out_offset, cap_per_frame, counts, tuning, &t);
+  if (st) return st;
+  if (!ws) return OF_EINVAL;
+  std::lock_guard<std::mutex> lk(g_host.mu);
+  CallPlan* c = &g_host.c;
+  plan_call(frames, n, *params, t, c);
+  if ((size_t)c->lay.total > ws_bytes) return OF_ENOSPACE;
+  return detect_batch_planned(frames, n, *params, t, c, ws, out, out_offset, counts, stream);
 }
 
 int of_candidate_counts(const of_image* frames, int32_t n, const of_params* params,
@@ -601,11 +627,11 @@ int of_candidate_counts(const of_image* frames, int32_t n, const of_params* para
   int st = check_frames(frames, n, params);
   if (st) return st;
   if (!ws || !out) return OF_EINVAL;
-  CallPlan* c = new CallPlan;
+  std::lock_guard<std::mutex> lk(g_host.mu);
+  CallPlan* c = &g_host.c;
   plan_call(frames, n, *params, default_tune(*params), c);
   const int64_t off = c->lay.off_counters + 8 * (int64_t)c->lay.n_entries;
   const size_t bytes = 4 * (size_t)c->lay.n_entries;
-  delete c;
   hipError_t e = hipMemcpyAsync(out, (const uint8_t*)ws + off, bytes, hipMemcpyDeviceToDevice,
                                 stream);
   return e == hipSuccess ? OF_OK : hip_fail(e);
@@ -724,9 +750,10 @@ int of_describe(const of_image* frames, int32_t n, const of_params* params,
   Tune t;
   st = resolve_tune(tuning, *params, &t);
   if (st) return st;
-  CallPlan* c = new CallPlan;
+  std::lock_guard<std::mutex> lk(g_host.mu);
+  CallPlan* c = &g_host.c;
   plan_call(frames, n, *params, t, c);
-  PrologueArgs* pa = new PrologueArgs;
+  PrologueArgs* pa = &g_host.pa;
   fill_prologue(pa, frames, n, *params, t, const_cast<void*>(ws), c->lay,
                 const_cast<of_keypoint*>(kps), kp_offset, const_cast<int32_t*>(counts));
   DescArgs a;
@@ -744,8 +771,6 @@ int of_describe(const of_image* frames, int32_t n, const of_params* params,
   a.centres = centres;
   a.desc = desc;
   for (int f = 0; f < n; ++f) a.off[f] = kp_offset[f];
-  delete pa;
-  delete c;
   hipError_t e = launch_describe(a, stream);
   return e == hipSuccess ? OF_OK : hip_fail(e);
 }

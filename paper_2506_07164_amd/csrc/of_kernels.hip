@@ -883,37 +883,8 @@ __global__ __launch_bounds__(256, 5) void k_mark(KArgs a) {
       const uint32_t ty_a = resample_tap_r(oy + min(lane, ny - 1), P.base_h, H, rh);
       const uint32_t ty_b = ny > 64 ? resample_tap_r(oy + min(lane + 64, ny - 1), P.base_h, H, rh)
                                     : 0u;
-      // The window of the frame the tile's taps fall in (taps are monotone: the first and
-      // last column and row bound it).  When it fits the LDS left by the tile, it is
-      // staged with coalesced word loads and the taps are read from there; otherwise each
-      // tap pair is a 16-bit gather from the frame.
-      uint32_t sx_lo, sx_hi;
-      u16x2 unused_w;
-      col_tap(0, &sx_lo, &unused_w);
-      col_tap(nx - 1, &sx_hi, &unused_w);
-      sx_lo = (uint32_t)uniform((int)sx_lo) & ~3u;
-      sx_hi = (uint32_t)uniform((int)sx_hi) + 1u;
-      const int sy_lo = uniform((int)(__builtin_amdgcn_readlane((int)ty_a, 0) >> 9));
-      const int yl = (int)((uint32_t)__builtin_amdgcn_readlane(
-                               (int)(ny - 1 < 64 ? ty_a : ty_b), (ny - 1) & 63) >> 9);
-      const int sy_hi = uniform(min(yl + 1, bh1));
-      const int sp = (int)(((sx_hi - sx_lo) | 3u) + 1u);  // window row pitch, multiple of 4
-      const bool staged = sp * (sy_hi - sy_lo + 1) <= M.src_bytes;
-      uint8_t* win = smem + M.off_src;
-      if (staged) {
-        stage_all<12>(win, sp, base, bs, bw, (int)sx_lo, (int)sx_hi + 1, sy_lo, sy_hi + 1);
-        lds_barrier();
-      }
-      typedef uint16_t u16_lds_any __attribute__((aligned(1)));
-      // The rows of the tile, with the two horizontal taps of source row y at column x
-      // read from the window (S) or the frame: one loop per source, chosen once.
-      auto resample_rows = [&](auto staged_c) {
-      constexpr bool S = decltype(staged_c)::value;
       auto tap_pair = [&](int y, uint32_t x) -> uint32_t {
-        if constexpr (S)
-          return (uint32_t)*(const u16_lds_any*)(win + (y - sy_lo) * sp + (x - sx_lo));
-        else
-          return load_pair(base + ((uint32_t)(y * bs) + x));
+        return load_pair(base + ((uint32_t)(y * bs) + x));
       };
       for (int j0 = RPI * wave; j0 < ny; j0 += RPI * nwave) {
         uint32_t v[RPI][NC][2];
@@ -957,11 +928,6 @@ __global__ __launch_bounds__(256, 5) void k_mark(KArgs a) {
           pix[j * PITCH + hcol] = (uint8_t)blend_q8(hv0, hv1, hwx, wy);
         }
       }
-      };
-      if (staged)
-        resample_rows(std::integral_constant<bool, true>{});
-      else
-        resample_rows(std::integral_constant<bool, false>{});
     } else {
       const int limit = P.level == 0 ? W : P.lvl_stride;
       stage_all<8>(pix, PITCH, G(P.lvl), P.lvl_stride, limit, ox, ex, oy, ey);

@@ -434,11 +434,10 @@ OF_HD int32_t base_table_bytes(int32_t n_entries) {
 }
 
 // Segment-test tile: pixels (tile + 3-pixel halo, 4-aligned origin), the queue of
-// pixels that pass the compass pre-test, both bitmaps, and (launches only) a window of
-// the input frame that a resampled tile's taps fall in.
+// pixels that pass the compass pre-test and both bitmaps.
 struct MarkLds {
   int32_t tw, th, pitch, rows, qseg;
-  int32_t off_queue, off_bml, off_bmh, off_src, src_bytes, bytes;
+  int32_t off_queue, off_bml, off_bmh, bytes;
 };
 
 OF_HD MarkLds mark_lds(const Tune& t) {
@@ -454,21 +453,7 @@ OF_HD MarkLds mark_lds(const Tune& t) {
   m.off_queue = o;  o += align16(2 * 4 * m.qseg);
   m.off_bml = o;    o += 4 * m.th * 2 * t.mark_words;
   m.off_bmh = o;    o += 4 * m.th * 2 * t.mark_words;
-  m.off_src = align16(o);
-  m.src_bytes = 0;
-  m.bytes = m.off_src;
-  return m;
-}
-
-// The layout of a segment-test launch over n_entries (frame, level) pairs: the block's
-// LDS (with the entry table after it) is held to 32 KB so that 5 blocks share a compute
-// unit's 160 KB, and what the tile itself leaves of that is the input-frame window.
-constexpr int32_t kMarkLdsBudget = 32768 - 64;  // room for the static LDS variables
-OF_HD MarkLds mark_lds_launch(const Tune& t, int32_t n_entries) {
-  MarkLds m = mark_lds(t);
-  const int32_t room = kMarkLdsBudget - m.off_src - base_table_bytes(n_entries);
-  m.src_bytes = room > 0 ? (int32_t)((uint32_t)room & ~15u) : 0;
-  m.bytes = m.off_src + m.src_bytes;
+  m.bytes = align16(o);
   return m;
 }
 

@@ -438,8 +438,7 @@ hipError_t launch_mark(const KArgs& a, bool fused, int grid, hipStream_t) {
   CHECK(M.pitch == PITCH && M.th == a.t.mark_rows, "k_mark: layout of another tuning");
   const int64_t lds_bytes = M.bytes + base_table_bytes(a.n_entries);
   CHECK(lds_bytes <= 65536, "k_mark: %lld bytes of LDS", (long long)lds_bytes);
-  CHECK(M.src_bytes == 0 || lds_bytes + 64 <= 32768, "k_mark: %lld bytes of LDS do not let 5 "
-        "blocks share a compute unit", (long long)lds_bytes);
+
   if (a.entry < 0) {
     acc(a.counters, 12 * (int64_t)a.n_entries, "counters zeroed", true);
     acc(a.qctr + 2, 4, "Harris queue counter", true);
@@ -472,31 +471,6 @@ hipError_t launch_mark(const KArgs& a, bool fused, int grid, hipStream_t) {
           acc(P.base + (size_t)y1 * P.base_stride + xx, 2, "k_mark resample tap");
           CHECK((int64_t)y1 * P.base_stride + xx + 1 <= INT32_MAX, "k_mark: 32-bit tap offset");
         }
-      // the frame window the taps fall in, staged in LDS when it fits
-      {
-        auto colx = [&](int i) {
-          int xx = (int)(resample_tap(T.ox + std::min(i, nx - 1), P.base_w, W) >> 9);
-          return xx >= P.base_w - 1 ? P.base_w - 2 : xx;
-        };
-        const int sx_lo = colx(0) & ~3, sx_hi = colx(nx - 1) + 1;
-        const int sy_lo = (int)(resample_tap(T.oy, P.base_h, H) >> 9);
-        const int sy_hi = std::min((int)(resample_tap(T.oy + ny - 1, P.base_h, H) >> 9) + 1,
-                                   P.base_h - 1);
-        const int sp = ((sx_hi - sx_lo) | 3) + 1;
-        CHECK(sx_hi <= P.base_w - 1 && sy_hi <= P.base_h - 1 && sx_lo >= 0 && sy_lo >= 0,
-              "k_mark: frame window outside the frame");
-        if ((int64_t)sp * (sy_hi - sy_lo + 1) <= M.src_bytes) {
-          lds(M.off_src, (int64_t)sp * (sy_hi - sy_lo + 1), M.off_src, M.bytes, "k_mark window");
-          const int wnw = (sx_hi + 1 - sx_lo + 3) >> 2;
-          CHECK(4 * wnw <= sp, "k_mark: window words %d in pitch %d", wnw, sp);
-          for (int row : {sy_lo, sy_hi})
-            for (int w : {0, wnw - 1}) {
-              const int x = sx_lo + 4 * w, room = P.base_w - x;
-              const int back = room >= 4 ? 0 : 4 - room;
-              acc(P.base + (size_t)row * P.base_stride + x - back, 4, "k_mark window word");
-            }
-        }
-      }
       // the tile's own pixels to the level buffer
       for (int r : {T.y_t0, T.y_t1 - 1})
         acc(P.lvl_w + (size_t)r * P.lvl_stride + T.x_t0, T.x_t1 - T.x_t0, "k_mark level store",

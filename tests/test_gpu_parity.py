@@ -252,11 +252,11 @@ def test_equal_scores_across_cells(hip):
         assert_same_keypoints(run_plain(hip, img, kw), ref, "plain")
 
 
-@pytest.mark.parametrize("L", [1, 4])
-def test_fig6_pattern_frames(hip, L):
+@pytest.mark.parametrize("L,N", [(1, 4000), (4, 8000), (1, 2000), (4, 2000)])
+def test_fig6_pattern_frames(hip, L, N):
     from test_oracle_pins import _fig6_cases
     for case, pos, corner in _fig6_cases():
-        kw = _kw(n_levels=L, cell=0, fast_t_min=20, n_features=4000 if L == 1 else 8000)
+        kw = _kw(n_levels=L, cell=0, fast_t_min=20, n_features=N)
         log(f"case: fig6 {case} L={L}")
         img = fig6_pattern_image(pos)
         ref = oracle.detect(img, oracle.params(**kw))
@@ -451,6 +451,35 @@ def test_graph_replay(hip):
         res = det.results()
         for k, i in enumerate(pair):
             assert_same_keypoints(res[k], refs[i], f"replay {rep} slot {k}")
+        del x
+
+
+def test_graph_replay_sixteen_frames(hip):
+    """Sixteen copies of the 1080p 8-level frame in one call (more entries than the
+    arguments carry, so the kernels read the workspace's prefix tables), captured in a
+    HIP graph with its planning launch and replayed with eager work in between: every
+    frame of every replay equals the oracle."""
+    spec, kw = CONFIGS["c2"]["frames"][0], CONFIGS["c2"]["params"]
+    log("case: graph replay, 16 x 1080p in one call")
+    img = make_frame(spec)
+    ref = oracle.detect(img, oracle.params(**kw))
+    frames = [torch.from_numpy(img).cuda() for _ in range(16)]
+    det = hip.Detector([img.shape] * 16, hip.params(**kw))
+    det.detect_batch(frames)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    stream = torch.cuda.Stream()
+    with torch.cuda.stream(stream):
+        with torch.cuda.graph(g, stream=stream):
+            det.detect_batch(frames, stream=stream)
+    for rep in range(3):
+        det.counts.zero_()
+        x = torch.randn(1000, device="cuda").sum()
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        for i, r in enumerate(det.results()):
+            assert_same_keypoints(r, ref, f"replay {rep} frame {i}")
         del x
 
 
