@@ -157,6 +157,21 @@ int of_detect_batch(const of_image* frames, int32_t n, const of_params* params, 
                     int32_t cap_per_frame, int32_t* counts, const of_tuning* tuning,
                     hipStream_t stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid hipMalloc): of_detect_batch on the library's own
+ * static workspace of OF_SCRATCH_BYTES per device, held from the library's load until the
+ * process ends, instead of a caller workspace.  Same arguments, results and errors as
+ * of_detect_batch otherwise; OF_ENOSPACE when the batch needs a larger workspace than
+ * OF_SCRATCH_BYTES (of_workspace_size tells).  The call allocates nothing: no device
+ * memory, no host memory.  Every call on one device shares that device's workspace and
+ * leaves its contents to the next call, so calls that overlap on one device race: issue
+ * them on one stream, or order them.  A caller that owns the device can pass
+ * plan_resident = 1 to skip re-planning repeated calls of one shape. */
+#define OF_SCRATCH_BYTES (64 * 1024 * 1024)
+int of_detect_batch_scratch(const of_image* frames, int32_t n, const of_params* params,
+                            of_keypoint* out, const int64_t* out_offset, int32_t cap_per_frame,
+                            int32_t* counts, const of_tuning* tuning, hipStream_t stream);
+
 /* Host only.  The tuning of_detect_batch uses when given NULL (or zero fields). */
 int of_tuning_default(const of_image* frames, int32_t n, const of_params* params,
                       of_tuning* out);

@@ -622,6 +622,22 @@ int of_detect_batch(const of_image* frames, int32_t n, const of_params* params, 
   return detect_batch_planned(frames, n, *params, t, c, ws, out, out_offset, counts, stream);
 }
 
+int of_detect_batch_scratch(const of_image* frames, int32_t n, const of_params* params,
+                            of_keypoint* out, const int64_t* out_offset, int32_t cap_per_frame,
+                            int32_t* counts, const of_tuning* tuning, hipStream_t stream) {
+  Tune t;
+  int st = check_batch(frames, n, params, out, out_offset, cap_per_frame, counts, tuning, &t);
+  if (st) return st;
+  std::lock_guard<std::mutex> lk(g_host.mu);
+  CallPlan* c = &g_host.c;
+  plan_call(frames, n, *params, t, c);
+  if ((uint64_t)c->lay.total > (uint64_t)OF_SCRATCH_BYTES) return OF_ENOSPACE;
+  void* ws = nullptr;
+  const hipError_t e = scratch_workspace(&ws);
+  if (e != hipSuccess) return hip_fail(e);
+  return detect_batch_planned(frames, n, *params, t, c, ws, out, out_offset, counts, stream);
+}
+
 int of_candidate_counts(const of_image* frames, int32_t n, const of_params* params,
                         const void* ws, int32_t* out, hipStream_t stream) {
   int st = check_frames(frames, n, params);

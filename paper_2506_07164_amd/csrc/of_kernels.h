@@ -185,6 +185,11 @@ struct DescArgs {
 
 hipError_t launch_describe(const DescArgs& a, hipStream_t s);
 
+// Device address of this device's static workspace (OF_SCRATCH_BYTES), looked up once per
+// device.
+constexpr int kMaxDevices = 64;
+hipError_t scratch_workspace(void** ptr);
+
 // Levels of one ablation launch (in the kernel arguments).
 constexpr int kAbMaxLevels = 64;
 struct AbLevel {

@@ -16,6 +16,8 @@
 
 #include <hip/hip_ext.h>
 
+#include <mutex>
+
 #include "of_kernels.h"
 
 namespace ofk {
@@ -2325,6 +2327,33 @@ __global__ __launch_bounds__(256) void k_ab_harris_dense(AbArgs a) {
       }
     }
   }
+}
+
+// ------------------------------------------------------- static workspace --
+
+// The workspace of of_detect_batch_scratch: device memory of the library itself, for
+// callers that cannot allocate (code under graph capture, tight serving loops).  Each
+// device holds its own copy from the library's load until the process ends.  Host code
+// never passes the array's name to a kernel or a copy: the name is a host-side stand-in;
+// the device address comes from hipGetSymbolAddress, once per device.
+static __device__ __align__(256) uint8_t scratch[OF_SCRATCH_BYTES];
+
+hipError_t scratch_workspace(void** ptr) {
+  static std::mutex mu;
+  static void* addr[kMaxDevices] = {};
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lk(mu);
+  if (!addr[dev]) {
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));  // with device `dev` current
+    if (e != hipSuccess) return e;
+    addr[dev] = p;
+  }
+  *ptr = addr[dev];
+  return hipSuccess;
 }
 
 // Events attached to the next launch (profiling): recorded by the dispatch itself, so

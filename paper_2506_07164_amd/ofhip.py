@@ -73,6 +73,8 @@ def lib() -> ctypes.CDLL:
         L.of_detect.argtypes = [P(OfImage), P(OfParams), vp, ctypes.c_size_t, vp, i32, vp, vp]
         L.of_detect_batch.argtypes = [P(OfImage), i32, P(OfParams), vp, ctypes.c_size_t, vp,
                                       i64p, i32, vp, P(OfTuning), vp]
+        L.of_detect_batch_scratch.argtypes = [P(OfImage), i32, P(OfParams), vp, i64p, i32, vp,
+                                              P(OfTuning), vp]
         L.of_tuning_default.argtypes = [P(OfImage), i32, P(OfParams), P(OfTuning)]
         L.of_test_segment.argtypes = [vp, i32, i32, i32, vp, vp]
         L.of_candidate_counts.argtypes = [P(OfImage), i32, P(OfParams), vp, vp, vp]
@@ -168,6 +170,19 @@ def of_detect_batch(images, p: OfParams, ws_ptr: int, ws_bytes: int, out_ptr: in
                                  cap_per_frame, counts_ptr,
                                  ctypes.byref(tune) if tune is not None else None, stream),
            "of_detect_batch")
+
+
+OF_SCRATCH_BYTES = 64 * 1024 * 1024
+
+
+def of_detect_batch_scratch(images, p: OfParams, out_ptr: int, out_offsets, cap_per_frame: int,
+                            counts_ptr: int, tune: OfTuning | None, stream: int) -> None:
+    n = len(images)
+    arr = (OfImage * n)(*images)
+    offs = (ctypes.c_int64 * n)(*[int(o) for o in out_offsets])
+    _check(lib().of_detect_batch_scratch(arr, n, ctypes.byref(p), out_ptr, offs, cap_per_frame,
+                                         counts_ptr, ctypes.byref(tune) if tune is not None
+                                         else None, stream), "of_detect_batch_scratch")
 
 
 def of_candidate_counts(images, p: OfParams, ws_ptr: int, out_ptr: int, stream: int) -> None:

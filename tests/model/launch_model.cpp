@@ -790,6 +790,14 @@ int ablate_harris_blocks(int variant, int W, int H, int n) {
 }
 void set_launch_events(hipEvent_t, hipEvent_t) {}
 
+// The static workspace: a host buffer of the same size stands in for the device array.
+hipError_t scratch_workspace(void** ptr) {
+  static void* p = nullptr;
+  if (!p) p = dev_alloc(OF_SCRATCH_BYTES, "static workspace");
+  *ptr = p;
+  return hipSuccess;
+}
+
 }  // namespace ofk
 
 // ---------------------------------------------------- HIP runtime stand-ins --
@@ -1098,6 +1106,35 @@ static void run_scenario(const std::string& name) {
                      tune_of({{"mark_grid", 7}, {"det_grid", 3}, {"pyr_pass", 1}})})
         expect_ok(d.batch(t), "batch tuned");
     }
+  } else if (name == "scratch") {
+    // the static-workspace entry point: two calls in a row, the second smaller, then a
+    // batch too large for it (rejected before any launch)
+    const of_params p = params(8, 20, 7, 30, 2000);
+    for (int n : {3, 1}) {
+      std::vector<Frame> fr;
+      for (int i = 0; i < n; ++i) fr.push_back(make_frame(1920, 1080));
+      std::vector<of_image> im;
+      for (const Frame& f : fr) im.push_back({f.data, f.w, f.h, f.stride});
+      of_keypoint* out = (of_keypoint*)dev_alloc(sizeof(of_keypoint) * 2000 * n, "keypoints");
+      int32_t* counts = (int32_t*)dev_alloc(4 * n, "counts");
+      std::vector<int64_t> offs;
+      for (int i = 0; i < n; ++i) offs.push_back((int64_t)i * 2000);
+      of_tuning t = tuning();
+      expect_ok(of_detect_batch_scratch(im.data(), n, &p, out, offs.data(), 2000, counts, &t,
+                                        nullptr), "scratch call");
+      dev_free(out);
+      dev_free(counts);
+    }
+    std::vector<Frame> big;
+    for (int i = 0; i < 16; ++i) big.push_back(make_frame(1920, 1080));
+    std::vector<of_image> im;
+    for (const Frame& f : big) im.push_back({f.data, f.w, f.h, f.stride});
+    of_keypoint* out = (of_keypoint*)dev_alloc(sizeof(of_keypoint) * 2000 * 16, "keypoints");
+    int32_t* counts = (int32_t*)dev_alloc(4 * 16, "counts");
+    std::vector<int64_t> offs;
+    for (int i = 0; i < 16; ++i) offs.push_back((int64_t)i * 2000);
+    CHECK(of_detect_batch_scratch(im.data(), 16, &p, out, offs.data(), 2000, counts, nullptr,
+                                  nullptr) == OF_ENOSPACE, "scratch: oversized batch accepted");
   } else {
     fail("unknown scenario");
   }

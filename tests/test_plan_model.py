@@ -11,7 +11,8 @@ def test_segment_test_queue_holds_every_append():
     assert res.stdout.strip() == "ok 244"
 
 
-SCENARIOS = ["tuner_c2", "tuner_cell0", "tuner_c3", "bench_legs", "served", "test_shapes"]
+SCENARIOS = ["tuner_c2", "tuner_cell0", "tuner_c3", "bench_legs", "served", "test_shapes",
+             "scratch"]
 
 
 def test_launch_model_every_launch_in_bounds():
