@@ -781,6 +781,86 @@ __global__ __launch_bounds__(256) void k_pyramid_batch(KArgs a) {
 
 // ------------------------------------------------------------ segment test --
 
+// Resampled pixels of a segment-test tile, K adjacent output columns per lane: columns
+// [4, 4 + TW) of the tile (the 7 side columns are left to the caller).  The taps of K
+// adjacent output columns lie within 8 bytes of a frame row when (K - 1) * bw < 6 * W
+// (K = 4 below scale 2, K = 2 below scale 6), so one unaligned 64-bit load per source
+// row serves all K (moved back from the row's end where 8 bytes would pass it), and the
+// K resampled bytes go to LDS in one 32- or 16-bit store.  Each wave step covers R
+// tile rows (64 / (TW / K) lanes per row); RPI steps' loads are in flight at once.
+template <int K, int TW, int RPI>
+__device__ __forceinline__ void resample_groups(uint8_t* pix, int pitch, gptr<const uint8_t> base,
+                                                int bs, int bw, int bh1, int W, int ox, int nx,
+                                                int ny, uint32_t ty_a, uint32_t ty_b, double rw,
+                                                int lane, int wave) {
+  constexpr int G = TW / K;                // lane groups per tile row
+  constexpr int R = G <= 64 ? 64 / G : 1;  // tile rows per wave step
+  constexpr int C = G <= 64 ? 1 : G / 64;  // column groups per lane
+  typedef uint64_t u64_any_align __attribute__((aligned(1)));
+  const int r = G <= 64 ? lane / G : 0;
+  const int q0 = G <= 64 ? lane - r * G : lane;
+  uint32_t b[C], sh[C][K];
+  u16x2 wx[C][K];
+#pragma unroll
+  for (int c = 0; c < C; ++c) {
+    const int i0 = 4 + K * (q0 + 64 * c);
+    uint32_t x0[K];
+#pragma unroll
+    for (int m = 0; m < K; ++m) {
+      const uint32_t t = resample_tap_r(ox + min(i0 + m, nx - 1), bw, W, rw);
+      int xx = (int)(t >> 9), w = (int)(t & 511);
+      if (xx >= bw - 1) {
+        xx = bw - 2;
+        w = 256;
+      }
+      x0[m] = (uint32_t)xx;
+      wx[c][m] = pair16((uint32_t)(256 - w), (uint32_t)w);
+    }
+    b[c] = min(x0[0], (uint32_t)(bw - 8));
+#pragma unroll
+    for (int m = 0; m < K; ++m) sh[c][m] = 8u * (x0[m] - b[c]);
+  }
+  for (int j0 = R * RPI * wave; j0 < ny; j0 += R * RPI * 4) {
+    uint64_t v[RPI][C][2];
+    u16x2 wy[RPI];
+#pragma unroll
+    for (int h = 0; h < RPI; ++h) {
+      const int j = min(j0 + h * R + r, ny - 1);
+      const int ta = __shfl((int)ty_a, j & 63, 64), tb = __shfl((int)ty_b, j & 63, 64);
+      const uint32_t tyy = (uint32_t)(j < 64 ? ta : tb);
+      const int y0 = (int)(tyy >> 9);
+      wy[h] = pair16(256u - (tyy & 511u), tyy & 511u);
+      const uint32_t o0 = (uint32_t)(y0 * bs), o1 = (uint32_t)(min(y0 + 1, bh1) * bs);
+#pragma unroll
+      for (int c = 0; c < C; ++c) {
+        v[h][c][0] = *(gptr<const u64_any_align>)(base + (o0 + b[c]));
+        v[h][c][1] = *(gptr<const u64_any_align>)(base + (o1 + b[c]));
+      }
+    }
+#pragma unroll
+    for (int h = 0; h < RPI; ++h) {
+      const int j = j0 + h * R + r;
+      if (j >= ny) continue;
+#pragma unroll
+      for (int c = 0; c < C; ++c) {
+        uint32_t packed = 0;
+#pragma unroll
+        for (int m = 0; m < K; ++m) {
+          const uint32_t t = (uint32_t)(v[h][c][0] >> sh[c][m]) & 0xffffu;
+          const uint32_t u = (uint32_t)(v[h][c][1] >> sh[c][m]) & 0xffffu;
+          packed |= blend_q8(t, u, wx[c][m], wy[h]) << (8 * m);
+        }
+        uint8_t* dst = pix + j * pitch + 4 + K * (q0 + 64 * c);
+        if constexpr (K == 4)
+          *(uint32_t*)dst = packed;
+        else
+          *(uint16_t*)dst = (uint16_t)packed;
+      }
+    }
+  }
+}
+
+
 // One block per segment-test tile of 64*TWW x mark_rows level pixels.  TWW fixes the
 // LDS row pitch at compile time, so every circle and compass offset below is a
 // ds_read immediate.
@@ -868,6 +948,43 @@ __global__ __launch_bounds__(256, 5) void k_mark(KArgs a) {
         *x0 = (uint32_t)xx;
         *w = pair16((uint32_t)(256 - wx), (uint32_t)wx);  // (256 - wx, wx)
       };
+      const uint32_t ty_a = resample_tap_r(oy + min(lane, ny - 1), P.base_h, H, rh);
+      const uint32_t ty_b = ny > 64 ? resample_tap_r(oy + min(lane + 64, ny - 1), P.base_h, H, rh)
+                                    : 0u;
+      // Adjacent output columns whose taps share 8 bytes of a frame row: 4 below scale 2,
+      // 2 below scale 6 (one 64-bit load per source row for all of them), else one
+      // 16-bit gather per column and source row.
+      const int kgrp = 3 * bw < 6 * W ? 4 : (bw < 6 * W ? 2 : 1);
+      auto side_columns = [&]() {  // the left halo and the last 3 columns, by (row, column)
+        for (int t0 = 0; t0 < 7 * ny; t0 += kBlock) {
+          const int t = t0 + (int)threadIdx.x;
+          const int jr = t / 7, k = t - jr * 7;
+          const int j = min(jr, ny - 1);
+          const int ta = __shfl((int)ty_a, j & 63, 64), tb = __shfl((int)ty_b, j & 63, 64);
+          const int col = k < 4 ? k : TW + k;
+          if (jr < ny && col < nx) {
+            uint32_t x0;
+            u16x2 w;
+            col_tap(col, &x0, &w);
+            const uint32_t tyy = (uint32_t)(j < 64 ? ta : tb);
+            const int y0 = (int)(tyy >> 9);
+            const uint32_t v0 = load_pair(base + ((uint32_t)(y0 * bs) + x0));
+            const uint32_t v1 = load_pair(base + ((uint32_t)(min(y0 + 1, bh1) * bs) + x0));
+            pix[j * PITCH + col] = (uint8_t)blend_q8(v0, v1, w, pair16(256u - (tyy & 511u), tyy & 511u));
+          }
+        }
+      };
+      if (kgrp == 4) {
+        constexpr int G4 = TW / 4, R4 = G4 <= 64 ? 64 / G4 : 1;
+        resample_groups<4, TW, (R4 >= 4 ? 2 : (R4 == 2 ? 4 : 8))>(
+            pix, PITCH, base, bs, bw, bh1, W, ox, nx, ny, ty_a, ty_b, rw, lane, wave);
+        side_columns();
+      } else if (kgrp == 2) {
+        constexpr int G2 = TW / 2, R2 = G2 <= 64 ? 64 / G2 : 1, C2 = G2 <= 64 ? 1 : G2 / 64;
+        resample_groups<2, TW, (R2 * C2 >= 4 ? 2 : (R2 * C2 == 2 ? 4 : 8))>(
+            pix, PITCH, base, bs, bw, bh1, W, ox, nx, ny, ty_a, ty_b, rw, lane, wave);
+        side_columns();
+      } else {
       uint32_t cx[NC];
       u16x2 cwx[NC];
 #pragma unroll
@@ -882,9 +999,6 @@ __global__ __launch_bounds__(256, 5) void k_mark(KArgs a) {
       u16x2 hwx;
       col_tap(hcol, &hx, &hwx);
       const bool hlane = lane < 7 * RPI && hcol < nx;
-      const uint32_t ty_a = resample_tap_r(oy + min(lane, ny - 1), P.base_h, H, rh);
-      const uint32_t ty_b = ny > 64 ? resample_tap_r(oy + min(lane + 64, ny - 1), P.base_h, H, rh)
-                                    : 0u;
       auto tap_pair = [&](int y, uint32_t x) -> uint32_t {
         return load_pair(base + ((uint32_t)(y * bs) + x));
       };
@@ -929,6 +1043,7 @@ __global__ __launch_bounds__(256, 5) void k_mark(KArgs a) {
           const u16x2 wy = pair16(256u - (hty & 511u), hty & 511u);
           pix[j * PITCH + hcol] = (uint8_t)blend_q8(hv0, hv1, hwx, wy);
         }
+      }
       }
     } else {
       const int limit = P.level == 0 ? W : P.lvl_stride;

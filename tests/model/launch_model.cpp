@@ -471,6 +471,28 @@ hipError_t launch_mark(const KArgs& a, bool fused, int grid, hipStream_t) {
           acc(P.base + (size_t)y1 * P.base_stride + xx, 2, "k_mark resample tap");
           CHECK((int64_t)y1 * P.base_stride + xx + 1 <= INT32_MAX, "k_mark: 32-bit tap offset");
         }
+      // grouped taps: one 8-byte load per source row for 4 or 2 adjacent columns
+      const int kgrp = 3 * P.base_w < 6 * W ? 4 : (P.base_w < 6 * W ? 2 : 1);
+      if (kgrp > 1) {
+        CHECK(P.base_w >= 8, "k_mark: frame narrower than one 8-byte load");
+        for (int i0 : {4, 4 + TW - kgrp}) {
+          auto colx = [&](int i) {
+            int xx = (int)(resample_tap(T.ox + std::min(i, nx - 1), P.base_w, W) >> 9);
+            return xx >= P.base_w - 1 ? P.base_w - 2 : xx;
+          };
+          const int b = std::min(colx(i0), P.base_w - 8);
+          for (int m = 0; m < kgrp; ++m)
+            CHECK(colx(i0 + m) - b >= 0 && colx(i0 + m) - b <= 6,
+                  "k_mark: column tap %d bytes into an 8-byte load", colx(i0 + m) - b);
+          for (int j : {0, ny - 1}) {
+            const int y0 = (int)(resample_tap(T.oy + j, P.base_h, H) >> 9);
+            const int y1 = std::min(y0 + 1, P.base_h - 1);
+            acc(P.base + (size_t)y0 * P.base_stride + b, 8, "k_mark grouped taps");
+            acc(P.base + (size_t)y1 * P.base_stride + b, 8, "k_mark grouped taps");
+          }
+        }
+        lds((int64_t)(ny - 1) * PITCH + 4 + TW - kgrp, kgrp, 0, M.off_queue, "k_mark grouped store");
+      }
       // the tile's own pixels to the level buffer
       for (int r : {T.y_t0, T.y_t1 - 1})
         acc(P.lvl_w + (size_t)r * P.lvl_stride + T.x_t0, T.x_t1 - T.x_t0, "k_mark level store",
