@@ -45,6 +45,7 @@ OF_HD void fill_level_plan(LevelPlan& P, const PrologueArgs& a, uint8_t* ws, con
   P.frame = f;
   P.n_levels = L;
   P.cs = g.cs[l];
+  P.csd = fast_div((uint32_t)g.cs[l]);
   P.ncx = g.ncx[l];
   P.ncy = g.ncy[l];
   P.quota = g.quota[l];

@@ -1244,13 +1244,19 @@ __device__ __forceinline__ uint32_t bit_range(int a, int b) {
 // Candidate word: pixels x0 .. x0+31 of row y that are corners at the threshold of
 // their own cell (hi: fast_t; lo: fast_t_min, used where the cell has no fast_t
 // corner), restricted to the columns [xa, xb).
+// A 32-pixel span meets at most 5 cells of side >= 8.
 __device__ __forceinline__ uint32_t candidate_word(uint32_t lo, uint32_t hi, int x0, int xa,
-                                                   int xb, const uint8_t* frow, int cs) {
+                                                   int xb, const uint8_t* frow, int cs,
+                                                   const FastDiv& csd) {
   const int a = max(x0, xa), b = min(x0 + 32, xb);
   if (a >= b) return 0u;
   uint32_t fm = 0;  // pixels whose cell holds a fast_t corner
-  for (int c = a / cs; c * cs < b; ++c)
-    if (frow[c]) fm |= bit_range(max(c * cs, a) - x0, min(c * cs + cs, b) - x0);
+  const int c0 = (int)div_by((uint32_t)a, csd);
+#pragma unroll
+  for (int k = 0; k < 5; ++k) {
+    const int c = c0 + k;
+    if (c * cs < b && frow[c]) fm |= bit_range(max(c * cs, a) - x0, min(c * cs + cs, b) - x0);
+  }
   return (hi | (lo & ~fm)) & bit_range(a - x0, b - x0);
 }
 
@@ -1342,21 +1348,18 @@ __global__ __launch_bounds__(256, 4) void k_detect(KArgs a) {
       stage_begin(st, sx0, sx1, sy0, sy1);
       stage_issue(st, G(P.lvl), P.lvl_stride, limit, sx0, sy0);
       uint32_t vfl[2];
+      // no branches: an index past its region loads the region's last element, dropped
 #pragma unroll
       for (int u = 0; u < 2; ++u) {
         const int i = u * bd + tid;
-        vlo[u] = vhi[u] = vfl[u] = 0;
         vr[u] = i / nbw;
         vk[u] = i - vr[u] * nbw;
-        if (i < nunits) {
-          const size_t gi = (size_t)(ry0 + vr[u]) * P.wpr + bw0 + vk[u];
-          vlo[u] = glo[gi];
-          vhi[u] = ghi[gi];
-        }
-        if (i < nfl) {
-          const int r = i / nfx, k = i - r * nfx;
-          vfl[u] = gfl[(fcy0 + r) * P.ncx + fcx0 + k];
-        }
+        const int iu = min(i, nunits - 1), ru = iu / nbw;
+        const size_t gi = (size_t)(ry0 + ru) * P.wpr + bw0 + (iu - ru * nbw);
+        vlo[u] = glo[gi];
+        vhi[u] = ghi[gi];
+        const int jf = min(i, nfl - 1), rf = jf / nfx;
+        vfl[u] = gfl[(fcy0 + rf) * P.ncx + fcx0 + (jf - rf * nfx)];
       }
       stage_store(st, pix, D.pitch);
       stage_rest(st, pix, D.pitch, G(P.lvl), P.lvl_stride, limit, sx0, sy0);
@@ -1364,6 +1367,7 @@ __global__ __launch_bounds__(256, 4) void k_detect(KArgs a) {
       for (int u = 0; u < 2; ++u) {
         const int i = u * bd + tid;
         if (i < nfl) lfl[i] = (uint8_t)vfl[u];
+        if (i >= nunits) vlo[u] = vhi[u] = 0;
       }
       for (int i = 2 * bd + tid; i < nfl; i += bd) {
         const int r = i / nfx, k = i - r * nfx;
@@ -1401,7 +1405,8 @@ __global__ __launch_bounds__(256, 4) void k_detect(KArgs a) {
         const int y = ry0 + vr[u];
         if (y >= B && y < H - B)
           cwr[u] = candidate_word(vlo[u], vhi[u], (bw0 + vk[u]) << 5, xa, xb,
-                                  lfl + (y / cs - fcy0) * nfx - fcx0, cs);
+                                  lfl + ((int)div_by((uint32_t)y, P.csd) - fcy0) * nfx - fcx0,
+                                  cs, P.csd);
         cw[i] = cwr[u];
         ucnt[i] = (uint32_t)__popc(cwr[u]);
       }
@@ -1413,7 +1418,8 @@ __global__ __launch_bounds__(256, 4) void k_detect(KArgs a) {
       if (y >= B && y < H - B) {
         const size_t gi = (size_t)y * P.wpr + bw0 + k;
         c = candidate_word(glo[gi], ghi[gi], (bw0 + k) << 5, xa, xb,
-                           lfl + (y / cs - fcy0) * nfx - fcx0, cs);
+                           lfl + ((int)div_by((uint32_t)y, P.csd) - fcy0) * nfx - fcx0, cs,
+                           P.csd);
       }
       cw[i] = c;
       ucnt[i] = (uint32_t)__popc(c);
@@ -1529,7 +1535,9 @@ __global__ __launch_bounds__(256, 4) void k_detect(KArgs a) {
       }
       if (alive) {
         const int si = atomicAdd(&s_ns, 1);
-        const int c = multi ? (y / cs - cya) * nlcx + (x / cs - cxa) : 0;
+        const int c = multi ? ((int)div_by((uint32_t)y, P.csd) - cya) * nlcx +
+                                  ((int)div_by((uint32_t)x, P.csd) - cxa)
+                            : 0;
         sci[si] = (uint16_t)ci;
         if (multi) scell[si] = (uint16_t)c;
         if (best1) atomicMax((long long*)&cbest[c], (long long)R);
@@ -1608,7 +1616,8 @@ __global__ __launch_bounds__(256, 4) void k_detect(KArgs a) {
           int slot;
           if (h.cell > 0) {
             const int r = (int)atomicAdd(&ckept[c], 1u);
-            slot = ((y / cs - P.det_y0) * nvx + (x / cs - P.det_x0)) * P.kslot + r;
+            slot = (((int)div_by((uint32_t)y, P.csd) - P.det_y0) * nvx +
+                    ((int)div_by((uint32_t)x, P.csd) - P.det_x0)) * P.kslot + r;
           } else if (P.compact) {  // listed here, appended below
             order[atomicAdd(&s_ne, 1)] = (uint16_t)s;
             continue;

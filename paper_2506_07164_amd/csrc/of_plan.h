@@ -53,6 +53,30 @@ OF_HD int32_t band_rows(int32_t mark_ty, int32_t rot, int32_t k) {
   return band_row0(mark_ty, rot, k + 1) - band_row0(mark_ty, rot, k);
 }
 
+// Division of small non-negative numerators by a divisor fixed for a whole tile:
+// q = n / d as a multiply-high by m = ceil(2^32 / d) (the low 32 bits of it; d = 1, whose
+// m is 2^32, adds n itself).  Exact for n * d < 2^32, which every use here satisfies
+// (numerators and divisors below 2^16).
+struct FastDiv {
+  uint32_t mlo, one;  // one = 0xffffffff when d == 1
+};
+
+OF_HD FastDiv fast_div(uint32_t d) {
+  const uint64_t m = ((1ull << 32) + d - 1) / d;
+  FastDiv f;
+  f.mlo = (uint32_t)m;
+  f.one = d == 1 ? 0xffffffffu : 0u;
+  return f;
+}
+
+OF_HD uint32_t div_by(uint32_t n, const FastDiv& f) {
+#ifdef __HIP_DEVICE_COMPILE__
+  return __umulhi(n, f.mlo) + (n & f.one);
+#else
+  return (uint32_t)(((uint64_t)n * f.mlo) >> 32) + (n & f.one);
+#endif
+}
+
 // One ranked candidate: R' and (y << 16 | x) in level coordinates.
 struct Cand {
   int64_t score;
@@ -64,6 +88,7 @@ struct Cand {
 struct LevelPlan {
   int32_t W, H, B, level, frame, n_levels;
   int32_t cs, ncx, ncy;        // cell side (whole level when cell == 0) and cell grid
+  FastDiv csd;                 // division by cs
   int32_t quota, kcell;
   int32_t fast_t, fast_t_min;
   const uint8_t* base;         // input frame
