@@ -224,6 +224,8 @@ int of_describe(const of_image* frames, int32_t n, const of_params* params,
  *   OF_AB_FAST_MASKS_LDS    the same reading 64 x 16 tiles staged in LDS
  *   OF_AB_FAST_MINMAX_LDS   the production scheme: LDS tiles, exact compass pre-test as a
  *                           wave-wide early-out, min/max windows
+ *   OF_AB_FAST_MASKS_PRETEST_LDS  LDS tiles and the same compass pre-test, then the masks
+ *                           and shift-and test of OF_AB_FAST_MASKS instead of min/max
  * outs[i] (device, width * height bytes, row pitch = width) gets 1 for corners of the
  * region x, y in [border, size - border) and 0 elsewhere.  border >= 3, 1 <= t <= 255.
  *
@@ -232,7 +234,7 @@ int of_describe(const of_image* frames, int32_t n, const of_params* params,
  * of level i (device):
  *   OF_AB_HARRIS_2D          one thread per position, 2D Sobel at each window pixel
  *   OF_AB_HARRIS_SEPARABLE   one thread per position, separable Sobel row by row (Eq. 4)
- *   OF_AB_HARRIS_GROUPS      8 lanes per position, one window row each (production)
+ *   OF_AB_HARRIS_GROUPS      8 lanes per position, one window row each
  * outs[i][k] (device int64) gets R', or 0 when x or y is closer than 4 to the border.
  *   OF_AB_HARRIS_DENSE_SLIDING  R' at every pixel by sliding column and row sums (the
  *                           structure of Alg. 3); pos and counts are ignored (may be NULL)
@@ -242,6 +244,7 @@ int of_describe(const of_image* frames, int32_t n, const of_params* params,
 #define OF_AB_FAST_MASKS 1
 #define OF_AB_FAST_MASKS_LDS 2
 #define OF_AB_FAST_MINMAX_LDS 3
+#define OF_AB_FAST_MASKS_PRETEST_LDS 4
 #define OF_AB_HARRIS_2D 0
 #define OF_AB_HARRIS_SEPARABLE 1
 #define OF_AB_HARRIS_GROUPS 2

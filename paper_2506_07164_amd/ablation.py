@@ -19,6 +19,7 @@ from . import ofhip
 
 FAST_LADDER = [("branchy, global reads", "branchy"), ("bit masks, global reads", "masks"),
                ("bit masks, LDS tile", "masks_lds"),
+               ("LDS tile + compass pre-test + bit masks", "masks_pretest_lds"),
                ("LDS tile + compass pre-test + min/max windows", "minmax_lds")]
 HARRIS_LADDER = [("2D Sobel, thread per candidate", "2d"),
                  ("separable Sobel, thread per candidate", "separable"),

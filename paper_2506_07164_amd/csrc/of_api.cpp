@@ -646,10 +646,8 @@ int of_candidate_counts(const of_image* frames, int32_t n, const of_params* para
   std::lock_guard<std::mutex> lk(g_host.mu);
   CallPlan* c = &g_host.c;
   plan_call(frames, n, *params, default_tune(*params), c);
-  const int64_t off = c->lay.off_counters + 8 * (int64_t)c->lay.n_entries;
-  const size_t bytes = 4 * (size_t)c->lay.n_entries;
-  hipError_t e = hipMemcpyAsync(out, (const uint8_t*)ws + off, bytes, hipMemcpyDeviceToDevice,
-                                stream);
+  const uint32_t* counters = (const uint32_t*)((const uint8_t*)ws + c->lay.off_counters);
+  hipError_t e = launch_sum_fast_counts(counters, c->lay.n_entries, out, stream);
   return e == hipSuccess ? OF_OK : hip_fail(e);
 }
 
@@ -661,7 +659,7 @@ static bool ab_level_ok(const of_image& L) {
 int of_ablate_fast(const of_image* levels, int32_t n, int32_t t, int32_t border,
                    int32_t variant, uint8_t* const* outs, hipStream_t stream) {
   if (!levels || !outs || n < 1 || n > kAbMaxLevels) return OF_EINVAL;
-  if (t < 1 || t > 255 || border < 3 || variant < 0 || variant > OF_AB_FAST_MINMAX_LDS)
+  if (t < 1 || t > 255 || border < 3 || variant < 0 || variant > OF_AB_FAST_MASKS_PRETEST_LDS)
     return OF_EINVAL;
   AbArgs a;
   memset(&a, 0, sizeof(a));

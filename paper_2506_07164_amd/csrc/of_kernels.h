@@ -70,14 +70,16 @@ OF_HD void fill_level_plan(LevelPlan& P, const PrologueArgs& a, uint8_t* ws, con
   P.bm_hi = P.bm_lo + (int64_t)s.wpr * P.H;
   P.flags = ws + a.lay.off_flags + o.flag;
   P.cand = (Cand*)(ws + a.lay.off_cand) + o.cand;
+  const int32_t cstride = count_stride(a.lay.n_entries);
   P.cand_count = o.counters + i;
+  P.count_stride = cstride;
   P.cand_cap = (int32_t)s.cand_cap;
   P.kslot = s.kslot;
   P.compact = a.p.cell == 0 && s.cand_cap > kRankCap;
   P.slot_w = s.slot_w;
   P.sel = (Cand*)(ws + a.lay.off_sel) + o.sel;
-  P.sel_count = o.counters + a.lay.n_entries + i;
-  P.ncand_count = o.counters + 2 * a.lay.n_entries + i;
+  P.sel_count = o.counters + 2 * (int64_t)kCountSpread * cstride + i;
+  P.ncand_count = o.counters + (int64_t)kCountSpread * cstride + i;
   P.mark_tx = s.mark_tx;
   P.mark_ty = s.mark_ty;
   P.band_rot = o.band_rot;
@@ -118,7 +120,7 @@ struct KArgs {
   DetLds dl;
   // The state each call leaves zeroed for the next: k_mark clears the counters, the
   // selection clears the cell flags and the segment-test queue counter.
-  uint32_t* counters;          // 3 per entry
+  uint32_t* counters;          // counter_words(n_entries)
   uint8_t* flags;
   int64_t flag_bytes;          // multiple of 16
   int32_t* frame_counts;
@@ -166,6 +168,8 @@ hipError_t launch_pyramid_batch(const KArgs& a, int blocks, hipStream_t s);
 hipError_t launch_mark(const KArgs& a, bool fused, int grid, hipStream_t s);
 hipError_t launch_detect(const KArgs& a, int grid, hipStream_t s);
 hipError_t launch_scale_counters(const KArgs& a, int times, hipStream_t s);
+// out[e] = the FAST candidates of entry e (the sum of its sub-counters), n entries.
+hipError_t launch_sum_fast_counts(const uint32_t* counters, int n, int32_t* out, hipStream_t s);
 hipError_t launch_select_orient(const KArgs& a, int slots, hipStream_t s);
 hipError_t launch_select(const KArgs& a, int grid, hipStream_t s);
 hipError_t launch_orient(const KArgs& a, int grid, hipStream_t s);

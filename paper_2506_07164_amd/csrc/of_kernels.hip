@@ -103,6 +103,20 @@ __device__ __forceinline__ uint32_t lanes_below(uint64_t m) {
 
 __device__ __forceinline__ int uniform(int v) { return __builtin_amdgcn_readfirstlane(v); }
 
+// Per-level counters spread over kCountSpread sub-counters (see kCountSpread).
+__device__ __forceinline__ void count_add(uint32_t* c, int stride, uint32_t v) {
+  atomicAdd(c + (int)(blockIdx.x % (unsigned)kCountSpread) * stride, v);
+}
+__device__ __forceinline__ uint32_t count_sum(gptr<const uint32_t> c, int stride) {
+  uint32_t v[kCountSpread];
+#pragma unroll
+  for (int k = 0; k < kCountSpread; ++k) v[k] = c[k * stride];
+  uint32_t t = 0;
+#pragma unroll
+  for (int k = 0; k < kCountSpread; ++k) t += v[k];
+  return t;
+}
+
 // Ranking order: higher R' first; equal R' -> smaller y, then smaller x (pos = y<<16|x).
 __device__ __forceinline__ bool better(int64_t sa, uint32_t pa, int64_t sb, uint32_t pb) {
   return sa > sb || (sa == sb && pa < pb);
@@ -321,6 +335,10 @@ __device__ __forceinline__ uint32_t load_pair(gptr<const uint8_t> p) {
 // pass into registers and stage_store writes it to LDS (then loads and stores any
 // further passes), so that a caller can issue other loads in between and wait for all
 // of them at once: a tile of up to U * kBlock words costs one round trip to memory.
+// s_waitcnt operand (gfx9 encoding) that waits for every vector memory operation of the
+// wave: vmcnt 0, expcnt and lgkmcnt at their maxima (no wait).
+constexpr int kWaitVmem = 0x0F70;
+
 template <int U>
 struct Stage {
   uint32_t v[U];
@@ -330,9 +348,11 @@ struct Stage {
 
 // Words i = i0 + u * kBlock + threadIdx.x of a pass: (row, word) advanced by (drow, dw)
 // per kBlock words, so only the first needs a division.  Every load is issued without a
-// branch (a word past the region re-reads its first word and is dropped), so the U loads
-// of a pass are all in flight before the first wait; a caller can issue other loads
-// between stage_issue and stage_store and wait for all of them at once.
+// branch, so the U loads of a pass are all in flight before the first wait (a caller can
+// issue other loads between stage_issue and stage_store and wait for all of them at
+// once).  A word past the region re-reads the region's first word and is dropped;
+// stage_store waits for every load of the pass, dropped ones included, so that none is
+// still in flight when its register is next written in a later step.
 template <int U>
 __device__ __forceinline__ void stage_begin(Stage<U>& st, int x0, int x1, int y0, int y1) {
   st.nw = (x1 - x0 + 3) >> 2;
@@ -380,6 +400,7 @@ __device__ __forceinline__ void stage_store(Stage<U>& st, uint8_t* lds, int lp) 
       ++row;
     }
   }
+  __builtin_amdgcn_s_waitcnt(kWaitVmem);  // the dropped loads too
   st.row = row;
   st.w = w;
   st.i0 += U * kBlock;
@@ -431,32 +452,74 @@ __device__ __forceinline__ void harris_row_words(const uint8_t* row, int s, int 
   }
 }
 
-__device__ __forceinline__ int64_t harris_point(const uint8_t* pix, int P, int cx, int cy) {
+// Sums of G_x^2, G_y^2 and G_x G_y over window rows w0 .. w0 + nr - 1 (0 .. 6 from the
+// top) of the 7x7 window at LDS pixel (cx, cy); NR >= nr rows are unrolled.
+template <int NR>
+__device__ __forceinline__ void harris_part(const uint8_t* pix, int P, int cx, int cy, int w0,
+                                            int nr, int& sxx, int& syy, int& sxy) {
   const int a = cx - 4, s = a & 3;
-  const uint8_t* row = pix + (cy - 4) * P + (a - s);
+  const uint8_t* row = pix + (cy - 4 + w0) * P + (a - s);
   int hd0[7], hs0[7], hd1[7], hs1[7];
   harris_row_words(row, s, hd0, hs0);
   harris_row_words(row + P, s, hd1, hs1);
-  int sxx = 0, syy = 0, sxy = 0;
+  sxx = syy = sxy = 0;
 #pragma unroll
-  for (int r = 2; r < 9; ++r) {
-    int hd2[7], hs2[7];
-    harris_row_words(row + r * P, s, hd2, hs2);
+  for (int r = 0; r < NR; ++r) {
+    if (r < nr) {
+      int hd2[7], hs2[7];
+      harris_row_words(row + (r + 2) * P, s, hd2, hs2);
 #pragma unroll
-    for (int c = 0; c < 7; ++c) {
-      const int gx = hd0[c] + 2 * hd1[c] + hd2[c];
-      const int gy = hs2[c] - hs0[c];
-      sxx += gx * gx;
-      syy += gy * gy;
-      sxy += gx * gy;
-      hd0[c] = hd1[c];
-      hd1[c] = hd2[c];
-      hs0[c] = hs1[c];
-      hs1[c] = hs2[c];
+      for (int c = 0; c < 7; ++c) {
+        const int gx = hd0[c] + 2 * hd1[c] + hd2[c];
+        const int gy = hs2[c] - hs0[c];
+        sxx += gx * gx;
+        syy += gy * gy;
+        sxy += gx * gy;
+        hd0[c] = hd1[c];
+        hd1[c] = hd2[c];
+        hs0[c] = hs1[c];
+        hs1[c] = hs2[c];
+      }
     }
   }
+}
+
+__device__ __forceinline__ int64_t harris_r(int sxx, int syy, int sxy) {
   const int64_t A = sxx, B = syy, C = sxy;
   return 25 * (A * B - C * C) - (A + B) * (A + B);
+}
+
+// Out of line: the rare path (candidates past the tile's score cache) has one copy, not
+// one per call site, so the tile kernel's hot code stays compact.
+__device__ __noinline__ int64_t harris_point(const uint8_t* pix, int P, int cx, int cy) {
+  int sxx, syy, sxy;
+  harris_part<7>(pix, P, cx, cy, 0, 7, sxx, syy, sxy);
+  return harris_r(sxx, syy, sxy);
+}
+
+// R' of the n cached candidates (positions y << 16 | x, pixels staged from (sx0, sy0)),
+// 2^lg adjacent lanes per candidate, each taking ceil(7 / 2^lg) window rows; the partial
+// sums are added across the group.  Few candidates per tile: more lanes each, so that
+// the step's latency is a few window rows rather than the whole window.  One code path
+// for every group size (rows past a lane's share are skipped by uniform branches where
+// no lane of the wave needs them), so that it stays in the instruction cache.
+__device__ __forceinline__ void harris_cache(const uint8_t* pix, int P, const uint32_t* cpos,
+                                             int64_t* crs, int n, int sx0, int sy0, int lg) {
+  const int G = 1 << lg, nr_max = (7 + G - 1) >> lg;
+  for (int i = (int)threadIdx.x; i < (n << lg); i += kBlock) {
+    const int c = i >> lg, j = i & (G - 1);
+    const uint32_t ps = cpos[c];
+    const int w0 = j * nr_max, nr = min(nr_max, 7 - w0);
+    int sxx, syy, sxy;
+    harris_part<7>(pix, P, (int)(ps & 0xffff) - sx0, (int)(ps >> 16) - sy0, w0, nr, sxx, syy,
+                   sxy);
+    for (int o = 1; o < G; o <<= 1) {
+      sxx += __shfl_xor(sxx, o, 64);
+      syy += __shfl_xor(syy, o, 64);
+      sxy += __shfl_xor(sxy, o, 64);
+    }
+    if (j == 0) crs[c] = harris_r(sxx, syy, sxy);
+  }
 }
 
 // Block barrier that orders LDS accesses only.  __syncthreads() also waits for the
@@ -596,7 +659,7 @@ __global__ __launch_bounds__(1024) void k_prologue(PrologueArgs a) {
   uint64_t* sig = (uint64_t*)(ws + a.lay.off_hdr + 128);
   {
     uint32_t* counters = (uint32_t*)(ws + a.lay.off_counters);
-    const int64_t ncnt = 3 * (int64_t)a.lay.n_entries;
+    const int64_t ncnt = counter_words(a.lay.n_entries);
     uint4* fl = (uint4*)(ws + a.lay.off_flags);
     const int64_t nq = a.lay.flag_bytes / 16;
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
@@ -885,7 +948,8 @@ __global__ __launch_bounds__(256, 5) void k_mark(KArgs a) {
   // the frames that its tiles resample from.
   const uint64_t wsig = *(cptr<uint64_t>)h.ws_sig;  // compared before the plan's pointers are used
   if (h.entry < 0 && blockIdx.x == 0) {  // counters of this call (read after this kernel)
-    for (int i = threadIdx.x; i < 3 * h.n_entries; i += kBlock) G(h.counters)[i] = 0u;
+    const int ncnt = (int)counter_words(h.n_entries);
+    for (int i = threadIdx.x; i < ncnt; i += kBlock) G(h.counters)[i] = 0u;
     if (threadIdx.x == 0) G(h.qctr)[2] = 0u;
   }
   if (h.entry < 0 && !h.small)
@@ -1241,25 +1305,6 @@ __device__ __forceinline__ uint32_t bit_range(int a, int b) {
   return a >= 32 ? 0u : hi & ~((1u << a) - 1u);
 }
 
-// Candidate word: pixels x0 .. x0+31 of row y that are corners at the threshold of
-// their own cell (hi: fast_t; lo: fast_t_min, used where the cell has no fast_t
-// corner), restricted to the columns [xa, xb).
-// A 32-pixel span meets at most 5 cells of side >= 8.
-__device__ __forceinline__ uint32_t candidate_word(uint32_t lo, uint32_t hi, int x0, int xa,
-                                                   int xb, const uint8_t* frow, int cs,
-                                                   const FastDiv& csd) {
-  const int a = max(x0, xa), b = min(x0 + 32, xb);
-  if (a >= b) return 0u;
-  uint32_t fm = 0;  // pixels whose cell holds a fast_t corner
-  const int c0 = (int)div_by((uint32_t)a, csd);
-#pragma unroll
-  for (int k = 0; k < 5; ++k) {
-    const int c = c0 + k;
-    if (c * cs < b && frow[c]) fm |= bit_range(max(c * cs, a) - x0, min(c * cs + cs, b) - x0);
-  }
-  return (hi | (lo & ~fm)) & bit_range(a - x0, b - x0);
-}
-
 // One block per Harris/NMS tile (whole cells, or det_w x det_h pixels when the level is
 // one cell).  Candidates of the tile and a 1-pixel ring are found word-parallel from
 // the segment-test bitmaps, scored with Harris from LDS, suppressed against their
@@ -1290,6 +1335,7 @@ __global__ __launch_bounds__(256, 4) void k_detect(KArgs a) {
   int64_t* cbest = (int64_t*)(smem + D.off_cbest);
   uint32_t* cwin = (uint32_t*)(smem + D.off_cwin);
   uint8_t* lfl = smem + D.off_lfl;
+  uint32_t* fmt = (uint32_t*)(smem + D.off_fm);  // candidate-word masks per flag row and word
   int32_t* s_base = (int32_t*)(smem + D.bytes);
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nwave = kBlock >> 6;
   const int bd = (int)kBlock, tid = (int)threadIdx.x;
@@ -1335,18 +1381,16 @@ __global__ __launch_bounds__(256, 4) void k_detect(KArgs a) {
     const int nvx = P.det_xend - P.det_x0;
     const int nbx = (vx1 - vx0 + 1) >> 1, nby = (vy1 - vy0 + 1) >> 1;  // 2x2 blocks
 
-    // 1. one batch of independent loads: the thread's bitmap words (kept in registers),
-    //    cell flags and pixels
+    // 1. loads: the thread's bitmap words (kept in registers) and the cell flags first,
+    //    then the tile's pixels, which stay in flight through the candidate words
     gptr<const uint32_t> glo = G((const uint32_t*)P.bm_lo), ghi = G((const uint32_t*)P.bm_hi);
     uint32_t vlo[2], vhi[2];
     int vr[2], vk[2];
+    const int limit = P.level == 0 ? W : P.lvl_stride;
+    Stage<10> st;
     {
       gptr<const uint8_t> gfl = G((const uint8_t*)P.flags);
       const int nfl = nfx * nfy;
-      const int limit = P.level == 0 ? W : P.lvl_stride;
-      Stage<10> st;
-      stage_begin(st, sx0, sx1, sy0, sy1);
-      stage_issue(st, G(P.lvl), P.lvl_stride, limit, sx0, sy0);
       uint32_t vfl[2];
       // no branches: an index past its region loads the region's last element, dropped
 #pragma unroll
@@ -1361,8 +1405,8 @@ __global__ __launch_bounds__(256, 4) void k_detect(KArgs a) {
         const int jf = min(i, nfl - 1), rf = jf / nfx;
         vfl[u] = gfl[(fcy0 + rf) * P.ncx + fcx0 + (jf - rf * nfx)];
       }
-      stage_store(st, pix, D.pitch);
-      stage_rest(st, pix, D.pitch, G(P.lvl), P.lvl_stride, limit, sx0, sy0);
+      stage_begin(st, sx0, sx1, sy0, sy1);
+      stage_issue(st, G(P.lvl), P.lvl_stride, limit, sx0, sy0);
 #pragma unroll
       for (int u = 0; u < 2; ++u) {
         const int i = u * bd + tid;
@@ -1394,33 +1438,50 @@ __global__ __launch_bounds__(256, 4) void k_detect(KArgs a) {
     }
     lds_barrier();
 
-    // 2. candidate words, 32 pixels per thread and step, and their counts
+    // 2. candidate words, 32 pixels per thread and step, and their counts.  A pixel is a
+    //    candidate at the threshold of its own cell: fast_t where the cell holds a fast_t
+    //    corner, else fast_t_min.  Per flag row and word column of the tile, the table
+    //    holds the word's columns inside [xa, xb) (hi bitmap) and those of them in cells
+    //    without a fast_t corner (lo bitmap); a 32-pixel span meets at most 5 cells.
     const int xa = max(rx0, B), xb = min(rx0 + rw, W - B);
+    for (int i = tid; i < nfy * nbw; i += bd) {
+      const int fr = i / nbw, k = i - fr * nbw;
+      const int x0 = (bw0 + k) << 5;
+      const int a0 = max(x0, xa), b0 = min(x0 + 32, xb);
+      uint32_t valid = 0, fm = 0;
+      if (a0 < b0) {
+        valid = bit_range(a0 - x0, b0 - x0);
+        const int c0 = (int)div_by((uint32_t)a0, P.csd);
+#pragma unroll
+        for (int q = 0; q < 5; ++q) {
+          const int c = c0 + q, ca = max(c * cs, a0), cb = min(c * cs + cs, b0);
+          if (ca < cb && lfl[fr * nfx + c - fcx0]) fm |= bit_range(ca - x0, cb - x0);
+        }
+      }
+      fmt[2 * i] = valid;
+      fmt[2 * i + 1] = valid & ~fm;
+    }
+    lds_barrier();
+    auto cand_word = [&](uint32_t lo, uint32_t hi, int y, int k) -> uint32_t {
+      if (y < B || y >= H - B) return 0u;
+      const uint32_t* m = fmt + 2 * (((int)div_by((uint32_t)y, P.csd) - fcy0) * nbw + k);
+      return (hi & m[0]) | (lo & m[1]);
+    };
     uint32_t cwr[2];
 #pragma unroll
     for (int u = 0; u < 2; ++u) {
       const int i = u * bd + tid;
       cwr[u] = 0;
       if (i < nunits) {
-        const int y = ry0 + vr[u];
-        if (y >= B && y < H - B)
-          cwr[u] = candidate_word(vlo[u], vhi[u], (bw0 + vk[u]) << 5, xa, xb,
-                                  lfl + ((int)div_by((uint32_t)y, P.csd) - fcy0) * nfx - fcx0,
-                                  cs, P.csd);
+        cwr[u] = cand_word(vlo[u], vhi[u], ry0 + vr[u], vk[u]);
         cw[i] = cwr[u];
         ucnt[i] = (uint32_t)__popc(cwr[u]);
       }
     }
     for (int i = 2 * bd + tid; i < nunits; i += bd) {
       const int r = i / nbw, k = i - r * nbw;
-      const int y = ry0 + r;
-      uint32_t c = 0;
-      if (y >= B && y < H - B) {
-        const size_t gi = (size_t)y * P.wpr + bw0 + k;
-        c = candidate_word(glo[gi], ghi[gi], (bw0 + k) << 5, xa, xb,
-                           lfl + ((int)div_by((uint32_t)y, P.csd) - fcy0) * nfx - fcx0, cs,
-                           P.csd);
-      }
+      const size_t gi = (size_t)(ry0 + r) * P.wpr + bw0 + k;
+      const uint32_t c = cand_word(glo[gi], ghi[gi], ry0 + r, k);
       cw[i] = c;
       ucnt[i] = (uint32_t)__popc(c);
     }
@@ -1476,12 +1537,12 @@ __global__ __launch_bounds__(256, 4) void k_detect(KArgs a) {
       const uint32_t yx = ((uint32_t)(ry0 + r) << 16) | (uint32_t)((bw0 + k) << 5);
       for (; m && idx < (uint32_t)kCandCache; m &= m - 1u) cpos[idx++] = yx + __builtin_ctz(m);
     }
+    stage_store(st, pix, D.pitch);
+    stage_rest(st, pix, D.pitch, G(P.lvl), P.lvl_stride, limit, sx0, sy0);
     lds_barrier();
     const int ncache = min(ncand, kCandCache);
-    for (int c = tid; c < ncache; c += bd) {
-      const uint32_t ps = cpos[c];
-      crs[c] = harris_point(pix, D.pitch, (int)(ps & 0xffff) - sx0, (int)(ps >> 16) - sy0);
-    }
+    harris_cache(pix, D.pitch, cpos, crs, ncache, sx0, sy0,
+                 ncache <= kBlock / 8 ? 3 : (ncache <= kBlock / 4 ? 2 : (ncache <= kBlock / 2 ? 1 : 0)));
     lds_barrier();
 
     // Position and R' of candidate ci (raster order); beyond the cache the position is
@@ -1545,7 +1606,7 @@ __global__ __launch_bounds__(256, 4) void k_detect(KArgs a) {
     }
     lds_barrier();
     const int ns = s_ns;
-    if (tid == 0 && s_nin > 0) atomicAdd(P.ncand_count, (uint32_t)s_nin);
+    if (tid == 0 && s_nin > 0) count_add(P.ncand_count, P.count_stride, (uint32_t)s_nin);
     // 5. per-cell top-K (K = quota when the whole level is one cell), written to fixed
     //    slots: K' = min(K, survivors a cell can hold) per cell, or one per 2x2 block
     //    when there are no cells.  Slots left empty get the sentinel.
@@ -1570,7 +1631,7 @@ __global__ __launch_bounds__(256, 4) void k_detect(KArgs a) {
           store_cand(out + slot, filled ? cbest[c] : INT64_MIN, cwin[c]);
         }
         const uint64_t m = __ballot(filled);
-        if (lane == 0 && m) atomicAdd(P.cand_count, (uint32_t)__popcll(m));
+        if (lane == 0 && m) count_add(P.cand_count, P.count_stride, (uint32_t)__popcll(m));
       }
       queue_park(h, next, &s_next);
       continue;
@@ -1633,8 +1694,9 @@ __global__ __launch_bounds__(256, 4) void k_detect(KArgs a) {
     lds_barrier();
     if (P.compact) {
       // Levels with more candidate slots than the rank path takes: the kept survivors
-      // are appended after the level's filled count (one reserving atomic per tile), so
-      // the radix select reads filled entries only.
+      // are appended after the level's filled count (one reserving atomic per tile, on
+      // sub-counter 0, which alone counts such a level), so the radix select reads
+      // filled entries only.
       if (tid == 0) s_ns = s_ne > 0 ? (int)atomicAdd(P.cand_count, (uint32_t)s_ne) : 0;
       lds_barrier();
       const int base = s_ns, ne = s_ne;
@@ -1664,12 +1726,30 @@ __global__ __launch_bounds__(256, 4) void k_detect(KArgs a) {
           if (!order[by * nbx + bx])
             store_cand(out + (size_t)(srow + by) * P.slot_w + scol + bx, INT64_MIN, kNoPos);
     }
-    if (tid == 0 && s_ne > 0) atomicAdd(P.cand_count, (uint32_t)s_ne);
+    if (tid == 0 && s_ne > 0) count_add(P.cand_count, P.count_stride, (uint32_t)s_ne);
     queue_park(h, next, &s_next);
   }
 }
 
 // ------------------------------------------- level selection + orientation --
+
+// Sum over levels 0 .. upto-1 of the frame of min(filled slots, quota): the first output
+// index of level `upto` (upto = n_levels: the frame's keypoint count).  counts0 is level
+// 0's sub-counter 0.  Every lane of the wave takes part (16 lanes per level, one
+// sub-counter each); the result is the same in every lane.
+__device__ __forceinline__ int level_prefix(const LevelPlan* plan, int entry0,
+                                            gptr<const uint32_t> counts0, int stride, int upto) {
+  const int lane = (int)(threadIdx.x & 63);
+  int acc = 0;
+  for (int l0 = 0; l0 < upto; l0 += 64 / kCountSpread) {
+    const int l = l0 + lane / kCountSpread, k = lane % kCountSpread;
+    uint32_t v = l < upto ? counts0[l + k * stride] : 0u;
+#pragma unroll
+    for (int o = 1; o < kCountSpread; o <<= 1) v += (uint32_t)__shfl_xor((int)v, o, 64);
+    if (k == 0 && l < upto) acc += min((int)v, plan_quota(plan, entry0 + l));
+  }
+  return wave_sum(acc);
+}
 
 // One wave per candidate slot.  A candidate's rank is the number of candidates of its
 // level that rank above it; ranks of the N_l best are exactly their sorted positions, so
@@ -1723,12 +1803,13 @@ __global__ __launch_bounds__(256) void k_select_orient(KArgs a) {
   const LevelPlan P = plan_at(h.plan, e);
   if (wsig != h.sig) return;
   gptr<const uint32_t> counts = G((const uint32_t*)P.cand_count) - e;  // all entries
-  const int C = ranked_candidates(P, counts[e]);  // empty slots hold the sentinel
-  if (live && P.level == 0 && i == 0 && lane == 0) {
-    int total = 0;
-    for (int l = 0; l < P.n_levels; ++l)
-      total += min((int)counts[P.entry0 + l], plan_quota(a.plan, P.entry0 + l));
-    *G(P.count_out) = total;
+  // empty slots hold the sentinel; only an appended level's count bounds its list
+  const int C = P.compact ? ranked_candidates(P, count_sum(counts + e, P.count_stride))
+                          : P.cand_cap;
+  if (live && P.level == 0 && i == 0) {
+    const int total =
+        level_prefix(a.plan, P.entry0, counts + P.entry0, P.count_stride, P.n_levels);
+    if (lane == 0) *G(P.count_out) = total;
   }
   if (one && slot0 - st0 >= C) return;  // the block's slots are past the level's list
   gptr<const Cand> cand = G((const Cand*)P.cand);
@@ -1782,9 +1863,7 @@ __global__ __launch_bounds__(256) void k_select_orient(KArgs a) {
   }
   const int rank = wave_sum(cnt);
   if (rank >= P.quota) return;
-  int prefix = 0;
-  for (int l = 0; l < P.level; ++l)
-    prefix += min((int)counts[P.entry0 + l], plan_quota(a.plan, P.entry0 + l));
+  const int prefix = level_prefix(a.plan, P.entry0, counts + P.entry0, P.count_stride, P.level);
   const int x = (int)(me.pos & 0xffff), y = (int)(me.pos >> 16);
   int m10, m01;
   wave_moments(G(P.lvl), P.lvl_stride, x, y, P.B, lane, &m10, &m01);
@@ -1836,7 +1915,7 @@ __global__ __launch_bounds__(1024) void k_select(KArgs a) {
   const LevelPlan P = plan_at(a.plan, e);
   if (wsig != a.sig) return;  // not the plan this launch was made for
   const int N = P.quota;
-  const int nfill = (int)*G(P.cand_count);
+  const int nfill = (int)count_sum(G((const uint32_t*)P.cand_count), P.count_stride);
   // slots (empty ones hold the sentinel and are skipped), or the appended entries
   const int C = ranked_candidates(P, (uint32_t)nfill);
   if (a.rank_path && C <= kRankCap) return;  // handled by k_select_orient
@@ -1976,17 +2055,15 @@ __global__ __launch_bounds__(256) void k_orient(KArgs a) {
   const LevelPlan P = plan_at(a.plan, e);
   if (wsig != a.sig) return;  // not the plan this launch was made for
   gptr<const uint32_t> counts = G((const uint32_t*)P.cand_count) - e;
-  if (a.rank_path && ranked_candidates(P, counts[e]) <= kRankCap) return;  // k_select_orient's
+  if (a.rank_path && ranked_candidates(P, count_sum(counts + e, P.count_stride)) <= kRankCap)
+    return;  // k_select_orient's
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int nsel = (int)*G(P.sel_count);
-  int prefix = 0;
-  for (int l = 0; l < P.level; ++l)
-    prefix += min((int)counts[P.entry0 + l], plan_quota(a.plan, P.entry0 + l));
-  if (!a.rank_path && P.level == 0 && chunk == 0 && threadIdx.x == 0) {
-    int total = 0;
-    for (int l = 0; l < P.n_levels; ++l)
-      total += min((int)counts[P.entry0 + l], plan_quota(a.plan, P.entry0 + l));
-    *G(P.count_out) = total;
+  const int prefix = level_prefix(a.plan, P.entry0, counts + P.entry0, P.count_stride, P.level);
+  if (!a.rank_path && P.level == 0 && chunk == 0 && wave == 0) {
+    const int total =
+        level_prefix(a.plan, P.entry0, counts + P.entry0, P.count_stride, P.n_levels);
+    if (lane == 0) *G(P.count_out) = total;
   }
   gptr<const Cand> sel = G((const Cand*)P.sel);
   for (int kk = 0; kk < kOrientPerBlock / 4; ++kk) {
@@ -2024,8 +2101,20 @@ __global__ __launch_bounds__(256) void k_test_segment(const uint8_t* circles, in
 // and l + 192 of the bin's rotated pattern (5x5 binomial sums compared), and the four
 // ballots are the 256-bit descriptor.  Slots beyond the frame's count, or a workspace
 // that does not hold the expected plan, are left untouched.
+constexpr int kPatchPitch = 36;  // bytes per patch row
+constexpr int kSumPitch = 28;    // uint16 per row of the sum tables
+
+// LDS written by some lanes of a wave, read by others of the same wave.
+__device__ __forceinline__ void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront", "local");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront", "local");
+}
+
 __global__ __launch_bounds__(256) void k_describe(DescArgs a) {
-  __shared__ uint8_t patch[4][31 * 32];
+  __shared__ __align__(16) uint8_t patch[4][31 * kPatchPitch];
+  __shared__ __align__(16) uint16_t hsum[4][31 * kSumPitch];  // horizontal 5-tap sums
+  __shared__ __align__(16) uint16_t ssum[4][27 * kSumPitch];  // 5 x 5 binomial sums
   const int lane = (int)(threadIdx.x & 63), wave = (int)(threadIdx.x >> 6);
   const int slot = (int)blockIdx.x * 4 + wave;
   const int f = slot / a.cap, i = slot - f * a.cap;
@@ -2049,7 +2138,8 @@ __global__ __launch_bounds__(256) void k_describe(DescArgs a) {
     key = other > key ? other : key;
   }
   const int bin = 31 - (int)(key & 31);
-  // the 31 x 31 patch (row pitch 32)
+  // The 31 x 31 patch, row pitch 36 bytes (9 words: the rows a lane each reads below
+  // start in distinct banks).
   uint8_t* pt = patch[wave];
   gptr<const uint8_t> lvl = G(P.lvl);
   uint8_t v[16];
@@ -2061,35 +2151,64 @@ __global__ __launch_bounds__(256) void k_describe(DescArgs a) {
 #pragma unroll
   for (int k = 0; k < 16; ++k) {
     const int idx = lane + 64 * k;
-    if (idx < 961) pt[(idx / 31) * 32 + idx % 31] = v[k];
+    if (idx < 961) pt[(idx / 31) * kPatchPitch + idx % 31] = v[k];
   }
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront", "local");
-  __builtin_amdgcn_wave_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront", "local");
-  auto smooth = [&](int u, int w) {  // 5x5 binomial sum at patch offset (u, w)
-    const uint8_t* c = pt + (15 + w - 2) * 32 + 15 + u - 2;
-    int s = 0;
+  wave_lds_sync();
+  // Every test point lies within 13 pixels of the keypoint, so the 5 x 5 binomial sums
+  // (weights 1 4 6 4 1 in each direction, not normalised) are needed at the 27 x 27
+  // centres only: formed once per keypoint, separably and exactly in integers.
+  // Horizontal pass: lane (row r, half h) sums patch columns c .. c+4 of row r for the
+  // 14 (h = 0) or 13 (h = 1) centre columns c of its half.
+  uint16_t* hs = hsum[wave];
+  {
+    const int r = lane & 31, h = lane >> 5;
+    if (r < 31) {
+      const uint32_t* row = (const uint32_t*)(pt + r * kPatchPitch) + 3 * h;
+      uint32_t w[5];
 #pragma unroll
-    for (int b = 0; b < 5; ++b) {
-      const int wb = b == 2 ? 6 : (b == 1 || b == 3 ? 4 : 1);
-      const int r = c[0] + 4 * c[1] + 6 * c[2] + 4 * c[3] + c[4];
-      s += wb * r;
-      c += 32;
+      for (int k = 0; k < 5; ++k) w[k] = row[k];  // bytes 12h .. 12h + 19 of the row
+      int b[20];
+#pragma unroll
+      for (int k = 0; k < 20; ++k) b[k] = (int)((w[k >> 2] >> (8 * (k & 3))) & 0xffu);
+      // centre column c = 14h + j takes bytes c .. c + 4, i.e. b[2h + j ..]
+      uint32_t* out = (uint32_t*)(hs + r * kSumPitch) + 7 * h;
+#pragma unroll
+      for (int j = 0; j < 14; j += 2) {
+        const int o = 2 * h + j;
+        const int s0 = b[o] + 4 * b[o + 1] + 6 * b[o + 2] + 4 * b[o + 3] + b[o + 4];
+        const int s1 = b[o + 1] + 4 * b[o + 2] + 6 * b[o + 3] + 4 * b[o + 4] + b[o + 5];
+        out[j >> 1] = (uint32_t)s0 | ((uint32_t)s1 << 16);
+      }
     }
-    return s;
-  };
+  }
+  wave_lds_sync();
+  // Vertical pass: lane (column c, half h) sums rows w .. w+4 of the horizontal sums for
+  // the 14 (h = 0) or 13 (h = 1) centre rows w of its half.
+  uint16_t* ss = ssum[wave];
+  if (lane < 54) {
+    const int h = lane >= 27 ? 1 : 0, c = lane - 27 * h;
+    const uint16_t* col = hs + 14 * h * kSumPitch + c;
+    int hv[18];
+#pragma unroll
+    for (int k = 0; k < 18; ++k) hv[k] = k < 17 + (h ^ 1) ? (int)col[k * kSumPitch] : 0;
+#pragma unroll
+    for (int j = 0; j < 14; ++j)
+      if (j < 14 - h)
+        ss[(14 * h + j) * kSumPitch + c] =
+            (uint16_t)(hv[j] + 4 * hv[j + 1] + 6 * hv[j + 2] + 4 * hv[j + 3] + hv[j + 4]);
+  }
+  wave_lds_sync();
   gptr<const uint32_t> tbl = (gptr<const uint32_t>)(G(a.rot) + (size_t)bin * 256 * 4);
   uint64_t words[4];
 #pragma unroll
   for (int r = 0; r < 4; ++r) {
     const uint32_t t = tbl[r * 64 + lane];
-    // table points lie within 13 of the keypoint; clamped so that no entry reads outside
-    // the patch
+    // clamped so that no entry reads outside the table
     const int x1 = min(max((int)(int8_t)(t & 0xff), -13), 13);
     const int y1 = min(max((int)(int8_t)((t >> 8) & 0xff), -13), 13);
     const int x2 = min(max((int)(int8_t)((t >> 16) & 0xff), -13), 13);
     const int y2 = min(max((int)(int8_t)(t >> 24), -13), 13);
-    words[r] = __ballot(smooth(x1, y1) < smooth(x2, y2));
+    words[r] = __ballot(ss[(y1 + 13) * kSumPitch + x1 + 13] < ss[(y2 + 13) * kSumPitch + x2 + 13]);
   }
   if (lane == 0) {
     gptr<uint64_t> d = (gptr<uint64_t>)(G(a.desc) + (size_t)(a.off[f] + i) * 32);
@@ -2215,7 +2334,9 @@ __global__ __launch_bounds__(256) void k_ab_fast_masks(AbArgs a) {
 
 // Production scheme on one level: LDS tile (64 x 16 pixels, 4 rows per thread), exact
 // compass pre-test as a wave-wide early-out, min/max windows (the segment-test kernel
-// without pyramid, queue and bitmaps).
+// without pyramid, queue and bitmaps).  MASKS: the same tile and pre-test, then bright
+// and dark masks and the shift-and run test instead of the min/max windows.
+template <bool MASKS>
 __global__ __launch_bounds__(256) void k_ab_fast_minmax(AbArgs a) {
   int b;
   const AbLevel& L = a.lv[ab_level(a, (int)blockIdx.x, &b)];
@@ -2254,7 +2375,17 @@ __global__ __launch_bounds__(256) void k_ab_fast_minmax(AbArgs a) {
         constexpr int8_t cy[16] = {-3, -3, -2, -1, 0, 1, 2, 3, 3, 3, 2, 1, 0, -1, -2, -3};
         d[i] = (int)tile[ly + 3 + cy[i]][lx + 3 + cx[i]] - p;
       }
-      r = (uint8_t)(segment_test2(d, t, t) & 1u);
+      if (MASKS) {
+        uint32_t mb = 0, md = 0;
+#pragma unroll
+        for (int i = 0; i < 16; ++i) {
+          mb |= (d[i] >= t ? 1u : 0u) << i;
+          md |= (d[i] <= -t ? 1u : 0u) << i;
+        }
+        r = (run9_bits(mb) || run9_bits(md)) ? 1 : 0;
+      } else {
+        r = (uint8_t)(segment_test2(d, t, t) & 1u);
+      }
     }
     if (x < W && y < H) G(out)[(size_t)y * W + x] = r;
   }
@@ -2548,18 +2679,33 @@ hipError_t launch_detect(const KArgs& a, int grid, hipStream_t s) {
 // Candidate counters of the entries (one, or all when entry < 0) divided by `times`:
 // after a Harris/NMS launch issued `times` times back to back for profiling, each count
 // is exactly `times` times its value (every issue adds the same amount).
+// Every sub-counter of the filled slots and FAST candidates divided by the number of
+// repeated issues (each issue adds the same amounts to the same sub-counters).
 __global__ __launch_bounds__(256) void k_scale_counters(uint32_t* counters, int n, int entry,
                                                         int times) {
   const int i = (int)(blockIdx.x * blockDim.x + threadIdx.x);
   const int e = entry >= 0 ? entry : i;
   if ((entry >= 0 && i > 0) || e >= n) return;
-  G(counters)[e] /= (uint32_t)times;          // filled candidate slots
-  G(counters)[2 * n + e] /= (uint32_t)times;  // FAST candidates
+  const int cs = count_stride(n);
+  for (int k = 0; k < 2 * kCountSpread; ++k) G(counters)[k * cs + e] /= (uint32_t)times;
 }
 
 hipError_t launch_scale_counters(const KArgs& a, int times, hipStream_t s) {
   hipLaunchKernelGGL(k_scale_counters, dim3(cdiv(a.n_entries, 256)), dim3(256), 0, s, a.counters,
                      a.n_entries, a.entry, times);
+  return hipGetLastError();
+}
+
+__global__ __launch_bounds__(256) void k_sum_fast_counts(const uint32_t* counters, int n,
+                                                         int32_t* out) {
+  const int e = (int)(blockIdx.x * blockDim.x + threadIdx.x);
+  if (e >= n) return;
+  const int cs = count_stride(n);
+  G(out)[e] = (int32_t)count_sum(G(counters) + kCountSpread * cs + e, cs);
+}
+
+hipError_t launch_sum_fast_counts(const uint32_t* counters, int n, int32_t* out, hipStream_t s) {
+  hipLaunchKernelGGL(k_sum_fast_counts, dim3(cdiv(n, 256)), dim3(256), 0, s, counters, n, out);
   return hipGetLastError();
 }
 
@@ -2610,7 +2756,8 @@ hipError_t launch_ablate_fast(const AbArgs& a, int variant, hipStream_t s) {
     case 0: OF_LAUNCH(k_ab_fast_branchy, grid, dim3(256), 0, s, a); break;
     case 1: OF_LAUNCH((k_ab_fast_masks<false>), grid, dim3(256), 0, s, a); break;
     case 2: OF_LAUNCH((k_ab_fast_masks<true>), grid, dim3(256), 0, s, a); break;
-    default: OF_LAUNCH(k_ab_fast_minmax, grid, dim3(256), 0, s, a); break;
+    case 3: OF_LAUNCH((k_ab_fast_minmax<false>), grid, dim3(256), 0, s, a); break;
+    default: OF_LAUNCH((k_ab_fast_minmax<true>), grid, dim3(256), 0, s, a); break;
   }
   return hipGetLastError();
 }

@@ -24,6 +24,11 @@ constexpr int kCandCache = 1024;                     // Harris scores cached per
 constexpr int kRankCap = 16384;                      // levels ranked by counting, not radix
 constexpr int kSelLdsCap = 2560;                     // level R' staged in LDS for ranking
 constexpr uint32_t kNoPos = 0xffffffffu;              // position of an empty candidate slot
+// Per-level counters that many tiles add to are split into kCountSpread sub-counters in
+// separate 128-byte lines (a tile adds to sub-counter blockIdx mod kCountSpread; readers
+// sum them): device-wide atomics on one address are serialised where they are
+// performed, and the last of them hold the launch's completion.
+constexpr int kCountSpread = 16;
 
 struct Tune {
   int32_t mark_words, mark_rows;
@@ -101,13 +106,14 @@ struct LevelPlan {
   int32_t wpr;
   uint8_t* flags;              // ncx * ncy bytes: 1 = cell holds a fast_t corner
   Cand* cand;                  // candidate slots written by the Harris/NMS tiles
-  uint32_t* cand_count;        // filled slots
+  uint32_t* cand_count;        // filled slots: sub-counter 0 (count_stride apart)
   int32_t cand_cap;            // slots (filled or holding the kNoPos sentinel)
   int32_t kslot;               // slots per cell (cell > 0)
   int32_t compact;             // 1: no fixed slots; tiles append (level past kRankCap, cell 0)
   Cand* sel;                   // level selection, sorted, quota entries
   uint32_t* sel_count;
-  uint32_t* ncand_count;       // FAST candidates of the level (statistics)
+  uint32_t* ncand_count;       // FAST candidates of the level (statistics), sub-counter 0
+  int32_t count_stride;        // words between sub-counters
   int32_t mark_tx, mark_ty;    // segment-test tile grid (covers the whole level)
   int32_t band_rot;            // first band that takes one of the leftover tile rows
   int32_t det_band_rot;        // the same for the Harris/NMS tile rows
@@ -125,6 +131,14 @@ struct LevelPlan {
 
 OF_HD int32_t cdiv(int32_t a, int32_t b) { return (a + b - 1) / b; }
 OF_HD int64_t align_up(int64_t v, int64_t a) { return (v + a - 1) / a * a; }
+
+// Counter region of a call with n entries: kCountSpread sub-counters of the filled slots
+// and of the FAST candidates (one 128-byte-aligned array of n words each), then one
+// selected count per entry.
+OF_HD int32_t count_stride(int32_t n_entries) { return (int32_t)align_up(n_entries, 32); }
+OF_HD int64_t counter_words(int32_t n_entries) {
+  return 2 * (int64_t)kCountSpread * count_stride(n_entries) + n_entries;
+}
 
 // The same for the LDS layouts that every wave of a tile kernel computes at its start:
 // non-negative 32-bit values, so unsigned arithmetic (a power-of-two divisor is a shift).
@@ -300,8 +314,8 @@ OF_HD void ws_layout_finish(WsLayout* w) {
   w->off_pyr_base = o;     o = align_up(o + 4 * ((int64_t)w->n_entries + 1), 256);
   w->off_band_base = o;    o = align_up(o + 4 * kXcds * ((int64_t)w->n_entries + 1), 256);
   w->off_det_band_base = o;  o = align_up(o + 4 * kXcds * ((int64_t)w->n_entries + 1), 256);
-  // counters per entry: filled candidate slots, selected (radix path), FAST candidates
-  w->off_counters = o;     o = align_up(o + 12 * (int64_t)w->n_entries, 256);
+  // counters: filled candidate slots and FAST candidates (spread), selected (radix path)
+  w->off_counters = o;     o = align_up(o + 4 * counter_words(w->n_entries), 256);
   w->off_flags = o;        o = align_up(o + w->flag_bytes, 256);
   w->off_bm = o;           o = align_up(o + 4 * w->bm_words, 256);
   w->off_cand = o;         o = align_up(o + (int64_t)sizeof(Cand) * w->cand_entries, 256);
@@ -492,7 +506,7 @@ struct DetLds {
   int32_t nbw, nunits;       // candidate words per ring row (at most), total words
   int32_t max_surv, max_cells;
   int32_t off_cw, off_ucnt, off_cpre, off_crs, off_cpos, off_sci, off_scell, off_order, off_ccnt,
-      off_coff, off_cfill, off_ckept, off_cbest, off_cwin, off_lfl, bytes;
+      off_coff, off_cfill, off_ckept, off_cbest, off_cwin, off_lfl, fm_rows, off_fm, bytes;
 };
 
 OF_HD DetLds det_lds(const Tune& t, int32_t cell) {
@@ -530,6 +544,8 @@ OF_HD DetLds det_lds(const Tune& t, int32_t cell) {
   d.off_cwin = o;   o += align16(4 * d.max_cells);   // K = 1: its position
   const int32_t nfl = cell > 0 ? (t.det_cx + 2) * (t.det_cy + 2) : 4;  // cells of the ring
   d.off_lfl = o;    o += align16(nfl);
+  d.fm_rows = cell > 0 ? t.det_cy + 2 : 4;  // flag rows of the ring
+  d.off_fm = o;     o += 8 * d.fm_rows * d.nbw;  // candidate-word masks (hi, lo)
   d.bytes = o;      // + the entry base table of the launch
   return d;
 }

@@ -213,7 +213,7 @@ def of_describe(images, p: OfParams, tune, ws_ptr: int, kps_ptr: int, kp_offsets
                              centres_ptr, desc_ptr, stream), "of_describe")
 
 
-AB_FAST = {"branchy": 0, "masks": 1, "masks_lds": 2, "minmax_lds": 3}
+AB_FAST = {"branchy": 0, "masks": 1, "masks_lds": 2, "minmax_lds": 3, "masks_pretest_lds": 4}
 AB_HARRIS = {"2d": 0, "separable": 1, "groups": 2, "dense_sliding": 3}
 
 

@@ -197,8 +197,8 @@ hipError_t launch_prologue(const PrologueArgs& a, int grid, hipStream_t) {
   uint32_t* qctr = (uint32_t*)(ws + lay.off_hdr);
   uint64_t* sig = (uint64_t*)(ws + lay.off_hdr + 128);
   g_in_prologue = true;
-  acc(counters, 12 * (int64_t)lay.n_entries, "counters zeroed", true);
-  memset(counters, 0, 12 * (size_t)lay.n_entries);
+  acc(counters, 4 * counter_words(lay.n_entries), "counters zeroed", true);
+  memset(counters, 0, 4 * (size_t)counter_words(lay.n_entries));
   acc(ws + lay.off_flags, lay.flag_bytes / 16 * 16, "flags zeroed", true);
   acc(qctr, 128, "queue counters zeroed", true);
   memset(qctr, 0, 128);
@@ -440,7 +440,7 @@ hipError_t launch_mark(const KArgs& a, bool fused, int grid, hipStream_t) {
   CHECK(lds_bytes <= 65536, "k_mark: %lld bytes of LDS", (long long)lds_bytes);
 
   if (a.entry < 0) {
-    acc(a.counters, 12 * (int64_t)a.n_entries, "counters zeroed", true);
+    acc(a.counters, 4 * counter_words(a.n_entries), "counters zeroed", true);
     acc(a.qctr + 2, 4, "Harris queue counter", true);
     a.qctr[2] = 0;
     st.counters_dirty = false;
@@ -580,6 +580,23 @@ hipError_t launch_detect(const KArgs& a, int grid, hipStream_t) {
     // LDS regions
     CHECK(T.nunits <= D.nunits, "k_detect: %d candidate words > %d", T.nunits, D.nunits);
     CHECK(T.nfx * T.nfy <= nfl_alloc, "k_detect: %d ring cells > %d", T.nfx * T.nfy, nfl_alloc);
+    // candidate-word masks: two words per (flag row, word column)
+    CHECK(T.nfy <= D.fm_rows && T.nbw <= D.nbw, "k_detect: %dx%d mask table > %dx%d", T.nfy,
+          T.nbw, D.fm_rows, D.nbw);
+    lds(D.off_fm + 8 * ((int64_t)T.nfy * T.nbw - 1), 8, D.off_fm, D.bytes, "k_detect word masks");
+    // the cells a word column's table entry reads: c0 .. c0 + 4 from the first valid column,
+    // those overlapping the word inside the ring's flag columns
+    {
+      const int xa0 = std::max(T.rx0, B), xb0 = std::min(T.rx0 + T.rw, W - B);
+      for (int k = 0; k < T.nbw; ++k) {
+        const int x0 = (T.bw0 + k) << 5, a0 = std::max(x0, xa0), b0 = std::min(x0 + 32, xb0);
+        if (a0 >= b0) continue;
+        for (int c = a0 / cs; c * cs < b0; ++c) {
+          CHECK(c - a0 / cs < 5, "k_detect: word %d meets more than 5 cells", k);
+          CHECK(c >= T.fcx0 && c < T.fcx0 + T.nfx, "k_detect: cell %d outside the ring's flags", c);
+        }
+      }
+    }
     CHECK(T.nlcx * T.nlcy <= D.max_cells, "k_detect: %d cells > %d", T.nlcx * T.nlcy, D.max_cells);
     const int vw = T.vx1 - T.vx0, vh = T.vy1 - T.vy0;
     CHECK(((vw + 1) / 2) * ((vh + 1) / 2) <= D.max_surv, "k_detect: survivors may exceed %d",
@@ -649,15 +666,24 @@ hipError_t launch_detect(const KArgs& a, int grid, hipStream_t) {
         acc(P.cand + s0, (int64_t)sizeof(Cand) * nbx, "k_detect block slots", true);
       }
     }
-    acc(P.cand_count, 4, "k_detect count", true);
-    acc(P.ncand_count, 4, "k_detect FAST count", true);
+    for (int k : {0, kCountSpread - 1}) {  // the sub-counters a tile may add to
+      acc(P.cand_count + (int64_t)k * P.count_stride, 4, "k_detect count", true);
+      acc(P.ncand_count + (int64_t)k * P.count_stride, 4, "k_detect FAST count", true);
+    }
   }
   g_ws[ws_base(a)].counters_dirty = true;
   return hipSuccess;
 }
 
+hipError_t launch_sum_fast_counts(const uint32_t* counters, int n, int32_t* out, hipStream_t) {
+  const int64_t cs = count_stride(n);
+  acc(counters + kCountSpread * cs, 4 * kCountSpread * cs, "FAST count sums");
+  acc(out, 4 * (int64_t)n, "FAST count output", true);
+  return hipSuccess;
+}
+
 hipError_t launch_scale_counters(const KArgs& a, int, hipStream_t) {
-  acc(a.counters, 12 * (int64_t)a.n_entries, "k_scale_counters", true);
+  acc(a.counters, 4 * counter_words(a.n_entries), "k_scale_counters", true);
   return hipSuccess;
 }
 
@@ -723,6 +749,11 @@ hipError_t launch_select_orient(const KArgs& a, int slots, hipStream_t) {
       if (P.quota > 0) check_out(P, a, prefix + P.quota - 1, "k_select_orient keypoint");
     }
     acc(P.count_out, 4, "k_select_orient count", true);
+    // the frame's level counters: every sub-counter of its levels
+    const LevelPlan& P0 = plan(a, P.entry0);
+    acc(P0.cand_count, 4, "k_select_orient level counters");
+    acc(P0.cand_count + (P.n_levels - 1) + (int64_t)(kCountSpread - 1) * P.count_stride, 4,
+        "k_select_orient level counters");
   }
   return hipSuccess;
 }

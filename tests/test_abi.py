@@ -139,7 +139,7 @@ def test_ablation_entry_points_validate_before_launch(lib):
     one = (ctypes.c_void_p * 1)(0x1000)
     null = (ctypes.c_void_p * 1)(None)
     for lv, t, b, v in ((bad_img, 20, 15, 0), (img, 0, 15, 0), (img, 256, 15, 0),
-                        (img, 20, 2, 0), (img, 20, 15, 4), (img, 20, 15, -1)):
+                        (img, 20, 2, 0), (img, 20, 15, 5), (img, 20, 15, -1)):
         arr = (ofhip.OfImage * 1)(lv)
         assert lib.of_ablate_fast(arr, 1, t, b, v, one, None) == ofhip.OF_EINVAL, (t, b, v)
     arr = (ofhip.OfImage * 1)(img)
