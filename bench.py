@@ -362,6 +362,7 @@ def main():
         from synth import stream_schedule
         pool = serve.camera_pool(32, 2)
         server = serve.Server(p, hbm_budget=4 << 30, max_batch=16, lanes=3)
+        server.warm(sorted({tuple(v[0].shape) for v in pool.values()}))
         frame_of = lambda s_, k_: (pool[(s_, k_ % 2)][0], (s_, k_ % 2))
         serve.run_schedule(server, stream_schedule(32, 0.2, 30.0), frame_of, rate_scale=4.0)
         served = {"workload": "32 streams x 30 fps Poisson, 720x540..1920x1080, 8 levels, N=2000",
@@ -372,6 +373,7 @@ def main():
             assert all(r.status == "ok" for r in res)
             row = serve.summarize(res, wall, 32 * 30.0 * scale)
             row["scale"] = scale
+            row["resident_mib"] = round(server.resident / 2**20, 1)
             served["runs"].append(row)
         log(f"# served {served['runs']}")
         del pool, server
