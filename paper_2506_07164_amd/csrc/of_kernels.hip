@@ -933,6 +933,7 @@ __global__ __launch_bounds__(256, 5) void k_mark(KArgs a) {
   constexpr int PITCH = TW + 8;
   extern __shared__ __align__(16) uint8_t smem[];
   __shared__ int s_next, s_qcnt[4];
+  __shared__ uint8_t s_cf[kMarkCellFlags];  // cells of the tile that hold a fast_t corner
   const int band = (int)(blockIdx.x % kXcds);  // used in the band order only
   Head h = read_head(a, band);
   h.persistent = PERSIST;  // one tile per block otherwise: straight-line code, no loop state
@@ -1114,27 +1115,12 @@ __global__ __launch_bounds__(256, 5) void k_mark(KArgs a) {
       stage_all<8>(pix, PITCH, G(P.lvl), P.lvl_stride, limit, ox, ex, oy, ey);
     }
     for (int i = threadIdx.x; i < 2 * M.th * 2 * TWW; i += kBlock) bml[i] = 0u;  // lo, hi
+    // cells of the tile's pixels: flagged in LDS by the full test, written once at the end
+    const int cx_t0 = (int)div_by((uint32_t)x_t0, P.csd), cy_t0 = (int)div_by((uint32_t)y_t0, P.csd);
+    const int ncx_t = (int)div_by((uint32_t)(x_t1 - 1), P.csd) - cx_t0 + 1;
+    const int ncf = ncx_t * ((int)div_by((uint32_t)(y_t1 - 1), P.csd) - cy_t0 + 1);
+    for (int i = threadIdx.x; i < ncf; i += kBlock) s_cf[i] = 0;
     lds_barrier();
-    if (FUSED && P.level > 0) {
-      // The tile's own pixels to the level buffer, 16 bytes per store (level rows are
-      // 64-byte aligned and tiles start at multiples of 64; a ragged right end goes
-      // byte by byte).  The stores drain while the pre-test runs.
-      const int ow = x_t1 - x_t0, nfull = ow >> 4;
-      gptr<uint8_t> lv = G(P.lvl_w) + (size_t)y_t0 * P.lvl_stride + x_t0;
-      const uint8_t* own = pix + (y_t0 - oy) * PITCH + (x_t0 - ox);  // 4-byte aligned
-      for (int q = threadIdx.x; q < (y_t1 - y_t0) * (TW / 16); q += kBlock) {
-        const int r = q / (TW / 16), k = q - r * (TW / 16);
-        const uint8_t* src = own + r * PITCH + 16 * k;
-        gptr<uint8_t> dst = lv + (size_t)r * P.lvl_stride + 16 * k;
-        if (k < nfull) {
-          const uint32_t* s4 = (const uint32_t*)src;
-          *(gptr<u32x4>)dst = u32x4{s4[0], s4[1], s4[2], s4[3]};
-        } else {
-          for (int b = 0; b < ow - 16 * k; ++b) dst[b] = src[b];
-        }
-      }
-    }
-
     // 2. compass pre-test at fast_t_min: a run of 9 holds two cyclically adjacent
     //    compass points (positions 1/5/9/13), so (n|s) & (e|w) per polarity is
     //    necessary; (n >= hi | s >= hi) & (e >= hi | w >= hi) is
@@ -1239,7 +1225,6 @@ __global__ __launch_bounds__(256, 5) void k_mark(KArgs a) {
       qoff[w] = qtot;
       qtot += w < nwave ? s_qcnt[w] : 0;
     }
-    gptr<uint8_t> flags = G(P.flags);
     for (int q = threadIdx.x; q < qtot; q += kBlock) {
       int w = 0;
 #pragma unroll
@@ -1273,7 +1258,8 @@ __global__ __launch_bounds__(256, 5) void k_mark(KArgs a) {
         atomicOr(&bml[word], 1u << (bit & 31));
         if (r & 2u) {
           atomicOr(&bmh[word], 1u << (bit & 31));
-          flags[(y / P.cs) * P.ncx + x / P.cs] = 1;
+          s_cf[((int)div_by((uint32_t)y, P.csd) - cy_t0) * ncx_t +
+               ((int)div_by((uint32_t)x, P.csd) - cx_t0)] = 1;
         }
       }
     }
@@ -1290,6 +1276,36 @@ __global__ __launch_bounds__(256, 5) void k_mark(KArgs a) {
           const size_t gi = (size_t)(y_t0 + r) * P.wpr + w0 + k;
           glo[gi] = bml[r * 2 * TWW + k];
           ghi[gi] = bmh[r * 2 * TWW + k];
+        }
+      }
+    }
+    // 5. the tile's flagged cells and (fused) its level pixels.  Global stores come last:
+    //    a store's registers are reused only after it completes, so a store issued
+    //    before a later step would hold that step up.
+    {
+      gptr<uint8_t> flags = G(P.flags);
+      for (int i = threadIdx.x; i < ncf; i += kBlock)
+        if (s_cf[i]) {
+          const int r = (int)((uint32_t)i / (uint32_t)ncx_t);
+          flags[(cy_t0 + r) * P.ncx + cx_t0 + (i - r * ncx_t)] = 1;
+        }
+    }
+    if (FUSED && P.level > 0) {
+      // The tile's own pixels to the level buffer, 16 bytes per store (level rows are
+      // 64-byte aligned and tiles start at multiples of 64; a ragged right end goes
+      // byte by byte).
+      const int ow = x_t1 - x_t0, nfull = ow >> 4;
+      gptr<uint8_t> lv = G(P.lvl_w) + (size_t)y_t0 * P.lvl_stride + x_t0;
+      const uint8_t* own = pix + (y_t0 - oy) * PITCH + (x_t0 - ox);  // 4-byte aligned
+      for (int q = threadIdx.x; q < (y_t1 - y_t0) * (TW / 16); q += kBlock) {
+        const int r = q / (TW / 16), k = q - r * (TW / 16);
+        const uint8_t* src = own + r * PITCH + 16 * k;
+        gptr<uint8_t> dst = lv + (size_t)r * P.lvl_stride + 16 * k;
+        if (k < nfull) {
+          const uint32_t* s4 = (const uint32_t*)src;
+          *(gptr<u32x4>)dst = u32x4{s4[0], s4[1], s4[2], s4[3]};
+        } else {
+          for (int b = 0; b < ow - 16 * k; ++b) dst[b] = src[b];
         }
       }
     }

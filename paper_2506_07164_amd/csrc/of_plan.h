@@ -21,6 +21,7 @@ constexpr int kSortCap = 4096;                       // candidates sorted in LDS
 constexpr int kOrientPerBlock = 16;                  // keypoints per orientation block
 constexpr int kMaxDetW = 256, kMaxDetH = 128;        // Harris/NMS tile limits (pixels)
 constexpr int kCandCache = 1024;                     // Harris scores cached per tile
+constexpr int kMarkCellFlags = 320;  // cells a segment-test tile meets (cell >= 8: 33 x 9)
 constexpr int kRankCap = 16384;                      // levels ranked by counting, not radix
 constexpr int kSelLdsCap = 2560;                     // level R' staged in LDS for ranking
 constexpr uint32_t kNoPos = 0xffffffffu;              // position of an empty candidate slot

@@ -544,6 +544,16 @@ hipError_t launch_mark(const KArgs& a, bool fused, int grid, hipStream_t) {
             acc(P.flags + c, 1, "k_mark cell flag", true);
           }
     }
+    // the tile's cells, flagged in LDS and written at the end of the tile
+    {
+      const int cx0 = T.x_t0 / P.cs, cy0 = T.y_t0 / P.cs;
+      const int ncxt = (T.x_t1 - 1) / P.cs - cx0 + 1, ncyt = (T.y_t1 - 1) / P.cs - cy0 + 1;
+      CHECK(ncxt * ncyt <= kMarkCellFlags, "k_mark: %d cells in a tile > %d", ncxt * ncyt,
+            kMarkCellFlags);
+      CHECK(cx0 + ncxt <= P.ncx && cy0 + ncyt <= P.ncy, "k_mark: tile cells outside the level");
+      acc(P.flags + (int64_t)cy0 * P.ncx + cx0, 1, "k_mark cell flag", true);
+      acc(P.flags + (int64_t)(cy0 + ncyt - 1) * P.ncx + cx0 + ncxt - 1, 1, "k_mark cell flag", true);
+    }
     // bitmap words of the tile rows
     const int w0 = T.x_t0 >> 5, nwd = std::min(2 * TWW, P.wpr - w0);
     CHECK(nwd <= 8, "k_mark: %d bitmap words per tile row", nwd);
