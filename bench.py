@@ -337,7 +337,13 @@ def main():
             frames = ([frame.clone() for _ in specs] if same else
                       [torch.from_numpy(make_frame(sp)).cuda() for sp in specs])
             cdet = ofhip.Detector([tuple(f.shape) for f in frames], cp, resident=True)
-            ctune = tune if same else None
+            if same:
+                ctune = tune
+            elif args.no_tune:
+                ctune = None
+            else:  # the workload's shipped launch shape (else the library default)
+                from paper_2506_07164_amd.tune import autotune
+                ctune = ofhip.tuning(**autotune(frames, cp))
             run = lambda: cdet.detect_batch(frames, tune=ctune, stream=stream)
             g = capture(run, stream)
             ms = event_median_ms(g.replay, stream)

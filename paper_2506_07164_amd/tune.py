@@ -26,8 +26,9 @@ FIELDS = ("mark_words", "mark_rows", "det_cells_x", "det_cells_y", "det_w", "det
 
 # Searching is off unless OF_TUNE_SEARCH=1: a search (many launch shapes timed one after
 # another on one resident workspace) has faulted the device once and the cause is not
-# yet found.  Without it, a workload missing from the caches takes the shipped tuning
-# of the same device, or the library default, untimed.
+# yet found.  Without it, a workload missing from the caches takes the library default
+# for its frames and parameters (sweeps of the shipped workloads found the default
+# within 10% of the best shape, and another workload's shape is no better a guess).
 SEARCH = os.environ.get("OF_TUNE_SEARCH") == "1"
 
 
@@ -76,6 +77,11 @@ def candidates(p, n_cus):
     return marks, dets, grids
 
 
+def _descriptors(shapes):
+    """Frame descriptors of these (H, W) shapes for the host-only calls (no pixels)."""
+    return [ofhip.OfImage(None, w, h, w) for h, w in shapes]
+
+
 def device_key():
     """Architecture and compute-unit count of device 0, e.g. 'gfx950/256'."""
     import torch
@@ -86,8 +92,8 @@ def device_key():
 def autotune(frames, p, calls=20, use_cache=True, verbose=False):
     """Best tuning (as a dict of of_tuning fields) for these frames and parameters:
     from the local cache, else from the shipped results, else searched when SEARCH is on
-    (else the shipped tuning of this device, or the library default).  The result of a
-    search is written to the local cache (also when use_cache is False)."""
+    (else the library default for these frames).  The result of a search is written to
+    the local cache (also when use_cache is False)."""
     import torch
     name = device_key()
     shapes = [tuple(f.shape) for f in frames]
@@ -107,19 +113,12 @@ def autotune(frames, p, calls=20, use_cache=True, verbose=False):
     if not SEARCH:
         if not use_cache:
             raise SearchDisabled("tuner search is off (set OF_TUNE_SEARCH=1 to search)")
-        try:
-            with open(SHIPPED) as fh:
-                for k, v in json.load(fh).items():
-                    if json.loads(k).get("dev") == name:
-                        return v["tuning"]
-        except (OSError, ValueError):
-            pass
-        default = ofhip.of_tuning_default([ofhip.image_of(f) for f in frames], p)
+        default = ofhip.of_tuning_default(_descriptors(shapes), p)
         return {f: getattr(default, f) for f in FIELDS}
     n_cus = torch.cuda.get_device_properties(0).multi_processor_count
     det = ofhip.Detector(shapes, p, resident=True)  # timed as bench.py runs it: plan resident
     best = {}
-    default = ofhip.of_tuning_default([ofhip.image_of(f) for f in frames], p)
+    default = ofhip.of_tuning_default(_descriptors(shapes), p)
     for f in FIELDS:
         best[f] = getattr(default, f)
     marks, dets, grids = candidates(p, n_cus)

@@ -40,6 +40,18 @@ def run_batch(hip, imgs, kw, tune=None):
     return det.results()
 
 
+def shipped_tuning(hip, name):
+    """The launch shape shipped for benchmark workload `name` on this device (what the
+    benchmark runs it with), or None when none is shipped for this device."""
+    import json
+    from paper_2506_07164_amd import tune
+    cfg = CONFIGS[name]
+    shapes = [(s.height, s.width) for s in cfg["frames"]]
+    with open(tune.SHIPPED) as fh:
+        entry = json.load(fh).get(tune._key(shapes, hip.params(**cfg["params"]), tune.device_key()))
+    return hip.tuning(**entry["tuning"]) if entry else None
+
+
 def run_plain(hip, img, kw):
     frame = torch.from_numpy(img).cuda()
     det = hip.Detector([img.shape], hip.params(**kw))
@@ -295,6 +307,10 @@ def test_c1_plain_and_batch(hip):
     assert len(ref) > 50
     assert_same_keypoints(run_plain(hip, img, kw), ref, "c1 plain")
     assert_same_keypoints(run_batch(hip, [img], kw)[0], ref, "c1 batch")
+    t = shipped_tuning(hip, "c1")
+    if t is not None:
+        log("case: c1 batch, shipped launch shape")
+        assert_same_keypoints(run_batch(hip, [img], kw, t)[0], ref, "c1 batch (shipped shape)")
 
 
 def test_c2_plain_and_fused(hip):
@@ -396,6 +412,12 @@ def test_c3_batch(hip):
     res = run_batch(hip, imgs, kw, hip.tuning(mark_order=1, det_order=1))
     for i, (g, r) in enumerate(zip(res, refs)):
         assert_same_keypoints(g, r, f"c3 frame {i} (bands)")
+    t = shipped_tuning(hip, "c3")
+    if t is not None:
+        log("case: c3 batch, shipped launch shape")
+        res = run_batch(hip, imgs, kw, t)
+        for i, (g, r) in enumerate(zip(res, refs)):
+            assert_same_keypoints(g, r, f"c3 frame {i} (shipped shape)")
 
 
 def test_c4_batch(hip):
@@ -403,9 +425,16 @@ def test_c4_batch(hip):
     kw = CONFIGS["c4"]["params"]
     log(f"case: c4 batch of {len(specs)}")
     refs = detect_many(specs, kw)
-    res = run_batch(hip, [make_frame(s) for s in specs], kw)
+    imgs = [make_frame(s) for s in specs]
+    res = run_batch(hip, imgs, kw)
     for i, (g, r) in enumerate(zip(res, refs)):
         assert_same_keypoints(g, r, f"c4 frame {i}")
+    t = shipped_tuning(hip, "c4")
+    if t is not None:
+        log("case: c4 batch, shipped launch shape")
+        res = run_batch(hip, imgs, kw, t)
+        for i, (g, r) in enumerate(zip(res, refs)):
+            assert_same_keypoints(g, r, f"c4 frame {i} (shipped shape)")
 
 
 def test_batch_equals_alone(hip):

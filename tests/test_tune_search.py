@@ -1,6 +1,6 @@
 """The tuner's search is off unless OF_TUNE_SEARCH=1: an explicit re-search raises
-before any GPU work, and a workload missing from the caches takes the device's shipped
-tuning (host logic only, no GPU)."""
+before any GPU work, a shipped workload takes its shipped shape and a workload missing
+from the caches takes the library default (host logic only, no GPU)."""
 import json
 
 import numpy as np
@@ -25,15 +25,28 @@ def test_retune_raises_without_search(no_search):
         tune.autotune([np.zeros((1080, 1920), np.uint8)], _params(), use_cache=False)
 
 
-def test_missing_workload_takes_shipped_tuning(no_search):
-    with open(tune.SHIPPED) as fh:
-        shipped = json.load(fh)
-    dev = [v["tuning"] for k, v in shipped.items() if json.loads(k)["dev"] == "gfx950/256"]
-    assert dev, "no shipped tuning for gfx950/256"
-    got = tune.autotune([np.zeros((480, 640), np.uint8)], _params(), use_cache=True)
-    assert got == dev[0]
+def test_missing_workload_takes_library_default(no_search):
+    shapes = [(480, 640)]
+    got = tune.autotune([np.zeros(sh, np.uint8) for sh in shapes], _params(), use_cache=True)
+    d = ofhip.of_tuning_default([ofhip.OfImage(None, w, h, w) for h, w in shapes], _params())
+    assert got == {f: getattr(d, f) for f in tune.FIELDS}
 
 
 def test_shipped_workload_found(no_search):
     got = tune.autotune([np.zeros((1080, 1920), np.uint8)], _params(), use_cache=True)
     assert got["mark_words"] == 2 and got["mark_rows"] == 48
+
+
+@pytest.mark.parametrize("name", ["c1", "c3", "c4"])
+def test_shipped_config_workloads_found(no_search, name):
+    """The benchmark's other workloads have shipped shapes of their own, with the sweep's
+    per-call time recorded beside them."""
+    from synth import CONFIGS
+    cfg = CONFIGS[name]
+    p = ofhip.params(**cfg["params"])
+    shapes = [(s.height, s.width) for s in cfg["frames"]]
+    with open(tune.SHIPPED) as fh:
+        entry = json.load(fh)[tune._key(shapes, p, "gfx950/256")]
+    assert entry["ms"] > 0 and entry["trials"] > 1
+    got = tune.autotune([np.zeros(sh, np.uint8) for sh in shapes], p, use_cache=True)
+    assert got == entry["tuning"]
