@@ -166,6 +166,7 @@ Tune default_tune(const of_params& p) {
   t.mark_order = 1;  // XCD bands: measured faster on every workload here
   t.plan_resident = 0;
   t.det_order = 0;
+  t.rank_cap = kRankCap;  // per call: set_rank_cap
   // narrower Harris tiles where large cells would exceed the LDS budget
   while (p.cell > 0 && t.det_cx > 1 &&
          det_lds(t, p.cell).bytes + base_table_bytes(kMaxEntries) > 65536)
@@ -205,6 +206,34 @@ int resolve_tune(const of_tuning* user, const of_params& p, Tune* out) {
     return OF_EINVAL;
   *out = t;
   return OF_OK;
+}
+
+// The counting selection's cap for a call (Tune::rank_cap).  Ranking by counting takes
+// C^2 compares per level of C candidate slots but runs every slot's wave at once, which is
+// the shortest path while the call's counting work is small (up to a few 1080p frames:
+// about 10M compares each); past that, the radix select (a few passes over C in one
+// block per level, every level at once) takes the levels above kRankCapBusy, whose C^2
+// dominates the counting work.  Levels with appended lists (whole-level cells past
+// kRankCap) count no work here: their length is known only on the device, which takes
+// the radix path when it exceeds the cap.
+constexpr int64_t kRankWorkFew = 40000000;
+constexpr int32_t kRankCapBusy = kSortCap;
+
+void set_rank_cap(const of_image* frames, int n, const of_params& p, Tune* t) {
+  t->rank_cap = kRankCap;
+  int64_t work = 0;
+  for (int f = 0; f < n; ++f) {
+    FrameGeom g;
+    frame_geom(frames[f].width, frames[f].height, p, &g);
+    for (int l = 0; l < p.n_levels; ++l) {
+      EntrySize s;
+      entry_size(g, p, *t, l, &s);
+      if (p.cell == 0 && s.cand_cap > kRankCap) continue;
+      const int64_t c = std::min<int64_t>(s.cand_cap, kRankCap);
+      work += c * c;
+    }
+  }
+  if (work > kRankWorkFew) t->rank_cap = kRankCapBusy;
 }
 
 struct CallPlan {
@@ -338,7 +367,7 @@ void set_small_bases(KArgs& k, const CallPlan& c, BaseKind kind) {
           acc += s.det_tx * band_rows(s.det_ty, drot, r);
           drot = (drot + s.det_ty % kXcds) % kXcds;
           break;
-        case kRankSlots: acc += (int32_t)(s.cand_cap < kRankCap ? s.cand_cap : kRankCap); break;
+        case kRankSlots: acc += s.rank_slots; break;
         case kPyrBlocks: acc += s.pyr_blocks; break;
       }
     }
@@ -348,8 +377,9 @@ void set_small_bases(KArgs& k, const CallPlan& c, BaseKind kind) {
   }
 }
 
-// Level selection + orientation: ranks by counting for every level, and the radix
-// select + separate orientation only when some level could exceed kRankCap candidates.
+// Level selection + orientation: ranks by counting for every level up to the call's
+// rank cap, and the radix select + separate orientation only when some level could
+// exceed it.
 hipError_t launch_selection(KArgs k, const CallPlan& c, hipStream_t stream) {
   const WsLayout& lay = c.lay;
   k.entry = -1;
@@ -359,14 +389,16 @@ hipError_t launch_selection(KArgs k, const CallPlan& c, hipStream_t stream) {
   // (latency then sets the time, and a staged level is ranked without round trips);
   // otherwise waves rank from memory and most stop early, which takes less work.
   int32_t widest = 0;  // largest level the rank path takes (appended lists: up to the cap)
-  for (int i = 0; i < lay.n_entries; ++i)
-    widest = std::max(widest, (int32_t)std::min<int64_t>(c.es[i].cand_cap, kRankCap));
+  for (int i = 0; i < lay.n_entries; ++i) widest = std::max(widest, c.es[i].rank_slots);
   k.sel_lds = std::min(widest, kSelLdsCap);
   const int64_t blocks_per_cu = std::min<int64_t>(8, 163840 / (8 * (int64_t)k.sel_lds + 4352));
   if ((int64_t)lay.rank_slots > (int64_t)device_cus() * 4 * blocks_per_cu) k.sel_lds = 0;
-  hipError_t e = timed(4, stream, [&] { return launch_select_orient(k, lay.rank_slots, stream); },
-                       true);
-  if (e == hipSuccess && lay.max_cand_cap > kRankCap) {
+  // At least one block: besides ranking, the launch clears the cell flags and the
+  // segment-test queue counter for the next call (a call whose every level takes the
+  // radix path ranks nothing here).
+  const int32_t slots = std::max<int32_t>(lay.rank_slots, 1);
+  hipError_t e = timed(4, stream, [&] { return launch_select_orient(k, slots, stream); }, true);
+  if (e == hipSuccess && lay.max_cand_cap > k.t.rank_cap) {
     k.total = lay.n_entries;
     e = timed(4, stream, [&] { return launch_select(k, lay.n_entries, stream); });
     if (e == hipSuccess) {
@@ -471,7 +503,8 @@ int of_detect(const of_image* in, const of_params* params, void* ws, size_t ws_b
   if (st) return st;
   if (!ws || !out || !count || cap < params->n_features) return OF_EINVAL;
   const of_params& p = *params;
-  const Tune t = default_tune(p);
+  Tune t = default_tune(p);
+  set_rank_cap(in, 1, p, &t);
   std::lock_guard<std::mutex> lk(g_host.mu);
   CallPlan* c = &g_host.c;
   plan_call(in, 1, p, t, c);
@@ -531,7 +564,10 @@ int check_batch(const of_image* frames, int32_t n, const of_params* params, of_k
     if (st) return st;
   }
   if (!out || !out_offset || !counts || cap_per_frame < params->n_features) return OF_EINVAL;
-  return resolve_tune(tuning, *params, t);
+  st = resolve_tune(tuning, *params, t);
+  if (st) return st;
+  set_rank_cap(frames, n, *params, t);
+  return OF_OK;
 }
 
 // The batched path on a workspace of ws_bytes (the caller holds g_host.mu; c holds the
@@ -764,6 +800,7 @@ int of_describe(const of_image* frames, int32_t n, const of_params* params,
   Tune t;
   st = resolve_tune(tuning, *params, &t);
   if (st) return st;
+  set_rank_cap(frames, n, *params, &t);  // the plan of_detect_batch made for these frames
   std::lock_guard<std::mutex> lk(g_host.mu);
   CallPlan* c = &g_host.c;
   plan_call(frames, n, *params, t, c);

@@ -113,7 +113,7 @@ struct KArgs {
   int32_t small;               // 1: the prefix table of this launch is in sbase
   uint32_t* qctr;              // queue counters: [0] segment-test tiles, [2] Harris tiles
   int32_t cell;                // params.cell
-  int32_t rank_path;           // 1: k_select_orient ranks levels with <= kRankCap candidates
+  int32_t rank_path;           // 1: k_select_orient ranks levels with <= t.rank_cap candidates
   Tune t;
   int32_t pad;
   MarkLds ml;                  // LDS layouts of the tile kernels for this tuning (host-made)

@@ -711,7 +711,7 @@ __global__ __launch_bounds__(1024) void k_prologue(PrologueArgs a) {
   const int64_t o_flag = scan(s.flag_bytes);
   const int64_t o_bm = scan(s.bm_words);
   const int64_t o_cand = scan(s.cand_cap);
-  const int64_t o_rank = scan(s.cand_cap < kRankCap ? s.cand_cap : kRankCap);
+  const int64_t o_rank = scan(s.rank_slots);
   const int64_t t_rank = s_tot;
   const int64_t o_sel = scan(s.sel_cap);
   const int64_t o_lvl = scan(s.lvl_bytes);
@@ -1770,8 +1770,8 @@ __device__ __forceinline__ int level_prefix(const LevelPlan* plan, int entry0,
 // One wave per candidate slot.  A candidate's rank is the number of candidates of its
 // level that rank above it; ranks of the N_l best are exactly their sorted positions, so
 // the wave that holds rank < N_l computes the orientation and writes its keypoint at
-// out[level prefix + rank].  Levels whose candidate count exceeds kRankCap are left to
-// the radix-select path.
+// out[level prefix + rank].  Levels whose candidate count exceeds the call's rank cap
+// are left to the radix-select path.
 __global__ __launch_bounds__(256) void k_select_orient(KArgs a) {
   extern __shared__ __align__(16) uint8_t smem[];  // the level's R' when staged
   __shared__ int32_t s_base[kMaxEntries + 1];
@@ -1835,7 +1835,7 @@ __global__ __launch_bounds__(256) void k_select_orient(KArgs a) {
   Cand me;
   me.score = INT64_MIN;
   me.pos = kNoPos;
-  if (live && i < C && C <= kRankCap) me = load_cand(cand + i);
+  if (live && i < C && C <= h.t.rank_cap) me = load_cand(cand + i);
   int cnt = 0;
   if (staged) {
     int64_t* s_sc = (int64_t*)smem;
@@ -1918,8 +1918,8 @@ __device__ void bitonic_best_first(int64_t* sc, uint32_t* ps, int n) {
   }
 }
 
-// Levels with more than kRankCap candidates: the N-th best score by radix select (8
-// bits at a time), ties at that score by the smallest positions, then a sort.
+// Levels with more candidates than the call's rank cap: the N-th best score by radix
+// select (8 bits at a time), ties at that score by the smallest positions, then a sort.
 __global__ __launch_bounds__(1024) void k_select(KArgs a) {
   __shared__ int64_t sc[kSortCap];
   __shared__ uint32_t ps[kSortCap];
@@ -1934,7 +1934,7 @@ __global__ __launch_bounds__(1024) void k_select(KArgs a) {
   const int nfill = (int)count_sum(G((const uint32_t*)P.cand_count), P.count_stride);
   // slots (empty ones hold the sentinel and are skipped), or the appended entries
   const int C = ranked_candidates(P, (uint32_t)nfill);
-  if (a.rank_path && C <= kRankCap) return;  // handled by k_select_orient
+  if (a.rank_path && C <= a.t.rank_cap) return;  // handled by k_select_orient
   const int nout = min(nfill, N);
   if (nout <= 0) {
     if (threadIdx.x == 0) *G(P.sel_count) = 0;
@@ -2071,12 +2071,13 @@ __global__ __launch_bounds__(256) void k_orient(KArgs a) {
   const LevelPlan P = plan_at(a.plan, e);
   if (wsig != a.sig) return;  // not the plan this launch was made for
   gptr<const uint32_t> counts = G((const uint32_t*)P.cand_count) - e;
-  if (a.rank_path && ranked_candidates(P, count_sum(counts + e, P.count_stride)) <= kRankCap)
+  if (a.rank_path && ranked_candidates(P, count_sum(counts + e, P.count_stride)) <= a.t.rank_cap)
     return;  // k_select_orient's
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int nsel = (int)*G(P.sel_count);
   const int prefix = level_prefix(a.plan, P.entry0, counts + P.entry0, P.count_stride, P.level);
-  if (!a.rank_path && P.level == 0 && chunk == 0 && wave == 0) {
+  // the frame's keypoint count, when its level 0 took this path (else k_select_orient's)
+  if (P.level == 0 && chunk == 0 && wave == 0) {
     const int total =
         level_prefix(a.plan, P.entry0, counts + P.entry0, P.count_stride, P.n_levels);
     if (lane == 0) *G(P.count_out) = total;

@@ -39,6 +39,11 @@ struct Tune {
   int32_t mark_order;  // 1: segment-test tiles in XCD bands (block b on XCD b % 8)
   int32_t plan_resident;  // 1: skip the prologue when this workspace holds this plan
   int32_t det_order;  // 1: Harris/NMS tiles in the segment test's XCD bands
+  // Largest candidate count of a level that the selection ranks by counting (at most
+  // kRankCap); larger levels take the radix select.  Set per call from its size: counting
+  // costs C^2 per level but runs every slot's wave at once (shortest for a few frames),
+  // the radix select costs a few passes over C in one block per level.
+  int32_t rank_cap;
 };
 
 constexpr int kXcds = 8;  // blocks are dispatched to the XCDs round-robin by block index
@@ -206,6 +211,8 @@ struct EntrySize {
   int32_t slot_w;       // slots per row of 2x2 blocks (no cells)
   int32_t kslot;        // slots per cell (cells): K_l capped by the survivors a cell holds
   int32_t pyr_blocks;   // 64 x 16 resample blocks of a level >= 1
+  int32_t rank_slots;   // waves of the counting selection: the slots of a level it ranks,
+                        // none past the rank cap (an appended list: up to the cap)
 };
 
 OF_HD void entry_size(const FrameGeom& g, const of_params& p, const Tune& t, int l,
@@ -251,6 +258,11 @@ OF_HD void entry_size(const FrameGeom& g, const of_params& p, const Tune& t, int
     }
   }
   s->det_tiles = s->det_tx * s->det_ty;
+  // Fixed slots are ranked by counting only up to the rank cap; an appended list (a
+  // whole-level cell past kRankCap) has a length known only on the device, so it gets
+  // the cap's waves and takes whichever path its length falls to.
+  const bool appended = p.cell == 0 && s->cand_cap > kRankCap;
+  s->rank_slots = appended ? t.rank_cap : (s->cand_cap <= t.rank_cap ? (int32_t)s->cand_cap : 0);
   s->sel_cap = g.quota[l];
   int32_t ob = cdiv(g.quota[l], kOrientPerBlock);
   s->orient_blocks = ob < 1 ? 1 : ob;
@@ -260,8 +272,9 @@ OF_HD void entry_size(const FrameGeom& g, const of_params& p, const Tune& t, int
 
 // Candidates the level selection ranks for a level: its slots (fixed slots, empty ones
 // holding the sentinel), or the survivors its tiles appended (a whole-level cell past the
-// rank cap: a dense list of `filled` entries).  Levels with at most kRankCap of them are
-// ranked by counting (k_select_orient); the rest take the radix select.
+// rank cap: a dense list of `filled` entries).  Levels with at most the call's rank cap
+// (Tune::rank_cap) of them are ranked by counting (k_select_orient); the rest take the
+// radix select.
 OF_HD int32_t ranked_candidates(const LevelPlan& P, uint32_t filled) {
   return P.compact ? ((int64_t)filled < P.cand_cap ? (int32_t)filled : P.cand_cap) : P.cand_cap;
 }
@@ -298,7 +311,7 @@ OF_HD void ws_layout_accumulate(WsLayout* w, const EntrySize& s) {
   w->flag_bytes += s.flag_bytes;
   w->bm_words += s.bm_words;
   w->cand_entries += s.cand_cap;
-  w->rank_slots += (int32_t)(s.cand_cap < kRankCap ? s.cand_cap : kRankCap);
+  w->rank_slots += s.rank_slots;
   if (s.cand_cap > w->max_cand_cap) w->max_cand_cap = (int32_t)s.cand_cap;
   w->sel_entries += s.sel_cap;
   w->lvl_bytes += s.lvl_bytes;

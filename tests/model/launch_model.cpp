@@ -250,7 +250,7 @@ hipError_t launch_prologue(const PrologueArgs& a, int grid, hipStream_t) {
       o_flag += s.flag_bytes;
       o_bm += s.bm_words;
       o_cand += s.cand_cap;
-      o_rank += std::min<int64_t>(s.cand_cap, kRankCap);
+      o_rank += s.rank_slots;
       o_sel += s.sel_cap;
       o_lvl += s.lvl_bytes;
       o_pyr += s.pyr_blocks;
@@ -731,24 +731,24 @@ hipError_t launch_select_orient(const KArgs& a, int slots, hipStream_t) {
   a.qctr[0] = 0;
   CHECK((int64_t)8 * a.sel_lds <= 65536 - 4100, "k_select_orient: LDS");
   const int nslots = table_total(a, a.rank_base, 0);
-  CHECK(nslots == slots, "k_select_orient: %d slots launched for %d", slots, nslots);
+  CHECK(slots == std::max(nslots, 1), "k_select_orient: %d slots launched for %d", slots, nslots);
   // per entry: the slot range, ranked candidates and outputs
   for (int e = 0; e < a.n_entries; ++e) {
     const LevelPlan& P = plan(a, e);
     int ee, s0, en;
     const int32_t first = a.small ? a.sbase[e] : a.rank_base[e];
     if (!a.small) acc(a.rank_base + e, 4, "rank prefix");
-    if (e + 1 < a.n_entries) {
-      const int32_t next = a.small ? a.sbase[e + 1] : a.rank_base[e + 1];
-      if (next == first) continue;  // an entry without slots
-    }
+    const int32_t next = e + 1 < a.n_entries ? (a.small ? a.sbase[e + 1] : a.rank_base[e + 1])
+                                             : nslots;
+    if (next == first) continue;  // an entry without slots (its level takes the radix path)
     entry_of(a, a.rank_base, 0, first, &ee, &s0, &en);
     CHECK(ee == e || first == en, "k_select_orient: slot %d of entry %d found in entry %d",
           first, e, ee);
     const int C = ranked_candidates(P, (uint32_t)model_filled(P));
-    CHECK(en - s0 == std::min(P.cand_cap, kRankCap), "k_select_orient: entry %d has %d slots", e,
-          en - s0);
-    if (C <= kRankCap) {
+    const int want = P.compact ? std::min(P.cand_cap, a.t.rank_cap)
+                               : (P.cand_cap <= a.t.rank_cap ? P.cand_cap : 0);
+    CHECK(en - s0 == want, "k_select_orient: entry %d has %d slots", e, en - s0);
+    if (C <= a.t.rank_cap) {
       acc(P.cand, (int64_t)sizeof(Cand) * C, "k_select_orient candidate reads");
       if (a.sel_lds > 0 && C <= a.sel_lds) lds(0, 8 * (int64_t)C, 0, 8 * (int64_t)a.sel_lds,
                                                 "k_select_orient staged R'");
@@ -775,7 +775,7 @@ hipError_t launch_select(const KArgs& a, int grid, hipStream_t) {
     const LevelPlan& P = plan(a, e);
     const int nfill = model_filled(P);
     const int C = ranked_candidates(P, (uint32_t)nfill);
-    if (a.rank_path && C <= kRankCap) continue;
+    if (a.rank_path && C <= a.t.rank_cap) continue;
     acc(P.cand, (int64_t)sizeof(Cand) * C, "k_select candidate reads");
     const int nout = std::min(nfill, P.quota);
     CHECK(nout <= kSortCap, "k_select: %d selected > sort capacity", nout);
@@ -800,7 +800,7 @@ hipError_t launch_orient(const KArgs& a, int grid, hipStream_t) {
     }
     const LevelPlan& P = plan(a, e);
     const int C = ranked_candidates(P, (uint32_t)model_filled(P));
-    if (a.rank_path && C <= kRankCap) continue;
+    if (a.rank_path && C <= a.t.rank_cap) continue;
     const int i_last = chunk * kOrientPerBlock + kOrientPerBlock - 1;
     const int nsel = std::min(P.quota, model_filled(P));
     if (chunk * kOrientPerBlock >= nsel) continue;

@@ -262,6 +262,12 @@ def test_equal_scores_across_cells(hip):
         assert len(set(ref["score"].tolist())) <= 4
         assert_same_keypoints(run_batch(hip, [img], kw)[0], ref, "batch")
         assert_same_keypoints(run_plain(hip, img, kw), ref, "plain")
+    # three copies of the large case in one call: counting work past the few-frame budget,
+    # so its level (4,800 slots, every winner tied) takes the radix select with the ties
+    # settled by position
+    log(f"case: equal scores, 3 x {img.shape}, radix select")
+    for i, got in enumerate(run_batch(hip, [img] * 3, kw)):
+        assert_same_keypoints(got, ref, f"batch copy {i}")
 
 
 @pytest.mark.parametrize("L,N", [(1, 4000), (4, 8000), (1, 2000), (4, 2000)])
