@@ -264,8 +264,10 @@ int of_test_segment(const uint8_t* circles, int32_t n, int32_t t_lo, int32_t t_h
 /* Step timing.  While enabled (host call, not during graph capture), of_detect and
  * of_detect_batch attach two HIP events to each step launch's dispatch on their stream,
  * recorded as the kernel begins and as it ends:
- * step 0 prologue, 1 pyramid, 2 segment test, 3 Harris/NMS/cells, 4 level selection,
- * 5 orientation; the ablation entry points are steps 6 (segment test) and 7 (Harris).  of_profile_read waits for the recorded events, writes the summed
+ * step 0 prologue, 1 pyramid, 2 segment test, 3 Harris/NMS/cells, 4 level selection
+ * (counting, and the radix select of levels past the call's rank cap), 5 ranking of the
+ * radix-selected lists; the ablation entry points are steps 6 (segment test) and 7
+ * (Harris).  of_profile_read waits for the recorded events, writes the summed
  * milliseconds and launch counts of the first n steps (host arrays) and clears them.
  * Events come from a fixed pool created on the first enable; launches beyond the pool
  * are not timed (their count is still reported in launches[]).  on > 1 also issues each

@@ -212,12 +212,15 @@ int resolve_tune(const of_tuning* user, const of_params& p, Tune* out) {
 // C^2 compares per level of C candidate slots but runs every slot's wave at once, which is
 // the shortest path while the call's counting work is small (up to a few 1080p frames:
 // about 10M compares each); past that, the radix select (a few passes over C in one
-// block per level, every level at once) takes the levels above kRankCapBusy, whose C^2
-// dominates the counting work.  Levels with appended lists (whole-level cells past
-// kRankCap) count no work here: their length is known only on the device, which takes
-// the radix path when it exceeds the cap.
+// block per level, every level at once, then a count over the N_l it keeps) takes every
+// level above kRankCapBusy slots.  On a single 1080p frame the radix path takes 60 us
+// per call against 43.5 for counting; on 16 such frames 385 us against 422, and 2.07 ms
+// against 2.65 on 16 frames of 3840 x 2160 (caps of 512 and 4096 were slower there).
+// Levels with appended lists (whole-level cells past kRankCap) count no work here:
+// their length is known only on the device, which takes the radix path when it
+// exceeds the cap.
 constexpr int64_t kRankWorkFew = 40000000;
-constexpr int32_t kRankCapBusy = kSortCap;
+constexpr int32_t kRankCapBusy = 128;
 
 void set_rank_cap(const of_image* frames, int n, const of_params& p, Tune* t) {
   t->rank_cap = kRankCap;
@@ -320,7 +323,7 @@ KArgs kargs(void* ws, const WsLayout& lay, const Tune& t, const of_params& p) {
   k.plan = (LevelPlan*)(b + lay.off_plan);
   k.mark_base = (const int32_t*)(b + lay.off_mark_base);
   k.det_base = (const int32_t*)(b + lay.off_det_base);
-  k.orient_base = (const int32_t*)(b + lay.off_orient_base);
+  k.sel_base = (const int32_t*)(b + lay.off_sel_base);
   k.rank_base = (const int32_t*)(b + lay.off_rank_base);
   k.pyr_base = (const int32_t*)(b + lay.off_pyr_base);
   k.counters = (uint32_t*)(b + lay.off_counters);
@@ -340,7 +343,7 @@ KArgs kargs(void* ws, const WsLayout& lay, const Tune& t, const of_params& p) {
   return k;
 }
 
-enum BaseKind { kMarkTiles, kMarkBands, kDetTiles, kDetBands, kRankSlots, kPyrBlocks };
+enum BaseKind { kMarkTiles, kMarkBands, kDetTiles, kDetBands, kRankSlots, kSelSlots, kPyrBlocks };
 
 // The launch's prefix table (units per entry), copied into the kernel arguments when the
 // call has at most kSmallEntries entries; the kernels then skip loading it.
@@ -349,7 +352,7 @@ void set_small_bases(KArgs& k, const CallPlan& c, BaseKind kind) {
   k.small = n <= kSmallEntries;
   if (!k.small) return;
   // the tile kernels read row blockIdx % kXcds (their band, or a copy of row 0)
-  const int rows = kind == kRankSlots || kind == kPyrBlocks ? 1 : kXcds;
+  const int rows = kind == kRankSlots || kind == kSelSlots || kind == kPyrBlocks ? 1 : kXcds;
   for (int r = 0; r < rows; ++r) {
     int32_t* b = k.sbase + r * (kSmallEntries + 1);
     int32_t acc = 0, rot = 0, drot = 0;
@@ -368,6 +371,7 @@ void set_small_bases(KArgs& k, const CallPlan& c, BaseKind kind) {
           drot = (drot + s.det_ty % kXcds) % kXcds;
           break;
         case kRankSlots: acc += s.rank_slots; break;
+        case kSelSlots: acc += s.sel_slots; break;
         case kPyrBlocks: acc += s.pyr_blocks; break;
       }
     }
@@ -378,8 +382,8 @@ void set_small_bases(KArgs& k, const CallPlan& c, BaseKind kind) {
 }
 
 // Level selection + orientation: ranks by counting for every level up to the call's
-// rank cap, and the radix select + separate orientation only when some level could
-// exceed it.
+// rank cap; when some level can exceed it, the radix select lists the best N_l of each
+// such level and a second counting launch ranks those lists.
 hipError_t launch_selection(KArgs k, const CallPlan& c, hipStream_t stream) {
   const WsLayout& lay = c.lay;
   k.entry = -1;
@@ -398,12 +402,19 @@ hipError_t launch_selection(KArgs k, const CallPlan& c, hipStream_t stream) {
   // radix path ranks nothing here).
   const int32_t slots = std::max<int32_t>(lay.rank_slots, 1);
   hipError_t e = timed(4, stream, [&] { return launch_select_orient(k, slots, stream); }, true);
-  if (e == hipSuccess && lay.max_cand_cap > k.t.rank_cap) {
+  if (e == hipSuccess && lay.sel_slots > 0) {
     k.total = lay.n_entries;
     e = timed(4, stream, [&] { return launch_select(k, lay.n_entries, stream); });
     if (e == hipSuccess) {
-      k.total = lay.orient_blocks;
-      e = timed(5, stream, [&] { return launch_orient(k, lay.orient_blocks, stream); });
+      // the lists (at most N_l <= kSortCap long) ranked by the same kernel, staged
+      k.from_sel = 1;
+      k.flags = nullptr;  // cleared by the first launch
+      k.rank_base = k.sel_base;
+      set_small_bases(k, c, kSelSlots);
+      int32_t longest = 0;
+      for (int i = 0; i < lay.n_entries; ++i) longest = std::max(longest, c.es[i].sel_slots);
+      k.sel_lds = std::min(longest, kSortCap);
+      e = timed(5, stream, [&] { return launch_select_orient(k, lay.sel_slots, stream); }, true);
     }
   }
   return e;

@@ -90,7 +90,6 @@ OF_HD void fill_level_plan(LevelPlan& P, const PrologueArgs& a, uint8_t* ws, con
   P.det_y0 = s.det_y0;
   P.det_xend = s.det_xend;
   P.det_yend = s.det_yend;
-  P.orient_blocks = s.orient_blocks;
   P.entry0 = f * L;
   P.out = a.out + a.f[f].out_off;
   P.count_out = a.counts + f;
@@ -126,13 +125,15 @@ struct KArgs {
   int32_t* frame_counts;
   const int32_t* mark_base;    // exclusive prefix of tiles per entry (n_entries + 1)
   const int32_t* det_base;
-  const int32_t* orient_base;
-  const int32_t* rank_base;    // exclusive prefix of ranked candidate slots per entry
+  const int32_t* sel_base;     // exclusive prefix of selection-list slots per entry
+  const int32_t* rank_base;    // exclusive prefix of the slots a counting launch ranks per
+                               // entry (rank_slots, or sel_slots for a from_sel launch)
   const int32_t* pyr_base;     // exclusive prefix of resample blocks per entry
   const int32_t* band_base;    // kXcds tables: prefix of segment-test tiles per entry in band k
   const int32_t* det_band_base;  // the same for Harris/NMS tiles
   int32_t n_frames;
   int32_t sel_lds;             // level R' the selection stages in LDS (0: none)
+  int32_t from_sel;            // 1: k_select_orient ranks each level's radix-selected list
   int32_t det_rev;             // 1: Harris/NMS tiles taken last first (grid resident at once)
   int32_t mark_rev;            // 1: segment-test tiles taken last first (grid resident at once)
   // Batches of at most kSmallEntries entries carry the launch's prefix table here, so
@@ -172,7 +173,6 @@ hipError_t launch_scale_counters(const KArgs& a, int times, hipStream_t s);
 hipError_t launch_sum_fast_counts(const uint32_t* counters, int n, int32_t* out, hipStream_t s);
 hipError_t launch_select_orient(const KArgs& a, int slots, hipStream_t s);
 hipError_t launch_select(const KArgs& a, int grid, hipStream_t s);
-hipError_t launch_orient(const KArgs& a, int grid, hipStream_t s);
 // Arguments of the rBRIEF launch: keypoints of n frames (cap slots each) described on
 // the levels of the plan in the workspace, which must carry signature `sig`.
 struct DescArgs {

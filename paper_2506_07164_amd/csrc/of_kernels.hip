@@ -10,7 +10,8 @@
 //                       (Sec. 3.2 / Eq. 4, 7x7 window), 3x3 NMS, per-cell top-K
 //   k_select_orient  -- per-level top-N_l by (R' desc, y asc, x asc) through rank counts,
 //                       fused with the intensity-centroid orientation of each winner
-//   k_select, k_orient -- radix-select fallback for levels with very many candidates
+//   k_select         -- radix select of the best N_l of levels with very many candidates
+//                       into a short list, which a second k_select_orient launch ranks
 // Wave64 throughout; nothing here is a dense contraction, so there is no MFMA use.
 #include <hip/hip_runtime.h>
 
@@ -706,8 +707,8 @@ __global__ __launch_bounds__(1024) void k_prologue(PrologueArgs a) {
   const int64_t t_mark = s_tot;
   const int64_t o_det = scan(s.det_tiles);
   const int64_t t_det = s_tot;
-  const int64_t o_or = scan(s.orient_blocks);
-  const int64_t t_or = s_tot;
+  const int64_t o_sl = scan(s.sel_slots);
+  const int64_t t_sl = s_tot;
   const int64_t o_flag = scan(s.flag_bytes);
   const int64_t o_bm = scan(s.bm_words);
   const int64_t o_cand = scan(s.cand_cap);
@@ -737,7 +738,7 @@ __global__ __launch_bounds__(1024) void k_prologue(PrologueArgs a) {
   LevelPlan* plan = (LevelPlan*)(ws + a.lay.off_plan);
   int32_t* mark_base = (int32_t*)(ws + a.lay.off_mark_base);
   int32_t* det_base = (int32_t*)(ws + a.lay.off_det_base);
-  int32_t* or_base = (int32_t*)(ws + a.lay.off_orient_base);
+  int32_t* sl_base = (int32_t*)(ws + a.lay.off_sel_base);
   int32_t* rank_base = (int32_t*)(ws + a.lay.off_rank_base);
   int32_t* pyr_base = (int32_t*)(ws + a.lay.off_pyr_base);
   uint32_t* counters = (uint32_t*)(ws + a.lay.off_counters);
@@ -749,14 +750,14 @@ __global__ __launch_bounds__(1024) void k_prologue(PrologueArgs a) {
     plan[i] = P;
     mark_base[i] = (int32_t)o_mark;
     det_base[i] = (int32_t)o_det;
-    or_base[i] = (int32_t)o_or;
+    sl_base[i] = (int32_t)o_sl;
     rank_base[i] = (int32_t)o_rank;
     pyr_base[i] = (int32_t)o_pyr;
   }
   if (i == 0) {
     mark_base[nL] = (int32_t)t_mark;
     det_base[nL] = (int32_t)t_det;
-    or_base[nL] = (int32_t)t_or;
+    sl_base[nL] = (int32_t)t_sl;
     rank_base[nL] = (int32_t)t_rank;
     pyr_base[nL] = (int32_t)t_pyr;
   }
@@ -1771,7 +1772,8 @@ __device__ __forceinline__ int level_prefix(const LevelPlan* plan, int entry0,
 // level that rank above it; ranks of the N_l best are exactly their sorted positions, so
 // the wave that holds rank < N_l computes the orientation and writes its keypoint at
 // out[level prefix + rank].  Levels whose candidate count exceeds the call's rank cap
-// are left to the radix-select path.
+// are left to the radix select, which lists their best N_l for a second launch of this
+// kernel (from_sel) to rank the same way.
 __global__ __launch_bounds__(256) void k_select_orient(KArgs a) {
   extern __shared__ __align__(16) uint8_t smem[];  // the level's R' when staged
   __shared__ int32_t s_base[kMaxEntries + 1];
@@ -1819,23 +1821,25 @@ __global__ __launch_bounds__(256) void k_select_orient(KArgs a) {
   const LevelPlan P = plan_at(h.plan, e);
   if (wsig != h.sig) return;
   gptr<const uint32_t> counts = G((const uint32_t*)P.cand_count) - e;  // all entries
-  // empty slots hold the sentinel; only an appended level's count bounds its list
-  const int C = P.compact ? ranked_candidates(P, count_sum(counts + e, P.count_stride))
-                          : P.cand_cap;
+  // empty slots hold the sentinel; only an appended level's count bounds its list (and
+  // a radix-selected list its own count)
+  const int C = a.from_sel ? min((int)*G((const uint32_t*)P.sel_count), P.quota)
+                : P.compact ? ranked_candidates(P, count_sum(counts + e, P.count_stride))
+                            : P.cand_cap;
   if (live && P.level == 0 && i == 0) {
     const int total =
         level_prefix(a.plan, P.entry0, counts + P.entry0, P.count_stride, P.n_levels);
     if (lane == 0) *G(P.count_out) = total;
   }
   if (one && slot0 - st0 >= C) return;  // the block's slots are past the level's list
-  gptr<const Cand> cand = G((const Cand*)P.cand);
+  gptr<const Cand> cand = G((const Cand*)(a.from_sel ? P.sel : P.cand));
   // A block whose slots all belong to one level that fits the LDS stages the level's
   // R' once (one load per 256 slots per thread, all in flight) and ranks from there.
   const bool staged = a.sel_lds > 0 && one && C <= a.sel_lds;
   Cand me;
   me.score = INT64_MIN;
   me.pos = kNoPos;
-  if (live && i < C && C <= h.t.rank_cap) me = load_cand(cand + i);
+  if (live && i < C && (a.from_sel || C <= h.t.rank_cap)) me = load_cand(cand + i);
   int cnt = 0;
   if (staged) {
     int64_t* s_sc = (int64_t*)smem;
@@ -1894,206 +1898,237 @@ __device__ __forceinline__ uint64_t score_key(int64_t s) {
   return (uint64_t)s ^ 0x8000000000000000ull;
 }
 
-// Bitonic sort of n (power of two) entries in LDS, best first.
-__device__ void bitonic_best_first(int64_t* sc, uint32_t* ps, int n) {
-  for (int k = 2; k <= n; k <<= 1) {
-    for (int j = k >> 1; j > 0; j >>= 1) {
-      for (int i = threadIdx.x; i < n; i += blockDim.x) {
-        const int ixj = i ^ j;
-        if (ixj > i) {
-          const int64_t x = sc[i], y = sc[ixj];
-          const uint32_t px = ps[i], py = ps[ixj];
-          const bool first_half = (i & k) == 0;
-          const bool swap = first_half ? better(y, py, x, px) : better(x, px, y, py);
-          if (swap) {
-            sc[i] = y;
-            sc[ixj] = x;
-            ps[i] = py;
-            ps[ixj] = px;
-          }
-        }
-      }
-      __syncthreads();
-    }
+// Adds 1 to bin b of an LDS histogram for every active lane (act): a wave whose active
+// lanes share one bin adds its count once (the high digits of nearby scores mostly
+// agree, and same-address LDS atomics are performed one lane at a time); otherwise each
+// lane adds its own.
+__device__ __forceinline__ void hist_add(uint32_t* hist, uint32_t b, bool act) {
+  const uint64_t m = __ballot(act);
+  if (!m) return;
+  const uint32_t b0 = (uint32_t)__builtin_amdgcn_readlane((int)b, __builtin_ctzll(m));
+  if (__ballot(act && b == b0) == m) {
+    if (act && lanes_below(m) == 0) atomicAdd(&hist[b0], (uint32_t)__popcll(m));
+  } else if (act) {
+    atomicAdd(&hist[b], 1u);
   }
 }
 
-// Levels with more candidates than the call's rank cap: the N-th best score by radix
-// select (8 bits at a time), ties at that score by the smallest positions, then a sort.
+// Slot in an LDS list for every active lane: one counter atomic per wave, lanes placed in
+// lane order after it.
+__device__ __forceinline__ uint32_t list_slot(uint32_t* count, bool act) {
+  const uint64_t m = __ballot(act);
+  uint32_t base = 0;
+  if (m) {
+    const int first = __builtin_ctzll(m);
+    if ((int)(threadIdx.x & 63) == first) base = atomicAdd(count, (uint32_t)__popcll(m));
+    base = (uint32_t)__builtin_amdgcn_readlane((int)base, first);
+  }
+  return base + lanes_below(m);
+}
+
+// Digit of a 256-bin histogram at which the running count, taken from the high digits
+// down (desc) or from the low digits up, first reaches k (k >= 1, at most the total), and
+// the count of the digits before it.  Run by one whole wave: lane l sums four bins, a
+// wave scan gives each lane the count before its bins, and the first lane whose bins
+// reach k walks them.
+__device__ __forceinline__ void hist_find(const uint32_t* hist, uint32_t k, bool desc, int* digit,
+                                          uint32_t* before) {
+  const int lane = (int)(threadIdx.x & 63);
+  uint32_t h[4], sum = 0;
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    h[j] = hist[desc ? 255 - 4 * lane - j : 4 * lane + j];
+    sum += h[j];
+  }
+  const uint32_t incl = wave_incl_scan(sum);
+  const uint64_t m = __ballot(incl >= k);
+  const int L = m ? __builtin_ctzll(m) : 63;
+  int d = 0;
+  uint32_t acc = incl - sum;
+  if (lane == L) {
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      d = desc ? 255 - 4 * lane - j : 4 * lane + j;
+      if (acc + h[j] >= k) break;
+      acc += h[j];
+    }
+  }
+  *digit = __builtin_amdgcn_readlane(d, L);
+  *before = (uint32_t)__builtin_amdgcn_readlane((int)acc, L);
+}
+
+// Threshold of the best k of a level's candidates, by radix select: the k-th best score
+// key T (8 bits at a time from the top), and, when more candidates than the k needed
+// hold T, the largest position pcut among the smallest positions that complete the k
+// (8 bits at a time from the top); else pcut = 0xffffffff.  The best k are those with
+// key > T, or key == T and position <= pcut.  get(i, &key, &pos) reads candidate i < n
+// (false: an empty slot); every thread of the block calls this.
+template <class Get>
+__device__ void radix_threshold(Get get, int n, uint32_t k, uint32_t* hist, uint64_t* s_key,
+                                uint32_t* s_k, uint32_t* s_eq, uint64_t* T, uint32_t* pcut) {
+  const int tid = (int)threadIdx.x, bd = (int)blockDim.x;
+  if (tid == 0) {
+    *s_key = 0;
+    *s_k = k;
+    *s_eq = 0;
+  }
+  uint64_t mask = 0;
+  for (int shift = 56; shift >= 0; shift -= 8) {
+    for (int i = tid; i < 256; i += bd) hist[i] = 0;
+    __syncthreads();
+    const uint64_t prefix = *s_key;
+    for (int i0 = 0; i0 < n; i0 += bd) {  // whole waves in every step
+      uint64_t u = 0;
+      uint32_t pos = 0;
+      const bool ok = i0 + tid < n && get(i0 + tid, &u, &pos);
+      hist_add(hist, (uint32_t)(u >> shift) & 255u, ok && (u & mask) == prefix);
+    }
+    __syncthreads();
+    if (tid < 64) {
+      int dg;
+      uint32_t before;
+      hist_find(hist, *s_k, true, &dg, &before);
+      if (tid == 0) {
+        *s_k -= before;
+        *s_key = prefix | ((uint64_t)dg << shift);
+      }
+    }
+    mask |= 255ull << shift;
+    __syncthreads();
+  }
+  *T = *s_key;
+  const uint32_t k_eq = *s_k;  // candidates at T that the k still needs
+  for (int i0 = 0; i0 < n; i0 += bd) {
+    uint64_t u = 0;
+    uint32_t pos = 0;
+    const bool ok = i0 + tid < n && get(i0 + tid, &u, &pos);
+    hist_add(s_eq, 0u, ok && u == *T);
+  }
+  __syncthreads();
+  *pcut = 0xffffffffu;
+  if (*s_eq <= k_eq) return;  // every candidate at T is needed (block-uniform)
+  __syncthreads();  // every thread has read s_eq
+  if (tid == 0) {
+    *s_key = 0;
+    *s_k = k_eq;
+  }
+  uint32_t pmask = 0;
+  for (int shift = 24; shift >= 0; shift -= 8) {
+    for (int i = tid; i < 256; i += bd) hist[i] = 0;
+    __syncthreads();
+    const uint32_t pp = (uint32_t)*s_key;
+    for (int i0 = 0; i0 < n; i0 += bd) {
+      uint64_t u = 0;
+      uint32_t pos = 0;
+      const bool ok = i0 + tid < n && get(i0 + tid, &u, &pos);
+      hist_add(hist, (pos >> shift) & 255u, ok && u == *T && (pos & pmask) == pp);
+    }
+    __syncthreads();
+    if (tid < 64) {
+      int dg;
+      uint32_t before;
+      hist_find(hist, *s_k, false, &dg, &before);
+      if (tid == 0) {
+        *s_k -= before;
+        *s_key = pp | ((uint32_t)dg << shift);
+      }
+    }
+    pmask |= 255u << shift;
+    __syncthreads();
+  }
+  *pcut = (uint32_t)*s_key;
+}
+
+// Levels with more candidates than the call's rank cap (one block per level): the best
+// min(filled, N_l) candidates, found by radix select from the level's slots (or from
+// its filled slots gathered into LDS when they fit), are written unsorted to the level's
+// selection list; k_select_orient then ranks that short list by counting.  A level that
+// the first counting launch took gets an empty list.
 __global__ __launch_bounds__(1024) void k_select(KArgs a) {
   __shared__ int64_t sc[kSortCap];
   __shared__ uint32_t ps[kSortCap];
   __shared__ uint32_t hist[256];
-  __shared__ uint64_t s_prefix;
+  __shared__ uint64_t s_key;
   __shared__ uint32_t s_k, s_n, s_eq;
   const int e = a.entry >= 0 ? a.entry : (int)blockIdx.x;
   const uint64_t wsig = *(cptr<uint64_t>)a.ws_sig;
   const LevelPlan P = plan_at(a.plan, e);
   if (wsig != a.sig) return;  // not the plan this launch was made for
+  const int tid = (int)threadIdx.x, bd = (int)blockDim.x;
   const int N = P.quota;
   const int nfill = (int)count_sum(G((const uint32_t*)P.cand_count), P.count_stride);
   // slots (empty ones hold the sentinel and are skipped), or the appended entries
   const int C = ranked_candidates(P, (uint32_t)nfill);
-  if (a.rank_path && C <= a.t.rank_cap) return;  // handled by k_select_orient
   const int nout = min(nfill, N);
-  if (nout <= 0) {
-    if (threadIdx.x == 0) *G(P.sel_count) = 0;
+  if ((a.rank_path && C <= a.t.rank_cap) || nout <= 0) {  // nothing for the list
+    if (tid == 0) *G(P.sel_count) = 0;
     return;
   }
   gptr<const Cand> cand = G((const Cand*)P.cand);
-  int nsort;
-  if (nfill <= kSortCap) {  // every filled slot fits: gather them all
-    if (threadIdx.x == 0) s_n = 0;
-    __syncthreads();
-    for (int i = threadIdx.x; i < C; i += blockDim.x) {
-      const Cand cd = load_cand(cand + i);
-      if (cd.pos != kNoPos) {
-        const uint32_t slot = atomicAdd(&s_n, 1u);
-        if (slot < (uint32_t)kSortCap) {
-          sc[slot] = cd.score;
-          ps[slot] = cd.pos;
-        }
-      }
-    }
-    __syncthreads();
-    nsort = min((int)s_n, kSortCap);
-  } else {
-    if (threadIdx.x == 0) {
-      s_prefix = 0;
-      s_k = (uint32_t)N;
-    }
-    uint64_t mask = 0;
-    for (int shift = 56; shift >= 0; shift -= 8) {
-      for (int i = threadIdx.x; i < 256; i += blockDim.x) hist[i] = 0;
-      __syncthreads();
-      const uint64_t prefix = s_prefix;
-      for (int i = threadIdx.x; i < C; i += blockDim.x) {
-        const Cand cd = load_cand(cand + i);
-        const uint64_t u = score_key(cd.score);
-        if (cd.pos != kNoPos && (u & mask) == prefix) atomicAdd(&hist[(u >> shift) & 255u], 1u);
-      }
-      __syncthreads();
-      if (threadIdx.x == 0) {
-        uint32_t acc = 0, k = s_k;
-        int dsel = 0;
-        for (int dgt = 255; dgt >= 0; --dgt) {
-          if (acc + hist[dgt] >= k) {
-            dsel = dgt;
-            break;
-          }
-          acc += hist[dgt];
-        }
-        s_k = k - acc;
-        s_prefix = prefix | ((uint64_t)dsel << shift);
-      }
-      mask |= 255ull << shift;
-      __syncthreads();
-    }
-    const uint64_t T = s_prefix;
-    const uint32_t k_eq = s_k;
-    if (threadIdx.x == 0) s_eq = 0;
-    __syncthreads();
-    for (int i = threadIdx.x; i < C; i += blockDim.x) {
-      const Cand cd = load_cand(cand + i);
-      if (cd.pos != kNoPos && score_key(cd.score) == T) atomicAdd(&s_eq, 1u);
-    }
-    __syncthreads();
-    uint32_t pcut = 0xffffffffu;
-    if (s_eq > k_eq) {
-      if (threadIdx.x == 0) {
-        s_prefix = 0;
-        s_k = k_eq;
-      }
-      uint32_t pmask = 0;
-      for (int shift = 24; shift >= 0; shift -= 8) {
-        for (int i = threadIdx.x; i < 256; i += blockDim.x) hist[i] = 0;
-        __syncthreads();
-        const uint32_t pp = (uint32_t)s_prefix;
-        for (int i = threadIdx.x; i < C; i += blockDim.x) {
-          const Cand cd = load_cand(cand + i);
-          if (cd.pos != kNoPos && score_key(cd.score) == T && (cd.pos & pmask) == pp)
-            atomicAdd(&hist[(cd.pos >> shift) & 255u], 1u);
-        }
-        __syncthreads();
-        if (threadIdx.x == 0) {
-          uint32_t acc = 0, k = s_k;
-          int dsel = 0;
-          for (int dgt = 0; dgt < 256; ++dgt) {
-            if (acc + hist[dgt] >= k) {
-              dsel = dgt;
-              break;
-            }
-            acc += hist[dgt];
-          }
-          s_k = k - acc;
-          s_prefix = pp | ((uint32_t)dsel << shift);
-        }
-        pmask |= 255u << shift;
-        __syncthreads();
-      }
-      pcut = (uint32_t)s_prefix;
-    }
-    if (threadIdx.x == 0) s_n = 0;
-    __syncthreads();
-    for (int i = threadIdx.x; i < C; i += blockDim.x) {
-      const Cand cd = load_cand(cand + i);
-      const uint64_t u = score_key(cd.score);
-      if (cd.pos != kNoPos && (u > T || (u == T && cd.pos <= pcut))) {
-        const uint32_t slot = atomicAdd(&s_n, 1u);
-        if (slot < (uint32_t)kSortCap) {
-          sc[slot] = cd.score;
-          ps[slot] = cd.pos;
-        }
-      }
-    }
-    __syncthreads();
-    nsort = min((int)s_n, kSortCap);
-  }
-  int n2 = 1;
-  while (n2 < nsort) n2 <<= 1;
-  for (int i = nsort + threadIdx.x; i < n2; i += blockDim.x) {
-    sc[i] = INT64_MIN;
-    ps[i] = 0xffffffffu;
-  }
-  __syncthreads();
-  bitonic_best_first(sc, ps, n2);
   gptr<Cand> sel = G(P.sel);
-  for (int i = threadIdx.x; i < nout; i += blockDim.x) store_cand(sel + i, sc[i], ps[i]);
-  if (threadIdx.x == 0) *G(P.sel_count) = (uint32_t)nout;
-}
-
-// Orientation of the radix-selected keypoints: one wave per keypoint.
-__global__ __launch_bounds__(256) void k_orient(KArgs a) {
-  const int b = (int)blockIdx.x;
-  const int e = a.entry >= 0 ? a.entry : prefix_entry(a.orient_base, a.n_entries, b);
-  const int chunk = a.entry >= 0 ? b : b - a.orient_base[e];
-  const uint64_t wsig = *(cptr<uint64_t>)a.ws_sig;
-  const LevelPlan P = plan_at(a.plan, e);
-  if (wsig != a.sig) return;  // not the plan this launch was made for
-  gptr<const uint32_t> counts = G((const uint32_t*)P.cand_count) - e;
-  if (a.rank_path && ranked_candidates(P, count_sum(counts + e, P.count_stride)) <= a.t.rank_cap)
-    return;  // k_select_orient's
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int nsel = (int)*G(P.sel_count);
-  const int prefix = level_prefix(a.plan, P.entry0, counts + P.entry0, P.count_stride, P.level);
-  // the frame's keypoint count, when its level 0 took this path (else k_select_orient's)
-  if (P.level == 0 && chunk == 0 && wave == 0) {
-    const int total =
-        level_prefix(a.plan, P.entry0, counts + P.entry0, P.count_stride, P.n_levels);
-    if (lane == 0) *G(P.count_out) = total;
+  if (tid == 0) s_n = 0;
+  __syncthreads();
+  if (nfill <= kSortCap) {
+    // every filled slot fits: gather them all, then keep the best nout
+    for (int i0 = 0; i0 < C; i0 += bd) {
+      Cand cd;
+      cd.pos = kNoPos;
+      if (i0 + tid < C) cd = load_cand(cand + i0 + tid);
+      const bool keep = cd.pos != kNoPos;
+      const uint32_t slot = list_slot(&s_n, keep);
+      if (keep && slot < (uint32_t)kSortCap) {
+        sc[slot] = cd.score;
+        ps[slot] = cd.pos;
+      }
+    }
+    __syncthreads();
+    const int n = min((int)s_n, kSortCap);
+    uint64_t T = 0;
+    uint32_t pcut = 0xffffffffu;
+    if (n > nout) {
+      auto get = [&](int i, uint64_t* u, uint32_t* pos) {
+        *u = score_key(sc[i]);
+        *pos = ps[i];
+        return true;
+      };
+      radix_threshold(get, n, (uint32_t)nout, hist, &s_key, &s_k, &s_eq, &T, &pcut);
+    }
+    __syncthreads();
+    if (tid == 0) s_n = 0;
+    __syncthreads();
+    for (int i0 = 0; i0 < n; i0 += bd) {
+      const int i = i0 + tid;
+      const uint64_t u = i < n ? score_key(sc[i]) : 0;
+      const uint32_t pos = i < n ? ps[i] : 0u;
+      const bool keep = i < n && (u > T || (u == T && pos <= pcut));
+      const uint32_t slot = list_slot(&s_n, keep);
+      if (keep && slot < (uint32_t)nout) store_cand(sel + slot, sc[i], pos);
+    }
+  } else {
+    auto get = [&](int i, uint64_t* u, uint32_t* pos) {
+      const Cand cd = load_cand(cand + i);
+      *u = score_key(cd.score);
+      *pos = cd.pos;
+      return cd.pos != kNoPos;
+    };
+    uint64_t T;
+    uint32_t pcut;
+    radix_threshold(get, C, (uint32_t)nout, hist, &s_key, &s_k, &s_eq, &T, &pcut);
+    __syncthreads();
+    if (tid == 0) s_n = 0;
+    __syncthreads();
+    for (int i0 = 0; i0 < C; i0 += bd) {
+      Cand cd;
+      cd.pos = kNoPos;
+      cd.score = 0;
+      if (i0 + tid < C) cd = load_cand(cand + i0 + tid);
+      const uint64_t u = score_key(cd.score);
+      const bool keep = cd.pos != kNoPos && (u > T || (u == T && cd.pos <= pcut));
+      const uint32_t slot = list_slot(&s_n, keep);
+      if (keep && slot < (uint32_t)nout) store_cand(sel + slot, cd.score, cd.pos);
+    }
   }
-  gptr<const Cand> sel = G((const Cand*)P.sel);
-  for (int kk = 0; kk < kOrientPerBlock / 4; ++kk) {
-    const int i = chunk * kOrientPerBlock + wave * (kOrientPerBlock / 4) + kk;
-    if (i >= nsel) break;
-    const Cand cd = load_cand(sel + i);
-    const int x = (int)(cd.pos & 0xffff), y = (int)(cd.pos >> 16);
-    int m10, m01;
-    wave_moments(G(P.lvl), P.lvl_stride, x, y, P.B, lane, &m10, &m01);
-    if (lane == 0)
-      store_keypoint(G(P.out) + prefix + i, x, y, P.level, m10, m01,
-                     atan2f((float)m01, (float)m10), cd.score);
-  }
+  if (tid == 0) *G(P.sel_count) = (uint32_t)nout;
 }
 
 // ------------------------------------------------------------ test kernel --
@@ -2733,11 +2768,6 @@ hipError_t launch_select_orient(const KArgs& a, int slots, hipStream_t s) {
 
 hipError_t launch_select(const KArgs& a, int grid, hipStream_t s) {
   OF_LAUNCH(k_select, dim3(grid), dim3(1024), 0, s, a);
-  return hipGetLastError();
-}
-
-hipError_t launch_orient(const KArgs& a, int grid, hipStream_t s) {
-  OF_LAUNCH(k_orient, dim3(grid), dim3(256), 0, s, a);
   return hipGetLastError();
 }
 

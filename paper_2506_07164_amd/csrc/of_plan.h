@@ -18,7 +18,6 @@ constexpr int kMaxBatch = OF_MAX_BATCH;
 constexpr int kMaxEntries = kMaxLevels * kMaxBatch;  // (frame, level) pairs per call
 constexpr int kMaxQuota = 4096;                      // keypoints per level
 constexpr int kSortCap = 4096;                       // candidates sorted in LDS at once
-constexpr int kOrientPerBlock = 16;                  // keypoints per orientation block
 constexpr int kMaxDetW = 256, kMaxDetH = 128;        // Harris/NMS tile limits (pixels)
 constexpr int kCandCache = 1024;                     // Harris scores cached per tile
 constexpr int kMarkCellFlags = 320;  // cells a segment-test tile meets (cell >= 8: 33 x 9)
@@ -126,7 +125,6 @@ struct LevelPlan {
   int32_t det_tx, det_ty;      // Harris/NMS tile grid (covers the valid region)
   int32_t det_x0, det_y0;      // first cell column/row (cell > 0) or first pixel (cell == 0)
   int32_t det_xend, det_yend;  // one past the last cell column/row, or W-B / H-B
-  int32_t orient_blocks;       // orientation blocks of this level
   int32_t slot_w;              // output slots per row of 2x2 blocks (no cells)
   int32_t entry0;              // plan index of this frame's level 0
   of_keypoint* out;            // this frame's output
@@ -200,7 +198,7 @@ OF_HD int32_t level_stride(int32_t W) { return (int32_t)align_up(W, 64); }
 
 // Sizes of one (frame, level) entry inside each workspace region.
 struct EntrySize {
-  int32_t mark_tiles, det_tiles, orient_blocks;
+  int32_t mark_tiles, det_tiles;
   int64_t bm_words;   // 32-bit words of both bitmaps
   int64_t flag_bytes;
   int64_t cand_cap;
@@ -213,6 +211,8 @@ struct EntrySize {
   int32_t pyr_blocks;   // 64 x 16 resample blocks of a level >= 1
   int32_t rank_slots;   // waves of the counting selection: the slots of a level it ranks,
                         // none past the rank cap (an appended list: up to the cap)
+  int32_t sel_slots;    // waves of the second counting pass over a radix-selected list:
+                        // N_l for a level that can take the radix path, else none
 };
 
 OF_HD void entry_size(const FrameGeom& g, const of_params& p, const Tune& t, int l,
@@ -263,9 +263,8 @@ OF_HD void entry_size(const FrameGeom& g, const of_params& p, const Tune& t, int
   // the cap's waves and takes whichever path its length falls to.
   const bool appended = p.cell == 0 && s->cand_cap > kRankCap;
   s->rank_slots = appended ? t.rank_cap : (s->cand_cap <= t.rank_cap ? (int32_t)s->cand_cap : 0);
+  s->sel_slots = appended || s->cand_cap > t.rank_cap ? g.quota[l] : 0;
   s->sel_cap = g.quota[l];
-  int32_t ob = cdiv(g.quota[l], kOrientPerBlock);
-  s->orient_blocks = ob < 1 ? 1 : ob;
   s->lvl_bytes = l == 0 ? 0 : align_up((int64_t)level_stride(W) * H, 256);
   s->pyr_blocks = l == 0 ? 0 : cdiv(W, 64) * cdiv(H, 16);
 }
@@ -283,12 +282,12 @@ OF_HD int32_t ranked_candidates(const LevelPlan& P, uint32_t filled) {
 
 // Region sizes of a whole call; offsets are from the workspace base (256-aligned).
 struct WsLayout {
-  int64_t off_hdr, off_plan, off_mark_base, off_det_base, off_orient_base, off_rank_base;
+  int64_t off_hdr, off_plan, off_mark_base, off_det_base, off_sel_base, off_rank_base;
   int64_t off_pyr_base;
   int64_t off_band_base;   // kXcds prefix tables of segment-test tiles per entry, by band
   int64_t off_det_band_base;  // the same for Harris/NMS tiles
   int64_t off_counters, off_flags, off_bm, off_cand, off_sel, off_lvl, total;
-  int32_t n_entries, mark_tiles, det_tiles, orient_blocks, rank_slots, max_cand_cap, pyr_blocks;
+  int32_t n_entries, mark_tiles, det_tiles, sel_slots, rank_slots, max_cand_cap, pyr_blocks;
   int32_t band_tiles[kXcds];
   int32_t det_band_tiles[kXcds];
   int32_t band_rot;        // rotation of the next entry's leftover rows
@@ -300,7 +299,7 @@ OF_HD void ws_layout_accumulate(WsLayout* w, const EntrySize& s) {
   w->n_entries += 1;
   w->mark_tiles += s.mark_tiles;
   w->det_tiles += s.det_tiles;
-  w->orient_blocks += s.orient_blocks;
+  w->sel_slots += s.sel_slots;
   w->pyr_blocks += s.pyr_blocks;
   for (int k = 0; k < kXcds; ++k) {
     w->band_tiles[k] += s.mark_tx * band_rows(s.mark_ty, w->band_rot, k);
@@ -323,7 +322,7 @@ OF_HD void ws_layout_finish(WsLayout* w) {
   w->off_plan = o;         o = align_up(o + (int64_t)w->n_entries * sizeof(LevelPlan), 256);
   w->off_mark_base = o;    o = align_up(o + 4 * ((int64_t)w->n_entries + 1), 256);
   w->off_det_base = o;     o = align_up(o + 4 * ((int64_t)w->n_entries + 1), 256);
-  w->off_orient_base = o;  o = align_up(o + 4 * ((int64_t)w->n_entries + 1), 256);
+  w->off_sel_base = o;     o = align_up(o + 4 * ((int64_t)w->n_entries + 1), 256);
   w->off_rank_base = o;    o = align_up(o + 4 * ((int64_t)w->n_entries + 1), 256);
   w->off_pyr_base = o;     o = align_up(o + 4 * ((int64_t)w->n_entries + 1), 256);
   w->off_band_base = o;    o = align_up(o + 4 * kXcds * ((int64_t)w->n_entries + 1), 256);

@@ -243,7 +243,7 @@ def of_test_segment(circles_ptr: int, n: int, t_lo: int, t_hi: int, out_ptr: int
 
 OF_PROFILE_STEPS = 8
 PROFILE_STEP_NAMES = ["prologue", "pyramid", "segment_test", "harris_nms_cells", "select",
-                      "orient", "ablate_fast", "ablate_harris"]
+                      "select_lists", "ablate_fast", "ablate_harris"]
 
 
 def of_profile_enable(on) -> None:

@@ -212,12 +212,12 @@ hipError_t launch_prologue(const PrologueArgs& a, int grid, hipStream_t) {
     LevelPlan* pl = (LevelPlan*)(ws + lay.off_plan);
     int32_t* mark_base = (int32_t*)(ws + lay.off_mark_base);
     int32_t* det_base = (int32_t*)(ws + lay.off_det_base);
-    int32_t* or_base = (int32_t*)(ws + lay.off_orient_base);
+    int32_t* sl_base = (int32_t*)(ws + lay.off_sel_base);
     int32_t* rank_base = (int32_t*)(ws + lay.off_rank_base);
     int32_t* pyr_base = (int32_t*)(ws + lay.off_pyr_base);
     int32_t* band_base = (int32_t*)(ws + lay.off_band_base);
     int32_t* det_band_base = (int32_t*)(ws + lay.off_det_band_base);
-    int64_t o_mark = 0, o_det = 0, o_or = 0, o_flag = 0, o_bm = 0, o_cand = 0, o_rank = 0,
+    int64_t o_mark = 0, o_det = 0, o_sl = 0, o_flag = 0, o_bm = 0, o_cand = 0, o_rank = 0,
             o_sel = 0, o_lvl = 0, o_pyr = 0, rot = 0, drot = 0;
     int64_t o_band[kXcds] = {}, o_dband[kXcds] = {};
     for (int i = 0; i < nL; ++i) {
@@ -235,7 +235,7 @@ hipError_t launch_prologue(const PrologueArgs& a, int grid, hipStream_t) {
       acc(mark_base + i, 4, "prefix write", true);
       mark_base[i] = (int32_t)o_mark;
       det_base[i] = (int32_t)o_det;
-      or_base[i] = (int32_t)o_or;
+      sl_base[i] = (int32_t)o_sl;
       rank_base[i] = (int32_t)o_rank;
       pyr_base[i] = (int32_t)o_pyr;
       for (int k = 0; k < kXcds; ++k) {
@@ -246,7 +246,7 @@ hipError_t launch_prologue(const PrologueArgs& a, int grid, hipStream_t) {
       }
       o_mark += s.mark_tiles;
       o_det += s.det_tiles;
-      o_or += s.orient_blocks;
+      o_sl += s.sel_slots;
       o_flag += s.flag_bytes;
       o_bm += s.bm_words;
       o_cand += s.cand_cap;
@@ -265,7 +265,7 @@ hipError_t launch_prologue(const PrologueArgs& a, int grid, hipStream_t) {
     }
     mark_base[nL] = (int32_t)o_mark;
     det_base[nL] = (int32_t)o_det;
-    or_base[nL] = (int32_t)o_or;
+    sl_base[nL] = (int32_t)o_sl;
     rank_base[nL] = (int32_t)o_rank;
     pyr_base[nL] = (int32_t)o_pyr;
     for (int k = 0; k < kXcds; ++k) {
@@ -276,7 +276,7 @@ hipError_t launch_prologue(const PrologueArgs& a, int grid, hipStream_t) {
       CHECK(o_dband[k] == lay.det_band_tiles[k], "Harris band %d: %lld tiles vs host %d", k,
             (long long)o_dband[k], lay.det_band_tiles[k]);
     }
-    CHECK(o_mark == lay.mark_tiles && o_det == lay.det_tiles && o_or == lay.orient_blocks &&
+    CHECK(o_mark == lay.mark_tiles && o_det == lay.det_tiles && o_sl == lay.sel_slots &&
               o_rank == lay.rank_slots && o_pyr == lay.pyr_blocks,
           "prologue totals differ from the host layout");
     CHECK(o_flag == lay.flag_bytes && o_bm == lay.bm_words && o_cand == lay.cand_entries &&
@@ -725,13 +725,18 @@ hipError_t launch_select_orient(const KArgs& a, int slots, hipStream_t) {
   if (!sig_ok(a)) return hipSuccess;
   WsState& st = g_ws[ws_base(a)];
   CHECK(slots >= 1, "k_select_orient: %d slots", slots);
-  acc(a.flags, a.flag_bytes, "flags zeroed", true);
-  st.flags_dirty.assign(a.n_entries, false);
-  acc(a.qctr, 4, "queue counter zeroed", true);
-  a.qctr[0] = 0;
+  if (a.flags) {  // the first counting launch clears them for the next call
+    acc(a.flags, a.flag_bytes, "flags zeroed", true);
+    st.flags_dirty.assign(a.n_entries, false);
+    acc(a.qctr, 4, "queue counter zeroed", true);
+    a.qctr[0] = 0;
+  }
   CHECK((int64_t)8 * a.sel_lds <= 65536 - 4100, "k_select_orient: LDS");
   const int nslots = table_total(a, a.rank_base, 0);
-  CHECK(slots == std::max(nslots, 1), "k_select_orient: %d slots launched for %d", slots, nslots);
+  CHECK(slots == (a.from_sel ? nslots : std::max(nslots, 1)),
+        "k_select_orient: %d slots launched for %d", slots, nslots);
+  if (a.from_sel)
+    CHECK(a.rank_base == a.sel_base && !a.flags, "k_select_orient: list launch tables");
   // per entry: the slot range, ranked candidates and outputs
   for (int e = 0; e < a.n_entries; ++e) {
     const LevelPlan& P = plan(a, e);
@@ -744,12 +749,17 @@ hipError_t launch_select_orient(const KArgs& a, int slots, hipStream_t) {
     entry_of(a, a.rank_base, 0, first, &ee, &s0, &en);
     CHECK(ee == e || first == en, "k_select_orient: slot %d of entry %d found in entry %d",
           first, e, ee);
-    const int C = ranked_candidates(P, (uint32_t)model_filled(P));
-    const int want = P.compact ? std::min(P.cand_cap, a.t.rank_cap)
-                               : (P.cand_cap <= a.t.rank_cap ? P.cand_cap : 0);
+    const bool radix = P.compact || P.cand_cap > a.t.rank_cap;  // can take the radix path
+    const int C = a.from_sel ? std::min(model_filled(P), P.quota)
+                             : ranked_candidates(P, (uint32_t)model_filled(P));
+    const int want = a.from_sel ? (radix ? P.quota : 0)
+                     : P.compact ? std::min(P.cand_cap, a.t.rank_cap)
+                                 : (P.cand_cap <= a.t.rank_cap ? P.cand_cap : 0);
     CHECK(en - s0 == want, "k_select_orient: entry %d has %d slots", e, en - s0);
-    if (C <= a.t.rank_cap) {
-      acc(P.cand, (int64_t)sizeof(Cand) * C, "k_select_orient candidate reads");
+    if (a.from_sel || C <= a.t.rank_cap) {
+      if (a.from_sel) acc(P.sel_count, 4, "k_select_orient list count");
+      acc(a.from_sel ? P.sel : P.cand, (int64_t)sizeof(Cand) * C,
+          "k_select_orient candidate reads");
       if (a.sel_lds > 0 && C <= a.sel_lds) lds(0, 8 * (int64_t)C, 0, 8 * (int64_t)a.sel_lds,
                                                 "k_select_orient staged R'");
       model_moments(P, "k_select_orient moments");
@@ -775,41 +785,13 @@ hipError_t launch_select(const KArgs& a, int grid, hipStream_t) {
     const LevelPlan& P = plan(a, e);
     const int nfill = model_filled(P);
     const int C = ranked_candidates(P, (uint32_t)nfill);
+    acc(P.sel_count, 4, "k_select count", true);
     if (a.rank_path && C <= a.t.rank_cap) continue;
     acc(P.cand, (int64_t)sizeof(Cand) * C, "k_select candidate reads");
     const int nout = std::min(nfill, P.quota);
     CHECK(nout <= kSortCap, "k_select: %d selected > sort capacity", nout);
     if (nout > 0) acc(P.sel, (int64_t)sizeof(Cand) * nout, "k_select selection", true);
     acc(P.sel_count, 4, "k_select count", true);
-  }
-  return hipSuccess;
-}
-
-hipError_t launch_orient(const KArgs& a, int grid, hipStream_t) {
-  if (!sig_ok(a)) return hipSuccess;
-  acc(a.orient_base + a.n_entries, 4, "orient prefix total");
-  CHECK(grid == a.orient_base[a.n_entries], "k_orient: grid %d for %d blocks", grid,
-        a.orient_base[a.n_entries]);
-  for (int b = 0; b < grid; ++b) {
-    int e = a.entry;
-    int chunk = b;
-    if (e < 0) {
-      acc(a.orient_base, 4 * ((int64_t)a.n_entries + 1), "orient prefix");
-      e = prefix_entry(a.orient_base, a.n_entries, b);
-      chunk = b - a.orient_base[e];
-    }
-    const LevelPlan& P = plan(a, e);
-    const int C = ranked_candidates(P, (uint32_t)model_filled(P));
-    if (a.rank_path && C <= a.t.rank_cap) continue;
-    const int i_last = chunk * kOrientPerBlock + kOrientPerBlock - 1;
-    const int nsel = std::min(P.quota, model_filled(P));
-    if (chunk * kOrientPerBlock >= nsel) continue;
-    const int i = std::min(i_last, nsel - 1);
-    acc(P.sel + i, sizeof(Cand), "k_orient selection read");
-    int64_t prefix = 0;
-    for (int l = 0; l < P.level; ++l) prefix += plan(a, P.entry0 + l).quota;
-    check_out(P, a, prefix + i, "k_orient keypoint");
-    model_moments(P, "k_orient moments");
   }
   return hipSuccess;
 }
