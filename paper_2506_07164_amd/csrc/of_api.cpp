@@ -397,10 +397,12 @@ hipError_t launch_selection(KArgs k, const CallPlan& c, hipStream_t stream) {
   k.sel_lds = std::min(widest, kSelLdsCap);
   const int64_t blocks_per_cu = std::min<int64_t>(8, 163840 / (8 * (int64_t)k.sel_lds + 4352));
   if ((int64_t)lay.rank_slots > (int64_t)device_cus() * 4 * blocks_per_cu) k.sel_lds = 0;
-  // At least one block: besides ranking, the launch clears the cell flags and the
-  // segment-test queue counter for the next call (a call whose every level takes the
-  // radix path ranks nothing here).
-  const int32_t slots = std::max<int32_t>(lay.rank_slots, 1);
+  // Besides ranking, the launch clears the cell flags and the segment-test queue counter
+  // for the next call, so it keeps enough blocks for that (8 16-byte stores per thread)
+  // also when every level takes the radix path and nothing is ranked here.
+  const int64_t clear_blocks = (lay.flag_bytes / 16 + 8 * 256 - 1) / (8 * 256);
+  const int32_t slots =
+      (int32_t)std::max<int64_t>(lay.rank_slots, 4 * std::max<int64_t>(clear_blocks, 1));
   hipError_t e = timed(4, stream, [&] { return launch_select_orient(k, slots, stream); }, true);
   if (e == hipSuccess && lay.sel_slots > 0) {
     k.total = lay.n_entries;

@@ -733,7 +733,8 @@ hipError_t launch_select_orient(const KArgs& a, int slots, hipStream_t) {
   }
   CHECK((int64_t)8 * a.sel_lds <= 65536 - 4100, "k_select_orient: LDS");
   const int nslots = table_total(a, a.rank_base, 0);
-  CHECK(slots == (a.from_sel ? nslots : std::max(nslots, 1)),
+  const int64_t clear = 4 * std::max<int64_t>((a.flag_bytes / 16 + 2047) / 2048, 1);
+  CHECK(slots == (a.from_sel ? nslots : (int)std::max<int64_t>(nslots, clear)),
         "k_select_orient: %d slots launched for %d", slots, nslots);
   if (a.from_sel)
     CHECK(a.rank_base == a.sel_base && !a.flags, "k_select_orient: list launch tables");
