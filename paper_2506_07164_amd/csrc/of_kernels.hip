@@ -1214,6 +1214,30 @@ __global__ __launch_bounds__(256, 5) void k_mark(KArgs a) {
           }
         }
       }
+      // 2b. the same necessary condition on the diagonal points (positions 2/6/10/14,
+      //     (+-2, +-2)): a run of 9 holds two cyclically adjacent ones too.  Each wave
+      //     filters its own queue segment in place (a lane writes at or below the entry it
+      //     read, and all reads of a step come before its writes), at either polarity: on
+      //     textured frames the compass test passes most pixels and this one few of them.
+      {
+        int kept = 0;
+        for (int q0 = 0; q0 < qn; q0 += 64) {
+          const int q = q0 + lane;
+          const int ent = q < qn ? myq[q] : 0;
+          bool keep = false;
+          if (q < qn) {
+            const uint8_t* c = pix + (ent >> 9) * PITCH + (ent & 511);
+            const int p = c[0], ne = c[2 - 2 * PITCH], se = c[2 + 2 * PITCH];
+            const int sw = c[2 * PITCH - 2], nw = c[-2 - 2 * PITCH];
+            keep = min(max(ne, sw), max(se, nw)) >= p + tlo ||
+                   max(min(ne, sw), min(se, nw)) <= p - tlo;
+          }
+          const uint64_t m = __ballot(keep);
+          if (keep) myq[kept + lanes_below(m)] = (uint16_t)ent;
+          kept += __popcll(m);
+        }
+        qn = kept;
+      }
       if (lane == 0) s_qcnt[wave] = qn;
     }
     lds_barrier();

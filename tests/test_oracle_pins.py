@@ -50,6 +50,15 @@ def test_compass_prefilter_is_necessary():
             assert (b[0] | b[2]) & (b[1] | b[3])
 
 
+def test_diagonal_prefilter_is_necessary():
+    """Likewise for the diagonal points (2,6), (6,10), (10,14), (14,2): the segment test's
+    second pre-test stage, (b2|b10)&(b6|b14), never rejects a corner mask either."""
+    for m in range(1 << 16):
+        if oracle.run9(m):
+            b = [(m >> i) & 1 for i in (2, 6, 10, 14)]
+            assert (b[0] | b[2]) & (b[1] | b[3])
+
+
 def _fig6_cases():
     cases = []
     with open(os.path.join(GOLDEN, "fig6_patterns.txt")) as f:
