@@ -428,29 +428,44 @@ __device__ __forceinline__ void stage_all(uint8_t* lds, int lp, gptr<const uint8
   stage_rest(st, lds, lp, src, stride, row_limit, x0, y0);
 }
 
-// Harris R' at LDS pixel (cx, cy) by one lane: the 9 x 9 neighbourhood is read as three
-// aligned 32-bit words per row (bytes extracted by alignbyte), horizontal differences
-// hd = I[c+1] - I[c-1] and smoothings hs = I[c-1] + 2 I[c] + I[c+1] are formed per row,
-// and three rows are kept in registers for G_x = hd[r-1] + 2 hd[r] + hd[r+1] and
-// G_y = hs[r+1] - hs[r-1] (Eq. 4, separable).  pix and the row pitch P are 4-aligned.
-__device__ __forceinline__ void harris_row_words(const uint8_t* row, int s, int (&hd)[7],
-                                                 int (&hs)[7]) {
+// Harris R' at LDS pixel (cx, cy) by one lane, in 16-bit pairs of window columns: the
+// 9 x 9 neighbourhood is read as three aligned 32-bit words per row (bytes moved into
+// 16-bit lanes by byte permutes), the horizontal differences hd = I[c+1] - I[c-1] and
+// smoothings hs = I[c-1] + 2 I[c] + I[c+1] are formed for columns (0,1), (2,3), (4,5), (6,-)
+// of the window, three rows are kept for G_x = hd[r-1] + 2 hd[r] + hd[r+1] and
+// G_y = hs[r+1] - hs[r-1] (Eq. 4, separable), and the sums of products take one
+// dot2 (two 16 x 16-bit products added to 32 bits) per pair.  Every intermediate fits
+// 16 bits (|hd| <= 255, hs <= 1020, |G| <= 1020) and every sum 32 bits (49 * 2 * 1020^2),
+// so the integers are those of the plain definition.  pix and the row pitch P are
+// 4-aligned.
+typedef short s16x2 __attribute__((ext_vector_type(2)));
+
+__device__ __forceinline__ void harris_row_pairs(const uint8_t* row, int s, s16x2 (&hd)[4],
+                                                 s16x2 (&hs)[4]) {
   const uint32_t* w = (const uint32_t*)row;
   const uint32_t w0 = w[0], w1 = w[1], w2 = w[2];
-  const uint32_t lo = __builtin_amdgcn_alignbyte(w1, w0, (uint32_t)s);  // bytes 0..3
+  const uint32_t lo = __builtin_amdgcn_alignbyte(w1, w0, (uint32_t)s);   // bytes 0..3
   const uint32_t mid = __builtin_amdgcn_alignbyte(w2, w1, (uint32_t)s);  // bytes 4..7
-  int v[9];
+  const uint32_t b8 = (w2 >> (8 * s)) & 255u;                           // byte 8
+  // p[k] = bytes (2k, 2k+1), q[k] = bytes (2k+1, 2k+2), each in two 16-bit lanes
+  s16x2 p[5], q[4];
+  p[0] = __builtin_bit_cast(s16x2, __builtin_amdgcn_perm(0u, lo, 0x0c010c00u));
+  p[1] = __builtin_bit_cast(s16x2, __builtin_amdgcn_perm(0u, lo, 0x0c030c02u));
+  p[2] = __builtin_bit_cast(s16x2, __builtin_amdgcn_perm(0u, mid, 0x0c010c00u));
+  p[3] = __builtin_bit_cast(s16x2, __builtin_amdgcn_perm(0u, mid, 0x0c030c02u));
+  p[4] = __builtin_bit_cast(s16x2, b8);
+  q[0] = __builtin_bit_cast(s16x2, __builtin_amdgcn_perm(0u, lo, 0x0c020c01u));
+  q[1] = __builtin_bit_cast(s16x2, __builtin_amdgcn_perm(mid, lo, 0x0c040c03u));
+  q[2] = __builtin_bit_cast(s16x2, __builtin_amdgcn_perm(0u, mid, 0x0c020c01u));
+  q[3] = __builtin_bit_cast(s16x2, __builtin_amdgcn_perm(b8, mid, 0x0c040c03u));
 #pragma unroll
   for (int k = 0; k < 4; ++k) {
-    v[k] = (int)((lo >> (8 * k)) & 255u);
-    v[k + 4] = (int)((mid >> (8 * k)) & 255u);
+    hd[k] = p[k + 1] - p[k];
+    hs[k] = p[k] + p[k + 1] + (s16x2)2 * q[k];
   }
-  v[8] = (int)((w2 >> (8 * s)) & 255u);
-#pragma unroll
-  for (int c = 0; c < 7; ++c) {
-    hd[c] = v[c + 2] - v[c];
-    hs[c] = v[c] + 2 * v[c + 1] + v[c + 2];
-  }
+  // column 7 is outside the window: its lanes are cleared
+  hd[3] = __builtin_bit_cast(s16x2, __builtin_bit_cast(uint32_t, hd[3]) & 0xffffu);
+  hs[3] = __builtin_bit_cast(s16x2, __builtin_bit_cast(uint32_t, hs[3]) & 0xffffu);
 }
 
 // Sums of G_x^2, G_y^2 and G_x G_y over window rows w0 .. w0 + nr - 1 (0 .. 6 from the
@@ -460,26 +475,26 @@ __device__ __forceinline__ void harris_part(const uint8_t* pix, int P, int cx, i
                                             int nr, int& sxx, int& syy, int& sxy) {
   const int a = cx - 4, s = a & 3;
   const uint8_t* row = pix + (cy - 4 + w0) * P + (a - s);
-  int hd0[7], hs0[7], hd1[7], hs1[7];
-  harris_row_words(row, s, hd0, hs0);
-  harris_row_words(row + P, s, hd1, hs1);
+  s16x2 hd0[4], hs0[4], hd1[4], hs1[4];
+  harris_row_pairs(row, s, hd0, hs0);
+  harris_row_pairs(row + P, s, hd1, hs1);
   sxx = syy = sxy = 0;
 #pragma unroll
   for (int r = 0; r < NR; ++r) {
     if (r < nr) {
-      int hd2[7], hs2[7];
-      harris_row_words(row + (r + 2) * P, s, hd2, hs2);
+      s16x2 hd2[4], hs2[4];
+      harris_row_pairs(row + (r + 2) * P, s, hd2, hs2);
 #pragma unroll
-      for (int c = 0; c < 7; ++c) {
-        const int gx = hd0[c] + 2 * hd1[c] + hd2[c];
-        const int gy = hs2[c] - hs0[c];
-        sxx += gx * gx;
-        syy += gy * gy;
-        sxy += gx * gy;
-        hd0[c] = hd1[c];
-        hd1[c] = hd2[c];
-        hs0[c] = hs1[c];
-        hs1[c] = hs2[c];
+      for (int k = 0; k < 4; ++k) {
+        const s16x2 gx = hd0[k] + (s16x2)2 * hd1[k] + hd2[k];
+        const s16x2 gy = hs2[k] - hs0[k];
+        sxx = __builtin_amdgcn_sdot2(gx, gx, sxx, false);
+        syy = __builtin_amdgcn_sdot2(gy, gy, syy, false);
+        sxy = __builtin_amdgcn_sdot2(gx, gy, sxy, false);
+        hd0[k] = hd1[k];
+        hd1[k] = hd2[k];
+        hs0[k] = hs1[k];
+        hs1[k] = hs2[k];
       }
     }
   }
