@@ -1365,7 +1365,10 @@ __device__ __forceinline__ uint32_t bit_range(int a, int b) {
 // one cell).  Candidates of the tile and a 1-pixel ring are found word-parallel from
 // the segment-test bitmaps, scored with Harris from LDS, suppressed against their
 // candidate neighbours, and the per-cell best are written to the cells' fixed slots.
-template <bool PERSIST>
+// LA > 0 compiles the tile shape in (LA x LB cells of side LCELL, or LA x LB pixels when
+// LCELL == 0): its LDS layout and tile geometry are then constants rather than values held
+// in scalar registers (which spilled); LA == 0 takes the shape from the arguments.
+template <bool PERSIST, int LA, int LB, int LCELL>
 __global__ __launch_bounds__(256, 4) void k_detect(KArgs a) {
   extern __shared__ __align__(16) uint8_t smem[];
   __shared__ int s_next, s_ns, s_ne, s_nin;
@@ -1373,7 +1376,11 @@ __global__ __launch_bounds__(256, 4) void k_detect(KArgs a) {
   const int band = (int)(blockIdx.x % kXcds);  // used in the band order only
   Head h = read_head(a, band);
   h.persistent = PERSIST;  // one tile per block otherwise: straight-line code, no loop state
-  const DetLds& D = a.dl;  // computed by the host
+  constexpr Tune kT = det_shape_tune(LA, LB, LCELL);
+  constexpr DetLds kD = det_lds(kT, LCELL);
+  const DetLds& D = LA > 0 ? kD : a.dl;  // else computed by the host
+  const Tune& TT = LA > 0 ? kT : h.t;     // the tile shape's fields
+  const int cellm = LA > 0 ? LCELL : h.cell;
   uint8_t* pix = smem;
   uint32_t* cw = (uint32_t*)(smem + D.off_cw);
   uint32_t* ucnt = (uint32_t*)(smem + D.off_ucnt);
@@ -1426,7 +1433,7 @@ __global__ __launch_bounds__(256, 4) void k_detect(KArgs a) {
     const int W = P.W, H = P.H, B = P.B, cs = P.cs;
     const int tx = t % P.det_tx;
     const int ty = t / P.det_tx + (h.bands ? band_row0(P.det_ty, P.det_band_rot, band) : 0);
-    const DetTile T = det_tile(P, h.t, h.cell, tx, ty);
+    const DetTile T = det_tile(P, TT, cellm, tx, ty);
     const int vx0 = T.vx0, vx1 = T.vx1, vy0 = T.vy0, vy1 = T.vy1;
     const int cxa = T.cxa, cya = T.cya, nlcx = T.nlcx, nlcy = T.nlcy;
     const int rx0 = T.rx0, ry0 = T.ry0, rw = T.rw;
@@ -1480,8 +1487,8 @@ __global__ __launch_bounds__(256, 4) void k_detect(KArgs a) {
       s_nin = 0;
     }
     // one survivor kept per cell: the cell's winner is found with LDS atomics
-    const bool best1 = h.cell > 0 && P.kcell == 1;
-    if (h.cell > 0) {
+    const bool best1 = cellm > 0 && P.kcell == 1;
+    if (cellm > 0) {
       for (int c = tid; c < ncell; c += bd) {
         ccnt[c] = 0;
         cfill[c] = 0;
@@ -1693,7 +1700,7 @@ __global__ __launch_bounds__(256, 4) void k_detect(KArgs a) {
       continue;
     }
     if (ns > 0) {
-      if (h.cell > 0) {
+      if (cellm > 0) {
         for (int s2 = tid; s2 < ns; s2 += bd) atomicAdd(&ccnt[multi ? scell[s2] : 0], 1u);
         lds_barrier();
         if (tid == 0) {
@@ -1715,13 +1722,13 @@ __global__ __launch_bounds__(256, 4) void k_detect(KArgs a) {
         const uint32_t pos = cand_pos(ci);
         const int64_t R = cand_score(ci, pos);
         const int c = multi ? scell[s] : 0;
-        const int n = h.cell > 0 ? (int)ccnt[c] : ns;
+        const int n = cellm > 0 ? (int)ccnt[c] : ns;
         bool keep = true;
         if (n > K) {
           int rank = 0;
-          const int o = h.cell > 0 ? (int)coff[c] : 0;
+          const int o = cellm > 0 ? (int)coff[c] : 0;
           for (int q = 0; q < n && rank < K; ++q) {
-            const int s2 = h.cell > 0 ? order[o + q] : q;
+            const int s2 = cellm > 0 ? order[o + q] : q;
             const int ci2 = sci[s2];
             const uint32_t pos2 = cand_pos(ci2);
             rank += better(cand_score(ci2, pos2), pos2, R, pos) ? 1 : 0;
@@ -1731,7 +1738,7 @@ __global__ __launch_bounds__(256, 4) void k_detect(KArgs a) {
         if (keep) {
           const int x = (int)(pos & 0xffff), y = (int)(pos >> 16);
           int slot;
-          if (h.cell > 0) {
+          if (cellm > 0) {
             const int r = (int)atomicAdd(&ckept[c], 1u);
             slot = (((int)div_by((uint32_t)y, P.csd) - P.det_y0) * nvx +
                     ((int)div_by((uint32_t)x, P.csd) - P.det_x0)) * P.kslot + r;
@@ -1764,7 +1771,7 @@ __global__ __launch_bounds__(256, 4) void k_detect(KArgs a) {
       queue_park(h, next, &s_next);
       continue;
     }
-    if (h.cell > 0) {
+    if (cellm > 0) {
       const int ks = P.kslot;
       for (int i = tid; i < ncell * ks; i += bd) {
         const int c = ks == 1 ? i : i / ks;
@@ -2760,10 +2767,21 @@ hipError_t launch_mark(const KArgs& a, bool fused, int grid, hipStream_t s) {
 
 hipError_t launch_detect(const KArgs& a, int grid, hipStream_t s) {
   const int bytes = a.dl.bytes + base_table_bytes(a.n_entries);
+  // the shipped and default tile shapes with their layout compiled in
+  const bool cells = a.cell > 0;
+  const int sa = cells ? a.t.det_cx : a.t.det_w, sb = cells ? a.t.det_cy : a.t.det_h;
   if (a.persistent)
-    OF_LAUNCH(k_detect<true>, dim3(grid), dim3(256), bytes, s, a);
+    OF_LAUNCH((k_detect<true, 0, 0, 0>), dim3(grid), dim3(256), bytes, s, a);
+  else if (a.cell == 30 && sa == 8 && sb == 1)
+    OF_LAUNCH((k_detect<false, 8, 1, 30>), dim3(grid), dim3(256), bytes, s, a);
+  else if (a.cell == 30 && sa == 4 && sb == 2)
+    OF_LAUNCH((k_detect<false, 4, 2, 30>), dim3(grid), dim3(256), bytes, s, a);
+  else if (!cells && sa == 128 && sb == 32)
+    OF_LAUNCH((k_detect<false, 128, 32, 0>), dim3(grid), dim3(256), bytes, s, a);
+  else if (!cells && sa == 64 && sb == 32)
+    OF_LAUNCH((k_detect<false, 64, 32, 0>), dim3(grid), dim3(256), bytes, s, a);
   else
-    OF_LAUNCH(k_detect<false>, dim3(grid), dim3(256), bytes, s, a);
+    OF_LAUNCH((k_detect<false, 0, 0, 0>), dim3(grid), dim3(256), bytes, s, a);
   return hipGetLastError();
 }
 

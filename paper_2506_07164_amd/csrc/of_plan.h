@@ -146,8 +146,8 @@ OF_HD int64_t counter_words(int32_t n_entries) {
 
 // The same for the LDS layouts that every wave of a tile kernel computes at its start:
 // non-negative 32-bit values, so unsigned arithmetic (a power-of-two divisor is a shift).
-OF_HD int32_t align16(int32_t v) { return (int32_t)(((uint32_t)v + 15u) & ~15u); }
-OF_HD int32_t cdiv_u(int32_t a, int32_t b) {
+constexpr OF_HD int32_t align16(int32_t v) { return (int32_t)(((uint32_t)v + 15u) & ~15u); }
+constexpr OF_HD int32_t cdiv_u(int32_t a, int32_t b) {
   return (int32_t)(((uint32_t)a + (uint32_t)b - 1u) / (uint32_t)b);
 }
 
@@ -522,8 +522,22 @@ struct DetLds {
       off_coff, off_cfill, off_ckept, off_cbest, off_cwin, off_lfl, fm_rows, off_fm, bytes;
 };
 
-OF_HD DetLds det_lds(const Tune& t, int32_t cell) {
-  DetLds d;
+// The tuning fields of a Harris/NMS tile shape known at compile time: a x b cells
+// (cell > 0) or a x b pixels (whole-level cells, cell == 0); the rest zero.
+constexpr OF_HD Tune det_shape_tune(int32_t a, int32_t b, int32_t cell) {
+  Tune t{};
+  if (cell > 0) {
+    t.det_cx = a;
+    t.det_cy = b;
+  } else {
+    t.det_w = a;
+    t.det_h = b;
+  }
+  return t;
+}
+
+constexpr OF_HD DetLds det_lds(const Tune& t, int32_t cell) {
+  DetLds d{};
   if (cell > 0) {
     d.mtw = t.det_cx * cell;
     d.mth = t.det_cy * cell;
