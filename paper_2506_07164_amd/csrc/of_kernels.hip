@@ -1641,20 +1641,49 @@ __global__ __launch_bounds__(256, 4) void k_detect(KArgs a) {
       if (lane == 0 && im) atomicAdd(&s_nin, (int)__popcll(im));
       if (!inside) continue;
       const int x = (int)(pos & 0xffff), y = (int)(pos >> 16);
-      const int64_t R = cand_score(ci, pos);
-      bool alive = true;
-#pragma unroll  // the 8 neighbour lookups independent: their LDS reads overlap
+      // The 8 neighbours' lookups in three rounds of independent LDS reads (candidate
+      // words and their prefix counts, then scores), with no branch between them, so
+      // that their latencies overlap; a neighbour past the score cache (rare) is
+      // recomputed afterwards.
+      const int64_t R0 = crs[min(ci, kCandCache - 1)];
+      uint32_t qm[8], qp[8];
+      int qb[8];
+#pragma unroll
       for (int nb = 0; nb < 8; ++nb) {
         const int dx = nb < 3 ? nb - 1 : (nb < 5 ? (nb == 3 ? -1 : 1) : nb - 6);
         const int dy = nb < 3 ? -1 : (nb < 5 ? 0 : 1);
         const int qx = x + dx, qy = y + dy;
         const int qu = (qy - ry0) * nbw + (qx >> 5) - bw0;
-        const uint32_t qm = cw[qu];
-        const int qb = qx & 31;
-        if ((qm >> qb) & 1u) {
-          const int qi = (int)(cpre[qu] + (uint32_t)__popc(qm & ((1u << qb) - 1u)));
-          const uint32_t qpos = ((uint32_t)qy << 16) | (uint32_t)qx;
-          alive = alive && better(R, pos, cand_score(qi, qpos), qpos);
+        qb[nb] = qx & 31;
+        qm[nb] = cw[qu];
+        qp[nb] = cpre[qu];
+      }
+      int qi[8];
+      int64_t qs[8];
+#pragma unroll
+      for (int nb = 0; nb < 8; ++nb) {
+        qi[nb] = (int)(qp[nb] + (uint32_t)__popc(qm[nb] & ((1u << qb[nb]) - 1u)));
+        qs[nb] = crs[min(qi[nb], kCandCache - 1)];
+      }
+      const int64_t R = ci < kCandCache ? R0 : cand_score(ci, pos);
+      bool alive = true, far = false;
+#pragma unroll
+      for (int nb = 0; nb < 8; ++nb) {
+        const int dx = nb < 3 ? nb - 1 : (nb < 5 ? (nb == 3 ? -1 : 1) : nb - 6);
+        const int dy = nb < 3 ? -1 : (nb < 5 ? 0 : 1);
+        const uint32_t qpos = ((uint32_t)(y + dy) << 16) | (uint32_t)(x + dx);
+        const bool isc = (qm[nb] >> qb[nb]) & 1u;
+        far = far || (isc && qi[nb] >= kCandCache);
+        alive = alive && !(isc && qi[nb] < kCandCache && !better(R, pos, qs[nb], qpos));
+      }
+      if (far) {  // neighbours past the score cache: recomputed from the staged pixels
+#pragma unroll 1
+        for (int nb = 0; nb < 8; ++nb) {
+          const int dx = nb < 3 ? nb - 1 : (nb < 5 ? (nb == 3 ? -1 : 1) : nb - 6);
+          const int dy = nb < 3 ? -1 : (nb < 5 ? 0 : 1);
+          const uint32_t qpos = ((uint32_t)(y + dy) << 16) | (uint32_t)(x + dx);
+          if (((qm[nb] >> qb[nb]) & 1u) && qi[nb] >= kCandCache)
+            alive = alive && better(R, pos, cand_score(qi[nb], qpos), qpos);
         }
       }
       if (alive) {
