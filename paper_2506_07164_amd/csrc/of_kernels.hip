@@ -864,21 +864,24 @@ __global__ __launch_bounds__(256) void k_pyramid_batch(KArgs a) {
 // [4, 4 + TW) of the tile (the 7 side columns are left to the caller).  The taps of K
 // adjacent output columns lie within 8 bytes of a frame row when (K - 1) * bw < 6 * W
 // (K = 4 below scale 2, K = 2 below scale 6), so one unaligned 64-bit load per source
-// row serves all K (moved back from the row's end where 8 bytes would pass it), and the
-// K resampled bytes go to LDS in one 32- or 16-bit store.  Each wave step covers R
-// tile rows (64 / (TW / K) lanes per row); RPI steps' loads are in flight at once.
+// row serves all K (moved back from the row's end where 8 bytes would pass it); a byte
+// permute takes each column's two tap bytes out of it into 16-bit lanes, and the K
+// resampled bytes go to LDS in one 32- or 16-bit store.  The taps come from the tile's
+// LDS tables: column i has x0 cx[i] and weights cw[i], row j source row offsets
+// ro[2j], ro[2j + 1] and weights rwy[j].  Each wave step covers R tile rows
+// (64 / (TW / K) lanes per row); RPI steps' loads are in flight at once.
 template <int K, int TW, int RPI>
 __device__ __forceinline__ void resample_groups(uint8_t* pix, int pitch, gptr<const uint8_t> base,
-                                                int bs, int bw, int bh1, int W, int ox, int nx,
-                                                int ny, uint32_t ty_a, uint32_t ty_b, double rw,
-                                                int lane, int wave) {
+                                                int bw, int nx, int ny, const uint32_t* cx,
+                                                const uint32_t* cw, const uint32_t* ro,
+                                                const uint32_t* rwy, int lane, int wave) {
   constexpr int G = TW / K;                // lane groups per tile row
   constexpr int R = G <= 64 ? 64 / G : 1;  // tile rows per wave step
   constexpr int C = G <= 64 ? 1 : G / 64;  // column groups per lane
   typedef uint64_t u64_any_align __attribute__((aligned(1)));
   const int r = G <= 64 ? lane / G : 0;
   const int q0 = G <= 64 ? lane - r * G : lane;
-  uint32_t b[C], sh[C][K];
+  uint32_t b[C], sel[C][K];
   u16x2 wx[C][K];
 #pragma unroll
   for (int c = 0; c < C; ++c) {
@@ -886,18 +889,17 @@ __device__ __forceinline__ void resample_groups(uint8_t* pix, int pitch, gptr<co
     uint32_t x0[K];
 #pragma unroll
     for (int m = 0; m < K; ++m) {
-      const uint32_t t = resample_tap_r(ox + min(i0 + m, nx - 1), bw, W, rw);
-      int xx = (int)(t >> 9), w = (int)(t & 511);
-      if (xx >= bw - 1) {
-        xx = bw - 2;
-        w = 256;
-      }
-      x0[m] = (uint32_t)xx;
-      wx[c][m] = pair16((uint32_t)(256 - w), (uint32_t)w);
+      const int i = min(i0 + m, nx - 1);
+      x0[m] = cx[i];
+      wx[c][m] = __builtin_bit_cast(u16x2, cw[i]);
     }
     b[c] = min(x0[0], (uint32_t)(bw - 8));
+    // bytes s and s + 1 of the 8 loaded (s <= 6) into the low bytes of the two halves
 #pragma unroll
-    for (int m = 0; m < K; ++m) sh[c][m] = 8u * (x0[m] - b[c]);
+    for (int m = 0; m < K; ++m) {
+      const uint32_t sb = x0[m] - b[c];
+      sel[c][m] = 0x0c000c00u | sb | ((sb + 1u) << 16);
+    }
   }
   for (int j0 = R * RPI * wave; j0 < ny; j0 += R * RPI * 4) {
     uint64_t v[RPI][C][2];
@@ -905,11 +907,8 @@ __device__ __forceinline__ void resample_groups(uint8_t* pix, int pitch, gptr<co
 #pragma unroll
     for (int h = 0; h < RPI; ++h) {
       const int j = min(j0 + h * R + r, ny - 1);
-      const int ta = __shfl((int)ty_a, j & 63, 64), tb = __shfl((int)ty_b, j & 63, 64);
-      const uint32_t tyy = (uint32_t)(j < 64 ? ta : tb);
-      const int y0 = (int)(tyy >> 9);
-      wy[h] = pair16(256u - (tyy & 511u), tyy & 511u);
-      const uint32_t o0 = (uint32_t)(y0 * bs), o1 = (uint32_t)(min(y0 + 1, bh1) * bs);
+      const uint32_t o0 = ro[2 * j], o1 = ro[2 * j + 1];
+      wy[h] = __builtin_bit_cast(u16x2, rwy[j]);
 #pragma unroll
       for (int c = 0; c < C; ++c) {
         v[h][c][0] = *(gptr<const u64_any_align>)(base + (o0 + b[c]));
@@ -922,18 +921,28 @@ __device__ __forceinline__ void resample_groups(uint8_t* pix, int pitch, gptr<co
       if (j >= ny) continue;
 #pragma unroll
       for (int c = 0; c < C; ++c) {
-        uint32_t packed = 0;
+        // R4's blend: horizontal 16-bit dot products per source row, packed into one
+        // word for the vertical one; the result (< 2^24) is byte 2 of res
+        uint32_t res[K];
 #pragma unroll
         for (int m = 0; m < K; ++m) {
-          const uint32_t t = (uint32_t)(v[h][c][0] >> sh[c][m]) & 0xffffu;
-          const uint32_t u = (uint32_t)(v[h][c][1] >> sh[c][m]) & 0xffffu;
-          packed |= blend_q8(t, u, wx[c][m], wy[h]) << (8 * m);
+          const u16x2 t = __builtin_bit_cast(
+              u16x2, __builtin_amdgcn_perm((uint32_t)(v[h][c][0] >> 32), (uint32_t)v[h][c][0],
+                                           sel[c][m]));
+          const u16x2 u = __builtin_bit_cast(
+              u16x2, __builtin_amdgcn_perm((uint32_t)(v[h][c][1] >> 32), (uint32_t)v[h][c][1],
+                                           sel[c][m]));
+          const uint32_t top = __builtin_amdgcn_udot2(t, wx[c][m], 0u, false);
+          const uint32_t bot = __builtin_amdgcn_udot2(u, wx[c][m], 0u, false);
+          res[m] = __builtin_amdgcn_udot2(pair16(top, bot), wy[h], 32768u, false);
         }
         uint8_t* dst = pix + j * pitch + 4 + K * (q0 + 64 * c);
-        if constexpr (K == 4)
-          *(uint32_t*)dst = packed;
-        else
-          *(uint16_t*)dst = (uint16_t)packed;
+        if constexpr (K == 4) {
+          *(uint32_t*)dst = __builtin_amdgcn_perm(res[1], res[0], 0x0c0c0602u) |
+                            __builtin_amdgcn_perm(res[3], res[2], 0x06020c0cu);
+        } else {
+          *(uint16_t*)dst = (uint16_t)__builtin_amdgcn_perm(res[1], res[0], 0x0c0c0602u);
+        }
       }
     }
   }
@@ -1007,14 +1016,11 @@ __global__ __launch_bounds__(256, 5) void k_mark(KArgs a) {
 
     // 1. level pixels of the tile and its 3-pixel halo
     if (FUSED && P.level > 0) {
-      // Taps in registers: lane owns the columns 4 + lane + 64c (c < TWW: the tile's
-      // width from the left halo's end), and lane j holds the row tap of tile row j
-      // (j + 64 in the second value), read per row with readlane.  The 7 other columns
-      // (the left halo and the last 3) are spread over the lanes by (row, column) instead,
-      // so no lane slot holds a column for a few lanes only.  A column tap keeps x0 + 1
-      // inside the source row (at the right border x0 = w - 2 with weight 256: the same
-      // value as x0 = x1 = w - 1), so one 16-bit load fetches both horizontal neighbours.
-      // Each wave takes RPI consecutive rows per round trip.
+      // A column tap keeps x0 + 1 inside the source row (at the right border x0 = w - 2
+      // with weight 256: the same value as x0 = x1 = w - 1), so one 16-bit load fetches
+      // both horizontal neighbours.  The 7 side columns (the left halo and the last 3)
+      // are spread over the lanes by (row, column), so no lane slot holds a column for a
+      // few lanes only.
       gptr<const uint8_t> base = G(P.base);
       const int bs = P.base_stride, bw = P.base_w, bh1 = P.base_h - 1;
       constexpr int NC = TWW;  // tile columns per lane
@@ -1029,43 +1035,65 @@ __global__ __launch_bounds__(256, 5) void k_mark(KArgs a) {
         *x0 = (uint32_t)xx;
         *w = pair16((uint32_t)(256 - wx), (uint32_t)wx);  // (256 - wx, wx)
       };
-      const uint32_t ty_a = resample_tap_r(oy + min(lane, ny - 1), P.base_h, H, rh);
-      const uint32_t ty_b = ny > 64 ? resample_tap_r(oy + min(lane + 64, ny - 1), P.base_h, H, rh)
-                                    : 0u;
       // Adjacent output columns whose taps share 8 bytes of a frame row: 4 below scale 2,
       // 2 below scale 6 (one 64-bit load per source row for all of them), else one
       // 16-bit gather per column and source row.
       const int kgrp = 3 * bw < 6 * W ? 4 : (bw < 6 * W ? 2 : 1);
-      auto side_columns = [&]() {  // the left halo and the last 3 columns, by (row, column)
-        for (int t0 = 0; t0 < 7 * ny; t0 += kBlock) {
-          const int t = t0 + (int)threadIdx.x;
-          const int jr = t / 7, k = t - jr * 7;
-          const int j = min(jr, ny - 1);
-          const int ta = __shfl((int)ty_a, j & 63, 64), tb = __shfl((int)ty_b, j & 63, 64);
-          const int col = k < 4 ? k : TW + k;
-          if (jr < ny && col < nx) {
+      if (kgrp > 1) {
+        // The tile's taps, once per block, in the queue's region (free until step 2):
+        // per column x0 and (256 - wx, wx), per row the offsets of source rows y0 and
+        // min(y0 + 1, h - 1) and (256 - wy, wy).
+        uint32_t* tcx = (uint32_t*)(smem + M.off_queue);
+        uint32_t* tcw = tcx + M.tcols;
+        uint32_t* tro = tcw + M.tcols;
+        uint32_t* trw = tro + 2 * M.rows;
+        for (int i = threadIdx.x; i < nx + ny; i += kBlock) {
+          if (i < nx) {
             uint32_t x0;
             u16x2 w;
-            col_tap(col, &x0, &w);
-            const uint32_t tyy = (uint32_t)(j < 64 ? ta : tb);
+            col_tap(i, &x0, &w);
+            tcx[i] = x0;
+            tcw[i] = __builtin_bit_cast(uint32_t, w);
+          } else {
+            const int j = i - nx;
+            const uint32_t tyy = resample_tap_r(oy + j, P.base_h, H, rh);
             const int y0 = (int)(tyy >> 9);
-            const uint32_t v0 = load_pair(base + ((uint32_t)(y0 * bs) + x0));
-            const uint32_t v1 = load_pair(base + ((uint32_t)(min(y0 + 1, bh1) * bs) + x0));
-            pix[j * PITCH + col] = (uint8_t)blend_q8(v0, v1, w, pair16(256u - (tyy & 511u), tyy & 511u));
+            tro[2 * j] = (uint32_t)(y0 * bs);
+            tro[2 * j + 1] = (uint32_t)(min(y0 + 1, bh1) * bs);
+            trw[j] = (256u - (tyy & 511u)) | ((tyy & 511u) << 16);
           }
         }
-      };
-      if (kgrp == 4) {
-        constexpr int G4 = TW / 4, R4 = G4 <= 64 ? 64 / G4 : 1;
-        resample_groups<4, TW, (R4 >= 4 ? 2 : (R4 == 2 ? 4 : 8))>(
-            pix, PITCH, base, bs, bw, bh1, W, ox, nx, ny, ty_a, ty_b, rw, lane, wave);
-        side_columns();
-      } else if (kgrp == 2) {
-        constexpr int G2 = TW / 2, R2 = G2 <= 64 ? 64 / G2 : 1, C2 = G2 <= 64 ? 1 : G2 / 64;
-        resample_groups<2, TW, (R2 * C2 >= 4 ? 2 : (R2 * C2 == 2 ? 4 : 8))>(
-            pix, PITCH, base, bs, bw, bh1, W, ox, nx, ny, ty_a, ty_b, rw, lane, wave);
-        side_columns();
+        lds_barrier();
+        if (kgrp == 4) {
+          constexpr int G4 = TW / 4, R4 = G4 <= 64 ? 64 / G4 : 1;
+          resample_groups<4, TW, (R4 >= 4 ? 2 : (R4 == 2 ? 4 : 8))>(
+              pix, PITCH, base, bw, nx, ny, tcx, tcw, tro, trw, lane, wave);
+        } else {
+          constexpr int G2 = TW / 2, R2 = G2 <= 64 ? 64 / G2 : 1, C2 = G2 <= 64 ? 1 : G2 / 64;
+          resample_groups<2, TW, (R2 * C2 >= 4 ? 2 : (R2 * C2 == 2 ? 4 : 8))>(
+              pix, PITCH, base, bw, nx, ny, tcx, tcw, tro, trw, lane, wave);
+        }
+        // the left halo and the last 3 columns, by (row, column)
+        for (int t0 = 0; t0 < 7 * ny; t0 += kBlock) {
+          const int t = t0 + (int)threadIdx.x;
+          const int j = t / 7, k = t - j * 7;
+          const int col = k < 4 ? k : TW + k;
+          if (j < ny && col < nx) {
+            const uint32_t x0 = tcx[col];
+            const uint32_t v0 = load_pair(base + (tro[2 * j] + x0));
+            const uint32_t v1 = load_pair(base + (tro[2 * j + 1] + x0));
+            pix[j * PITCH + col] = (uint8_t)blend_q8(v0, v1, __builtin_bit_cast(u16x2, tcw[col]),
+                                                     __builtin_bit_cast(u16x2, trw[j]));
+          }
+        }
       } else {
+      // Taps in registers: lane owns the columns 4 + lane + 64c (c < TWW: the tile's
+      // width from the left halo's end), and lane j holds the row tap of tile row j
+      // (j + 64 in the second value), read per row with readlane.  Each wave takes RPI
+      // consecutive rows per round trip.
+      const uint32_t ty_a = resample_tap_r(oy + min(lane, ny - 1), P.base_h, H, rh);
+      const uint32_t ty_b = ny > 64 ? resample_tap_r(oy + min(lane + 64, ny - 1), P.base_h, H, rh)
+                                    : 0u;
       uint32_t cx[NC];
       u16x2 cwx[NC];
 #pragma unroll

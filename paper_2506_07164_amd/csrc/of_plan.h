@@ -490,6 +490,7 @@ OF_HD int32_t base_table_bytes(int32_t n_entries) {
 struct MarkLds {
   int32_t tw, th, pitch, rows, qseg;
   int32_t off_queue, off_bml, off_bmh, bytes;
+  int32_t tcols;  // resample taps of the tile's columns (in the queue's region, before its use)
 };
 
 OF_HD MarkLds mark_lds(const Tune& t) {
@@ -502,7 +503,11 @@ OF_HD MarkLds mark_lds(const Tune& t) {
   // four per-wave queue segments: wave w tests tile rows w, w + 4, ..., at most
   // ceil(rows / 4) of them, and each row appends at most 64 * mark_words pixels
   m.qseg = 64 * t.mark_words * cdiv_u(m.th, 4);
-  m.off_queue = o;  o += align16(2 * 4 * m.qseg);
+  // the same region holds the resample taps while the tile is resampled: per column
+  // x0 and (256 - wx, wx), per row two source row offsets and (256 - wy, wy)
+  m.tcols = m.tw + 7;
+  const int32_t taps = 4 * (2 * m.tcols + 3 * m.rows);
+  m.off_queue = o;  o += align16(2 * 4 * m.qseg > taps ? 2 * 4 * m.qseg : taps);
   m.off_bml = o;    o += 4 * m.th * 2 * t.mark_words;
   m.off_bmh = o;    o += 4 * m.th * 2 * t.mark_words;
   m.bytes = align16(o);

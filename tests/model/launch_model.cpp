@@ -475,6 +475,17 @@ hipError_t launch_mark(const KArgs& a, bool fused, int grid, hipStream_t) {
       const int kgrp = 3 * P.base_w < 6 * W ? 4 : (P.base_w < 6 * W ? 2 : 1);
       if (kgrp > 1) {
         CHECK(P.base_w >= 8, "k_mark: frame narrower than one 8-byte load");
+        // tap tables in the queue's region: x0 and weights of columns [0, nx), two row
+        // offsets and weights of rows [0, ny)
+        CHECK(nx <= M.tcols, "k_mark: %d columns for %d tap slots", nx, M.tcols);
+        const int64_t tq = M.off_queue;
+        lds(tq, 4 * (int64_t)nx, M.off_queue, M.off_bml, "k_mark column taps x0");
+        lds(tq + 4 * (int64_t)M.tcols, 4 * (int64_t)nx, M.off_queue, M.off_bml,
+            "k_mark column tap weights");
+        lds(tq + 8 * (int64_t)M.tcols, 8 * (int64_t)ny, M.off_queue, M.off_bml,
+            "k_mark row offsets");
+        lds(tq + 8 * (int64_t)M.tcols + 8 * (int64_t)M.rows, 4 * (int64_t)ny, M.off_queue,
+            M.off_bml, "k_mark row weights");
         for (int i0 : {4, 4 + TW - kgrp}) {
           auto colx = [&](int i) {
             int xx = (int)(resample_tap(T.ox + std::min(i, nx - 1), P.base_w, W) >> 9);
