@@ -59,6 +59,31 @@ def test_diagonal_prefilter_is_necessary():
             assert (b[0] | b[2]) & (b[1] | b[3])
 
 
+def test_pretests_hold_per_polarity():
+    """The pre-tests in the min/max form the segment-test tiles evaluate (the compass
+    pairs and the diagonal pairs, each as min(max(a, a'), max(b, b')) >= p + t for bright
+    and max(min(..), min(..)) <= p - t for dark) are necessary per polarity: a corner of
+    either polarity passes both pre-tests of that polarity.  Random circles, centres and
+    thresholds."""
+    rng = np.random.Generator(np.random.PCG64(17))
+    n = 40000
+    p = rng.integers(0, 256, n)
+    c = np.clip(p[:, None] + rng.integers(-60, 61, (n, 16)), 0, 255)
+    t = rng.integers(1, 40, n)
+    comp, diag = (0, 4, 8, 12), (2, 6, 10, 14)  # positions 1/5/9/13 and 3/7/11/15
+    for i in range(n):
+        ci, pi, ti = c[i], int(p[i]), int(t[i])
+        for sign in (+1, -1):
+            mask = sum(1 << k for k in range(16) if sign * (int(ci[k]) - pi) >= ti)
+            if not oracle.run9(mask):
+                continue
+            for a, b, a2, b2 in (comp, diag):
+                if sign > 0:
+                    assert min(max(ci[a], ci[a2]), max(ci[b], ci[b2])) >= pi + ti
+                else:
+                    assert max(min(ci[a], ci[a2]), min(ci[b], ci[b2])) <= pi - ti
+
+
 def _fig6_cases():
     cases = []
     with open(os.path.join(GOLDEN, "fig6_patterns.txt")) as f:
