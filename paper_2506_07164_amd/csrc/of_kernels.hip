@@ -331,20 +331,27 @@ __device__ __forceinline__ uint32_t load_pair(gptr<const uint8_t> p) {
 }
 
 // Rows [y0, y1) x columns [x0, x1) of a level into LDS (row pitch lp), as 32-bit words
-// (x0 a multiple of 4; bytes past the row's readable limit read as zero).  The block's
-// threads take the words in order, U per thread per pass.  stage_issue loads the first
-// pass into registers and stage_store writes it to LDS (then loads and stores any
-// further passes), so that a caller can issue other loads in between and wait for all
-// of them at once: a tile of up to U * kBlock words costs one round trip to memory.
+// (x0 a multiple of 4; bytes past the row's readable limit read as zero), or as 16-byte
+// chunks where stage_wide allows (bytes past x1 up to the chunk's end are staged too).
+// The block's threads take the units in order, U words' worth per thread per pass.
+// stage_issue loads the first pass into registers and stage_store writes it to LDS
+// (then loads and stores any further passes), so that a caller can issue other loads in
+// between and wait for all of them at once: a tile of up to U * kBlock words costs one
+// round trip to memory.
 // s_waitcnt operand (gfx9 encoding) that waits for every vector memory operation of the
 // wave: vmcnt 0, expcnt and lgkmcnt at their maxima (no wait).
 constexpr int kWaitVmem = 0x0F70;
 
-template <int U>
+typedef u32x4 u32x4_any_align_g __attribute__((aligned(1)));
+
+// CHUNKS: the 16-byte form is compiled in (U a multiple of 4).
+template <int U, bool CHUNKS>
 struct Stage {
+  static_assert(!CHUNKS || U % 4 == 0, "whole chunks per pass");
   uint32_t v[U];
-  int nw, total, drow, dw;  // words per row, in all; walk advance per kBlock words
-  int row, w, i0;           // walk position of this thread's next word; first word of the pass
+  int nw, total, drow, dw;  // units per row, in all; walk advance per kBlock units
+  int row, w, i0;           // walk position of this thread's next unit; first unit of the pass
+  bool wide;                // 16-byte units (U / 4 per thread and pass), else words
 };
 
 // Words i = i0 + u * kBlock + threadIdx.x of a pass: (row, word) advanced by (drow, dw)
@@ -354,9 +361,11 @@ struct Stage {
 // once).  A word past the region re-reads the region's first word and is dropped;
 // stage_store waits for every load of the pass, dropped ones included, so that none is
 // still in flight when its register is next written in a later step.
-template <int U>
-__device__ __forceinline__ void stage_begin(Stage<U>& st, int x0, int x1, int y0, int y1) {
-  st.nw = (x1 - x0 + 3) >> 2;
+template <int U, bool CHUNKS>
+__device__ __forceinline__ void stage_begin(Stage<U, CHUNKS>& st, int x0, int x1, int y0,
+                                            int y1, int row_limit, int lp) {
+  st.wide = CHUNKS && stage_wide(x0, x1, row_limit, lp);  // the same for the block
+  st.nw = st.wide ? (x1 - x0 + 15) >> 4 : (x1 - x0 + 3) >> 2;
   st.total = st.nw * (y1 - y0);
   st.drow = (int)((uint32_t)kBlock / (uint32_t)st.nw);
   st.dw = kBlock - st.drow * st.nw;
@@ -365,11 +374,33 @@ __device__ __forceinline__ void stage_begin(Stage<U>& st, int x0, int x1, int y0
   st.i0 = 0;
 }
 
-template <int U>
-__device__ __forceinline__ void stage_issue(Stage<U>& st, gptr<const uint8_t> src, int stride,
-                                            int row_limit, int x0, int y0) {
+template <int U, bool CHUNKS>
+__device__ __forceinline__ void stage_issue(Stage<U, CHUNKS>& st, gptr<const uint8_t> src,
+                                            int stride, int row_limit, int x0, int y0) {
   int row = st.row, w = st.w;
   const gptr<const uint8_t> first = src + (size_t)y0 * stride + x0;
+  if constexpr (CHUNKS) {
+    if (st.wide) {
+#pragma unroll
+      for (int c = 0; c < U / 4; ++c) {
+        const bool in = st.i0 + c * kBlock + (int)threadIdx.x < st.total;
+        const gptr<const uint8_t> p = in ? src + (size_t)(y0 + row) * stride + (x0 + 16 * w)
+                                         : first;
+        const u32x4 q = *(gptr<const u32x4_any_align_g>)p;
+        st.v[4 * c] = q.x;
+        st.v[4 * c + 1] = q.y;
+        st.v[4 * c + 2] = q.z;
+        st.v[4 * c + 3] = q.w;
+        row += st.drow;
+        w += st.dw;
+        if (w >= st.nw) {
+          w -= st.nw;
+          ++row;
+        }
+      }
+      return;
+    }
+  }
 #pragma unroll
   for (int u = 0; u < U; ++u) {
     const bool in = st.i0 + u * kBlock + (int)threadIdx.x < st.total;
@@ -387,9 +418,34 @@ __device__ __forceinline__ void stage_issue(Stage<U>& st, gptr<const uint8_t> sr
   }
 }
 
-template <int U>
-__device__ __forceinline__ void stage_store(Stage<U>& st, uint8_t* lds, int lp) {
+template <int U, bool CHUNKS>
+__device__ __forceinline__ void stage_store(Stage<U, CHUNKS>& st, uint8_t* lds, int lp) {
   int row = st.row, w = st.w;
+  if constexpr (CHUNKS) {
+    if (st.wide) {
+#pragma unroll
+      for (int c = 0; c < U / 4; ++c) {
+        if (st.i0 + c * kBlock + (int)threadIdx.x < st.total) {
+          uint32_t* d = (uint32_t*)(lds + row * lp + 16 * w);  // 4-byte aligned
+          d[0] = st.v[4 * c];
+          d[1] = st.v[4 * c + 1];
+          d[2] = st.v[4 * c + 2];
+          d[3] = st.v[4 * c + 3];
+        }
+        row += st.drow;
+        w += st.dw;
+        if (w >= st.nw) {
+          w -= st.nw;
+          ++row;
+        }
+      }
+      __builtin_amdgcn_s_waitcnt(kWaitVmem);  // the dropped loads too
+      st.row = row;
+      st.w = w;
+      st.i0 += U / 4 * kBlock;
+      return;
+    }
+  }
 #pragma unroll
   for (int u = 0; u < U; ++u) {
     if (st.i0 + u * kBlock + (int)threadIdx.x < st.total)
@@ -408,8 +464,8 @@ __device__ __forceinline__ void stage_store(Stage<U>& st, uint8_t* lds, int lp) 
 }
 
 // The passes left after the first (regions larger than U * kBlock words).
-template <int U>
-__device__ __forceinline__ void stage_rest(Stage<U>& st, uint8_t* lds, int lp,
+template <int U, bool CHUNKS>
+__device__ __forceinline__ void stage_rest(Stage<U, CHUNKS>& st, uint8_t* lds, int lp,
                                            gptr<const uint8_t> src, int stride, int row_limit,
                                            int x0, int y0) {
   while (st.i0 < st.total) {
@@ -418,13 +474,13 @@ __device__ __forceinline__ void stage_rest(Stage<U>& st, uint8_t* lds, int lp,
   }
 }
 
-// A whole region, pass by pass.
+// A whole region, pass by pass, word by word.
 template <int U>
 __device__ __forceinline__ void stage_all(uint8_t* lds, int lp, gptr<const uint8_t> src,
                                           int stride, int row_limit, int x0, int x1, int y0,
                                           int y1) {
-  Stage<U> st;
-  stage_begin(st, x0, x1, y0, y1);
+  Stage<U, false> st;
+  stage_begin(st, x0, x1, y0, y1, row_limit, lp);
   stage_rest(st, lds, lp, src, stride, row_limit, x0, y0);
 }
 
@@ -1478,7 +1534,7 @@ __global__ __launch_bounds__(256, 4) void k_detect(KArgs a) {
     uint32_t vlo[2], vhi[2];
     int vr[2], vk[2];
     const int limit = P.level == 0 ? W : P.lvl_stride;
-    Stage<10> st;
+    Stage<12, true> st;
     {
       gptr<const uint8_t> gfl = G((const uint8_t*)P.flags);
       const int nfl = nfx * nfy;
@@ -1496,7 +1552,7 @@ __global__ __launch_bounds__(256, 4) void k_detect(KArgs a) {
         const int jf = min(i, nfl - 1), rf = jf / nfx;
         vfl[u] = gfl[(fcy0 + rf) * P.ncx + fcx0 + (jf - rf * nfx)];
       }
-      stage_begin(st, sx0, sx1, sy0, sy1);
+      stage_begin(st, sx0, sx1, sy0, sy1, limit, D.pitch);
       stage_issue(st, G(P.lvl), P.lvl_stride, limit, sx0, sy0);
 #pragma unroll
       for (int u = 0; u < 2; ++u) {

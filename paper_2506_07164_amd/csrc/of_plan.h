@@ -381,6 +381,14 @@ OF_HD uint32_t resample_tap_r(int32_t i, int32_t n_src, int32_t n_dst, double rd
 }
 
 // ------------------------------------------------------------- tile geometry --
+
+// Whether columns [x0, x1) of a row (x0 a multiple of 4) are staged in whole 16-byte
+// chunks: when the last chunk ends inside the row's readable bytes (row_limit) and
+// inside an LDS row of lp bytes; otherwise the staging goes word by word.
+OF_HD bool stage_wide(int32_t x0, int32_t x1, int32_t row_limit, int32_t lp) {
+  const int32_t span = 16 * ((x1 - x0 + 15) >> 4);
+  return x0 + span <= row_limit && span <= lp;
+}
 // The same functions place every tile in the kernels and in the CPU launch model of the
 // tests, so both check one arithmetic.
 
@@ -552,9 +560,10 @@ constexpr OF_HD DetLds det_lds(const Tune& t, int32_t cell) {
     d.mth = t.det_h;
     d.max_cells = 1;
   }
-  // odd number of 32-bit words per row: the rows of a Harris window fall in distinct banks
-  d.pitch = (int32_t)(((uint32_t)d.mtw + 16u) & ~3u);  // mtw + 10 + 3 rounded up to 4
-  if ((d.pitch >> 2) % 2 == 0) d.pitch += 4;
+  // The staged width (at most mtw + 13 bytes) rounded up to 16-byte chunks, plus one word:
+  // an odd number of 32-bit words per row, so the rows of a Harris window fall in
+  // distinct banks, and room for whole chunks (stage_wide).
+  d.pitch = (int32_t)(((uint32_t)d.mtw + 13u + 15u) & ~15u) + 4;
   d.rows = d.mth + 10;
   d.nbw = cdiv_u(d.mtw + 2, 32) + 1;
   d.nunits = (d.mth + 2) * d.nbw;

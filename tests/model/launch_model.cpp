@@ -658,12 +658,20 @@ hipError_t launch_detect(const KArgs& a, int grid, hipStream_t) {
     acc(P.flags + (int64_t)(T.fcy0 + T.nfy - 1) * P.ncx + T.fcx0 + T.nfx - 1, 1,
         "k_detect flag read");
     const int limit = P.level == 0 ? W : P.lvl_stride;
-    for (int row : {T.sy0, T.sy1 - 1})
-      for (int w : {0, nw - 1}) {
-        const int x = T.sx0 + 4 * w, room = limit - x;
-        const int back = room >= 4 ? 0 : 4 - room;
-        acc(P.lvl + (size_t)row * P.lvl_stride + x - back, 4, "k_detect staged word");
-      }
+    if (stage_wide(T.sx0, T.sx1, limit, D.pitch)) {  // whole 16-byte chunks
+      const int span = 16 * ((T.sx1 - T.sx0 + 15) >> 4);
+      CHECK(span <= D.pitch, "k_detect: %d-byte chunks in a %d-byte LDS row", span, D.pitch);
+      for (int row : {T.sy0, T.sy1 - 1})
+        acc(P.lvl + (size_t)row * P.lvl_stride + T.sx0, span, "k_detect staged chunks");
+      lds((int64_t)(T.sy1 - T.sy0 - 1) * D.pitch, span, 0, D.off_cw, "k_detect staged chunks");
+    } else {
+      for (int row : {T.sy0, T.sy1 - 1})
+        for (int w : {0, nw - 1}) {
+          const int x = T.sx0 + 4 * w, room = limit - x;
+          const int back = room >= 4 ? 0 : 4 - room;
+          acc(P.lvl + (size_t)row * P.lvl_stride + x - back, 4, "k_detect staged word");
+        }
+    }
     // outputs: slots of the tile's cells, or of its 2x2 blocks, or the appended list
     const int nvx = P.det_xend - P.det_x0;
     if (a.cell > 0) {
