@@ -474,12 +474,12 @@ __device__ __forceinline__ void stage_rest(Stage<U, CHUNKS>& st, uint8_t* lds, i
   }
 }
 
-// A whole region, pass by pass, word by word.
-template <int U>
+// A whole region, pass by pass.
+template <int U, bool CHUNKS>
 __device__ __forceinline__ void stage_all(uint8_t* lds, int lp, gptr<const uint8_t> src,
                                           int stride, int row_limit, int x0, int x1, int y0,
                                           int y1) {
-  Stage<U, false> st;
+  Stage<U, CHUNKS> st;
   stage_begin(st, x0, x1, y0, y1, row_limit, lp);
   stage_rest(st, lds, lp, src, stride, row_limit, x0, y0);
 }
@@ -1011,7 +1011,7 @@ __device__ __forceinline__ void resample_groups(uint8_t* pix, int pitch, gptr<co
 template <bool FUSED, int TWW, bool PERSIST>
 __global__ __launch_bounds__(256, 5) void k_mark(KArgs a) {
   constexpr int TW = 64 * TWW;
-  constexpr int PITCH = TW + 8;
+  constexpr int PITCH = TW + 16;  // the staged width (TW + 7) in whole 16-byte chunks
   extern __shared__ __align__(16) uint8_t smem[];
   __shared__ int s_next, s_qcnt[4];
   __shared__ uint8_t s_cf[kMarkCellFlags];  // cells of the tile that hold a fast_t corner
@@ -1212,7 +1212,7 @@ __global__ __launch_bounds__(256, 5) void k_mark(KArgs a) {
       }
     } else {
       const int limit = P.level == 0 ? W : P.lvl_stride;
-      stage_all<8>(pix, PITCH, G(P.lvl), P.lvl_stride, limit, ox, ex, oy, ey);
+      stage_all<8, true>(pix, PITCH, G(P.lvl), P.lvl_stride, limit, ox, ex, oy, ey);
     }
     for (int i = threadIdx.x; i < 2 * M.th * 2 * TWW; i += kBlock) bml[i] = 0u;  // lo, hi
     // cells of the tile's pixels: flagged in LDS by the full test, written once at the end

@@ -505,7 +505,7 @@ OF_HD MarkLds mark_lds(const Tune& t) {
   MarkLds m;
   m.tw = 64 * t.mark_words;
   m.th = t.mark_rows;
-  m.pitch = m.tw + 8;
+  m.pitch = m.tw + 16;  // the staged width (tw + 7) rounded up to 16-byte chunks
   m.rows = m.th + 6;
   int32_t o = align16(m.pitch * m.rows);
   // four per-wave queue segments: wave w tests tile rows w, w + 4, ..., at most

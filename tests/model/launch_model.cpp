@@ -434,7 +434,7 @@ hipError_t launch_mark(const KArgs& a, bool fused, int grid, hipStream_t) {
             e);
   if (!sig_ok(a)) return hipSuccess;
   const MarkLds& M = a.ml;
-  const int TWW = a.t.mark_words, TW = 64 * TWW, PITCH = TW + 8;
+  const int TWW = a.t.mark_words, TW = 64 * TWW, PITCH = TW + 16;
   CHECK(M.pitch == PITCH && M.th == a.t.mark_rows, "k_mark: layout of another tuning");
   const int64_t lds_bytes = M.bytes + base_table_bytes(a.n_entries);
   CHECK(lds_bytes <= 65536, "k_mark: %lld bytes of LDS", (long long)lds_bytes);
@@ -509,6 +509,11 @@ hipError_t launch_mark(const KArgs& a, bool fused, int grid, hipStream_t) {
         acc(P.lvl_w + (size_t)r * P.lvl_stride + T.x_t0, T.x_t1 - T.x_t0, "k_mark level store",
             true);
       CHECK(T.x_t0 % 16 == 0 || T.x_t1 - T.x_t0 < 16, "k_mark: 16-byte stores misaligned");
+    } else if (stage_wide(T.ox, T.ex, P.level == 0 ? W : P.lvl_stride, PITCH)) {
+      const int span = 16 * ((T.ex - T.ox + 15) >> 4);
+      for (int row : {T.oy, T.ey - 1})
+        acc(P.lvl + (size_t)row * P.lvl_stride + T.ox, span, "k_mark staged chunks");
+      lds((int64_t)(ny - 1) * PITCH, span, 0, M.off_queue, "k_mark staged chunks");
     } else {
       const int limit = P.level == 0 ? W : P.lvl_stride;
       const int nw = (T.ex - T.ox + 3) >> 2;
