@@ -48,7 +48,7 @@ typedef struct ihipStream_t* hipStream_t;
 #define OF_MAX_LEVELS 16
 #define OF_MAX_BATCH 64  /* frames per of_detect_batch call */
 
-/* 8-bit grey frame, row-major, `stride` bytes between rows (stride >= width).
+/* 8-bit grey frame, row-major, `stride` bytes between rows (width <= stride < 2^24).
  * 1 <= width, height <= 16384, and the frame spans at most 2^31 - 1 bytes:
  * stride * (height - 1) + width <= 2147483647 (else OF_EINVAL from every call that
  * reads frame pixels). */

@@ -123,7 +123,7 @@ int check_frame_size(int32_t W, int32_t H, const of_params& p) {
 
 int check_image(const of_image* im, const of_params& p) {
   if (!im || !im->data) return OF_EINVAL;
-  if (im->stride < im->width) return OF_EINVAL;
+  if (im->stride < im->width || im->stride >= (1 << 24)) return OF_EINVAL;  // 24-bit row math
   int st = check_frame_size(im->width, im->height, p);
   if (st) return st;
   // The fused resample addresses the frame by 32-bit signed offsets from its first byte.

@@ -104,6 +104,24 @@ __device__ __forceinline__ uint32_t lanes_below(uint64_t m) {
 
 __device__ __forceinline__ int uniform(int v) { return __builtin_amdgcn_readfirstlane(v); }
 
+// Byte offset of row y in a buffer of `stride` bytes per row, by one full-rate 24-bit
+// multiply: every frame (stride < 2^24, at most 2^31 bytes, checked by the host), level
+// buffer, bitmap and slot table here has rows and strides below 2^24 and spans below
+// 2^32 bytes.
+__device__ __forceinline__ uint32_t row_off(int y, int stride) {
+  return (uint32_t)__umul24((uint32_t)y, (uint32_t)stride);
+}
+
+// floor(i / d) for small operands: recip16(d) = ceil(2^16 / d), and (i * recip16(d)) >> 16
+// is exact while i * d < 2^16 (its error i (recip16(d) d - 2^16) / (d 2^16) stays below
+// 1 / d, under the distance from i / d to the next integer).
+__device__ __forceinline__ uint32_t recip16(int d) {
+  return (65536u + (uint32_t)d - 1u) / (uint32_t)d;
+}
+__device__ __forceinline__ int div16(int i, uint32_t r) {
+  return (int)((uint32_t)__umul24((uint32_t)i, r) >> 16);
+}
+
 // Per-level counters spread over kCountSpread sub-counters (see kCountSpread).
 __device__ __forceinline__ void count_add(uint32_t* c, int stride, uint32_t v) {
   atomicAdd(c + (int)(blockIdx.x % (unsigned)kCountSpread) * stride, v);
@@ -378,13 +396,13 @@ template <int U, bool CHUNKS>
 __device__ __forceinline__ void stage_issue(Stage<U, CHUNKS>& st, gptr<const uint8_t> src,
                                             int stride, int row_limit, int x0, int y0) {
   int row = st.row, w = st.w;
-  const gptr<const uint8_t> first = src + (size_t)y0 * stride + x0;
+  const gptr<const uint8_t> first = src + (row_off(y0, stride) + x0);
   if constexpr (CHUNKS) {
     if (st.wide) {
 #pragma unroll
       for (int c = 0; c < U / 4; ++c) {
         const bool in = st.i0 + c * kBlock + (int)threadIdx.x < st.total;
-        const gptr<const uint8_t> p = in ? src + (size_t)(y0 + row) * stride + (x0 + 16 * w)
+        const gptr<const uint8_t> p = in ? src + (row_off(y0 + row, stride) + x0 + 16 * w)
                                          : first;
         const u32x4 q = *(gptr<const u32x4_any_align_g>)p;
         st.v[4 * c] = q.x;
@@ -407,7 +425,7 @@ __device__ __forceinline__ void stage_issue(Stage<U, CHUNKS>& st, gptr<const uin
     const int x = x0 + 4 * w;
     const int room = in ? row_limit - x : 4;
     const int back = room >= 4 ? 0 : 4 - room;
-    const gptr<const uint8_t> p = in ? src + (size_t)(y0 + row) * stride + (x - back) : first;
+    const gptr<const uint8_t> p = in ? src + (row_off(y0 + row, stride) + x - back) : first;
     st.v[u] = *(gptr<const u32_any_align_g>)p >> (8 * back);
     row += st.drow;
     w += st.dw;
@@ -641,12 +659,12 @@ __device__ __forceinline__ void wave_moments(gptr<const uint8_t> lvl, int stride
   if (r <= 15) {
     const int lr = lane >> 3, lc4 = (lane & 7) * 4;
     const int c0 = min(lc4, span - 4);  // first box column of this lane's load
-    gptr<const uint8_t> base = lvl + (size_t)(y - r) * stride + (x - r + c0);
+    gptr<const uint8_t> base = lvl + (row_off(y - r, stride) + x - r + c0);
     uint32_t v[4];
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
       const int row = lr + 8 * k;
-      v[k] = row < span ? *(gptr<const u32_any_align>)(base + (size_t)row * stride) : 0u;
+      v[k] = row < span ? *(gptr<const u32_any_align>)(base + row_off(row, stride)) : 0u;
     }
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
@@ -1397,7 +1415,7 @@ __global__ __launch_bounds__(256, 5) void k_mark(KArgs a) {
       const int k = threadIdx.x & 7;  // at most 8 words per tile row
       for (int r = threadIdx.x >> 3; r < y_t1 - y_t0; r += kBlock >> 3) {
         if (k < nwd) {
-          const size_t gi = (size_t)(y_t0 + r) * P.wpr + w0 + k;
+          const uint32_t gi = row_off(y_t0 + r, P.wpr) + w0 + k;
           glo[gi] = bml[r * 2 * TWW + k];
           ghi[gi] = bmh[r * 2 * TWW + k];
         }
@@ -1419,12 +1437,12 @@ __global__ __launch_bounds__(256, 5) void k_mark(KArgs a) {
       // 64-byte aligned and tiles start at multiples of 64; a ragged right end goes
       // byte by byte).
       const int ow = x_t1 - x_t0, nfull = ow >> 4;
-      gptr<uint8_t> lv = G(P.lvl_w) + (size_t)y_t0 * P.lvl_stride + x_t0;
+      gptr<uint8_t> lv = G(P.lvl_w) + (row_off(y_t0, P.lvl_stride) + x_t0);
       const uint8_t* own = pix + (y_t0 - oy) * PITCH + (x_t0 - ox);  // 4-byte aligned
       for (int q = threadIdx.x; q < (y_t1 - y_t0) * (TW / 16); q += kBlock) {
         const int r = q / (TW / 16), k = q - r * (TW / 16);
         const uint8_t* src = own + r * PITCH + 16 * k;
-        gptr<uint8_t> dst = lv + (size_t)r * P.lvl_stride + 16 * k;
+        gptr<uint8_t> dst = lv + (row_off(r, P.lvl_stride) + 16 * k);
         if (k < nfull) {
           const uint32_t* s4 = (const uint32_t*)src;
           *(gptr<u32x4>)dst = u32x4{s4[0], s4[1], s4[2], s4[3]};
@@ -1527,6 +1545,9 @@ __global__ __launch_bounds__(256, 4) void k_detect(KArgs a) {
     const int ncell = nlcx * nlcy;
     const int nvx = P.det_xend - P.det_x0;
     const int nbx = (vx1 - vx0 + 1) >> 1, nby = (vy1 - vy0 + 1) >> 1;  // 2x2 blocks
+    // divisions by the words per ring row and the ring's flag columns (i * d < 2^16 for
+    // every index here: at most 2 * 256 + (mth + 2) * nbw words and flags, nbw <= 10)
+    const uint32_t rnbw = recip16(nbw), rnfx = recip16(nfx);
 
     // 1. loads: the thread's bitmap words (kept in registers) and the cell flags first,
     //    then the tile's pixels, which stay in flight through the candidate words
@@ -1543,14 +1564,14 @@ __global__ __launch_bounds__(256, 4) void k_detect(KArgs a) {
 #pragma unroll
       for (int u = 0; u < 2; ++u) {
         const int i = u * bd + tid;
-        vr[u] = i / nbw;
+        vr[u] = div16(i, rnbw);
         vk[u] = i - vr[u] * nbw;
-        const int iu = min(i, nunits - 1), ru = iu / nbw;
-        const size_t gi = (size_t)(ry0 + ru) * P.wpr + bw0 + (iu - ru * nbw);
+        const int iu = min(i, nunits - 1), ru = div16(iu, rnbw);
+        const uint32_t gi = row_off(ry0 + ru, P.wpr) + bw0 + (iu - ru * nbw);
         vlo[u] = glo[gi];
         vhi[u] = ghi[gi];
-        const int jf = min(i, nfl - 1), rf = jf / nfx;
-        vfl[u] = gfl[(fcy0 + rf) * P.ncx + fcx0 + (jf - rf * nfx)];
+        const int jf = min(i, nfl - 1), rf = div16(jf, rnfx);
+        vfl[u] = gfl[row_off(fcy0 + rf, P.ncx) + fcx0 + (jf - rf * nfx)];
       }
       stage_begin(st, sx0, sx1, sy0, sy1, limit, D.pitch);
       stage_issue(st, G(P.lvl), P.lvl_stride, limit, sx0, sy0);
@@ -1592,7 +1613,7 @@ __global__ __launch_bounds__(256, 4) void k_detect(KArgs a) {
     //    without a fast_t corner (lo bitmap); a 32-pixel span meets at most 5 cells.
     const int xa = max(rx0, B), xb = min(rx0 + rw, W - B);
     for (int i = tid; i < nfy * nbw; i += bd) {
-      const int fr = i / nbw, k = i - fr * nbw;
+      const int fr = div16(i, rnbw), k = i - fr * nbw;
       const int x0 = (bw0 + k) << 5;
       const int a0 = max(x0, xa), b0 = min(x0 + 32, xb);
       uint32_t valid = 0, fm = 0;
@@ -1626,8 +1647,8 @@ __global__ __launch_bounds__(256, 4) void k_detect(KArgs a) {
       }
     }
     for (int i = 2 * bd + tid; i < nunits; i += bd) {
-      const int r = i / nbw, k = i - r * nbw;
-      const size_t gi = (size_t)(ry0 + r) * P.wpr + bw0 + k;
+      const int r = div16(i, rnbw), k = i - r * nbw;
+      const uint32_t gi = row_off(ry0 + r, P.wpr) + bw0 + k;
       const uint32_t c = cand_word(glo[gi], ghi[gi], ry0 + r, k);
       cw[i] = c;
       ucnt[i] = (uint32_t)__popc(c);
@@ -1680,7 +1701,7 @@ __global__ __launch_bounds__(256, 4) void k_detect(KArgs a) {
     for (int i = 2 * bd + tid; i < nunits; i += bd) {
       uint32_t m = cw[i];
       uint32_t idx = cpre[i];
-      const int r = i / nbw, k = i - r * nbw;
+      const int r = div16(i, rnbw), k = i - r * nbw;
       const uint32_t yx = ((uint32_t)(ry0 + r) << 16) | (uint32_t)((bw0 + k) << 5);
       for (; m && idx < (uint32_t)kCandCache; m &= m - 1u) cpos[idx++] = yx + __builtin_ctz(m);
     }
@@ -1900,7 +1921,7 @@ __global__ __launch_bounds__(256, 4) void k_detect(KArgs a) {
       for (int by = wave; by < nby; by += nwave)
         for (int bx = lane; bx < nbx; bx += 64)
           if (!order[by * nbx + bx])
-            store_cand(out + (size_t)(srow + by) * P.slot_w + scol + bx, INT64_MIN, kNoPos);
+            store_cand(out + (row_off(srow + by, P.slot_w) + scol + bx), INT64_MIN, kNoPos);
     }
     if (tid == 0 && s_ne > 0) count_add(P.cand_count, P.count_stride, (uint32_t)s_ne);
     queue_park(h, next, &s_next);

@@ -630,6 +630,10 @@ hipError_t launch_detect(const KArgs& a, int grid, hipStream_t) {
     const int nw = (T.sx1 - T.sx0 + 3) >> 2;
     CHECK(4 * nw <= D.pitch && T.sy1 - T.sy0 <= D.rows, "k_detect: staged %dx%d words in %dx%d",
           nw, T.sy1 - T.sy0, D.pitch / 4, D.rows);
+    // the kernel's 16-bit reciprocal divisions by nbw and nfx need index * divisor < 2^16
+    CHECK((int64_t)std::max(T.nunits, std::max(T.nfy * T.nbw, 2 * 256)) * T.nbw < 65536 &&
+              (int64_t)std::max(T.nfx * T.nfy, 2 * 256) * T.nfx < 65536,
+          "k_detect: divisions by %d and %d beyond their exact range", T.nbw, T.nfx);
     // Harris windows of the extreme ring candidates: 3 words per row from (cx - 4) & ~3
     const int xa = std::max(T.rx0, B), xb = std::min(T.rx0 + T.rw, W - B);
     const int ya = std::max(T.ry0, B), yb = std::min(T.ry0 + T.rh, H - B);
