@@ -1265,12 +1265,15 @@ __global__ __launch_bounds__(256, 5) void k_mark(KArgs a) {
         constexpr int NP = TWW / 2;
         int lxp[NP];
         bool v0[NP], v1[NP];
+        uint64_t vm0[NP], vm1[NP];  // the same as lane masks
 #pragma unroll
         for (int q = 0; q < NP; ++q) {
           const int x = x_t0 + 128 * q + 2 * lane;
           lxp[q] = x - ox;  // even; ox is a multiple of 4
           v0[q] = x >= B && x < W - B;
           v1[q] = x + 1 >= B && x + 1 < W - B;
+          vm0[q] = __ballot(v0[q]);
+          vm1[q] = __ballot(v1[q]);
         }
         const u16x2 t2 = pair16((uint32_t)tlo, (uint32_t)tlo);
         for (int y = ya + wave; y < yb; y += nwave) {
@@ -1298,17 +1301,19 @@ __global__ __launch_bounds__(256, 5) void k_mark(KArgs a) {
             const u16x2 zb = __builtin_elementwise_sub_sat(pp + t2, hb);
             const u16x2 zd = __builtin_elementwise_sub_sat(hd + t2, pp);
             const uint32_t z = __builtin_bit_cast(uint32_t, __builtin_elementwise_min(zb, zd));
-            const bool pass0 = v0[q] && (z & 0xffffu) == 0u;
-            const bool pass1 = v1[q] && z < 0x10000u;
-            const uint64_t m0 = __ballot(pass0);
-            if (m0) {
-              if (pass0) myq[qn + lanes_below(m0)] = (uint16_t)(lx | (ly << 9));
-              qn += __popcll(m0);
-            }
-            const uint64_t m1 = __ballot(pass1);
-            if (m1) {
-              if (pass1) myq[qn + lanes_below(m1)] = (uint16_t)((lx + 1) | (ly << 9));
-              qn += __popcll(m1);
+            // One append for both pixels: a lane's entries follow those of the lanes below
+            // it (pixel order in the queue does not matter).  The lane masks come from
+            // the compares themselves (ICMP_EQ 32, ICMP_ULT 36) and the fixed column masks.
+            const uint64_t m0 = __builtin_amdgcn_uicmp(z & 0xffffu, 0u, 32) & vm0[q];
+            const uint64_t m1 = __builtin_amdgcn_uicmp(z, 0x10000u, 36) & vm1[q];
+            if (m0 | m1) {
+              const bool pass0 = v0[q] && (z & 0xffffu) == 0u;
+              const bool pass1 = v1[q] && z < 0x10000u;
+              const int slot = qn + (int)(lanes_below(m0) + lanes_below(m1));
+              const uint32_t e = (uint32_t)(lx | (ly << 9));
+              if (pass0) myq[slot] = (uint16_t)e;
+              if (pass1) myq[slot + (pass0 ? 1 : 0)] = (uint16_t)(e + 1u);
+              qn += __popcll(m0) + __popcll(m1);
             }
           }
         }
