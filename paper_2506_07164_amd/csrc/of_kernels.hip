@@ -267,25 +267,41 @@ __device__ __forceinline__ int wave_sum(int v) {
          __builtin_amdgcn_readlane(v, 32) + __builtin_amdgcn_readlane(v, 48);
 }
 
-// Segment test at two thresholds from the 16 circle differences d[i] = I_i - I_p.
-// A bright run of 9 at threshold t exists iff max_s min_{k<9} d[s+k] >= t; a dark run
-// iff -(min_s max_{k<9} d[s+k]) >= t.  Both come from 3-input min/max over cyclic
-// windows (3 x 3 = 9 positions).  Returns bit 0 = corner at t_lo, bit 1 = at t_hi.
-__device__ __forceinline__ uint32_t segment_test2(const int (&d)[16], int t_lo, int t_hi) {
+// Segment test at two thresholds from the 16 circle pixels c[i] and the centre p.  A
+// bright run of 9 at threshold t exists iff max_s min_{k<9} c[s+k] - p >= t; a dark run
+// iff p - min_s max_{k<9} c[s+k] >= t (the centre is one constant of every difference,
+// so the windows are taken over the pixels themselves).  Both come from 3-input min/max
+// over cyclic windows (3 x 3 = 9 positions), folded over the 16 starts 3 at a time.
+// Returns bit 0 = corner at t_lo, bit 1 = at t_hi.
+__device__ __forceinline__ uint32_t segment_test_px(const int (&c)[16], int p, int t_lo,
+                                                    int t_hi) {
   int mn3[16], mx3[16];
 #pragma unroll
   for (int i = 0; i < 16; ++i) {
-    mn3[i] = imin3(d[i], d[(i + 1) & 15], d[(i + 2) & 15]);
-    mx3[i] = imax3(d[i], d[(i + 1) & 15], d[(i + 2) & 15]);
+    mn3[i] = imin3(c[i], c[(i + 1) & 15], c[(i + 2) & 15]);
+    mx3[i] = imax3(c[i], c[(i + 1) & 15], c[(i + 2) & 15]);
   }
-  int sb = -1024, sd = 1024;
+  int m9[16], M9[16];
 #pragma unroll
   for (int i = 0; i < 16; ++i) {
-    sb = max(sb, imin3(mn3[i], mn3[(i + 3) & 15], mn3[(i + 6) & 15]));
-    sd = min(sd, imax3(mx3[i], mx3[(i + 3) & 15], mx3[(i + 6) & 15]));
+    m9[i] = imin3(mn3[i], mn3[(i + 3) & 15], mn3[(i + 6) & 15]);
+    M9[i] = imax3(mx3[i], mx3[(i + 3) & 15], mx3[(i + 6) & 15]);
   }
-  const int s = max(sb, -sd);
+  int sb = imax3(m9[0], m9[1], m9[2]), sd = imin3(M9[0], M9[1], M9[2]);
+#pragma unroll
+  for (int i = 3; i < 15; i += 2) {
+    sb = imax3(sb, m9[i], m9[i + 1]);
+    sd = imin3(sd, M9[i], M9[i + 1]);
+  }
+  sb = max(sb, m9[15]);
+  sd = min(sd, M9[15]);
+  const int s = max(sb - p, p - sd);
   return (s >= t_lo ? 1u : 0u) | (s >= t_hi ? 2u : 0u);
+}
+
+// The same from the 16 differences d[i] = I_i - I_p (a centre of 0).
+__device__ __forceinline__ uint32_t segment_test2(const int (&d)[16], int t_lo, int t_hi) {
+  return segment_test_px(d, 0, t_lo, t_hi);
 }
 
 // Circle differences around pixel c of an LDS tile with row pitch P.  Positions 1..16
@@ -1380,24 +1396,24 @@ __global__ __launch_bounds__(256, 5) void k_mark(KArgs a) {
       const int lx = ent & 511, ly = ent >> 9;
       const uint8_t* c0 = pix + (ly - 3) * PITCH + (lx - 3);  // top-left of the 7x7 box
       const int p = c0[3 * PITCH + 3];
-      int d[16];
-      d[0] = c0[3] - p;
-      d[1] = c0[4] - p;
-      d[2] = c0[PITCH + 5] - p;
-      d[3] = c0[2 * PITCH + 6] - p;
-      d[4] = c0[3 * PITCH + 6] - p;
-      d[5] = c0[4 * PITCH + 6] - p;
-      d[6] = c0[5 * PITCH + 5] - p;
-      d[7] = c0[6 * PITCH + 4] - p;
-      d[8] = c0[6 * PITCH + 3] - p;
-      d[9] = c0[6 * PITCH + 2] - p;
-      d[10] = c0[5 * PITCH + 1] - p;
-      d[11] = c0[4 * PITCH] - p;
-      d[12] = c0[3 * PITCH] - p;
-      d[13] = c0[2 * PITCH] - p;
-      d[14] = c0[PITCH + 1] - p;
-      d[15] = c0[2] - p;
-      const uint32_t r = segment_test2(d, tlo, thi);
+      int c[16];
+      c[0] = c0[3];
+      c[1] = c0[4];
+      c[2] = c0[PITCH + 5];
+      c[3] = c0[2 * PITCH + 6];
+      c[4] = c0[3 * PITCH + 6];
+      c[5] = c0[4 * PITCH + 6];
+      c[6] = c0[5 * PITCH + 5];
+      c[7] = c0[6 * PITCH + 4];
+      c[8] = c0[6 * PITCH + 3];
+      c[9] = c0[6 * PITCH + 2];
+      c[10] = c0[5 * PITCH + 1];
+      c[11] = c0[4 * PITCH];
+      c[12] = c0[3 * PITCH];
+      c[13] = c0[2 * PITCH];
+      c[14] = c0[PITCH + 1];
+      c[15] = c0[2];
+      const uint32_t r = segment_test_px(c, p, tlo, thi);
       if (r) {
         const int x = ox + lx, y = oy + ly;
         const int bit = x - x_t0;
@@ -2323,9 +2339,10 @@ __global__ __launch_bounds__(256) void k_test_segment(const uint8_t* circles, in
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
   const uint8_t* c = circles + (size_t)i * 17;
-  int d[16];
-  for (int k = 0; k < 16; ++k) d[k] = (int)c[1 + k] - (int)c[0];
-  out[i] = (uint8_t)segment_test2(d, t_lo, t_hi);
+  int cc[16];
+#pragma unroll
+  for (int k = 0; k < 16; ++k) cc[k] = c[1 + k];
+  out[i] = (uint8_t)segment_test_px(cc, c[0], t_lo, t_hi);  // the segment-test tiles' routine
 }
 
 // ----------------------------------------------------------------- launches --
