@@ -59,6 +59,18 @@ def test_diagonal_prefilter_is_necessary():
             assert (b[0] | b[2]) & (b[1] | b[3])
 
 
+def test_odd_position_prefilters_are_necessary():
+    """Likewise for the two sets of odd positions, (1,5,9,13) and (3,7,11,15) (0-based
+    from the top, clockwise): nine consecutive positions hold two points of every residue
+    class mod 4 that are adjacent in the class, so (b1|b9)&(b5|b13) and (b3|b11)&(b7|b15)
+    never reject a corner mask (the segment test's third pre-test stage)."""
+    for m in range(1 << 16):
+        if oracle.run9(m):
+            b = [(m >> i) & 1 for i in range(16)]
+            assert (b[1] | b[9]) & (b[5] | b[13])
+            assert (b[3] | b[11]) & (b[7] | b[15])
+
+
 def test_pretests_hold_per_polarity():
     """The pre-tests in the min/max form the segment-test tiles evaluate (the compass
     pairs and the diagonal pairs, each as min(max(a, a'), max(b, b')) >= p + t for bright
@@ -71,13 +83,14 @@ def test_pretests_hold_per_polarity():
     c = np.clip(p[:, None] + rng.integers(-60, 61, (n, 16)), 0, 255)
     t = rng.integers(1, 40, n)
     comp, diag = (0, 4, 8, 12), (2, 6, 10, 14)  # positions 1/5/9/13 and 3/7/11/15
+    odd_a, odd_b = (1, 5, 9, 13), (3, 7, 11, 15)  # the third stage's two sets
     for i in range(n):
         ci, pi, ti = c[i], int(p[i]), int(t[i])
         for sign in (+1, -1):
             mask = sum(1 << k for k in range(16) if sign * (int(ci[k]) - pi) >= ti)
             if not oracle.run9(mask):
                 continue
-            for a, b, a2, b2 in (comp, diag):
+            for a, b, a2, b2 in (comp, diag, odd_a, odd_b):
                 if sign > 0:
                     assert min(max(ci[a], ci[a2]), max(ci[b], ci[b2])) >= pi + ti
                 else:
