@@ -394,7 +394,8 @@ hipError_t launch_selection(KArgs k, const CallPlan& c, hipStream_t stream) {
   // otherwise waves rank from memory and most stop early, which takes less work.
   int32_t widest = 0;  // largest level the rank path takes (appended lists: up to the cap)
   for (int i = 0; i < lay.n_entries; ++i) widest = std::max(widest, c.es[i].rank_slots);
-  k.sel_lds = std::min(widest, kSelLdsCap);
+  // (a staged copy is padded to a multiple of 256)
+  k.sel_lds = std::min((int32_t)align_up(widest, 256), kSelLdsCap);
   const int64_t blocks_per_cu = std::min<int64_t>(8, 163840 / (8 * (int64_t)k.sel_lds + 4352));
   if ((int64_t)lay.rank_slots > (int64_t)device_cus() * 4 * blocks_per_cu) k.sel_lds = 0;
   // Besides ranking, the launch clears the cell flags and the segment-test queue counter
@@ -415,7 +416,7 @@ hipError_t launch_selection(KArgs k, const CallPlan& c, hipStream_t stream) {
       set_small_bases(k, c, kSelSlots);
       int32_t longest = 0;
       for (int i = 0; i < lay.n_entries; ++i) longest = std::max(longest, c.es[i].sel_slots);
-      k.sel_lds = std::min(longest, kSortCap);
+      k.sel_lds = std::min((int32_t)align_up(longest, 256), kSortCap);
       e = timed(5, stream, [&] { return launch_select_orient(k, lay.sel_slots, stream); }, true);
     }
   }

@@ -2074,17 +2074,26 @@ __global__ __launch_bounds__(256) void k_select_orient(KArgs a) {
   int cnt = 0;
   if (staged) {
     int64_t* s_sc = (int64_t*)smem;
-    for (int k = threadIdx.x; k < C; k += kBlock) s_sc[k] = *(gptr<const int64_t>)(cand + k);
+    // Padded to a multiple of 256 with the empty slots' INT64_MIN (below every
+    // candidate's R'), so that every lane takes the same steps, four reads at a time,
+    // with no bounds test and no per-lane loop exit (sel_lds is a multiple of 256).
+    const int Cp = uniform((C + 255) & ~255);
+    for (int k = threadIdx.x; k < Cp; k += kBlock)
+      s_sc[k] = k < C ? *(gptr<const int64_t>)(cand + k) : INT64_MIN;
     lds_barrier();
     if (me.pos == kNoPos) return;
-    bool tie = false;
-#pragma unroll 4
-    for (int j = lane; j < C; j += 64) {
-      const int64_t sj = s_sc[j];
-      cnt += sj > me.score ? 1 : 0;
-      tie = tie || (sj == me.score && j != i);
+    int eq = 0;  // candidates with the same R', the wave's own included
+    for (int j0 = 0; j0 < Cp; j0 += 256) {
+      int64_t sj[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) sj[u] = s_sc[j0 + 64 * u + lane];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        cnt += sj[u] > me.score ? 1 : 0;
+        eq += __popcll(__ballot(sj[u] == me.score));
+      }
     }
-    if (__ballot(tie)) {  // equal R' (rare): ordered by position
+    if (eq > 1) {  // equal R' (rare): ordered by position
       for (int j = lane; j < C; j += 64) {
         const Cand o = load_cand(cand + j);
         cnt += (o.score == me.score && o.pos < me.pos) ? 1 : 0;

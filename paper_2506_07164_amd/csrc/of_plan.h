@@ -23,6 +23,7 @@ constexpr int kCandCache = 1024;                     // Harris scores cached per
 constexpr int kMarkCellFlags = 320;  // cells a segment-test tile meets (cell >= 8: 33 x 9)
 constexpr int kRankCap = 16384;                      // levels ranked by counting, not radix
 constexpr int kSelLdsCap = 2560;                     // level R' staged in LDS for ranking
+static_assert(kSelLdsCap % 256 == 0 && kSortCap % 256 == 0, "staged copies padded to 256");
 constexpr uint32_t kNoPos = 0xffffffffu;              // position of an empty candidate slot
 // Per-level counters that many tiles add to are split into kCountSpread sub-counters in
 // separate 128-byte lines (a tile adds to sub-counter blockIdx mod kCountSpread; readers

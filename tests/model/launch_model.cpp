@@ -789,8 +789,11 @@ hipError_t launch_select_orient(const KArgs& a, int slots, hipStream_t) {
       if (a.from_sel) acc(P.sel_count, 4, "k_select_orient list count");
       acc(a.from_sel ? P.sel : P.cand, (int64_t)sizeof(Cand) * C,
           "k_select_orient candidate reads");
-      if (a.sel_lds > 0 && C <= a.sel_lds) lds(0, 8 * (int64_t)C, 0, 8 * (int64_t)a.sel_lds,
-                                                "k_select_orient staged R'");
+      if (a.sel_lds > 0 && C <= a.sel_lds) {
+        CHECK(a.sel_lds % 256 == 0, "k_select_orient: staged copy padded to 256");
+        lds(0, 8 * (((int64_t)C + 255) & ~255), 0, 8 * (int64_t)a.sel_lds,
+            "k_select_orient staged R' (padded)");
+      }
       model_moments(P, "k_select_orient moments");
       // the level's keypoints at prefix .. prefix + quota of the frame's output
       int64_t prefix = 0;
